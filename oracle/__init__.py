@@ -1,0 +1,302 @@
+"""Python access to the plain CPU oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` import this module.  The product library
+never loads it, and it shares no code with the HIP path.
+
+Problems are plain dicts with the keys of ``paper_2005_10494_amd.workloads``;
+this module converts them to the oracle's own C struct.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP, FP64, no FMA contraction)."""
+    if force or not os.path.exists(_SO):
+        cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-fopenmp", "-ffp-contract=off",
+               "-fPIC", "-shared", _SRC, "-lm", "-o", _SO + ".tmp"]
+        subprocess.check_call(cmd, cwd=_HERE)
+        os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int32), ("m", ctypes.c_int32 * 6),
+        ("q_lo", ctypes.c_double), ("q_hi", ctypes.c_double),
+        ("rho_b", ctypes.c_double), ("info", ctypes.c_double), ("alpha0", ctypes.c_double),
+        ("alpha_rule", ctypes.c_int32), ("alpha_fixed", ctypes.c_double * 2),
+        ("effect", ctypes.c_int32),
+        ("mu_b0", ctypes.c_double), ("sd_b0", ctypes.c_double),
+        ("mu_b1", ctypes.c_double), ("sd_b1", ctypes.c_double),
+        ("tau_lo", ctypes.c_double), ("tau_hi", ctypes.c_double),
+        ("paper_a", ctypes.c_double), ("paper_b", ctypes.c_double),
+        ("paper_events", ctypes.c_double),
+        ("width", ctypes.c_double), ("bandwidth", ctypes.c_double * 6),
+        ("seed", ctypes.c_uint64), ("scenario", ctypes.c_uint32),
+    ]
+
+
+class _Design(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_double * 6), ("c", ctypes.c_double * 6),
+                ("r", ctypes.c_double), ("rho", ctypes.c_double),
+                ("z1", ctypes.c_double), ("z2", ctypes.c_double)]
+
+
+class _Draw(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_double * 8), ("b0", ctypes.c_double), ("b1", ctypes.c_double),
+                ("tau", ctypes.c_double * 6), ("t", ctypes.c_double * 6),
+                ("PR", ctypes.c_double), ("e1", ctypes.c_double), ("e2", ctypes.c_double)]
+
+
+_ALPHA = {"fwer": 0, "fwer_equal": 0, "bonferroni": 1, "fixed": 2}
+_EFFECT = {"step": 0, "paper": 1, "paper_gauss": 1}
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build(force=False)
+        L = ctypes.CDLL(_SO)
+        D, P, I64, U64, U32 = ctypes.c_double, ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32
+        pp = ctypes.POINTER(_Problem)
+        sig = {
+            "or_Phi": (D, [D]), "or_phi": (D, [D]), "or_Phiinv": (D, [D]),
+            "or_bvn": (D, [D, D, D]), "or_bvn_density": (D, [D, D, D]),
+            "or_orthant": (D, [ctypes.c_int, P, D]), "or_zstar": (D, [D, D]),
+            "or_info_units": (D, [D, D, D]),
+            "or_philox4x32_10": (None, [P, P, P]), "or_uniform52": (D, [U32, U32]),
+            "or_grid_point": (None, [pp, I64, P, P]), "or_grid_size": (I64, [pp]),
+            "or_make_design": (None, [pp, P, ctypes.POINTER(_Design)]),
+            "or_make_draw": (None, [pp, U64, ctypes.POINTER(_Draw)]),
+            "or_overlap": (D, [pp, ctypes.POINTER(_Design), ctypes.POINTER(_Draw)]),
+            "or_success": (D, [pp, ctypes.POINTER(_Design), ctypes.POINTER(_Draw)]),
+            "or_eval_points": (None, [pp, I64, P, U64, U64, P, P]),
+            "or_eval_grid": (None, [pp, I64, P, U64, U64, P, P]),
+            "or_smooth_direct": (None, [pp, P, P]), "or_smooth_separable": (None, [pp, P, P]),
+            "or_argmax": (I64, [I64, P]),
+            "or_grad_points": (None, [pp, I64, P, U64, U64, P, P, P]),
+            "or_exact_step": (D, [pp, P]), "or_exact_paper": (D, [pp, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def problem_struct(prob: dict) -> _Problem:
+    s = _Problem()
+    d = int(prob["d"])
+    s.d = d
+    m = list(prob.get("m") or [2] * d)
+    for j in range(6):
+        s.m[j] = int(m[j]) if j < len(m) else 1
+    s.q_lo = float(prob.get("q_lo", 0.05))
+    s.q_hi = float(prob.get("q_hi", 0.95))
+    s.rho_b = float(prob.get("rho_b", 0.0))
+    s.info = float(prob["info"])
+    s.alpha0 = float(prob.get("alpha0", 0.025))
+    rule = prob.get("alpha_rule", "fwer")
+    s.alpha_rule = _ALPHA[rule] if isinstance(rule, str) else int(rule)
+    af = prob.get("alpha_fixed", (0.0, 0.0))
+    s.alpha_fixed[0], s.alpha_fixed[1] = float(af[0]), float(af[1])
+    eff = prob.get("effect", "step")
+    s.effect = _EFFECT[eff] if isinstance(eff, str) else int(eff)
+    for k in ("mu_b0", "sd_b0", "mu_b1", "sd_b1", "tau_lo", "tau_hi",
+              "paper_a", "paper_b", "paper_events", "width"):
+        setattr(s, k, float(prob.get(k, 0.0)))
+    bw = list(prob.get("bandwidth") or [0.02] * d)
+    for j in range(6):
+        s.bandwidth[j] = float(bw[j]) if j < len(bw) else 1.0
+    s.seed = int(prob.get("seed", 0))
+    s.scenario = int(prob.get("scenario", 0))
+    return s
+
+
+# ---- primitives -------------------------------------------------------------
+
+def Phi(x): return lib().or_Phi(float(x))
+def phi(x): return lib().or_phi(float(x))
+def Phiinv(p): return lib().or_Phiinv(float(p))
+def bvn(h, k, rho): return lib().or_bvn(float(h), float(k), float(rho))
+def bvn_density(h, k, rho): return lib().or_bvn_density(float(h), float(k), float(rho))
+def zstar(r, alpha0=0.025): return lib().or_zstar(float(r), float(alpha0))
+def info_units(alpha, beta, delta): return lib().or_info_units(float(alpha), float(beta), float(delta))
+def uniform52(wa, wb): return lib().or_uniform52(int(wa), int(wb))
+
+
+def orthant(v, rho_b):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    return lib().or_orthant(int(v.size), _ptr(v), float(rho_b))
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().or_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+# ---- model ------------------------------------------------------------------
+
+def grid_size(prob):
+    return int(np.prod([int(x) for x in prob["m"][: int(prob["d"])]]))
+
+
+def grid_point(prob, g):
+    s = problem_struct(prob)
+    q = np.zeros(6)
+    idx = np.zeros(6, dtype=np.int32)
+    lib().or_grid_point(ctypes.byref(s), int(g), _ptr(q), _ptr(idx))
+    d = s.d
+    return q[:d].copy(), idx[:d].copy()
+
+
+def grid_points(prob, g_list):
+    d = int(prob["d"])
+    return np.array([grid_point(prob, g)[0] for g in g_list]).reshape(len(g_list), d)
+
+
+def make_design(prob, q):
+    s = problem_struct(prob)
+    qq = np.zeros(6)
+    qq[: s.d] = q
+    ds = _Design()
+    lib().or_make_design(ctypes.byref(s), _ptr(qq), ctypes.byref(ds))
+    d = s.d
+    return {"q": np.array(ds.q[:d]), "c": np.array(ds.c[:d]), "r": ds.r, "rho": ds.rho,
+            "z1": ds.z1, "z2": ds.z2}
+
+
+def make_draw(prob, k):
+    s = problem_struct(prob)
+    dr = _Draw()
+    lib().or_make_draw(ctypes.byref(s), int(k), ctypes.byref(dr))
+    d = s.d
+    return {"u": np.array(dr.u[:]), "b0": dr.b0, "b1": dr.b1, "tau": np.array(dr.tau[:d]),
+            "t": np.array(dr.t[:d]), "PR": dr.PR, "e1": dr.e1, "e2": dr.e2}
+
+
+def _design_draw(prob, q, k):
+    s = problem_struct(prob)
+    qq = np.zeros(6)
+    qq[: s.d] = q
+    ds = _Design()
+    dr = _Draw()
+    lib().or_make_design(ctypes.byref(s), _ptr(qq), ctypes.byref(ds))
+    lib().or_make_draw(ctypes.byref(s), int(k), ctypes.byref(dr))
+    return s, ds, dr
+
+
+def overlap(prob, q, k):
+    s, ds, dr = _design_draw(prob, q, k)
+    return lib().or_overlap(ctypes.byref(s), ctypes.byref(ds), ctypes.byref(dr))
+
+
+def success(prob, q, k):
+    s, ds, dr = _design_draw(prob, q, k)
+    return lib().or_success(ctypes.byref(s), ctypes.byref(ds), ctypes.byref(dr))
+
+
+def eval_points(prob, q, M, k0=0, want_var=True):
+    s = problem_struct(prob)
+    q = np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(-1, s.d))
+    n = q.shape[0]
+    mean = np.zeros(n)
+    var = np.zeros(n)
+    lib().or_eval_points(ctypes.byref(s), n, _ptr(q), int(k0), int(M), _ptr(mean),
+                         _ptr(var) if want_var else None)
+    return (mean, var) if want_var else mean
+
+
+def eval_grid(prob, g_list, M, k0=0):
+    s = problem_struct(prob)
+    g = np.ascontiguousarray(g_list, dtype=np.int64)
+    mean = np.zeros(g.size)
+    var = np.zeros(g.size)
+    lib().or_eval_grid(ctypes.byref(s), g.size, _ptr(g), int(k0), int(M), _ptr(mean), _ptr(var))
+    return mean, var
+
+
+def smooth_direct(prob, f):
+    s = problem_struct(prob)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros_like(f)
+    lib().or_smooth_direct(ctypes.byref(s), _ptr(f), _ptr(out))
+    return out
+
+
+def smooth_separable(prob, f):
+    s = problem_struct(prob)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros_like(f)
+    lib().or_smooth_separable(ctypes.byref(s), _ptr(f), _ptr(out))
+    return out
+
+
+def argmax(v):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    return int(lib().or_argmax(v.size, _ptr(v)))
+
+
+def grad_points(prob, q, M, k0=0):
+    s = problem_struct(prob)
+    q = np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(-1, s.d))
+    n = q.shape[0]
+    obj = np.zeros(n)
+    gq = np.zeros((n, s.d))
+    gmu = np.zeros((n, 2))
+    lib().or_grad_points(ctypes.byref(s), n, _ptr(q), int(k0), int(M), _ptr(obj), _ptr(gq), _ptr(gmu))
+    return obj, gq, gmu
+
+
+def exact_step(prob, q):
+    s = problem_struct(prob)
+    qq = np.zeros(6)
+    qq[: s.d] = q
+    return lib().or_exact_step(ctypes.byref(s), _ptr(qq))
+
+
+def exact_paper(prob, q):
+    s = problem_struct(prob)
+    qq = np.zeros(6)
+    qq[: s.d] = q
+    return lib().or_exact_paper(ctypes.byref(s), _ptr(qq))
+
+
+def success_with_draw(prob, q, draw: dict):
+    """Success probability for design q and an explicitly given draw."""
+    s = problem_struct(prob)
+    qq = np.zeros(6)
+    qq[: s.d] = q
+    ds = _Design()
+    lib().or_make_design(ctypes.byref(s), _ptr(qq), ctypes.byref(ds))
+    dr = _Draw()
+    for j, v in enumerate(draw.get("u", [])):
+        dr.u[j] = v
+    dr.b0, dr.b1, dr.PR = draw["b0"], draw["b1"], draw["PR"]
+    dr.e1, dr.e2 = draw.get("e1", 0.0), draw.get("e2", 0.0)
+    for j in range(s.d):
+        dr.tau[j] = draw["tau"][j]
+        dr.t[j] = draw["t"][j]
+    return lib().or_success(ctypes.byref(s), ctypes.byref(ds), ctypes.byref(dr))

@@ -1,0 +1,874 @@
+/*
+ * Plain CPU oracle for the biomarker-cutoff design objective (arXiv 2005.10494).
+ *
+ * TEST INFRASTRUCTURE ONLY: see oracle.h.  Only the test suite, the smoke
+ * check and the CPU-baseline leg of the benchmark load this library.
+ *
+ * Build: gcc -O2 -std=c11 -fopenmp -ffp-contract=off -fPIC -shared oracle.c -lm
+ * (-ffp-contract=off keeps every product and sum separately rounded, which the
+ * bit-exact grid coordinates and uniforms rely on).
+ */
+#define _GNU_SOURCE
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ======================================================================== */
+/* Standard normal distribution                                             */
+/* ======================================================================== */
+
+/* Phi(x) = P(N(0,1) <= x), through the C library's complementary error
+ * function, which keeps relative accuracy in the lower tail. */
+double or_Phi(double x)
+{
+    if (x == INFINITY) return 1.0;
+    if (x == -INFINITY) return 0.0;
+    return 0.5 * erfc(-x / sqrt(2.0));
+}
+
+double or_phi(double x)
+{
+    return exp(-0.5 * x * x) / sqrt(2.0 * M_PI);
+}
+
+/* Phi^-1(p): the root of Phi(x) = p.
+ * Central region p in [1/4, 3/4]: Newton on erf(x/sqrt 2)/2 = p - 1/2, where
+ * p - 1/2 is exact, so x keeps relative accuracy near 0.
+ * Lower region: a rough start (Abramowitz & Stegun 26.2.23), then Newton on
+ * log Phi(x) = log p, which converges in a few steps down to p ~ 1e-308.
+ * Upper region: Phi^-1(p) = -Phi^-1(1-p); 1-p is exact for p in [1/2, 1). */
+double or_Phiinv(double p)
+{
+    if (isnan(p) || p < 0.0 || p > 1.0) return NAN;
+    if (p == 0.0) return -INFINITY;
+    if (p == 1.0) return INFINITY;
+    if (p == 0.5) return 0.0;
+    if (p >= 0.25 && p <= 0.75) {
+        double a = p - 0.5;
+        double x = a * sqrt(2.0 * M_PI);
+        for (int it = 0; it < 100; ++it) {
+            double step = (0.5 * erf(x / sqrt(2.0)) - a) / or_phi(x);
+            x -= step;
+            if (step == 0.0 || fabs(step) <= 1e-17 * fabs(x)) break;
+        }
+        return x;
+    }
+    if (p > 0.5) return -or_Phiinv(1.0 - p);
+    double t = sqrt(-2.0 * log(p));
+    double x = -(t - (2.515517 + 0.802853 * t + 0.010328 * t * t) /
+                         (1.0 + 1.432788 * t + 0.189269 * t * t + 0.001308 * t * t * t));
+    for (int it = 0; it < 100; ++it) {
+        double F = or_Phi(x);
+        double step = log1p((F - p) / p) * F / or_phi(x);
+        x -= step;
+        if (step == 0.0 || fabs(step) <= 1e-17 * fabs(x)) break;
+    }
+    return x;
+}
+
+/* ======================================================================== */
+/* Adaptive Gauss-Kronrod (7-point Gauss, 15-point Kronrod) quadrature      */
+/* ======================================================================== */
+
+static const double gk_x[8] = {
+    0.991455371120812639206854697526329, 0.949107912342758524526189684047851,
+    0.864864423359769072789712788640926, 0.741531185599394439863864773280788,
+    0.586087235467691130294144845693013, 0.405845151377397166906606412076961,
+    0.207784955007898467600689403773245, 0.000000000000000000000000000000000};
+static const double gk_wk[8] = {
+    0.022935322010529224963732008058970, 0.063092092629978553290700663189204,
+    0.104790010322250183839876322541518, 0.140653259715525918745189590510238,
+    0.169004726639267902826583426598550, 0.190350578064785409913256402421014,
+    0.204432940075298892414161999234649, 0.209482141084727828012999174891714};
+static const double gk_wg[4] = {
+    0.129484966168869693270611432679082, 0.279705391489276667901467771423780,
+    0.381830050505118944950369775488975, 0.417959183673469387755102040816327};
+
+typedef double (*or_fn)(double, void *);
+
+static double gk15(or_fn f, void *ctx, double a, double b, double *err)
+{
+    double c = 0.5 * (a + b), h = 0.5 * (b - a);
+    double fc = f(c, ctx);
+    double rk = fc * gk_wk[7], rg = fc * gk_wg[3];
+    for (int j = 0; j < 7; ++j) {
+        double dx = h * gk_x[j];
+        double s = f(c - dx, ctx) + f(c + dx, ctx);
+        rk += gk_wk[j] * s;
+        if (j & 1) rg += gk_wg[j / 2] * s;
+    }
+    *err = fabs((rk - rg) * h);
+    return rk * h;
+}
+
+static double gk_adapt(or_fn f, void *ctx, double a, double b, double tol, int depth)
+{
+    double err, r = gk15(f, ctx, a, b, &err);
+    if (err <= tol || err <= 1e-15 * fabs(r) || depth >= 40) return r;
+    double m = 0.5 * (a + b);
+    return gk_adapt(f, ctx, a, m, 0.5 * tol, depth + 1) +
+           gk_adapt(f, ctx, m, b, 0.5 * tol, depth + 1);
+}
+
+/* Integral of f over [a, b]: eight equal panels, each refined by bisection
+ * until the Gauss/Kronrod difference is below 1e-17 absolute or 1e-15
+ * relative. */
+double or_quad(or_fn f, void *ctx, double a, double b)
+{
+    const int n0 = 8;
+    double s = 0.0;
+    for (int i = 0; i < n0; ++i) {
+        double lo = a + (b - a) * i / n0;
+        double hi = (i == n0 - 1) ? b : a + (b - a) * (i + 1) / n0;
+        s += gk_adapt(f, ctx, lo, hi, 1e-17, 0);
+    }
+    return s;
+}
+
+/* ======================================================================== */
+/* Bivariate normal CDF                                                     */
+/* ======================================================================== */
+
+typedef struct { double k, rho, sig; } bvn_ctx;
+
+static double bvn_integrand(double x, void *v)
+{
+    const bvn_ctx *c = (const bvn_ctx *)v;
+    return or_phi(x) * or_Phi((c->k - c->rho * x) / c->sig);
+}
+
+/* Phi_2(h, k; rho) = P(X <= h, Y <= k) for a standard bivariate normal with
+ * correlation rho, from its definition by conditioning on X:
+ *   Phi_2 = int_{-inf}^{h} phi(x) Phi((k - rho x) / sqrt(1 - rho^2)) dx.
+ * This is the CDF Phi_Sigma of Formula 1 for n = 2. */
+double or_bvn(double h, double k, double rho)
+{
+    if (isnan(h) || isnan(k) || isnan(rho)) return NAN;
+    if (h == -INFINITY || k == -INFINITY) return 0.0;
+    if (h == INFINITY) return or_Phi(k);
+    if (k == INFINITY) return or_Phi(h);
+    if (rho >= 1.0) return or_Phi(fmin(h, k));
+    if (rho <= -1.0) {
+        double v = or_Phi(h) - or_Phi(-k);
+        return v > 0.0 ? v : 0.0;
+    }
+    if (k < h) { double t = h; h = k; k = t; }
+    bvn_ctx c = {k, rho, sqrt((1.0 - rho) * (1.0 + rho))};
+    double lo = fmin(-12.0, h - 10.0);
+    return or_quad(bvn_integrand, &c, lo, h);
+}
+
+/* Density of the standard bivariate normal (the integrand of Plackett's
+ * identity d Phi_2 / d rho = phi_2). */
+double or_bvn_density(double h, double k, double rho)
+{
+    double om = (1.0 - rho) * (1.0 + rho);
+    return exp(-(h * h - 2.0 * rho * h * k + k * k) / (2.0 * om)) / (2.0 * M_PI * sqrt(om));
+}
+
+/* ======================================================================== */
+/* Equicorrelated orthant probabilities                                     */
+/* ======================================================================== */
+/*
+ * With X_j = sqrt(rho_b) Z + sqrt(1 - rho_b) E_j (Z, E_j iid N(0,1)), the
+ * event {X_j > v_j} given Z = z has probability Phi((sqrt(rho_b) z - v_j) /
+ * sqrt(1 - rho_b)), independently across j.  Integrating over z gives every
+ * orthant-type probability used below as a one-dimensional integral.
+ *
+ * Each axis contributes one factor.  Factor kinds:
+ *   FK_CUT   Phi(a_j),                        a_j = (sqrt(rho) z - c_j)/sqrt(1-rho)
+ *   FK_MIX   s_j Phi(a_j) + (1 - s_j) Phi(b_j), b_j likewise with t_j
+ *   FK_DENS  phi(a_j)                         (derivative of FK_CUT in -c_j)
+ *   FK_DMIX  Phi(a_j) - Phi(b_j)              (derivative of FK_MIX in s_j)
+ */
+enum { FK_CUT = 0, FK_MIX = 1, FK_DENS = 2, FK_DMIX = 3 };
+
+typedef struct {
+    int d;
+    double c[6], t[6], s[6];
+    int kind[6];
+    double sr, sq;
+} orth_ctx;
+
+static double orth_integrand(double z, void *v)
+{
+    const orth_ctx *o = (const orth_ctx *)v;
+    double prod = or_phi(z);
+    for (int j = 0; j < o->d; ++j) {
+        double a = (o->sr * z - o->c[j]) / o->sq;
+        double f;
+        switch (o->kind[j]) {
+        case FK_CUT: f = or_Phi(a); break;
+        case FK_DENS: f = or_phi(a); break;
+        case FK_MIX: {
+            double b = (o->sr * z - o->t[j]) / o->sq;
+            f = o->s[j] * or_Phi(a) + (1.0 - o->s[j]) * or_Phi(b);
+            break;
+        }
+        default: {
+            double b = (o->sr * z - o->t[j]) / o->sq;
+            f = or_Phi(a) - or_Phi(b);
+            break;
+        }
+        }
+        prod *= f;
+    }
+    return prod;
+}
+
+static double orth_integral(orth_ctx *o, double rho_b)
+{
+    o->sr = sqrt(rho_b);
+    o->sq = sqrt(1.0 - rho_b);
+    return or_quad(orth_integrand, o, -12.0, 12.0);
+}
+
+/* P(X_j > v_j for all j), X ~ N_d(0, (1-rho_b) I + rho_b 11'). */
+double or_orthant(int d, const double *v, double rho_b)
+{
+    orth_ctx o;
+    memset(&o, 0, sizeof o);
+    o.d = d;
+    for (int j = 0; j < d; ++j) { o.c[j] = v[j]; o.kind[j] = FK_CUT; }
+    return orth_integral(&o, rho_b);
+}
+
+/* ======================================================================== */
+/* Critical values                                                          */
+/* ======================================================================== */
+
+/* Family-wise error of two one-sided tests at a common critical value z with
+ * null correlation rho (Formula 2 for n = 2):
+ *   1 - Phi_2(z, z; rho) = 2 Phi(-z) - Phi_2(-z, -z; rho),
+ * written in the second form so both terms keep relative accuracy. */
+static double fwer_equal(double z, double rho)
+{
+    return 2.0 * or_Phi(-z) - or_bvn(-z, -z, rho);
+}
+
+/* Common critical value z* with FWER(z*) = alpha0, by bisection between the
+ * one-test value (rho = 1) and the Bonferroni value (which is conservative). */
+double or_zstar(double r, double alpha0)
+{
+    double rho = sqrt(r);
+    double lo = -or_Phiinv(alpha0), hi = -or_Phiinv(0.5 * alpha0);
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (fwer_equal(mid, rho) > alpha0) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* Information units needed for a one-sided level-alpha test with power
+ * 1 - beta at hazard reduction delta (Sec. 3, the I_3 sizing formula). */
+double or_info_units(double alpha, double beta, double delta)
+{
+    double za = -or_Phiinv(alpha), zb = -or_Phiinv(beta);
+    double l = log1p(-delta);
+    return (za + zb) * (za + zb) / (l * l);
+}
+
+/* ======================================================================== */
+/* Counter-based random numbers                                             */
+/* ======================================================================== */
+
+/* Philox4x32 with 10 rounds (Salmon, Moraes, Dror & Shaw, "Parallel random
+ * numbers: as easy as 1, 2, 3", SC 2011): each round multiplies counter words
+ * 0 and 2 by fixed 32-bit constants, mixes the high halves with words 1 and 3
+ * and the key, and the key is advanced by two Weyl constants between rounds. */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        uint32_t y1 = (uint32_t)p1;
+        uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        uint32_t y3 = (uint32_t)p0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Uniform on (0,1) from two words: the top 26 bits of each form a 52-bit
+ * integer n, and u = (n + 1/2) 2^-52.  Every step is exact in FP64, so
+ * u is never 0 or 1 and 1 - u is again such a value. */
+double or_uniform52(uint32_t wa, uint32_t wb)
+{
+    uint64_t n = ((uint64_t)(wa >> 6) << 26) | (uint64_t)(wb >> 6);
+    return ((double)n + 0.5) * 0x1p-52;
+}
+
+/* The uniforms of draw k: Philox blocks with key (seed lo, seed hi) and
+ * counter (k lo, k hi, scenario, b) for b = 0, 1, ...; uniform i takes words
+ * 2i and 2i+1 of the concatenated output. */
+static void draw_uniforms(const or_problem *p, uint64_t k, int nu, double *u)
+{
+    uint32_t key[2] = {(uint32_t)p->seed, (uint32_t)(p->seed >> 32)};
+    uint32_t words[16];
+    int nblk = (2 * nu + 3) / 4;
+    for (int b = 0; b < nblk; ++b) {
+        uint32_t ctr[4] = {(uint32_t)k, (uint32_t)(k >> 32), p->scenario, (uint32_t)b};
+        or_philox4x32_10(ctr, key, words + 4 * b);
+    }
+    for (int i = 0; i < nu; ++i) u[i] = or_uniform52(words[2 * i], words[2 * i + 1]);
+}
+
+/* ======================================================================== */
+/* Designs and draws                                                        */
+/* ======================================================================== */
+
+int64_t or_grid_size(const or_problem *p)
+{
+    int64_t G = 1;
+    for (int j = 0; j < p->d; ++j) G *= p->m[j];
+    return G;
+}
+
+/* Grid design g (row-major, axis 0 slowest): q_j = q_lo + ((q_hi - q_lo) i_j)
+ * / (m_j - 1), each operation rounded separately in this order. */
+void or_grid_point(const or_problem *p, int64_t g, double *q, int32_t *idx)
+{
+    for (int j = p->d - 1; j >= 0; --j) {
+        int64_t i = g % p->m[j];
+        g /= p->m[j];
+        double span = p->q_hi - p->q_lo;
+        double t = span * (double)i;
+        t = t / (double)(p->m[j] - 1);
+        q[j] = p->q_lo + t;
+        if (idx) idx[j] = (int32_t)i;
+    }
+}
+
+/* Design quantities: cutoffs, subgroup fraction r (the proportion r_i of
+ * Sec. 2.1), correlation sqrt(r) of the nested tests (Appendix A.1) and the
+ * critical values from the chosen alpha rule (Formula 2). */
+void or_make_design(const or_problem *p, const double *q, or_design *o)
+{
+    memset(o, 0, sizeof *o);
+    for (int j = 0; j < p->d; ++j) {
+        o->q[j] = q[j];
+        o->c[j] = or_Phiinv(q[j]);
+    }
+    o->r = (p->d == 1) ? 1.0 - q[0] : or_orthant(p->d, o->c, p->rho_b);
+    o->rho = sqrt(o->r);
+    switch (p->alpha_rule) {
+    case OR_ALPHA_FWER_EQUAL:
+        o->z1 = o->z2 = or_zstar(o->r, p->alpha0);
+        break;
+    case OR_ALPHA_BONFERRONI:
+        o->z1 = o->z2 = -or_Phiinv(0.5 * p->alpha0);
+        break;
+    default:
+        o->z1 = p->alpha_fixed[0] > 0.0 ? -or_Phiinv(p->alpha_fixed[0]) : INFINITY;
+        o->z2 = p->alpha_fixed[1] > 0.0 ? -or_Phiinv(p->alpha_fixed[1]) : INFINITY;
+        break;
+    }
+}
+
+/* One draw from the prior f(Delta) of Formula 4.
+ * Step prior: baseline effect b0, extra effect b1 in responders, true cutoff
+ * quantile tau_j per biomarker; responders R = {x_j > Phi^-1(tau_j) all j}.
+ * Paper prior (Formula 10): two standard normals for the Gaussian effects. */
+void or_make_draw(const or_problem *p, uint64_t k, or_draw *o)
+{
+    memset(o, 0, sizeof *o);
+    if (p->effect == OR_EFFECT_STEP) {
+        int d = p->d;
+        draw_uniforms(p, k, 2 + d, o->u);
+        o->b0 = p->mu_b0 + p->sd_b0 * or_Phiinv(o->u[0]);
+        o->b1 = p->mu_b1 + p->sd_b1 * or_Phiinv(o->u[1]);
+        for (int j = 0; j < d; ++j) {
+            double span = p->tau_hi - p->tau_lo;
+            double x = span * o->u[2 + j];
+            o->tau[j] = p->tau_lo + x;
+            o->t[j] = or_Phiinv(o->tau[j]);
+        }
+        o->PR = (d == 1) ? 1.0 - o->tau[0] : or_orthant(d, o->t, p->rho_b);
+    } else {
+        draw_uniforms(p, k, 2, o->u);
+        o->e1 = or_Phiinv(o->u[0]);
+        o->e2 = or_Phiinv(o->u[1]);
+    }
+}
+
+static double logistic(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+/* Fraction of the population that is both in the subgroup S and a responder:
+ * P(x_j > max(c_j, t_j) for all j).  Axis j takes c_j when q_j > tau_j.  With a
+ * logistic width w > 0 the axis factor is the mix s_j [cut at c_j] +
+ * (1 - s_j) [cut at t_j], s_j = 1 / (1 + exp(-(q_j - tau_j)/w)). */
+double or_overlap(const or_problem *p, const or_design *ds, const or_draw *dr)
+{
+    int d = p->d;
+    if (d == 1) {
+        double q = ds->q[0], tau = dr->tau[0];
+        if (p->width > 0.0) {
+            double s = logistic((q - tau) / p->width);
+            return 1.0 - (s * q + (1.0 - s) * tau);
+        }
+        return 1.0 - (q > tau ? q : tau);
+    }
+    orth_ctx o;
+    memset(&o, 0, sizeof o);
+    o.d = d;
+    for (int j = 0; j < d; ++j) {
+        if (p->width > 0.0) {
+            o.kind[j] = FK_MIX;
+            o.c[j] = ds->c[j];
+            o.t[j] = dr->t[j];
+            o.s[j] = logistic((ds->q[j] - dr->tau[j]) / p->width);
+        } else {
+            o.kind[j] = FK_CUT;
+            o.c[j] = (ds->q[j] > dr->tau[j]) ? ds->c[j] : dr->t[j];
+        }
+    }
+    return orth_integral(&o, p->rho_b);
+}
+
+/* Effects on the paper's Delta scale for the two populations. */
+static void effects(const or_problem *p, const or_design *ds, const or_draw *dr,
+                    double *d1, double *d2, double *O_out)
+{
+    if (p->effect == OR_EFFECT_STEP) {
+        double O = or_overlap(p, ds, dr);
+        *d1 = dr->b0 + dr->b1 * dr->PR;
+        *d2 = dr->b0 + dr->b1 * O / ds->r;
+        if (O_out) *O_out = O;
+    } else {
+        double r = ds->r, E = p->paper_events;
+        double th1 = -log1p(-(p->paper_a - p->paper_b));
+        double th2 = -log1p(-(p->paper_a - p->paper_b * r));
+        double s1 = 1.0 / sqrt(E / 4.0), s2 = 1.0 / sqrt(E * r / 4.0);
+        *d1 = th1 + s1 * dr->e1;
+        *d2 = th2 + s2 * (sqrt(r) * dr->e1 + sqrt(1.0 - r) * dr->e2);
+        if (O_out) *O_out = 0.0;
+    }
+}
+
+/* Success probability for one design and one draw: one minus the CDF of the
+ * alternative distribution (Formula 3) at the critical values, i.e. one
+ * summand of Formula 5. */
+double or_success(const or_problem *p, const or_design *ds, const or_draw *dr)
+{
+    double d1, d2;
+    effects(p, ds, dr, &d1, &d2, NULL);
+    double mu1 = sqrt(p->info) * d1;
+    double mu2 = sqrt(ds->r * p->info) * d2;
+    return 1.0 - or_bvn(ds->z1 - mu1, ds->z2 - mu2, ds->rho);
+}
+
+/* ======================================================================== */
+/* Monte Carlo estimate (Formula 5)                                         */
+/* ======================================================================== */
+
+static double pairwise_sum(const double *x, int64_t n)
+{
+    if (n <= 8) {
+        double s = 0.0;
+        for (int64_t i = 0; i < n; ++i) s += x[i];
+        return s;
+    }
+    int64_t h = n / 2;
+    return pairwise_sum(x, h) + pairwise_sum(x + h, n - h);
+}
+
+static void mean_var(double *vals, int64_t M, double *mean, double *var)
+{
+    double m = pairwise_sum(vals, M) / (double)M;
+    *mean = m;
+    if (var) {
+        for (int64_t k = 0; k < M; ++k) vals[k] = (vals[k] - m) * (vals[k] - m);
+        *var = M > 1 ? pairwise_sum(vals, M) / (double)(M - 1) : 0.0;
+    }
+}
+
+static or_draw *make_draws(const or_problem *p, uint64_t k0, uint64_t M)
+{
+    or_draw *dr = (or_draw *)malloc(sizeof(or_draw) * (size_t)M);
+    if (!dr) return NULL;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < (int64_t)M; ++k) or_make_draw(p, k0 + (uint64_t)k, &dr[k]);
+    return dr;
+}
+
+void or_eval_points(const or_problem *p, int64_t n, const double *q,
+                    uint64_t k0, uint64_t M, double *mean, double *var)
+{
+    or_draw *dr = make_draws(p, k0, M);
+    double *vals = (double *)malloc(sizeof(double) * (size_t)M);
+    if (!dr || !vals) { free(dr); free(vals); return; }
+    for (int64_t i = 0; i < n; ++i) {
+        or_design ds;
+        or_make_design(p, q + i * p->d, &ds);
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t k = 0; k < (int64_t)M; ++k) vals[k] = or_success(p, &ds, &dr[k]);
+        mean_var(vals, (int64_t)M, &mean[i], var ? &var[i] : NULL);
+    }
+    free(vals);
+    free(dr);
+}
+
+void or_eval_grid(const or_problem *p, int64_t n, const int64_t *g_list,
+                  uint64_t k0, uint64_t M, double *mean, double *var)
+{
+    double *q = (double *)malloc(sizeof(double) * (size_t)(n * p->d));
+    if (!q) return;
+    for (int64_t i = 0; i < n; ++i) or_grid_point(p, g_list[i], q + i * p->d, NULL);
+    or_eval_points(p, n, q, k0, M, mean, var);
+    free(q);
+}
+
+/* ======================================================================== */
+/* Smoothing and argmax                                                     */
+/* ======================================================================== */
+/*
+ * Nadaraya-Watson smoothing of the grid surface with a product Gaussian
+ * kernel K(g,h) = prod_j exp(-((q_j(g) - q_j(h)) / b_j)^2 / 2), untruncated:
+ * S(g) = sum_h K(g,h) f(h) / sum_h K(g,h).  This stands in for the paper's
+ * thin-plate-spline fit of the noisy estimates (Sec. 2.3).
+ */
+void or_smooth_direct(const or_problem *p, const double *in, double *out)
+{
+    int d = p->d;
+    int64_t G = or_grid_size(p);
+    double *q = (double *)malloc(sizeof(double) * (size_t)(G * d));
+    if (!q) return;
+    for (int64_t g = 0; g < G; ++g) or_grid_point(p, g, q + g * d, NULL);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t g = 0; g < G; ++g) {
+        double num = 0.0, den = 0.0;
+        for (int64_t h = 0; h < G; ++h) {
+            double e = 0.0;
+            for (int j = 0; j < d; ++j) {
+                double x = (q[g * d + j] - q[h * d + j]) / p->bandwidth[j];
+                e += -0.5 * x * x;
+            }
+            double w = exp(e);
+            num += w * in[h];
+            den += w;
+        }
+        out[g] = num / den;
+    }
+    free(q);
+}
+
+/* The same smoother through its factorisation: the row-normalised product
+ * kernel is the product of row-normalised one-axis kernels, applied one axis
+ * at a time. */
+void or_smooth_separable(const or_problem *p, const double *in, double *out)
+{
+    int d = p->d;
+    int64_t G = or_grid_size(p);
+    double *a = (double *)malloc(sizeof(double) * (size_t)G);
+    double *b = (double *)malloc(sizeof(double) * (size_t)G);
+    if (!a || !b) { free(a); free(b); return; }
+    memcpy(a, in, sizeof(double) * (size_t)G);
+    int64_t inner = G;
+    for (int j = 0; j < d; ++j) {
+        int m = p->m[j];
+        inner /= m;                    /* product of axis sizes after j */
+        int64_t outer = G / (inner * m);
+        double *W = (double *)malloc(sizeof(double) * (size_t)m * m);
+        double *qa = (double *)malloc(sizeof(double) * (size_t)m);
+        for (int i = 0; i < m; ++i) {
+            double span = p->q_hi - p->q_lo;
+            double t = span * (double)i;
+            t = t / (double)(m - 1);
+            qa[i] = p->q_lo + t;
+        }
+        for (int i = 0; i < m; ++i) {
+            double den = 0.0;
+            for (int h = 0; h < m; ++h) {
+                double x = (qa[i] - qa[h]) / p->bandwidth[j];
+                W[i * m + h] = exp(-0.5 * x * x);
+                den += W[i * m + h];
+            }
+            for (int h = 0; h < m; ++h) W[i * m + h] /= den;
+        }
+#pragma omp parallel for schedule(static)
+        for (int64_t o = 0; o < outer; ++o)
+            for (int i = 0; i < m; ++i)
+                for (int64_t s = 0; s < inner; ++s) {
+                    double acc = 0.0;
+                    for (int h = 0; h < m; ++h) acc += W[i * m + h] * a[(o * m + h) * inner + s];
+                    b[(o * m + i) * inner + s] = acc;
+                }
+        double *tmp = a; a = b; b = tmp;
+        free(W);
+        free(qa);
+    }
+    memcpy(out, a, sizeof(double) * (size_t)G);
+    free(a);
+    free(b);
+}
+
+/* Index of the largest value; ties go to the lowest index (the best point on
+ * the smoothed surface, Sec. 2.3). */
+int64_t or_argmax(int64_t n, const double *v)
+{
+    int64_t best = 0;
+    for (int64_t i = 1; i < n; ++i)
+        if (v[i] > v[best]) best = i;
+    return best;
+}
+
+/* ======================================================================== */
+/* Gradient: forward-mode derivatives on the same draws                     */
+/* ======================================================================== */
+
+typedef struct {
+    double dr[6];     /* d r / d q_j     */
+    double drho[6];   /* d sqrt(r)/d q_j */
+    double dz1[6], dz2[6];
+} design_tangent;
+
+/* d r / d q_j for the subgroup fraction, and the implicit derivative of the
+ * common critical value through Formula 2:
+ *   dz/drho = -phi_2(z,z;rho) / (2 phi(z) Phi(z sqrt((1-rho)/(1+rho)))). */
+static void design_derivs(const or_problem *p, const or_design *ds, design_tangent *t)
+{
+    memset(t, 0, sizeof *t);
+    int d = p->d;
+    for (int j = 0; j < d; ++j) {
+        if (d == 1) {
+            t->dr[j] = -1.0;
+        } else {
+            orth_ctx o;
+            memset(&o, 0, sizeof o);
+            o.d = d;
+            for (int l = 0; l < d; ++l) { o.c[l] = ds->c[l]; o.kind[l] = FK_CUT; }
+            o.kind[j] = FK_DENS;
+            double I = orth_integral(&o, p->rho_b);
+            t->dr[j] = -I / sqrt(1.0 - p->rho_b) / or_phi(ds->c[j]);
+        }
+        t->drho[j] = t->dr[j] / (2.0 * ds->rho);
+    }
+    if (p->alpha_rule == OR_ALPHA_FWER_EQUAL) {
+        double z = ds->z1, rho = ds->rho;
+        double dzdrho = -or_bvn_density(z, z, rho) /
+                        (2.0 * or_phi(z) * or_Phi(z * sqrt((1.0 - rho) / (1.0 + rho))));
+        for (int j = 0; j < d; ++j) t->dz1[j] = t->dz2[j] = dzdrho * t->drho[j];
+    }
+}
+
+/* d O / d q_j for one draw. */
+static void overlap_derivs(const or_problem *p, const or_design *ds, const or_draw *dr,
+                           double *dO)
+{
+    int d = p->d;
+    double w = p->width;
+    if (d == 1) {
+        double q = ds->q[0], tau = dr->tau[0];
+        if (w > 0.0) {
+            double s = logistic((q - tau) / w);
+            double sp = s * (1.0 - s) / w;
+            dO[0] = -(s + sp * (q - tau));
+        } else {
+            dO[0] = (q > tau) ? -1.0 : 0.0;
+        }
+        return;
+    }
+    double isq = 1.0 / sqrt(1.0 - p->rho_b);
+    for (int j = 0; j < d; ++j) {
+        orth_ctx o;
+        memset(&o, 0, sizeof o);
+        o.d = d;
+        if (w > 0.0) {
+            double s[6];
+            for (int l = 0; l < d; ++l) {
+                s[l] = logistic((ds->q[l] - dr->tau[l]) / w);
+                o.kind[l] = FK_MIX; o.c[l] = ds->c[l]; o.t[l] = dr->t[l]; o.s[l] = s[l];
+            }
+            /* d/dq_j of [s Phi(a) + (1-s) Phi(b)] = s' (Phi(a) - Phi(b))
+             *   + s phi(a) (-1/sqrt(1-rho_b)) (1/phi(c_j)). */
+            double sp = s[j] * (1.0 - s[j]) / w;
+            o.kind[j] = FK_DMIX;
+            double Ia = orth_integral(&o, p->rho_b);
+            o.kind[j] = FK_DENS;
+            double Ib = orth_integral(&o, p->rho_b);
+            dO[j] = sp * Ia - s[j] * Ib * isq / or_phi(ds->c[j]);
+        } else {
+            int flag = ds->q[j] > dr->tau[j];
+            if (!flag) { dO[j] = 0.0; continue; }
+            for (int l = 0; l < d; ++l) {
+                o.kind[l] = FK_CUT;
+                o.c[l] = (ds->q[l] > dr->tau[l]) ? ds->c[l] : dr->t[l];
+            }
+            o.kind[j] = FK_DENS;
+            double I = orth_integral(&o, p->rho_b);
+            dO[j] = -I * isq / or_phi(ds->c[j]);
+        }
+    }
+}
+
+void or_grad_points(const or_problem *p, int64_t n, const double *q,
+                    uint64_t k0, uint64_t M, double *obj,
+                    double *grad_q, double *grad_mu)
+{
+    int d = p->d;
+    int nv = d + 3;                       /* value, d design partials, two mu partials */
+    or_draw *dr = make_draws(p, k0, M);
+    double *vals = (double *)malloc(sizeof(double) * (size_t)M * nv);
+    double *col = (double *)malloc(sizeof(double) * (size_t)M);
+    if (!dr || !vals || !col) { free(dr); free(vals); free(col); return; }
+    double sI = sqrt(p->info);
+    for (int64_t i = 0; i < n; ++i) {
+        or_design ds;
+        design_tangent tg;
+        or_make_design(p, q + i * d, &ds);
+        design_derivs(p, &ds, &tg);
+        double r = ds.r, sr = sqrt(r), srI = sqrt(r * p->info);
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t k = 0; k < (int64_t)M; ++k) {
+            const or_draw *w = &dr[k];
+            double d1, d2, O, dO[6];
+            effects(p, &ds, w, &d1, &d2, &O);
+            overlap_derivs(p, &ds, w, dO);
+            double h = ds.z1 - sI * d1, kk = ds.z2 - srI * d2, rho = ds.rho;
+            double pv = or_bvn(h, kk, rho);
+            double om = sqrt((1.0 - rho) * (1.0 + rho));
+            double ph, pk, pr;
+            if (kk == INFINITY) { ph = or_phi(h); pk = 0.0; pr = 0.0; }
+            else if (h == INFINITY) { ph = 0.0; pk = or_phi(kk); pr = 0.0; }
+            else {
+                ph = or_phi(h) * or_Phi((kk - rho * h) / om);
+                pk = or_phi(kk) * or_Phi((h - rho * kk) / om);
+                pr = or_bvn_density(h, kk, rho);
+            }
+            double *v = vals + (size_t)k * nv;
+            v[0] = 1.0 - pv;
+            for (int j = 0; j < d; ++j) {
+                double drj = tg.dr[j];
+                double dmu2 = sI * (w->b0 * drj / (2.0 * sr) +
+                                    w->b1 * (dO[j] / sr - O * drj / (2.0 * r * sr)));
+                double dh = tg.dz1[j];
+                double dk = tg.dz2[j] - dmu2;
+                v[1 + j] = -(ph * dh + pk * dk + pr * tg.drho[j]);
+            }
+            v[1 + d] = -(ph * (-sI) + pk * (-srI));
+            v[2 + d] = -(ph * (-sI * w->PR) + pk * (-srI * O / r));
+        }
+        for (int c = 0; c < nv; ++c) {
+            for (int64_t k = 0; k < (int64_t)M; ++k) col[k] = vals[(size_t)k * nv + c];
+            double m;
+            mean_var(col, (int64_t)M, &m, NULL);
+            if (c == 0) obj[i] = m;
+            else if (c <= d) grad_q[i * d + (c - 1)] = m;
+            else grad_mu[i * 2 + (c - 1 - d)] = m;
+        }
+    }
+    free(col);
+    free(vals);
+    free(dr);
+}
+
+/* ======================================================================== */
+/* Exact expectations                                                       */
+/* ======================================================================== */
+/*
+ * Step prior: given the true cutoffs tau, (Delta_1, Delta_2) is a linear map
+ * A(tau) of the Gaussian (b0, b1), so the two Z-statistics are jointly normal
+ * with mean S A mu_b and covariance Sigma_Z + S A Sigma_b A' S, S =
+ * diag(sqrt(I), sqrt(r I)).  The conditional failure probability is then one
+ * bivariate normal CDF, and the expected power integrates it over the uniform
+ * prior of tau, split where tau_j crosses q_j (the kink of max(c_j, t_j)).
+ */
+static double cond_fail(const or_problem *p, const or_design *ds, const double *tau)
+{
+    int d = p->d;
+    or_draw dr;
+    memset(&dr, 0, sizeof dr);
+    for (int j = 0; j < d; ++j) { dr.tau[j] = tau[j]; dr.t[j] = or_Phiinv(tau[j]); }
+    dr.PR = (d == 1) ? 1.0 - tau[0] : or_orthant(d, dr.t, p->rho_b);
+    double O = or_overlap(p, ds, &dr);
+    double r = ds->r, I = p->info;
+    double a1 = dr.PR, a2 = O / r;           /* rows (1, a1) and (1, a2) of A */
+    double m1 = sqrt(I) * (p->mu_b0 + p->mu_b1 * a1);
+    double m2 = sqrt(r * I) * (p->mu_b0 + p->mu_b1 * a2);
+    double v0 = p->sd_b0 * p->sd_b0, v1 = p->sd_b1 * p->sd_b1;
+    double V11 = 1.0 + I * (v0 + v1 * a1 * a1);
+    double V22 = 1.0 + r * I * (v0 + v1 * a2 * a2);
+    double V12 = sqrt(r) + sqrt(I) * sqrt(r * I) * (v0 + v1 * a1 * a2);
+    double s1 = sqrt(V11), s2 = sqrt(V22);
+    return or_bvn((ds->z1 - m1) / s1, (ds->z2 - m2) / s2, V12 / (s1 * s2));
+}
+
+typedef struct {
+    const or_problem *p;
+    const or_design *ds;
+    double tau[2];
+    int axis;
+} exact_ctx;
+
+static double exact_integrand(double x, void *v);
+
+/* Integral over tau_axis..tau_{d-1} of cond_fail, with earlier taus fixed. */
+static double exact_level(exact_ctx *e)
+{
+    const or_problem *p = e->p;
+    double lo = p->tau_lo, hi = p->tau_hi;
+    if (hi <= lo) {
+        e->tau[e->axis] = lo;
+        if (e->axis + 1 == p->d) return cond_fail(p, e->ds, e->tau);
+        exact_ctx in = *e;
+        in.axis = e->axis + 1;
+        return exact_level(&in);
+    }
+    double s = e->ds->q[e->axis];
+    if (s < lo) s = lo;
+    if (s > hi) s = hi;
+    double tot = 0.0;
+    if (s > lo) tot += or_quad(exact_integrand, e, lo, s);
+    if (hi > s) tot += or_quad(exact_integrand, e, s, hi);
+    return tot / (hi - lo);
+}
+
+static double exact_integrand(double x, void *v)
+{
+    exact_ctx *e = (exact_ctx *)v;
+    exact_ctx in = *e;
+    in.tau[e->axis] = x;
+    if (e->axis + 1 == e->p->d) return cond_fail(e->p, e->ds, in.tau);
+    in.axis = e->axis + 1;
+    return exact_level(&in);
+}
+
+double or_exact_step(const or_problem *p, const double *q)
+{
+    if (p->d > 2 || p->effect != OR_EFFECT_STEP) return NAN;
+    or_design ds;
+    or_make_design(p, q, &ds);
+    exact_ctx e = {p, &ds, {0.0, 0.0}, 0};
+    return 1.0 - exact_level(&e);
+}
+
+/* Paper prior (Formula 10) on the two nested populations: Delta ~
+ * N(theta, Sigma_p) with theta_i = -log(1 - D0(r_i)), sigma_i = 1/sqrt(E r_i/4)
+ * and correlation sqrt(r_2/r_1); then X ~ N(D theta, Sigma_Z + D Sigma_p D). */
+double or_exact_paper(const or_problem *p, const double *q)
+{
+    if (p->effect != OR_EFFECT_PAPER_GAUSS) return NAN;
+    or_design ds;
+    or_make_design(p, q, &ds);
+    double r = ds.r, I = p->info, E = p->paper_events;
+    double th1 = -log1p(-(p->paper_a - p->paper_b));
+    double th2 = -log1p(-(p->paper_a - p->paper_b * r));
+    double sg1 = 1.0 / sqrt(E / 4.0), sg2 = 1.0 / sqrt(E * r / 4.0);
+    double m1 = sqrt(I) * th1, m2 = sqrt(r * I) * th2;
+    double V11 = 1.0 + I * sg1 * sg1;
+    double V22 = 1.0 + r * I * sg2 * sg2;
+    double V12 = sqrt(r) + sqrt(I) * sqrt(r * I) * sqrt(r) * sg1 * sg2;
+    double s1 = sqrt(V11), s2 = sqrt(V22);
+    return 1.0 - or_bvn((ds.z1 - m1) / s1, (ds.z2 - m2) / s2, V12 / (s1 * s2));
+}

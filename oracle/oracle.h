@@ -1,0 +1,120 @@
+/*
+ * Plain CPU oracle for the biomarker-cutoff design objective of
+ * Lu, Zhou, Xing & Zhang, "The Optimal Design of Clinical Trials with
+ * Potential Biomarker Effects, A Novel Computational Approach" (arXiv 2005.10494).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this code; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or constant
+ * generator with the HIP implementation.
+ *
+ * Everything is FP64 and written for clarity, not speed: integrals are
+ * evaluated by adaptive Gauss-Kronrod quadrature of their defining
+ * one-dimensional forms, roots by bisection, sums by pairwise summation.
+ *
+ * Reading of the paper used throughout (the "signature" reading):
+ *   - d correlated biomarkers X ~ N_d(0, (1-rho_b) I + rho_b 11'), one cutoff
+ *     quantile q_j per biomarker; the subgroup S = {x_j > Phi^-1(q_j) for all j}
+ *     has population fraction r (Sec. 2.1, the proportion r_i of a subset).
+ *   - two nested tests, full population and S, so the null Z-correlation is
+ *     sqrt(r) (Formula 1, Appendix A.1).
+ *   - equal critical values chosen so the family-wise error equals alpha0
+ *     (Formula 2), or Bonferroni, or fixed levels.
+ *   - expected power over a prior on the effects (Formula 4), estimated by the
+ *     outer Monte Carlo average of Formula 5 with an exact bivariate normal CDF.
+ */
+#ifndef BMD_ORACLE_H
+#define BMD_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_ALPHA_FWER_EQUAL = 0, OR_ALPHA_BONFERRONI = 1, OR_ALPHA_FIXED = 2 };
+enum { OR_EFFECT_STEP = 0, OR_EFFECT_PAPER_GAUSS = 1 };
+
+typedef struct {
+    int32_t d;              /* number of biomarkers (cutoff axes), 1..6          */
+    int32_t m[6];           /* grid points per axis (grid problems only)         */
+    double q_lo, q_hi;      /* cutoff-quantile range of the grid                 */
+    double rho_b;           /* biomarker equicorrelation, 0 <= rho_b < 1         */
+    double info;            /* information units I (paper: I_3)                 */
+    double alpha0;          /* family-wise error rate                            */
+    int32_t alpha_rule;     /* OR_ALPHA_*                                        */
+    double alpha_fixed[2];  /* fixed levels (rule FIXED); 0 switches a test off  */
+    int32_t effect;         /* OR_EFFECT_*                                       */
+    double mu_b0, sd_b0;    /* step prior: baseline effect ~ N(mu_b0, sd_b0^2)   */
+    double mu_b1, sd_b1;    /* step prior: responder effect ~ N(mu_b1, sd_b1^2)  */
+    double tau_lo, tau_hi;  /* step prior: true cutoff quantile ~ U(lo, hi)      */
+    double paper_a, paper_b, paper_events; /* Formula 10: D0(r)=a-b r, E events  */
+    double width;           /* logistic indicator width (0 = exact indicator)    */
+    double bandwidth[6];    /* Gaussian smoothing sd per axis, quantile units    */
+    uint64_t seed;          /* Philox key                                        */
+    uint32_t scenario;      /* third Philox counter word                         */
+} or_problem;
+
+/* A design: cutoff quantiles and every quantity that depends on them only. */
+typedef struct {
+    double q[6], c[6];      /* quantiles and cutoffs c_j = Phi^-1(q_j)           */
+    double r;               /* subgroup fraction                                 */
+    double rho;             /* sqrt(r): null correlation of the two Z-statistics */
+    double z1, z2;          /* critical values (may be +inf)                     */
+} or_design;
+
+/* One Monte Carlo draw of the effect parameters. */
+typedef struct {
+    double u[8];            /* the uniforms consumed by the draw                 */
+    double b0, b1;          /* step prior effects                                */
+    double tau[6], t[6];    /* true cutoff quantiles and cutoffs                 */
+    double PR;              /* population fraction of responders                 */
+    double e1, e2;          /* standard normals (paper Gaussian prior)           */
+} or_draw;
+
+/* ---- primitives -------------------------------------------------------- */
+double or_Phi(double x);                 /* standard normal CDF (libm erfc)   */
+double or_phi(double x);                 /* standard normal density           */
+double or_Phiinv(double p);              /* root of Phi(x) = p                */
+double or_quad(double (*f)(double, void *), void *ctx, double a, double b);
+double or_bvn(double h, double k, double rho);     /* P(X<=h, Y<=k)          */
+double or_bvn_density(double h, double k, double rho);
+double or_orthant(int d, const double *v, double rho_b);   /* P(X_j > v_j)    */
+double or_zstar(double r, double alpha0);
+double or_info_units(double alpha, double beta, double delta);
+void   or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double or_uniform52(uint32_t wa, uint32_t wb);
+
+/* ---- model ------------------------------------------------------------- */
+void   or_grid_point(const or_problem *p, int64_t g, double *q, int32_t *idx);
+int64_t or_grid_size(const or_problem *p);
+void   or_make_design(const or_problem *p, const double *q, or_design *out);
+void   or_make_draw(const or_problem *p, uint64_t k, or_draw *out);
+double or_overlap(const or_problem *p, const or_design *ds, const or_draw *dr);
+double or_success(const or_problem *p, const or_design *ds, const or_draw *dr);
+
+/* MC estimate (Formula 5) over draws k0..k0+M-1 at n design points q[n*d].
+ * mean[i] = average success probability, var[i] = its sample variance. */
+void   or_eval_points(const or_problem *p, int64_t n, const double *q,
+                      uint64_t k0, uint64_t M, double *mean, double *var);
+/* Same, at grid designs g_list[n]. */
+void   or_eval_grid(const or_problem *p, int64_t n, const int64_t *g_list,
+                    uint64_t k0, uint64_t M, double *mean, double *var);
+
+/* ---- smoothing and argmax ---------------------------------------------- */
+void   or_smooth_direct(const or_problem *p, const double *in, double *out);
+void   or_smooth_separable(const or_problem *p, const double *in, double *out);
+int64_t or_argmax(int64_t n, const double *v);
+
+/* ---- gradient (forward mode, same draws) -------------------------------- */
+void   or_grad_points(const or_problem *p, int64_t n, const double *q,
+                      uint64_t k0, uint64_t M, double *obj,
+                      double *grad_q, double *grad_mu);
+
+/* ---- exact expectation (no Monte Carlo) -------------------------------- */
+double or_exact_step(const or_problem *p, const double *q);    /* d <= 2 */
+double or_exact_paper(const or_problem *p, const double *q);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,95 @@
+"""Seeded synthetic workloads: problem descriptors and input generators.
+
+This module holds only inputs (problem settings, seeds, design points drawn for
+the continuous form, the batch of scenarios).  It contains none of the method's
+arithmetic, so both the HIP path and the CPU oracle may use it.
+
+The paper measures on no dataset; its experiments are simulation settings
+(Sec. 3).  The workloads below mirror those settings for a biomarker-cutoff
+design: a 1-D cutoff grid, a 3-D grid of three correlated biomarkers, a 5-D
+grid, a continuous 5-D design batch for gradients, and a batch of uneven
+scenarios.  Priors: baseline effect ~ N(0, 0.1^2), extra responder effect ~
+N(0.5, 0.2^2), true cutoff quantile ~ U(0.2, 0.8); n = 200 patients per arm,
+so I = n/2 = 100 information units (the paper's I_3 is a quarter of the total
+events, Sec. 2.1; with 400 patients all having events I_3 = 100).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+STEP_PRIOR = dict(mu_b0=0.0, sd_b0=0.1, mu_b1=0.5, sd_b1=0.2, tau_lo=0.2, tau_hi=0.8)
+
+#: grid points per axis used by the batch scenarios, indexed by d - 1
+BATCH_M = (201, 64, 40, 24, 14, 10)
+
+
+def base_problem(d: int, m, rho_b: float, bandwidth: float, **kw) -> dict:
+    p = dict(d=d, m=list(m) if m is not None else None, q_lo=0.05, q_hi=0.95, rho_b=rho_b,
+             info=100.0, alpha0=0.025, alpha_rule="fwer", alpha_fixed=(0.0, 0.0),
+             effect="step", paper_a=0.0, paper_b=0.0, paper_events=80.0, width=0.0,
+             bandwidth=[bandwidth] * d, gh_nodes=0, seed=0, scenario=0)
+    p.update(STEP_PRIOR)
+    p.update(kw)
+    return p
+
+
+def plain_1d() -> dict:
+    """One biomarker, 201-point cutoff grid, M = 10,000 draws, bandwidth 0.02."""
+    p = base_problem(1, [201], 0.0, 0.02)
+    p["n_draws"] = 10_000
+    return p
+
+
+def plain_3d() -> dict:
+    """Three biomarkers (correlation 0.3), 64^3 grid, M = 100,000, bandwidth 0.03."""
+    p = base_problem(3, [64, 64, 64], 0.3, 0.03)
+    p["n_draws"] = 100_000
+    return p
+
+
+def precision_5d() -> dict:
+    """Five biomarkers (correlation 0.3), 24^5 grid, M = 200,000, bandwidth 0.03."""
+    p = base_problem(5, [24] * 5, 0.3, 0.03)
+    p["n_draws"] = 200_000
+    return p
+
+
+def grad_5d() -> dict:
+    """Continuous 5-D designs, logistic indicator width 0.01, M = 1,000,000."""
+    p = base_problem(5, None, 0.3, 0.03, width=0.01)
+    p["n_draws"] = 1_000_000
+    p["n_points"] = 4096
+    return p
+
+
+def design_points(n: int, d: int, seed: int = 1, lo: float = 0.1, hi: float = 0.9) -> np.ndarray:
+    """Continuous design points, iid U(lo, hi)^d (cutoff quantiles)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=(n, d))
+
+
+def batch_scenarios(n: int = 256, seed: int = 2, m_scale: float = 1.0,
+                    m_draws=(1e4, 1e6)) -> list:
+    """Uneven scenarios: d ~ U{1..6}, per-axis grid from ``BATCH_M`` (optionally
+    scaled down for tests), M log-uniform in ``m_draws``, n per arm U{100..400},
+    rho_b ~ U(0, 0.5), prior means (responder effect, centre of the true-cutoff
+    interval) scaled by a factor in [0.8, 1.2].  Scenario i uses Philox
+    counter word ``scenario = i``."""
+    rng = np.random.default_rng(seed)
+    out = []
+    lo, hi = np.log10(m_draws[0]), np.log10(m_draws[1])
+    for i in range(n):
+        d = int(rng.integers(1, 7))
+        m = max(2, int(round(BATCH_M[d - 1] * m_scale)))
+        n_arm = int(rng.integers(100, 401))
+        rho_b = float(rng.uniform(0.0, 0.5))
+        f1 = 1.0 + 0.4 * (float(rng.uniform()) - 0.5)
+        f2 = 1.0 + 0.4 * (float(rng.uniform()) - 0.5)
+        M = int(round(10 ** rng.uniform(lo, hi)))
+        p = base_problem(d, [m] * d, rho_b, 0.03, info=n_arm / 2.0, scenario=i)
+        p["mu_b1"] = STEP_PRIOR["mu_b1"] * f1
+        centre = 0.5 * f2
+        p["tau_lo"], p["tau_hi"] = centre - 0.3, centre + 0.3
+        p["n_draws"] = M
+        out.append(p)
+    return out

@@ -1,0 +1,193 @@
+/*
+ * bmd.h - C ABI of the MI355X (gfx950) hot path for optimal biomarker-cutoff
+ * trial designs, after Lu, Zhou, Xing & Zhang, "The Optimal Design of Clinical
+ * Trials with Potential Biomarker Effects, A Novel Computational Approach"
+ * (arXiv 2005.10494).
+ *
+ * The method (Sec. 2): the expected power of a trial that tests the full
+ * population and a biomarker-defined subgroup (Formula 4) is estimated by an
+ * outer Monte Carlo average over prior draws of the effects (Formula 5), at
+ * every point of a grid of candidate designs; the noisy surface is smoothed
+ * (Sec. 2.3) and its maximiser is the design (Sec. 2.4).  Here a design is a
+ * vector of biomarker cutoff quantiles q (one per biomarker), the subgroup is
+ * S = {x_j > Phi^-1(q_j) for all j}, its population fraction r plays the role
+ * of the paper's r_2 (Sec. 2.1), the two Z-statistics have null correlation
+ * sqrt(r) (Formula 1, Appendix A.1), and Phi_Sigma is a bivariate normal CDF
+ * evaluated in closed quadrature form rather than by the paper's inner
+ * sampling layer (Formula 6).
+ *
+ * Conventions for every entry point:
+ *   - Status codes are returned; nothing throws across the ABI.  On failure
+ *     bmd_last_error() describes the cause (thread-local, valid until the next
+ *     call from the same thread).  Outputs are then unspecified and the
+ *     problem stays usable.
+ *   - Arguments are validated on the host before any launch.
+ *   - Pointers named d_* are device pointers (HBM of the current device),
+ *     h_* are host pointers.  The caller owns every output buffer; the problem
+ *     owns its device constants and workspace.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *     asynchronous on the stream unless stated otherwise.
+ *   - A problem is used from one host thread at a time; calls on one problem
+ *     must not overlap on different streams.
+ */
+#ifndef BMD_H
+#define BMD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BMD_ABI_VERSION 1
+#define BMD_MAX_DIM 6
+
+typedef struct bmd_problem bmd_problem;
+
+typedef enum {
+    BMD_OK = 0,
+    BMD_EINVAL = -1,   /* invalid argument (NULL pointer, bad enum, non-finite) */
+    BMD_ERANGE = -2,   /* argument outside the supported range                 */
+    BMD_ENOMEM = -3,   /* device or host allocation failed                     */
+    BMD_EDEVICE = -4,  /* a HIP call or kernel launch failed                   */
+    BMD_ENOTSUP = -5,  /* combination not supported by this entry point        */
+    BMD_ESTATE = -6    /* call not valid for this problem (e.g. grid vs points)*/
+} bmd_status;
+
+typedef enum {
+    BMD_FP64 = 0,       /* integrand, sums and smoothing in FP64                */
+    BMD_FP32_COMP = 1   /* FP32 integrand, FP64 per-design sums, FP32 smoothing */
+} bmd_precision;
+
+/* Critical values of the two tests (Formula 2 and its alternatives, Sec. 1). */
+typedef enum {
+    BMD_ALPHA_FWER_EQUAL = 0,  /* z1 = z2 = z*, 1 - Phi_2(z*, z*; sqrt r) = alpha0 */
+    BMD_ALPHA_BONFERRONI = 1,  /* z1 = z2 = Phi^-1(1 - alpha0/2)                   */
+    BMD_ALPHA_FIXED = 2        /* z_i = Phi^-1(1 - alpha_fixed[i]); 0 = test off   */
+} bmd_alpha_rule;
+
+/* Prior f(Delta) of Formula 4. */
+typedef enum {
+    /* Baseline effect b0 ~ N(mu_b0, sd_b0^2), extra effect b1 ~ N(mu_b1, sd_b1^2)
+     * in responders R = {x_j > Phi^-1(tau_j) all j}, true cutoff quantiles
+     * tau_j ~ U(tau_lo, tau_hi) iid.  Population-average effects:
+     * Delta_1 = b0 + b1 P(R), Delta_2 = b0 + b1 P(R and S) / r. */
+    BMD_EFFECT_STEP = 0,
+    /* Formula 10 on the two nested populations: Delta ~ N(theta, Sigma_p) with
+     * theta_i = -log(1 - (paper_a - paper_b r_i)), sigma_i = 1/sqrt(E r_i / 4),
+     * corr(Delta_1, Delta_2) = sqrt(r), r_1 = 1, r_2 = r, E = paper_events. */
+    BMD_EFFECT_PAPER_GAUSS = 1
+} bmd_effect_model;
+
+/* Problem descriptor (copied by bmd_create_problem). */
+typedef struct {
+    int32_t d;                 /* number of biomarkers / cutoff axes, 1..6          */
+    int32_t m[BMD_MAX_DIM];    /* grid points per axis (>= 2 for j < d); all zero =>
+                                  continuous-design problem (bmd_grad_design only)  */
+    double q_lo, q_hi;         /* cutoff-quantile range, 0 < q_lo < q_hi < 1; grid
+                                  q_j,i = q_lo + ((q_hi - q_lo) i) / (m_j - 1)       */
+    double rho_b;              /* biomarker equicorrelation, 0 <= rho_b <= 0.5      */
+    double info;               /* information units I (paper I_3), > 0              */
+    double alpha0;             /* family-wise error rate, 0 < alpha0 < 0.5          */
+    int32_t alpha_rule;        /* bmd_alpha_rule                                    */
+    double alpha_fixed[2];     /* levels for BMD_ALPHA_FIXED, each in [0, 0.5)      */
+    int32_t effect;            /* bmd_effect_model                                  */
+    double mu_b0, sd_b0;       /* step prior, sd >= 0 (0 = point mass)              */
+    double mu_b1, sd_b1;
+    double tau_lo, tau_hi;     /* 0 < tau_lo <= tau_hi < 1                          */
+    double paper_a, paper_b;   /* Formula 10 effect D0(r) = a - b r, D0 < 1         */
+    double paper_events;       /* E in sigma_i = 1/sqrt(E r_i / 4), > 0             */
+    double indicator_width;    /* 0: exact cutoff indicator; w > 0: logistic mix
+                                  1/(1 + exp(-(q_j - tau_j)/w)) of the two cutoffs  */
+    double bandwidth[BMD_MAX_DIM]; /* smoothing kernel sd per axis (quantile units) */
+    int32_t gh_nodes;          /* Gauss-Hermite nodes for orthant probabilities:
+                                  0 = chosen per precision from rho_b and d         */
+    uint64_t seed;             /* Philox4x32-10 key (lo, hi words)                  */
+    uint32_t scenario_id;      /* third Philox counter word                         */
+} bmd_problem_desc;
+
+/* Version of this header the library was built from (BMD_ABI_VERSION). */
+int32_t bmd_abi_version(void);
+
+/* Last error message of the calling thread ("" if none). */
+const char *bmd_last_error(void);
+
+/* Create a problem (Sec. 2.1 inputs: r via the cutoffs, I_3, alpha0, prior).
+ * Allocates the problem's device constants on the current device and launches
+ * the per-design precompute (subgroup fraction r, critical values z1, z2) on
+ * `stream`.  *out receives the handle; destroy it with bmd_destroy_problem.
+ * ERANGE if some grid design has r > 0.95 (the bivariate quadrature supports
+ * correlations sqrt(r) <= 0.975), or rho_b > 0.5. */
+bmd_status bmd_create_problem(const bmd_problem_desc *desc, bmd_problem **out, void *stream);
+
+/* Release a problem and its device memory (synchronises the device).  NULL-safe. */
+void bmd_destroy_problem(bmd_problem *p);
+
+/* Number of grid designs G = prod m_j (0 for continuous-design problems). */
+int64_t bmd_grid_size(const bmd_problem *p);
+
+/* Monte Carlo estimate of the expected power (Formula 5) at every grid design
+ * from draws k = 0 .. n_draws-1:
+ *   d_mean[g] = (1/M) sum_k (1 - Phi_2(z1 - mu1_k, z2 - mu2_gk; sqrt r_g)),
+ *   d_var[g]  = sample variance of the summands (may be NULL).
+ * Both are FP64 arrays of length G in row-major design order (axis 0 slowest).
+ * prec selects the integrand precision (sums are FP64 in both).
+ * ESTATE for continuous-design problems; ERANGE if n_draws is 0 or > 2^40. */
+bmd_status bmd_eval_grid(bmd_problem *p, uint64_t n_draws, int32_t prec,
+                         double *d_mean, double *d_var, void *stream);
+
+/* Nadaraya-Watson smoothing with the product Gaussian kernel
+ * K(g,h) = prod_j exp(-((q_j(g) - q_j(h)) / b_j)^2 / 2), untruncated, applied
+ * separably along each axis (the stand-in for the paper's thin-plate spline,
+ * Sec. 2.3).  d_in and d_out are FP64 arrays of length G and must not alias.
+ * prec: FP64 uses FP64 matrix cores; FP32_COMP uses FP32 matrix cores with
+ * FP32 accumulation. */
+bmd_status bmd_smooth(bmd_problem *p, const double *d_in, double *d_out, int32_t prec,
+                      void *stream);
+
+/* Maximiser of a surface (the best grid point, Sec. 2.3): index g* of the
+ * largest value, ties to the lowest index, NaN never wins.  Writes *h_index,
+ * *h_value and, if h_cell is not NULL, the d grid indices of g*.
+ * Synchronises `stream` (returns the result on the host). */
+bmd_status bmd_argmax(bmd_problem *p, const double *d_surface, int64_t *h_index,
+                      double *h_value, int32_t *h_cell, void *stream);
+
+/* Objective and its gradient at B continuous design points (the smoothness of
+ * Appendix A.3 made explicit for the Newton step of Sec. 2.3):
+ *   d_q       [B*d] FP64 cutoff quantiles, row-major, in [q_lo, q_hi]
+ *   d_obj     [B]   FP64 Monte Carlo objective (as bmd_eval_grid's mean)
+ *   d_grad_q  [B*d] d obj_b / d q_b,j (may be NULL)
+ *   d_grad_mu [B*2] d obj_b / d (mu_b0, mu_b1) (may be NULL)
+ * Draws are regenerated from their Philox counters, never stored.  Works on
+ * grid and continuous problems; requires BMD_EFFECT_STEP (ENOTSUP otherwise). */
+bmd_status bmd_grad_design(bmd_problem *p, const double *d_q, int64_t B, uint64_t n_draws,
+                           int32_t prec, double *d_obj, double *d_grad_q, double *d_grad_mu,
+                           void *stream);
+
+/* Batched evaluation of n independent grid problems in one persistent launch:
+ * d_means[i] receives problem i's FP64 mean surface for n_draws[i] draws.
+ * h_wall_ms (may be NULL) receives each problem's completion time in ms after
+ * the launch started, measured on the device.  Synchronises `stream`. */
+bmd_status bmd_eval_batch(bmd_problem *const *ps, int32_t n, const uint64_t *n_draws,
+                          int32_t prec, double *const *d_means, double *h_wall_ms,
+                          void *stream);
+
+/* ---- inspection (bit-exactness of sample generation and grid indexing) ---- */
+
+#define BMD_DRAW_FIELDS 17
+/* Draws k0 .. k0+n-1 as the kernels generate them.
+ *   d_u      [n*8]  FP64 uniforms in consumption order (unused slots 0)
+ *   d_fields [n*BMD_DRAW_FIELDS] FP64: b0, b1, P(R), e1, e2, tau[6], t[6]
+ *            (step prior: b0, b1, P(R), tau, t = Phi^-1(tau); paper prior: e1, e2) */
+bmd_status bmd_draws(bmd_problem *p, uint64_t k0, uint64_t n, double *d_u, double *d_fields,
+                     void *stream);
+
+#define BMD_DESIGN_FIELDS 16
+/* Design quantities for grid designs g0 .. g0+n-1:
+ *   d_fields [n*BMD_DESIGN_FIELDS] FP64: q[6], c[6] = Phi^-1(q), r, sqrt(r), z1, z2 */
+bmd_status bmd_designs(bmd_problem *p, int64_t g0, int64_t n, double *d_fields, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BMD_H */

@@ -1,0 +1,244 @@
+"""MI355X-native hot path for optimal biomarker-cutoff trial designs.
+
+Thin Python binding over ``libbmd.so`` (see ``include/bmd.h``): argument
+marshalling only.  Every step of the computation runs in the library's HIP
+kernels; PyTorch provides device memory and streams.  Importing works without
+a GPU; creating a problem needs the built library and a GPU.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["BmdError", "Problem", "library", "FP64", "FP32_COMP", "LIB_PATH"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbmd.so")
+
+FP64, FP32_COMP = 0, 1
+_PREC = {"fp64": FP64, "f64": FP64, "fp32": FP32_COMP, "fp32_comp": FP32_COMP, "f32": FP32_COMP}
+_ALPHA = {"fwer": 0, "fwer_equal": 0, "bonferroni": 1, "fixed": 2}
+_EFFECT = {"step": 0, "paper": 1, "paper_gauss": 1}
+DRAW_FIELDS = 17
+DESIGN_FIELDS = 16
+
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "ENOMEM", -4: "EDEVICE", -5: "ENOTSUP", -6: "ESTATE"}
+
+
+class BmdError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"bmd {_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int32), ("m", ctypes.c_int32 * 6),
+        ("q_lo", ctypes.c_double), ("q_hi", ctypes.c_double),
+        ("rho_b", ctypes.c_double), ("info", ctypes.c_double), ("alpha0", ctypes.c_double),
+        ("alpha_rule", ctypes.c_int32), ("alpha_fixed", ctypes.c_double * 2),
+        ("effect", ctypes.c_int32),
+        ("mu_b0", ctypes.c_double), ("sd_b0", ctypes.c_double),
+        ("mu_b1", ctypes.c_double), ("sd_b1", ctypes.c_double),
+        ("tau_lo", ctypes.c_double), ("tau_hi", ctypes.c_double),
+        ("paper_a", ctypes.c_double), ("paper_b", ctypes.c_double),
+        ("paper_events", ctypes.c_double), ("indicator_width", ctypes.c_double),
+        ("bandwidth", ctypes.c_double * 6), ("gh_nodes", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("scenario_id", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+
+#: every entry point declared in include/bmd.h, with (restype, argtypes)
+SIGNATURES = {
+    "bmd_abi_version": (ctypes.c_int32, []),
+    "bmd_last_error": (ctypes.c_char_p, []),
+    "bmd_create_problem": (ctypes.c_int, [ctypes.POINTER(_Desc), ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
+    "bmd_destroy_problem": (None, [ctypes.c_void_p]),
+    "bmd_grid_size": (ctypes.c_int64, [ctypes.c_void_p]),
+    "bmd_eval_grid": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p]),
+    "bmd_smooth": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "bmd_argmax": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_void_p]),
+    "bmd_grad_design": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64,
+                                       ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
+    "bmd_eval_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "bmd_draws": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_void_p]),
+    "bmd_designs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                   ctypes.c_void_p]),
+}
+
+
+def library():
+    """Load libbmd.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2005_10494_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        msg = library().bmd_last_error()
+        raise BmdError(status, msg.decode() if msg else "")
+
+
+def _prec(p) -> int:
+    return _PREC[p.lower()] if isinstance(p, str) else int(p)
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_desc(spec: dict) -> _Desc:
+    """Descriptor from a problem dict (keys as in ``workloads.base_problem``)."""
+    D = _Desc()
+    d = int(spec["d"])
+    D.d = d
+    m = spec.get("m")
+    for j in range(6):
+        D.m[j] = int(m[j]) if (m is not None and j < len(m)) else 0
+    D.q_lo = float(spec.get("q_lo", 0.05))
+    D.q_hi = float(spec.get("q_hi", 0.95))
+    D.rho_b = float(spec.get("rho_b", 0.0))
+    D.info = float(spec["info"])
+    D.alpha0 = float(spec.get("alpha0", 0.025))
+    rule = spec.get("alpha_rule", "fwer")
+    D.alpha_rule = _ALPHA[rule] if isinstance(rule, str) else int(rule)
+    af = spec.get("alpha_fixed", (0.0, 0.0))
+    D.alpha_fixed[0], D.alpha_fixed[1] = float(af[0]), float(af[1])
+    eff = spec.get("effect", "step")
+    D.effect = _EFFECT[eff] if isinstance(eff, str) else int(eff)
+    for k in ("mu_b0", "sd_b0", "mu_b1", "sd_b1", "tau_lo", "tau_hi", "paper_a", "paper_b", "paper_events"):
+        setattr(D, k, float(spec.get(k, 0.0)))
+    D.indicator_width = float(spec.get("width", 0.0))
+    bw = spec.get("bandwidth") or [0.02] * d
+    for j in range(6):
+        D.bandwidth[j] = float(bw[j]) if j < len(bw) else 0.0
+    D.gh_nodes = int(spec.get("gh_nodes", 0))
+    D.seed = int(spec.get("seed", 0))
+    D.scenario_id = int(spec.get("scenario", 0))
+    return D
+
+
+class Problem:
+    """One design problem on the current GPU (owns its device constants)."""
+
+    def __init__(self, spec: dict, stream=None):
+        import torch
+        self.spec = dict(spec)
+        self.d = int(spec["d"])
+        self._h = ctypes.c_void_p()
+        self._desc = make_desc(spec)
+        _check(library().bmd_create_problem(ctypes.byref(self._desc), ctypes.byref(self._h), _stream(stream)))
+        self.G = int(library().bmd_grid_size(self._h))
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            library().bmd_destroy_problem(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- entry points ---------------------------------------------------------
+    def eval_grid(self, n_draws: int, precision="fp64", want_var=False, out=None, out_var=None, stream=None):
+        import torch
+        mean = out if out is not None else torch.empty(self.G, dtype=torch.float64, device=self.device)
+        var = None
+        if want_var:
+            var = out_var if out_var is not None else torch.empty(self.G, dtype=torch.float64, device=self.device)
+        _check(library().bmd_eval_grid(self._h, int(n_draws), _prec(precision), ctypes.c_void_p(mean.data_ptr()),
+                                       ctypes.c_void_p(var.data_ptr()) if var is not None else None,
+                                       _stream(stream)))
+        return (mean, var) if want_var else mean
+
+    def smooth(self, surface, precision="fp64", out=None, stream=None):
+        import torch
+        assert surface.dtype == torch.float64 and surface.is_contiguous() and surface.numel() == self.G
+        res = out if out is not None else torch.empty_like(surface)
+        _check(library().bmd_smooth(self._h, ctypes.c_void_p(surface.data_ptr()), ctypes.c_void_p(res.data_ptr()),
+                                    _prec(precision), _stream(stream)))
+        return res
+
+    def argmax(self, surface, stream=None):
+        import torch
+        assert surface.dtype == torch.float64 and surface.is_contiguous() and surface.numel() == self.G
+        idx = ctypes.c_int64()
+        val = ctypes.c_double()
+        cell = (ctypes.c_int32 * 6)()
+        _check(library().bmd_argmax(self._h, ctypes.c_void_p(surface.data_ptr()), ctypes.byref(idx),
+                                    ctypes.byref(val), cell, _stream(stream)))
+        return int(idx.value), float(val.value), tuple(int(cell[j]) for j in range(self.d))
+
+    def grad_design(self, q, n_draws: int, precision="fp32", want_grad=True, stream=None):
+        import torch
+        q = q.to(device=self.device, dtype=torch.float64).contiguous()
+        B = q.shape[0]
+        obj = torch.empty(B, dtype=torch.float64, device=self.device)
+        gq = torch.empty(B, self.d, dtype=torch.float64, device=self.device) if want_grad else None
+        gmu = torch.empty(B, 2, dtype=torch.float64, device=self.device) if want_grad else None
+        _check(library().bmd_grad_design(self._h, ctypes.c_void_p(q.data_ptr()), B, int(n_draws), _prec(precision),
+                                         ctypes.c_void_p(obj.data_ptr()),
+                                         ctypes.c_void_p(gq.data_ptr()) if gq is not None else None,
+                                         ctypes.c_void_p(gmu.data_ptr()) if gmu is not None else None,
+                                         _stream(stream)))
+        return obj, gq, gmu
+
+    def draws(self, k0: int, n: int, stream=None):
+        import torch
+        u = torch.empty(n, 8, dtype=torch.float64, device=self.device)
+        f = torch.empty(n, DRAW_FIELDS, dtype=torch.float64, device=self.device)
+        _check(library().bmd_draws(self._h, int(k0), int(n), ctypes.c_void_p(u.data_ptr()),
+                                   ctypes.c_void_p(f.data_ptr()), _stream(stream)))
+        return u, f
+
+    def designs(self, g0: int, n: int, stream=None):
+        import torch
+        f = torch.empty(n, DESIGN_FIELDS, dtype=torch.float64, device=self.device)
+        _check(library().bmd_designs(self._h, int(g0), int(n), ctypes.c_void_p(f.data_ptr()), _stream(stream)))
+        return f
+
+
+def eval_batch(problems, n_draws, precision="fp32", stream=None):
+    """Evaluate several grid problems in one launch; returns (means, wall_ms)."""
+    import torch
+    n = len(problems)
+    handles = (ctypes.c_void_p * n)(*[p.handle.value for p in problems])
+    draws = (ctypes.c_uint64 * n)(*[int(x) for x in n_draws])
+    outs = [torch.empty(p.G, dtype=torch.float64, device=p.device) for p in problems]
+    ptrs = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    wall = np.zeros(n, dtype=np.float64)
+    _check(library().bmd_eval_batch(handles, n, draws, _prec(precision), ptrs,
+                                    wall.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+    return outs, wall

@@ -1,0 +1,540 @@
+// C ABI of libbmd: argument validation, problem construction, workspace
+// management and the launch sequence of each entry point (see include/bmd.h).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bmd_internal.hpp"
+
+using namespace bmd;
+
+namespace {
+
+thread_local std::string g_err;
+
+bmd_status fail(bmd_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+bmd_status hip_fail(hipError_t e, const char* what) {
+    return fail(BMD_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, what)                         \
+    do {                                            \
+        hipError_t e_ = (call);                     \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// Keeps the caller's current device, switching to the problem's for the call.
+struct DeviceGuard {
+    int old = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&old) == hipSuccess && old != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur;
+        if (old >= 0 && hipGetDevice(&cur) == hipSuccess && cur != old) (void)hipSetDevice(old);
+    }
+};
+
+bool finite(double x) { return std::isfinite(x); }
+
+double host_Phi(double x) { return 0.5 * std::erfc(-x / std::sqrt(2.0)); }
+
+// Standard normal quantile on the host: bisection in the tails' bracket, then
+// Newton polishing on erfc.
+double host_quantile(double p) {
+    if (p <= 0.0) return -INFINITY;
+    if (p >= 1.0) return INFINITY;
+    if (p > 0.5) return -host_quantile(1.0 - p);
+    double lo = -40.0, hi = 0.0;
+    for (int it = 0; it < 80; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (host_Phi(mid) < p) lo = mid; else hi = mid;
+    }
+    double x = 0.5 * (lo + hi);
+    for (int it = 0; it < 3; ++it) {
+        double dens = std::exp(-0.5 * x * x) / std::sqrt(2.0 * M_PI);
+        if (dens <= 0.0) break;
+        x -= (host_Phi(x) - p) / dens;
+    }
+    return x;
+}
+
+double host_grid(double q_lo, double q_hi, int64_t i, int m) {
+    double span = q_hi - q_lo;
+    double t = span * static_cast<double>(i);
+    t = t / static_cast<double>(m - 1);
+    return q_lo + t;
+}
+
+// Orthant P(X_j > v_j) by the one-factor Gauss-Hermite rule (x[0..K), w[0..K)).
+double host_orthant(const std::vector<double>& v, double rho, const double* x, const double* w, int K) {
+    const double sr = std::sqrt(rho), sq = std::sqrt(1.0 - rho);
+    double acc = 0.0;
+    for (int m = 0; m < K; ++m) {
+        double prod = w[m];
+        for (double vj : v) prod *= host_Phi((sr * x[m] - vj) / sq);
+        acc += prod;
+    }
+    return acc;
+}
+
+// Smallest Gauss-Hermite rule whose orthant probabilities match a 128-node
+// reference to `target` relative error at probe points spanning the cutoffs
+// the problem can produce (design cutoffs and drawn responder cutoffs).
+int choose_gh(const bmd_problem_desc& d, double target) {
+    if (d.d == 1) return 4;   // closed forms; tables unused
+    static const int cand[] = {4, 8, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 128};
+    std::vector<double> xr(128), wr(128);
+    gauss_hermite_prob(128, xr.data(), wr.data());
+    double lo_q = d.q_lo, hi_q = d.q_hi;
+    if (d.effect == BMD_EFFECT_STEP) {
+        lo_q = std::min(lo_q, d.tau_lo);
+        hi_q = std::max(hi_q, d.tau_hi);
+    }
+    const double vlo = host_quantile(lo_q), vhi = host_quantile(hi_q);
+    std::vector<std::vector<double>> probes;
+    for (int s = 0; s <= 4; ++s) probes.push_back(std::vector<double>(d.d, vlo + (vhi - vlo) * s / 4.0));
+    std::vector<double> mix(d.d);
+    for (int j = 0; j < d.d; ++j) mix[j] = (j % 2) ? vlo : vhi;
+    probes.push_back(mix);
+    std::vector<double> ref;
+    for (auto& v : probes) ref.push_back(host_orthant(v, d.rho_b, xr.data(), wr.data(), 128));
+    for (int K : cand) {
+        std::vector<double> x(K), w(K);
+        gauss_hermite_prob(K, x.data(), w.data());
+        double err = 0.0;
+        for (size_t i = 0; i < probes.size(); ++i)
+            err = std::max(err, std::fabs(host_orthant(probes[i], d.rho_b, x.data(), w.data(), K) - ref[i]) / ref[i]);
+        if (err <= target) return K;
+    }
+    return 128;
+}
+
+bmd_status validate(const bmd_problem_desc* d, bool* grid) {
+    if (!d) return fail(BMD_EINVAL, "desc is NULL");
+    if (d->d < 1 || d->d > BMD_MAX_DIM) return fail(BMD_ERANGE, "d = %d outside 1..6", d->d);
+    bool any = false, all = true;
+    for (int j = 0; j < d->d; ++j) {
+        if (d->m[j] != 0) any = true;
+        if (d->m[j] < 2) all = false;
+    }
+    if (any && !all) return fail(BMD_ERANGE, "grid needs m_j >= 2 on every axis (or all zero)");
+    *grid = any;
+    if (any) {
+        double G = 1.0;
+        for (int j = 0; j < d->d; ++j) {
+            if (d->m[j] > 100000) return fail(BMD_ERANGE, "m_%d = %d too large", j, d->m[j]);
+            G *= d->m[j];
+        }
+        if (G > 2e9) return fail(BMD_ERANGE, "grid of %.3g designs exceeds 2e9", G);
+        for (int j = 0; j < d->d; ++j)
+            if (!finite(d->bandwidth[j]) || d->bandwidth[j] <= 0.0)
+                return fail(BMD_ERANGE, "bandwidth_%d must be > 0", j);
+    }
+    if (!finite(d->q_lo) || !finite(d->q_hi) || !(0.0 < d->q_lo && d->q_lo < d->q_hi && d->q_hi < 1.0))
+        return fail(BMD_ERANGE, "need 0 < q_lo < q_hi < 1");
+    if (!finite(d->rho_b) || d->rho_b < 0.0 || d->rho_b > 0.5)
+        return fail(BMD_ERANGE, "rho_b = %g outside [0, 0.5]", d->rho_b);
+    if (!finite(d->info) || d->info <= 0.0) return fail(BMD_ERANGE, "info must be > 0");
+    if (!finite(d->alpha0) || !(d->alpha0 > 0.0 && d->alpha0 < 0.5)) return fail(BMD_ERANGE, "alpha0 outside (0, 0.5)");
+    if (d->alpha_rule < 0 || d->alpha_rule > 2) return fail(BMD_EINVAL, "unknown alpha_rule %d", d->alpha_rule);
+    if (d->alpha_rule == BMD_ALPHA_FIXED)
+        for (int i = 0; i < 2; ++i)
+            if (!finite(d->alpha_fixed[i]) || d->alpha_fixed[i] < 0.0 || d->alpha_fixed[i] >= 0.5)
+                return fail(BMD_ERANGE, "alpha_fixed[%d] outside [0, 0.5)", i);
+    if (d->effect == BMD_EFFECT_STEP) {
+        const double v[] = {d->mu_b0, d->sd_b0, d->mu_b1, d->sd_b1, d->tau_lo, d->tau_hi};
+        for (double x : v)
+            if (!finite(x)) return fail(BMD_EINVAL, "non-finite prior parameter");
+        if (d->sd_b0 < 0.0 || d->sd_b1 < 0.0) return fail(BMD_ERANGE, "prior sd must be >= 0");
+        if (!(0.0 < d->tau_lo && d->tau_lo <= d->tau_hi && d->tau_hi < 1.0))
+            return fail(BMD_ERANGE, "need 0 < tau_lo <= tau_hi < 1");
+    } else if (d->effect == BMD_EFFECT_PAPER_GAUSS) {
+        if (!finite(d->paper_a) || !finite(d->paper_b) || !finite(d->paper_events) || d->paper_events <= 0.0)
+            return fail(BMD_ERANGE, "paper prior needs finite a, b and events > 0");
+        if (!(d->paper_a < 1.0 && d->paper_a - d->paper_b < 1.0))
+            return fail(BMD_ERANGE, "paper prior effect a - b r must stay below 1");
+    } else {
+        return fail(BMD_EINVAL, "unknown effect model %d", d->effect);
+    }
+    if (!finite(d->indicator_width) || d->indicator_width < 0.0) return fail(BMD_ERANGE, "indicator_width must be >= 0");
+    if (d->gh_nodes != 0 && (d->gh_nodes < 4 || d->gh_nodes > kMaxGH))
+        return fail(BMD_ERANGE, "gh_nodes must be 0 or in [4, 128]");
+    return BMD_OK;
+}
+
+bmd_status ensure(void** buf, size_t* cap, size_t need) {
+    if (*cap >= need && *buf) return BMD_OK;
+    if (*buf) {
+        (void)hipFree(*buf);
+        *buf = nullptr;
+        *cap = 0;
+    }
+    size_t want = std::max<size_t>(need, 1 << 20);
+    hipError_t e = hipMalloc(buf, want);
+    if (e != hipSuccess) {
+        *buf = nullptr;
+        (void)hipGetLastError();
+        return fail(BMD_ENOMEM, "workspace of %zu bytes: %s", want, hipGetErrorString(e));
+    }
+    *cap = want;
+    return BMD_OK;
+}
+
+template <typename T>
+bmd_status upload(T** dst, const T* src, size_t n) {
+    hipError_t e = hipMalloc(dst, sizeof(T) * std::max<size_t>(n, 1));
+    if (e != hipSuccess) {
+        *dst = nullptr;
+        (void)hipGetLastError();
+        return fail(BMD_ENOMEM, "device allocation of %zu bytes: %s", sizeof(T) * n, hipGetErrorString(e));
+    }
+    if (src && n) {
+        e = hipMemcpy(*dst, src, sizeof(T) * n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    }
+    return BMD_OK;
+}
+
+void free_problem(bmd_problem* p) {
+    if (!p) return;
+    auto f = [](void* x) {
+        if (x) (void)hipFree(x);
+    };
+    for (auto& t : p->tab) {
+        f(t.gh);
+        f(t.A);
+        f(t.glw);
+    }
+    f(p->d_gl);
+    f(p->d_ghp);
+    f(p->d_r);
+    f(p->d_z1);
+    f(p->d_z2);
+    f(p->d_W);
+    f(p->d_Wf);
+    f(p->d_ws);
+    f(p->d_ws2);
+    delete p;
+}
+
+bool valid_prec(int32_t prec) { return prec == BMD_FP64 || prec == BMD_FP32_COMP; }
+
+}  // namespace
+
+extern "C" {
+
+int32_t bmd_abi_version(void) { return BMD_ABI_VERSION; }
+
+const char* bmd_last_error(void) { return g_err.c_str(); }
+
+bmd_status bmd_create_problem(const bmd_problem_desc* desc, bmd_problem** out, void* stream) {
+    g_err.clear();
+    if (!out) return fail(BMD_EINVAL, "out is NULL");
+    *out = nullptr;
+    bool grid = false;
+    bmd_status st = validate(desc, &grid);
+    if (st != BMD_OK) return st;
+    const bmd_problem_desc& d = *desc;
+
+    // Subgroup fractions above 0.95 would need correlations beyond the
+    // bivariate quadrature's supported range (sqrt(r) <= 0.975).
+    std::vector<double> ghx(kPrecomputeGH), ghw(kPrecomputeGH);
+    gauss_hermite_prob(kPrecomputeGH, ghx.data(), ghw.data());
+    {
+        double rmax;
+        if (d.d == 1) rmax = 1.0 - d.q_lo;
+        else rmax = host_orthant(std::vector<double>(d.d, host_quantile(d.q_lo)), d.rho_b, ghx.data(), ghw.data(),
+                                 kPrecomputeGH);
+        if (rmax > 0.95 + 1e-12)
+            return fail(BMD_ERANGE, "subgroup fraction reaches %.6f > 0.95 at q_lo = %g", rmax, d.q_lo);
+    }
+
+    bmd_problem* p = new bmd_problem();
+    p->desc = d;
+    p->grid = grid;
+    (void)hipGetDevice(&p->device);
+    DevProblem& P = p->P;
+    std::memset(&P, 0, sizeof P);
+    P.d = d.d;
+    P.G = 0;
+    P.mmax = 1;
+    if (grid) {
+        P.G = 1;
+        for (int j = 0; j < d.d; ++j) {
+            P.m[j] = d.m[j];
+            P.G *= d.m[j];
+            P.mmax = std::max(P.mmax, d.m[j]);
+        }
+        int64_t s = 1;
+        for (int j = d.d - 1; j >= 0; --j) {
+            P.stride[j] = s;
+            s *= d.m[j];
+        }
+    }
+    P.q_lo = d.q_lo;
+    P.q_hi = d.q_hi;
+    P.rho_b = d.rho_b;
+    P.sr = std::sqrt(d.rho_b);
+    P.sq = std::sqrt(1.0 - d.rho_b);
+    P.info = d.info;
+    P.sqrtI = std::sqrt(d.info);
+    P.alpha0 = d.alpha0;
+    P.alpha_rule = d.alpha_rule;
+    if (d.alpha_rule == BMD_ALPHA_BONFERRONI) {
+        P.zf1 = P.zf2 = -host_quantile(0.5 * d.alpha0);
+    } else if (d.alpha_rule == BMD_ALPHA_FIXED) {
+        P.zf1 = d.alpha_fixed[0] > 0.0 ? -host_quantile(d.alpha_fixed[0]) : INFINITY;
+        P.zf2 = d.alpha_fixed[1] > 0.0 ? -host_quantile(d.alpha_fixed[1]) : INFINITY;
+        P.zinf = (std::isinf(P.zf1) ? 1 : 0) | (std::isinf(P.zf2) ? 2 : 0);
+    }
+    P.effect = d.effect;
+    P.mu_b0 = d.mu_b0;
+    P.sd_b0 = d.sd_b0;
+    P.mu_b1 = d.mu_b1;
+    P.sd_b1 = d.sd_b1;
+    P.tau_lo = d.tau_lo;
+    P.tau_hi = d.tau_hi;
+    P.paper_a = d.paper_a;
+    P.paper_b = d.paper_b;
+    P.paper_events = d.paper_events;
+    if (d.effect == BMD_EFFECT_PAPER_GAUSS) {
+        P.th1 = -std::log1p(-(d.paper_a - d.paper_b));
+        P.sg1 = 1.0 / std::sqrt(d.paper_events / 4.0);
+    }
+    P.width = d.indicator_width;
+    P.key0 = static_cast<uint32_t>(d.seed);
+    P.key1 = static_cast<uint32_t>(d.seed >> 32);
+    P.scenario = d.scenario_id;
+    P.n_uniform = d.effect == BMD_EFFECT_STEP ? 2 + d.d : 2;
+
+    // Quadrature rules.
+    std::vector<double> gl(kGLTable);
+    gl_table(gl.data());
+    std::vector<float> glf(gl.begin(), gl.end());
+    const int K64 = d.gh_nodes ? d.gh_nodes : choose_gh(d, 1e-13);
+    const int K32 = d.gh_nodes ? d.gh_nodes : choose_gh(d, 3e-8);
+    const int Ks[2] = {K64, K32};
+    std::vector<double> ghp(2 * kPrecomputeGH);
+    std::copy(ghx.begin(), ghx.end(), ghp.begin());
+    std::copy(ghw.begin(), ghw.end(), ghp.begin() + kPrecomputeGH);
+
+    st = upload(&p->d_gl, gl.data(), gl.size());
+    if (st == BMD_OK) st = upload(&p->d_ghp, ghp.data(), ghp.size());
+    for (int prec = 0; prec < 2 && st == BMD_OK; ++prec) {
+        const int K = Ks[prec];
+        std::vector<double> x(K), w(K);
+        gauss_hermite_prob(K, x.data(), w.data());
+        std::vector<double>& gh = p->gh_host[prec];
+        gh.assign(2 * K, 0.0);
+        std::copy(x.begin(), x.end(), gh.begin());
+        std::copy(w.begin(), w.end(), gh.begin() + K);
+        p->tab[prec].K = K;
+        st = upload(&p->tab[prec].gh, gh.data(), gh.size());
+        if (st != BMD_OK) break;
+        if (prec == BMD_FP64) {
+            double* g = nullptr;
+            st = upload(&g, gl.data(), gl.size());
+            p->tab[prec].glw = g;
+        } else {
+            float* g = nullptr;
+            st = upload(&g, glf.data(), glf.size());
+            p->tab[prec].glw = g;
+        }
+        if (st != BMD_OK) break;
+        if (grid) {
+            const size_t n = static_cast<size_t>(d.d) * K * P.mmax;
+            if (prec == BMD_FP64) {
+                double* a = nullptr;
+                st = upload<double>(&a, nullptr, n);
+                p->tab[prec].A = a;
+            } else {
+                float* a = nullptr;
+                st = upload<float>(&a, nullptr, n);
+                p->tab[prec].A = a;
+            }
+        }
+    }
+    if (st == BMD_OK && grid) {
+        st = upload<double>(&p->d_r, nullptr, P.G);
+        if (st == BMD_OK) st = upload<double>(&p->d_z1, nullptr, P.G);
+        if (st == BMD_OK) st = upload<double>(&p->d_z2, nullptr, P.G);
+        // Smoothing matrices.
+        std::vector<double> W;
+        for (int j = 0; j < d.d && st == BMD_OK; ++j) {
+            const int m = d.m[j];
+            p->w_off[j] = static_cast<int64_t>(W.size());
+            std::vector<double> q(m);
+            for (int i = 0; i < m; ++i) q[i] = host_grid(d.q_lo, d.q_hi, i, m);
+            for (int i = 0; i < m; ++i) {
+                double den = 0.0;
+                const size_t row = W.size();
+                for (int h = 0; h < m; ++h) {
+                    const double z = (q[i] - q[h]) / d.bandwidth[j];
+                    W.push_back(std::exp(-0.5 * z * z));
+                    den += W.back();
+                }
+                for (int h = 0; h < m; ++h) W[row + h] /= den;
+            }
+        }
+        std::vector<float> Wf(W.begin(), W.end());
+        if (st == BMD_OK) st = upload(&p->d_W, W.data(), W.size());
+        if (st == BMD_OK) st = upload(&p->d_Wf, Wf.data(), Wf.size());
+    }
+    if (st != BMD_OK) {
+        std::string msg = g_err;
+        free_problem(p);
+        g_err = msg;
+        return st;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_design_precompute(p, s);
+    if (e == hipSuccess) e = launch_axis_tables(p, BMD_FP64, s);
+    if (e == hipSuccess) e = launch_axis_tables(p, BMD_FP32_COMP, s);
+    if (e != hipSuccess) {
+        free_problem(p);
+        return hip_fail(e, "setup kernels");
+    }
+    *out = p;
+    return BMD_OK;
+}
+
+void bmd_destroy_problem(bmd_problem* p) {
+    if (!p) return;
+    DeviceGuard guard(p->device);
+    (void)hipDeviceSynchronize();
+    free_problem(p);
+}
+
+int64_t bmd_grid_size(const bmd_problem* p) { return p ? p->P.G : 0; }
+
+bmd_status bmd_eval_grid(bmd_problem* p, uint64_t n_draws, int32_t prec, double* d_mean, double* d_var,
+                         void* stream) {
+    g_err.clear();
+    if (!p) return fail(BMD_EINVAL, "problem is NULL");
+    if (!p->grid) return fail(BMD_ESTATE, "eval_grid needs a grid problem");
+    if (!valid_prec(prec)) return fail(BMD_EINVAL, "unknown precision %d", prec);
+    if (!d_mean) return fail(BMD_EINVAL, "d_mean is NULL");
+    if (n_draws == 0 || n_draws > (1ull << 40)) return fail(BMD_ERANGE, "n_draws must be in [1, 2^40]");
+    DeviceGuard guard(p->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t M = static_cast<int64_t>(n_draws);
+    const int64_t G = p->P.G;
+    const int64_t bx = (G + kEvalBlock - 1) / kEvalBlock;
+    int64_t n_slices = std::max<int64_t>(1, std::min<int64_t>((2048 + bx - 1) / bx, (M + 63) / 64));
+    n_slices = std::min<int64_t>(n_slices, 65535);
+    const int64_t slice_len = (M + n_slices - 1) / n_slices;
+    n_slices = (M + slice_len - 1) / slice_len;
+    const size_t draw_bytes = (draw_workspace_bytes(p, prec, M) + 255) / 256 * 256;
+    const size_t part_bytes = sizeof(double) * 2 * static_cast<size_t>(G) * n_slices;
+    bmd_status st = ensure(&p->d_ws, &p->ws_cap, draw_bytes + part_bytes);
+    if (st != BMD_OK) return st;
+    double* partials = reinterpret_cast<double*>(static_cast<char*>(p->d_ws) + draw_bytes);
+    HIP_TRY(launch_draws(p, prec, 0, M, p->d_ws, s), "draw kernel");
+    HIP_TRY(launch_eval_grid(p, prec, M, p->d_ws, partials, static_cast<int>(n_slices), slice_len, s), "eval kernel");
+    HIP_TRY(launch_finalize(p, M, partials, static_cast<int>(n_slices), d_mean, d_var, s), "finalize kernel");
+    return BMD_OK;
+}
+
+bmd_status bmd_smooth(bmd_problem* p, const double* d_in, double* d_out, int32_t prec, void* stream) {
+    g_err.clear();
+    if (!p) return fail(BMD_EINVAL, "problem is NULL");
+    if (!p->grid) return fail(BMD_ESTATE, "smooth needs a grid problem");
+    if (!valid_prec(prec)) return fail(BMD_EINVAL, "unknown precision %d", prec);
+    if (!d_in || !d_out) return fail(BMD_EINVAL, "NULL surface pointer");
+    if (d_in == d_out) return fail(BMD_EINVAL, "d_in and d_out must not alias");
+    DeviceGuard guard(p->device);
+    bmd_status st = ensure(&p->d_ws2, &p->ws2_cap, sizeof(double) * static_cast<size_t>(p->P.G));
+    if (st != BMD_OK) return st;
+    HIP_TRY(launch_smooth(p, prec, d_in, d_out, static_cast<double*>(p->d_ws2), static_cast<hipStream_t>(stream)),
+            "smooth kernel");
+    return BMD_OK;
+}
+
+bmd_status bmd_argmax(bmd_problem* p, const double* d_surface, int64_t* h_index, double* h_value, int32_t* h_cell,
+                      void* stream) {
+    g_err.clear();
+    if (!p) return fail(BMD_EINVAL, "problem is NULL");
+    if (!p->grid) return fail(BMD_ESTATE, "argmax needs a grid problem");
+    if (!d_surface || !h_index || !h_value) return fail(BMD_EINVAL, "NULL pointer argument");
+    DeviceGuard guard(p->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = p->P.G;
+    const int n_part = static_cast<int>(std::min<int64_t>(1024, (n + 255) / 256));
+    bmd_status st = ensure(&p->d_ws2, &p->ws2_cap, std::max<size_t>(sizeof(double) * n, 16 * 1024 + 256));
+    if (st != BMD_OK) return st;
+    double* pv = static_cast<double*>(p->d_ws2);
+    int64_t* pi = reinterpret_cast<int64_t*>(static_cast<char*>(p->d_ws2) + 8 * 1024);
+    HIP_TRY(launch_argmax(p, d_surface, n, pv, pi, n_part, s), "argmax kernels");
+    double v;
+    int64_t i;
+    HIP_TRY(hipMemcpyAsync(&v, pv, sizeof v, hipMemcpyDeviceToHost, s), "argmax readback");
+    HIP_TRY(hipMemcpyAsync(&i, pi, sizeof i, hipMemcpyDeviceToHost, s), "argmax readback");
+    HIP_TRY(hipStreamSynchronize(s), "argmax sync");
+    if (i == INT64_MAX) {
+        i = 0;
+        v = NAN;
+    }
+    *h_index = i;
+    *h_value = v;
+    if (h_cell) {
+        int64_t rem = i;
+        for (int j = 0; j < p->P.d; ++j) {
+            h_cell[j] = static_cast<int32_t>(rem / p->P.stride[j]);
+            rem -= static_cast<int64_t>(h_cell[j]) * p->P.stride[j];
+        }
+    }
+    return BMD_OK;
+}
+
+bmd_status bmd_grad_design(bmd_problem* p, const double* d_q, int64_t B, uint64_t n_draws, int32_t prec,
+                           double* d_obj, double* d_grad_q, double* d_grad_mu, void* stream) {
+    g_err.clear();
+    (void)d_q; (void)B; (void)n_draws; (void)prec; (void)d_obj; (void)d_grad_q; (void)d_grad_mu; (void)stream;
+    if (!p) return fail(BMD_EINVAL, "problem is NULL");
+    return fail(BMD_ENOTSUP, "grad_design is not available in this build");
+}
+
+bmd_status bmd_eval_batch(bmd_problem* const* ps, int32_t n, const uint64_t* n_draws, int32_t prec,
+                          double* const* d_means, double* h_wall_ms, void* stream) {
+    g_err.clear();
+    (void)ps; (void)n; (void)n_draws; (void)prec; (void)d_means; (void)h_wall_ms; (void)stream;
+    return fail(BMD_ENOTSUP, "eval_batch is not available in this build");
+}
+
+bmd_status bmd_draws(bmd_problem* p, uint64_t k0, uint64_t n, double* d_u, double* d_fields, void* stream) {
+    g_err.clear();
+    if (!p) return fail(BMD_EINVAL, "problem is NULL");
+    if (!d_u || !d_fields) return fail(BMD_EINVAL, "NULL output pointer");
+    if (n == 0 || n > (1ull << 32)) return fail(BMD_ERANGE, "n must be in [1, 2^32]");
+    DeviceGuard guard(p->device);
+    HIP_TRY(launch_inspect_draws(p, k0, static_cast<int64_t>(n), d_u, d_fields, static_cast<hipStream_t>(stream)),
+            "draw inspection kernel");
+    return BMD_OK;
+}
+
+bmd_status bmd_designs(bmd_problem* p, int64_t g0, int64_t n, double* d_fields, void* stream) {
+    g_err.clear();
+    if (!p) return fail(BMD_EINVAL, "problem is NULL");
+    if (!p->grid) return fail(BMD_ESTATE, "designs needs a grid problem");
+    if (!d_fields) return fail(BMD_EINVAL, "NULL output pointer");
+    if (g0 < 0 || n < 1 || g0 + n > p->P.G) return fail(BMD_ERANGE, "design range outside the grid");
+    DeviceGuard guard(p->device);
+    HIP_TRY(launch_inspect_designs(p, g0, n, d_fields, static_cast<hipStream_t>(stream)), "design inspection kernel");
+    return BMD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+// Internal declarations shared by the HIP translation units of libbmd.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "bmd.h"
+
+namespace bmd {
+
+constexpr int kMaxDim = BMD_MAX_DIM;
+constexpr int kMaxGH = 128;          // Gauss-Hermite nodes, upper bound
+constexpr int kPrecomputeGH = 128;   // nodes for the per-design subgroup fraction r
+constexpr int kGLTable = 200;        // packed Gauss-Legendre rules n = 4..24
+constexpr int kEvalBlock = 256;      // designs per workgroup in the eval kernels
+
+// Problem constants passed by value to every kernel.
+struct DevProblem {
+    int d;
+    int64_t G;                 // grid size (0 for continuous problems)
+    int32_t m[kMaxDim];
+    int64_t stride[kMaxDim];   // stride[j] = prod_{l>j} m_l
+    int mmax;
+    double q_lo, q_hi;
+    double rho_b, sr, sq;      // sqrt(rho_b), sqrt(1 - rho_b)
+    double info, sqrtI;
+    double alpha0;
+    int alpha_rule;
+    double zf1, zf2;           // critical values for the non-FWER rules (may be +inf)
+    int zinf;                  // bit 0: z1 = +inf, bit 1: z2 = +inf (fixed rule only)
+    int effect;
+    double mu_b0, sd_b0, mu_b1, sd_b1, tau_lo, tau_hi;
+    double paper_a, paper_b, paper_events;
+    double th1, sg1;           // paper prior: theta_1 and sigma_1 of the full population
+    double width;              // logistic indicator width (0 = exact)
+    uint32_t key0, key1, scenario;
+    int n_uniform;             // uniforms per draw
+};
+
+// Per-draw arrays, produced by the draw kernel and read by the eval kernels.
+template <typename T>
+struct DrawArrays {
+    T* b0;      // [M]
+    T* b1;      // [M]
+    T* mu1;     // [M]  sqrt(I) * Delta_1
+    T* PR;      // [M]  responder fraction
+    T* tauT;    // [M]  tau_0 (one-biomarker closed form)
+    T* e1;      // [M]  paper prior normals
+    T* e2;      // [M]
+    int32_t* thr;   // [d][M] first grid index whose cutoff quantile exceeds tau_j
+    double* tau;    // [d][M]
+    T* B;       // [M][d][K] Phi((sqrt(rho) x_m - t_j)/sqrt(1-rho)), GH weight folded into j = 0
+    int64_t M;
+    int K;
+};
+
+// Device constants owned by a problem, per integrand precision.
+struct PrecTables {
+    int K = 0;                  // Gauss-Hermite nodes
+    double* gh = nullptr;       // [2K] nodes then weights (FP64)
+    void* A = nullptr;          // [d][K][mmax] axis tables in T (weights folded into axis 0)
+    void* glw = nullptr;        // packed GL weights in T
+};
+
+}  // namespace bmd
+
+// Opaque handle of the C ABI.
+struct bmd_problem {
+    bmd_problem_desc desc;
+    bmd::DevProblem P;
+    bool grid = false;
+    int device = 0;
+    bmd::PrecTables tab[2];          // [BMD_FP64], [BMD_FP32_COMP]
+    double* d_gl = nullptr;          // packed GL table (x and w, FP64)
+    double* d_ghp = nullptr;         // [2*kPrecomputeGH] GH rule for r
+    double* d_r = nullptr;           // [G]
+    double* d_z1 = nullptr;          // [G]
+    double* d_z2 = nullptr;          // [G]
+    double* d_W = nullptr;           // smoothing matrices, FP64, sum_j m_j^2
+    float* d_Wf = nullptr;           // same in FP32
+    int64_t w_off[bmd::kMaxDim] = {0, 0, 0, 0, 0, 0};
+    void* d_ws = nullptr;            // workspace
+    size_t ws_cap = 0;
+    void* d_ws2 = nullptr;           // second workspace (smoothing ping-pong, argmax partials)
+    size_t ws2_cap = 0;
+    std::vector<double> gh_host[2];  // host copies of the eval GH rules
+};
+
+namespace bmd {
+
+// Host quadrature rules (quad_nodes.cpp).
+void gauss_hermite_prob(int n, double* x, double* w);   // int f(z) phi(z) dz
+void gauss_legendre(int n, double* x, double* w);       // int_{-1}^{1} f(x) dx
+void gl_table(double* out);                             // packed n = 4,6,8,10,12,16,20,24
+
+// Launchers (return hipSuccess or the first HIP error).
+hipError_t launch_design_precompute(const bmd_problem* p, hipStream_t s);
+hipError_t launch_axis_tables(const bmd_problem* p, int prec, hipStream_t s);
+hipError_t launch_draws(const bmd_problem* p, int prec, uint64_t k0, int64_t M, void* ws,
+                        hipStream_t s);
+size_t draw_workspace_bytes(const bmd_problem* p, int prec, int64_t M);
+DrawArrays<double> draws_fp64(const bmd_problem* p, int64_t M, const void* ws);
+DrawArrays<float> draws_fp32(const bmd_problem* p, int64_t M, const void* ws);
+hipError_t launch_eval_grid(const bmd_problem* p, int prec, int64_t M, const void* ws,
+                            double* partials, int n_slices, int64_t slice_len, hipStream_t s);
+hipError_t launch_finalize(const bmd_problem* p, int64_t M, const double* partials, int n_slices,
+                           double* mean, double* var, hipStream_t s);
+hipError_t launch_smooth(const bmd_problem* p, int prec, const double* in, double* out,
+                         double* tmp, hipStream_t s);
+hipError_t launch_argmax(const bmd_problem* p, const double* v, int64_t n, double* part_v,
+                         int64_t* part_i, int n_part, hipStream_t s);
+hipError_t launch_inspect_draws(const bmd_problem* p, uint64_t k0, int64_t n, double* u,
+                                double* fields, hipStream_t s);
+hipError_t launch_inspect_designs(const bmd_problem* p, int64_t g0, int64_t n, double* fields,
+                                  hipStream_t s);
+
+}  // namespace bmd

@@ -1,0 +1,184 @@
+// Device-side numerics for the design-objective kernels (gfx950).
+//
+// Normal CDF / quantile come from the device math library (ocml: erfc,
+// normcdfinv); the bivariate normal CDF is evaluated from Plackett's identity
+// d Phi_2 / d rho = phi_2 integrated over the angle theta = asin(rho)
+// (Drezner & Wesolowsky 1990, as organised by Genz 2004, Stat. Comput. 14:251),
+// with a Gauss-Legendre rule whose node count grows with the correlation.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bmd {
+
+// ---------------------------------------------------------------------------
+// Counter-based random numbers: Philox4x32-10 (Salmon et al., SC 2011).
+// Round: multiply words 0 and 2 by fixed constants, xor the high halves into
+// words 1 and 3 with the key; the key advances by two Weyl constants.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// (n + 1/2) * 2^-52 with n the 52-bit integer made of the top 26 bits of each
+// word; exact in FP64, strictly inside (0, 1).
+__device__ __forceinline__ double uniform52(uint32_t wa, uint32_t wb) {
+#pragma clang fp contract(off)
+    const uint64_t n = (static_cast<uint64_t>(wa >> 6) << 26) | static_cast<uint64_t>(wb >> 6);
+    const double t = static_cast<double>(n) + 0.5;
+    return t * 0x1p-52;
+}
+
+// Fill u[0..nu) for draw k: block b uses counter (k lo, k hi, scenario, b).
+template <int NU>
+__device__ __forceinline__ void draw_uniforms(uint64_t k, uint32_t scenario, uint32_t key0,
+                                              uint32_t key1, int nu, double* u) {
+    uint32_t w[2 * NU + 4];
+#pragma unroll
+    for (int b = 0; b < (2 * NU + 3) / 4; ++b) {
+        if (4 * b < 2 * nu) {
+            const uint4 o = philox4x32_10(
+                make_uint4(static_cast<uint32_t>(k), static_cast<uint32_t>(k >> 32), scenario,
+                           static_cast<uint32_t>(b)),
+                key0, key1);
+            w[4 * b + 0] = o.x;
+            w[4 * b + 1] = o.y;
+            w[4 * b + 2] = o.z;
+            w[4 * b + 3] = o.w;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NU; ++i)
+        if (i < nu) u[i] = uniform52(w[2 * i], w[2 * i + 1]);
+}
+
+// Grid coordinate q_lo + ((q_hi - q_lo) * i) / (m - 1), each step rounded
+// (no fused multiply-add: the value must be bit-identical to a plain IEEE
+// evaluation in this order).
+__device__ __forceinline__ double grid_coord(double q_lo, double q_hi, int64_t i, int m) {
+#pragma clang fp contract(off)
+    const double span = q_hi - q_lo;
+    const double t = (span * static_cast<double>(i)) / static_cast<double>(m - 1);
+    return q_lo + t;
+}
+
+// lo + (hi - lo) * u, each step rounded (no fused multiply-add).
+__device__ __forceinline__ double affine_uniform(double lo, double hi, double u) {
+#pragma clang fp contract(off)
+    const double span = hi - lo;
+    const double x = span * u;
+    return lo + x;
+}
+
+// ---------------------------------------------------------------------------
+// Univariate normal
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double norm_cdf(double x) { return 0.5 * erfc(-x * 0.70710678118654752440); }
+__device__ __forceinline__ float norm_cdf(float x) { return 0.5f * erfcf(-x * 0.70710678118654752440f); }
+__device__ __forceinline__ double norm_pdf(double x) { return 0.39894228040143267794 * exp(-0.5 * x * x); }
+__device__ __forceinline__ float norm_pdf(float x) {
+    return 0.39894228040143267794f * __builtin_amdgcn_exp2f(-0.72134752044448170368f * x * x);
+}
+
+// Phi^-1(p): the library quantile, then one Newton step on a residual that
+// keeps relative accuracy (erf form near 1/2, where p - 1/2 is exact; erfc
+// forms in the tails, where p or 1 - p is exact).
+__device__ __forceinline__ double norm_quantile(double p) {
+    const double x = p <= 0.5 ? normcdfinv(p) : -normcdfinv(1.0 - p);
+    const double a = p - 0.5;
+    double res;
+    if (fabs(a) <= 0.25) res = 0.5 * erf(x * 0.70710678118654752440) - a;
+    else if (a < 0.0) res = 0.5 * erfc(-x * 0.70710678118654752440) - p;
+    else res = (1.0 - p) - 0.5 * erfc(x * 0.70710678118654752440);
+    return x - res / norm_pdf(x);
+}
+
+// ---------------------------------------------------------------------------
+// Bivariate normal CDF with per-design constants.
+//
+// Phi_2(h,k;rho) = Phi(h) Phi(k) + (1/2pi) int_0^{asin rho}
+//                      exp(-(h^2 + k^2 - 2 h k sin t) / (2 cos^2 t)) dt.
+// With Gauss-Legendre nodes x_i on [-1,1], s_i = sin(asin(rho)(1 + x_i)/2):
+//   integrand_i = exp(b_i h k - a_i (h^2 + k^2)/2),  a_i = 1/(1 - s_i^2), b_i = s_i a_i,
+// and the integral is asin(rho)/(4 pi) sum_i w_i integrand_i.
+// The per-design constants (a_i, b_i, scale) live in registers; the weights w_i
+// belong to the n-point rule shared by the wavefront.
+// ---------------------------------------------------------------------------
+
+// Number of Gauss-Legendre nodes for a target accuracy at correlation rho
+// (max abs error over h, k in [-6, 4]: <= 1e-14 for FP64, <= 2e-8 for FP32).
+__device__ __forceinline__ int bvn_nodes_fp64(double rho) {
+    return rho < 0.3 ? 6 : rho < 0.5 ? 8 : rho < 0.75 ? 12 : rho < 0.9 ? 16 : rho < 0.95 ? 20 : 24;
+}
+__device__ __forceinline__ int bvn_nodes_fp32(double rho) {
+    return rho < 0.5 ? 4 : rho < 0.75 ? 6 : rho < 0.9 ? 8 : rho < 0.95 ? 10 : 12;
+}
+
+// Offsets of the n-point rules inside the packed Gauss-Legendre table
+// (rules for n = 4, 6, 8, 10, 12, 16, 20, 24; x then w, n doubles each).
+__device__ __forceinline__ int gl_offset(int n) {
+    // 2 * (sum of smaller rule sizes)
+    return n == 4 ? 0 : n == 6 ? 8 : n == 8 ? 20 : n == 10 ? 36 : n == 12 ? 56
+         : n == 16 ? 80 : n == 20 ? 112 : 152;
+}
+
+template <typename T, int NMAX>
+struct BvnConst {
+    T a[NMAX], b[NMAX];
+    T scale;  // asin(rho) / (4 pi)
+
+    // gl: packed table; n: wave-uniform rule size (<= NMAX).
+    __device__ __forceinline__ void init(double rho, int n, const double* __restrict__ gl) {
+        // FP32 evaluates exp2, so its exponent coefficients carry log2(e).
+        const double L = sizeof(T) == 4 ? 1.4426950408889634074 : 1.0;
+        const double th = asin(rho);
+        scale = static_cast<T>(th * 0.079577471545947667884);  // 1/(4 pi)
+        const double* x = gl + gl_offset(n);
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i) {
+            if (i < n) {
+                const double s = sin(0.5 * th * (1.0 + x[i]));
+                const double ai = 1.0 / ((1.0 - s) * (1.0 + s));
+                a[i] = static_cast<T>(L * ai);
+                b[i] = static_cast<T>(L * s * ai);
+            } else {
+                a[i] = T(0);
+                b[i] = T(0);
+            }
+        }
+    }
+};
+
+// FP64: sum_i w_i exp(b_i hk - a_i hs)
+template <int NMAX>
+__device__ __forceinline__ double bvn_cdf(double h, double k, const BvnConst<double, NMAX>& c,
+                                          const double* __restrict__ w, int n) {
+    const double hk = h * k, hs = 0.5 * (h * h + k * k);
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i)
+        if (i < n) acc += w[i] * exp(c.b[i] * hk - c.a[i] * hs);
+    return norm_cdf(h) * norm_cdf(k) + c.scale * acc;
+}
+
+// FP32: exponent coefficients pre-multiplied by log2(e), hardware exp2.
+template <int NMAX>
+__device__ __forceinline__ float bvn_cdf(float h, float k, const BvnConst<float, NMAX>& c,
+                                         const float* __restrict__ w, int n) {
+    const float hk = h * k, hs = 0.5f * (h * h + k * k);
+    float acc = 0.0f;
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i)
+        if (i < n) acc += w[i] * __builtin_amdgcn_exp2f(c.b[i] * hk - c.a[i] * hs);
+    return norm_cdf(h) * norm_cdf(k) + c.scale * acc;
+}
+
+}  // namespace bmd

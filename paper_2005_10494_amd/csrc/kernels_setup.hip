@@ -1,0 +1,312 @@
+// Per-design and per-draw setup kernels: grid coordinates, subgroup fractions,
+// critical values (Formula 2), axis tables, and the prior draws of Formula 5.
+#include "bmd_internal.hpp"
+#include "device_math.hpp"
+
+namespace bmd {
+namespace {
+
+// Decode a row-major grid index (axis 0 slowest).
+__device__ __forceinline__ void decode(const DevProblem& P, int64_t g, int* idx) {
+#pragma unroll
+    for (int j = 0; j < kMaxDim; ++j) {
+        if (j < P.d) {
+            const int64_t s = P.stride[j];
+            idx[j] = static_cast<int>(g / s);
+            g -= static_cast<int64_t>(idx[j]) * s;
+        }
+    }
+}
+
+// Equicorrelated orthant probability P(X_j > v_j, j < d) through the one-factor
+// representation, integrated over the common factor with a Gauss-Hermite rule.
+__device__ double orthant_gh(const DevProblem& P, const double* v, const double* __restrict__ gh,
+                             int K) {
+    const double* x = gh;
+    const double* w = gh + K;
+    double acc = 0.0;
+    for (int m = 0; m < K; ++m) {
+        double prod = w[m];
+        const double t = P.sr * x[m];
+        for (int j = 0; j < P.d; ++j) prod *= norm_cdf((t - v[j]) / P.sq);
+        acc += prod;
+    }
+    return acc;
+}
+
+// Phi_2 with the largest Gauss-Legendre rule (setup-time accuracy, FP64).
+__device__ double bvn_setup(double h, double k, double rho, const double* __restrict__ gl) {
+    const int n = 24;
+    const double* x = gl + gl_offset(n);
+    const double* w = x + n;
+    const double th = asin(rho);
+    const double hk = h * k, hs = 0.5 * (h * h + k * k);
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double s = sin(0.5 * th * (1.0 + x[i]));
+        const double a = 1.0 / ((1.0 - s) * (1.0 + s));
+        acc += w[i] * exp(a * (s * hk - hs));
+    }
+    return norm_cdf(h) * norm_cdf(k) + th * 0.079577471545947667884 * acc;
+}
+
+// Common critical value with family-wise error alpha0 at null correlation
+// rho (Formula 2 for two tests): F(z) = 2 Phi(-z) - Phi_2(-z, -z; rho) - alpha0
+// is decreasing; safeguarded Newton inside [z(alpha0), z(alpha0/2)] with
+// F'(z) = -2 phi(z) Phi(z sqrt((1 - rho)/(1 + rho))).
+__device__ double zstar(double rho, double alpha0, const double* __restrict__ gl) {
+    double lo = -norm_quantile(alpha0), hi = -norm_quantile(0.5 * alpha0);
+    double z = 0.5 * (lo + hi);
+    const double c = sqrt((1.0 - rho) / (1.0 + rho));
+    for (int it = 0; it < 60; ++it) {
+        const double F = 2.0 * norm_cdf(-z) - bvn_setup(-z, -z, rho, gl) - alpha0;
+        if (F > 0.0) lo = z; else hi = z;
+        const double dF = -2.0 * norm_pdf(z) * norm_cdf(z * c);
+        double zn = z - F / dF;
+        if (!(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
+        const double step = fabs(zn - z);
+        z = zn;
+        if (step <= 4e-16 * z || hi - lo <= 4e-16 * z) break;
+    }
+    return z;
+}
+
+__global__ void k_design_precompute(DevProblem P, const double* __restrict__ ghp, int Kp,
+                                    const double* __restrict__ gl, double* __restrict__ r_out,
+                                    double* __restrict__ z1_out, double* __restrict__ z2_out) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= P.G) return;
+    int idx[kMaxDim];
+    decode(P, g, idx);
+    double c[kMaxDim];
+    double r;
+    if (P.d == 1) {
+        r = 1.0 - grid_coord(P.q_lo, P.q_hi, idx[0], P.m[0]);
+    } else {
+        for (int j = 0; j < P.d; ++j) c[j] = norm_quantile(grid_coord(P.q_lo, P.q_hi, idx[j], P.m[j]));
+        r = orthant_gh(P, c, ghp, Kp);
+    }
+    r_out[g] = r;
+    if (P.alpha_rule == BMD_ALPHA_FWER_EQUAL) {
+        const double z = zstar(sqrt(r), P.alpha0, gl);
+        z1_out[g] = z;
+        z2_out[g] = z;
+    } else {
+        z1_out[g] = P.zf1;
+        z2_out[g] = P.zf2;
+    }
+}
+
+// A[(j*K + m)*mmax + i] = w_m^[j==0] Phi((sqrt(rho) x_m - c_{j,i}) / sqrt(1-rho)).
+template <typename T>
+__global__ void k_axis_tables(DevProblem P, const double* __restrict__ gh, int K, T* __restrict__ A) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t total = static_cast<int64_t>(P.d) * K * P.mmax;
+    if (t >= total) return;
+    const int i = static_cast<int>(t % P.mmax);
+    const int m = static_cast<int>((t / P.mmax) % K);
+    const int j = static_cast<int>(t / (static_cast<int64_t>(P.mmax) * K));
+    double v = 0.0;
+    if (i < P.m[j]) {
+        const double c = norm_quantile(grid_coord(P.q_lo, P.q_hi, i, P.m[j]));
+        v = norm_cdf((P.sr * gh[m] - c) / P.sq);
+        if (j == 0) v *= gh[K + m];
+    }
+    A[t] = static_cast<T>(v);
+}
+
+// Number of grid indices i in [0, m) with q_i <= tau (the grid is nondecreasing).
+__device__ __forceinline__ int32_t count_le(const DevProblem& P, int j, double tau) {
+    int lo = 0, hi = P.m[j];   // answer in [lo, hi]
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (grid_coord(P.q_lo, P.q_hi, mid, P.m[j]) <= tau) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// One prior draw per thread (Formula 5's Delta^(k)).
+template <typename T>
+__global__ void k_draws(DevProblem P, const double* __restrict__ gh, int K, uint64_t k0, int64_t M,
+                        DrawArrays<T> D) {
+    const int64_t kk = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (kk >= M) return;
+    const uint64_t k = k0 + static_cast<uint64_t>(kk);
+    double u[8];
+    draw_uniforms<8>(k, P.scenario, P.key0, P.key1, P.n_uniform, u);
+    if (P.effect == BMD_EFFECT_STEP) {
+        const double b0 = P.mu_b0 + P.sd_b0 * norm_quantile(u[0]);
+        const double b1 = P.mu_b1 + P.sd_b1 * norm_quantile(u[1]);
+        double t[kMaxDim];
+        for (int j = 0; j < P.d; ++j) {
+            const double tau = affine_uniform(P.tau_lo, P.tau_hi, u[2 + j]);
+            t[j] = norm_quantile(tau);
+            D.tau[j * M + kk] = tau;
+            if (P.G > 0) D.thr[j * M + kk] = count_le(P, j, tau);
+        }
+        double PR;
+        if (P.d == 1) {
+            PR = 1.0 - D.tau[kk];
+        } else {
+            PR = 0.0;
+            T* B = D.B + static_cast<int64_t>(kk) * P.d * K;
+            for (int m = 0; m < K; ++m) {
+                double prod = gh[K + m];
+                const double s = P.sr * gh[m];
+                for (int j = 0; j < P.d; ++j) {
+                    const double v = norm_cdf((s - t[j]) / P.sq);
+                    B[j * K + m] = static_cast<T>(j == 0 ? gh[K + m] * v : v);
+                    prod *= v;
+                }
+                PR += prod;
+            }
+        }
+        D.b0[kk] = static_cast<T>(b0);
+        D.b1[kk] = static_cast<T>(b1);
+        D.PR[kk] = static_cast<T>(PR);
+        D.mu1[kk] = static_cast<T>(P.sqrtI * (b0 + b1 * PR));
+        D.tauT[kk] = static_cast<T>(D.tau[kk]);
+    } else {
+        const double e1 = norm_quantile(u[0]);
+        const double e2 = norm_quantile(u[1]);
+        D.e1[kk] = static_cast<T>(e1);
+        D.e2[kk] = static_cast<T>(e2);
+        D.mu1[kk] = static_cast<T>(P.sqrtI * (P.th1 + P.sg1 * e1));
+    }
+}
+
+__global__ void k_inspect_draws(DevProblem P, const double* __restrict__ gh, int K, uint64_t k0,
+                                int64_t n, double* __restrict__ u_out, double* __restrict__ f_out) {
+    const int64_t kk = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (kk >= n) return;
+    double u[8];
+    for (int i = 0; i < 8; ++i) u[i] = 0.0;
+    draw_uniforms<8>(k0 + static_cast<uint64_t>(kk), P.scenario, P.key0, P.key1, P.n_uniform, u);
+    double* f = f_out + kk * BMD_DRAW_FIELDS;
+    for (int i = 0; i < BMD_DRAW_FIELDS; ++i) f[i] = 0.0;
+    for (int i = 0; i < 8; ++i) u_out[kk * 8 + i] = u[i];
+    if (P.effect == BMD_EFFECT_STEP) {
+        f[0] = P.mu_b0 + P.sd_b0 * norm_quantile(u[0]);
+        f[1] = P.mu_b1 + P.sd_b1 * norm_quantile(u[1]);
+        double t[kMaxDim];
+        for (int j = 0; j < P.d; ++j) {
+            const double tau = affine_uniform(P.tau_lo, P.tau_hi, u[2 + j]);
+            t[j] = norm_quantile(tau);
+            f[5 + j] = tau;
+            f[11 + j] = t[j];
+        }
+        f[2] = P.d == 1 ? 1.0 - f[5] : orthant_gh(P, t, gh, K);
+    } else {
+        f[3] = norm_quantile(u[0]);
+        f[4] = norm_quantile(u[1]);
+    }
+}
+
+__global__ void k_inspect_designs(DevProblem P, int64_t g0, int64_t n, const double* __restrict__ r,
+                                  const double* __restrict__ z1, const double* __restrict__ z2,
+                                  double* __restrict__ out) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int64_t g = g0 + t;
+    int idx[kMaxDim];
+    decode(P, g, idx);
+    double* f = out + t * BMD_DESIGN_FIELDS;
+    for (int i = 0; i < BMD_DESIGN_FIELDS; ++i) f[i] = 0.0;
+    for (int j = 0; j < P.d; ++j) {
+        f[j] = grid_coord(P.q_lo, P.q_hi, idx[j], P.m[j]);
+        f[6 + j] = norm_quantile(f[j]);
+    }
+    f[12] = r[g];
+    f[13] = sqrt(r[g]);
+    f[14] = z1[g];
+    f[15] = z2[g];
+}
+
+inline unsigned blocks_for(int64_t n, int b) { return static_cast<unsigned>((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_design_precompute(const bmd_problem* p, hipStream_t s) {
+    if (p->P.G == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_design_precompute, dim3(blocks_for(p->P.G, 128)), dim3(128), 0, s, p->P,
+                       p->d_ghp, kPrecomputeGH, p->d_gl, p->d_r, p->d_z1, p->d_z2);
+    return hipGetLastError();
+}
+
+hipError_t launch_axis_tables(const bmd_problem* p, int prec, hipStream_t s) {
+    if (p->P.G == 0) return hipSuccess;
+    const PrecTables& t = p->tab[prec];
+    const int64_t total = static_cast<int64_t>(p->P.d) * t.K * p->P.mmax;
+    if (prec == BMD_FP64)
+        hipLaunchKernelGGL(k_axis_tables<double>, dim3(blocks_for(total, 256)), dim3(256), 0, s, p->P,
+                           t.gh, t.K, static_cast<double*>(t.A));
+    else
+        hipLaunchKernelGGL(k_axis_tables<float>, dim3(blocks_for(total, 256)), dim3(256), 0, s, p->P,
+                           t.gh, t.K, static_cast<float*>(t.A));
+    return hipGetLastError();
+}
+
+template <typename T>
+static DrawArrays<T> carve(const bmd_problem* p, int prec, int64_t M, void* ws) {
+    DrawArrays<T> D;
+    const int d = p->P.d, K = p->tab[prec].K;
+    char* c = static_cast<char*>(ws);
+    auto take = [&](size_t bytes) {
+        char* r = c;
+        c += (bytes + 255) / 256 * 256;
+        return r;
+    };
+    D.b0 = reinterpret_cast<T*>(take(sizeof(T) * M));
+    D.b1 = reinterpret_cast<T*>(take(sizeof(T) * M));
+    D.mu1 = reinterpret_cast<T*>(take(sizeof(T) * M));
+    D.PR = reinterpret_cast<T*>(take(sizeof(T) * M));
+    D.tauT = reinterpret_cast<T*>(take(sizeof(T) * M));
+    D.e1 = reinterpret_cast<T*>(take(sizeof(T) * M));
+    D.e2 = reinterpret_cast<T*>(take(sizeof(T) * M));
+    D.thr = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * d * M));
+    D.tau = reinterpret_cast<double*>(take(sizeof(double) * d * M));
+    D.B = reinterpret_cast<T*>(take(sizeof(T) * (d >= 2 ? static_cast<size_t>(M) * d * K : 1)));
+    D.M = M;
+    D.K = K;
+    return D;
+}
+
+size_t draw_workspace_bytes(const bmd_problem* p, int prec, int64_t M) {
+    const size_t T = prec == BMD_FP64 ? 8 : 4;
+    const int d = p->P.d, K = p->tab[prec].K;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    return 7 * al(T * M) + al(4 * d * M) + al(8 * d * M) + al(T * (d >= 2 ? static_cast<size_t>(M) * d * K : 1));
+}
+
+DrawArrays<double> draws_fp64(const bmd_problem* p, int64_t M, const void* ws) {
+    return carve<double>(p, BMD_FP64, M, const_cast<void*>(ws));
+}
+DrawArrays<float> draws_fp32(const bmd_problem* p, int64_t M, const void* ws) {
+    return carve<float>(p, BMD_FP32_COMP, M, const_cast<void*>(ws));
+}
+
+hipError_t launch_draws(const bmd_problem* p, int prec, uint64_t k0, int64_t M, void* ws, hipStream_t s) {
+    const PrecTables& t = p->tab[prec];
+    if (prec == BMD_FP64)
+        hipLaunchKernelGGL(k_draws<double>, dim3(blocks_for(M, 128)), dim3(128), 0, s, p->P, t.gh, t.K, k0, M,
+                           carve<double>(p, prec, M, ws));
+    else
+        hipLaunchKernelGGL(k_draws<float>, dim3(blocks_for(M, 128)), dim3(128), 0, s, p->P, t.gh, t.K, k0, M,
+                           carve<float>(p, prec, M, ws));
+    return hipGetLastError();
+}
+
+hipError_t launch_inspect_draws(const bmd_problem* p, uint64_t k0, int64_t n, double* u, double* fields,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_inspect_draws, dim3(blocks_for(n, 128)), dim3(128), 0, s, p->P, p->d_ghp,
+                       kPrecomputeGH, k0, n, u, fields);
+    return hipGetLastError();
+}
+
+hipError_t launch_inspect_designs(const bmd_problem* p, int64_t g0, int64_t n, double* fields, hipStream_t s) {
+    hipLaunchKernelGGL(k_inspect_designs, dim3(blocks_for(n, 128)), dim3(128), 0, s, p->P, g0, n, p->d_r,
+                       p->d_z1, p->d_z2, fields);
+    return hipGetLastError();
+}
+
+}  // namespace bmd

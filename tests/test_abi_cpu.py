@@ -1,0 +1,93 @@
+"""The C-ABI library without a GPU: it loads, exports every symbol that
+include/bmd.h declares, its Python descriptor mirrors the C struct, and the
+host-side validation rejects bad problems before any device call."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2005_10494_amd as bmd
+from paper_2005_10494_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bmd.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bmd_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = bmd.library()
+    names = _declared()
+    assert "bmd_create_problem" in names and "bmd_grad_design" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(bmd.SIGNATURES), "binding and header disagree"
+    out = subprocess.run(["nm", "-D", "--defined-only", bmd.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (bmd_\w+)", out))
+    assert set(names) <= exported
+    assert lib.bmd_abi_version() == 1
+
+
+def test_descriptor_layout_matches_c(tmp_path):
+    src = tmp_path / "layout.c"
+    fields = [f[0] for f in bmd._Desc._fields_]
+    body = "\n".join(f'printf("%zu\\n", offsetof(bmd_problem_desc, {f}));' for f in fields)
+    src.write_text(f"""#include <stdio.h>
+#include <stddef.h>
+#include "bmd.h"
+int main(void) {{ printf("%zu\\n", sizeof(bmd_problem_desc)); {body} return 0; }}
+""")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    vals = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert vals[0] == ctypes.sizeof(bmd._Desc)
+    for f, off in zip(fields, vals[1:]):
+        assert getattr(bmd._Desc, f).offset == off, f
+
+
+def _create_status(spec):
+    lib = bmd.library()
+    desc = bmd.make_desc(spec)
+    h = ctypes.c_void_p()
+    st = lib.bmd_create_problem(ctypes.byref(desc), ctypes.byref(h), None)
+    return st, lib.bmd_last_error().decode()
+
+
+@pytest.mark.parametrize("change,status", [
+    ({"d": 0}, -2), ({"d": 7}, -2), ({"q_lo": 0.6, "q_hi": 0.5}, -2), ({"q_lo": 0.0}, -2),
+    ({"rho_b": 0.7}, -2), ({"info": -1.0}, -2), ({"alpha0": 0.0}, -2), ({"alpha_rule": 5}, -1),
+    ({"effect": 3}, -1), ({"sd_b0": -0.1}, -2), ({"tau_lo": 0.9, "tau_hi": 0.1}, -2),
+    ({"width": -1.0}, -2), ({"gh_nodes": 2}, -2), ({"bandwidth": [0.0]}, -2),
+    ({"m": [1]}, -2), ({"q_lo": 0.01}, -2),   # r = 0.99 > 0.95: bivariate quadrature range
+    ({"mu_b1": float("nan")}, -1),
+])
+def test_validation_rejects_before_any_launch(change, status):
+    spec = W.plain_1d()
+    spec.update(change)
+    st, msg = _create_status(spec)
+    assert st == status, msg
+    assert msg
+
+
+def test_null_arguments():
+    lib = bmd.library()
+    assert lib.bmd_create_problem(None, None, None) == -1
+    assert lib.bmd_eval_grid(None, 10, 0, None, None, None) == -1
+    assert lib.bmd_smooth(None, None, None, 0, None) == -1
+    assert lib.bmd_grid_size(None) == 0
+    lib.bmd_destroy_problem(None)  # NULL-safe
+
+
+def test_workloads_are_inputs_only():
+    # the shared input module must not import the oracle or the library
+    src = open(W.__file__).read()
+    assert "oracle" not in src.split('"""')[-1] and "ctypes" not in src
+    assert W.plain_3d()["m"] == [64, 64, 64] and W.precision_5d()["n_draws"] == 200_000
+    sc = W.batch_scenarios(16)
+    assert all(1 <= s["d"] <= 6 and 1e4 <= s["n_draws"] <= 1e6 for s in sc)

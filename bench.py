@@ -1,0 +1,221 @@
+"""Benchmark of the design-objective hot path on one MI355X.
+
+One step = the whole grid hot path on one synthetic problem: per-design
+precompute (grid, subgroup fraction, critical values), prior draws, the
+designs x draws sweep of the Formula 5 estimate, separable smoothing and the
+argmax.  Workload (default): three correlated biomarkers (rho_b = 0.3), a 64^3
+cutoff grid, M = 100,000 draws, bandwidth 0.03.  `value` is integrand
+evaluations per second of the FP32+FP64-sum path over whole steps; the plain
+FP64 path is timed the same way beside it.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "integrand evals/sec and % VALU roofline, FP32+comp vs FP64, at |Δobj|≤1e-5"
+PEAK_FP32_TFLOPS = 157.3          # published dense FP32 vector peak (packed FMA)
+PEAK_FP32_UNPACKED_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 flop x 2.4 GHz, unpacked FMA
+PEAK_FP64_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name: str) -> dict:
+    from paper_2005_10494_amd import workloads as W
+    return {"3d": W.plain_3d, "1d": W.plain_1d, "5d": W.precision_5d}[name]()
+
+
+# --------------------------------------------------------------- algorithmic work
+# Floating-point operations per (design, draw) evaluation, as the method needs
+# them (transcendentals count as one operation each):
+#   drift and thresholds                    6
+#   bivariate normal: 2 Phi (3 each) + h k, (h^2+k^2)/2 (4) + combine (3)  13
+#     plus 6 per Gauss-Legendre node (exponent 3, exp 1, weighted sum 2)
+#   summand and FP64 sums (1 - p, s1, s2)    4
+#   responder-in-subgroup overlap O, only when the design's cutoffs are on
+#     both sides of the drawn true cutoffs: d flops per Gauss-Hermite node.
+
+def bvn_nodes(rho: np.ndarray, prec: str) -> np.ndarray:
+    if prec == "fp64":
+        edges, counts = [0.3, 0.5, 0.75, 0.9, 0.95], [6, 8, 12, 16, 20, 24]
+    else:
+        edges, counts = [0.5, 0.75, 0.9, 0.95], [4, 6, 8, 10, 12]
+    return np.asarray(counts)[np.searchsorted(edges, rho, side="right")]
+
+
+def algorithmic_flops(spec: dict, r: np.ndarray, tau: np.ndarray, prec: str, K: int) -> float:
+    """Total flops of one sweep launch (all designs x all draws)."""
+    G = r.size
+    M = tau.shape[0]
+    n = bvn_nodes(np.sqrt(r), prec)
+    per_design = 23.0 + 6.0 * n
+    total = float(per_design.sum()) * M
+    d = spec["d"]
+    if d >= 2 and spec["effect"] == "step":
+        m = spec["m"]
+        # T_j(k) = number of grid cutoffs at or below the drawn tau_j
+        T = np.zeros((M, d), dtype=np.int64)
+        for j in range(d):
+            i = np.arange(m[j])
+            q = spec["q_lo"] + ((spec["q_hi"] - spec["q_lo"]) * i) / (m[j] - 1)
+            T[:, j] = np.searchsorted(q, tau[:, j], side="right")
+        above = np.prod(np.asarray(m)[None, :] - T, axis=1)   # all cutoffs above tau
+        below = np.prod(T, axis=1)                             # all below
+        mixed = G - above - below
+        total += float(mixed.sum()) * d * K
+    return total
+
+
+# --------------------------------------------------------------- GPU steps
+
+def run_steps(spec, prec, steps, warmup):
+    import torch
+    import paper_2005_10494_amd as bmd
+    M = spec["n_draws"]
+    sweep_ms, phase = [], []
+    t_total = 0.0
+    result = None
+    for it in range(warmup + steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = bmd.Problem(spec)
+        p.profile(True)
+        mean = p.eval_grid(M, prec)
+        smooth = p.smooth(mean, prec)
+        idx, val, cell = p.argmax(smooth)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ph = p.profile_read()
+        if it >= warmup:
+            t_total += t1 - t0
+            sweep_ms.append(ph["sweep"])
+            phase.append(ph)
+        if it == warmup + steps - 1:
+            result = dict(mean=mean, smooth=smooth, idx=idx, val=val, cell=cell, problem=p)
+        else:
+            p.close()
+        log(f"  {prec} step {it}{' (warmup)' if it < warmup else ''}: {1e3 * (t1 - t0):.1f} ms, "
+            f"sweep {ph['sweep']:.1f} ms, draws {ph['draws']:.2f} ms, smooth {ph['smooth']:.3f} ms")
+    avg_phase = {k: float(np.mean([p_[k] for p_ in phase])) for k in phase[0]}
+    return t_total, float(np.mean(sweep_ms)), avg_phase, result
+
+
+def cpu_baseline(spec, budget_s=12.0):
+    """The oracle as it stands, on a bounded sample of the same workload."""
+    import oracle as O
+    rng = np.random.default_rng(0)
+    G = int(np.prod(spec["m"]))
+    t0 = time.perf_counter()
+    O.eval_grid(spec, [G // 2], 500)           # calibration
+    per_eval = (time.perf_counter() - t0) / 500
+    n_designs = 8
+    M = int(max(200, min(spec["n_draws"], budget_s / per_eval / n_designs)))
+    gs = np.sort(rng.choice(G, n_designs, replace=False))
+    t0 = time.perf_counter()
+    O.eval_grid(spec, gs, M)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n_designs * M / dt, "unit": "integrand evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_designs} random designs of the {'x'.join(map(str, spec['m']))} grid x draws 0..{M - 1}"
+                      f" ({n_designs * M} evaluations, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="3d", choices=["3d", "1d", "5d"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is "
+              f"described in DESIGN.md and not launched.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2005_10494_amd as bmd
+    if not os.path.exists(bmd.LIB_PATH):
+        from paper_2005_10494_amd import build
+        build.build()
+    torch.cuda.set_device(0)
+    spec = workload(args.workload)
+    M, G = spec["n_draws"], int(np.prod(spec["m"]))
+    log(f"workload {args.workload}: d={spec['d']} grid={spec['m']} G={G} M={M}")
+
+    t32, sweep32, ph32, res32 = run_steps(spec, "fp32", args.steps, args.warmup)
+    evals = G * M
+    value = evals * args.steps / t32
+    out = {"metric": METRIC, "value": value, "unit": "integrand evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * t32 / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{spec['d']}-biomarker cutoff grid {'x'.join(map(str, spec['m']))}, "
+                                  f"M={M} prior draws, rho_b={spec['rho_b']}, bandwidth {spec['bandwidth'][0]}, "
+                                  f"FP32 integrand + FP64 sums, steps = precompute+draws+sweep+smooth+argmax",
+                      "d": spec["d"], "grid": spec["m"], "n_draws": M, "designs": G}}
+
+    # algorithmic work of the sweep launch
+    p32 = res32["problem"]
+    r = p32.designs(0, G)[:, 12].cpu().numpy()
+    d = spec["d"]
+    _, f = p32.draws(0, M)
+    tau = f[:, 5:5 + d].cpu().numpy()
+    flops32 = algorithmic_flops(spec, r, tau, "fp32", _gh_nodes(p32, "fp32"))
+    achieved = flops32 / (sweep32 * 1e-3) / 1e12
+    out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                       "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                       "kernel": "k_eval_direct<float,%d,12> (designs x draws sweep)" % d,
+                       "sweep_ms": sweep32, "flops_per_launch": flops32,
+                       "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
+                       "frac_unpacked": achieved / PEAK_FP32_UNPACKED_TFLOPS,
+                       "sweep_evals_per_s": evals / (sweep32 * 1e-3)}
+    out["phases_ms"] = ph32
+
+    if not args.no_fp64:
+        t64, sweep64, ph64, res64 = run_steps(spec, "fp64", args.steps, args.warmup)
+        flops64 = algorithmic_flops(spec, r, tau, "fp64", _gh_nodes(res64["problem"], "fp64"))
+        m32, m64 = res32["mean"], res64["mean"]
+        s32, s64 = res32["smooth"], res64["smooth"]
+        out["fp64"] = {"value": evals * args.steps / t64, "ms_per_step": 1e3 * t64 / args.steps,
+                       "sweep_ms": sweep64, "achieved_tflops": flops64 / (sweep64 * 1e-3) / 1e12,
+                       "frac_of_fp64_peak": flops64 / (sweep64 * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
+        out["fp32_vs_fp64"] = {
+            "speedup_step": (evals * args.steps / t32) / (evals * args.steps / t64),
+            "speedup_sweep": sweep64 / sweep32,
+            "max_abs_diff_objective": float((m32 - m64).abs().max()),
+            "max_abs_diff_smoothed": float((s32 - s64).abs().max()),
+            "max_rel_diff_smoothed": float(((s32 - s64).abs() / s64.abs().clamp_min(1e-3)).max()),
+            "objective_max_fp32": res32["val"], "objective_max_fp64": res64["val"],
+            "argmax_cell_fp32": list(res32["cell"]), "argmax_cell_fp64": list(res64["cell"])}
+        res64["problem"].close()
+    p32.close()
+
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(spec)
+    print(json.dumps(out), flush=True)
+
+
+def _gh_nodes(problem, prec) -> int:
+    """Gauss-Hermite node count the library chose (read from its axis tables' size)."""
+    import paper_2005_10494_amd as bmd
+    return bmd.gh_nodes(problem, prec)
+
+
+if __name__ == "__main__":
+    main()

@@ -126,6 +126,10 @@ void bmd_destroy_problem(bmd_problem *p);
 /* Number of grid designs G = prod m_j (0 for continuous-design problems). */
 int64_t bmd_grid_size(const bmd_problem *p);
 
+/* Gauss-Hermite nodes the problem uses for orthant probabilities at precision
+ * prec (chosen at creation when desc.gh_nodes is 0); -1 for a bad argument. */
+int32_t bmd_gh_nodes(const bmd_problem *p, int32_t prec);
+
 /* Monte Carlo estimate of the expected power (Formula 5) at every grid design
  * from draws k = 0 .. n_draws-1:
  *   d_mean[g] = (1/M) sum_k (1 - Phi_2(z1 - mu1_k, z2 - mu2_gk; sqrt r_g)),
@@ -171,6 +175,20 @@ bmd_status bmd_grad_design(bmd_problem *p, const double *d_q, int64_t B, uint64_
 bmd_status bmd_eval_batch(bmd_problem *const *ps, int32_t n, const uint64_t *n_draws,
                           int32_t prec, double *const *d_means, double *h_wall_ms,
                           void *stream);
+
+/* ---- profiling ------------------------------------------------------------ */
+
+#define BMD_PROFILE_PHASES 5
+/* Turn per-phase timing on (enable != 0) or off.  While on, bmd_eval_grid,
+ * bmd_smooth and bmd_argmax record HIP events around their kernels on the
+ * stream they launch on. */
+bmd_status bmd_profile(bmd_problem *p, int32_t enable);
+
+/* Device milliseconds of the latest profiled calls, h_ms[BMD_PROFILE_PHASES]:
+ * [0] draw kernel, [1] grid sweep kernel, [2] finalize kernel, [3] smoothing
+ * kernels, [4] argmax kernels (0 for phases not run since profiling began).
+ * Synchronises on the recorded events. */
+bmd_status bmd_profile_read(bmd_problem *p, double *h_ms);
 
 /* ---- inspection (bit-exactness of sample generation and grid indexing) ---- */
 

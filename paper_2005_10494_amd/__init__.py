@@ -58,6 +58,7 @@ SIGNATURES = {
     "bmd_create_problem": (ctypes.c_int, [ctypes.POINTER(_Desc), ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
     "bmd_destroy_problem": (None, [ctypes.c_void_p]),
     "bmd_grid_size": (ctypes.c_int64, [ctypes.c_void_p]),
+    "bmd_gh_nodes": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "bmd_eval_grid": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p]),
     "bmd_smooth": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
@@ -68,6 +69,8 @@ SIGNATURES = {
                                        ctypes.c_void_p]),
     "bmd_eval_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "bmd_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "bmd_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "bmd_draws": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.c_void_p]),
     "bmd_designs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
@@ -215,6 +218,15 @@ class Problem:
                                          _stream(stream)))
         return obj, gq, gmu
 
+    def profile(self, enable: bool = True):
+        _check(library().bmd_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """Device ms of the latest profiled phases: draws, sweep, finalize, smooth, argmax."""
+        out = np.zeros(5, dtype=np.float64)
+        _check(library().bmd_profile_read(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return dict(zip(("draws", "sweep", "finalize", "smooth", "argmax"), out.tolist()))
+
     def draws(self, k0: int, n: int, stream=None):
         import torch
         u = torch.empty(n, 8, dtype=torch.float64, device=self.device)
@@ -228,6 +240,10 @@ class Problem:
         f = torch.empty(n, DESIGN_FIELDS, dtype=torch.float64, device=self.device)
         _check(library().bmd_designs(self._h, int(g0), int(n), ctypes.c_void_p(f.data_ptr()), _stream(stream)))
         return f
+
+
+def gh_nodes(problem: "Problem", precision="fp64") -> int:
+    return int(library().bmd_gh_nodes(problem.handle, _prec(precision)))
 
 
 def eval_batch(problems, n_draws, precision="fp32", stream=None):

@@ -228,10 +228,19 @@ void free_problem(bmd_problem* p) {
     f(p->d_Wf);
     f(p->d_ws);
     f(p->d_ws2);
+    for (auto& e : p->ev)
+        if (e) (void)hipEventDestroy(e);
     delete p;
 }
 
 bool valid_prec(int32_t prec) { return prec == BMD_FP64 || prec == BMD_FP32_COMP; }
+
+// Event i of the profiling pairs (phase = i / 2), recorded when profiling is on.
+void mark(bmd_problem* p, int i, hipStream_t s) {
+    if (!p->profiling) return;
+    (void)hipEventRecord(p->ev[i], s);
+    p->ev_used[i / 2] = true;
+}
 
 }  // namespace
 
@@ -421,6 +430,11 @@ void bmd_destroy_problem(bmd_problem* p) {
 
 int64_t bmd_grid_size(const bmd_problem* p) { return p ? p->P.G : 0; }
 
+int32_t bmd_gh_nodes(const bmd_problem* p, int32_t prec) {
+    if (!p || !valid_prec(prec)) return -1;
+    return p->tab[prec].K;
+}
+
 bmd_status bmd_eval_grid(bmd_problem* p, uint64_t n_draws, int32_t prec, double* d_mean, double* d_var,
                          void* stream) {
     g_err.clear();
@@ -443,9 +457,15 @@ bmd_status bmd_eval_grid(bmd_problem* p, uint64_t n_draws, int32_t prec, double*
     bmd_status st = ensure(&p->d_ws, &p->ws_cap, draw_bytes + part_bytes);
     if (st != BMD_OK) return st;
     double* partials = reinterpret_cast<double*>(static_cast<char*>(p->d_ws) + draw_bytes);
+    mark(p, 0, s);
     HIP_TRY(launch_draws(p, prec, 0, M, p->d_ws, s), "draw kernel");
+    mark(p, 1, s);
+    mark(p, 2, s);
     HIP_TRY(launch_eval_grid(p, prec, M, p->d_ws, partials, static_cast<int>(n_slices), slice_len, s), "eval kernel");
+    mark(p, 3, s);
+    mark(p, 4, s);
     HIP_TRY(launch_finalize(p, M, partials, static_cast<int>(n_slices), d_mean, d_var, s), "finalize kernel");
+    mark(p, 5, s);
     return BMD_OK;
 }
 
@@ -459,8 +479,10 @@ bmd_status bmd_smooth(bmd_problem* p, const double* d_in, double* d_out, int32_t
     DeviceGuard guard(p->device);
     bmd_status st = ensure(&p->d_ws2, &p->ws2_cap, sizeof(double) * static_cast<size_t>(p->P.G));
     if (st != BMD_OK) return st;
-    HIP_TRY(launch_smooth(p, prec, d_in, d_out, static_cast<double*>(p->d_ws2), static_cast<hipStream_t>(stream)),
-            "smooth kernel");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    mark(p, 6, s);
+    HIP_TRY(launch_smooth(p, prec, d_in, d_out, static_cast<double*>(p->d_ws2), s), "smooth kernel");
+    mark(p, 7, s);
     return BMD_OK;
 }
 
@@ -478,7 +500,9 @@ bmd_status bmd_argmax(bmd_problem* p, const double* d_surface, int64_t* h_index,
     if (st != BMD_OK) return st;
     double* pv = static_cast<double*>(p->d_ws2);
     int64_t* pi = reinterpret_cast<int64_t*>(static_cast<char*>(p->d_ws2) + 8 * 1024);
+    mark(p, 8, s);
     HIP_TRY(launch_argmax(p, d_surface, n, pv, pi, n_part, s), "argmax kernels");
+    mark(p, 9, s);
     double v;
     int64_t i;
     HIP_TRY(hipMemcpyAsync(&v, pv, sizeof v, hipMemcpyDeviceToHost, s), "argmax readback");
@@ -513,6 +537,33 @@ bmd_status bmd_eval_batch(bmd_problem* const* ps, int32_t n, const uint64_t* n_d
     g_err.clear();
     (void)ps; (void)n; (void)n_draws; (void)prec; (void)d_means; (void)h_wall_ms; (void)stream;
     return fail(BMD_ENOTSUP, "eval_batch is not available in this build");
+}
+
+bmd_status bmd_profile(bmd_problem* p, int32_t enable) {
+    g_err.clear();
+    if (!p) return fail(BMD_EINVAL, "problem is NULL");
+    DeviceGuard guard(p->device);
+    if (enable && !p->ev[0])
+        for (auto& e : p->ev) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+    p->profiling = enable != 0;
+    for (bool& u : p->ev_used) u = false;
+    return BMD_OK;
+}
+
+bmd_status bmd_profile_read(bmd_problem* p, double* h_ms) {
+    g_err.clear();
+    if (!p || !h_ms) return fail(BMD_EINVAL, "NULL argument");
+    if (!p->ev[0]) return fail(BMD_ESTATE, "profiling was never enabled");
+    DeviceGuard guard(p->device);
+    for (int ph = 0; ph < BMD_PROFILE_PHASES; ++ph) {
+        h_ms[ph] = 0.0;
+        if (!p->ev_used[ph]) continue;
+        HIP_TRY(hipEventSynchronize(p->ev[2 * ph + 1]), "hipEventSynchronize");
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, p->ev[2 * ph], p->ev[2 * ph + 1]), "hipEventElapsedTime");
+        h_ms[ph] = ms;
+    }
+    return BMD_OK;
 }
 
 bmd_status bmd_draws(bmd_problem* p, uint64_t k0, uint64_t n, double* d_u, double* d_fields, void* stream) {

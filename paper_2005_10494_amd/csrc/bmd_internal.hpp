@@ -86,6 +86,9 @@ struct bmd_problem {
     void* d_ws2 = nullptr;           // second workspace (smoothing ping-pong, argmax partials)
     size_t ws2_cap = 0;
     std::vector<double> gh_host[2];  // host copies of the eval GH rules
+    bool profiling = false;
+    hipEvent_t ev[10] = {};          // begin/end pairs per profiled phase
+    bool ev_used[5] = {false, false, false, false, false};
 };
 
 namespace bmd {

@@ -4,6 +4,8 @@
 // sign changes, refined by bisection and a Newton step; weights are the
 // Christoffel numbers 1 / sum_{j<n} p_j(x_i)^2 of the orthonormal family.
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "bmd_internal.hpp"
@@ -64,18 +66,48 @@ void zeros_and_weights(int n, double lo, double hi, double step, F values, doubl
 
 }  // namespace
 
-void gauss_hermite_prob(int n, double* x, double* w) {
-    const double R = std::sqrt(2.0 * n + 1.0) + 1.0;
-    zeros_and_weights(n, -R, R, 1e-3, hermite_values, x, w);
-    // weight exp(-x^2)  ->  standard normal density: z = sqrt(2) x, w / sqrt(pi)
+namespace {
+
+// Rules are pure functions of n: build each once per process.
+std::mutex g_rule_mutex;
+std::map<int, std::vector<double>> g_hermite, g_legendre;
+
+template <typename Build>
+void cached(std::map<int, std::vector<double>>& cache, int n, double* x, double* w, Build build) {
+    std::lock_guard<std::mutex> lock(g_rule_mutex);
+    auto it = cache.find(n);
+    if (it == cache.end()) {
+        std::vector<double> r(2 * n);
+        build(n, r.data(), r.data() + n);
+        it = cache.emplace(n, std::move(r)).first;
+    }
     for (int i = 0; i < n; ++i) {
-        x[i] *= std::sqrt(2.0);
-        w[i] /= std::sqrt(M_PI);
+        x[i] = it->second[i];
+        w[i] = it->second[n + i];
     }
 }
 
+}  // namespace
+
+void gauss_hermite_prob(int n, double* x, double* w) {
+    cached(g_hermite, n, x, w, [](int n_, double* xx, double* ww) {
+        // zeros of the degree-n Hermite polynomial lie in |x| < sqrt(2n+1) and are
+        // at least ~pi/sqrt(2n+1) apart: scan in quarters of that spacing
+        const double R = std::sqrt(2.0 * n_ + 1.0) + 1.0;
+        zeros_and_weights(n_, -R, R, 0.25 * M_PI / std::sqrt(2.0 * n_ + 1.0), hermite_values, xx, ww);
+        // weight exp(-x^2)  ->  standard normal density: z = sqrt(2) x, w / sqrt(pi)
+        for (int i = 0; i < n_; ++i) {
+            xx[i] *= std::sqrt(2.0);
+            ww[i] /= std::sqrt(M_PI);
+        }
+    });
+}
+
 void gauss_legendre(int n, double* x, double* w) {
-    zeros_and_weights(n, -1.0, 1.0, 2e-5, legendre_values, x, w);
+    cached(g_legendre, n, x, w, [](int n_, double* xx, double* ww) {
+        // the outermost zeros are about (2.4/(n+1/2))^2/2 from +-1; scan finer than that
+        zeros_and_weights(n_, -1.0, 1.0, 0.25 / ((n_ + 1.0) * (n_ + 1.0)), legendre_values, xx, ww);
+    });
 }
 
 void gl_table(double* out) {

@@ -158,7 +158,8 @@ bmd_status bmd_argmax(bmd_problem *p, const double *d_surface, int64_t *h_index,
 
 /* Objective and its gradient at B continuous design points (the smoothness of
  * Appendix A.3 made explicit for the Newton step of Sec. 2.3):
- *   d_q       [B*d] FP64 cutoff quantiles, row-major, in [q_lo, q_hi]
+ *   d_q       [B*d] FP64 cutoff quantiles, row-major, in [q_lo, q_hi] (to 1e-12);
+ *             points outside get NaN outputs
  *   d_obj     [B]   FP64 Monte Carlo objective (as bmd_eval_grid's mean)
  *   d_grad_q  [B*d] d obj_b / d q_b,j (may be NULL)
  *   d_grad_mu [B*2] d obj_b / d (mu_b0, mu_b1) (may be NULL)

@@ -4,7 +4,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -329,6 +331,12 @@ bmd_status bmd_create_problem(const bmd_problem_desc* desc, bmd_problem** out, v
     P.key1 = static_cast<uint32_t>(d.seed >> 32);
     P.scenario = d.scenario_id;
     P.n_uniform = d.effect == BMD_EFFECT_STEP ? 2 + d.d : 2;
+    {
+        // BMD_SWEEP=direct selects the direct (vector-unit) sweep for every grid
+        // problem; both sweeps compute the same estimate (used by the tests).
+        const char* sw = std::getenv("BMD_SWEEP");
+        p->force_direct = sw && std::strcmp(sw, "direct") == 0;
+    }
 
     // Quadrature rules.
     std::vector<double> gl(kGLTable);
@@ -527,16 +535,259 @@ bmd_status bmd_argmax(bmd_problem* p, const double* d_surface, int64_t* h_index,
 bmd_status bmd_grad_design(bmd_problem* p, const double* d_q, int64_t B, uint64_t n_draws, int32_t prec,
                            double* d_obj, double* d_grad_q, double* d_grad_mu, void* stream) {
     g_err.clear();
-    (void)d_q; (void)B; (void)n_draws; (void)prec; (void)d_obj; (void)d_grad_q; (void)d_grad_mu; (void)stream;
     if (!p) return fail(BMD_EINVAL, "problem is NULL");
-    return fail(BMD_ENOTSUP, "grad_design is not available in this build");
+    if (!valid_prec(prec)) return fail(BMD_EINVAL, "unknown precision %d", prec);
+    if (!d_q || !d_obj) return fail(BMD_EINVAL, "NULL d_q or d_obj");
+    if (B < 1 || B > (int64_t(1) << 30)) return fail(BMD_ERANGE, "B must be in [1, 2^30]");
+    if (n_draws == 0 || n_draws > (1ull << 40)) return fail(BMD_ERANGE, "n_draws must be in [1, 2^40]");
+    if (p->P.effect != BMD_EFFECT_STEP) return fail(BMD_ENOTSUP, "grad_design needs the step prior");
+    DeviceGuard guard(p->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t M = static_cast<int64_t>(n_draws);
+    const int chunk = grad_chunk(prec, p->P.d, p->tab[prec].K);
+    const int64_t bx = (B + 127) / 128;
+    int64_t n_slices = std::max<int64_t>(1, std::min<int64_t>((2048 + bx - 1) / bx, (M + chunk - 1) / chunk));
+    n_slices = std::min<int64_t>(n_slices, 65535);
+    int64_t slice_len = (M + n_slices - 1) / n_slices;
+    slice_len = (slice_len + chunk - 1) / chunk * chunk;
+    n_slices = (M + slice_len - 1) / slice_len;
+    bmd_status st = ensure(&p->d_ws, &p->ws_cap, grad_workspace_bytes(p, prec, B, static_cast<int>(n_slices)));
+    if (st != BMD_OK) return st;
+    HIP_TRY(launch_grad(p, prec, d_q, B, M, p->d_ws, static_cast<int>(n_slices), slice_len, d_obj, d_grad_q,
+                        d_grad_mu, s),
+            "gradient kernels");
+    return BMD_OK;
 }
+
+namespace {
+
+// Measured GPU-wide seconds per (design, draw) evaluation of the batched
+// kernel, per precision and biomarker count; filled by probe launches.
+std::mutex g_cost_mutex;
+double g_cost[2][BMD_MAX_DIM + 1] = {};
+
+struct DeviceBuffer {
+    void* ptr = nullptr;
+    ~DeviceBuffer() {
+        if (ptr) (void)hipFree(ptr);
+    }
+};
+
+// Time the persistent kernel on a synthetic work list drawn from scenario S:
+// every tile, one slice of `L` draws, enough items to fill the device twice.
+bmd_status probe_cost(const BatchScenario& S0, int prec, int chunk, size_t lds, int grid, const double* gl,
+                      hipStream_t cs, double* cost) {
+    BatchScenario S = S0;
+    const int64_t L = 4 * chunk;
+    S.slice_len = L;
+    S.n_slices = 1;
+    const int n_items = 2 * grid;
+    S.n_items = n_items;
+    S.g_offset = 0;
+    std::vector<int4> items(n_items);
+    for (int i = 0; i < n_items; ++i) items[i] = make_int4(0, i % S.tiles, 0, 0);
+    const size_t part = sizeof(double) * static_cast<size_t>(S.P.G);
+    const size_t bytes = 256 + sizeof(BatchScenario) + sizeof(int4) * n_items + 4096 + part;
+    DeviceBuffer buf;
+    HIP_TRY(hipMalloc(&buf.ptr, bytes), "probe buffer");
+    char* c = static_cast<char*>(buf.ptr);
+    BatchScenario* d_sc = reinterpret_cast<BatchScenario*>(c);
+    int4* d_items = reinterpret_cast<int4*>(c + 256 + sizeof(BatchScenario));
+    char* ctr = c + 256 + sizeof(BatchScenario) + sizeof(int4) * n_items;
+    S.partials = reinterpret_cast<double*>(ctr + 4096);
+    S.mean = nullptr;
+    HIP_TRY(hipMemcpy(d_sc, &S, sizeof S, hipMemcpyHostToDevice), "probe upload");
+    HIP_TRY(hipMemcpy(d_items, items.data(), sizeof(int4) * n_items, hipMemcpyHostToDevice), "probe upload");
+    BatchArgs a{d_sc, 1, d_items, n_items, reinterpret_cast<int*>(ctr), reinterpret_cast<int*>(ctr + 64),
+                reinterpret_cast<unsigned long long*>(ctr + 128), reinterpret_cast<unsigned long long*>(ctr + 192),
+                gl, chunk, S.P.G};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+    float ms = 0.0f;
+    hipError_t e = hipSuccess;
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {   // the first run absorbs one-time costs
+        e = hipEventRecord(e0, cs);
+        if (e == hipSuccess) e = launch_batch(prec, a, grid, lds, true, false, cs);
+        if (e == hipSuccess) e = hipEventRecord(e1, cs);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "autotune probe");
+    *cost = (ms * 1e-3) / (static_cast<double>(n_items) * kEvalBlock * L);
+    return BMD_OK;
+}
+
+}  // namespace
 
 bmd_status bmd_eval_batch(bmd_problem* const* ps, int32_t n, const uint64_t* n_draws, int32_t prec,
                           double* const* d_means, double* h_wall_ms, void* stream) {
     g_err.clear();
-    (void)ps; (void)n; (void)n_draws; (void)prec; (void)d_means; (void)h_wall_ms; (void)stream;
-    return fail(BMD_ENOTSUP, "eval_batch is not available in this build");
+    if (!ps || !n_draws || !d_means) return fail(BMD_EINVAL, "NULL argument");
+    if (n < 1 || n > 65536) return fail(BMD_ERANGE, "n must be in [1, 65536]");
+    if (!valid_prec(prec)) return fail(BMD_EINVAL, "unknown precision %d", prec);
+    for (int i = 0; i < n; ++i) {
+        if (!ps[i] || !d_means[i]) return fail(BMD_EINVAL, "problem or output %d is NULL", i);
+        if (!ps[i]->grid) return fail(BMD_ESTATE, "problem %d has no grid", i);
+        if (ps[i]->device != ps[0]->device) return fail(BMD_EINVAL, "problems live on different devices");
+        if (n_draws[i] == 0 || n_draws[i] > (1ull << 40)) return fail(BMD_ERANGE, "n_draws[%d] outside [1, 2^40]", i);
+    }
+    DeviceGuard guard(ps[0]->device);
+    hipStream_t us = static_cast<hipStream_t>(stream);
+    const int dev = ps[0]->device;
+    int n_cu = 0, clock_khz = 0;
+    HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev), "device attribute");
+    HIP_TRY(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev), "device attribute");
+    int Kmax = 1;
+    for (int i = 0; i < n; ++i) Kmax = std::max(Kmax, ps[i]->tab[prec].K);
+    int chunk = 32;
+    while (chunk > 1 && batch_lds_bytes(prec, chunk, Kmax) > 48 * 1024) chunk /= 2;
+    const size_t lds = batch_lds_bytes(prec, chunk, Kmax);
+    const int grid = n_cu * batch_blocks_per_cu(prec, lds);
+
+    // Scenario records (device pointers filled below).
+    std::vector<BatchScenario> sc(n);
+    for (int i = 0; i < n; ++i) {
+        const bmd_problem* p = ps[i];
+        BatchScenario& S = sc[i];
+        std::memset(&S, 0, sizeof S);
+        S.P = p->P;
+        S.r = p->d_r;
+        S.z1 = p->d_z1;
+        S.z2 = p->d_z2;
+        S.A = p->tab[prec].A;
+        S.gh = p->tab[prec].gh;
+        S.glw = p->tab[prec].glw;
+        S.K = p->tab[prec].K;
+        S.tiles = static_cast<int>((p->P.G + kEvalBlock - 1) / kEvalBlock);
+        S.M = static_cast<int64_t>(n_draws[i]);
+        S.mean = d_means[i];
+    }
+
+    hipStream_t cs = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() { (void)hipStreamDestroy(s); }
+    } sg{cs};
+    {
+        hipEvent_t ev;
+        HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
+        hipError_t e = hipEventRecord(ev, us);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, ev, 0);
+        (void)hipEventDestroy(ev);
+        HIP_TRY(e, "stream ordering");
+    }
+
+    // Autotuner: per biomarker count, measured cost of one evaluation.
+    double cost[BMD_MAX_DIM + 1] = {};
+    for (int i = 0; i < n; ++i) {
+        const int d = sc[i].P.d;
+        if (cost[d] > 0.0) continue;
+        {
+            std::lock_guard<std::mutex> lock(g_cost_mutex);
+            cost[d] = g_cost[prec][d];
+        }
+        if (cost[d] > 0.0) continue;
+        bmd_status st = probe_cost(sc[i], prec, chunk, lds, grid, ps[i]->d_gl, cs, &cost[d]);
+        if (st != BMD_OK) return st;
+        std::lock_guard<std::mutex> lock(g_cost_mutex);
+        g_cost[prec][d] = cost[d];
+    }
+
+    // Plan: slices sized so the list holds about eight items per resident
+    // workgroup, each item costing about the same.
+    double total = 0.0;
+    for (int i = 0; i < n; ++i) total += static_cast<double>(sc[i].tiles) * kEvalBlock * sc[i].M * cost[sc[i].P.d];
+    const double target = total / (8.0 * grid);
+    struct Item {
+        int4 v;
+        double c;
+    };
+    std::vector<Item> list;
+    int64_t g_off = 0;
+    size_t part_bytes = 0;
+    for (int i = 0; i < n; ++i) {
+        BatchScenario& S = sc[i];
+        const double c = cost[S.P.d];
+        int64_t L = static_cast<int64_t>(std::ceil(target / (kEvalBlock * c) / chunk)) * chunk;
+        const int64_t Mr = (S.M + chunk - 1) / chunk * chunk;
+        L = std::max<int64_t>(chunk, std::min<int64_t>(L, Mr));
+        S.slice_len = L;
+        S.n_slices = static_cast<int>((S.M + L - 1) / L);
+        S.n_items = S.tiles * S.n_slices;
+        S.g_offset = g_off;
+        g_off += S.P.G;
+        part_bytes += (sizeof(double) * static_cast<size_t>(S.n_slices) * S.P.G + 255) / 256 * 256;
+        for (int t = 0; t < S.tiles; ++t)
+            for (int sl = 0; sl < S.n_slices; ++sl) {
+                const double active = static_cast<double>(std::min<int64_t>(kEvalBlock, S.P.G - int64_t(t) * kEvalBlock));
+                const double draws = static_cast<double>(std::min<int64_t>(L, S.M - int64_t(sl) * L));
+                list.push_back({make_int4(i, t, sl, 0), active * draws * c});
+            }
+    }
+    if (list.size() > (1u << 24)) return fail(BMD_ERANGE, "batch work list of %zu items is too large", list.size());
+    std::stable_sort(list.begin(), list.end(), [](const Item& x, const Item& y) { return x.c > y.c; });
+    std::vector<int4> items(list.size());
+    for (size_t i = 0; i < list.size(); ++i) items[i] = list[i].v;
+
+    // Device buffers: scenarios, items, counters, partials.
+    const size_t sc_bytes = (sizeof(BatchScenario) * n + 255) / 256 * 256;
+    const size_t it_bytes = (sizeof(int4) * items.size() + 255) / 256 * 256;
+    const size_t ctr_bytes = (64 + 4 * static_cast<size_t>(n) + 64 + 8 * static_cast<size_t>(n) + 255) / 256 * 256 + 256;
+    DeviceBuffer buf;
+    {
+        hipError_t e = hipMalloc(&buf.ptr, sc_bytes + it_bytes + ctr_bytes + part_bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(BMD_ENOMEM, "batch workspace: %s", hipGetErrorString(e));
+        }
+    }
+    char* base = static_cast<char*>(buf.ptr);
+    BatchScenario* d_sc = reinterpret_cast<BatchScenario*>(base);
+    int4* d_items = reinterpret_cast<int4*>(base + sc_bytes);
+    char* ctr = base + sc_bytes + it_bytes;
+    int* d_counter = reinterpret_cast<int*>(ctr);
+    int* d_left = reinterpret_cast<int*>(ctr + 64);
+    unsigned long long* d_tstart = reinterpret_cast<unsigned long long*>(ctr + (64 + 4 * static_cast<size_t>(n) + 7) / 8 * 8);
+    unsigned long long* d_tdone = d_tstart + 8;
+    char* part = base + sc_bytes + it_bytes + ctr_bytes;
+    for (int i = 0; i < n; ++i) {
+        sc[i].partials = reinterpret_cast<double*>(part);
+        part += (sizeof(double) * static_cast<size_t>(sc[i].n_slices) * sc[i].P.G + 255) / 256 * 256;
+    }
+    HIP_TRY(hipMemcpy(d_sc, sc.data(), sizeof(BatchScenario) * n, hipMemcpyHostToDevice), "batch upload");
+    HIP_TRY(hipMemcpy(d_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice), "batch upload");
+    BatchArgs a{d_sc, n, d_items, static_cast<int>(items.size()), d_counter, d_left, d_tstart, d_tdone,
+                ps[0]->d_gl, chunk, g_off};
+
+    // One graph: reset counters, persistent sweep, finalize.
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    hipError_t le = launch_batch(prec, a, grid, lds, true, true, cs);
+    hipError_t ce = hipStreamEndCapture(cs, &graph);
+    if (le != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(le, "batch capture");
+    }
+    HIP_TRY(ce, "hipStreamEndCapture");
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, cs);
+    if (e == hipSuccess) e = hipStreamSynchronize(cs);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    HIP_TRY(e, "batch graph");
+    if (h_wall_ms) {
+        std::vector<unsigned long long> t(n + 1);
+        HIP_TRY(hipMemcpy(t.data(), d_tstart, sizeof(unsigned long long), hipMemcpyDeviceToHost), "batch readback");
+        HIP_TRY(hipMemcpy(t.data() + 1, d_tdone, sizeof(unsigned long long) * n, hipMemcpyDeviceToHost), "batch readback");
+        for (int i = 0; i < n; ++i)
+            h_wall_ms[i] = t[i + 1] >= t[0] ? static_cast<double>(t[i + 1] - t[0]) / clock_khz : 0.0;
+    }
+    return BMD_OK;
 }
 
 bmd_status bmd_profile(bmd_problem* p, int32_t enable) {

@@ -56,6 +56,41 @@ struct DrawArrays {
     int K;
 };
 
+// One scenario of a batched launch (bmd_eval_batch).
+struct BatchScenario {
+    DevProblem P;
+    const double* r;
+    const double* z1;
+    const double* z2;
+    const void* A;          // axis tables in T
+    const double* gh;       // FP64 Gauss-Hermite rule x[K], w[K]
+    const void* glw;        // packed GL weights in T
+    int K;
+    int tiles;
+    int n_slices;
+    int n_items;
+    int64_t M;
+    int64_t slice_len;
+    int64_t g_offset;       // first flattened design index (finalize)
+    double* partials;       // [n_slices][G]
+    double* mean;           // output [G]
+};
+
+// Arguments of the batched persistent kernel.
+struct BatchArgs {
+    const BatchScenario* sc;
+    int n_sc;
+    const int4* items;      // (scenario, tile, slice, 0)
+    int n_items;
+    int* counter;
+    int* left;              // items not yet finished, per scenario
+    unsigned long long* t_start;
+    unsigned long long* t_done;
+    const double* gl;
+    int chunk;
+    int64_t G_total;
+};
+
 // Device constants owned by a problem, per integrand precision.
 struct PrecTables {
     int K = 0;                  // Gauss-Hermite nodes
@@ -86,6 +121,7 @@ struct bmd_problem {
     void* d_ws2 = nullptr;           // second workspace (smoothing ping-pong, argmax partials)
     size_t ws2_cap = 0;
     std::vector<double> gh_host[2];  // host copies of the eval GH rules
+    bool force_direct = false;      // BMD_SWEEP=direct: use the direct sweep everywhere
     bool profiling = false;
     hipEvent_t ev[10] = {};          // begin/end pairs per profiled phase
     bool ev_used[5] = {false, false, false, false, false};
@@ -106,6 +142,7 @@ hipError_t launch_draws(const bmd_problem* p, int prec, uint64_t k0, int64_t M, 
 size_t draw_workspace_bytes(const bmd_problem* p, int prec, int64_t M);
 DrawArrays<double> draws_fp64(const bmd_problem* p, int64_t M, const void* ws);
 DrawArrays<float> draws_fp32(const bmd_problem* p, int64_t M, const void* ws);
+bool use_mfma_sweep(const bmd_problem* p);
 hipError_t launch_eval_grid(const bmd_problem* p, int prec, int64_t M, const void* ws,
                             double* partials, int n_slices, int64_t slice_len, hipStream_t s);
 hipError_t launch_finalize(const bmd_problem* p, int64_t M, const double* partials, int n_slices,
@@ -114,6 +151,14 @@ hipError_t launch_smooth(const bmd_problem* p, int prec, const double* in, doubl
                          double* tmp, hipStream_t s);
 hipError_t launch_argmax(const bmd_problem* p, const double* v, int64_t n, double* part_v,
                          int64_t* part_i, int n_part, hipStream_t s);
+size_t grad_workspace_bytes(const bmd_problem* p, int prec, int64_t B, int n_slices);
+int grad_chunk(int prec, int d, int K);
+hipError_t launch_grad(const bmd_problem* p, int prec, const double* d_q, int64_t B, int64_t M, void* ws,
+                       int n_slices, int64_t slice_len, double* obj, double* gq, double* gmu, hipStream_t s);
+size_t batch_lds_bytes(int prec, int chunk, int K);
+int batch_blocks_per_cu(int prec, size_t lds);
+hipError_t launch_batch(int prec, const BatchArgs& a, int grid, size_t lds, bool reset, bool finalize,
+                        hipStream_t s);
 hipError_t launch_inspect_draws(const bmd_problem* p, uint64_t k0, int64_t n, double* u,
                                 double* fields, hipStream_t s);
 hipError_t launch_inspect_designs(const bmd_problem* p, int64_t g0, int64_t n, double* fields,

@@ -181,4 +181,13 @@ __device__ __forceinline__ float bvn_cdf(float h, float k, const BvnConst<float,
     return norm_cdf(h) * norm_cdf(k) + c.scale * acc;
 }
 
+// Row of the 16x16 result held in accumulator element v of a lane in quarter
+// kq = lane / 16 (the column is lane % 16).  Operands: lane l supplies A[l%16][l/16]
+// and B[l/16][l%16].  The FP32 16x16x4 instruction gives each quarter four
+// consecutive rows; the FP64 one interleaves them with stride 4.
+template <typename T>
+__device__ __forceinline__ int mfma16_row(int kq, int v) {
+    return sizeof(T) == 8 ? kq + 4 * v : 4 * kq + v;
+}
+
 }  // namespace bmd

@@ -1,13 +1,11 @@
 // Grid sweep of the expected-power estimate (Formula 5): one thread per design,
-// draw slices across workgroups, FP64 per-design sums.
-//
-// Per (design g, draw k) the summand is 1 - Phi_2(z1 - mu1_k, z2 - mu2_gk; sqrt r_g):
-//   step prior:  mu1 = sqrt(I) (b0 + b1 P(R)),  mu2 = sqrt(r I) (b0 + b1 O / r),
-//                O = P(x_j > max(c_j, t_j) all j)  (responders inside the subgroup)
-//   paper prior: mu1 = sqrt(I) Delta_1,  mu2 = sqrt(r I) Delta_2  (Formula 10)
-// The integrand is evaluated in T (double or float); sums are always FP64.
+// draw slices across workgroups, FP64 per-design sums reduced in fixed order.
+// The summand itself is in eval_core.hpp; T is the integrand type.
+#include <type_traits>
+
 #include "bmd_internal.hpp"
 #include "device_math.hpp"
+#include "eval_core.hpp"
 
 namespace bmd {
 namespace {
@@ -26,150 +24,162 @@ struct EvalArgs {
     double* partials;    // [n_slices][2][G]
 };
 
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
-    return __builtin_amdgcn_readfirstlane(v);
-}
-
-template <typename T>
-__device__ __forceinline__ T logistic(T x) {
-    return T(1) / (T(1) + exp(-x));
-}
-
-// Responder-in-subgroup fraction O for draw k (d >= 2, grid design idx).
-template <typename T, int D>
-__device__ __forceinline__ T overlap_grid(const EvalArgs<T>& a, const int* idx, const double* q, T rT,
-                                          int64_t k) {
-    const int64_t M = a.D.M;
-    const int K = a.D.K;
-    const int mmax = a.P.mmax;
-    const T* Bk = a.D.B + k * D * K;
-    if (a.P.width > 0.0) {
-        T s[D];
-#pragma unroll
-        for (int j = 0; j < D; ++j)
-            s[j] = logistic(static_cast<T>((q[j] - a.D.tau[j * M + k]) / a.P.width));
-        T acc = T(0);
-        for (int m = 0; m < K; ++m) {
-            T prod = T(1);
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-                const T av = a.A[(static_cast<int64_t>(j) * K + m) * mmax + idx[j]];
-                const T bv = Bk[j * K + m];
-                prod *= s[j] * av + (T(1) - s[j]) * bv;
-            }
-            acc += prod;
-        }
-        return acc;
-    }
-    bool fl[D];
-    bool all = true, none = true;
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-        fl[j] = idx[j] >= a.D.thr[j * M + k];
-        all = all && fl[j];
-        none = none && !fl[j];
-    }
-    if (all) return rT;
-    if (none) return a.D.PR[k];
-    const T* src[D];
-    int64_t step[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-        src[j] = fl[j] ? a.A + static_cast<int64_t>(j) * K * mmax + idx[j] : Bk + j * K;
-        step[j] = fl[j] ? mmax : 1;
-    }
-    T acc = T(0);
-    for (int m = 0; m < K; ++m) {
-        T prod = src[0][m * step[0]];
-#pragma unroll
-        for (int j = 1; j < D; ++j) prod *= src[j][m * step[j]];
-        acc += prod;
-    }
-    return acc;
-}
-
 template <typename T, int D, int NMAX>
 __global__ __launch_bounds__(kEvalBlock) void k_eval_direct(EvalArgs<T> a) {
     const int64_t G = a.P.G;
     const int64_t g = static_cast<int64_t>(blockIdx.x) * kEvalBlock + threadIdx.x;
     const bool valid = g < G;
     const int64_t gg = valid ? g : G - 1;   // idle lanes shadow the last design
-
-    int idx[D];
-    double q[D];
-    {
-        int64_t rem = gg;
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            idx[j] = static_cast<int>(rem / a.P.stride[j]);
-            rem -= static_cast<int64_t>(idx[j]) * a.P.stride[j];
-            q[j] = grid_coord(a.P.q_lo, a.P.q_hi, idx[j], a.P.m[j]);
-        }
-    }
-    const double r = a.r[gg];
-    const double rho = sqrt(r);
-    const int n_lane = sizeof(T) == 8 ? bvn_nodes_fp64(rho) : bvn_nodes_fp32(rho);
-    const int n = wave_max(n_lane);
-    BvnConst<T, NMAX> bc;
-    bc.init(rho, n, a.gl);
-    const T* w = a.glw + gl_offset(n) + n;
-
-    const double srI_d = sqrt(r * a.P.info);
-    const T z1 = static_cast<T>(a.z1[gg]);
-    const T z2 = static_cast<T>(a.z2[gg]);
-    const T srI = static_cast<T>(srI_d);
-    const T invr = static_cast<T>(1.0 / r);
-    const T rT = static_cast<T>(r);
-    const T omq = static_cast<T>(1.0 - q[0]);
-    // paper prior: mu2 = c0 + c1 e1 + c2 e2
-    T c0 = T(0), c1 = T(0), c2 = T(0);
-    if (a.P.effect == BMD_EFFECT_PAPER_GAUSS) {
-        const double th2 = -log1p(-(a.P.paper_a - a.P.paper_b * r));
-        const double sg2 = 1.0 / sqrt(a.P.paper_events * r / 4.0);
-        c0 = static_cast<T>(srI_d * th2);
-        c1 = static_cast<T>(srI_d * sg2 * sqrt(r));
-        c2 = static_cast<T>(srI_d * sg2 * sqrt(1.0 - r));
-    }
-
+    DesignState<T, D, NMAX> s;
+    s.init(a.P, gg, a.r, a.z1, a.z2, a.gl, a.glw);
+    const GlobalDraws<T> src{a.D, D};
     const int64_t M = a.D.M;
     const int64_t kb = static_cast<int64_t>(blockIdx.y) * a.slice_len;
     const int64_t ke = min(M, kb + a.slice_len);
-    const bool step_prior = a.P.effect == BMD_EFFECT_STEP;
-    const int zinf = a.P.zinf;
     double s1 = 0.0, s2 = 0.0;
     for (int64_t k = kb; k < ke; ++k) {
-        const T mu1 = a.D.mu1[k];
-        T mu2;
-        if (step_prior) {
-            T O;
-            if constexpr (D == 1) {
-                if (a.P.width > 0.0) {
-                    const double tau = a.D.tau[k];
-                    const T s = logistic(static_cast<T>((q[0] - tau) / a.P.width));
-                    O = T(1) - (s * static_cast<T>(q[0]) + (T(1) - s) * a.D.tauT[k]);
-                } else {
-                    O = idx[0] >= a.D.thr[k] ? omq : T(1) - a.D.tauT[k];
-                }
-            } else {
-                O = overlap_grid<T, D>(a, idx, q, rT, k);
-            }
-            mu2 = srI * (a.D.b0[k] + a.D.b1[k] * O * invr);
-        } else {
-            mu2 = c0 + c1 * a.D.e1[k] + c2 * a.D.e2[k];
-        }
-        const T h = z1 - mu1, kq = z2 - mu2;
-        T p;
-        if (zinf == 0) p = bvn_cdf<NMAX>(h, kq, bc, w, n);
-        else if (zinf == 1) p = norm_cdf(kq);
-        else if (zinf == 2) p = norm_cdf(h);
-        else p = T(1);
-        const double v = static_cast<double>(T(1) - p);
+        const double v = static_cast<double>(summand<T, D, NMAX>(a.P, s, src, k, a.A, a.D.K));
         s1 += v;
         s2 += v * v;
     }
     if (valid) {
+        double* out = a.partials + static_cast<int64_t>(blockIdx.y) * 2 * G;
+        out[g] = s1;
+        out[G + g] = s2;
+    }
+}
+
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ mf_f4 mf_step(float a, float b, mf_f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ mf_d4 mf_step(double a, double b, mf_d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Tile geometry of the matrix-core sweep: designs g = p * Sn + l with prefix
+// index p (axes < split) and suffix index l (axes >= split); a workgroup owns a
+// 16 x 16 tile of (p, l) and a slice of draws.
+struct MfmaGeom {
+    int split;
+    int64_t Pn, Sn;       // prefix and suffix counts
+    int64_t tiles_l;      // tiles along the suffix index
+    int chunk;            // draws staged per LDS chunk
+};
+
+// Sweep for grid designs with d >= 2, step prior, exact cutoff indicator.
+// Phase A (matrix cores): for each draw of the chunk,
+//   O[p][l] = sum_m Pre[p][m] Suf[l][m],
+//   Pre[p][m] = prod_{j < split} v_j(p)[m],  Suf[l][m] = prod_{j >= split} v_j(l)[m],
+//   v_j[m] = A_j[i_j][m] if the design's cutoff on axis j lies above the drawn one
+//            (i_j >= thr_j(k)), else the draw's B_j[m]  (Gauss-Hermite weights in axis 0),
+// i.e. the one-factor quadrature of P(x_j > max(c_j, t_j) all j) for all 256
+// designs at once; each wavefront takes every fourth draw.
+// Phase B (vector units): one design per thread, the bivariate normal part.
+template <typename T, int D, int NMAX>
+__global__ __launch_bounds__(kEvalBlock) void k_eval_mfma(EvalArgs<T> a, MfmaGeom geo) {
+    using acc_t = typename std::conditional<sizeof(T) == 8, mf_d4, mf_f4>::type;
+    extern __shared__ __align__(16) char lds[];
+    const int K = a.D.K;
+    const int CH = geo.chunk;
+    const int Kp = (K + 3) / 4 * 4;
+    T* sO = reinterpret_cast<T*>(lds);                       // [CH][256]
+    T* sB = sO + static_cast<size_t>(CH) * kEvalBlock;        // [CH][D][Kp]
+    T* sb0 = sB + static_cast<size_t>(CH) * D * Kp;          // [CH]
+    T* sb1 = sb0 + CH;
+    T* smu1 = sb1 + CH;
+    int* sthr = reinterpret_cast<int*>(smu1 + CH);            // [CH][D]
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t tile = blockIdx.x;
+    const int64_t p0 = (tile / geo.tiles_l) * 16, l0 = (tile % geo.tiles_l) * 16;
+    const int64_t G = a.P.G;
+    const int64_t M = a.D.M;
+    const int mmax = a.P.mmax;
+
+    // phase B design: row tid/16, column tid%16 of the tile
+    const int64_t pB = p0 + tid / 16, lB = l0 + tid % 16;
+    const bool validB = pB < geo.Pn && lB < geo.Sn;
+    const int64_t g = validB ? pB * geo.Sn + lB : G - 1;
+    DesignState<T, D, NMAX> st;
+    st.init(a.P, g, a.r, a.z1, a.z2, a.gl, a.glw);
+
+    // phase A operands: lane supplies row (p0 + lane%16) of Pre and column
+    // (l0 + lane%16) of Suf at node m0 + lane/16
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int64_t pA = p0 + r16, lA = l0 + r16;
+    const bool rowA = pA < geo.Pn, colA = lA < geo.Sn;
+    int iA[D];
+    {
+        int64_t rem = (rowA ? pA : 0) * geo.Sn + (colA ? lA : 0);
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            iA[j] = static_cast<int>(rem / a.P.stride[j]);
+            rem -= static_cast<int64_t>(iA[j]) * a.P.stride[j];
+        }
+    }
+
+    const int64_t kb = static_cast<int64_t>(blockIdx.y) * a.slice_len;
+    const int64_t ke = min(M, kb + a.slice_len);
+    double s1 = 0.0, s2 = 0.0;
+    for (int64_t k0 = kb; k0 < ke; k0 += CH) {
+        const int nk = static_cast<int>(min<int64_t>(CH, ke - k0));
+        __syncthreads();
+        // stage the chunk's draws
+        for (int e = tid; e < nk * D * Kp; e += kEvalBlock) {
+            const int i = e / (D * Kp), rem = e % (D * Kp), j = rem / Kp, m = rem % Kp;
+            sB[e] = m < K ? a.D.B[(k0 + i) * D * K + j * K + m] : T(0);
+        }
+        for (int e = tid; e < nk; e += kEvalBlock) {
+            sb0[e] = a.D.b0[k0 + e];
+            sb1[e] = a.D.b1[k0 + e];
+            smu1[e] = a.D.mu1[k0 + e];
+        }
+        for (int e = tid; e < nk * D; e += kEvalBlock) {
+            const int i = e / D, j = e % D;
+            sthr[e] = a.D.thr[j * M + k0 + i];
+        }
+        __syncthreads();
+        // phase A: overlaps of the tile, one draw per wavefront at a time
+        for (int i = wave; i < nk; i += kEvalBlock / 64) {
+            bool fl[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) fl[j] = iA[j] >= sthr[i * D + j];
+            const T* Bi = sB + static_cast<size_t>(i) * D * Kp;
+            acc_t c = {0, 0, 0, 0};
+            for (int m0 = 0; m0 < Kp; m0 += 4) {
+                const int m = m0 + kq;
+                T pre = T(1), suf = T(1);
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const T av = m < K ? a.A[(static_cast<int64_t>(j) * K + m) * mmax + iA[j]] : T(0);
+                    const T v = fl[j] ? av : Bi[j * Kp + m];
+                    if (j < geo.split) pre *= v; else suf *= v;
+                }
+                c = mf_step(rowA ? pre : T(0), colA ? suf : T(0), c);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                sO[static_cast<size_t>(i) * kEvalBlock + mfma16_row<T>(kq, v) * 16 + r16] = c[v];
+        }
+        __syncthreads();
+        // phase B: bivariate normal part for this thread's design
+        for (int i = 0; i < nk; ++i) {
+            const T O = sO[static_cast<size_t>(i) * kEvalBlock + tid];
+            const T mu2 = st.srI * (sb0[i] + sb1[i] * O * st.invr);
+            const T h = st.z1 - smu1[i], kq2 = st.z2 - mu2;
+            T p;
+            if (a.P.zinf == 0) p = bvn_cdf<NMAX>(h, kq2, st.bc, st.w, st.n);
+            else if (a.P.zinf == 1) p = norm_cdf(kq2);
+            else if (a.P.zinf == 2) p = norm_cdf(h);
+            else p = T(1);
+            const double v = static_cast<double>(T(1) - p);
+            s1 += v;
+            s2 += v * v;
+        }
+    }
+    if (validB) {
         double* out = a.partials + static_cast<int64_t>(blockIdx.y) * 2 * G;
         out[g] = s1;
         out[G + g] = s2;
@@ -190,10 +200,59 @@ __global__ void k_finalize(int64_t G, int64_t M, int n_slices, const double* __r
     if (var) var[g] = M > 1 ? fmax(0.0, (s2 - s1 * s1 / Md) / (Md - 1.0)) : 0.0;
 }
 
+template <typename T>
+size_t mfma_lds_bytes(int chunk, int d, int K) {
+    const int Kp = (K + 3) / 4 * 4;
+    return sizeof(T) * static_cast<size_t>(chunk) * (kEvalBlock + static_cast<size_t>(d) * Kp + 3) +
+           sizeof(int) * static_cast<size_t>(chunk) * d;
+}
+
+// Prefix/suffix split with the least tile padding (ties: the later split).
+MfmaGeom mfma_geometry(const bmd_problem* p, int prec) {
+    MfmaGeom geo{};
+    const int d = p->P.d;
+    double best = 1e300;
+    for (int s = 1; s < d; ++s) {
+        int64_t P = 1, S = 1;
+        for (int j = 0; j < s; ++j) P *= p->P.m[j];
+        for (int j = s; j < d; ++j) S *= p->P.m[j];
+        const double padded = static_cast<double>((P + 15) / 16 * 16) * static_cast<double>((S + 15) / 16 * 16);
+        if (padded <= best) {
+            best = padded;
+            geo.split = s;
+            geo.Pn = P;
+            geo.Sn = S;
+        }
+    }
+    geo.tiles_l = (geo.Sn + 15) / 16;
+    const int K = p->tab[prec].K;
+    int ch = 32;
+    const size_t cap = 48 * 1024;
+    while (ch > 4 && (prec == BMD_FP64 ? mfma_lds_bytes<double>(ch, d, K) : mfma_lds_bytes<float>(ch, d, K)) > cap)
+        ch /= 2;
+    geo.chunk = ch;
+    return geo;
+}
+
 template <typename T, int NMAX>
 hipError_t launch_typed(const bmd_problem* p, int prec, const EvalArgs<T>& a, int n_slices, hipStream_t s) {
+    const int d = p->P.d;
+    if (use_mfma_sweep(p)) {
+        const MfmaGeom geo = mfma_geometry(p, prec);
+        const int64_t tiles = ((geo.Pn + 15) / 16) * geo.tiles_l;
+        const dim3 grid(static_cast<unsigned>(tiles), static_cast<unsigned>(n_slices));
+        const size_t lds = mfma_lds_bytes<T>(geo.chunk, d, a.D.K);
+        switch (d) {
+            case 2: hipLaunchKernelGGL((k_eval_mfma<T, 2, NMAX>), grid, dim3(kEvalBlock), lds, s, a, geo); break;
+            case 3: hipLaunchKernelGGL((k_eval_mfma<T, 3, NMAX>), grid, dim3(kEvalBlock), lds, s, a, geo); break;
+            case 4: hipLaunchKernelGGL((k_eval_mfma<T, 4, NMAX>), grid, dim3(kEvalBlock), lds, s, a, geo); break;
+            case 5: hipLaunchKernelGGL((k_eval_mfma<T, 5, NMAX>), grid, dim3(kEvalBlock), lds, s, a, geo); break;
+            default: hipLaunchKernelGGL((k_eval_mfma<T, 6, NMAX>), grid, dim3(kEvalBlock), lds, s, a, geo); break;
+        }
+        return hipGetLastError();
+    }
     const dim3 grid(static_cast<unsigned>((p->P.G + kEvalBlock - 1) / kEvalBlock), static_cast<unsigned>(n_slices));
-    switch (p->P.d) {
+    switch (d) {
         case 1: hipLaunchKernelGGL((k_eval_direct<T, 1, NMAX>), grid, dim3(kEvalBlock), 0, s, a); break;
         case 2: hipLaunchKernelGGL((k_eval_direct<T, 2, NMAX>), grid, dim3(kEvalBlock), 0, s, a); break;
         case 3: hipLaunchKernelGGL((k_eval_direct<T, 3, NMAX>), grid, dim3(kEvalBlock), 0, s, a); break;
@@ -206,6 +265,12 @@ hipError_t launch_typed(const bmd_problem* p, int prec, const EvalArgs<T>& a, in
 }
 
 }  // namespace
+
+// The matrix-core sweep covers grid problems with at least two biomarkers,
+// the step prior and the exact cutoff indicator; the rest use the direct one.
+bool use_mfma_sweep(const bmd_problem* p) {
+    return p->grid && p->P.d >= 2 && p->P.effect == BMD_EFFECT_STEP && p->P.width == 0.0 && !p->force_direct;
+}
 
 hipError_t launch_eval_grid(const bmd_problem* p, int prec, int64_t M, const void* ws, double* partials,
                             int n_slices, int64_t slice_len, hipStream_t s) {

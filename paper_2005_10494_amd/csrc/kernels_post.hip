@@ -1,10 +1,13 @@
 // Smoothing of the estimated surface and its argmax (Sec. 2.3: borrow strength
-// from neighbouring designs, then take the best point).
+// from neighbouring designs, then take the best point).  Smoothing runs on the
+// matrix cores (FP64 16x16x4 or FP32 16x16x4 MFMA).
 //
 // The product-Gaussian Nadaraya-Watson smoother factorises: with row-normalised
 // one-axis matrices W_j[i][h] = exp(-((q_i - q_h)/b_j)^2/2) / sum_h' (...),
 // S = W_0 x_0 W_1 x_1 ... f, applied one axis at a time.
+#include <algorithm>
 #include <cfloat>
+#include <type_traits>
 
 #include "bmd_internal.hpp"
 #include "device_math.hpp"
@@ -12,20 +15,47 @@
 namespace bmd {
 namespace {
 
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+// One 16x16x4 matrix-core step: C += A (16x4) B (4x16); operand and result
+// layout as described at mfma16_row.
+__device__ __forceinline__ mfma_d4 mfma_step(double a, double b, mfma_d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ mfma_f4 mfma_step(float a, float b, mfma_f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// One separable smoothing pass as a batched GEMM on the matrix cores:
+//   out(i, n) = sum_h W[i][h] in(h, n),  i, h < m,  n < N,
+// with in(h, n) = in[ob + h*sh + n*sn] (same for out) and ob = blockIdx.z * ostride.
+// One wavefront per 16x16 output tile; T is the arithmetic type (FP64 or FP32,
+// the FP32 path converting the FP64 surface on load and accumulating in FP32).
 template <typename T>
-__global__ void k_smooth_axis(int64_t G, int m, int64_t inner, const T* __restrict__ W,
-                              const double* __restrict__ in, double* __restrict__ out) {
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= G) return;
-    const int64_t s = t % inner;
-    const int64_t oi = t / inner;
-    const int i = static_cast<int>(oi % m);
-    const int64_t o = oi / m;
-    const double* src = in + o * m * inner + s;
-    const T* Wi = W + static_cast<int64_t>(i) * m;
-    T acc = T(0);
-    for (int h = 0; h < m; ++h) acc += Wi[h] * static_cast<T>(src[static_cast<int64_t>(h) * inner]);
-    out[t] = static_cast<double>(acc);
+__global__ __launch_bounds__(64) void k_smooth_mfma(const T* __restrict__ W, int m, const double* __restrict__ in,
+                                                    double* __restrict__ out, int64_t N, int64_t sh, int64_t sn,
+                                                    int64_t ostride) {
+    using acc_t = typename std::conditional<sizeof(T) == 8, mfma_d4, mfma_f4>::type;
+    const int lane = threadIdx.x;
+    const int r = lane & 15, kq = lane >> 4;
+    const int64_t n0 = static_cast<int64_t>(blockIdx.x) * 16;
+    const int i0 = blockIdx.y * 16;
+    const int64_t ob = static_cast<int64_t>(blockIdx.z) * ostride;
+    const int i = i0 + r;
+    const int64_t n = n0 + r;
+    acc_t c = {0, 0, 0, 0};
+    for (int h0 = 0; h0 < m; h0 += 4) {
+        const int h = h0 + kq;
+        const T a = (i < m && h < m) ? W[static_cast<int64_t>(i) * m + h] : T(0);
+        const T b = (h < m && n < N) ? static_cast<T>(in[ob + h * sh + n * sn]) : T(0);
+        c = mfma_step(a, b, c);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int io = i0 + mfma16_row<T>(kq, v);
+        if (io < m && n < N) out[ob + io * sh + n * sn] = static_cast<double>(c[v]);
+    }
 }
 
 __device__ __forceinline__ bool better(double va, int64_t ia, double vb, int64_t ib) {
@@ -90,15 +120,30 @@ hipError_t launch_smooth(const bmd_problem* p, int prec, const double* in, doubl
     const double* src = in;
     for (int j = 0; j < d; ++j) {
         double* dst = ((d - 1 - j) % 2 == 0) ? out : tmp;
-        const unsigned blocks = static_cast<unsigned>((G + 255) / 256);
-        if (prec == BMD_FP64)
-            hipLaunchKernelGGL(k_smooth_axis<double>, dim3(blocks), dim3(256), 0, s, G, p->P.m[j], p->P.stride[j],
-                               p->d_W + p->w_off[j], src, dst);
-        else
-            hipLaunchKernelGGL(k_smooth_axis<float>, dim3(blocks), dim3(256), 0, s, G, p->P.m[j], p->P.stride[j],
-                               p->d_Wf + p->w_off[j], src, dst);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        const int m = p->P.m[j];
+        const int64_t inner = p->P.stride[j];
+        const int64_t outer = G / (inner * m);
+        // axis j as a batched GEMM: columns run over the inner index (batches
+        // over the outer one), or over the outer index when axis j is last
+        const int64_t N = inner > 1 ? inner : outer;
+        const int64_t sn = inner > 1 ? 1 : m;
+        const int64_t nb = inner > 1 ? outer : 1;
+        const int64_t ostride = inner > 1 ? static_cast<int64_t>(m) * inner : 0;
+        for (int64_t zb = 0; zb < nb; zb += 65535) {   // grid z is at most 65535
+            const int64_t nz = std::min<int64_t>(65535, nb - zb);
+            const dim3 grid(static_cast<unsigned>((N + 15) / 16), static_cast<unsigned>((m + 15) / 16),
+                            static_cast<unsigned>(nz));
+            const double* sz = src + zb * ostride;
+            double* dz = dst + zb * ostride;
+            if (prec == BMD_FP64)
+                hipLaunchKernelGGL(k_smooth_mfma<double>, grid, dim3(64), 0, s, p->d_W + p->w_off[j], m, sz, dz, N,
+                                   inner, sn, ostride);
+            else
+                hipLaunchKernelGGL(k_smooth_mfma<float>, grid, dim3(64), 0, s, p->d_Wf + p->w_off[j], m, sz, dz, N,
+                                   inner, sn, ostride);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
         src = dst;
     }
     return hipSuccess;

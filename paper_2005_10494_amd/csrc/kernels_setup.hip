@@ -71,7 +71,7 @@ __device__ double zstar(double rho, double alpha0, const double* __restrict__ gl
     return z;
 }
 
-__global__ void k_design_precompute(DevProblem P, const double* __restrict__ ghp, int Kp,
+__global__ __launch_bounds__(128) void k_design_precompute(DevProblem P, const double* __restrict__ ghp, int Kp,
                                     const double* __restrict__ gl, double* __restrict__ r_out,
                                     double* __restrict__ z1_out, double* __restrict__ z2_out) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -127,7 +127,7 @@ __device__ __forceinline__ int32_t count_le(const DevProblem& P, int j, double t
 
 // One prior draw per thread (Formula 5's Delta^(k)).
 template <typename T>
-__global__ void k_draws(DevProblem P, const double* __restrict__ gh, int K, uint64_t k0, int64_t M,
+__global__ __launch_bounds__(128) void k_draws(DevProblem P, const double* __restrict__ gh, int K, uint64_t k0, int64_t M,
                         DrawArrays<T> D) {
     const int64_t kk = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (kk >= M) return;
@@ -175,7 +175,7 @@ __global__ void k_draws(DevProblem P, const double* __restrict__ gh, int K, uint
     }
 }
 
-__global__ void k_inspect_draws(DevProblem P, const double* __restrict__ gh, int K, uint64_t k0,
+__global__ __launch_bounds__(128) void k_inspect_draws(DevProblem P, const double* __restrict__ gh, int K, uint64_t k0,
                                 int64_t n, double* __restrict__ u_out, double* __restrict__ f_out) {
     const int64_t kk = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (kk >= n) return;
@@ -202,7 +202,7 @@ __global__ void k_inspect_draws(DevProblem P, const double* __restrict__ gh, int
     }
 }
 
-__global__ void k_inspect_designs(DevProblem P, int64_t g0, int64_t n, const double* __restrict__ r,
+__global__ __launch_bounds__(128) void k_inspect_designs(DevProblem P, int64_t g0, int64_t n, const double* __restrict__ r,
                                   const double* __restrict__ z1, const double* __restrict__ z2,
                                   double* __restrict__ out) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;

@@ -1,0 +1,79 @@
+"""Batched form: many uneven grid problems in one persistent, graph-captured
+launch, checked against the single-problem sweep (same draws) and against the
+oracle on sampled designs."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2005_10494_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2005_10494_amd as bmd  # noqa: E402
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _scenarios(n, seed, m_scale, draws):
+    sc = W.batch_scenarios(n, seed=seed, m_scale=m_scale, m_draws=draws)
+    return sc
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_matches_single_problem_sweeps(prec):
+    sc = _scenarios(14, seed=4, m_scale=0.25, draws=(300, 3000))
+    say(f"batch of {len(sc)} scenarios, d = {[s['d'] for s in sc]}, {prec}")
+    probs = [bmd.Problem(s) for s in sc]
+    try:
+        means, wall = bmd.eval_batch(probs, [s["n_draws"] for s in sc], prec)
+        torch.cuda.synchronize()
+        for p, s, m in zip(probs, sc, means):
+            ref = p.eval_grid(s["n_draws"], prec)
+            torch.cuda.synchronize()
+            err = (m - ref).abs().max().item()
+            assert err <= 1e-12, (s["d"], s["m"], err)
+        assert np.all(wall > 0) and np.all(np.isfinite(wall))
+        means2, _ = bmd.eval_batch(probs, [s["n_draws"] for s in sc], prec)
+        for a, b in zip(means, means2):
+            assert torch.equal(a, b)
+    finally:
+        for p in probs:
+            p.close()
+
+
+def test_batch_matches_oracle_sampled():
+    sc = _scenarios(8, seed=9, m_scale=0.2, draws=(200, 800))
+    probs = [bmd.Problem(s) for s in sc]
+    try:
+        means, _ = bmd.eval_batch(probs, [s["n_draws"] for s in sc], "fp64")
+        m32, _ = bmd.eval_batch(probs, [s["n_draws"] for s in sc], "fp32")
+        rng = np.random.default_rng(0)
+        for p, s, m, m3 in zip(probs, sc, means, m32):
+            G = p.G
+            gs = np.unique(np.concatenate([[0, G - 1], rng.integers(0, G, 3)]))
+            ref, _ = O.eval_grid(s, gs, s["n_draws"])
+            got = m.cpu().numpy()[gs]
+            got32 = m3.cpu().numpy()[gs]
+            assert np.all(np.abs(got - ref) <= 1e-9 * np.maximum(np.abs(ref), 1e-3)), (s["d"], got, ref)
+            assert np.all(np.abs(got32 - ref) <= 1e-5 * np.maximum(np.abs(ref), 1e-3)), (s["d"], got32, ref)
+    finally:
+        for p in probs:
+            p.close()
+
+
+def test_batch_single_and_invalid():
+    spec = W.base_problem(2, [9, 11], 0.3, 0.05)
+    with bmd.Problem(spec) as p:
+        (m,), wall = bmd.eval_batch([p], [1234], "fp32")
+        ref = p.eval_grid(1234, "fp32")
+        assert (m - ref).abs().max().item() <= 1e-12
+        assert wall[0] > 0
+        with pytest.raises(bmd.BmdError):
+            bmd.eval_batch([p], [0], "fp32")

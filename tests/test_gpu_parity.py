@@ -196,7 +196,8 @@ def test_bitwise_deterministic_reruns():
 
 # ------------------------------------------------------------ smoothing and argmax
 
-@pytest.mark.parametrize("spec", [W.plain_1d(), W.base_problem(3, [9, 8, 7], 0.3, 0.08)])
+@pytest.mark.parametrize("spec", [W.plain_1d(), W.base_problem(3, [9, 8, 7], 0.3, 0.08),
+                                  W.base_problem(5, [5, 7, 3, 9, 4], 0.3, 0.1), W.base_problem(2, [40, 33], 0.2, 0.04)])
 def test_smooth_and_argmax_match_oracle(spec):
     G = O.grid_size(spec)
     with bmd.Problem(spec) as p:
@@ -263,3 +264,24 @@ def test_full_1d_config_both_precisions():
 def test_full_3d_config_fp64_sampled():
     spec = W.plain_3d()
     _sampled_full(spec, "fp64", n_sample=3, M=spec["n_draws"])
+
+
+@pytest.mark.parametrize("shape,rho", [((9, 7), 0.3), ((17, 6, 33), 0.3), ((3, 5, 3, 4, 3), 0.45), ((2, 3, 2, 3, 2, 3), 0.5)])
+def test_direct_and_matrix_core_sweeps_agree(shape, rho, monkeypatch):
+    spec = W.base_problem(len(shape), list(shape), rho, 0.05)
+    M = 777
+    out = {}
+    for mode in ("direct", "mfma"):
+        if mode == "direct":
+            monkeypatch.setenv("BMD_SWEEP", "direct")
+        else:
+            monkeypatch.delenv("BMD_SWEEP", raising=False)
+        for prec in ("fp64", "fp32"):
+            out[mode, prec] = gpu_eval(spec, M, prec)
+    assert np.max(np.abs(out["direct", "fp64"] - out["mfma", "fp64"])) <= 1e-12
+    assert np.max(np.abs(out["direct", "fp32"] - out["mfma", "fp32"])) <= 2e-6
+    G = O.grid_size(spec)
+    gs = np.unique(np.linspace(0, G - 1, 9).astype(int))
+    ref, _ = O.eval_grid(spec, gs, M)
+    assert_close(out["mfma", "fp64"][gs], ref, "fp64")
+    assert_close(out["mfma", "fp32"][gs], ref, "fp32")

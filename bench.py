@@ -28,6 +28,8 @@ METRIC = "integrand evals/sec and % VALU roofline, FP32+comp vs FP64, at |Δobj|
 PEAK_FP32_TFLOPS = 157.3          # published dense FP32 vector peak (packed FMA)
 PEAK_FP32_UNPACKED_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 flop x 2.4 GHz, unpacked FMA
 PEAK_FP64_TFLOPS = 78.6
+SWEEP_KERNEL = {"direct": "k_eval_direct<float,%d,12> (designs x draws sweep, one design per thread)",
+                "matrix": "k_eval_mfma<float,%d,12> (designs x draws sweep, 16x16 design tiles, overlap on MFMA)"}
 
 
 def log(*a):
@@ -114,23 +116,25 @@ def run_steps(spec, prec, steps, warmup):
     return t_total, float(np.mean(sweep_ms)), avg_phase, result
 
 
-def cpu_baseline(spec, budget_s=12.0):
-    """The oracle as it stands, on a bounded sample of the same workload."""
+def cpu_baseline(spec, budget_s=15.0):
+    """The oracle as it stands, on a bounded sample of the same workload:
+    random designs of the grid against the workload's full set of draws, as
+    many designs as a short calibration run says fit in about ``budget_s``."""
     import oracle as O
     rng = np.random.default_rng(0)
     G = int(np.prod(spec["m"]))
+    M = int(spec["n_draws"])
+    M_cal, n_cal = min(M, 5000), 16
     t0 = time.perf_counter()
-    O.eval_grid(spec, [G // 2], 500)           # calibration
-    per_eval = (time.perf_counter() - t0) / 500
-    n_designs = 8
-    M = int(max(200, min(spec["n_draws"], budget_s / per_eval / n_designs)))
+    O.eval_grid(spec, np.sort(rng.choice(G, n_cal, replace=False)), M_cal)   # calibration
+    per_eval = (time.perf_counter() - t0) / (M_cal * n_cal)
+    n_designs = int(min(G, max(4, budget_s / (per_eval * M))))
     gs = np.sort(rng.choice(G, n_designs, replace=False))
     t0 = time.perf_counter()
     O.eval_grid(spec, gs, M)
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": n_designs * M / dt, "unit": "integrand evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n_designs} random designs of the {'x'.join(map(str, spec['m']))} grid x draws 0..{M - 1}"
+    return {"value": n_designs * M / dt, "unit": "integrand evals/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{n_designs} random designs of the {'x'.join(map(str, spec['m']))} grid x all {M} draws"
                       f" ({n_designs * M} evaluations, {dt:.1f} s)"}
 
 
@@ -179,7 +183,7 @@ def main():
     achieved = flops32 / (sweep32 * 1e-3) / 1e12
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                        "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                       "kernel": "k_eval_direct<float,%d,12> (designs x draws sweep)" % d,
+                       "kernel": SWEEP_KERNEL[bmd.sweep_kind(p32)] % d,
                        "sweep_ms": sweep32, "flops_per_launch": flops32,
                        "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
                        "frac_unpacked": achieved / PEAK_FP32_UNPACKED_TFLOPS,

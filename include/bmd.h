@@ -130,6 +130,16 @@ int64_t bmd_grid_size(const bmd_problem *p);
  * prec (chosen at creation when desc.gh_nodes is 0); -1 for a bad argument. */
 int32_t bmd_gh_nodes(const bmd_problem *p, int32_t prec);
 
+/* Which kernel the designs x draws sweep of bmd_eval_grid uses for this
+ * problem: BMD_SWEEP_DIRECT (one design per thread; one biomarker, the
+ * logistic indicator, the paper's Formula 10 prior, or the environment
+ * variable BMD_SWEEP=direct at creation) or BMD_SWEEP_MATRIX (16x16 design
+ * tiles of the Sec. 2.2 sweep whose responder-overlap sums over the
+ * Gauss-Hermite nodes run on the matrix cores as rank-K products).
+ * Returns -1 for a NULL problem or a continuous-design one. */
+enum { BMD_SWEEP_DIRECT = 0, BMD_SWEEP_MATRIX = 1 };
+int32_t bmd_sweep_kind(const bmd_problem *p);
+
 /* Monte Carlo estimate of the expected power (Formula 5) at every grid design
  * from draws k = 0 .. n_draws-1:
  *   d_mean[g] = (1/M) sum_k (1 - Phi_2(z1 - mu1_k, z2 - mu2_gk; sqrt r_g)),

@@ -90,6 +90,7 @@ def lib():
             "or_argmax": (I64, [I64, P]),
             "or_grad_points": (None, [pp, I64, P, U64, U64, P, P, P]),
             "or_exact_step": (D, [pp, P]), "or_exact_paper": (D, [pp, P]),
+            "or_num_threads": (ctypes.c_int, []),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -282,6 +283,11 @@ def exact_paper(prob, q):
     qq = np.zeros(6)
     qq[: s.d] = q
     return lib().or_exact_paper(ctypes.byref(s), _ptr(qq))
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().or_num_threads())
 
 
 def success_with_draw(prob, q, draw: dict):

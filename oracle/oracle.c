@@ -12,6 +12,7 @@
 #include "oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -872,3 +873,6 @@ double or_exact_paper(const or_problem *p, const double *q)
     double s1 = sqrt(V11), s2 = sqrt(V22);
     return 1.0 - or_bvn((ds.z1 - m1) / s1, (ds.z2 - m2) / s2, V12 / (s1 * s2));
 }
+
+/* Threads the OpenMP loops of this library run with (for reporting). */
+int or_num_threads(void) { return omp_get_max_threads(); }

@@ -114,6 +114,9 @@ void   or_grad_points(const or_problem *p, int64_t n, const double *q,
 double or_exact_step(const or_problem *p, const double *q);    /* d <= 2 */
 double or_exact_paper(const or_problem *p, const double *q);
 
+/* ---- reporting ----------------------------------------------------------- */
+int    or_num_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -59,6 +59,7 @@ SIGNATURES = {
     "bmd_destroy_problem": (None, [ctypes.c_void_p]),
     "bmd_grid_size": (ctypes.c_int64, [ctypes.c_void_p]),
     "bmd_gh_nodes": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "bmd_sweep_kind": (ctypes.c_int32, [ctypes.c_void_p]),
     "bmd_eval_grid": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p]),
     "bmd_smooth": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
@@ -244,6 +245,14 @@ class Problem:
 
 def gh_nodes(problem: "Problem", precision="fp64") -> int:
     return int(library().bmd_gh_nodes(problem.handle, _prec(precision)))
+
+
+def sweep_kind(problem: "Problem") -> str:
+    """'direct' or 'matrix': the sweep kernel eval_grid uses for this problem."""
+    k = int(library().bmd_sweep_kind(problem.handle))
+    if k < 0:
+        raise BmdError(-1, "sweep_kind needs a grid problem")
+    return "matrix" if k == 1 else "direct"
 
 
 def eval_batch(problems, n_draws, precision="fp32", stream=None):

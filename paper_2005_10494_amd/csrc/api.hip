@@ -443,6 +443,11 @@ int32_t bmd_gh_nodes(const bmd_problem* p, int32_t prec) {
     return p->tab[prec].K;
 }
 
+int32_t bmd_sweep_kind(const bmd_problem* p) {
+    if (!p || !p->grid) return -1;
+    return use_mfma_sweep(p) ? BMD_SWEEP_MATRIX : BMD_SWEEP_DIRECT;
+}
+
 bmd_status bmd_eval_grid(bmd_problem* p, uint64_t n_draws, int32_t prec, double* d_mean, double* d_var,
                          void* stream) {
     g_err.clear();

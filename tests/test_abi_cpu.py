@@ -81,6 +81,8 @@ def test_null_arguments():
     assert lib.bmd_eval_grid(None, 10, 0, None, None, None) == -1
     assert lib.bmd_smooth(None, None, None, 0, None) == -1
     assert lib.bmd_grid_size(None) == 0
+    assert lib.bmd_sweep_kind(None) == -1
+    assert lib.bmd_gh_nodes(None, 0) == -1
     lib.bmd_destroy_problem(None)  # NULL-safe
 
 

@@ -27,11 +27,18 @@ def _scenarios(n, seed, m_scale, draws):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_batch_matches_single_problem_sweeps(prec):
+def test_batch_matches_single_problem_sweeps(prec, monkeypatch):
+    """The batched kernel evaluates each design with the per-design summand of
+    the direct sweep, so it matches that sweep up to the FP64 order of the
+    partial sums; the matrix-core sweep (d >= 2) rounds its FP32 overlap sums
+    in another order and is held to the FP32 bar."""
     sc = _scenarios(14, seed=4, m_scale=0.25, draws=(300, 3000))
     say(f"batch of {len(sc)} scenarios, d = {[s['d'] for s in sc]}, {prec}")
+    monkeypatch.setenv("BMD_SWEEP", "direct")
     probs = [bmd.Problem(s) for s in sc]
+    monkeypatch.delenv("BMD_SWEEP")
     try:
+        assert all(bmd.sweep_kind(p) == "direct" for p in probs)
         means, wall = bmd.eval_batch(probs, [s["n_draws"] for s in sc], prec)
         torch.cuda.synchronize()
         for p, s, m in zip(probs, sc, means):
@@ -43,6 +50,12 @@ def test_batch_matches_single_problem_sweeps(prec):
         means2, _ = bmd.eval_batch(probs, [s["n_draws"] for s in sc], prec)
         for a, b in zip(means, means2):
             assert torch.equal(a, b)
+        tol = 1e-12 if prec == "fp64" else 1e-6
+        for s, m in zip(sc, means):
+            with bmd.Problem(s) as q:
+                ref = q.eval_grid(s["n_draws"], prec)
+                err = (m - ref).abs().max().item()
+                assert err <= tol, (s["d"], bmd.sweep_kind(q), err)
     finally:
         for p in probs:
             p.close()
@@ -73,7 +86,7 @@ def test_batch_single_and_invalid():
     with bmd.Problem(spec) as p:
         (m,), wall = bmd.eval_batch([p], [1234], "fp32")
         ref = p.eval_grid(1234, "fp32")
-        assert (m - ref).abs().max().item() <= 1e-12
+        assert (m - ref).abs().max().item() <= 1e-6
         assert wall[0] > 0
         with pytest.raises(bmd.BmdError):
             bmd.eval_batch([p], [0], "fp32")

@@ -1,0 +1,52 @@
+"""The single-precision normal CDF of the FP32 integrand (fitted tail form,
+coefficients in csrc/normal_cdf_fit.hpp), replayed on the CPU operation by
+operation in single precision and checked against scipy's double-precision
+ndtr: absolute error within 1.2e-7 everywhere and no bias."""
+import importlib.util
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2005_10494_amd", "csrc")
+
+
+def _header_coefficients():
+    text = open(os.path.join(CSRC, "normal_cdf_fit.hpp")).read()
+    body = text[text.index("kPhiFit[kPhiFitDeg + 1]"):]
+    vals = re.findall(r"(-?0x[0-9a-fA-F.]+p[-+]\d+)f", body)
+    return np.array([float.fromhex(v) for v in vals], dtype=np.float32)
+
+
+def _generator():
+    spec = importlib.util.spec_from_file_location("gen_fit", os.path.join(CSRC, "gen_normal_cdf_fit.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_fit_header_matches_generator_degree():
+    gen = _generator()
+    c = _header_coefficients()
+    assert c.size == gen.DEG + 1 and c[0] == 0.0
+
+
+def test_fp32_normal_cdf_accuracy_and_bias():
+    scipy_special = pytest.importorskip("scipy.special")
+    gen = _generator()
+    c = _header_coefficients()
+    xs = np.concatenate([np.linspace(-13.0, 8.0, 6001), np.linspace(-1.0, 1.0, 2001),
+                         np.random.default_rng(3).normal(0.0, 2.0, 4000)]).astype(np.float32)
+    got = np.array([float(gen.phi32(x, c)) for x in xs])
+    ref = scipy_special.ndtr(xs.astype(np.float64))
+    err = got - ref
+    assert np.abs(err).max() <= 1.2e-7
+    assert abs(err.mean()) <= 2e-9
+    # tails: relative accuracy where Phi is still a normal float
+    tail = (xs < -1.0) & (ref > 1e-30)
+    assert np.all(np.abs(err[tail]) <= 2e-5 * ref[tail] + 1e-37)
+    # saturation and symmetry
+    assert float(gen.phi32(np.float32(40.0), c)) == 1.0 and float(gen.phi32(np.float32(-40.0), c)) == 0.0
+    assert abs(float(gen.phi32(np.float32(0.0), c)) - 0.5) <= 6e-8

@@ -16,6 +16,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -34,6 +35,36 @@ SWEEP_KERNEL = {"direct": "k_eval_direct<float,%d,12> (designs x draws sweep, on
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def source_digest() -> str:
+    """SHA-256 over the HIP sources and the C header (the code a counter run measured)."""
+    import hashlib
+    h = hashlib.sha256()
+    files = []
+    for sub in ("include", os.path.join("paper_2005_10494_amd", "csrc")):
+        base = os.path.join(ROOT, sub)
+        files += [os.path.join(sub, f) for f in sorted(os.listdir(base))
+                  if f.endswith((".hip", ".hpp", ".h", ".cpp"))]
+    for rel in sorted(files):
+        h.update(rel.encode())
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(summary: str, kernel: str):
+    """HBM bytes per launch of `kernel` from a committed counter summary, or None
+    when the summary is missing or was taken on other sources."""
+    path = os.path.join(ROOT, "profiles", summary)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"source digest: `([0-9a-f]{64})`", text)
+    if not m or m.group(1) != source_digest():
+        return None
+    row = re.search(r"\| `%s` \| ([0-9.e+]+) \| ([0-9.e+]+) \|" % re.escape(kernel), text)
+    return None if row is None else float(row.group(1)) + float(row.group(2))
 
 
 def workload(name: str) -> dict:
@@ -146,6 +177,9 @@ def main():
     ap.add_argument("--workload", default="3d", choices=["3d", "1d", "5d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many bytes (3 times): the reference "
+                         "kernel that scales the HBM byte counters of a profiler run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is "
@@ -158,6 +192,15 @@ def main():
         from paper_2005_10494_amd import build
         build.build()
     torch.cuda.set_device(0)
+    if args.copy_bytes > 0:
+        n = args.copy_bytes // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n, "launches": 3}), flush=True)
+        return
     spec = workload(args.workload)
     M, G = spec["n_draws"], int(np.prod(spec["m"]))
     log(f"workload {args.workload}: d={spec['d']} grid={spec['m']} G={G} M={M}")
@@ -171,7 +214,8 @@ def main():
            "config": {"workload": f"{spec['d']}-biomarker cutoff grid {'x'.join(map(str, spec['m']))}, "
                                   f"M={M} prior draws, rho_b={spec['rho_b']}, bandwidth {spec['bandwidth'][0]}, "
                                   f"FP32 integrand + FP64 sums, steps = precompute+draws+sweep+smooth+argmax",
-                      "d": spec["d"], "grid": spec["m"], "n_draws": M, "designs": G}}
+                      "d": spec["d"], "grid": spec["m"], "n_draws": M, "designs": G,
+                      "gauss_hermite_nodes": _gh_nodes(res32["problem"], "fp32")}}
 
     # algorithmic work of the sweep launch
     p32 = res32["problem"]
@@ -181,9 +225,13 @@ def main():
     tau = f[:, 5:5 + d].cpu().numpy()
     flops32 = algorithmic_flops(spec, r, tau, "fp32", _gh_nodes(p32, "fp32"))
     achieved = flops32 / (sweep32 * 1e-3) / 1e12
+    kind = bmd.sweep_kind(p32)
+    traffic = measured_traffic(f"k_eval_mfma_{d}d_{spec['m'][0]}cube_M{M // 1000}k_traffic.md",
+                               f"k_eval_{'mfma' if kind == 'matrix' else 'direct'}<float, {d}, 12>")
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                       "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                       "kernel": SWEEP_KERNEL[bmd.sweep_kind(p32)] % d,
+                       "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                       "traffic_unit": "bytes per launch (HBM, counter-measured)",
+                       "kernel": SWEEP_KERNEL[kind] % d,
                        "sweep_ms": sweep32, "flops_per_launch": flops32,
                        "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
                        "frac_unpacked": achieved / PEAK_FP32_UNPACKED_TFLOPS,

@@ -101,7 +101,9 @@ typedef struct {
                                   1/(1 + exp(-(q_j - tau_j)/w)) of the two cutoffs  */
     double bandwidth[BMD_MAX_DIM]; /* smoothing kernel sd per axis (quantile units) */
     int32_t gh_nodes;          /* Gauss-Hermite nodes for orthant probabilities:
-                                  0 = chosen per precision from rho_b and d         */
+                                  0 = chosen per precision from rho_b and d (a
+                                  multiple of 4 up to 128), else a multiple of 4
+                                  in [4, 128] (the kernels take nodes in fours)    */
     uint64_t seed;             /* Philox4x32-10 key (lo, hi words)                  */
     uint32_t scenario_id;      /* third Philox counter word                         */
 } bmd_problem_desc;

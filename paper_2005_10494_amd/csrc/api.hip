@@ -173,8 +173,8 @@ bmd_status validate(const bmd_problem_desc* d, bool* grid) {
         return fail(BMD_EINVAL, "unknown effect model %d", d->effect);
     }
     if (!finite(d->indicator_width) || d->indicator_width < 0.0) return fail(BMD_ERANGE, "indicator_width must be >= 0");
-    if (d->gh_nodes != 0 && (d->gh_nodes < 4 || d->gh_nodes > kMaxGH))
-        return fail(BMD_ERANGE, "gh_nodes must be 0 or in [4, 128]");
+    if (d->gh_nodes != 0 && (d->gh_nodes < 4 || d->gh_nodes > kMaxGH || d->gh_nodes % 4 != 0))
+        return fail(BMD_ERANGE, "gh_nodes must be 0 or a multiple of 4 in [4, 128]");
     return BMD_OK;
 }
 
@@ -278,6 +278,11 @@ bmd_status bmd_create_problem(const bmd_problem_desc* desc, bmd_problem** out, v
     p->desc = d;
     p->grid = grid;
     (void)hipGetDevice(&p->device);
+    if (hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
+        p->n_cu < 1) {
+        (void)hipGetLastError();
+        p->n_cu = 1;
+    }
     DevProblem& P = p->P;
     std::memset(&P, 0, sizeof P);
     P.d = d.d;
@@ -460,10 +465,17 @@ bmd_status bmd_eval_grid(bmd_problem* p, uint64_t n_draws, int32_t prec, double*
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t M = static_cast<int64_t>(n_draws);
     const int64_t G = p->P.G;
-    const int64_t bx = (G + kEvalBlock - 1) / kEvalBlock;
-    int64_t n_slices = std::max<int64_t>(1, std::min<int64_t>((2048 + bx - 1) / bx, (M + 63) / 64));
-    n_slices = std::min<int64_t>(n_slices, 65535);
-    const int64_t slice_len = (M + n_slices - 1) / n_slices;
+    // Draw slices: about kSweepRounds full rounds of resident workgroups, so the
+    // partly filled last round costs little; slices of at least 64 draws,
+    // whole draw chunks of the matrix-core sweep.
+    const int64_t bx = sweep_tiles(p, prec);
+    if (p->sweep_bpc[prec] == 0) p->sweep_bpc[prec] = sweep_blocks_per_cu(p, prec);
+    const int64_t resident = static_cast<int64_t>(p->n_cu) * p->sweep_bpc[prec];
+    const int64_t chunk = sweep_chunk(p, prec);
+    int64_t n_slices = (kSweepRounds * resident + bx - 1) / bx;
+    n_slices = std::max<int64_t>(1, std::min<int64_t>({n_slices, (M + 63) / 64, 65535}));
+    int64_t slice_len = (M + n_slices - 1) / n_slices;
+    slice_len = (slice_len + chunk - 1) / chunk * chunk;
     n_slices = (M + slice_len - 1) / slice_len;
     const size_t draw_bytes = (draw_workspace_bytes(p, prec, M) + 255) / 256 * 256;
     const size_t part_bytes = sizeof(double) * 2 * static_cast<size_t>(G) * n_slices;

@@ -15,6 +15,7 @@ constexpr int kMaxGH = 128;          // Gauss-Hermite nodes, upper bound
 constexpr int kPrecomputeGH = 128;   // nodes for the per-design subgroup fraction r
 constexpr int kGLTable = 200;        // packed Gauss-Legendre rules n = 4..24
 constexpr int kEvalBlock = 256;      // designs per workgroup in the eval kernels
+constexpr int kSweepRounds = 8;      // rounds of resident workgroups a grid sweep is sliced into
 
 // Problem constants passed by value to every kernel.
 struct DevProblem {
@@ -107,6 +108,8 @@ struct bmd_problem {
     bmd::DevProblem P;
     bool grid = false;
     int device = 0;
+    int n_cu = 0;                    // compute units of the device
+    int sweep_bpc[2] = {0, 0};       // resident sweep workgroups per CU, per precision (0: not yet queried)
     bmd::PrecTables tab[2];          // [BMD_FP64], [BMD_FP32_COMP]
     double* d_gl = nullptr;          // packed GL table (x and w, FP64)
     double* d_ghp = nullptr;         // [2*kPrecomputeGH] GH rule for r
@@ -143,6 +146,11 @@ size_t draw_workspace_bytes(const bmd_problem* p, int prec, int64_t M);
 DrawArrays<double> draws_fp64(const bmd_problem* p, int64_t M, const void* ws);
 DrawArrays<float> draws_fp32(const bmd_problem* p, int64_t M, const void* ws);
 bool use_mfma_sweep(const bmd_problem* p);
+// Workgroups along the design axis of the sweep launch, resident workgroups
+// per compute unit for it, and its draw chunk (1 for the direct sweep).
+int64_t sweep_tiles(const bmd_problem* p, int prec);
+int sweep_blocks_per_cu(const bmd_problem* p, int prec);
+int sweep_chunk(const bmd_problem* p, int prec);
 hipError_t launch_eval_grid(const bmd_problem* p, int prec, int64_t M, const void* ws,
                             double* partials, int n_slices, int64_t slice_len, hipStream_t s);
 hipError_t launch_finalize(const bmd_problem* p, int64_t M, const double* partials, int n_slices,

@@ -177,28 +177,60 @@ struct BvnConst {
     }
 };
 
-// FP64: sum_i w_i exp(b_i hk - a_i hs)
+// Node sum  sum_{i<n} w_i exp(b_i hk - a_i hs)  (FP32: exp2 with log2(e)
+// folded into a_i, b_i).  Every rule size is even and n is wave-uniform, so
+// the nodes go in pairs behind a scalar exit test, unrolled by template
+// recursion: only n nodes are evaluated and every coefficient index is a
+// compile-time constant (registers, no indexed scratch).  (A guard per node in
+// a loop is if-converted into evaluating all NMAX exponentials; a loop with an
+// early exit is kept rolled for FP64, its coefficients then indexed in scratch.)
+__device__ __forceinline__ double node_exp(double x) { return exp(x); }
+__device__ __forceinline__ float node_exp(float x) { return __builtin_amdgcn_exp2f(x); }
+
+template <int I, typename T, int NMAX, typename W>
+__device__ __forceinline__ void bvn_node_pairs(int n, T hk, T hs, const BvnConst<T, NMAX>& c, const W& w, T& acc0,
+                                               T& acc1) {
+    // smallest rule: 4 nodes (FP32 table) or 6 (FP64 table); those need no test
+    constexpr int kMinRule = sizeof(T) == 4 ? 4 : 6;
+    if constexpr (I < NMAX) {
+        if (I >= kMinRule && I >= n) return;
+        acc0 = fma(w[I], node_exp(c.b[I] * hk - c.a[I] * hs), acc0);
+        acc1 = fma(w[I + 1], node_exp(c.b[I + 1] * hk - c.a[I + 1] * hs), acc1);
+        bvn_node_pairs<I + 2>(n, hk, hs, c, w, acc0, acc1);
+    }
+}
+
+template <typename T, int NMAX, typename W>
+__device__ __forceinline__ T bvn_node_sum(int n, T hk, T hs, const BvnConst<T, NMAX>& c, const W& w) {
+    T acc0 = T(0), acc1 = T(0);
+    bvn_node_pairs<0>(n, hk, hs, c, w, acc0, acc1);
+    return acc0 + acc1;
+}
+
+// FP64: Phi(h) Phi(k) + asin(rho)/(4 pi) sum_i w_i exp(b_i hk - a_i hs)
 template <int NMAX>
 __device__ __forceinline__ double bvn_cdf(double h, double k, const BvnConst<double, NMAX>& c,
                                           const double* __restrict__ w, int n) {
     const double hk = h * k, hs = 0.5 * (h * h + k * k);
-    double acc = 0.0;
-#pragma unroll
-    for (int i = 0; i < NMAX; ++i)
-        if (i < n) acc += w[i] * exp(c.b[i] * hk - c.a[i] * hs);
-    return norm_cdf(h) * norm_cdf(k) + c.scale * acc;
+    return norm_cdf(h) * norm_cdf(k) + c.scale * bvn_node_sum(n, hk, hs, c, w);
 }
 
-// FP32: exponent coefficients pre-multiplied by log2(e), hardware exp2.
+// FP32: the same with exp2.  The weights are wave-uniform (one rule per
+// wavefront); BvnWeights holds them in scalar registers, read once per design.
 template <int NMAX>
-__device__ __forceinline__ float bvn_cdf(float h, float k, const BvnConst<float, NMAX>& c,
-                                         const float* __restrict__ w, int n) {
-    const float hk = h * k, hs = 0.5f * (h * h + k * k);
-    float acc = 0.0f;
+struct BvnWeights {
+    float w[NMAX];
+    __device__ __forceinline__ void load(const float* __restrict__ src, int n) {
 #pragma unroll
-    for (int i = 0; i < NMAX; ++i)
-        if (i < n) acc += w[i] * __builtin_amdgcn_exp2f(c.b[i] * hk - c.a[i] * hs);
-    return norm_cdf(h) * norm_cdf(k) + c.scale * acc;
+        for (int i = 0; i < NMAX; ++i) w[i] = i < n ? src[i] : 0.0f;
+    }
+    __device__ __forceinline__ float operator[](int i) const { return w[i]; }
+};
+
+template <int NMAX, typename W>
+__device__ __forceinline__ float bvn_cdf(float h, float k, const BvnConst<float, NMAX>& c, const W& w, int n) {
+    const float hk = h * k, hs = 0.5f * (h * h + k * k);
+    return fmaf(norm_cdf(h), norm_cdf(k), c.scale * bvn_node_sum(n, hk, hs, c, w));
 }
 
 // Row of the 16x16 result held in accumulator element v of a lane in quarter

@@ -49,6 +49,12 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_direct(EvalArgs<T> a) {
     }
 }
 
+// Four values of one draw read with one LDS access.
+template <typename T>
+struct alignas(4 * sizeof(T)) Quad {
+    T x, y, z, w;
+};
+
 typedef float mf_f4 __attribute__((ext_vector_type(4)));
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ mf_f4 mf_step(float a, float b, mf_f4 c) {
@@ -81,15 +87,12 @@ template <typename T, int D, int NMAX>
 __global__ __launch_bounds__(kEvalBlock) void k_eval_mfma(EvalArgs<T> a, MfmaGeom geo) {
     using acc_t = typename std::conditional<sizeof(T) == 8, mf_d4, mf_f4>::type;
     extern __shared__ __align__(16) char lds[];
-    const int K = a.D.K;
+    const int K = a.D.K;   // a multiple of 4 (node steps of four)
     const int CH = geo.chunk;
-    const int Kp = (K + 3) / 4 * 4;
-    T* sO = reinterpret_cast<T*>(lds);                       // [CH][256]
-    T* sB = sO + static_cast<size_t>(CH) * kEvalBlock;        // [CH][D][Kp]
-    T* sb0 = sB + static_cast<size_t>(CH) * D * Kp;          // [CH]
-    T* sb1 = sb0 + CH;
-    T* smu1 = sb1 + CH;
-    int* sthr = reinterpret_cast<int*>(smu1 + CH);            // [CH][D]
+    T* sO = reinterpret_cast<T*>(lds);                                  // [CH][256]
+    T* sB = sO + static_cast<size_t>(CH) * kEvalBlock;                   // [CH][D][K]
+    Quad<T>* sq = reinterpret_cast<Quad<T>*>(sB + static_cast<size_t>(CH) * D * K);  // [CH] (b0, b1, mu1, -)
+    int* sthr = reinterpret_cast<int*>(sq + CH);                         // [CH][D]
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t tile = blockIdx.x;
@@ -120,57 +123,105 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_mfma(EvalArgs<T> a, MfmaGeo
         }
     }
 
+    // This lane's axis-table values (draw independent) for the first kHoist
+    // node steps stay in registers (FP32; the FP64 kernel has none to spare);
+    // the remaining steps read them from memory.
+    constexpr int kHoist = sizeof(T) == 4 ? 6 : 0;
+    constexpr int kChains = sizeof(T) == 4 ? 2 : 1;   // draws per wavefront pass
+    const int S = K / 4;
+    T aH[kHoist > 0 ? kHoist : 1][D];
+#pragma unroll
+    for (int s = 0; s < kHoist; ++s) {
+        const int m = 4 * s + kq;
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+            aH[s][j] = (s < S && m < K) ? a.A[(static_cast<int64_t>(j) * K + m) * mmax + iA[j]] : T(0);
+    }
+    // Gauss-Legendre weights of this wavefront's rule: scalar registers in FP32
+    const auto wts = [&]() {
+        if constexpr (sizeof(T) == 4) {
+            BvnWeights<NMAX> w;
+            w.load(st.w, st.n);
+            return w;
+        } else {
+            return st.w;
+        }
+    }();
+
     const int64_t kb = static_cast<int64_t>(blockIdx.y) * a.slice_len;
     const int64_t ke = min(M, kb + a.slice_len);
     double s1 = 0.0, s2 = 0.0;
     for (int64_t k0 = kb; k0 < ke; k0 += CH) {
         const int nk = static_cast<int>(min<int64_t>(CH, ke - k0));
         __syncthreads();
-        // stage the chunk's draws
-        for (int e = tid; e < nk * D * Kp; e += kEvalBlock) {
-            const int i = e / (D * Kp), rem = e % (D * Kp), j = rem / Kp, m = rem % Kp;
-            sB[e] = m < K ? a.D.B[(k0 + i) * D * K + j * K + m] : T(0);
+        // stage the chunk's draws (the B rows of consecutive draws are contiguous)
+        {
+            const T* src = a.D.B + k0 * D * K;
+            for (int e = tid; e < nk * D * K; e += kEvalBlock) sB[e] = src[e];
         }
-        for (int e = tid; e < nk; e += kEvalBlock) {
-            sb0[e] = a.D.b0[k0 + e];
-            sb1[e] = a.D.b1[k0 + e];
-            smu1[e] = a.D.mu1[k0 + e];
-        }
+        for (int e = tid; e < nk; e += kEvalBlock)
+            sq[e] = Quad<T>{a.D.b0[k0 + e], a.D.b1[k0 + e], a.D.mu1[k0 + e], T(0)};
         for (int e = tid; e < nk * D; e += kEvalBlock) {
             const int i = e / D, j = e % D;
             sthr[e] = a.D.thr[j * M + k0 + i];
         }
         __syncthreads();
-        // phase A: overlaps of the tile, one draw per wavefront at a time
-        for (int i = wave; i < nk; i += kEvalBlock / 64) {
-            bool fl[D];
+        // phase A: overlaps of the tile; a wavefront takes kChains draws per
+        // pass (draws wave + 4c + 4 kChains t), one independent MFMA chain each
+        constexpr int kWaves = kEvalBlock / 64;
+        for (int i0 = wave; i0 < nk; i0 += kChains * kWaves) {
+            int ic[kChains];
+            bool fl[kChains][D];
+            const T* Bc[kChains];
+            acc_t c[kChains];
 #pragma unroll
-            for (int j = 0; j < D; ++j) fl[j] = iA[j] >= sthr[i * D + j];
-            const T* Bi = sB + static_cast<size_t>(i) * D * Kp;
-            acc_t c = {0, 0, 0, 0};
-            for (int m0 = 0; m0 < Kp; m0 += 4) {
-                const int m = m0 + kq;
-                T pre = T(1), suf = T(1);
+            for (int q = 0; q < kChains; ++q) {
+                ic[q] = i0 + q * kWaves < nk ? i0 + q * kWaves : i0;
 #pragma unroll
-                for (int j = 0; j < D; ++j) {
-                    const T av = m < K ? a.A[(static_cast<int64_t>(j) * K + m) * mmax + iA[j]] : T(0);
-                    const T v = fl[j] ? av : Bi[j * Kp + m];
-                    if (j < geo.split) pre *= v; else suf *= v;
+                for (int j = 0; j < D; ++j) fl[q][j] = iA[j] >= sthr[ic[q] * D + j];
+                Bc[q] = sB + static_cast<size_t>(ic[q]) * D * K;
+                c[q] = acc_t{0, 0, 0, 0};
+            }
+            auto step = [&](int m, const T* av) {
+#pragma unroll
+                for (int q = 0; q < kChains; ++q) {
+                    T pre = T(1), suf = T(1);
+#pragma unroll
+                    for (int j = 0; j < D; ++j) {
+                        const T v = fl[q][j] ? av[j] : Bc[q][j * K + m];
+                        if (j < geo.split) pre *= v; else suf *= v;
+                    }
+                    c[q] = mf_step(rowA ? pre : T(0), colA ? suf : T(0), c[q]);
                 }
-                c = mf_step(rowA ? pre : T(0), colA ? suf : T(0), c);
+            };
+#pragma unroll
+            for (int s = 0; s < kHoist; ++s)
+                if (s < S) step(4 * s + kq, aH[s]);
+            for (int s = kHoist; s < S; ++s) {
+                const int m = 4 * s + kq;
+                T av[D];
+#pragma unroll
+                for (int j = 0; j < D; ++j)
+                    av[j] = m < K ? a.A[(static_cast<int64_t>(j) * K + m) * mmax + iA[j]] : T(0);
+                step(m, av);
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                sO[static_cast<size_t>(i) * kEvalBlock + mfma16_row<T>(kq, v) * 16 + r16] = c[v];
+            for (int q = 0; q < kChains; ++q) {
+                if (q > 0 && i0 + q * kWaves >= nk) break;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    sO[static_cast<size_t>(ic[q]) * kEvalBlock + mfma16_row<T>(kq, v) * 16 + r16] = c[q][v];
+            }
         }
         __syncthreads();
         // phase B: bivariate normal part for this thread's design
         for (int i = 0; i < nk; ++i) {
             const T O = sO[static_cast<size_t>(i) * kEvalBlock + tid];
-            const T mu2 = st.srI * (sb0[i] + sb1[i] * O * st.invr);
-            const T h = st.z1 - smu1[i], kq2 = st.z2 - mu2;
+            const Quad<T> dq = sq[i];
+            const T mu2 = st.srI * (dq.x + dq.y * O * st.invr);
+            const T h = st.z1 - dq.z, kq2 = st.z2 - mu2;
             T p;
-            if (a.P.zinf == 0) p = bvn_cdf<NMAX>(h, kq2, st.bc, st.w, st.n);
+            if (a.P.zinf == 0) p = bvn_cdf<NMAX>(h, kq2, st.bc, wts, st.n);
             else if (a.P.zinf == 1) p = norm_cdf(kq2);
             else if (a.P.zinf == 2) p = norm_cdf(h);
             else p = T(1);
@@ -202,8 +253,7 @@ __global__ void k_finalize(int64_t G, int64_t M, int n_slices, const double* __r
 
 template <typename T>
 size_t mfma_lds_bytes(int chunk, int d, int K) {
-    const int Kp = (K + 3) / 4 * 4;
-    return sizeof(T) * static_cast<size_t>(chunk) * (kEvalBlock + static_cast<size_t>(d) * Kp + 3) +
+    return sizeof(T) * static_cast<size_t>(chunk) * (kEvalBlock + static_cast<size_t>(d) * K + 4) +
            sizeof(int) * static_cast<size_t>(chunk) * d;
 }
 
@@ -226,10 +276,12 @@ MfmaGeom mfma_geometry(const bmd_problem* p, int prec) {
     }
     geo.tiles_l = (geo.Sn + 15) / 16;
     const int K = p->tab[prec].K;
+    // Largest chunk (multiple of 4, at most 32 draws) within 40 KB of LDS, so
+    // four workgroups fit a compute unit's 160 KB.
     int ch = 32;
-    const size_t cap = 48 * 1024;
+    const size_t cap = 40 * 1024;
     while (ch > 4 && (prec == BMD_FP64 ? mfma_lds_bytes<double>(ch, d, K) : mfma_lds_bytes<float>(ch, d, K)) > cap)
-        ch /= 2;
+        ch -= 4;
     geo.chunk = ch;
     return geo;
 }
@@ -264,12 +316,61 @@ hipError_t launch_typed(const bmd_problem* p, int prec, const EvalArgs<T>& a, in
     return hipGetLastError();
 }
 
+// Resident workgroups per compute unit of the sweep kernel eval_grid launches.
+template <typename T, int NMAX>
+int resident_typed(const bmd_problem* p, int prec) {
+    const int d = p->P.d;
+    int nb = 0;
+    hipError_t e = hipSuccess;
+    if (use_mfma_sweep(p)) {
+        const MfmaGeom geo = mfma_geometry(p, prec);
+        const size_t lds = mfma_lds_bytes<T>(geo.chunk, d, p->tab[prec].K);
+        switch (d) {
+            case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_mfma<T, 2, NMAX>, kEvalBlock, lds); break;
+            case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_mfma<T, 3, NMAX>, kEvalBlock, lds); break;
+            case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_mfma<T, 4, NMAX>, kEvalBlock, lds); break;
+            case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_mfma<T, 5, NMAX>, kEvalBlock, lds); break;
+            default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_mfma<T, 6, NMAX>, kEvalBlock, lds); break;
+        }
+    } else {
+        switch (d) {
+            case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_direct<T, 1, NMAX>, kEvalBlock, 0); break;
+            case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_direct<T, 2, NMAX>, kEvalBlock, 0); break;
+            case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_direct<T, 3, NMAX>, kEvalBlock, 0); break;
+            case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_direct<T, 4, NMAX>, kEvalBlock, 0); break;
+            case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_direct<T, 5, NMAX>, kEvalBlock, 0); break;
+            default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_direct<T, 6, NMAX>, kEvalBlock, 0); break;
+        }
+    }
+    if (e != hipSuccess || nb < 1) {
+        (void)hipGetLastError();
+        nb = 1;
+    }
+    return nb;
+}
+
 }  // namespace
 
 // The matrix-core sweep covers grid problems with at least two biomarkers,
 // the step prior and the exact cutoff indicator; the rest use the direct one.
 bool use_mfma_sweep(const bmd_problem* p) {
     return p->grid && p->P.d >= 2 && p->P.effect == BMD_EFFECT_STEP && p->P.width == 0.0 && !p->force_direct;
+}
+
+int64_t sweep_tiles(const bmd_problem* p, int prec) {
+    if (use_mfma_sweep(p)) {
+        const MfmaGeom geo = mfma_geometry(p, prec);
+        return ((geo.Pn + 15) / 16) * geo.tiles_l;
+    }
+    return (p->P.G + kEvalBlock - 1) / kEvalBlock;
+}
+
+int sweep_blocks_per_cu(const bmd_problem* p, int prec) {
+    return prec == BMD_FP64 ? resident_typed<double, 24>(p, prec) : resident_typed<float, 12>(p, prec);
+}
+
+int sweep_chunk(const bmd_problem* p, int prec) {
+    return use_mfma_sweep(p) ? mfma_geometry(p, prec).chunk : 1;
 }
 
 hipError_t launch_eval_grid(const bmd_problem* p, int prec, int64_t M, const void* ws, double* partials,

@@ -63,7 +63,7 @@ def _create_status(spec):
     ({"d": 0}, -2), ({"d": 7}, -2), ({"q_lo": 0.6, "q_hi": 0.5}, -2), ({"q_lo": 0.0}, -2),
     ({"rho_b": 0.7}, -2), ({"info": -1.0}, -2), ({"alpha0": 0.0}, -2), ({"alpha_rule": 5}, -1),
     ({"effect": 3}, -1), ({"sd_b0": -0.1}, -2), ({"tau_lo": 0.9, "tau_hi": 0.1}, -2),
-    ({"width": -1.0}, -2), ({"gh_nodes": 2}, -2), ({"bandwidth": [0.0]}, -2),
+    ({"width": -1.0}, -2), ({"gh_nodes": 2}, -2), ({"gh_nodes": 6}, -2), ({"gh_nodes": 132}, -2), ({"bandwidth": [0.0]}, -2),
     ({"m": [1]}, -2), ({"q_lo": 0.01}, -2),   # r = 0.99 > 0.95: bivariate quadrature range
     ({"mu_b1": float("nan")}, -1),
 ])

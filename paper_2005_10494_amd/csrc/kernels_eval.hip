@@ -55,6 +55,17 @@ struct alignas(4 * sizeof(T)) Quad {
     T x, y, z, w;
 };
 
+// Bit pattern type of T, and a branch-free select of two values already read.
+template <typename T>
+using Bits = typename std::conditional<sizeof(T) == 8, unsigned long long, unsigned int>::type;
+__device__ __forceinline__ float bit_select(unsigned int m, float a, float b) {
+    return __uint_as_float((__float_as_uint(a) & m) | (__float_as_uint(b) & ~m));
+}
+__device__ __forceinline__ double bit_select(unsigned long long m, double a, double b) {
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(__double_as_longlong(a)) & m) |
+                                                      (static_cast<unsigned long long>(__double_as_longlong(b)) & ~m)));
+}
+
 typedef float mf_f4 __attribute__((ext_vector_type(4)));
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ mf_f4 mf_step(float a, float b, mf_f4 c) {
@@ -112,7 +123,7 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_mfma(EvalArgs<T> a, MfmaGeo
     // (l0 + lane%16) of Suf at node m0 + lane/16
     const int r16 = lane & 15, kq = lane >> 4;
     const int64_t pA = p0 + r16, lA = l0 + r16;
-    const bool rowA = pA < geo.Pn, colA = lA < geo.Sn;
+    const bool rowA = pA < geo.Pn, colA = lA < geo.Sn;   // else: shadow design 0's indices
     int iA[D];
     {
         int64_t rem = (rowA ? pA : 0) * geo.Sn + (colA ? lA : 0);
@@ -167,51 +178,62 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_mfma(EvalArgs<T> a, MfmaGeo
         }
         __syncthreads();
         // phase A: overlaps of the tile; a wavefront takes kChains draws per
-        // pass (draws wave + 4c + 4 kChains t), one independent MFMA chain each
+        // pass (draws wave + 4c + 4 kChains t), one independent MFMA chain each.
+        // Rows or columns past the grid (p >= Pn, l >= Sn) feed only tile
+        // entries that phase B never stores, so they need no masking.
         constexpr int kWaves = kEvalBlock / 64;
-        for (int i0 = wave; i0 < nk; i0 += kChains * kWaves) {
-            int ic[kChains];
-            bool fl[kChains][D];
-            const T* Bc[kChains];
-            acc_t c[kChains];
-#pragma unroll
-            for (int q = 0; q < kChains; ++q) {
-                ic[q] = i0 + q * kWaves < nk ? i0 + q * kWaves : i0;
-#pragma unroll
-                for (int j = 0; j < D; ++j) fl[q][j] = iA[j] >= sthr[ic[q] * D + j];
-                Bc[q] = sB + static_cast<size_t>(ic[q]) * D * K;
-                c[q] = acc_t{0, 0, 0, 0};
-            }
-            auto step = [&](int m, const T* av) {
+        auto phase_a = [&](auto split_c) {
+            constexpr int SPLIT = decltype(split_c)::value;
+            for (int i0 = wave; i0 < nk; i0 += kChains * kWaves) {
+                int ic[kChains];
+                Bits<T> msk[kChains][D];   // all ones: the design's axis-j cutoff is above the draw's
+                const T* Bc[kChains];
+                acc_t c[kChains];
 #pragma unroll
                 for (int q = 0; q < kChains; ++q) {
-                    T pre = T(1), suf = T(1);
+                    ic[q] = i0 + q * kWaves < nk ? i0 + q * kWaves : i0;
 #pragma unroll
-                    for (int j = 0; j < D; ++j) {
-                        const T v = fl[q][j] ? av[j] : Bc[q][j * K + m];
-                        if (j < geo.split) pre *= v; else suf *= v;
-                    }
-                    c[q] = mf_step(rowA ? pre : T(0), colA ? suf : T(0), c[q]);
+                    for (int j = 0; j < D; ++j) msk[q][j] = iA[j] >= sthr[ic[q] * D + j] ? ~Bits<T>(0) : Bits<T>(0);
+                    Bc[q] = sB + static_cast<size_t>(ic[q]) * D * K;
+                    c[q] = acc_t{0, 0, 0, 0};
                 }
-            };
+                auto step = [&](int m, const T* av) {
 #pragma unroll
-            for (int s = 0; s < kHoist; ++s)
-                if (s < S) step(4 * s + kq, aH[s]);
-            for (int s = kHoist; s < S; ++s) {
-                const int m = 4 * s + kq;
-                T av[D];
+                    for (int q = 0; q < kChains; ++q) {
+                        T pre = T(1), suf = T(1);
 #pragma unroll
-                for (int j = 0; j < D; ++j)
-                    av[j] = m < K ? a.A[(static_cast<int64_t>(j) * K + m) * mmax + iA[j]] : T(0);
-                step(m, av);
+                        for (int j = 0; j < D; ++j) {
+                            const T v = bit_select(msk[q][j], av[j], Bc[q][j * K + m]);
+                            if (j < SPLIT) pre *= v; else suf *= v;   // j, SPLIT: compile-time after unrolling
+                        }
+                        c[q] = mf_step(pre, suf, c[q]);
+                    }
+                };
+#pragma unroll
+                for (int s = 0; s < kHoist; ++s)
+                    if (s < S) step(4 * s + kq, aH[s]);
+                for (int s = kHoist; s < S; ++s) {
+                    const int m = 4 * s + kq;
+                    T av[D];
+#pragma unroll
+                    for (int j = 0; j < D; ++j) av[j] = a.A[(static_cast<int64_t>(j) * K + m) * mmax + iA[j]];
+                    step(m, av);
+                }
+#pragma unroll
+                for (int q = 0; q < kChains; ++q) {
+                    if (q > 0 && i0 + q * kWaves >= nk) break;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        sO[static_cast<size_t>(ic[q]) * kEvalBlock + mfma16_row<T>(kq, v) * 16 + r16] = c[q][v];
+                }
             }
-#pragma unroll
-            for (int q = 0; q < kChains; ++q) {
-                if (q > 0 && i0 + q * kWaves >= nk) break;
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    sO[static_cast<size_t>(ic[q]) * kEvalBlock + mfma16_row<T>(kq, v) * 16 + r16] = c[q][v];
-            }
+        };
+        switch (geo.split) {
+            case 1: phase_a(std::integral_constant<int, 1>{}); break;
+            case 2: if constexpr (D > 2) phase_a(std::integral_constant<int, 2>{}); break;
+            case 3: if constexpr (D > 3) phase_a(std::integral_constant<int, 3>{}); break;
+            case 4: if constexpr (D > 4) phase_a(std::integral_constant<int, 4>{}); break;
+            default: if constexpr (D > 5) phase_a(std::integral_constant<int, 5>{}); break;
         }
         __syncthreads();
         // phase B: bivariate normal part for this thread's design

@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_mfma(EvalArgs<T> a, MfmaGeo
     const int64_t ke = min(M, kb + a.slice_len);
     double s1 = 0.0, s2 = 0.0;
     for (int64_t k0 = kb; k0 < ke; k0 += CH) {
-        const int nk = static_cast<int>(min<int64_t>(CH, ke - k0));
+        const int nk = __builtin_amdgcn_readfirstlane(static_cast<int>(min<int64_t>(CH, ke - k0)));
         __syncthreads();
         // stage the chunk's draws (the B rows of consecutive draws are contiguous)
         {

@@ -1,7 +1,8 @@
 """The single-precision normal CDF of the FP32 integrand (fitted tail form,
 coefficients in csrc/normal_cdf_fit.hpp), replayed on the CPU operation by
-operation in single precision and checked against scipy's double-precision
-ndtr: absolute error within 1.2e-7 everywhere and no bias."""
+operation in single precision (the hardware reciprocal taken one ulp off) and
+checked against scipy's double-precision ndtr: absolute error within 1.6e-7
+everywhere and no bias."""
 import importlib.util
 import os
 import re
@@ -42,7 +43,7 @@ def test_fp32_normal_cdf_accuracy_and_bias():
     got = np.array([float(gen.phi32(x, c)) for x in xs])
     ref = scipy_special.ndtr(xs.astype(np.float64))
     err = got - ref
-    assert np.abs(err).max() <= 1.2e-7
+    assert np.abs(err).max() <= 1.6e-7
     assert abs(err.mean()) <= 2e-9
     # tails: relative accuracy where Phi is still a normal float
     tail = (xs < -1.0) & (ref > 1e-30)

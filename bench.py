@@ -174,7 +174,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="3d", choices=["3d", "1d", "5d"])
+    ap.add_argument("--workload", default="3d", choices=["3d", "1d", "5d", "grad", "batch"])
+    ap.add_argument("--batch-scale", type=float, default=1.0,
+                    help="batch workload only: scale of the per-axis grids and of the draw range (1 = full size)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -201,6 +203,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": 4 * n, "launches": 3}), flush=True)
         return
+    if args.workload == "grad":
+        return bench_grad(args)
+    if args.workload == "batch":
+        return bench_batch(args)
     spec = workload(args.workload)
     M, G = spec["n_draws"], int(np.prod(spec["m"]))
     log(f"workload {args.workload}: d={spec['d']} grid={spec['m']} G={G} M={M}")
@@ -260,6 +266,88 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(spec)
+    print(json.dumps(out), flush=True)
+
+
+def bench_grad(args):
+    """Differentiation form: objective and its gradient (cutoffs and prior
+    means) at 4,096 continuous 5-biomarker designs, M = 1e6 draws, logistic
+    indicator width 0.01; FP32 integrand and FP64 timed the same way."""
+    import torch
+    import paper_2005_10494_amd as bmd
+    from paper_2005_10494_amd import workloads as W
+    spec = W.grad_5d()
+    B, M = spec["n_points"], spec["n_draws"]
+    q = torch.tensor(W.design_points(B, spec["d"]), dtype=torch.float64, device="cuda")
+    res = {}
+    with bmd.Problem(spec) as p:
+        for prec in ("fp32", "fp64"):
+            ts = []
+            for it in range(args.warmup + args.steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                obj, gq, gmu = p.grad_design(q, M, prec)
+                torch.cuda.synchronize()
+                if it >= args.warmup:
+                    ts.append(time.perf_counter() - t0)
+                log(f"  grad {prec} step {it}: {1e3 * (time.perf_counter() - t0):.1f} ms")
+            res[prec] = (float(np.mean(ts)), obj, gq, gmu)
+    t32, o32, g32, m32 = res["fp32"]
+    t64, o64, g64, m64 = res["fp64"]
+    scale = torch.cat([g64.abs().flatten(), m64.abs().flatten()]).max().clamp_min(1e-12)
+    out = {"metric": "gradient evaluations (design point x draw, objective + d + 2 partials) per second",
+           "value": B * M / t32, "unit": "point-draws/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * t32, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"5-biomarker continuous designs, {B} points U(0.1, 0.9)^5, M={M} draws, "
+                                  f"logistic indicator width {spec['width']}, rho_b={spec['rho_b']}",
+                      "points": B, "n_draws": M},
+           "fp64": {"value": B * M / t64, "ms_per_step": 1e3 * t64},
+           "fp32_vs_fp64": {"speedup": t64 / t32,
+                            "max_abs_diff_objective": float((o32 - o64).abs().max()),
+                            "max_abs_diff_grad_rel_to_max": float(max((g32 - g64).abs().max(),
+                                                                      (m32 - m64).abs().max()) / scale)}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """Batching form: 256 uneven grid problems (d uniform on 1..6, grids
+    201/64/40/24/14/10 per axis, M log-uniform in [1e4, 1e6]) in one call."""
+    import torch
+    import paper_2005_10494_amd as bmd
+    from paper_2005_10494_amd import workloads as W
+    s = args.batch_scale
+    sc = W.batch_scenarios(256, m_scale=s, m_draws=(1e4 * s, 1e6 * s))
+    evals = float(sum(int(np.prod(x["m"])) * x["n_draws"] for x in sc))
+    log(f"batch: {len(sc)} problems, {evals:.3e} evaluations")
+    probs = [bmd.Problem(x) for x in sc]
+    ts, walls = [], None
+    try:
+        for it in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            means, wall = bmd.eval_batch(probs, [x["n_draws"] for x in sc], "fp32")
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if it >= args.warmup:
+                ts.append(dt)
+                walls = wall
+            log(f"  batch step {it}: {1e3 * dt:.1f} ms, last problem done at {wall.max():.1f} ms")
+            del means
+    finally:
+        for p in probs:
+            p.close()
+    t = float(np.mean(ts))
+    out = {"metric": "aggregate integrand evals/s over a batch of uneven grid problems",
+           "value": evals / t, "unit": "integrand evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * t, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{len(sc)} grid problems, d uniform on 1..6, per-axis grid "
+                                  f"{'/'.join(str(max(2, round(m * s))) for m in W.BATCH_M)}, M log-uniform in "
+                                  f"[{1e4 * s:.0f}, {1e6 * s:.0f}], FP32 integrand + FP64 sums",
+                      "problems": len(sc), "evaluations": evals},
+           "wall_ms_per_problem": {"p50": float(np.percentile(walls, 50)), "p99": float(np.percentile(walls, 99)),
+                                   "max": float(walls.max())}}
     print(json.dumps(out), flush=True)
 
 

@@ -578,11 +578,6 @@ bmd_status bmd_grad_design(bmd_problem* p, const double* d_q, int64_t B, uint64_
 
 namespace {
 
-// Measured GPU-wide seconds per (design, draw) evaluation of the batched
-// kernel, per precision and biomarker count; filled by probe launches.
-std::mutex g_cost_mutex;
-double g_cost[2][BMD_MAX_DIM + 1] = {};
-
 struct DeviceBuffer {
     void* ptr = nullptr;
     ~DeviceBuffer() {
@@ -590,50 +585,158 @@ struct DeviceBuffer {
     }
 };
 
-// Time the persistent kernel on a synthetic work list drawn from scenario S:
-// every tile, one slice of `L` draws, enough items to fill the device twice.
-bmd_status probe_cost(const BatchScenario& S0, int prec, int chunk, size_t lds, int grid, const double* gl,
-                      hipStream_t cs, double* cost) {
-    BatchScenario S = S0;
-    const int64_t L = 4 * chunk;
-    S.slice_len = L;
-    S.n_slices = 1;
-    const int n_items = 2 * grid;
-    S.n_items = n_items;
-    S.g_offset = 0;
-    std::vector<int4> items(n_items);
-    for (int i = 0; i < n_items; ++i) items[i] = make_int4(0, i % S.tiles, 0, 0);
-    const size_t part = sizeof(double) * static_cast<size_t>(S.P.G);
-    const size_t bytes = 256 + sizeof(BatchScenario) + sizeof(int4) * n_items + 4096 + part;
-    DeviceBuffer buf;
-    HIP_TRY(hipMalloc(&buf.ptr, bytes), "probe buffer");
-    char* c = static_cast<char*>(buf.ptr);
-    BatchScenario* d_sc = reinterpret_cast<BatchScenario*>(c);
-    int4* d_items = reinterpret_cast<int4*>(c + 256 + sizeof(BatchScenario));
-    char* ctr = c + 256 + sizeof(BatchScenario) + sizeof(int4) * n_items;
-    S.partials = reinterpret_cast<double*>(ctr + 4096);
-    S.mean = nullptr;
-    HIP_TRY(hipMemcpy(d_sc, &S, sizeof S, hipMemcpyHostToDevice), "probe upload");
-    HIP_TRY(hipMemcpy(d_items, items.data(), sizeof(int4) * n_items, hipMemcpyHostToDevice), "probe upload");
-    BatchArgs a{d_sc, 1, d_items, n_items, reinterpret_cast<int*>(ctr), reinterpret_cast<int*>(ctr + 64),
-                reinterpret_cast<unsigned long long*>(ctr + 128), reinterpret_cast<unsigned long long*>(ctr + 192),
-                gl, chunk, S.P.G};
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
-    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
-    float ms = 0.0f;
-    hipError_t e = hipSuccess;
-    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {   // the first run absorbs one-time costs
-        e = hipEventRecord(e0, cs);
-        if (e == hipSuccess) e = launch_batch(prec, a, grid, lds, true, false, cs);
-        if (e == hipSuccess) e = hipEventRecord(e1, cs);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Host plan of one problem of a batch.
+struct BatchPlan {
+    int key;              // launch group: 2 * d + (matrix-core sweep ? 1 : 0)
+    int64_t G, M, tiles, chunk;
+    int64_t slice_len = 0, n_slices = 0;
+    size_t draw_bytes = 0, part_bytes = 0;
+};
+
+// One group of consecutive problems: draws, sweeps and finalize of the group
+// captured in one graph and launched once.  Slices are sized so that a launch
+// holds about kSweepRounds workgroups per resident slot.
+bmd_status run_batch_group(bmd_problem* const* ps, const std::vector<BatchPlan>& plan, int first, int last, int prec,
+                           double* const* d_means, int n_cu, hipStream_t cs, unsigned long long* d_tstart,
+                           unsigned long long* d_tdone, int* d_left, bool restart_clock) {
+    const int n = last - first;
+    std::vector<BatchPlan> pl(plan.begin() + first, plan.begin() + last);
+    // Launch groups: the problems of one (d, kernel kind), planned together.
+    std::vector<int> keys;
+    for (const auto& b : pl)
+        if (std::find(keys.begin(), keys.end(), b.key) == keys.end()) keys.push_back(b.key);
+    std::sort(keys.begin(), keys.end());
+    struct Phase {
+        int key, rep;          // rep: a problem of the phase (index in the group)
+        size_t lds;
+        int grid;
+        std::vector<int> members;
+    };
+    std::vector<Phase> phases;
+    for (int key : keys) {
+        Phase ph{key, -1, 0, 0, {}};
+        for (int i = 0; i < n; ++i)
+            if (pl[i].key == key) {
+                ph.members.push_back(i);
+                if (ph.rep < 0) ph.rep = i;
+                ph.lds = std::max(ph.lds, batch_phase_lds(ps[first + i], prec));
+            }
+        const int bpc = batch_phase_blocks_per_cu(ps[first + ph.rep], prec, ph.lds);
+        ph.grid = n_cu * bpc;
+        // Slices: about kSweepRounds items per resident workgroup over the phase.
+        double work = 0.0;
+        for (int i : ph.members) work += static_cast<double>(pl[i].tiles) * kEvalBlock * pl[i].M;
+        const double target = work / (static_cast<double>(kSweepRounds) * ph.grid) / kEvalBlock;
+        for (int i : ph.members) {
+            BatchPlan& b = pl[i];
+            const int64_t Mr = (b.M + b.chunk - 1) / b.chunk * b.chunk;
+            int64_t L = static_cast<int64_t>(std::ceil(std::max(target, 64.0) / b.chunk)) * b.chunk;
+            L = std::max<int64_t>(b.chunk, std::min<int64_t>(L, Mr));
+            b.slice_len = L;
+            b.n_slices = (b.M + L - 1) / L;
+            b.part_bytes = align256(sizeof(double) * 2 * static_cast<size_t>(b.G) * b.n_slices);
+        }
+        phases.push_back(std::move(ph));
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (e != hipSuccess) return hip_fail(e, "autotune probe");
-    *cost = (ms * 1e-3) / (static_cast<double>(n_items) * kEvalBlock * L);
+    // Work lists, costliest items first (the ragged last slice of a problem is cheaper).
+    struct Item {
+        int4 v;
+        double c;
+    };
+    std::vector<std::vector<int4>> lists(phases.size());
+    std::vector<int> items_per(n, 0);
+    size_t n_items_total = 0;
+    for (size_t f = 0; f < phases.size(); ++f) {
+        std::vector<Item> list;
+        for (int i : phases[f].members) {
+            const BatchPlan& b = pl[i];
+            for (int64_t t = 0; t < b.tiles; ++t)
+                for (int64_t sl = 0; sl < b.n_slices; ++sl) {
+                    const double draws = static_cast<double>(std::min<int64_t>(b.slice_len, b.M - sl * b.slice_len));
+                    list.push_back({make_int4(i, static_cast<int>(t), static_cast<int>(sl), 0), draws});
+                }
+            items_per[i] = static_cast<int>(b.tiles * b.n_slices);
+        }
+        if (list.size() > (1u << 24)) return fail(BMD_ERANGE, "batch work list of %zu items is too large", list.size());
+        std::stable_sort(list.begin(), list.end(), [](const Item& x, const Item& y) { return x.c > y.c; });
+        for (const Item& it : list) lists[f].push_back(it.v);
+        n_items_total += list.size();
+    }
+
+    // One device allocation: records, draw jobs, finals, items, counters, draws, partials.
+    const size_t rec_b = batch_record_bytes(prec), job_b = draw_job_bytes(prec);
+    size_t off = 0;
+    const size_t o_rec = off;   off += align256(rec_b * n);
+    const size_t o_job = off;   off += align256(job_b * n);
+    const size_t o_fin = off;   off += align256(sizeof(BatchFinal) * n);
+    const size_t o_items = off; off += align256(sizeof(int4) * std::max<size_t>(n_items_total, 1));
+    const size_t o_ctr = off;   off += align256(sizeof(int) * n);   // items per problem
+    std::vector<size_t> o_draw(n), o_part(n);
+    for (int i = 0; i < n; ++i) { o_draw[i] = off; off += pl[i].draw_bytes; }
+    for (int i = 0; i < n; ++i) { o_part[i] = off; off += pl[i].part_bytes; }
+    DeviceBuffer buf;
+    {
+        hipError_t e = hipMalloc(&buf.ptr, off);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(BMD_ENOMEM, "batch workspace of %zu bytes: %s", off, hipGetErrorString(e));
+        }
+    }
+    char* base = static_cast<char*>(buf.ptr);
+    std::vector<char> host(o_draw.empty() ? o_ctr : o_draw[0], 0);   // everything before the draws
+    std::vector<BatchFinal> fin(n);
+    int64_t draws_total = 0, designs_total = 0;
+    for (int i = 0; i < n; ++i) {
+        bmd_problem* p = ps[first + i];
+        double* part = reinterpret_cast<double*>(base + o_part[i]);
+        batch_fill_record(prec, host.data() + o_rec + rec_b * i, p, base + o_draw[i], pl[i].M, pl[i].slice_len, part,
+                          first + i);
+        fill_draw_job(prec, host.data() + o_job + job_b * i, p, base + o_draw[i], pl[i].M, draws_total);
+        fin[i] = BatchFinal{designs_total, pl[i].G, pl[i].M, static_cast<int>(pl[i].n_slices), part, d_means[first + i]};
+        draws_total += pl[i].M;
+        designs_total += pl[i].G;
+    }
+    std::memcpy(host.data() + o_fin, fin.data(), sizeof(BatchFinal) * n);
+    {
+        size_t k = 0;
+        for (const auto& l : lists) {
+            std::memcpy(host.data() + o_items + sizeof(int4) * k, l.data(), sizeof(int4) * l.size());
+            k += l.size();
+        }
+    }
+    std::memcpy(host.data() + o_ctr, items_per.data(), sizeof(int) * n);
+    HIP_TRY(hipMemcpy(base, host.data(), host.size(), hipMemcpyHostToDevice), "batch upload");
+
+    const int* d_items_per = reinterpret_cast<const int*>(base + o_ctr);
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    hipError_t le = launch_batch_reset(d_left, d_tdone, d_items_per, first, n, restart_clock ? d_tstart : nullptr, cs);
+    if (le == hipSuccess) le = launch_draws_batch(prec, base + o_job, n, draws_total, cs);
+    size_t k = 0;
+    for (size_t f = 0; f < phases.size() && le == hipSuccess; ++f) {
+        // records are indexed within the group; left / t_done by batch index
+        BatchPhase ph{base + o_rec, reinterpret_cast<const int4*>(base + o_items) + k, static_cast<int>(lists[f].size()),
+                      d_left, d_tstart, d_tdone};
+        le = launch_batch_phase(ps[first + phases[f].rep], prec, ph, phases[f].lds, cs);
+        k += lists[f].size();
+    }
+    if (le == hipSuccess)
+        le = launch_batch_finalize(reinterpret_cast<const BatchFinal*>(base + o_fin), n, designs_total, cs);
+    hipError_t ce = hipStreamEndCapture(cs, &graph);
+    if (le != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(le, "batch capture");
+    }
+    HIP_TRY(ce, "hipStreamEndCapture");
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, cs);
+    if (e == hipSuccess) e = hipStreamSynchronize(cs);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    HIP_TRY(e, "batch graph");
     return BMD_OK;
 }
 
@@ -654,33 +757,33 @@ bmd_status bmd_eval_batch(bmd_problem* const* ps, int32_t n, const uint64_t* n_d
     DeviceGuard guard(ps[0]->device);
     hipStream_t us = static_cast<hipStream_t>(stream);
     const int dev = ps[0]->device;
-    int n_cu = 0, clock_khz = 0;
-    HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev), "device attribute");
+    int clock_khz = 0;
     HIP_TRY(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev), "device attribute");
-    int Kmax = 1;
-    for (int i = 0; i < n; ++i) Kmax = std::max(Kmax, ps[i]->tab[prec].K);
-    int chunk = 32;
-    while (chunk > 1 && batch_lds_bytes(prec, chunk, Kmax) > 48 * 1024) chunk /= 2;
-    const size_t lds = batch_lds_bytes(prec, chunk, Kmax);
-    const int grid = n_cu * batch_blocks_per_cu(prec, lds);
+    const int n_cu = ps[0]->n_cu;
 
-    // Scenario records (device pointers filled below).
-    std::vector<BatchScenario> sc(n);
+    std::vector<BatchPlan> plan(n);
     for (int i = 0; i < n; ++i) {
         const bmd_problem* p = ps[i];
-        BatchScenario& S = sc[i];
-        std::memset(&S, 0, sizeof S);
-        S.P = p->P;
-        S.r = p->d_r;
-        S.z1 = p->d_z1;
-        S.z2 = p->d_z2;
-        S.A = p->tab[prec].A;
-        S.gh = p->tab[prec].gh;
-        S.glw = p->tab[prec].glw;
-        S.K = p->tab[prec].K;
-        S.tiles = static_cast<int>((p->P.G + kEvalBlock - 1) / kEvalBlock);
-        S.M = static_cast<int64_t>(n_draws[i]);
-        S.mean = d_means[i];
+        BatchPlan& b = plan[i];
+        const bool mf = use_mfma_sweep(p);
+        b.key = 2 * p->P.d + (mf ? 1 : 0);
+        b.G = p->P.G;
+        b.M = static_cast<int64_t>(n_draws[i]);
+        b.tiles = sweep_tiles(p, prec);
+        b.chunk = mf ? sweep_chunk(p, prec) : 1;
+        b.draw_bytes = align256(draw_workspace_bytes(p, prec, b.M));
+    }
+    // Groups of consecutive problems whose draws fit the memory budget: half
+    // the free device memory, at most kBatchBudget.
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        free_b = kBatchBudget;
+    }
+    size_t budget = std::min<size_t>(kBatchBudget, free_b / 2);
+    if (const char* env = std::getenv("BMD_BATCH_BUDGET")) {   // bytes; small values force one problem per group
+        const long long v = std::atoll(env);
+        if (v > 0) budget = static_cast<size_t>(v);
     }
 
     hipStream_t cs = nullptr;
@@ -697,110 +800,27 @@ bmd_status bmd_eval_batch(bmd_problem* const* ps, int32_t n, const uint64_t* n_d
         (void)hipEventDestroy(ev);
         HIP_TRY(e, "stream ordering");
     }
+    // Clock and completion stamps, and per-problem item counts, for the whole batch.
+    DeviceBuffer clk;
+    HIP_TRY(hipMalloc(&clk.ptr, align256(sizeof(unsigned long long) * (n + 1)) + align256(sizeof(int) * n)),
+            "batch clock buffer");
+    unsigned long long* d_tstart = static_cast<unsigned long long*>(clk.ptr);
+    unsigned long long* d_tdone = d_tstart + 1;
+    int* d_left = reinterpret_cast<int*>(static_cast<char*>(clk.ptr) + align256(sizeof(unsigned long long) * (n + 1)));
 
-    // Autotuner: per biomarker count, measured cost of one evaluation.
-    double cost[BMD_MAX_DIM + 1] = {};
-    for (int i = 0; i < n; ++i) {
-        const int d = sc[i].P.d;
-        if (cost[d] > 0.0) continue;
-        {
-            std::lock_guard<std::mutex> lock(g_cost_mutex);
-            cost[d] = g_cost[prec][d];
-        }
-        if (cost[d] > 0.0) continue;
-        bmd_status st = probe_cost(sc[i], prec, chunk, lds, grid, ps[i]->d_gl, cs, &cost[d]);
+    for (int first = 0; first < n;) {
+        int last = first;
+        size_t bytes = 0;
+        while (last < n && (last == first || bytes + plan[last].draw_bytes <= budget)) bytes += plan[last++].draw_bytes;
+        bmd_status st = run_batch_group(ps, plan, first, last, prec, d_means, n_cu, cs, d_tstart, d_tdone, d_left,
+                                        first == 0);
         if (st != BMD_OK) return st;
-        std::lock_guard<std::mutex> lock(g_cost_mutex);
-        g_cost[prec][d] = cost[d];
+        first = last;
     }
-
-    // Plan: slices sized so the list holds about eight items per resident
-    // workgroup, each item costing about the same.
-    double total = 0.0;
-    for (int i = 0; i < n; ++i) total += static_cast<double>(sc[i].tiles) * kEvalBlock * sc[i].M * cost[sc[i].P.d];
-    const double target = total / (8.0 * grid);
-    struct Item {
-        int4 v;
-        double c;
-    };
-    std::vector<Item> list;
-    int64_t g_off = 0;
-    size_t part_bytes = 0;
-    for (int i = 0; i < n; ++i) {
-        BatchScenario& S = sc[i];
-        const double c = cost[S.P.d];
-        int64_t L = static_cast<int64_t>(std::ceil(target / (kEvalBlock * c) / chunk)) * chunk;
-        const int64_t Mr = (S.M + chunk - 1) / chunk * chunk;
-        L = std::max<int64_t>(chunk, std::min<int64_t>(L, Mr));
-        S.slice_len = L;
-        S.n_slices = static_cast<int>((S.M + L - 1) / L);
-        S.n_items = S.tiles * S.n_slices;
-        S.g_offset = g_off;
-        g_off += S.P.G;
-        part_bytes += (sizeof(double) * static_cast<size_t>(S.n_slices) * S.P.G + 255) / 256 * 256;
-        for (int t = 0; t < S.tiles; ++t)
-            for (int sl = 0; sl < S.n_slices; ++sl) {
-                const double active = static_cast<double>(std::min<int64_t>(kEvalBlock, S.P.G - int64_t(t) * kEvalBlock));
-                const double draws = static_cast<double>(std::min<int64_t>(L, S.M - int64_t(sl) * L));
-                list.push_back({make_int4(i, t, sl, 0), active * draws * c});
-            }
-    }
-    if (list.size() > (1u << 24)) return fail(BMD_ERANGE, "batch work list of %zu items is too large", list.size());
-    std::stable_sort(list.begin(), list.end(), [](const Item& x, const Item& y) { return x.c > y.c; });
-    std::vector<int4> items(list.size());
-    for (size_t i = 0; i < list.size(); ++i) items[i] = list[i].v;
-
-    // Device buffers: scenarios, items, counters, partials.
-    const size_t sc_bytes = (sizeof(BatchScenario) * n + 255) / 256 * 256;
-    const size_t it_bytes = (sizeof(int4) * items.size() + 255) / 256 * 256;
-    const size_t ctr_bytes = (64 + 4 * static_cast<size_t>(n) + 64 + 8 * static_cast<size_t>(n) + 255) / 256 * 256 + 256;
-    DeviceBuffer buf;
-    {
-        hipError_t e = hipMalloc(&buf.ptr, sc_bytes + it_bytes + ctr_bytes + part_bytes);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(BMD_ENOMEM, "batch workspace: %s", hipGetErrorString(e));
-        }
-    }
-    char* base = static_cast<char*>(buf.ptr);
-    BatchScenario* d_sc = reinterpret_cast<BatchScenario*>(base);
-    int4* d_items = reinterpret_cast<int4*>(base + sc_bytes);
-    char* ctr = base + sc_bytes + it_bytes;
-    int* d_counter = reinterpret_cast<int*>(ctr);
-    int* d_left = reinterpret_cast<int*>(ctr + 64);
-    unsigned long long* d_tstart = reinterpret_cast<unsigned long long*>(ctr + (64 + 4 * static_cast<size_t>(n) + 7) / 8 * 8);
-    unsigned long long* d_tdone = d_tstart + 8;
-    char* part = base + sc_bytes + it_bytes + ctr_bytes;
-    for (int i = 0; i < n; ++i) {
-        sc[i].partials = reinterpret_cast<double*>(part);
-        part += (sizeof(double) * static_cast<size_t>(sc[i].n_slices) * sc[i].P.G + 255) / 256 * 256;
-    }
-    HIP_TRY(hipMemcpy(d_sc, sc.data(), sizeof(BatchScenario) * n, hipMemcpyHostToDevice), "batch upload");
-    HIP_TRY(hipMemcpy(d_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice), "batch upload");
-    BatchArgs a{d_sc, n, d_items, static_cast<int>(items.size()), d_counter, d_left, d_tstart, d_tdone,
-                ps[0]->d_gl, chunk, g_off};
-
-    // One graph: reset counters, persistent sweep, finalize.
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-    hipError_t le = launch_batch(prec, a, grid, lds, true, true, cs);
-    hipError_t ce = hipStreamEndCapture(cs, &graph);
-    if (le != hipSuccess) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return hip_fail(le, "batch capture");
-    }
-    HIP_TRY(ce, "hipStreamEndCapture");
-    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e == hipSuccess) e = hipGraphLaunch(exec, cs);
-    if (e == hipSuccess) e = hipStreamSynchronize(cs);
-    if (exec) (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
-    HIP_TRY(e, "batch graph");
     if (h_wall_ms) {
         std::vector<unsigned long long> t(n + 1);
-        HIP_TRY(hipMemcpy(t.data(), d_tstart, sizeof(unsigned long long), hipMemcpyDeviceToHost), "batch readback");
-        HIP_TRY(hipMemcpy(t.data() + 1, d_tdone, sizeof(unsigned long long) * n, hipMemcpyDeviceToHost), "batch readback");
+        HIP_TRY(hipMemcpy(t.data(), d_tstart, sizeof(unsigned long long) * (n + 1), hipMemcpyDeviceToHost),
+                "batch readback");
         for (int i = 0; i < n; ++i)
             h_wall_ms[i] = t[i + 1] >= t[0] ? static_cast<double>(t[i + 1] - t[0]) / clock_khz : 0.0;
     }

@@ -16,6 +16,7 @@ constexpr int kPrecomputeGH = 128;   // nodes for the per-design subgroup fracti
 constexpr int kGLTable = 200;        // packed Gauss-Legendre rules n = 4..24
 constexpr int kEvalBlock = 256;      // designs per workgroup in the eval kernels
 constexpr int kSweepRounds = 8;      // rounds of resident workgroups a grid sweep is sliced into
+constexpr size_t kBatchBudget = size_t(16) << 30;   // draw bytes one batch group may hold
 
 // Problem constants passed by value to every kernel.
 struct DevProblem {
@@ -57,39 +58,33 @@ struct DrawArrays {
     int K;
 };
 
-// One scenario of a batched launch (bmd_eval_batch).
-struct BatchScenario {
+// One problem's share of a batched draw launch.
+template <typename T>
+struct DrawJob {
     DevProblem P;
-    const double* r;
-    const double* z1;
-    const double* z2;
-    const void* A;          // axis tables in T
     const double* gh;       // FP64 Gauss-Hermite rule x[K], w[K]
-    const void* glw;        // packed GL weights in T
     int K;
-    int tiles;
-    int n_slices;
-    int n_items;
-    int64_t M;
-    int64_t slice_len;
-    int64_t g_offset;       // first flattened design index (finalize)
-    double* partials;       // [n_slices][G]
-    double* mean;           // output [G]
+    int64_t first;          // first flattened draw index of this job
+    DrawArrays<T> D;        // D.M = this job's draws
 };
 
-// Arguments of the batched persistent kernel.
-struct BatchArgs {
-    const BatchScenario* sc;
-    int n_sc;
-    const int4* items;      // (scenario, tile, slice, 0)
+// The work list of one sweep launch of a batch (one workgroup per item).
+struct BatchPhase {
+    const void* sc;               // device array of per-scenario sweep records (type per precision)
+    const int4* items;            // (record, tile, slice, 0), costliest first
     int n_items;
-    int* counter;
-    int* left;              // items not yet finished, per scenario
-    unsigned long long* t_start;
-    unsigned long long* t_done;
-    const double* gl;
-    int chunk;
-    int64_t G_total;
+    int* left;                    // [n_scenarios] items not yet finished
+    unsigned long long* t_start;  // earliest start stamp of the whole batch
+    unsigned long long* t_done;   // [n_scenarios] completion stamp
+};
+
+// One problem's finalize record: mean over its draw slices.
+struct BatchFinal {
+    int64_t first;                // first flattened design index
+    int64_t G, M;
+    int n_slices;
+    const double* partials;       // [n_slices][2][G]
+    double* mean;                 // [G]
 };
 
 // Device constants owned by a problem, per integrand precision.
@@ -151,6 +146,8 @@ bool use_mfma_sweep(const bmd_problem* p);
 int64_t sweep_tiles(const bmd_problem* p, int prec);
 int sweep_blocks_per_cu(const bmd_problem* p, int prec);
 int sweep_chunk(const bmd_problem* p, int prec);
+struct MfmaGeom;
+MfmaGeom sweep_geometry(const bmd_problem* p, int prec);
 hipError_t launch_eval_grid(const bmd_problem* p, int prec, int64_t M, const void* ws,
                             double* partials, int n_slices, int64_t slice_len, hipStream_t s);
 hipError_t launch_finalize(const bmd_problem* p, int64_t M, const double* partials, int n_slices,
@@ -163,10 +160,25 @@ size_t grad_workspace_bytes(const bmd_problem* p, int prec, int64_t B, int n_sli
 int grad_chunk(int prec, int d, int K);
 hipError_t launch_grad(const bmd_problem* p, int prec, const double* d_q, int64_t B, int64_t M, void* ws,
                        int n_slices, int64_t slice_len, double* obj, double* gq, double* gmu, hipStream_t s);
-size_t batch_lds_bytes(int prec, int chunk, int K);
-int batch_blocks_per_cu(int prec, size_t lds);
-hipError_t launch_batch(int prec, const BatchArgs& a, int grid, size_t lds, bool reset, bool finalize,
-                        hipStream_t s);
+// Batched form.  Sweep records are filled on the host (batch_record_bytes
+// each, written by batch_fill_record for scenario `scenario` of the batch);
+// one sweep launch per (precision, d, kernel kind), one workgroup per item.
+DrawArrays<double> draws_fp64_at(const bmd_problem* p, int64_t M, void* ws);
+DrawArrays<float> draws_fp32_at(const bmd_problem* p, int64_t M, void* ws);
+hipError_t launch_draws_batch(int prec, const void* jobs, int n_jobs, int64_t total, hipStream_t s);
+size_t batch_record_bytes(int prec);
+void batch_fill_record(int prec, void* dst, const bmd_problem* p, void* draws_ws, int64_t M, int64_t slice_len,
+                       double* partials, int scenario);
+size_t batch_phase_lds(const bmd_problem* p, int prec);
+int batch_phase_blocks_per_cu(const bmd_problem* p, int prec, size_t lds);
+hipError_t launch_batch_phase(const bmd_problem* p, int prec, const BatchPhase& ph, size_t lds, hipStream_t s);
+// Set left[first .. first+n) from items and clear their completion stamps;
+// t_start (if non-NULL) restarts the clock.
+hipError_t launch_batch_reset(int* left, unsigned long long* t_done, const int* items, int first, int n,
+                              unsigned long long* t_start, hipStream_t s);
+size_t draw_job_bytes(int prec);
+void fill_draw_job(int prec, void* dst, const bmd_problem* p, void* draws_ws, int64_t M, int64_t first);
+hipError_t launch_batch_finalize(const BatchFinal* jobs, int n_jobs, int64_t total, hipStream_t s);
 hipError_t launch_inspect_draws(const bmd_problem* p, uint64_t k0, int64_t n, double* u,
                                 double* fields, hipStream_t s);
 hipError_t launch_inspect_designs(const bmd_problem* p, int64_t g0, int64_t n, double* fields,

@@ -221,7 +221,8 @@ struct BvnWeights {
     float w[NMAX];
     __device__ __forceinline__ void load(const float* __restrict__ src, int n) {
 #pragma unroll
-        for (int i = 0; i < NMAX; ++i) w[i] = i < n ? src[i] : 0.0f;
+        for (int i = 0; i < NMAX; ++i)
+            w[i] = i < n ? __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(src[i]))) : 0.0f;
     }
     __device__ __forceinline__ float operator[](int i) const { return w[i]; }
 };

@@ -1,149 +1,164 @@
-// Many independent grid problems in one persistent launch.
+// Many independent grid problems (Sec. 3's families of design problems) in
+// one captured graph: a draw launch for every problem's prior draws, then one
+// sweep launch per (precision, biomarker count, kernel kind) over a work list
+// of (problem, design tile, draw slice) items, then a fixed-order finalize.
 //
-// Work item = (scenario, tile of 256 designs, slice of draws).  Workgroups pull
-// items from a device counter until the list is exhausted (every workgroup
-// reaches the exit), regenerate the slice's draws chunk by chunk in LDS from
-// their Philox counters, and write one FP64 partial sum per design and slice.
-// The last item of a scenario stamps its completion time.  A finalize kernel
-// reduces the slices in fixed order, so results do not depend on scheduling.
+// Each item runs the same tile body as the one-problem sweep (sweep_body.hpp),
+// so a batch computes exactly the one-problem sums per slice.
+#include <algorithm>
 #include <climits>
+#include <cstring>
 
 #include "bmd_internal.hpp"
 #include "device_math.hpp"
-#include "draw_chunk.hpp"
-#include "eval_core.hpp"
+#include "sweep_body.hpp"
 
 namespace bmd {
 
 namespace {
 
-template <typename T, int D, int NMAX>
-__device__ void batch_item(const BatchScenario& S, int tile, int slice, char* lds, const BatchArgs& a) {
-    const DevProblem& P = S.P;
-    const int64_t G = P.G;
-    const int64_t g = static_cast<int64_t>(tile) * kEvalBlock + threadIdx.x;
-    const bool valid = g < G;
-    const int64_t gg = valid ? g : G - 1;
-    DesignState<T, D, NMAX> s;
-    s.init(P, gg, S.r, S.z1, S.z2, a.gl, static_cast<const T*>(S.glw));
-    const ChunkView<T> c = carve_chunk<T>(lds, a.chunk, S.K);
-    const ChunkDraws<T> src{c, D, S.K};
-    const T* A = static_cast<const T*>(S.A);
-    const int64_t kb = static_cast<int64_t>(slice) * S.slice_len;
-    const int64_t ke = min(S.M, kb + S.slice_len);
-    double s1 = 0.0;
-    for (int64_t k0 = kb; k0 < ke; k0 += a.chunk) {
-        const int nk = static_cast<int>(min<int64_t>(a.chunk, ke - k0));
-        regenerate_chunk<T, D>(P, S.gh, S.K, c, k0, nk);
-        for (int i = 0; i < nk; ++i) s1 += static_cast<double>(summand<T, D, NMAX>(P, s, src, i, A, S.K));
-    }
-    if (valid) S.partials[static_cast<int64_t>(slice) * G + g] = s1;
-}
+// One problem of a batch, as the sweep bodies read it.
+template <typename T>
+struct BatchRecord {
+    EvalArgs<T> a;
+    MfmaGeom geo;
+    int scenario;      // index of the problem in the batch (left / t_done slot)
+};
 
-// Work loop.  Thread 0 does all of its global bookkeeping in ONE guarded block
-// at the top of the iteration (retire the previous item, claim the next), and
-// the claimed index is broadcast through LDS and made wave-uniform, so the
-// loop exit is a scalar branch.  Two separate thread-0 blocks (claim at the
-// top, retire at the bottom) let the compiler thread them together across the
-// back edge into a loop nest in which lane 0 waits outside an inner loop that
-// the rest of its wave can only leave after lane 0 claims new work: a deadlock
-// under SIMT execution.
-template <typename T, int NMAX>
-__global__ __launch_bounds__(kEvalBlock) void k_batch(BatchArgs a) {
+// One work item per workgroup: item blockIdx.x of the list, which is sorted
+// costliest first, so the hardware dispatcher hands the long items out first
+// and back-fills the short ones (the balance a persistent queue would give,
+// without a work loop: with one, the compiler hoists the tile's per-thread
+// addressing out of the loop and keeps it live across items, costing about 70
+// VGPRs and half the occupancy).  The records come in as their own __restrict__
+// argument, read-only for the launch, so their wave-uniform fields are fetched
+// with scalar loads.  The last item of a problem stamps its completion time.
+template <typename T, int D, int NMAX, bool MF>
+__global__ __launch_bounds__(kEvalBlock) void k_batch(BatchPhase ph, const BatchRecord<T>* __restrict__ recs) {
     extern __shared__ __align__(16) char lds[];
-    __shared__ int s_item;
-    int prev_sc = -1;   // scenario of the item this workgroup finished last (thread 0)
-    if (threadIdx.x == 0) atomicMin(a.t_start, static_cast<unsigned long long>(wall_clock64()));
-    for (;;) {
-        if (threadIdx.x == 0) {
-            if (prev_sc >= 0) {
-                __threadfence();
-                if (atomicSub(&a.left[prev_sc], 1) == 1)
-                    a.t_done[prev_sc] = static_cast<unsigned long long>(wall_clock64());
-            }
-            s_item = atomicAdd(a.counter, 1);
-        }
-        __syncthreads();
-        const int item = __builtin_amdgcn_readfirstlane(s_item);
-        if (item >= a.n_items) break;
-        const int4 it = a.items[item];
-        const int sc = __builtin_amdgcn_readfirstlane(it.x);
-        const int tile = __builtin_amdgcn_readfirstlane(it.y);
-        const int slice = __builtin_amdgcn_readfirstlane(it.z);
-        const BatchScenario& S = a.sc[sc];
-        switch (__builtin_amdgcn_readfirstlane(S.P.d)) {
-            case 1: batch_item<T, 1, NMAX>(S, tile, slice, lds, a); break;
-            case 2: batch_item<T, 2, NMAX>(S, tile, slice, lds, a); break;
-            case 3: batch_item<T, 3, NMAX>(S, tile, slice, lds, a); break;
-            case 4: batch_item<T, 4, NMAX>(S, tile, slice, lds, a); break;
-            case 5: batch_item<T, 5, NMAX>(S, tile, slice, lds, a); break;
-            default: batch_item<T, 6, NMAX>(S, tile, slice, lds, a); break;
-        }
-        prev_sc = sc;
-        __syncthreads();   // item done by every thread; s_item free for the next claim
+    if (threadIdx.x == 0) atomicMin(ph.t_start, static_cast<unsigned long long>(wall_clock64()));
+    const int4 it = ph.items[blockIdx.x];
+    const int rec = __builtin_amdgcn_readfirstlane(it.x);
+    const int tile = __builtin_amdgcn_readfirstlane(it.y);
+    const int slice = __builtin_amdgcn_readfirstlane(it.z);
+    const BatchRecord<T>& R = recs[rec];
+    if constexpr (MF)
+        mfma_tile_body<T, D, NMAX>(R.a, R.geo, tile, slice, lds);
+    else
+        direct_body<T, D, NMAX>(R.a, tile, slice);
+    __syncthreads();   // every thread's partial sums are written
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const int sc = R.scenario;
+        if (atomicSub(&ph.left[sc], 1) == 1) ph.t_done[sc] = static_cast<unsigned long long>(wall_clock64());
     }
 }
 
-// Counters for one launch (a kernel, so the sequence can live in a graph).
-__global__ void k_batch_reset(BatchArgs a) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s == 0) {
-        *a.counter = 0;
-        *a.t_start = ULLONG_MAX;
+__global__ void k_batch_reset(int* left, unsigned long long* t_done, const int* items, int first, int n,
+                              unsigned long long* t_start) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) {
+        left[first + t] = items[t];
+        t_done[first + t] = 0;
     }
-    if (s < a.n_sc) {
-        a.left[s] = a.sc[s].n_items;
-        a.t_done[s] = 0;
-    }
+    if (t == 0 && t_start) *t_start = ULLONG_MAX;
 }
 
-__global__ void k_batch_finalize(BatchArgs a) {
+// mean[g] = (sum over slices, in slice order) / M for every design of every job.
+__global__ void k_batch_finalize(const BatchFinal* __restrict__ jobs, int n_jobs, int64_t total) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= a.G_total) return;
-    int lo = 0, hi = a.n_sc - 1;   // last scenario with g_offset <= t
+    if (t >= total) return;
+    int lo = 0, hi = n_jobs - 1;   // last job with first <= t
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (a.sc[mid].g_offset <= t) lo = mid; else hi = mid - 1;
+        if (jobs[mid].first <= t) lo = mid; else hi = mid - 1;
     }
-    const BatchScenario& S = a.sc[lo];
-    const int64_t g = t - S.g_offset;
+    const BatchFinal& J = jobs[lo];
+    const int64_t g = t - J.first;
     double s = 0.0;
-    for (int sl = 0; sl < S.n_slices; ++sl) s += S.partials[static_cast<int64_t>(sl) * S.P.G + g];
-    S.mean[g] = s / static_cast<double>(S.M);
+    for (int sl = 0; sl < J.n_slices; ++sl) s += J.partials[static_cast<int64_t>(sl) * 2 * J.G + g];
+    J.mean[g] = s / static_cast<double>(J.M);
+}
+
+template <typename T, int NMAX, bool MF>
+const void* batch_kernel(int d) {
+    switch (d) {
+        case 1: return MF ? nullptr : reinterpret_cast<const void*>(k_batch<T, 1, NMAX, false>);
+        case 2: return reinterpret_cast<const void*>(k_batch<T, 2, NMAX, MF>);
+        case 3: return reinterpret_cast<const void*>(k_batch<T, 3, NMAX, MF>);
+        case 4: return reinterpret_cast<const void*>(k_batch<T, 4, NMAX, MF>);
+        case 5: return reinterpret_cast<const void*>(k_batch<T, 5, NMAX, MF>);
+        default: return reinterpret_cast<const void*>(k_batch<T, 6, NMAX, MF>);
+    }
+}
+
+const void* phase_kernel(const bmd_problem* p, int prec) {
+    const bool mf = use_mfma_sweep(p);
+    if (prec == BMD_FP64) return mf ? batch_kernel<double, 24, true>(p->P.d) : batch_kernel<double, 24, false>(p->P.d);
+    return mf ? batch_kernel<float, 12, true>(p->P.d) : batch_kernel<float, 12, false>(p->P.d);
 }
 
 }  // namespace
 
-size_t batch_lds_bytes(int prec, int chunk, int K) {
-    return prec == BMD_FP64 ? chunk_bytes<double>(chunk, kMaxDim, K) : chunk_bytes<float>(chunk, kMaxDim, K);
+size_t batch_record_bytes(int prec) {
+    const size_t b = prec == BMD_FP64 ? sizeof(BatchRecord<double>) : sizeof(BatchRecord<float>);
+    return (b + 15) / 16 * 16;
 }
 
-int batch_blocks_per_cu(int prec, size_t lds) {
+void batch_fill_record(int prec, void* dst, const bmd_problem* p, void* draws_ws, int64_t M, int64_t slice_len,
+                       double* partials, int scenario) {
+    const MfmaGeom geo = use_mfma_sweep(p) ? sweep_geometry(p, prec) : MfmaGeom{};
+    if (prec == BMD_FP64) {
+        BatchRecord<double> r{EvalArgs<double>{p->P, p->d_r, p->d_z1, p->d_z2,
+                                               static_cast<const double*>(p->tab[prec].A), draws_fp64_at(p, M, draws_ws),
+                                               p->d_gl, static_cast<const double*>(p->tab[prec].glw), slice_len, partials},
+                              geo, scenario};
+        std::memcpy(dst, &r, sizeof r);
+    } else {
+        BatchRecord<float> r{EvalArgs<float>{p->P, p->d_r, p->d_z1, p->d_z2,
+                                             static_cast<const float*>(p->tab[prec].A), draws_fp32_at(p, M, draws_ws),
+                                             p->d_gl, static_cast<const float*>(p->tab[prec].glw), slice_len, partials},
+                             geo, scenario};
+        std::memcpy(dst, &r, sizeof r);
+    }
+}
+
+size_t batch_phase_lds(const bmd_problem* p, int prec) {
+    if (!use_mfma_sweep(p)) return 0;
+    const MfmaGeom geo = sweep_geometry(p, prec);
+    return prec == BMD_FP64 ? mfma_lds_bytes<double>(geo.chunk, p->P.d, p->tab[prec].K)
+                            : mfma_lds_bytes<float>(geo.chunk, p->P.d, p->tab[prec].K);
+}
+
+int batch_phase_blocks_per_cu(const bmd_problem* p, int prec, size_t lds) {
     int nb = 0;
-    hipError_t e = prec == BMD_FP64
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<double, 24>, kEvalBlock, lds)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<float, 12>, kEvalBlock, lds);
-    if (e != hipSuccess || nb < 1) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, phase_kernel(p, prec), kEvalBlock, lds) != hipSuccess ||
+        nb < 1) {
         (void)hipGetLastError();
         nb = 1;
     }
     return nb;
 }
 
-hipError_t launch_batch(int prec, const BatchArgs& a, int grid, size_t lds, bool reset, bool finalize,
-                        hipStream_t s) {
-    if (reset) {
-        hipLaunchKernelGGL(k_batch_reset, dim3((a.n_sc + 255) / 256), dim3(256), 0, s, a);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    if (prec == BMD_FP64)
-        hipLaunchKernelGGL((k_batch<double, 24>), dim3(grid), dim3(kEvalBlock), lds, s, a);
-    else
-        hipLaunchKernelGGL((k_batch<float, 12>), dim3(grid), dim3(kEvalBlock), lds, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !finalize) return e;
-    hipLaunchKernelGGL(k_batch_finalize, dim3(static_cast<unsigned>((a.G_total + 255) / 256)), dim3(256), 0, s, a);
+hipError_t launch_batch_phase(const bmd_problem* p, int prec, const BatchPhase& ph, size_t lds, hipStream_t s) {
+    if (ph.n_items <= 0) return hipSuccess;
+    const void* recs = ph.sc;
+    void* args[] = {const_cast<BatchPhase*>(&ph), const_cast<void**>(&recs)};
+    return hipLaunchKernel(phase_kernel(p, prec), dim3(static_cast<unsigned>(ph.n_items)), dim3(kEvalBlock), args, lds,
+                           s);
+}
+
+hipError_t launch_batch_reset(int* left, unsigned long long* t_done, const int* items, int first, int n,
+                              unsigned long long* t_start, hipStream_t s) {
+    const int m = std::max(n, 1);
+    hipLaunchKernelGGL(k_batch_reset, dim3((m + 255) / 256), dim3(256), 0, s, left, t_done, items, first, n, t_start);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(const BatchFinal* jobs, int n_jobs, int64_t total, hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_finalize, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s, jobs,
+                       n_jobs, total);
     return hipGetLastError();
 }
 

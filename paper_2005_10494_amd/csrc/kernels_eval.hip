@@ -6,257 +6,20 @@
 #include "bmd_internal.hpp"
 #include "device_math.hpp"
 #include "eval_core.hpp"
+#include "sweep_body.hpp"
 
 namespace bmd {
 namespace {
 
-template <typename T>
-struct EvalArgs {
-    DevProblem P;
-    const double* r;
-    const double* z1;
-    const double* z2;
-    const T* A;          // axis tables [d][K][mmax]
-    DrawArrays<T> D;
-    const double* gl;    // packed GL table (FP64 nodes)
-    const T* glw;        // packed GL table in T (weights read from here)
-    int64_t slice_len;
-    double* partials;    // [n_slices][2][G]
-};
-
 template <typename T, int D, int NMAX>
 __global__ __launch_bounds__(kEvalBlock) void k_eval_direct(EvalArgs<T> a) {
-    const int64_t G = a.P.G;
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * kEvalBlock + threadIdx.x;
-    const bool valid = g < G;
-    const int64_t gg = valid ? g : G - 1;   // idle lanes shadow the last design
-    DesignState<T, D, NMAX> s;
-    s.init(a.P, gg, a.r, a.z1, a.z2, a.gl, a.glw);
-    const GlobalDraws<T> src{a.D, D};
-    const int64_t M = a.D.M;
-    const int64_t kb = static_cast<int64_t>(blockIdx.y) * a.slice_len;
-    const int64_t ke = min(M, kb + a.slice_len);
-    double s1 = 0.0, s2 = 0.0;
-    for (int64_t k = kb; k < ke; ++k) {
-        const double v = static_cast<double>(summand<T, D, NMAX>(a.P, s, src, k, a.A, a.D.K));
-        s1 += v;
-        s2 += v * v;
-    }
-    if (valid) {
-        double* out = a.partials + static_cast<int64_t>(blockIdx.y) * 2 * G;
-        out[g] = s1;
-        out[G + g] = s2;
-    }
+    direct_body<T, D, NMAX>(a, blockIdx.x, blockIdx.y);
 }
 
-// Four values of one draw read with one LDS access.
-template <typename T>
-struct alignas(4 * sizeof(T)) Quad {
-    T x, y, z, w;
-};
-
-// Bit pattern type of T, and a branch-free select of two values already read.
-template <typename T>
-using Bits = typename std::conditional<sizeof(T) == 8, unsigned long long, unsigned int>::type;
-__device__ __forceinline__ float bit_select(unsigned int m, float a, float b) {
-    return __uint_as_float((__float_as_uint(a) & m) | (__float_as_uint(b) & ~m));
-}
-__device__ __forceinline__ double bit_select(unsigned long long m, double a, double b) {
-    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(__double_as_longlong(a)) & m) |
-                                                      (static_cast<unsigned long long>(__double_as_longlong(b)) & ~m)));
-}
-
-typedef float mf_f4 __attribute__((ext_vector_type(4)));
-typedef double mf_d4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ mf_f4 mf_step(float a, float b, mf_f4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ mf_d4 mf_step(double a, double b, mf_d4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-// Tile geometry of the matrix-core sweep: designs g = p * Sn + l with prefix
-// index p (axes < split) and suffix index l (axes >= split); a workgroup owns a
-// 16 x 16 tile of (p, l) and a slice of draws.
-struct MfmaGeom {
-    int split;
-    int64_t Pn, Sn;       // prefix and suffix counts
-    int64_t tiles_l;      // tiles along the suffix index
-    int chunk;            // draws staged per LDS chunk
-};
-
-// Sweep for grid designs with d >= 2, step prior, exact cutoff indicator.
-// Phase A (matrix cores): for each draw of the chunk,
-//   O[p][l] = sum_m Pre[p][m] Suf[l][m],
-//   Pre[p][m] = prod_{j < split} v_j(p)[m],  Suf[l][m] = prod_{j >= split} v_j(l)[m],
-//   v_j[m] = A_j[i_j][m] if the design's cutoff on axis j lies above the drawn one
-//            (i_j >= thr_j(k)), else the draw's B_j[m]  (Gauss-Hermite weights in axis 0),
-// i.e. the one-factor quadrature of P(x_j > max(c_j, t_j) all j) for all 256
-// designs at once; each wavefront takes every fourth draw.
-// Phase B (vector units): one design per thread, the bivariate normal part.
 template <typename T, int D, int NMAX>
 __global__ __launch_bounds__(kEvalBlock) void k_eval_mfma(EvalArgs<T> a, MfmaGeom geo) {
-    using acc_t = typename std::conditional<sizeof(T) == 8, mf_d4, mf_f4>::type;
     extern __shared__ __align__(16) char lds[];
-    const int K = a.D.K;   // a multiple of 4 (node steps of four)
-    const int CH = geo.chunk;
-    T* sO = reinterpret_cast<T*>(lds);                                  // [CH][256]
-    T* sB = sO + static_cast<size_t>(CH) * kEvalBlock;                   // [CH][D][K]
-    Quad<T>* sq = reinterpret_cast<Quad<T>*>(sB + static_cast<size_t>(CH) * D * K);  // [CH] (b0, b1, mu1, -)
-    int* sthr = reinterpret_cast<int*>(sq + CH);                         // [CH][D]
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t tile = blockIdx.x;
-    const int64_t p0 = (tile / geo.tiles_l) * 16, l0 = (tile % geo.tiles_l) * 16;
-    const int64_t G = a.P.G;
-    const int64_t M = a.D.M;
-    const int mmax = a.P.mmax;
-
-    // phase B design: row tid/16, column tid%16 of the tile
-    const int64_t pB = p0 + tid / 16, lB = l0 + tid % 16;
-    const bool validB = pB < geo.Pn && lB < geo.Sn;
-    const int64_t g = validB ? pB * geo.Sn + lB : G - 1;
-    DesignState<T, D, NMAX> st;
-    st.init(a.P, g, a.r, a.z1, a.z2, a.gl, a.glw);
-
-    // phase A operands: lane supplies row (p0 + lane%16) of Pre and column
-    // (l0 + lane%16) of Suf at node m0 + lane/16
-    const int r16 = lane & 15, kq = lane >> 4;
-    const int64_t pA = p0 + r16, lA = l0 + r16;
-    const bool rowA = pA < geo.Pn, colA = lA < geo.Sn;   // else: shadow design 0's indices
-    int iA[D];
-    {
-        int64_t rem = (rowA ? pA : 0) * geo.Sn + (colA ? lA : 0);
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            iA[j] = static_cast<int>(rem / a.P.stride[j]);
-            rem -= static_cast<int64_t>(iA[j]) * a.P.stride[j];
-        }
-    }
-
-    // This lane's axis-table values (draw independent) for the first kHoist
-    // node steps stay in registers (FP32; the FP64 kernel has none to spare);
-    // the remaining steps read them from memory.
-    constexpr int kHoist = sizeof(T) == 4 ? 6 : 0;
-    constexpr int kChains = sizeof(T) == 4 ? 2 : 1;   // draws per wavefront pass
-    const int S = K / 4;
-    T aH[kHoist > 0 ? kHoist : 1][D];
-#pragma unroll
-    for (int s = 0; s < kHoist; ++s) {
-        const int m = 4 * s + kq;
-#pragma unroll
-        for (int j = 0; j < D; ++j)
-            aH[s][j] = (s < S && m < K) ? a.A[(static_cast<int64_t>(j) * K + m) * mmax + iA[j]] : T(0);
-    }
-    // Gauss-Legendre weights of this wavefront's rule: scalar registers in FP32
-    const auto wts = [&]() {
-        if constexpr (sizeof(T) == 4) {
-            BvnWeights<NMAX> w;
-            w.load(st.w, st.n);
-            return w;
-        } else {
-            return st.w;
-        }
-    }();
-
-    const int64_t kb = static_cast<int64_t>(blockIdx.y) * a.slice_len;
-    const int64_t ke = min(M, kb + a.slice_len);
-    double s1 = 0.0, s2 = 0.0;
-    for (int64_t k0 = kb; k0 < ke; k0 += CH) {
-        const int nk = __builtin_amdgcn_readfirstlane(static_cast<int>(min<int64_t>(CH, ke - k0)));
-        __syncthreads();
-        // stage the chunk's draws (the B rows of consecutive draws are contiguous)
-        {
-            const T* src = a.D.B + k0 * D * K;
-            for (int e = tid; e < nk * D * K; e += kEvalBlock) sB[e] = src[e];
-        }
-        for (int e = tid; e < nk; e += kEvalBlock)
-            sq[e] = Quad<T>{a.D.b0[k0 + e], a.D.b1[k0 + e], a.D.mu1[k0 + e], T(0)};
-        for (int e = tid; e < nk * D; e += kEvalBlock) {
-            const int i = e / D, j = e % D;
-            sthr[e] = a.D.thr[j * M + k0 + i];
-        }
-        __syncthreads();
-        // phase A: overlaps of the tile; a wavefront takes kChains draws per
-        // pass (draws wave + 4c + 4 kChains t), one independent MFMA chain each.
-        // Rows or columns past the grid (p >= Pn, l >= Sn) feed only tile
-        // entries that phase B never stores, so they need no masking.
-        constexpr int kWaves = kEvalBlock / 64;
-        auto phase_a = [&](auto split_c) {
-            constexpr int SPLIT = decltype(split_c)::value;
-            for (int i0 = wave; i0 < nk; i0 += kChains * kWaves) {
-                int ic[kChains];
-                Bits<T> msk[kChains][D];   // all ones: the design's axis-j cutoff is above the draw's
-                const T* Bc[kChains];
-                acc_t c[kChains];
-#pragma unroll
-                for (int q = 0; q < kChains; ++q) {
-                    ic[q] = i0 + q * kWaves < nk ? i0 + q * kWaves : i0;
-#pragma unroll
-                    for (int j = 0; j < D; ++j) msk[q][j] = iA[j] >= sthr[ic[q] * D + j] ? ~Bits<T>(0) : Bits<T>(0);
-                    Bc[q] = sB + static_cast<size_t>(ic[q]) * D * K;
-                    c[q] = acc_t{0, 0, 0, 0};
-                }
-                auto step = [&](int m, const T* av) {
-#pragma unroll
-                    for (int q = 0; q < kChains; ++q) {
-                        T pre = T(1), suf = T(1);
-#pragma unroll
-                        for (int j = 0; j < D; ++j) {
-                            const T v = bit_select(msk[q][j], av[j], Bc[q][j * K + m]);
-                            if (j < SPLIT) pre *= v; else suf *= v;   // j, SPLIT: compile-time after unrolling
-                        }
-                        c[q] = mf_step(pre, suf, c[q]);
-                    }
-                };
-#pragma unroll
-                for (int s = 0; s < kHoist; ++s)
-                    if (s < S) step(4 * s + kq, aH[s]);
-                for (int s = kHoist; s < S; ++s) {
-                    const int m = 4 * s + kq;
-                    T av[D];
-#pragma unroll
-                    for (int j = 0; j < D; ++j) av[j] = a.A[(static_cast<int64_t>(j) * K + m) * mmax + iA[j]];
-                    step(m, av);
-                }
-#pragma unroll
-                for (int q = 0; q < kChains; ++q) {
-                    if (q > 0 && i0 + q * kWaves >= nk) break;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        sO[static_cast<size_t>(ic[q]) * kEvalBlock + mfma16_row<T>(kq, v) * 16 + r16] = c[q][v];
-                }
-            }
-        };
-        switch (geo.split) {
-            case 1: phase_a(std::integral_constant<int, 1>{}); break;
-            case 2: if constexpr (D > 2) phase_a(std::integral_constant<int, 2>{}); break;
-            case 3: if constexpr (D > 3) phase_a(std::integral_constant<int, 3>{}); break;
-            case 4: if constexpr (D > 4) phase_a(std::integral_constant<int, 4>{}); break;
-            default: if constexpr (D > 5) phase_a(std::integral_constant<int, 5>{}); break;
-        }
-        __syncthreads();
-        // phase B: bivariate normal part for this thread's design
-        for (int i = 0; i < nk; ++i) {
-            const T O = sO[static_cast<size_t>(i) * kEvalBlock + tid];
-            const Quad<T> dq = sq[i];
-            const T mu2 = st.srI * (dq.x + dq.y * O * st.invr);
-            const T h = st.z1 - dq.z, kq2 = st.z2 - mu2;
-            T p;
-            if (a.P.zinf == 0) p = bvn_cdf<NMAX>(h, kq2, st.bc, wts, st.n);
-            else if (a.P.zinf == 1) p = norm_cdf(kq2);
-            else if (a.P.zinf == 2) p = norm_cdf(h);
-            else p = T(1);
-            const double v = static_cast<double>(T(1) - p);
-            s1 += v;
-            s2 += v * v;
-        }
-    }
-    if (validB) {
-        double* out = a.partials + static_cast<int64_t>(blockIdx.y) * 2 * G;
-        out[g] = s1;
-        out[G + g] = s2;
-    }
+    mfma_tile_body<T, D, NMAX>(a, geo, blockIdx.x, blockIdx.y, lds);
 }
 
 __global__ void k_finalize(int64_t G, int64_t M, int n_slices, const double* __restrict__ part,
@@ -271,12 +34,6 @@ __global__ void k_finalize(int64_t G, int64_t M, int n_slices, const double* __r
     const double Md = static_cast<double>(M);
     mean[g] = s1 / Md;
     if (var) var[g] = M > 1 ? fmax(0.0, (s2 - s1 * s1 / Md) / (Md - 1.0)) : 0.0;
-}
-
-template <typename T>
-size_t mfma_lds_bytes(int chunk, int d, int K) {
-    return sizeof(T) * static_cast<size_t>(chunk) * (kEvalBlock + static_cast<size_t>(d) * K + 4) +
-           sizeof(int) * static_cast<size_t>(chunk) * d;
 }
 
 // Prefix/suffix split with the least tile padding (ties: the later split).
@@ -378,6 +135,8 @@ int resident_typed(const bmd_problem* p, int prec) {
 bool use_mfma_sweep(const bmd_problem* p) {
     return p->grid && p->P.d >= 2 && p->P.effect == BMD_EFFECT_STEP && p->P.width == 0.0 && !p->force_direct;
 }
+
+MfmaGeom sweep_geometry(const bmd_problem* p, int prec) { return mfma_geometry(p, prec); }
 
 int64_t sweep_tiles(const bmd_problem* p, int prec) {
     if (use_mfma_sweep(p)) {

@@ -1,5 +1,7 @@
 // Per-design and per-draw setup kernels: grid coordinates, subgroup fractions,
 // critical values (Formula 2), axis tables, and the prior draws of Formula 5.
+#include <cstring>
+
 #include "bmd_internal.hpp"
 #include "device_math.hpp"
 
@@ -125,13 +127,10 @@ __device__ __forceinline__ int32_t count_le(const DevProblem& P, int j, double t
     return lo;
 }
 
-// One prior draw per thread (Formula 5's Delta^(k)).
+// Prior draw k (Formula 5's Delta^(k)) into slot kk of the per-draw arrays.
 template <typename T>
-__global__ __launch_bounds__(128) void k_draws(DevProblem P, const double* __restrict__ gh, int K, uint64_t k0, int64_t M,
-                        DrawArrays<T> D) {
-    const int64_t kk = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (kk >= M) return;
-    const uint64_t k = k0 + static_cast<uint64_t>(kk);
+__device__ __forceinline__ void draw_one(const DevProblem& P, const double* __restrict__ gh, int K, uint64_t k,
+                                         int64_t kk, int64_t M, const DrawArrays<T>& D) {
     double u[8];
     draw_uniforms<8>(k, P.scenario, P.key0, P.key1, P.n_uniform, u);
     if (P.effect == BMD_EFFECT_STEP) {
@@ -173,6 +172,31 @@ __global__ __launch_bounds__(128) void k_draws(DevProblem P, const double* __res
         D.e2[kk] = static_cast<T>(e2);
         D.mu1[kk] = static_cast<T>(P.sqrtI * (P.th1 + P.sg1 * e1));
     }
+}
+
+// One prior draw per thread.
+template <typename T>
+__global__ __launch_bounds__(128) void k_draws(DevProblem P, const double* __restrict__ gh, int K, uint64_t k0, int64_t M,
+                        DrawArrays<T> D) {
+    const int64_t kk = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (kk >= M) return;
+    draw_one<T>(P, gh, K, k0 + static_cast<uint64_t>(kk), kk, M, D);
+}
+
+// Draws of many problems in one launch: thread t takes draw t - first[s] of the
+// last job s with first[s] <= t (jobs in increasing order of first).
+template <typename T>
+__global__ __launch_bounds__(128) void k_draws_batch(const DrawJob<T>* __restrict__ jobs, int n_jobs, int64_t total) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].first <= t) lo = mid; else hi = mid - 1;
+    }
+    const DrawJob<T>& j = jobs[lo];
+    const int64_t kk = t - j.first;
+    draw_one<T>(j.P, j.gh, j.K, static_cast<uint64_t>(kk), kk, j.D.M, j.D);
 }
 
 __global__ __launch_bounds__(128) void k_inspect_draws(DevProblem P, const double* __restrict__ gh, int K, uint64_t k0,
@@ -293,6 +317,35 @@ hipError_t launch_draws(const bmd_problem* p, int prec, uint64_t k0, int64_t M, 
     else
         hipLaunchKernelGGL(k_draws<float>, dim3(blocks_for(M, 128)), dim3(128), 0, s, p->P, t.gh, t.K, k0, M,
                            carve<float>(p, prec, M, ws));
+    return hipGetLastError();
+}
+
+DrawArrays<double> draws_fp64_at(const bmd_problem* p, int64_t M, void* ws) { return carve<double>(p, BMD_FP64, M, ws); }
+DrawArrays<float> draws_fp32_at(const bmd_problem* p, int64_t M, void* ws) {
+    return carve<float>(p, BMD_FP32_COMP, M, ws);
+}
+
+size_t draw_job_bytes(int prec) { return prec == BMD_FP64 ? sizeof(DrawJob<double>) : sizeof(DrawJob<float>); }
+
+void fill_draw_job(int prec, void* dst, const bmd_problem* p, void* draws_ws, int64_t M, int64_t first) {
+    const PrecTables& t = p->tab[prec];
+    if (prec == BMD_FP64) {
+        DrawJob<double> j{p->P, t.gh, t.K, first, carve<double>(p, prec, M, draws_ws)};
+        std::memcpy(dst, &j, sizeof j);
+    } else {
+        DrawJob<float> j{p->P, t.gh, t.K, first, carve<float>(p, prec, M, draws_ws)};
+        std::memcpy(dst, &j, sizeof j);
+    }
+}
+
+hipError_t launch_draws_batch(int prec, const void* jobs, int n_jobs, int64_t total, hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    if (prec == BMD_FP64)
+        hipLaunchKernelGGL(k_draws_batch<double>, dim3(blocks_for(total, 128)), dim3(128), 0, s,
+                           static_cast<const DrawJob<double>*>(jobs), n_jobs, total);
+    else
+        hipLaunchKernelGGL(k_draws_batch<float>, dim3(blocks_for(total, 128)), dim3(128), 0, s,
+                           static_cast<const DrawJob<float>*>(jobs), n_jobs, total);
     return hipGetLastError();
 }
 

@@ -69,6 +69,34 @@ def test_batch_groups_under_a_memory_budget(monkeypatch):
             p.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_mixed_kernel_kinds(prec):
+    """Problems that take the direct sweep at d >= 2 (logistic indicator,
+    Formula 10 prior, alpha rules) next to matrix-core ones in one batch."""
+    specs = []
+    a = W.base_problem(2, [11, 9], 0.3, 0.05, scenario=1)
+    a["width"] = 0.01
+    b = W.base_problem(3, [6, 5, 7], 0.25, 0.05, scenario=2)
+    b.update(effect="paper", paper_a=0.8, paper_b=0.6, paper_events=80.0, info=211.0)
+    c = W.base_problem(3, [8, 6, 5], 0.4, 0.05, scenario=3, alpha_rule="bonferroni")
+    e = W.base_problem(1, [33], 0.0, 0.05, scenario=4)
+    e["width"] = 0.02
+    specs = [a, b, c, e]
+    draws = [700, 1100, 900, 1300]
+    probs = [bmd.Problem(s) for s in specs]
+    try:
+        kinds = [bmd.sweep_kind(p) for p in probs]
+        assert kinds == ["direct", "direct", "matrix", "direct"]
+        means, wall = bmd.eval_batch(probs, draws, prec)
+        for p, m, M in zip(probs, means, draws):
+            ref = p.eval_grid(M, prec)
+            assert (m - ref).abs().max().item() <= 1e-12
+        assert np.all(wall > 0)
+    finally:
+        for p in probs:
+            p.close()
+
+
 def test_batch_matches_oracle_sampled():
     sc = _scenarios(8, seed=9, m_scale=0.2, draws=(200, 800))
     probs = [bmd.Problem(s) for s in sc]

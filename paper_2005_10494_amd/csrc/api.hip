@@ -562,13 +562,16 @@ bmd_status bmd_grad_design(bmd_problem* p, const double* d_q, int64_t B, uint64_
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t M = static_cast<int64_t>(n_draws);
     const int chunk = grad_chunk(prec, p->P.d, p->tab[prec].K);
-    const int64_t bx = (B + 127) / 128;
-    int64_t n_slices = std::max<int64_t>(1, std::min<int64_t>((2048 + bx - 1) / bx, (M + chunk - 1) / chunk));
-    n_slices = std::min<int64_t>(n_slices, 65535);
+    // Draw slices: about kSweepRounds rounds of resident workgroups.
+    const int64_t bx = (B + 127) / 128;   // 128 points per workgroup
+    const int64_t resident = static_cast<int64_t>(p->n_cu) * grad_blocks_per_cu(p, prec);
+    int64_t n_slices = (kSweepRounds * resident + bx - 1) / bx;
+    n_slices = std::max<int64_t>(1, std::min<int64_t>({n_slices, (M + chunk - 1) / chunk, 65535}));
     int64_t slice_len = (M + n_slices - 1) / n_slices;
     slice_len = (slice_len + chunk - 1) / chunk * chunk;
     n_slices = (M + slice_len - 1) / slice_len;
-    bmd_status st = ensure(&p->d_ws, &p->ws_cap, grad_workspace_bytes(p, prec, B, static_cast<int>(n_slices)));
+    bmd_status st =
+        ensure(&p->d_ws, &p->ws_cap, grad_workspace_bytes(p, prec, B, static_cast<int>(n_slices), M, slice_len));
     if (st != BMD_OK) return st;
     HIP_TRY(launch_grad(p, prec, d_q, B, M, p->d_ws, static_cast<int>(n_slices), slice_len, d_obj, d_grad_q,
                         d_grad_mu, s),

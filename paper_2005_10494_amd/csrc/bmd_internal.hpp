@@ -17,6 +17,7 @@ constexpr int kGLTable = 200;        // packed Gauss-Legendre rules n = 4..24
 constexpr int kEvalBlock = 256;      // designs per workgroup in the eval kernels
 constexpr int kSweepRounds = 8;      // rounds of resident workgroups a grid sweep is sliced into
 constexpr size_t kBatchBudget = size_t(16) << 30;   // draw bytes one batch group may hold
+constexpr size_t kGradDrawBudget = size_t(4) << 30; // draw bytes one gradient pass may hold
 
 // Problem constants passed by value to every kernel.
 struct DevProblem {
@@ -156,8 +157,9 @@ hipError_t launch_smooth(const bmd_problem* p, int prec, const double* in, doubl
                          double* tmp, hipStream_t s);
 hipError_t launch_argmax(const bmd_problem* p, const double* v, int64_t n, double* part_v,
                          int64_t* part_i, int n_part, hipStream_t s);
-size_t grad_workspace_bytes(const bmd_problem* p, int prec, int64_t B, int n_slices);
+size_t grad_workspace_bytes(const bmd_problem* p, int prec, int64_t B, int n_slices, int64_t M, int64_t slice_len);
 int grad_chunk(int prec, int d, int K);
+int grad_blocks_per_cu(const bmd_problem* p, int prec);   // resident gradient workgroups per CU
 hipError_t launch_grad(const bmd_problem* p, int prec, const double* d_q, int64_t B, int64_t M, void* ws,
                        int n_slices, int64_t slice_len, double* obj, double* gq, double* gmu, hipStream_t s);
 // Batched form.  Sweep records are filled on the host (batch_record_bytes

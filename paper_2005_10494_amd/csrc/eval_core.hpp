@@ -1,5 +1,5 @@
-// One summand of the Formula 5 estimate for a grid design and a prior draw,
-// shared by the single-problem sweep and the batched persistent kernel.
+// One summand of the Formula 5 estimate for a grid design and a prior draw
+// (the direct sweep body; the matrix-core body uses its pieces).
 //
 //   1 - Phi_2(z1 - mu1_k, z2 - mu2_gk; sqrt r_g)
 //   step prior:  mu1 = sqrt(I) (b0 + b1 P(R)),  mu2 = sqrt(r I) (b0 + b1 O / r),
@@ -8,7 +8,6 @@
 #pragma once
 #include "bmd_internal.hpp"
 #include "device_math.hpp"
-#include "draw_chunk.hpp"
 
 namespace bmd {
 
@@ -38,23 +37,6 @@ struct GlobalDraws {
     __device__ int thr(int j, int64_t k) const { return D.thr[j * D.M + k]; }
     __device__ double tau(int j, int64_t k) const { return D.tau[j * D.M + k]; }
     __device__ const T* B(int64_t k) const { return D.B + k * d * D.K; }
-};
-
-// Draws regenerated into an LDS chunk (index k local to the chunk).
-template <typename T>
-struct ChunkDraws {
-    ChunkView<T> c;
-    int d, K;
-    __device__ T b0(int64_t k) const { return c.b0[k]; }
-    __device__ T b1(int64_t k) const { return c.b1[k]; }
-    __device__ T mu1(int64_t k) const { return c.mu1[k]; }
-    __device__ T PR(int64_t k) const { return c.PR[k]; }
-    __device__ T tauT(int64_t k) const { return c.tauT[k]; }
-    __device__ T e1(int64_t k) const { return c.e1[k]; }
-    __device__ T e2(int64_t k) const { return c.e2[k]; }
-    __device__ int thr(int j, int64_t k) const { return c.thr[k * kMaxDim + j]; }
-    __device__ double tau(int j, int64_t k) const { return c.tau[k * kMaxDim + j]; }
-    __device__ const T* B(int64_t k) const { return c.Bt + k * d * K; }
 };
 
 // Everything about one grid design that the summand needs, held in registers.

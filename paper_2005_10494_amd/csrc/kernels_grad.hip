@@ -1,6 +1,7 @@
 // Objective and gradient at continuous design points (the differentiation
-// form): d obj / d q_j and d obj / d (mu_b0, mu_b1), averaged over draws that
-// are regenerated in the kernel from their Philox counters.
+// form): d obj / d q_j and d obj / d (mu_b0, mu_b1), averaged over the prior
+// draws, which the draw kernel writes to HBM in passes and the gradient kernel
+// stages chunk by chunk in LDS.
 //
 // Per (point, draw) the summand is f = 1 - Phi_2(h, k; rho) with
 //   h = z1 - sqrt(I) (b0 + b1 P(R)),  k = z2 - sqrt(r I) (b0 + b1 O / r),  rho = sqrt(r),
@@ -10,6 +11,8 @@
 // the overlap O (logistic or exact cutoff indicator, leave-one-out products
 // over the Gauss-Hermite nodes), the subgroup fraction r(q) and the equal-FWER
 // critical value z*(r) (implicit derivative of Formula 2).
+#include <algorithm>
+
 #include "bmd_internal.hpp"
 #include "device_math.hpp"
 #include "draw_chunk.hpp"
@@ -137,10 +140,14 @@ __global__ __launch_bounds__(128) void k_grad_points(DevProblem P, const double*
     }
 }
 
-template <typename T>
-__device__ __forceinline__ T lgst(T x) {
-    return T(1) / (T(1) + exp(-x));
+// Logistic 1/(1 + e^-x); FP32 with the hardware exp2 and reciprocal.
+__device__ __forceinline__ double lgst(double x) { return 1.0 / (1.0 + exp(-x)); }
+__device__ __forceinline__ float lgst(float x) {
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634074f * x));
 }
+// e^x; FP32 with the hardware exp2.
+__device__ __forceinline__ double expT(double x) { return exp(x); }
+__device__ __forceinline__ float expT(float x) { return __builtin_amdgcn_exp2f(1.4426950408889634074f * x); }
 
 struct GradArgs {
     DevProblem P;
@@ -151,16 +158,38 @@ struct GradArgs {
     const double* info;
     const void* A;
     const void* dA;
-    const double* gh;      // eval GH rule (FP64): x[K], w[K]
     const double* gl;
     const void* glw;
     int64_t slice_len;
+    int slice0;            // first draw slice of this launch (a pass over draws)
+    int64_t draw_k0;       // first draw held by the draw arrays of this pass
     double* partials;      // [n_slices][d+3][B]
 };
 
+// Copy draws k0 .. k0+nk-1 of a pass (local indices) from the draw arrays into
+// the LDS chunk; every thread of the block calls it.  Ends with the chunk
+// visible to the whole block.
+template <typename T, int D>
+__device__ void stage_chunk(const DrawArrays<T>& G, int K, const ChunkView<T>& c, int64_t k0, int nk) {
+    __syncthreads();   // previous chunk fully consumed
+    for (int e = threadIdx.x; e < nk; e += blockDim.x) {
+        c.b0[e] = G.b0[k0 + e];
+        c.b1[e] = G.b1[k0 + e];
+        c.PR[e] = G.PR[k0 + e];
+        c.mu1[e] = G.mu1[k0 + e];
+#pragma unroll
+        for (int j = 0; j < D; ++j) c.tau[e * kMaxDim + j] = G.tau[j * G.M + k0 + e];
+    }
+    if constexpr (D >= 2) {
+        const T* src = G.B + k0 * D * K;   // B rows of consecutive draws are contiguous
+        for (int e = threadIdx.x; e < nk * D * K; e += blockDim.x) c.Bt[e] = src[e];
+    }
+    __syncthreads();
+}
+
 // R draws per pass over the point's node tables.
 template <typename T, int D, int NMAX, int R>
-__global__ __launch_bounds__(kGradBlock) void k_grad(GradArgs a) {
+__global__ __launch_bounds__(kGradBlock) void k_grad(GradArgs a, DrawArrays<T> Dr) {
     extern __shared__ __align__(16) char lds[];
     const ChunkView<T> ch = carve_chunk<T>(lds, a.chunk, a.K);
     const DevProblem& P = a.P;
@@ -204,17 +233,19 @@ __global__ __launch_bounds__(kGradBlock) void k_grad(GradArgs a) {
     }
     const T vv = static_cast<T>(P.sqrtI / sqr);
     const bool logistic = P.width > 0.0;
-    const T iw = logistic ? static_cast<T>(1.0 / P.width) : T(0);
+    const double iw64 = logistic ? 1.0 / P.width : 0.0;
+    const T iw = static_cast<T>(iw64);
 
     double s_obj = 0.0, s_mu0 = 0.0, s_mu1 = 0.0, s_q[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) s_q[j] = 0.0;
 
-    const int64_t kb = static_cast<int64_t>(blockIdx.y) * a.slice_len;
+    const int slice = a.slice0 + static_cast<int>(blockIdx.y);
+    const int64_t kb = static_cast<int64_t>(slice) * a.slice_len;
     const int64_t ke = min(a.M, kb + a.slice_len);
     for (int64_t k0 = kb; k0 < ke; k0 += a.chunk) {
         const int nk = static_cast<int>(min<int64_t>(a.chunk, ke - k0));
-        regenerate_chunk<T, D>(P, a.gh, K, ch, k0, nk);
+        stage_chunk<T, D>(Dr, K, ch, k0 - a.draw_k0, nk);
         for (int i0 = 0; i0 < nk; i0 += R) {
             T O[R], dO[R][D], s[R][D], sp[R][D];
 #pragma unroll
@@ -225,7 +256,7 @@ __global__ __launch_bounds__(kGradBlock) void k_grad(GradArgs a) {
                 for (int j = 0; j < D; ++j) {
                     const double dq = qd[j] - ch.tau[i * kMaxDim + j];
                     if (logistic) {
-                        s[rr][j] = lgst(static_cast<T>(dq / P.width));
+                        s[rr][j] = lgst(static_cast<T>(dq * iw64));
                         sp[rr][j] = s[rr][j] * (T(1) - s[rr][j]) * iw;
                     } else {
                         s[rr][j] = dq > 0.0 ? T(1) : T(0);
@@ -261,21 +292,23 @@ __global__ __launch_bounds__(kGradBlock) void k_grad(GradArgs a) {
                     for (int rr = 0; rr < R; ++rr) {
                         const int i = min(i0 + rr, nk - 1);
                         const T* Bi = ch.Bt + static_cast<size_t>(i) * D * K + m;
-                        T mix[D], pre[D + 1];
+                        // mix_j = s_j a_j + (1 - s_j) b_j = b_j + s_j (a_j - b_j);
+                        // d mix_j / d q_j = s'_j (a_j - b_j) + s_j a'_j
+                        T dif[D], mix[D], pre[D + 1];
                         pre[0] = T(1);
 #pragma unroll
                         for (int j = 0; j < D; ++j) {
                             const T bv = Bi[j * K];
-                            mix[j] = s[rr][j] * av[j] + (T(1) - s[rr][j]) * bv;
+                            dif[j] = av[j] - bv;
+                            mix[j] = fma(s[rr][j], dif[j], bv);
                             pre[j + 1] = pre[j] * mix[j];
                         }
                         O[rr] += pre[D];
                         T suf = T(1);
 #pragma unroll
                         for (int j = D - 1; j >= 0; --j) {
-                            const T bv = Bi[j * K];
-                            const T dmix = sp[rr][j] * (av[j] - bv) + s[rr][j] * dav[j];
-                            dO[rr][j] += dmix * pre[j] * suf;
+                            const T dmix = fma(sp[rr][j], dif[j], s[rr][j] * dav[j]);
+                            dO[rr][j] = fma(dmix, pre[j] * suf, dO[rr][j]);
                             suf *= mix[j];
                         }
                     }
@@ -294,7 +327,7 @@ __global__ __launch_bounds__(kGradBlock) void k_grad(GradArgs a) {
                     ph = norm_pdf(h) * norm_cdf((kq - rhoT * h) * isig);
                     pk = norm_pdf(kq) * norm_cdf((h - rhoT * kq) * isig);
                     const T e = (h * h - T(2) * rhoT * h * kq + kq * kq) * isig * isig;
-                    pr = exp(-T(0.5) * e) * isig * T(0.15915494309189533577);
+                    pr = expT(-T(0.5) * e) * isig * T(0.15915494309189533577);
                 } else if (P.zinf == 2) {
                     p = norm_cdf(h); ph = norm_pdf(h); pk = T(0); pr = T(0);
                 } else if (P.zinf == 1) {
@@ -315,7 +348,7 @@ __global__ __launch_bounds__(kGradBlock) void k_grad(GradArgs a) {
         }
     }
     if (active) {
-        double* out = a.partials + static_cast<int64_t>(blockIdx.y) * (D + 3) * Bn;
+        double* out = a.partials + static_cast<int64_t>(slice) * (D + 3) * Bn;
         out[b] = s_obj;
 #pragma unroll
         for (int j = 0; j < D; ++j) out[(1 + j) * Bn + b] = s_q[j];
@@ -342,28 +375,71 @@ __global__ void k_grad_finalize(int d, int64_t B, int64_t M, int n_slices, const
 }
 
 template <typename T, int NMAX, int R>
-hipError_t launch_grad_typed(const GradArgs& ga, int d, int n_slices, hipStream_t s) {
+hipError_t launch_grad_typed(const GradArgs& ga, const DrawArrays<T>& Dr, int d, int n_slices, hipStream_t s) {
     const dim3 grid(static_cast<unsigned>((ga.B + kGradBlock - 1) / kGradBlock), static_cast<unsigned>(n_slices));
     const size_t lds = chunk_bytes<T>(ga.chunk, d, ga.K);
     switch (d) {
-        case 1: hipLaunchKernelGGL((k_grad<T, 1, NMAX, 1>), grid, dim3(kGradBlock), lds, s, ga); break;
-        case 2: hipLaunchKernelGGL((k_grad<T, 2, NMAX, R>), grid, dim3(kGradBlock), lds, s, ga); break;
-        case 3: hipLaunchKernelGGL((k_grad<T, 3, NMAX, R>), grid, dim3(kGradBlock), lds, s, ga); break;
-        case 4: hipLaunchKernelGGL((k_grad<T, 4, NMAX, R>), grid, dim3(kGradBlock), lds, s, ga); break;
-        case 5: hipLaunchKernelGGL((k_grad<T, 5, NMAX, R>), grid, dim3(kGradBlock), lds, s, ga); break;
-        default: hipLaunchKernelGGL((k_grad<T, 6, NMAX, R>), grid, dim3(kGradBlock), lds, s, ga); break;
+        case 1: hipLaunchKernelGGL((k_grad<T, 1, NMAX, 1>), grid, dim3(kGradBlock), lds, s, ga, Dr); break;
+        case 2: hipLaunchKernelGGL((k_grad<T, 2, NMAX, R>), grid, dim3(kGradBlock), lds, s, ga, Dr); break;
+        case 3: hipLaunchKernelGGL((k_grad<T, 3, NMAX, R>), grid, dim3(kGradBlock), lds, s, ga, Dr); break;
+        case 4: hipLaunchKernelGGL((k_grad<T, 4, NMAX, R>), grid, dim3(kGradBlock), lds, s, ga, Dr); break;
+        case 5: hipLaunchKernelGGL((k_grad<T, 5, NMAX, R>), grid, dim3(kGradBlock), lds, s, ga, Dr); break;
+        default: hipLaunchKernelGGL((k_grad<T, 6, NMAX, R>), grid, dim3(kGradBlock), lds, s, ga, Dr); break;
     }
     return hipGetLastError();
 }
 
 }  // namespace
 
-size_t grad_workspace_bytes(const bmd_problem* p, int prec, int64_t B, int n_slices) {
+// Draws held in HBM per pass: whole slices, at most kGradDrawBudget bytes.
+int64_t grad_pass_draws(const bmd_problem* p, int prec, int64_t M, int64_t slice_len) {
+    const double per = static_cast<double>(draw_workspace_bytes(p, prec, 1 << 20)) / (1 << 20);
+    int64_t slices = static_cast<int64_t>(static_cast<double>(kGradDrawBudget) / (per * slice_len));
+    slices = std::max<int64_t>(1, slices);
+    return std::min<int64_t>(M, slices * slice_len);
+}
+
+size_t grad_workspace_bytes(const bmd_problem* p, int prec, int64_t B, int n_slices, int64_t M, int64_t slice_len) {
     const size_t T = prec == BMD_FP64 ? 8 : 4;
     const int d = p->P.d, K = p->tab[prec].K;
     auto al = [](size_t x) { return (x + 255) / 256 * 256; };
     return al(sizeof(double) * kPointFields * B) + 2 * al(T * d * K * B) +
-           al(sizeof(double) * (d + 3) * B * n_slices);
+           al(sizeof(double) * (d + 3) * B * n_slices) +
+           al(draw_workspace_bytes(p, prec, grad_pass_draws(p, prec, M, slice_len)));
+}
+
+int grad_blocks_per_cu(const bmd_problem* p, int prec) {
+    const int d = p->P.d, K = p->tab[prec].K;
+    const int C = grad_chunk(prec, d, K);
+    const void* f = nullptr;
+    size_t lds = 0;
+    if (prec == BMD_FP64) {
+        lds = chunk_bytes<double>(C, d, K);
+        switch (d) {
+            case 1: f = reinterpret_cast<const void*>(k_grad<double, 1, 24, 1>); break;
+            case 2: f = reinterpret_cast<const void*>(k_grad<double, 2, 24, 1>); break;
+            case 3: f = reinterpret_cast<const void*>(k_grad<double, 3, 24, 1>); break;
+            case 4: f = reinterpret_cast<const void*>(k_grad<double, 4, 24, 1>); break;
+            case 5: f = reinterpret_cast<const void*>(k_grad<double, 5, 24, 1>); break;
+            default: f = reinterpret_cast<const void*>(k_grad<double, 6, 24, 1>); break;
+        }
+    } else {
+        lds = chunk_bytes<float>(C, d, K);
+        switch (d) {
+            case 1: f = reinterpret_cast<const void*>(k_grad<float, 1, 12, 1>); break;
+            case 2: f = reinterpret_cast<const void*>(k_grad<float, 2, 12, 2>); break;
+            case 3: f = reinterpret_cast<const void*>(k_grad<float, 3, 12, 2>); break;
+            case 4: f = reinterpret_cast<const void*>(k_grad<float, 4, 12, 2>); break;
+            case 5: f = reinterpret_cast<const void*>(k_grad<float, 5, 12, 2>); break;
+            default: f = reinterpret_cast<const void*>(k_grad<float, 6, 12, 2>); break;
+        }
+    }
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kGradBlock, lds) != hipSuccess || nb < 1) {
+        (void)hipGetLastError();
+        nb = 1;
+    }
+    return nb;
 }
 
 // Draws per LDS chunk: as many as fit in 48 KB, at most 32.
@@ -387,6 +463,8 @@ hipError_t launch_grad(const bmd_problem* p, int prec, const double* d_q, int64_
     void* dA = c;
     c += al(T * d * K * B);
     double* part = reinterpret_cast<double*>(c);
+    c += al(sizeof(double) * (d + 3) * B * n_slices);
+    void* dws = c;
     const unsigned pb = static_cast<unsigned>((B + 127) / 128);
     if (prec == BMD_FP64)
         hipLaunchKernelGGL(k_grad_points<double>, dim3(pb), dim3(128), 0, s, p->P, d_q, B, p->d_ghp, kPrecomputeGH,
@@ -396,11 +474,20 @@ hipError_t launch_grad(const bmd_problem* p, int prec, const double* d_q, int64_
                            p->tab[prec].gh, K, p->d_gl, info, static_cast<float*>(A), static_cast<float*>(dA));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    GradArgs ga{p->P, B, M, K, grad_chunk(prec, d, K), info, A, dA, p->tab[prec].gh, p->d_gl, p->tab[prec].glw,
-                slice_len, part};
-    e = prec == BMD_FP64 ? launch_grad_typed<double, 24, 1>(ga, d, n_slices, s)
-                         : launch_grad_typed<float, 12, 2>(ga, d, n_slices, s);
-    if (e != hipSuccess) return e;
+    // Passes over the draws: generate a pass into HBM, then the slices it holds.
+    const int64_t pass = grad_pass_draws(p, prec, M, slice_len);
+    for (int64_t k0 = 0; k0 < M; k0 += pass) {
+        const int64_t np = std::min<int64_t>(pass, M - k0);
+        e = launch_draws(p, prec, static_cast<uint64_t>(k0), np, dws, s);
+        if (e != hipSuccess) return e;
+        const int slice0 = static_cast<int>(k0 / slice_len);
+        const int ns = static_cast<int>((np + slice_len - 1) / slice_len);
+        GradArgs ga{p->P, B, M, K, grad_chunk(prec, d, K), info, A, dA, p->d_gl, p->tab[prec].glw,
+                    slice_len, slice0, k0, part};
+        e = prec == BMD_FP64 ? launch_grad_typed<double, 24, 1>(ga, draws_fp64_at(p, np, dws), d, ns, s)
+                             : launch_grad_typed<float, 12, 2>(ga, draws_fp32_at(p, np, dws), d, ns, s);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_grad_finalize, dim3(pb), dim3(128), 0, s, d, B, M, n_slices, part, info, obj, gq, gmu);
     return hipGetLastError();
 }

@@ -53,8 +53,9 @@ def source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(summary: str, kernel: str):
-    """HBM bytes per launch of `kernel` from a committed counter summary, or None
+def measured_counters(summary: str, kernel: str):
+    """Counter figures of `kernel` from a committed counter summary: HBM bytes
+    per launch (fetch + write), VALU issue fill and rocprofv3's VALUBusy; None
     when the summary is missing or was taken on other sources."""
     path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
@@ -63,8 +64,12 @@ def measured_traffic(summary: str, kernel: str):
     m = re.search(r"source digest: `([0-9a-f]{64})`", text)
     if not m or m.group(1) != source_digest():
         return None
-    row = re.search(r"\| `%s` \| ([0-9.e+]+) \| ([0-9.e+]+) \|" % re.escape(kernel), text)
-    return None if row is None else float(row.group(1)) + float(row.group(2))
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 9 and cells[0] == f"`{kernel}`":
+            return {"traffic": float(cells[1]) + float(cells[2]), "valu_issue_fill": float(cells[6]),
+                    "valu_busy_pct": float(cells[7])}
+    return None
 
 
 def workload(name: str) -> dict:
@@ -232,11 +237,15 @@ def main():
     flops32 = algorithmic_flops(spec, r, tau, "fp32", _gh_nodes(p32, "fp32"))
     achieved = flops32 / (sweep32 * 1e-3) / 1e12
     kind = bmd.sweep_kind(p32)
-    traffic = measured_traffic(f"k_eval_mfma_{d}d_{spec['m'][0]}cube_M{M // 1000}k_traffic.md",
-                               f"k_eval_{'mfma' if kind == 'matrix' else 'direct'}<float, {d}, 12>")
+    summary = f"k_eval_mfma_{d}d_{spec['m'][0]}cube_M{M // 1000}k_counters.md"
+    kname = "k_eval_" + ("mfma" if kind == "matrix" else "direct") + "<%s, " + str(d) + ", %d>"
+    cnt32 = measured_counters(summary, kname % ("float", 12)) or {}
+    cnt64 = measured_counters(summary, kname % ("double", 24)) or {}
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                       "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                       "frac": achieved / PEAK_FP32_TFLOPS, "traffic": cnt32.get("traffic"),
                        "traffic_unit": "bytes per launch (HBM, counter-measured)",
+                       "valu_issue_fill": cnt32.get("valu_issue_fill"),
+                       "valu_busy_pct": cnt32.get("valu_busy_pct"),
                        "kernel": SWEEP_KERNEL[kind] % d,
                        "sweep_ms": sweep32, "flops_per_launch": flops32,
                        "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
@@ -251,7 +260,8 @@ def main():
         s32, s64 = res32["smooth"], res64["smooth"]
         out["fp64"] = {"value": evals * args.steps / t64, "ms_per_step": 1e3 * t64 / args.steps,
                        "sweep_ms": sweep64, "achieved_tflops": flops64 / (sweep64 * 1e-3) / 1e12,
-                       "frac_of_fp64_peak": flops64 / (sweep64 * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
+                       "frac_of_fp64_peak": flops64 / (sweep64 * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                       "valu_issue_fill": cnt64.get("valu_issue_fill"), "valu_busy_pct": cnt64.get("valu_busy_pct")}
         out["fp32_vs_fp64"] = {
             "speedup_step": (evals * args.steps / t32) / (evals * args.steps / t64),
             "speedup_sweep": sweep64 / sweep32,

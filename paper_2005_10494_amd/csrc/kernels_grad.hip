@@ -12,6 +12,7 @@
 // over the Gauss-Hermite nodes), the subgroup fraction r(q) and the equal-FWER
 // critical value z*(r) (implicit derivative of Formula 2).
 #include <algorithm>
+#include <cstdlib>
 
 #include "bmd_internal.hpp"
 #include "device_math.hpp"
@@ -391,10 +392,16 @@ hipError_t launch_grad_typed(const GradArgs& ga, const DrawArrays<T>& Dr, int d,
 
 }  // namespace
 
-// Draws held in HBM per pass: whole slices, at most kGradDrawBudget bytes.
+// Draws held in HBM per pass: whole slices, at most kGradDrawBudget bytes
+// (BMD_GRAD_BUDGET, in bytes, overrides it; small values force many passes).
 int64_t grad_pass_draws(const bmd_problem* p, int prec, int64_t M, int64_t slice_len) {
+    size_t budget = kGradDrawBudget;
+    if (const char* env = std::getenv("BMD_GRAD_BUDGET")) {
+        const long long v = std::atoll(env);
+        if (v > 0) budget = static_cast<size_t>(v);
+    }
     const double per = static_cast<double>(draw_workspace_bytes(p, prec, 1 << 20)) / (1 << 20);
-    int64_t slices = static_cast<int64_t>(static_cast<double>(kGradDrawBudget) / (per * slice_len));
+    int64_t slices = static_cast<int64_t>(static_cast<double>(budget) / (per * slice_len));
     slices = std::max<int64_t>(1, slices);
     return std::min<int64_t>(M, slices * slice_len);
 }

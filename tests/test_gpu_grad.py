@@ -116,3 +116,19 @@ def test_differentiation_config_full_size():
     obj, gq, gmu = gpu_grad(spec, q[:2], 20000, "fp64")
     assert rel_err(obj, o_obj, 1e-3) <= 1e-9
     assert rel_err(gq, o_gq, 1e-2) <= 1e-7
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_grad_draw_passes_are_exact(prec, monkeypatch):
+    """Draws held in HBM in several passes (a tiny budget) give bit-identical
+    sums: the slices and their draws do not change, only when they are made."""
+    spec = W.base_problem(3, None, 0.3, 0.03, width=0.01)
+    q = torch.tensor(W.design_points(200, 3, seed=5), dtype=torch.float64, device="cuda")
+    with bmd.Problem(spec) as p:
+        one = p.grad_design(q, 5000, prec)
+        monkeypatch.setenv("BMD_GRAD_BUDGET", "1")
+        many = p.grad_design(q, 5000, prec)
+        monkeypatch.delenv("BMD_GRAD_BUDGET")
+    for a, b in zip(one, many):
+        assert torch.equal(a, b)
+

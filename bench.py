@@ -37,18 +37,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_digest() -> str:
-    """SHA-256 over the HIP sources and the C header (the code a counter run measured)."""
+def source_digest(unit: str = "kernels_eval.hip") -> str:
+    """SHA-256 over the sources a kernel is built from: the translation unit
+    `unit` under csrc/, every header it includes (transitively, local
+    includes), and the build script with its compiler flags."""
     import hashlib
+    csrc = os.path.join(ROOT, "paper_2005_10494_amd", "csrc")
+    inc = os.path.join(ROOT, "include")
+    seen, todo = [], [os.path.join(csrc, unit)]
+    while todo:
+        path = todo.pop()
+        if path in seen or not os.path.exists(path):
+            continue
+        seen.append(path)
+        for line in open(path):
+            m = re.match(r'\s*#\s*include\s+"([^"]+)"', line)
+            if m:
+                for base in (os.path.dirname(path), csrc, inc):
+                    cand = os.path.join(base, m.group(1))
+                    if os.path.exists(cand):
+                        todo.append(cand)
+                        break
+    seen.append(os.path.join(ROOT, "paper_2005_10494_amd", "build.py"))
     h = hashlib.sha256()
-    files = []
-    for sub in ("include", os.path.join("paper_2005_10494_amd", "csrc")):
-        base = os.path.join(ROOT, sub)
-        files += [os.path.join(sub, f) for f in sorted(os.listdir(base))
-                  if f.endswith((".hip", ".hpp", ".h", ".cpp"))]
-    for rel in sorted(files):
-        h.update(rel.encode())
-        with open(os.path.join(ROOT, rel), "rb") as fh:
+    for path in sorted(seen):
+        h.update(os.path.relpath(path, ROOT).encode())
+        with open(path, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 

@@ -38,9 +38,10 @@ def log(*a):
 
 
 def source_digest(unit: str = "kernels_eval.hip") -> str:
-    """SHA-256 over the sources a kernel is built from: the translation unit
-    `unit` under csrc/, every header it includes (transitively, local
-    includes), and the build script with its compiler flags."""
+    """SHA-256 over the code a kernel is built from: the translation unit
+    `unit` under csrc/ and every header it includes (transitively, local
+    includes), comments and layout removed, plus the build script with its
+    compiler flags."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2005_10494_amd", "csrc")
     inc = os.path.join(ROOT, "include")
@@ -62,8 +63,12 @@ def source_digest(unit: str = "kernels_eval.hip") -> str:
     h = hashlib.sha256()
     for path in sorted(seen):
         h.update(os.path.relpath(path, ROOT).encode())
-        with open(path, "rb") as fh:
-            h.update(fh.read())
+        text = open(path).read()
+        if not path.endswith(".py"):   # code only: comments and layout do not reach the code object
+            text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", " ", text)
+            text = " ".join(text.split())
+        h.update(text.encode())
     return h.hexdigest()
 
 

@@ -175,16 +175,29 @@ bmd_status bmd_argmax(bmd_problem *p, const double *d_surface, int64_t *h_index,
  *   d_obj     [B]   FP64 Monte Carlo objective (as bmd_eval_grid's mean)
  *   d_grad_q  [B*d] d obj_b / d q_b,j (may be NULL)
  *   d_grad_mu [B*2] d obj_b / d (mu_b0, mu_b1) (may be NULL)
- * Draws are regenerated from their Philox counters, never stored.  Works on
- * grid and continuous problems; requires BMD_EFFECT_STEP (ENOTSUP otherwise). */
+ * Draws are generated into the problem's workspace in passes of at most 4 GB
+ * (environment variable BMD_GRAD_BUDGET, in bytes, overrides the limit) and
+ * read by every point; results do not depend on the pass size.  Works on grid
+ * and continuous problems; requires BMD_EFFECT_STEP (ENOTSUP otherwise). */
 bmd_status bmd_grad_design(bmd_problem *p, const double *d_q, int64_t B, uint64_t n_draws,
                            int32_t prec, double *d_obj, double *d_grad_q, double *d_grad_mu,
                            void *stream);
 
-/* Batched evaluation of n independent grid problems in one persistent launch:
- * d_means[i] receives problem i's FP64 mean surface for n_draws[i] draws.
- * h_wall_ms (may be NULL) receives each problem's completion time in ms after
- * the launch started, measured on the device.  Synchronises `stream`. */
+/* Batched evaluation of n independent grid problems (the families of design
+ * problems of Sec. 3) in one call: d_means[i] (FP64, [G_i], device) receives
+ * problem i's mean surface for n_draws[i] draws, equal to bmd_eval_grid's up to
+ * the order of the FP64 slice sums.  All problems must live on one device.
+ * Problems are taken in order in groups whose draws fit half the free device
+ * memory, at most 16 GB (environment variable BMD_BATCH_BUDGET, in bytes,
+ * overrides the limit); each group is one captured HIP graph: draws of every
+ * problem, one sweep launch per (biomarker count, kernel kind) over a list of
+ * (problem, design tile, draw slice) items, finalize.  The call allocates and
+ * frees its workspace.  h_wall_ms (may be NULL, [n], host) receives each
+ * problem's completion time in ms after the first workgroup of the call
+ * started, from the device clock.  Synchronises `stream`.  EINVAL for NULL
+ * arguments or problems on different devices, ESTATE for continuous problems,
+ * ERANGE for n outside [1, 65536] or n_draws outside [1, 2^40], ENOMEM if a
+ * group's workspace cannot be allocated. */
 bmd_status bmd_eval_batch(bmd_problem *const *ps, int32_t n, const uint64_t *n_draws,
                           int32_t prec, double *const *d_means, double *h_wall_ms,
                           void *stream);

@@ -117,6 +117,30 @@ def test_batch_matches_oracle_sampled():
             p.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_full_size_scenarios_sampled(prec):
+    """Eight problems of the 256-problem batch at full size (grids up to 10^6
+    designs, M up to 43,281), sampled designs against the oracle."""
+    full = W.batch_scenarios()
+    pick = [2, 3, 5, 9, 12, 16, 17, 36]
+    sc = [full[i] for i in pick]
+    probs = [bmd.Problem(s) for s in sc]
+    try:
+        means, _ = bmd.eval_batch(probs, [s["n_draws"] for s in sc], prec)
+        rng = np.random.default_rng(1)
+        for p, s, m in zip(probs, sc, means):
+            G = p.G
+            gs = np.unique(np.concatenate([[0, G - 1], rng.integers(0, G, 2)]))
+            say(f"oracle check d={s['d']} G={G} M={s['n_draws']} {prec}")
+            ref, _ = O.eval_grid(s, gs, s["n_draws"])
+            got = m.cpu().numpy()[gs]
+            tol = 1e-9 if prec == "fp64" else 1e-5
+            assert np.all(np.abs(got - ref) <= tol * np.maximum(np.abs(ref), 1e-3)), (s["d"], got, ref)
+    finally:
+        for p in probs:
+            p.close()
+
+
 def test_batch_single_and_invalid():
     spec = W.base_problem(2, [9, 11], 0.3, 0.05)
     with bmd.Problem(spec) as p:

@@ -266,6 +266,28 @@ def test_full_3d_config_fp64_sampled():
     _sampled_full(spec, "fp64", n_sample=3, M=spec["n_draws"])
 
 
+def test_full_3d_config_fp32_as_benchmarked():
+    """The benchmarked launch (3-D 64^3, M = 1e5, FP32 integrand): sampled
+    designs against the oracle, the whole surface against the FP64 path within
+    1e-5, and the FP32 argmax inside the near-tie set of the FP64 smoothed
+    surface."""
+    spec = W.plain_3d()
+    m32, s32, i32 = _sampled_full(spec, "fp32", n_sample=3)
+    with bmd.Problem(spec) as p:
+        m64 = p.eval_grid(spec["n_draws"], "fp64")
+        s64 = p.smooth(m64, "fp64").cpu().numpy()
+        m64 = m64.cpu().numpy()
+    assert np.max(np.abs(m32 - m64)) <= 1e-5
+    assert np.max(np.abs(s32 - s64) / np.maximum(np.abs(s64), 1e-3)) <= 1e-5
+    assert s64[i32] >= s64.max() - 2e-5
+
+
+def test_full_5d_config_fp32_sampled():
+    """Precision form, 5-D: 24^5 designs, M = 2e5 draws, FP32 integrand."""
+    spec = W.precision_5d()
+    _sampled_full(spec, "fp32", n_sample=2)
+
+
 @pytest.mark.parametrize("shape,rho", [((9, 7), 0.3), ((17, 6, 33), 0.3), ((3, 5, 3, 4, 3), 0.45), ((2, 3, 2, 3, 2, 3), 0.5)])
 def test_direct_and_matrix_core_sweeps_agree(shape, rho, monkeypatch):
     spec = W.base_problem(len(shape), list(shape), rho, 0.05)

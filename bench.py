@@ -110,7 +110,7 @@ def bvn_nodes(rho: np.ndarray, prec: str) -> np.ndarray:
     if prec == "fp64":
         edges, counts = [0.3, 0.5, 0.75, 0.9, 0.95], [6, 8, 12, 16, 20, 24]
     else:
-        edges, counts = [0.5, 0.75, 0.9, 0.95], [4, 6, 8, 10, 12]
+        edges, counts = [0.58, 0.8, 0.91, 0.95], [4, 6, 8, 10, 12]
     return np.asarray(counts)[np.searchsorted(edges, rho, side="right")]
 
 

@@ -54,7 +54,7 @@ struct DrawArrays {
     T* e2;      // [M]
     int32_t* thr;   // [d][M] first grid index whose cutoff quantile exceeds tau_j
     double* tau;    // [d][M]
-    T* B;       // [M][d][K] Phi((sqrt(rho) x_m - t_j)/sqrt(1-rho)), GH weight folded into j = 0
+    T* B;       // [M][K][d] Phi((sqrt(rho) x_m - t_j)/sqrt(1-rho)), GH weight folded into j = 0
     int64_t M;
     int K;
 };

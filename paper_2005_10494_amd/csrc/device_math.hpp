@@ -85,22 +85,21 @@ __device__ __forceinline__ double affine_uniform(double lo, double hi, double u)
 // Univariate normal
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double norm_cdf(double x) { return 0.5 * erfc(-x * 0.70710678118654752440); }
-// Single precision: Phi(-|x|) = r 2^(P(v) - log2(e) z^2) with z = |x|/sqrt(2),
-// r = 1/(2+z) (the hardware reciprocal, within one ulp), v = z r and P the
-// fitted polynomial of normal_cdf_fit.hpp (max abs error 1.3e-7, unbiased);
-// one reciprocal, one exp2 and about twenty full-rate operations.  x must be
-// finite: beyond |x| = 14.8 the exponent underflows and Phi saturates to 0 or 1.
+// Single precision: Phi(-|x|) = r' 2^(c_0 + P(v) - y^2) with y = |x| sqrt(log2(e)/2),
+// r' = 1/(y + 2 sqrt(log2 e)) (the hardware reciprocal, within one ulp) and
+// v = y r' = z/(2+z), z = |x|/sqrt 2; P and c_0 from normal_cdf_fit.hpp (max abs
+// error 1.6e-7, unbiased), signed as 1/2 + copysign(1/2 - Phi(-|x|), x).  One
+// reciprocal, one exp2 and sixteen full-rate operations.  x must be finite: beyond |x| = 14.8 the exponent underflows and
+// Phi saturates to 0 or 1.
 __device__ __forceinline__ float norm_cdf(float x) {
-    const float z = fabsf(x) * 0.70710678118654752440f;
-    const float r = __builtin_amdgcn_rcpf(z + 2.0f);
-    const float v = z * r;
+    const float y = fabsf(x) * kPhiScale;
+    const float r = __builtin_amdgcn_rcpf(y + kPhiShift);
+    const float v = y * r;
     float p = kPhiFit[kPhiFitDeg];
 #pragma unroll
-    for (int i = kPhiFitDeg - 1; i >= 1; --i) p = fmaf(p, v, kPhiFit[i]);
-    p *= v;
-    const float e = fmaf(-(z * 1.4426950408889634074f), z, p);
-    const float q = r * __builtin_amdgcn_exp2f(e);
-    return x > 0.0f ? 1.0f - q : q;
+    for (int i = kPhiFitDeg - 1; i >= 0; --i) p = fmaf(p, v, kPhiFit[i]);
+    const float t = fmaf(-r, __builtin_amdgcn_exp2f(fmaf(-y, y, p)), 0.5f);   // 1/2 - Phi(-|x|)
+    return 0.5f + __builtin_copysignf(t, x);
 }
 __device__ __forceinline__ double norm_pdf(double x) { return 0.39894228040143267794 * exp(-0.5 * x * x); }
 __device__ __forceinline__ float norm_pdf(float x) {
@@ -126,19 +125,20 @@ __device__ __forceinline__ double norm_quantile(double p) {
 // Phi_2(h,k;rho) = Phi(h) Phi(k) + (1/2pi) int_0^{asin rho}
 //                      exp(-(h^2 + k^2 - 2 h k sin t) / (2 cos^2 t)) dt.
 // With Gauss-Legendre nodes x_i on [-1,1], s_i = sin(asin(rho)(1 + x_i)/2):
-//   integrand_i = exp(b_i h k - a_i (h^2 + k^2)/2),  a_i = 1/(1 - s_i^2), b_i = s_i a_i,
+//   integrand_i = exp(b_i h k - a_i (h^2 + k^2)),  a_i = 1/(2 (1 - s_i^2)), b_i = 2 s_i a_i,
 // and the integral is asin(rho)/(4 pi) sum_i w_i integrand_i.
 // The per-design constants (a_i, b_i, scale) live in registers; the weights w_i
 // belong to the n-point rule shared by the wavefront.
 // ---------------------------------------------------------------------------
 
-// Number of Gauss-Legendre nodes for a target accuracy at correlation rho
-// (max abs error over h, k in [-6, 4]: <= 1e-14 for FP64, <= 2e-8 for FP32).
+// Number of Gauss-Legendre nodes for a target accuracy at correlation rho:
+// max abs error of the integral <= 1e-14 for FP64 (h, k in [-6, 4]) and
+// <= 2e-8 for FP32 (h, k in [-8, 5]), up to rho = 0.975.
 __device__ __forceinline__ int bvn_nodes_fp64(double rho) {
     return rho < 0.3 ? 6 : rho < 0.5 ? 8 : rho < 0.75 ? 12 : rho < 0.9 ? 16 : rho < 0.95 ? 20 : 24;
 }
 __device__ __forceinline__ int bvn_nodes_fp32(double rho) {
-    return rho < 0.5 ? 4 : rho < 0.75 ? 6 : rho < 0.9 ? 8 : rho < 0.95 ? 10 : 12;
+    return rho < 0.58 ? 4 : rho < 0.8 ? 6 : rho < 0.91 ? 8 : rho < 0.95 ? 10 : 12;
 }
 
 // Offsets of the n-point rules inside the packed Gauss-Legendre table
@@ -166,7 +166,7 @@ struct BvnConst {
             if (i < n) {
                 const double s = sin(0.5 * th * (1.0 + x[i]));
                 const double ai = 1.0 / ((1.0 - s) * (1.0 + s));
-                a[i] = static_cast<T>(L * ai);
+                a[i] = static_cast<T>(0.5 * L * ai);
                 b[i] = static_cast<T>(L * s * ai);
             } else {
                 a[i] = T(0);
@@ -206,11 +206,11 @@ __device__ __forceinline__ T bvn_node_sum(int n, T hk, T hs, const BvnConst<T, N
     return acc0 + acc1;
 }
 
-// FP64: Phi(h) Phi(k) + asin(rho)/(4 pi) sum_i w_i exp(b_i hk - a_i hs)
+// FP64: Phi(h) Phi(k) + asin(rho)/(4 pi) sum_i w_i exp(b_i hk - a_i hs), hs = h^2 + k^2
 template <int NMAX>
 __device__ __forceinline__ double bvn_cdf(double h, double k, const BvnConst<double, NMAX>& c,
                                           const double* __restrict__ w, int n) {
-    const double hk = h * k, hs = 0.5 * (h * h + k * k);
+    const double hk = h * k, hs = fma(h, h, k * k);
     return norm_cdf(h) * norm_cdf(k) + c.scale * bvn_node_sum(n, hk, hs, c, w);
 }
 
@@ -229,8 +229,22 @@ struct BvnWeights {
 
 template <int NMAX, typename W>
 __device__ __forceinline__ float bvn_cdf(float h, float k, const BvnConst<float, NMAX>& c, const W& w, int n) {
-    const float hk = h * k, hs = 0.5f * (h * h + k * k);
+    const float hk = h * k, hs = fmaf(h, h, k * k);
     return fmaf(norm_cdf(h), norm_cdf(k), c.scale * bvn_node_sum(n, hk, hs, c, w));
+}
+
+// Upper complement 1 - Phi_2(h, k; rho) = (1 - scale S) - Phi(h) Phi(k), S the
+// node sum: two fused multiply-adds.
+template <int NMAX>
+__device__ __forceinline__ double bvn_sf(double h, double k, const BvnConst<double, NMAX>& c,
+                                         const double* __restrict__ w, int n) {
+    const double hk = h * k, hs = fma(h, h, k * k);
+    return fma(-norm_cdf(h), norm_cdf(k), fma(-c.scale, bvn_node_sum(n, hk, hs, c, w), 1.0));
+}
+template <int NMAX, typename W>
+__device__ __forceinline__ float bvn_sf(float h, float k, const BvnConst<float, NMAX>& c, const W& w, int n) {
+    const float hk = h * k, hs = fmaf(h, h, k * k);
+    return fmaf(-norm_cdf(h), norm_cdf(k), fmaf(-c.scale, bvn_node_sum(n, hk, hs, c, w), 1.0f));
 }
 
 // Row of the 16x16 result held in accumulator element v of a lane in quarter

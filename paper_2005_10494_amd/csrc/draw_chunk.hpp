@@ -8,7 +8,7 @@ namespace bmd {
 
 // LDS layout of a chunk of C draws:
 //   FP64:  tau[C][6]
-//   T:     b0[C] b1[C] PR[C] mu1[C] Bt[C][d][K]
+//   T:     b0[C] b1[C] PR[C] mu1[C] Bt[C][K][d]
 template <typename T>
 struct ChunkView {
     double* tau;

@@ -99,7 +99,7 @@ __device__ __forceinline__ T overlap(const DevProblem& P, const DesignState<T, D
 #pragma unroll
             for (int j = 0; j < D; ++j) {
                 const T av = A[(static_cast<int64_t>(j) * K + m) * mmax + s.idx[j]];
-                prod *= sw[j] * av + (T(1) - sw[j]) * Bk[j * K + m];
+                prod *= sw[j] * av + (T(1) - sw[j]) * Bk[m * D + j];
             }
             acc += prod;
         }
@@ -119,8 +119,8 @@ __device__ __forceinline__ T overlap(const DevProblem& P, const DesignState<T, D
     int64_t st[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        p[j] = fl[j] ? A + static_cast<int64_t>(j) * K * mmax + s.idx[j] : Bk + j * K;
-        st[j] = fl[j] ? mmax : 1;
+        p[j] = fl[j] ? A + static_cast<int64_t>(j) * K * mmax + s.idx[j] : Bk + j;
+        st[j] = fl[j] ? mmax : D;
     }
     T acc = T(0);
     for (int m = 0; m < K; ++m) {
@@ -155,12 +155,10 @@ __device__ __forceinline__ T summand(const DevProblem& P, const DesignState<T, D
         mu2 = s.c0 + s.c1 * src.e1(k) + s.c2 * src.e2(k);
     }
     const T h = s.z1 - mu1, kq = s.z2 - mu2;
-    T p;
-    if (P.zinf == 0) p = bvn_cdf<NMAX>(h, kq, s.bc, s.w, s.n);
-    else if (P.zinf == 1) p = norm_cdf(kq);
-    else if (P.zinf == 2) p = norm_cdf(h);
-    else p = T(1);
-    return T(1) - p;
+    if (P.zinf == 0) return bvn_sf<NMAX>(h, kq, s.bc, s.w, s.n);
+    if (P.zinf == 1) return T(1) - norm_cdf(kq);
+    if (P.zinf == 2) return T(1) - norm_cdf(h);
+    return T(0);
 }
 
 }  // namespace bmd

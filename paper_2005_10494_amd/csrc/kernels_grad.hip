@@ -292,14 +292,14 @@ __global__ __launch_bounds__(kGradBlock) void k_grad(GradArgs a, DrawArrays<T> D
 #pragma unroll
                     for (int rr = 0; rr < R; ++rr) {
                         const int i = min(i0 + rr, nk - 1);
-                        const T* Bi = ch.Bt + static_cast<size_t>(i) * D * K + m;
+                        const T* Bi = ch.Bt + (static_cast<size_t>(i) * K + m) * D;
                         // mix_j = s_j a_j + (1 - s_j) b_j = b_j + s_j (a_j - b_j);
                         // d mix_j / d q_j = s'_j (a_j - b_j) + s_j a'_j
                         T dif[D], mix[D], pre[D + 1];
                         pre[0] = T(1);
 #pragma unroll
                         for (int j = 0; j < D; ++j) {
-                            const T bv = Bi[j * K];
+                            const T bv = Bi[j];
                             dif[j] = av[j] - bv;
                             mix[j] = fma(s[rr][j], dif[j], bv);
                             pre[j + 1] = pre[j] * mix[j];

@@ -154,7 +154,7 @@ __device__ __forceinline__ void draw_one(const DevProblem& P, const double* __re
                 const double s = P.sr * gh[m];
                 for (int j = 0; j < P.d; ++j) {
                     const double v = norm_cdf((s - t[j]) / P.sq);
-                    B[j * K + m] = static_cast<T>(j == 0 ? gh[K + m] * v : v);
+                    B[m * P.d + j] = static_cast<T>(j == 0 ? gh[K + m] * v : v);
                     prod *= v;
                 }
                 PR += prod;

@@ -106,11 +106,12 @@ __device__ __forceinline__ void mfma_tile_body(const EvalArgs<T>& a, const MfmaG
     const int K = a.D.K;   // a multiple of 4 (node steps of four)
     const int CH = geo.chunk;
     T* sO = reinterpret_cast<T*>(lds);                                  // [CH][256]
-    T* sB = sO + static_cast<size_t>(CH) * kEvalBlock;                   // [CH][D][K]
+    T* sB = sO + static_cast<size_t>(CH) * kEvalBlock;                   // [CH][K][D]
     Quad<T>* sq = reinterpret_cast<Quad<T>*>(sB + static_cast<size_t>(CH) * D * K);  // [CH] (b0, b1, mu1, -)
     int* sthr = reinterpret_cast<int*>(sq + CH);                         // [CH][D]
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t p0 = (tile / geo.tiles_l) * 16, l0 = (tile % geo.tiles_l) * 16;
     const int64_t G = a.P.G;
     const int64_t M = a.D.M;
@@ -184,7 +185,9 @@ __device__ __forceinline__ void mfma_tile_body(const EvalArgs<T>& a, const MfmaG
         // phase A: overlaps of the tile; a wavefront takes kChains draws per
         // pass (draws wave + 4c + 4 kChains t), one independent MFMA chain each.
         // Rows or columns past the grid (p >= Pn, l >= Sn) feed only tile
-        // entries that phase B never stores, so they need no masking.
+        // entries that phase B never stores, so they need no masking.  The draw
+        // indices are wave-uniform (scalar loop and addressing); a lane reads
+        // node m = 4 s + kq of a staged draw at a fixed offset from its base.
         constexpr int kWaves = kEvalBlock / 64;
         auto phase_a = [&](auto split_c) {
             constexpr int SPLIT = decltype(split_c)::value;
@@ -198,16 +201,16 @@ __device__ __forceinline__ void mfma_tile_body(const EvalArgs<T>& a, const MfmaG
                     ic[q] = i0 + q * kWaves < nk ? i0 + q * kWaves : i0;
 #pragma unroll
                     for (int j = 0; j < D; ++j) msk[q][j] = iA[j] >= sthr[ic[q] * D + j] ? ~Bits<T>(0) : Bits<T>(0);
-                    Bc[q] = sB + static_cast<size_t>(ic[q]) * D * K;
+                    Bc[q] = sB + (static_cast<size_t>(ic[q]) * K + kq) * D;
                     c[q] = acc_t{0, 0, 0, 0};
                 }
-                auto step = [&](int m, const T* av) {
+                auto step = [&](int s, const T* av) {
 #pragma unroll
                     for (int q = 0; q < kChains; ++q) {
                         T pre = T(1), suf = T(1);
 #pragma unroll
                         for (int j = 0; j < D; ++j) {
-                            const T v = bit_select(msk[q][j], av[j], Bc[q][j * K + m]);
+                            const T v = bit_select(msk[q][j], av[j], Bc[q][4 * s * D + j]);
                             if (j < SPLIT) pre *= v; else suf *= v;   // j, SPLIT: compile-time after unrolling
                         }
                         c[q] = mf_step(pre, suf, c[q]);
@@ -215,13 +218,13 @@ __device__ __forceinline__ void mfma_tile_body(const EvalArgs<T>& a, const MfmaG
                 };
 #pragma unroll
                 for (int s = 0; s < kHoist; ++s)
-                    if (s < S) step(4 * s + kq, aH[s]);
+                    if (s < S) step(s, aH[s]);
                 for (int s = kHoist; s < S; ++s) {
                     const int m = 4 * s + kq;
                     T av[D];
 #pragma unroll
                     for (int j = 0; j < D; ++j) av[j] = a.A[(static_cast<int64_t>(j) * K + m) * mmax + iA[j]];
-                    step(m, av);
+                    step(s, av);
                 }
 #pragma unroll
                 for (int q = 0; q < kChains; ++q) {
@@ -246,12 +249,12 @@ __device__ __forceinline__ void mfma_tile_body(const EvalArgs<T>& a, const MfmaG
             const Quad<T> dq = sq[i];
             const T mu2 = st.srI * (dq.x + dq.y * O * st.invr);
             const T h = st.z1 - dq.z, kq2 = st.z2 - mu2;
-            T p;
-            if (a.P.zinf == 0) p = bvn_cdf<NMAX>(h, kq2, st.bc, wts, st.n);
-            else if (a.P.zinf == 1) p = norm_cdf(kq2);
-            else if (a.P.zinf == 2) p = norm_cdf(h);
-            else p = T(1);
-            const double v = static_cast<double>(T(1) - p);
+            T sv;   // 1 - P(both statistics below their critical values)
+            if (a.P.zinf == 0) sv = bvn_sf<NMAX>(h, kq2, st.bc, wts, st.n);
+            else if (a.P.zinf == 1) sv = T(1) - norm_cdf(kq2);
+            else if (a.P.zinf == 2) sv = T(1) - norm_cdf(h);
+            else sv = T(0);
+            const double v = static_cast<double>(sv);
             s1 += v;
             s2 += v * v;
         }

@@ -61,12 +61,12 @@ def test_counter_summary_reader(tmp_path, monkeypatch):
 def test_algorithmic_flops_one_biomarker():
     """d = 1: no overlap quadrature, so F = 23 + 6 n(rho_g) per evaluation."""
     spec = {"d": 1, "m": [4], "effect": "step", "q_lo": 0.05, "q_hi": 0.95}
-    r = np.array([0.04, 0.2, 0.5, 0.81])     # rho = 0.2, 0.447, 0.707, 0.9
+    r = np.array([0.04, 0.2, 0.5, 0.8, 0.87, 0.93])   # rho = 0.2, 0.447, 0.707, 0.894, 0.933, 0.964
     tau = np.full((10, 1), 0.5)
     f32 = bench.algorithmic_flops(spec, r, tau, "fp32", 4)
     f64 = bench.algorithmic_flops(spec, r, tau, "fp64", 4)
-    assert f32 == 10 * sum(23 + 6 * n for n in (4, 4, 6, 10))
-    assert f64 == 10 * sum(23 + 6 * n for n in (6, 8, 12, 20))
+    assert f32 == 10 * sum(23 + 6 * n for n in (4, 4, 6, 8, 10, 12))
+    assert f64 == 10 * sum(23 + 6 * n for n in (6, 8, 12, 16, 20, 24))
 
 
 def test_algorithmic_flops_overlap_counts_mixed_designs_only():

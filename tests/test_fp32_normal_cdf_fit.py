@@ -2,7 +2,8 @@
 coefficients in csrc/normal_cdf_fit.hpp), replayed on the CPU operation by
 operation in single precision (the hardware reciprocal taken one ulp off) and
 checked against scipy's double-precision ndtr: absolute error within 1.6e-7
-everywhere and no bias."""
+everywhere, no bias, symmetric to one rounding; the fitted tail itself is
+relatively accurate."""
 import importlib.util
 import os
 import re
@@ -17,7 +18,7 @@ CSRC = os.path.join(ROOT, "paper_2005_10494_amd", "csrc")
 def _header_coefficients():
     text = open(os.path.join(CSRC, "normal_cdf_fit.hpp")).read()
     body = text[text.index("kPhiFit[kPhiFitDeg + 1]"):]
-    vals = re.findall(r"(-?0x[0-9a-fA-F.]+p[-+]\d+)f", body)
+    vals = re.findall(r"(-?0x[0-9a-fA-F.]+p[-+]\d+)f,", body)
     return np.array([float.fromhex(v) for v in vals], dtype=np.float32)
 
 
@@ -31,7 +32,8 @@ def _generator():
 def test_fit_header_matches_generator_degree():
     gen = _generator()
     c = _header_coefficients()
-    assert c.size == gen.DEG + 1 and c[0] == 0.0
+    assert c.size == gen.DEG + 1
+    assert c[0] == np.float32(0.5 * np.log2(gen.L2E))   # log2(sqrt(log2 e)): the folded scale
 
 
 def test_fp32_normal_cdf_accuracy_and_bias():
@@ -45,9 +47,22 @@ def test_fp32_normal_cdf_accuracy_and_bias():
     err = got - ref
     assert np.abs(err).max() <= 1.6e-7
     assert abs(err.mean()) <= 2e-9
-    # tails: relative accuracy where Phi is still a normal float
-    tail = (xs < -1.0) & (ref > 1e-30)
-    assert np.all(np.abs(err[tail]) <= 2e-5 * ref[tail] + 1e-37)
-    # saturation and symmetry
+    # the signed value 1/2 + copysign(1/2 - tail, x) is symmetric to one rounding
+    neg = np.array([float(gen.phi32(-x, c)) for x in xs])
+    assert np.abs(got + neg - 1.0).max() <= 6e-8
+    # saturation, and Phi(0) = 1/2
     assert float(gen.phi32(np.float32(40.0), c)) == 1.0 and float(gen.phi32(np.float32(-40.0), c)) == 0.0
     assert abs(float(gen.phi32(np.float32(0.0), c)) - 0.5) <= 6e-8
+
+
+def test_fp32_normal_tail_relative_accuracy():
+    """The fitted tail r' 2^e itself keeps relative accuracy wherever Phi(-|x|)
+    is a normal float (the signed CDF keeps absolute accuracy only)."""
+    scipy_special = pytest.importorskip("scipy.special")
+    gen = _generator()
+    c = _header_coefficients()
+    xs = np.linspace(-13.0, 0.0, 6001).astype(np.float32)
+    got = np.array([float(gen.tail32(x, c)) for x in xs])
+    ref = scipy_special.ndtr(xs.astype(np.float64))
+    keep = ref > 1e-30
+    assert np.all(np.abs(got[keep] - ref[keep]) <= 2e-5 * ref[keep] + 1e-37)

@@ -29,8 +29,8 @@ METRIC = "integrand evals/sec and % VALU roofline, FP32+comp vs FP64, at |Δobj|
 PEAK_FP32_TFLOPS = 157.3          # published dense FP32 vector peak (packed FMA)
 PEAK_FP32_UNPACKED_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 flop x 2.4 GHz, unpacked FMA
 PEAK_FP64_TFLOPS = 78.6
-SWEEP_KERNEL = {"direct": "k_eval_direct<float,%d,12> (designs x draws sweep, one design per thread)",
-                "matrix": "k_eval_mfma<float,%d,12> (designs x draws sweep, 16x16 design tiles, overlap on MFMA)"}
+SWEEP_KERNEL = {"direct": "k_eval_direct<float,%d,12,false> (designs x draws sweep, one design per thread)",
+                "matrix": "k_eval_mfma<float,%d,12,false> (designs x draws sweep, 16x16 design tiles, overlap on MFMA)"}
 
 
 def log(*a):
@@ -257,7 +257,7 @@ def main():
     achieved = flops32 / (sweep32 * 1e-3) / 1e12
     kind = bmd.sweep_kind(p32)
     summary = f"k_eval_mfma_{d}d_{spec['m'][0]}cube_M{M // 1000}k_counters.md"
-    kname = "k_eval_" + ("mfma" if kind == "matrix" else "direct") + "<%s, " + str(d) + ", %d>"
+    kname = "k_eval_" + ("mfma" if kind == "matrix" else "direct") + "<%s, " + str(d) + ", %d, false>"
     cnt32 = measured_counters(summary, kname % ("float", 12)) or {}
     cnt64 = measured_counters(summary, kname % ("double", 24)) or {}
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",

@@ -486,7 +486,8 @@ bmd_status bmd_eval_grid(bmd_problem* p, uint64_t n_draws, int32_t prec, double*
     HIP_TRY(launch_draws(p, prec, 0, M, p->d_ws, s), "draw kernel");
     mark(p, 1, s);
     mark(p, 2, s);
-    HIP_TRY(launch_eval_grid(p, prec, M, p->d_ws, partials, static_cast<int>(n_slices), slice_len, s), "eval kernel");
+    HIP_TRY(launch_eval_grid(p, prec, M, p->d_ws, partials, static_cast<int>(n_slices), slice_len, d_var != nullptr, s),
+            "eval kernel");
     mark(p, 3, s);
     mark(p, 4, s);
     HIP_TRY(launch_finalize(p, M, partials, static_cast<int>(n_slices), d_mean, d_var, s), "finalize kernel");

@@ -149,8 +149,9 @@ int sweep_blocks_per_cu(const bmd_problem* p, int prec);
 int sweep_chunk(const bmd_problem* p, int prec);
 struct MfmaGeom;
 MfmaGeom sweep_geometry(const bmd_problem* p, int prec);
+// want_var: also write the sums of squares (the second half of each slice).
 hipError_t launch_eval_grid(const bmd_problem* p, int prec, int64_t M, const void* ws,
-                            double* partials, int n_slices, int64_t slice_len, hipStream_t s);
+                            double* partials, int n_slices, int64_t slice_len, bool want_var, hipStream_t s);
 hipError_t launch_finalize(const bmd_problem* p, int64_t M, const double* partials, int n_slices,
                            double* mean, double* var, hipStream_t s);
 hipError_t launch_smooth(const bmd_problem* p, int prec, const double* in, double* out,

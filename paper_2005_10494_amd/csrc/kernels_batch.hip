@@ -43,9 +43,9 @@ __global__ __launch_bounds__(kEvalBlock) void k_batch(BatchPhase ph, const Batch
     const int slice = __builtin_amdgcn_readfirstlane(it.z);
     const BatchRecord<T>& R = recs[rec];
     if constexpr (MF)
-        mfma_tile_body<T, D, NMAX>(R.a, R.geo, tile, slice, lds);
+        mfma_tile_body<T, D, NMAX, false>(R.a, R.geo, tile, slice, lds);
     else
-        direct_body<T, D, NMAX>(R.a, tile, slice);
+        direct_body<T, D, NMAX, false>(R.a, tile, slice);
     __syncthreads();   // every thread's partial sums are written
     if (threadIdx.x == 0) {
         __threadfence();

@@ -11,15 +11,16 @@
 namespace bmd {
 namespace {
 
-template <typename T, int D, int NMAX>
+// VAR: also the per-design sums of squares (only when a variance is asked for).
+template <typename T, int D, int NMAX, bool VAR>
 __global__ __launch_bounds__(kEvalBlock) void k_eval_direct(EvalArgs<T> a) {
-    direct_body<T, D, NMAX>(a, blockIdx.x, blockIdx.y);
+    direct_body<T, D, NMAX, VAR>(a, blockIdx.x, blockIdx.y);
 }
 
-template <typename T, int D, int NMAX>
+template <typename T, int D, int NMAX, bool VAR>
 __global__ __launch_bounds__(kEvalBlock) void k_eval_mfma(EvalArgs<T> a, MfmaGeom geo) {
     extern __shared__ __align__(16) char lds[];
-    mfma_tile_body<T, D, NMAX>(a, geo, blockIdx.x, blockIdx.y, lds);
+    mfma_tile_body<T, D, NMAX, VAR>(a, geo, blockIdx.x, blockIdx.y, lds);
 }
 
 __global__ void k_finalize(int64_t G, int64_t M, int n_slices, const double* __restrict__ part,
@@ -27,13 +28,13 @@ __global__ void k_finalize(int64_t G, int64_t M, int n_slices, const double* __r
     const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= G) return;
     double s1 = 0.0, s2 = 0.0;
-    for (int s = 0; s < n_slices; ++s) {
-        s1 += part[static_cast<int64_t>(s) * 2 * G + g];
-        s2 += part[static_cast<int64_t>(s) * 2 * G + G + g];
-    }
+    for (int s = 0; s < n_slices; ++s) s1 += part[static_cast<int64_t>(s) * 2 * G + g];
     const double Md = static_cast<double>(M);
     mean[g] = s1 / Md;
-    if (var) var[g] = M > 1 ? fmax(0.0, (s2 - s1 * s1 / Md) / (Md - 1.0)) : 0.0;
+    if (var) {
+        for (int s = 0; s < n_slices; ++s) s2 += part[static_cast<int64_t>(s) * 2 * G + G + g];
+        var[g] = M > 1 ? fmax(0.0, (s2 - s1 * s1 / Md) / (Md - 1.0)) : 0.0;
+    }
 }
 
 // Prefix/suffix split with the least tile padding (ties: the later split).
@@ -65,63 +66,62 @@ MfmaGeom mfma_geometry(const bmd_problem* p, int prec) {
     return geo;
 }
 
-template <typename T, int NMAX>
-hipError_t launch_typed(const bmd_problem* p, int prec, const EvalArgs<T>& a, int n_slices, hipStream_t s) {
-    const int d = p->P.d;
-    if (use_mfma_sweep(p)) {
-        const MfmaGeom geo = mfma_geometry(p, prec);
-        const int64_t tiles = ((geo.Pn + 15) / 16) * geo.tiles_l;
-        const dim3 grid(static_cast<unsigned>(tiles), static_cast<unsigned>(n_slices));
-        const size_t lds = mfma_lds_bytes<T>(geo.chunk, d, a.D.K);
+// The sweep kernel for biomarker count d.
+template <typename T, int NMAX, bool VAR>
+const void* sweep_kernel(int d, bool mf) {
+    if (mf) {
         switch (d) {
-            case 2: hipLaunchKernelGGL((k_eval_mfma<T, 2, NMAX>), grid, dim3(kEvalBlock), lds, s, a, geo); break;
-            case 3: hipLaunchKernelGGL((k_eval_mfma<T, 3, NMAX>), grid, dim3(kEvalBlock), lds, s, a, geo); break;
-            case 4: hipLaunchKernelGGL((k_eval_mfma<T, 4, NMAX>), grid, dim3(kEvalBlock), lds, s, a, geo); break;
-            case 5: hipLaunchKernelGGL((k_eval_mfma<T, 5, NMAX>), grid, dim3(kEvalBlock), lds, s, a, geo); break;
-            default: hipLaunchKernelGGL((k_eval_mfma<T, 6, NMAX>), grid, dim3(kEvalBlock), lds, s, a, geo); break;
+            case 2: return reinterpret_cast<const void*>(k_eval_mfma<T, 2, NMAX, VAR>);
+            case 3: return reinterpret_cast<const void*>(k_eval_mfma<T, 3, NMAX, VAR>);
+            case 4: return reinterpret_cast<const void*>(k_eval_mfma<T, 4, NMAX, VAR>);
+            case 5: return reinterpret_cast<const void*>(k_eval_mfma<T, 5, NMAX, VAR>);
+            default: return reinterpret_cast<const void*>(k_eval_mfma<T, 6, NMAX, VAR>);
         }
-        return hipGetLastError();
     }
-    const dim3 grid(static_cast<unsigned>((p->P.G + kEvalBlock - 1) / kEvalBlock), static_cast<unsigned>(n_slices));
     switch (d) {
-        case 1: hipLaunchKernelGGL((k_eval_direct<T, 1, NMAX>), grid, dim3(kEvalBlock), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_eval_direct<T, 2, NMAX>), grid, dim3(kEvalBlock), 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_eval_direct<T, 3, NMAX>), grid, dim3(kEvalBlock), 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_eval_direct<T, 4, NMAX>), grid, dim3(kEvalBlock), 0, s, a); break;
-        case 5: hipLaunchKernelGGL((k_eval_direct<T, 5, NMAX>), grid, dim3(kEvalBlock), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_eval_direct<T, 6, NMAX>), grid, dim3(kEvalBlock), 0, s, a); break;
+        case 1: return reinterpret_cast<const void*>(k_eval_direct<T, 1, NMAX, VAR>);
+        case 2: return reinterpret_cast<const void*>(k_eval_direct<T, 2, NMAX, VAR>);
+        case 3: return reinterpret_cast<const void*>(k_eval_direct<T, 3, NMAX, VAR>);
+        case 4: return reinterpret_cast<const void*>(k_eval_direct<T, 4, NMAX, VAR>);
+        case 5: return reinterpret_cast<const void*>(k_eval_direct<T, 5, NMAX, VAR>);
+        default: return reinterpret_cast<const void*>(k_eval_direct<T, 6, NMAX, VAR>);
     }
-    (void)prec;
-    return hipGetLastError();
 }
 
-// Resident workgroups per compute unit of the sweep kernel eval_grid launches.
+template <typename T, int NMAX>
+hipError_t launch_typed(const bmd_problem* p, int prec, const EvalArgs<T>& a, int n_slices, bool var,
+                        hipStream_t s) {
+    const int d = p->P.d;
+    const bool mf = use_mfma_sweep(p);
+    const void* k = var ? sweep_kernel<T, NMAX, true>(d, mf) : sweep_kernel<T, NMAX, false>(d, mf);
+    if (mf) {
+        MfmaGeom geo = mfma_geometry(p, prec);
+        const int64_t tiles = ((geo.Pn + 15) / 16) * geo.tiles_l;
+        const size_t lds = mfma_lds_bytes<T>(geo.chunk, d, a.D.K);
+        void* args[] = {const_cast<EvalArgs<T>*>(&a), &geo};
+        return hipLaunchKernel(k, dim3(static_cast<unsigned>(tiles), static_cast<unsigned>(n_slices)),
+                               dim3(kEvalBlock), args, lds, s);
+    }
+    void* args[] = {const_cast<EvalArgs<T>*>(&a)};
+    return hipLaunchKernel(k, dim3(static_cast<unsigned>((p->P.G + kEvalBlock - 1) / kEvalBlock),
+                                   static_cast<unsigned>(n_slices)),
+                           dim3(kEvalBlock), args, 0, s);
+}
+
+// Resident workgroups per compute unit of the sweep kernel eval_grid launches
+// (the variant without sums of squares).
 template <typename T, int NMAX>
 int resident_typed(const bmd_problem* p, int prec) {
-    const int d = p->P.d;
-    int nb = 0;
-    hipError_t e = hipSuccess;
-    if (use_mfma_sweep(p)) {
+    const bool mf = use_mfma_sweep(p);
+    size_t lds = 0;
+    if (mf) {
         const MfmaGeom geo = mfma_geometry(p, prec);
-        const size_t lds = mfma_lds_bytes<T>(geo.chunk, d, p->tab[prec].K);
-        switch (d) {
-            case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_mfma<T, 2, NMAX>, kEvalBlock, lds); break;
-            case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_mfma<T, 3, NMAX>, kEvalBlock, lds); break;
-            case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_mfma<T, 4, NMAX>, kEvalBlock, lds); break;
-            case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_mfma<T, 5, NMAX>, kEvalBlock, lds); break;
-            default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_mfma<T, 6, NMAX>, kEvalBlock, lds); break;
-        }
-    } else {
-        switch (d) {
-            case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_direct<T, 1, NMAX>, kEvalBlock, 0); break;
-            case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_direct<T, 2, NMAX>, kEvalBlock, 0); break;
-            case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_direct<T, 3, NMAX>, kEvalBlock, 0); break;
-            case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_direct<T, 4, NMAX>, kEvalBlock, 0); break;
-            case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_direct<T, 5, NMAX>, kEvalBlock, 0); break;
-            default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_direct<T, 6, NMAX>, kEvalBlock, 0); break;
-        }
+        lds = mfma_lds_bytes<T>(geo.chunk, p->P.d, p->tab[prec].K);
     }
-    if (e != hipSuccess || nb < 1) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_kernel<T, NMAX, false>(p->P.d, mf), kEvalBlock,
+                                                     lds) != hipSuccess ||
+        nb < 1) {
         (void)hipGetLastError();
         nb = 1;
     }
@@ -155,17 +155,17 @@ int sweep_chunk(const bmd_problem* p, int prec) {
 }
 
 hipError_t launch_eval_grid(const bmd_problem* p, int prec, int64_t M, const void* ws, double* partials,
-                            int n_slices, int64_t slice_len, hipStream_t s) {
+                            int n_slices, int64_t slice_len, bool want_var, hipStream_t s) {
     if (prec == BMD_FP64) {
         EvalArgs<double> a{p->P, p->d_r, p->d_z1, p->d_z2, static_cast<const double*>(p->tab[prec].A),
                            draws_fp64(p, M, ws), p->d_gl, static_cast<const double*>(p->tab[prec].glw),
                            slice_len, partials};
-        return launch_typed<double, 24>(p, prec, a, n_slices, s);
+        return launch_typed<double, 24>(p, prec, a, n_slices, want_var, s);
     }
     EvalArgs<float> a{p->P, p->d_r, p->d_z1, p->d_z2, static_cast<const float*>(p->tab[prec].A),
                       draws_fp32(p, M, ws), p->d_gl, static_cast<const float*>(p->tab[prec].glw),
                       slice_len, partials};
-    return launch_typed<float, 12>(p, prec, a, n_slices, s);
+    return launch_typed<float, 12>(p, prec, a, n_slices, want_var, s);
 }
 
 hipError_t launch_finalize(const bmd_problem* p, int64_t M, const double* partials, int n_slices, double* mean,

@@ -21,12 +21,12 @@ struct EvalArgs {
     const double* gl;    // packed GL table (FP64 nodes)
     const T* glw;        // packed GL table in T (weights read from here)
     int64_t slice_len;
-    double* partials;    // [n_slices][2][G]
+    double* partials;    // [n_slices][2][G]: sums, then sums of squares (VAR only)
 };
 
 // Direct sweep, one workgroup's work: designs bx * 256 + thread (one per
-// thread), draws of slice `slice`.
-template <typename T, int D, int NMAX>
+// thread), draws of slice `slice`.  VAR: also the sums of squares.
+template <typename T, int D, int NMAX, bool VAR>
 __device__ __forceinline__ void direct_body(const EvalArgs<T>& a, int64_t bx, int slice) {
     const int64_t G = a.P.G;
     const int64_t g = bx * kEvalBlock + threadIdx.x;
@@ -42,12 +42,12 @@ __device__ __forceinline__ void direct_body(const EvalArgs<T>& a, int64_t bx, in
     for (int64_t k = kb; k < ke; ++k) {
         const double v = static_cast<double>(summand<T, D, NMAX>(a.P, s, src, k, a.A, a.D.K));
         s1 += v;
-        s2 += v * v;
+        if constexpr (VAR) s2 = fma(v, v, s2);
     }
     if (valid) {
         double* out = a.partials + static_cast<int64_t>(slice) * 2 * G;
         out[g] = s1;
-        out[G + g] = s2;
+        if constexpr (VAR) out[G + g] = s2;
     }
 }
 
@@ -98,8 +98,8 @@ struct MfmaGeom {
 // Phase B (vector units): one design per thread, the bivariate normal part.
 // One workgroup's work: tile `tile`, draws of slice `slice`; lds holds
 // mfma_lds_bytes<T>(geo.chunk, D, K) bytes.  Starts and ends with barriers, so
-// a persistent caller may run items back to back.
-template <typename T, int D, int NMAX>
+// a persistent caller may run items back to back.  VAR: also the sums of squares.
+template <typename T, int D, int NMAX, bool VAR>
 __device__ __forceinline__ void mfma_tile_body(const EvalArgs<T>& a, const MfmaGeom& geo, int64_t tile, int slice,
                                                char* lds) {
     using acc_t = typename std::conditional<sizeof(T) == 8, mf_d4, mf_f4>::type;
@@ -244,6 +244,7 @@ __device__ __forceinline__ void mfma_tile_body(const EvalArgs<T>& a, const MfmaG
         }
         __syncthreads();
         // phase B: bivariate normal part for this thread's design
+#pragma unroll 2
         for (int i = 0; i < nk; ++i) {
             const T O = sO[static_cast<size_t>(i) * kEvalBlock + tid];
             const Quad<T> dq = sq[i];
@@ -256,13 +257,13 @@ __device__ __forceinline__ void mfma_tile_body(const EvalArgs<T>& a, const MfmaG
             else sv = T(0);
             const double v = static_cast<double>(sv);
             s1 += v;
-            s2 += v * v;
+            if constexpr (VAR) s2 = fma(v, v, s2);
         }
     }
     if (validB) {
         double* out = a.partials + static_cast<int64_t>(slice) * 2 * G;
         out[g] = s1;
-        out[G + g] = s2;
+        if constexpr (VAR) out[G + g] = s2;
     }
 }
 

@@ -47,15 +47,15 @@ def test_counter_summary_reader(tmp_path, monkeypatch):
     _copy_sources(str(tmp_path))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     (tmp_path / "profiles").mkdir()
-    row = "| `k_eval_mfma<float, 3, 12>` | 2.0e+08 | 3.0e+07 | 1 | 2 | 3.9e+10 | 0.945 | 101.0 | 99.7 |"
+    row = "| `k_eval_mfma<float, 3, 12, false>` | 2.0e+08 | 3.0e+07 | 1 | 2 | 3.9e+10 | 0.945 | 101.0 | 99.7 |"
     good = f"source digest: `{bench.source_digest()}`\n\n| kernel | a | b | c | d | e | f | g | h |\n|---|\n{row}\n"
     (tmp_path / "profiles" / "s.md").write_text(good)
-    c = bench.measured_counters("s.md", "k_eval_mfma<float, 3, 12>")
+    c = bench.measured_counters("s.md", "k_eval_mfma<float, 3, 12, false>")
     assert c == {"traffic": 2.3e8, "valu_issue_fill": 0.945, "valu_busy_pct": 101.0}
-    assert bench.measured_counters("s.md", "k_eval_mfma<double, 3, 24>") is None
+    assert bench.measured_counters("s.md", "k_eval_mfma<double, 3, 24, false>") is None
     (tmp_path / "profiles" / "t.md").write_text(good.replace(bench.source_digest(), "0" * 64))
-    assert bench.measured_counters("t.md", "k_eval_mfma<float, 3, 12>") is None   # stale counters
-    assert bench.measured_counters("missing.md", "k_eval_mfma<float, 3, 12>") is None
+    assert bench.measured_counters("t.md", "k_eval_mfma<float, 3, 12, false>") is None   # stale counters
+    assert bench.measured_counters("missing.md", "k_eval_mfma<float, 3, 12, false>") is None
 
 
 def test_algorithmic_flops_one_biomarker():

@@ -17,8 +17,9 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_direct(EvalArgs<T> a) {
     direct_body<T, D, NMAX, VAR>(a, blockIdx.x, blockIdx.y);
 }
 
+// FP32: at most 96 VGPRs, so that five wavefronts share each SIMD.
 template <typename T, int D, int NMAX, bool VAR>
-__global__ __launch_bounds__(kEvalBlock) void k_eval_mfma(EvalArgs<T> a, MfmaGeom geo) {
+__global__ __launch_bounds__(kEvalBlock, sizeof(T) == 4 ? 5 : 1) void k_eval_mfma(EvalArgs<T> a, MfmaGeom geo) {
     extern __shared__ __align__(16) char lds[];
     mfma_tile_body<T, D, NMAX, VAR>(a, geo, blockIdx.x, blockIdx.y, lds);
 }
@@ -56,12 +57,16 @@ MfmaGeom mfma_geometry(const bmd_problem* p, int prec) {
     }
     geo.tiles_l = (geo.Sn + 15) / 16;
     const int K = p->tab[prec].K;
-    // Largest chunk (multiple of 4, at most 32 draws) within 40 KB of LDS, so
-    // four workgroups fit a compute unit's 160 KB.
+    // Largest chunk of at most 32 draws that keeps every wavefront pass of
+    // phase A full (a multiple of 8 in FP32: two draws per pass, four
+    // wavefronts; of 4 in FP64) within the LDS share of the resident
+    // workgroups: five per compute unit in FP32 (32 KB each of 160 KB), four
+    // in FP64 (40 KB).
+    const int step = prec == BMD_FP64 ? 4 : 8;
+    const size_t cap = prec == BMD_FP64 ? 40 * 1024 : 32 * 1024;
     int ch = 32;
-    const size_t cap = 40 * 1024;
-    while (ch > 4 && (prec == BMD_FP64 ? mfma_lds_bytes<double>(ch, d, K) : mfma_lds_bytes<float>(ch, d, K)) > cap)
-        ch -= 4;
+    while (ch > step && (prec == BMD_FP64 ? mfma_lds_bytes<double>(ch, d, K) : mfma_lds_bytes<float>(ch, d, K)) > cap)
+        ch -= step;
     geo.chunk = ch;
     return geo;
 }

@@ -34,7 +34,7 @@ struct BatchRecord {
 // argument, read-only for the launch, so their wave-uniform fields are fetched
 // with scalar loads.  The last item of a problem stamps its completion time.
 template <typename T, int D, int NMAX, bool MF>
-__global__ __launch_bounds__(kEvalBlock) void k_batch(BatchPhase ph, const BatchRecord<T>* __restrict__ recs) {
+__global__ __launch_bounds__(kEvalBlock, sizeof(T) == 4 && MF && D <= 3 ? 5 : 1) void k_batch(BatchPhase ph, const BatchRecord<T>* __restrict__ recs) {
     extern __shared__ __align__(16) char lds[];
     if (threadIdx.x == 0) atomicMin(ph.t_start, static_cast<unsigned long long>(wall_clock64()));
     const int4 it = ph.items[blockIdx.x];

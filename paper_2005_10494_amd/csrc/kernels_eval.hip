@@ -17,9 +17,10 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_direct(EvalArgs<T> a) {
     direct_body<T, D, NMAX, VAR>(a, blockIdx.x, blockIdx.y);
 }
 
-// FP32: at most 96 VGPRs, so that five wavefronts share each SIMD.
+// FP32 with up to three biomarkers: at most 96 VGPRs, so that five wavefronts
+// share each SIMD (more axes would spill the node coefficients).
 template <typename T, int D, int NMAX, bool VAR>
-__global__ __launch_bounds__(kEvalBlock, sizeof(T) == 4 ? 5 : 1) void k_eval_mfma(EvalArgs<T> a, MfmaGeom geo) {
+__global__ __launch_bounds__(kEvalBlock, sizeof(T) == 4 && D <= 3 ? 5 : 1) void k_eval_mfma(EvalArgs<T> a, MfmaGeom geo) {
     extern __shared__ __align__(16) char lds[];
     mfma_tile_body<T, D, NMAX, VAR>(a, geo, blockIdx.x, blockIdx.y, lds);
 }
@@ -60,10 +61,10 @@ MfmaGeom mfma_geometry(const bmd_problem* p, int prec) {
     // Largest chunk of at most 32 draws that keeps every wavefront pass of
     // phase A full (a multiple of 8 in FP32: two draws per pass, four
     // wavefronts; of 4 in FP64) within the LDS share of the resident
-    // workgroups: five per compute unit in FP32 (32 KB each of 160 KB), four
-    // in FP64 (40 KB).
+    // workgroups: five per compute unit for FP32 with up to three biomarkers
+    // (32 KB each of 160 KB), else four (40 KB).
     const int step = prec == BMD_FP64 ? 4 : 8;
-    const size_t cap = prec == BMD_FP64 ? 40 * 1024 : 32 * 1024;
+    const size_t cap = prec != BMD_FP64 && d <= 3 ? 32 * 1024 : 40 * 1024;
     int ch = 32;
     while (ch > step && (prec == BMD_FP64 ? mfma_lds_bytes<double>(ch, d, K) : mfma_lds_bytes<float>(ch, d, K)) > cap)
         ch -= step;

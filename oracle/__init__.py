@@ -44,6 +44,7 @@ class _Problem(ctypes.Structure):
         ("paper_events", ctypes.c_double),
         ("width", ctypes.c_double), ("bandwidth", ctypes.c_double * 6),
         ("seed", ctypes.c_uint64), ("scenario", ctypes.c_uint32),
+        ("design_space", ctypes.c_int32), ("r_lo", ctypes.c_double), ("r_hi", ctypes.c_double),
     ]
 
 
@@ -61,6 +62,7 @@ class _Draw(ctypes.Structure):
 
 _ALPHA = {"fwer": 0, "fwer_equal": 0, "bonferroni": 1, "fixed": 2}
 _EFFECT = {"step": 0, "paper": 1, "paper_gauss": 1}
+_DESIGN = {"cutoffs": 0, "alpha": 1}
 
 _lib = None
 
@@ -76,7 +78,7 @@ def lib():
         sig = {
             "or_Phi": (D, [D]), "or_phi": (D, [D]), "or_Phiinv": (D, [D]),
             "or_bvn": (D, [D, D, D]), "or_bvn_density": (D, [D, D, D]),
-            "or_orthant": (D, [ctypes.c_int, P, D]), "or_zstar": (D, [D, D]),
+            "or_orthant": (D, [ctypes.c_int, P, D]), "or_zstar": (D, [D, D]), "or_z2_fwer": (D, [D, D, D]),
             "or_info_units": (D, [D, D, D]),
             "or_philox4x32_10": (None, [P, P, P]), "or_uniform52": (D, [U32, U32]),
             "or_grid_point": (None, [pp, I64, P, P]), "or_grid_size": (I64, [pp]),
@@ -130,6 +132,9 @@ def problem_struct(prob: dict) -> _Problem:
         s.bandwidth[j] = float(bw[j]) if j < len(bw) else 1.0
     s.seed = int(prob.get("seed", 0))
     s.scenario = int(prob.get("scenario", 0))
+    s.design_space = _DESIGN[prob.get("design", "cutoffs")]
+    s.r_lo = float(prob.get("r_lo", 0.0))
+    s.r_hi = float(prob.get("r_hi", 0.0))
     return s
 
 
@@ -141,6 +146,7 @@ def Phiinv(p): return lib().or_Phiinv(float(p))
 def bvn(h, k, rho): return lib().or_bvn(float(h), float(k), float(rho))
 def bvn_density(h, k, rho): return lib().or_bvn_density(float(h), float(k), float(rho))
 def zstar(r, alpha0=0.025): return lib().or_zstar(float(r), float(alpha0))
+def z2_fwer(z1, r, alpha0=0.025): return lib().or_z2_fwer(float(z1), float(r), float(alpha0))
 def info_units(alpha, beta, delta): return lib().or_info_units(float(alpha), float(beta), float(delta))
 def uniform52(wa, wb): return lib().or_uniform52(int(wa), int(wb))
 

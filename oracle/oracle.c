@@ -267,6 +267,27 @@ double or_zstar(double r, double alpha0)
     return 0.5 * (lo + hi);
 }
 
+/* Second critical value z2 with FWER(z1, z2) = P(Z1 > z1 or Z2 > z2) =
+ * Phi(-z1) + Phi(-z2) - Phi_2(-z1, -z2; sqrt r) = alpha0 (Formula 2 for n = 2
+ * with the first level alpha_1 = Phi(-z1) given), by bisection: the FWER falls
+ * in z2, is at least alpha0 where the second test alone has level alpha0 and
+ * at most alpha0 where it has level alpha0 - alpha_1 (the union bound).
+ * +inf when alpha_1 >= alpha0. */
+double or_z2_fwer(double z1, double r, double alpha0)
+{
+    double a1 = or_Phi(-z1);
+    if (!(a1 < alpha0)) return INFINITY;
+    double rho = sqrt(r);
+    double lo = -or_Phiinv(alpha0), hi = -or_Phiinv(alpha0 - a1);
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        double fwer = a1 + or_Phi(-mid) - or_bvn(-z1, -mid, rho);
+        if (fwer > alpha0) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 /* Information units needed for a one-sided level-alpha test with power
  * 1 - beta at hazard reduction delta (Sec. 3, the I_3 sizing formula). */
 double or_info_units(double alpha, double beta, double delta)
@@ -338,15 +359,30 @@ int64_t or_grid_size(const or_problem *p)
 
 /* Grid design g (row-major, axis 0 slowest): q_j = q_lo + ((q_hi - q_lo) i_j)
  * / (m_j - 1), each operation rounded separately in this order. */
+/* Coordinate range of grid axis j: the subgroup-fraction axis of the alpha
+ * design space, else [q_lo, q_hi]. */
+static void axis_range(const or_problem *p, int j, double *lo, double *hi)
+{
+    if (p->design_space == OR_DESIGN_ALPHA && p->d == 2 && j == 0) {
+        *lo = p->r_lo;
+        *hi = p->r_hi;
+    } else {
+        *lo = p->q_lo;
+        *hi = p->q_hi;
+    }
+}
+
 void or_grid_point(const or_problem *p, int64_t g, double *q, int32_t *idx)
 {
     for (int j = p->d - 1; j >= 0; --j) {
         int64_t i = g % p->m[j];
         g /= p->m[j];
-        double span = p->q_hi - p->q_lo;
+        double lo, hi;
+        axis_range(p, j, &lo, &hi);
+        double span = hi - lo;
         double t = span * (double)i;
         t = t / (double)(p->m[j] - 1);
-        q[j] = p->q_lo + t;
+        q[j] = lo + t;
         if (idx) idx[j] = (int32_t)i;
     }
 }
@@ -357,6 +393,16 @@ void or_grid_point(const or_problem *p, int64_t g, double *q, int32_t *idx)
 void or_make_design(const or_problem *p, const double *q, or_design *o)
 {
     memset(o, 0, sizeof *o);
+    if (p->design_space == OR_DESIGN_ALPHA) {
+        /* (r_2, alpha_1) or alpha_1 alone: the nested pair of Sec. 2.2 with the
+         * level split on the FWER boundary of Formula 2. */
+        for (int j = 0; j < p->d; ++j) o->q[j] = q[j];
+        o->r = (p->d == 2) ? q[0] : p->r_lo;
+        o->rho = sqrt(o->r);
+        o->z1 = -or_Phiinv(q[p->d - 1]);
+        o->z2 = or_z2_fwer(o->z1, o->r, p->alpha0);
+        return;
+    }
     for (int j = 0; j < p->d; ++j) {
         o->q[j] = q[j];
         o->c[j] = or_Phiinv(q[j]);
@@ -582,11 +628,13 @@ void or_smooth_separable(const or_problem *p, const double *in, double *out)
         int64_t outer = G / (inner * m);
         double *W = (double *)malloc(sizeof(double) * (size_t)m * m);
         double *qa = (double *)malloc(sizeof(double) * (size_t)m);
+        double lo, hi;
+        axis_range(p, j, &lo, &hi);
         for (int i = 0; i < m; ++i) {
-            double span = p->q_hi - p->q_lo;
+            double span = hi - lo;
             double t = span * (double)i;
             t = t / (double)(m - 1);
-            qa[i] = p->q_lo + t;
+            qa[i] = lo + t;
         }
         for (int i = 0; i < m; ++i) {
             double den = 0.0;

@@ -33,6 +33,7 @@ extern "C" {
 
 enum { OR_ALPHA_FWER_EQUAL = 0, OR_ALPHA_BONFERRONI = 1, OR_ALPHA_FIXED = 2 };
 enum { OR_EFFECT_STEP = 0, OR_EFFECT_PAPER_GAUSS = 1 };
+enum { OR_DESIGN_CUTOFFS = 0, OR_DESIGN_ALPHA = 1 };
 
 typedef struct {
     int32_t d;              /* number of biomarkers (cutoff axes), 1..6          */
@@ -52,6 +53,14 @@ typedef struct {
     double bandwidth[6];    /* Gaussian smoothing sd per axis, quantile units    */
     uint64_t seed;          /* Philox key                                        */
     uint32_t scenario;      /* third Philox counter word                         */
+    /* Design space.  OR_DESIGN_CUTOFFS: the d cutoff quantiles above.
+     * OR_DESIGN_ALPHA (Sec. 2.2-2.3, n = 2 nested populations, the paper's own
+     * design variables): the last axis is the first test's level alpha_1 on
+     * [q_lo, q_hi] inside (0, alpha0); alpha_2 follows from Formula 2 at FWER =
+     * alpha0.  With d = 2, axis 0 is the subgroup fraction r_2 on [r_lo, r_hi];
+     * with d = 1, r_2 = r_lo.  Paper prior (Formula 10) only. */
+    int32_t design_space;
+    double r_lo, r_hi;
 } or_problem;
 
 /* A design: cutoff quantiles and every quantity that depends on them only. */
@@ -80,6 +89,7 @@ double or_bvn(double h, double k, double rho);     /* P(X<=h, Y<=k)          */
 double or_bvn_density(double h, double k, double rho);
 double or_orthant(int d, const double *v, double rho_b);   /* P(X_j > v_j)    */
 double or_zstar(double r, double alpha0);
+double or_z2_fwer(double z1, double r, double alpha0);   /* second level on the FWER boundary */
 double or_info_units(double alpha, double beta, double delta);
 void   or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double or_uniform52(uint32_t wa, uint32_t wb);

@@ -62,6 +62,24 @@ def grad_5d() -> dict:
     return p
 
 
+def alpha_design(m_alpha: int, r=0.365, m_r: int = 0, r_range=(0.05, 0.95), n_draws: int = 10_240,
+                 bandwidth=(0.05, 0.0015)) -> dict:
+    """The paper's own design variables for n = 2 nested populations (Sec. 3,
+    condition (b): drug effect D0(r) = 0.3 - 0.1 r, I_3 = 211, Formula 10 prior
+    with E = 80): the first test's level alpha_1 on an ``m_alpha``-point grid over
+    [0.0005, 0.0245] (alpha_2 from the FWER boundary), at subgroup fraction
+    ``r`` (m_r = 0), or on an (r_2, alpha_1) grid with ``m_r`` points of r_2 over
+    ``r_range``.  M defaults to the paper's N1 = 10,240 outer draws."""
+    d = 2 if m_r else 1
+    p = base_problem(d, [m_r, m_alpha] if m_r else [m_alpha], 0.0, 0.0, design="alpha",
+                     q_lo=0.0005, q_hi=0.0245, info=211.0, effect="paper", paper_a=0.3,
+                     paper_b=0.1, paper_events=80.0)
+    p["bandwidth"] = list(bandwidth) if m_r else [bandwidth[-1]]
+    p["r_lo"], p["r_hi"] = (float(r_range[0]), float(r_range[1])) if m_r else (float(r), float(r))
+    p["n_draws"] = n_draws
+    return p
+
+
 def design_points(n: int, d: int, seed: int = 1, lo: float = 0.1, hi: float = 0.9) -> np.ndarray:
     """Continuous design points, iid U(lo, hi)^d (cutoff quantiles)."""
     rng = np.random.default_rng(seed)

@@ -442,3 +442,96 @@ def test_gradient_zero_under_null_prior():
     assert abs(obj[0] - 0.025) < 1e-14
     assert np.max(np.abs(gq)) < 1e-12
     assert np.all(gmu > 0)
+
+
+# ---------------------------------------------------------------- alpha design space
+# The paper's own design variables for n = 2 nested populations (Sec. 2.2-2.3):
+# the first test's level alpha_1, with alpha_2 on the FWER boundary of Formula 2.
+
+def _z2_scipy(z1, r, alpha0=0.025):
+    """Second critical value from scipy: brentq on the FWER through Owen's T."""
+    rho = math.sqrt(r)
+    a1 = ndtr(-z1)
+    f = lambda z2: a1 + ndtr(-z2) - _bvn_owen(-z1, -z2, rho) - alpha0  # noqa: E731
+    return brentq(f, -ndtri(alpha0) - 1.0, -ndtri(alpha0 - a1) + 1.0, xtol=1e-14)
+
+
+def _alpha_power_scipy(a1, r, I=211.0, a=0.3, b=0.1):
+    """Condition (b) of Sec. 3 under Formula 10 (E = 80), closed form with scipy:
+    P = 1 - Phi_2((z - D theta) / sqrt(1 + I/20); sqrt r)."""
+    z1 = -ndtri(a1)
+    z2 = _z2_scipy(z1, r)
+    th1, th2 = -math.log(1 - (a - b)), -math.log(1 - (a - b * r))
+    s = math.sqrt(1 + I / 20.0)
+    return 1.0 - _bvn_owen((z1 - math.sqrt(I) * th1) / s, (z2 - math.sqrt(r * I) * th2) / s, math.sqrt(r))
+
+
+def test_alpha_design_second_level_on_fwer_boundary():
+    for r in (0.1, 0.365, 0.8):
+        for a1 in (0.001, 0.0125, 0.024):
+            z1 = -ndtri(a1)
+            z2 = O.z2_fwer(z1, r)
+            assert abs(z2 - _z2_scipy(z1, r)) < 1e-10, (r, a1)
+            fwer = a1 + ndtr(-z2) - _bvn_owen(-z1, -z2, math.sqrt(r))
+            assert abs(fwer - 0.025) < 1e-13
+            # union bound and single-test bound bracket the second level
+            assert 0.025 - a1 - 1e-15 <= ndtr(-z2) <= 0.025
+    assert O.z2_fwer(-ndtri(0.025), 0.5) == math.inf
+
+
+def test_alpha_design_condition_b_optimum():
+    """At r_2 = 0.365 (the subgroup size of the paper's condition (b) optimum)
+    the optimal level split maximises a closed form; the oracle's design
+    quantities, its closed-form power and the maximiser of its surface agree
+    with scipy's."""
+    from scipy.optimize import minimize_scalar
+    r = 0.365
+    p = W.alpha_design(97, r=r)
+    res = minimize_scalar(lambda x: -_alpha_power_scipy(x, r), bounds=(0.005, 0.024), method="bounded",
+                          options={"xatol": 1e-9})
+    a_star, p_star = res.x, -res.fun
+    ds = O.make_design(p, [a_star])
+    assert ds["r"] == r and abs(ds["z1"] + ndtri(a_star)) < 1e-12
+    assert abs(ds["z2"] - _z2_scipy(ds["z1"], r)) < 1e-10
+    assert abs(O.exact_paper(p, [a_star]) - p_star) < 1e-12
+    grid = np.linspace(0.012, 0.020, 161)
+    best = grid[int(np.argmax([O.exact_paper(p, [x]) for x in grid]))]
+    assert abs(best - a_star) <= 0.5 * (grid[1] - grid[0]) + 1e-12
+    # the optimum sits inside (0, alpha0) with both tests on: sum of levels > alpha0
+    assert 0.012 < a_star < 0.02 and a_star + ndtr(-ds["z2"]) > 0.025
+
+
+def test_alpha_design_limits_and_monte_carlo():
+    r = 0.365
+    p = W.alpha_design(5, r=r)
+    I, th1 = 211.0, -math.log(1 - 0.2)
+    s = math.sqrt(1 + I / 20.0)
+    # alpha_1 = alpha0: the second test is off (z2 = +inf) and the power is the
+    # one-population closed form of Sec. 3's condition (a) type
+    one = 1.0 - ndtr((-ndtri(0.025) - math.sqrt(I) * th1) / s)
+    assert O.make_design(p, [0.025])["z2"] == math.inf
+    assert abs(O.exact_paper(p, [0.025]) - one) < 1e-13
+    # the power is continuous there only through z2 -> inf, which is slow: the
+    # prior's spread keeps the second test useful at tiny levels
+    assert O.exact_paper(p, [0.025 * (1 - 1e-9)]) > one
+    # Formula 5 on the oracle's draws converges to the closed form
+    M = 20000
+    q = np.array([[0.005], [0.0159], [0.022]])
+    m, v = O.eval_points(p, q, M)
+    for i in range(3):
+        ex = O.exact_paper(p, q[i])
+        assert abs(m[i] - ex) < 4 * math.sqrt(v[i] / M), (q[i], m[i], ex)
+
+
+def test_alpha_design_grid_and_smoothing():
+    p = W.alpha_design(6, m_r=5, r_range=(0.2, 0.8))
+    G = O.grid_size(p)
+    assert G == 30
+    for g in range(G):
+        q, idx = O.grid_point(p, g)
+        assert tuple(idx) == np.unravel_index(g, (5, 6))
+        assert q[0] == 0.2 + ((0.8 - 0.2) * float(idx[0])) / 4
+        assert q[1] == 0.0005 + ((0.0245 - 0.0005) * float(idx[1])) / 5
+        assert O.make_design(p, q)["r"] == q[0]
+    f = np.random.default_rng(5).uniform(0.5, 0.8, G)
+    assert np.max(np.abs(O.smooth_direct(p, f) - O.smooth_separable(p, f))) < 1e-14

@@ -93,7 +93,7 @@ def measured_counters(summary: str, kernel: str):
 
 def workload(name: str) -> dict:
     from paper_2005_10494_amd import workloads as W
-    return {"3d": W.plain_3d, "1d": W.plain_1d, "5d": W.precision_5d}[name]()
+    return {"3d": W.plain_3d, "1d": W.plain_1d, "5d": W.precision_5d, "alpha": W.alpha_grid}[name]()
 
 
 # --------------------------------------------------------------- algorithmic work
@@ -198,7 +198,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="3d", choices=["3d", "1d", "5d", "grad", "batch"])
+    ap.add_argument("--workload", default="3d", choices=["3d", "1d", "5d", "alpha", "grad", "batch"])
     ap.add_argument("--batch-scale", type=float, default=1.0,
                     help="batch workload only: scale of the per-axis grids and of the draw range (1 = full size)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -241,9 +241,7 @@ def main():
     out = {"metric": METRIC, "value": value, "unit": "integrand evals/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * t32 / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"{spec['d']}-biomarker cutoff grid {'x'.join(map(str, spec['m']))}, "
-                                  f"M={M} prior draws, rho_b={spec['rho_b']}, bandwidth {spec['bandwidth'][0]}, "
-                                  f"FP32 integrand + FP64 sums, steps = precompute+draws+sweep+smooth+argmax",
+           "config": {"workload": _describe(spec, M),
                       "d": spec["d"], "grid": spec["m"], "n_draws": M, "designs": G,
                       "gauss_hermite_nodes": _gh_nodes(res32["problem"], "fp32")}}
 
@@ -296,6 +294,17 @@ def main():
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(spec)
     print(json.dumps(out), flush=True)
+
+
+def _describe(spec: dict, M: int) -> str:
+    grid = "x".join(map(str, spec["m"]))
+    if spec.get("design") == "alpha":
+        return (f"two nested populations, (r_2, alpha_1) grid {grid} with alpha_2 on the FWER boundary, "
+                f"Formula 10 prior D0(r) = {spec['paper_a']} - {spec['paper_b']} r, I_3 = {spec['info']:g}, "
+                f"M={M} prior draws, FP32 integrand + FP64 sums, steps = precompute+draws+sweep+smooth+argmax")
+    return (f"{spec['d']}-biomarker cutoff grid {grid}, M={M} prior draws, rho_b={spec['rho_b']}, "
+            f"bandwidth {spec['bandwidth'][0]}, FP32 integrand + FP64 sums, "
+            f"steps = precompute+draws+sweep+smooth+argmax")
 
 
 def bench_grad(args):

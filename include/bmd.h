@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define BMD_ABI_VERSION 1
+#define BMD_ABI_VERSION 2
 #define BMD_MAX_DIM 6
 
 typedef struct bmd_problem bmd_problem;
@@ -79,6 +79,20 @@ typedef enum {
     BMD_EFFECT_PAPER_GAUSS = 1
 } bmd_effect_model;
 
+/* What a grid design is. */
+typedef enum {
+    /* d biomarker cutoff quantiles (the paper's r-design through cutoffs). */
+    BMD_DESIGN_CUTOFFS = 0,
+    /* The paper's own design variables for n = 2 nested populations (Sec. 2.2,
+     * Sec. 3): the first test's level alpha_1 on the last axis, over [q_lo,
+     * q_hi] inside (0, alpha0), with alpha_2 on the FWER boundary of Formula 2
+     * (alpha_rule must be BMD_ALPHA_FWER_EQUAL, which then means FWER =
+     * alpha0); with d = 2, axis 0 is the subgroup fraction r_2 over [r_lo,
+     * r_hi]; with d = 1, r_2 = r_lo.  Formula 10 prior only
+     * (BMD_EFFECT_PAPER_GAUSS); rho_b, gh_nodes and indicator_width are unused. */
+    BMD_DESIGN_ALPHA = 1
+} bmd_design_space;
+
 /* Problem descriptor (copied by bmd_create_problem). */
 typedef struct {
     int32_t d;                 /* number of biomarkers / cutoff axes, 1..6          */
@@ -106,6 +120,9 @@ typedef struct {
                                   in [4, 128] (the kernels take nodes in fours)    */
     uint64_t seed;             /* Philox4x32-10 key (lo, hi words)                  */
     uint32_t scenario_id;      /* third Philox counter word                         */
+    int32_t design_space;      /* bmd_design_space (0 = cutoffs)                    */
+    double r_lo, r_hi;         /* BMD_DESIGN_ALPHA: subgroup-fraction axis (d = 2),
+                                  0 < r_lo < r_hi <= 0.95, or r_2 = r_lo (d = 1)    */
 } bmd_problem_desc;
 
 /* Version of this header the library was built from (BMD_ABI_VERSION). */
@@ -119,7 +136,10 @@ const char *bmd_last_error(void);
  * the per-design precompute (subgroup fraction r, critical values z1, z2) on
  * `stream`.  *out receives the handle; destroy it with bmd_destroy_problem.
  * ERANGE if some grid design has r > 0.95 (the bivariate quadrature supports
- * correlations sqrt(r) <= 0.975), or rho_b > 0.5. */
+ * correlations sqrt(r) <= 0.975), or rho_b > 0.5.  Alpha design space: EINVAL
+ * unless the prior is BMD_EFFECT_PAPER_GAUSS and the rule
+ * BMD_ALPHA_FWER_EQUAL; ERANGE unless d is 1 or 2, the problem is a grid,
+ * 0 < q_lo < q_hi < alpha0 and the r range is as stated above. */
 bmd_status bmd_create_problem(const bmd_problem_desc *desc, bmd_problem **out, void *stream);
 
 /* Release a problem and its device memory (synchronises the device).  NULL-safe. */

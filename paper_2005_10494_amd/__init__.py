@@ -20,6 +20,7 @@ FP64, FP32_COMP = 0, 1
 _PREC = {"fp64": FP64, "f64": FP64, "fp32": FP32_COMP, "fp32_comp": FP32_COMP, "f32": FP32_COMP}
 _ALPHA = {"fwer": 0, "fwer_equal": 0, "bonferroni": 1, "fixed": 2}
 _EFFECT = {"step": 0, "paper": 1, "paper_gauss": 1}
+_DESIGN = {"cutoffs": 0, "alpha": 1}
 DRAW_FIELDS = 17
 DESIGN_FIELDS = 16
 
@@ -46,10 +47,14 @@ class _Desc(ctypes.Structure):
         ("paper_events", ctypes.c_double), ("indicator_width", ctypes.c_double),
         ("bandwidth", ctypes.c_double * 6), ("gh_nodes", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("scenario_id", ctypes.c_uint32),
+        ("design_space", ctypes.c_int32), ("r_lo", ctypes.c_double), ("r_hi", ctypes.c_double),
     ]
 
 
 _lib = None
+
+#: version of include/bmd.h this binding marshals (its descriptor layout)
+ABI_VERSION = 2
 
 #: every entry point declared in include/bmd.h, with (restype, argtypes)
 SIGNATURES = {
@@ -90,6 +95,8 @@ def library():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        if L.bmd_abi_version() != ABI_VERSION:
+            raise ImportError(f"{LIB_PATH} has ABI {L.bmd_abi_version()}, this binding needs {ABI_VERSION}: rebuild it")
         _lib = L
     return _lib
 
@@ -138,6 +145,9 @@ def make_desc(spec: dict) -> _Desc:
     D.gh_nodes = int(spec.get("gh_nodes", 0))
     D.seed = int(spec.get("seed", 0))
     D.scenario_id = int(spec.get("scenario", 0))
+    D.design_space = _DESIGN[spec.get("design", "cutoffs")]
+    D.r_lo = float(spec.get("r_lo", 0.0))
+    D.r_hi = float(spec.get("r_hi", 0.0))
     return D
 
 

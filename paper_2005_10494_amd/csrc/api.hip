@@ -97,7 +97,7 @@ double host_orthant(const std::vector<double>& v, double rho, const double* x, c
 // reference to `target` relative error at probe points spanning the cutoffs
 // the problem can produce (design cutoffs and drawn responder cutoffs).
 int choose_gh(const bmd_problem_desc& d, double target) {
-    if (d.d == 1) return 4;   // closed forms; tables unused
+    if (d.d == 1 || d.design_space == BMD_DESIGN_ALPHA) return 4;   // closed forms; tables unused
     static const int cand[] = {4, 8, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 128};
     std::vector<double> xr(128), wr(128);
     gauss_hermite_prob(128, xr.data(), wr.data());
@@ -175,7 +175,29 @@ bmd_status validate(const bmd_problem_desc* d, bool* grid) {
     if (!finite(d->indicator_width) || d->indicator_width < 0.0) return fail(BMD_ERANGE, "indicator_width must be >= 0");
     if (d->gh_nodes != 0 && (d->gh_nodes < 4 || d->gh_nodes > kMaxGH || d->gh_nodes % 4 != 0))
         return fail(BMD_ERANGE, "gh_nodes must be 0 or a multiple of 4 in [4, 128]");
+    if (d->design_space == BMD_DESIGN_ALPHA) {
+        if (d->effect != BMD_EFFECT_PAPER_GAUSS || d->alpha_rule != BMD_ALPHA_FWER_EQUAL)
+            return fail(BMD_EINVAL, "alpha designs need the Formula 10 prior and the FWER-boundary rule");
+        if (!any || d->d > 2) return fail(BMD_ERANGE, "alpha designs are a grid over alpha_1 or (r_2, alpha_1)");
+        if (!(d->q_hi < d->alpha0)) return fail(BMD_ERANGE, "alpha_1 range must lie inside (0, alpha0)");
+        if (!finite(d->r_lo) || !finite(d->r_hi) || !(d->r_lo > 0.0 && d->r_hi <= 0.95) ||
+            (d->d == 2 && !(d->r_lo < d->r_hi)))
+            return fail(BMD_ERANGE, "need 0 < r_lo %s r_hi <= 0.95", d->d == 2 ? "<" : "and");
+    } else if (d->design_space != BMD_DESIGN_CUTOFFS) {
+        return fail(BMD_EINVAL, "unknown design_space %d", d->design_space);
+    }
     return BMD_OK;
+}
+
+// Coordinate range of grid axis j (host copy of the device rule).
+void axis_range(const bmd_problem_desc& d, int j, double* lo, double* hi) {
+    if (d.design_space == BMD_DESIGN_ALPHA && d.d == 2 && j == 0) {
+        *lo = d.r_lo;
+        *hi = d.r_hi;
+    } else {
+        *lo = d.q_lo;
+        *hi = d.q_hi;
+    }
 }
 
 bmd_status ensure(void** buf, size_t* cap, size_t need) {
@@ -265,7 +287,7 @@ bmd_status bmd_create_problem(const bmd_problem_desc* desc, bmd_problem** out, v
     // bivariate quadrature's supported range (sqrt(r) <= 0.975).
     std::vector<double> ghx(kPrecomputeGH), ghw(kPrecomputeGH);
     gauss_hermite_prob(kPrecomputeGH, ghx.data(), ghw.data());
-    {
+    if (d.design_space == BMD_DESIGN_CUTOFFS) {
         double rmax;
         if (d.d == 1) rmax = 1.0 - d.q_lo;
         else rmax = host_orthant(std::vector<double>(d.d, host_quantile(d.q_lo)), d.rho_b, ghx.data(), ghw.data(),
@@ -303,6 +325,9 @@ bmd_status bmd_create_problem(const bmd_problem_desc* desc, bmd_problem** out, v
     }
     P.q_lo = d.q_lo;
     P.q_hi = d.q_hi;
+    P.design_space = d.design_space;
+    P.r_lo = d.r_lo;
+    P.r_hi = d.r_hi;
     P.rho_b = d.rho_b;
     P.sr = std::sqrt(d.rho_b);
     P.sq = std::sqrt(1.0 - d.rho_b);
@@ -400,7 +425,9 @@ bmd_status bmd_create_problem(const bmd_problem_desc* desc, bmd_problem** out, v
             const int m = d.m[j];
             p->w_off[j] = static_cast<int64_t>(W.size());
             std::vector<double> q(m);
-            for (int i = 0; i < m; ++i) q[i] = host_grid(d.q_lo, d.q_hi, i, m);
+            double lo, hi;
+            axis_range(d, j, &lo, &hi);
+            for (int i = 0; i < m; ++i) q[i] = host_grid(lo, hi, i, m);
             for (int i = 0; i < m; ++i) {
                 double den = 0.0;
                 const size_t row = W.size();
@@ -424,8 +451,10 @@ bmd_status bmd_create_problem(const bmd_problem_desc* desc, bmd_problem** out, v
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = launch_design_precompute(p, s);
-    if (e == hipSuccess) e = launch_axis_tables(p, BMD_FP64, s);
-    if (e == hipSuccess) e = launch_axis_tables(p, BMD_FP32_COMP, s);
+    if (d.design_space == BMD_DESIGN_CUTOFFS) {   // the alpha design space has no cutoff axes
+        if (e == hipSuccess) e = launch_axis_tables(p, BMD_FP64, s);
+        if (e == hipSuccess) e = launch_axis_tables(p, BMD_FP32_COMP, s);
+    }
     if (e != hipSuccess) {
         free_problem(p);
         return hip_fail(e, "setup kernels");

@@ -27,6 +27,8 @@ struct DevProblem {
     int64_t stride[kMaxDim];   // stride[j] = prod_{l>j} m_l
     int mmax;
     double q_lo, q_hi;
+    int design_space;          // bmd_design_space
+    double r_lo, r_hi;         // alpha design space: subgroup-fraction axis (d = 2) or r_2 = r_lo
     double rho_b, sr, sq;      // sqrt(rho_b), sqrt(1 - rho_b)
     double info, sqrtI;
     double alpha0;
@@ -163,8 +165,9 @@ int grad_chunk(int prec, int d, int K);
 int grad_blocks_per_cu(const bmd_problem* p, int prec);   // resident gradient workgroups per CU
 hipError_t launch_grad(const bmd_problem* p, int prec, const double* d_q, int64_t B, int64_t M, void* ws,
                        int n_slices, int64_t slice_len, double* obj, double* gq, double* gmu, hipStream_t s);
-// Batched form.  Sweep records are filled on the host (batch_record_bytes
-// each, written by batch_fill_record for scenario `scenario` of the batch);
+// Batched form.  Sweep records are filled on the host (batch_record_bytes, the
+// record size and the stride the kernel indexes them with, each written by
+// batch_fill_record for scenario `scenario` of the batch);
 // one sweep launch per (precision, d, kernel kind), one workgroup per item.
 DrawArrays<double> draws_fp64_at(const bmd_problem* p, int64_t M, void* ws);
 DrawArrays<float> draws_fp32_at(const bmd_problem* p, int64_t M, void* ws);

@@ -17,13 +17,18 @@ namespace bmd {
 
 namespace {
 
-// One problem of a batch, as the sweep bodies read it.
+// One problem of a batch, as the sweep bodies read it.  The host packs the
+// records at stride sizeof(BatchRecord<T>) and the kernel indexes them the
+// same way; 16-byte alignment keeps every record on a 16-byte boundary for
+// the kernel's wide scalar loads.
 template <typename T>
-struct BatchRecord {
+struct alignas(16) BatchRecord {
     EvalArgs<T> a;
     MfmaGeom geo;
     int scenario;      // index of the problem in the batch (left / t_done slot)
 };
+static_assert(sizeof(BatchRecord<float>) % 16 == 0 && sizeof(BatchRecord<double>) % 16 == 0,
+              "record stride must equal its aligned size");
 
 // One work item per workgroup: item blockIdx.x of the list, which is sorted
 // costliest first, so the hardware dispatcher hands the long items out first
@@ -104,8 +109,7 @@ const void* phase_kernel(const bmd_problem* p, int prec) {
 }  // namespace
 
 size_t batch_record_bytes(int prec) {
-    const size_t b = prec == BMD_FP64 ? sizeof(BatchRecord<double>) : sizeof(BatchRecord<float>);
-    return (b + 15) / 16 * 16;
+    return prec == BMD_FP64 ? sizeof(BatchRecord<double>) : sizeof(BatchRecord<float>);
 }
 
 void batch_fill_record(int prec, void* dst, const bmd_problem* p, void* draws_ws, int64_t M, int64_t slice_len,

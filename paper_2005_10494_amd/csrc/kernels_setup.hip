@@ -9,6 +9,13 @@ namespace bmd {
 namespace {
 
 // Decode a row-major grid index (axis 0 slowest).
+// Coordinate of grid index i on axis j: the subgroup-fraction axis of the
+// alpha design space, else a cutoff quantile (or the alpha_1 axis).
+__device__ __forceinline__ double axis_coord(const DevProblem& P, int j, int i) {
+    if (P.design_space == BMD_DESIGN_ALPHA && P.d == 2 && j == 0) return grid_coord(P.r_lo, P.r_hi, i, P.m[0]);
+    return grid_coord(P.q_lo, P.q_hi, i, P.m[j]);
+}
+
 __device__ __forceinline__ void decode(const DevProblem& P, int64_t g, int* idx) {
 #pragma unroll
     for (int j = 0; j < kMaxDim; ++j) {
@@ -73,6 +80,30 @@ __device__ double zstar(double rho, double alpha0, const double* __restrict__ gl
     return z;
 }
 
+// Second critical value on the FWER boundary given the first (Formula 2 for
+// two nested tests): FWER(z2) = Phi(-z1) + Phi(-z2) - Phi_2(-z1, -z2; rho) =
+// alpha0, which falls in z2 with derivative -phi(z2) Phi((z1 - rho z2) /
+// sqrt(1 - rho^2)).  Newton steps inside the bracket [level alpha0 for the
+// second test alone, level alpha0 - alpha_1 (the union bound)], bisection when
+// a step leaves it.  Needs alpha_1 = Phi(-z1) < alpha0.
+__device__ double z2_on_fwer(double z1, double rho, double alpha0, const double* __restrict__ gl) {
+    const double a1 = norm_cdf(-z1);
+    double lo = -norm_quantile(alpha0), hi = -norm_quantile(alpha0 - a1);
+    double z = 0.5 * (lo + hi);
+    const double c = 1.0 / sqrt((1.0 - rho) * (1.0 + rho));
+    for (int it = 0; it < 60; ++it) {
+        const double F = a1 + norm_cdf(-z) - bvn_setup(-z1, -z, rho, gl) - alpha0;
+        if (F > 0.0) lo = z; else hi = z;
+        const double dF = -norm_pdf(z) * norm_cdf((z1 - rho * z) * c);
+        double zn = z - F / dF;
+        if (!(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
+        const double step = fabs(zn - z);
+        z = zn;
+        if (step <= 4e-16 * fabs(z) || hi - lo <= 4e-16 * fabs(z)) break;
+    }
+    return z;
+}
+
 __global__ __launch_bounds__(128) void k_design_precompute(DevProblem P, const double* __restrict__ ghp, int Kp,
                                     const double* __restrict__ gl, double* __restrict__ r_out,
                                     double* __restrict__ z1_out, double* __restrict__ z2_out) {
@@ -80,6 +111,15 @@ __global__ __launch_bounds__(128) void k_design_precompute(DevProblem P, const d
     if (g >= P.G) return;
     int idx[kMaxDim];
     decode(P, g, idx);
+    if (P.design_space == BMD_DESIGN_ALPHA) {
+        // (r_2, alpha_1) or alpha_1 at r_2 = r_lo; alpha_2 on the FWER boundary
+        const double r = P.d == 2 ? axis_coord(P, 0, idx[0]) : P.r_lo;
+        const double z1 = -norm_quantile(axis_coord(P, P.d - 1, idx[P.d - 1]));
+        r_out[g] = r;
+        z1_out[g] = z1;
+        z2_out[g] = z2_on_fwer(z1, sqrt(r), P.alpha0, gl);
+        return;
+    }
     double c[kMaxDim];
     double r;
     if (P.d == 1) {
@@ -237,8 +277,8 @@ __global__ __launch_bounds__(128) void k_inspect_designs(DevProblem P, int64_t g
     double* f = out + t * BMD_DESIGN_FIELDS;
     for (int i = 0; i < BMD_DESIGN_FIELDS; ++i) f[i] = 0.0;
     for (int j = 0; j < P.d; ++j) {
-        f[j] = grid_coord(P.q_lo, P.q_hi, idx[j], P.m[j]);
-        f[6 + j] = norm_quantile(f[j]);
+        f[j] = axis_coord(P, j, idx[j]);
+        f[6 + j] = P.design_space == BMD_DESIGN_ALPHA ? 0.0 : norm_quantile(f[j]);
     }
     f[12] = r[g];
     f[13] = sqrt(r[g]);

@@ -80,6 +80,14 @@ def alpha_design(m_alpha: int, r=0.365, m_r: int = 0, r_range=(0.05, 0.95), n_dr
     return p
 
 
+def alpha_grid() -> dict:
+    """Sec. 3's two-population experiment under condition (b) as a design grid:
+    r_2 over [0.05, 0.95] in steps of 0.005 (181 points) times alpha_1 over
+    [0.0005, 0.0245] in steps of 0.0001 (241 points), M = 1,000,000 draws;
+    smoothing sd 0.02 in r_2 and 0.0005 in alpha_1."""
+    return alpha_design(241, m_r=181, r_range=(0.05, 0.95), n_draws=1_000_000, bandwidth=(0.02, 0.0005))
+
+
 def design_points(n: int, d: int, seed: int = 1, lo: float = 0.1, hi: float = 0.9) -> np.ndarray:
     """Continuous design points, iid U(lo, hi)^d (cutoff quantiles)."""
     rng = np.random.default_rng(seed)

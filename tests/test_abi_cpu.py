@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
     out = subprocess.run(["nm", "-D", "--defined-only", bmd.LIB_PATH], capture_output=True, text=True).stdout
     exported = set(re.findall(r" T (bmd_\w+)", out))
     assert set(names) <= exported
-    assert lib.bmd_abi_version() == 1
+    assert lib.bmd_abi_version() == bmd.ABI_VERSION == 2
 
 
 def test_descriptor_layout_matches_c(tmp_path):
@@ -73,6 +73,30 @@ def test_validation_rejects_before_any_launch(change, status):
     st, msg = _create_status(spec)
     assert st == status, msg
     assert msg
+
+
+@pytest.mark.parametrize("change,status", [
+    ({"effect": "step"}, -1), ({"alpha_rule": "bonferroni"}, -1),
+    ({"q_hi": 0.025}, -2), ({"q_hi": 0.03}, -2), ({"r_lo": 0.0}, -2), ({"r_hi": 0.96}, -2),
+    ({"r_lo": 0.6, "r_hi": 0.4}, -2), ({"d": 3, "m": [4, 4, 4], "bandwidth": [0.1] * 3}, -2),
+    ({"m": [0, 0]}, -2),
+])
+def test_alpha_design_validation(change, status):
+    """The alpha design space (Sec. 2.2 levels, n = 2) rejects what it does not cover."""
+    spec = W.alpha_design(8, m_r=5)
+    spec.update(change)
+    st, msg = _create_status(spec)
+    assert st == status, msg
+    assert msg
+
+
+def test_unknown_design_space():
+    lib = bmd.library()
+    desc = bmd.make_desc(W.alpha_design(8))
+    desc.design_space = 7
+    h = ctypes.c_void_p()
+    assert lib.bmd_create_problem(ctypes.byref(desc), ctypes.byref(h), None) == -1
+    assert lib.bmd_last_error()
 
 
 def test_null_arguments():

@@ -54,7 +54,8 @@ struct DrawArrays {
     T* tauT;    // [M]  tau_0 (one-biomarker closed form)
     T* e1;      // [M]  paper prior normals
     T* e2;      // [M]
-    int32_t* thr;   // [d][M] first grid index whose cutoff quantile exceeds tau_j
+    int32_t* thr;   // [M][d] first grid index whose cutoff quantile exceeds tau_j
+    T* q4;      // [M][4] (b0, b1, mu1, 0): one 4-vector per draw for the matrix-core sweep
     double* tau;    // [d][M]
     T* B;       // [M][K][d] Phi((sqrt(rho) x_m - t_j)/sqrt(1-rho)), GH weight folded into j = 0
     int64_t M;

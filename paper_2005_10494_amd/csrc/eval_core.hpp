@@ -34,7 +34,7 @@ struct GlobalDraws {
     __device__ T tauT(int64_t k) const { return D.tauT[k]; }
     __device__ T e1(int64_t k) const { return D.e1[k]; }
     __device__ T e2(int64_t k) const { return D.e2[k]; }
-    __device__ int thr(int j, int64_t k) const { return D.thr[j * D.M + k]; }
+    __device__ int thr(int j, int64_t k) const { return D.thr[k * d + j]; }
     __device__ double tau(int j, int64_t k) const { return D.tau[j * D.M + k]; }
     __device__ const T* B(int64_t k) const { return D.B + k * d * D.K; }
 };

@@ -181,7 +181,7 @@ __device__ __forceinline__ void draw_one(const DevProblem& P, const double* __re
             const double tau = affine_uniform(P.tau_lo, P.tau_hi, u[2 + j]);
             t[j] = norm_quantile(tau);
             D.tau[j * M + kk] = tau;
-            if (P.G > 0) D.thr[j * M + kk] = count_le(P, j, tau);
+            if (P.G > 0) D.thr[kk * P.d + j] = count_le(P, j, tau);
         }
         double PR;
         if (P.d == 1) {
@@ -205,6 +205,10 @@ __device__ __forceinline__ void draw_one(const DevProblem& P, const double* __re
         D.PR[kk] = static_cast<T>(PR);
         D.mu1[kk] = static_cast<T>(P.sqrtI * (b0 + b1 * PR));
         D.tauT[kk] = static_cast<T>(D.tau[kk]);
+        D.q4[4 * kk + 0] = D.b0[kk];
+        D.q4[4 * kk + 1] = D.b1[kk];
+        D.q4[4 * kk + 2] = D.mu1[kk];
+        D.q4[4 * kk + 3] = T(0);
     } else {
         const double e1 = norm_quantile(u[0]);
         const double e2 = norm_quantile(u[1]);
@@ -328,6 +332,7 @@ static DrawArrays<T> carve(const bmd_problem* p, int prec, int64_t M, void* ws) 
     D.e1 = reinterpret_cast<T*>(take(sizeof(T) * M));
     D.e2 = reinterpret_cast<T*>(take(sizeof(T) * M));
     D.thr = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * d * M));
+    D.q4 = reinterpret_cast<T*>(take(sizeof(T) * 4 * M));
     D.tau = reinterpret_cast<double*>(take(sizeof(double) * d * M));
     D.B = reinterpret_cast<T*>(take(sizeof(T) * (d >= 2 ? static_cast<size_t>(M) * d * K : 1)));
     D.M = M;
@@ -339,7 +344,8 @@ size_t draw_workspace_bytes(const bmd_problem* p, int prec, int64_t M) {
     const size_t T = prec == BMD_FP64 ? 8 : 4;
     const int d = p->P.d, K = p->tab[prec].K;
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    return 7 * al(T * M) + al(4 * d * M) + al(8 * d * M) + al(T * (d >= 2 ? static_cast<size_t>(M) * d * K : 1));
+    return 7 * al(T * M) + al(4 * d * M) + al(4 * T * M) + al(8 * d * M) +
+           al(T * (d >= 2 ? static_cast<size_t>(M) * d * K : 1));
 }
 
 DrawArrays<double> draws_fp64(const bmd_problem* p, int64_t M, const void* ws) {

@@ -68,6 +68,28 @@ __device__ __forceinline__ double bit_select(unsigned long long m, double a, dou
                                                       (static_cast<unsigned long long>(__double_as_longlong(b)) & ~m)));
 }
 
+// Copy n units of U bytes (U = 4 or 16) from global memory into LDS through
+// the vector memory unit's load-to-LDS path: no registers are involved and
+// completion is tracked by the wavefront's vmcnt.  Every wavefront of the
+// workgroup calls it; wavefront w moves units 64 (w + 4 t) + lane.  src and dst
+// are U-byte aligned; dst offsets are wave-uniform, as the instruction needs.
+template <int U>
+__device__ __forceinline__ void lds_dma(void* dst, const void* src, int n, int wave, int lane) {
+    static_assert(U == 4 || U == 16, "unit of 4 or 16 bytes");
+    char* d = static_cast<char*>(dst);
+    const char* s = static_cast<const char*>(src);
+    for (int r = wave * 64; r < n; r += kEvalBlock) {
+        if (r + lane < n) {
+            const void* g = s + static_cast<size_t>(U) * (r + lane);
+            auto* l = (__attribute__((address_space(3))) void*)(d + static_cast<size_t>(U) * r);
+            if constexpr (U == 16)
+                __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
+            else
+                __builtin_amdgcn_global_load_lds(g, l, 4, 0, 0);
+        }
+    }
+}
+
 typedef float mf_f4 __attribute__((ext_vector_type(4)));
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ mf_f4 mf_step(float a, float b, mf_f4 c) {
@@ -107,8 +129,8 @@ __device__ __forceinline__ void mfma_tile_body(const EvalArgs<T>& a, const MfmaG
     const int CH = geo.chunk;
     T* sO = reinterpret_cast<T*>(lds);                                  // [CH][256]
     T* sB = sO + static_cast<size_t>(CH) * kEvalBlock;                   // [CH][K][D]
-    Quad<T>* sq = reinterpret_cast<Quad<T>*>(sB + static_cast<size_t>(CH) * D * K);  // [CH] (b0, b1, mu1, -)
-    int* sthr = reinterpret_cast<int*>(sq + CH);                         // [CH][D]
+    Quad<T>* sq0 = reinterpret_cast<Quad<T>*>(sB + static_cast<size_t>(CH) * D * K);  // 2 x [CH] (b0, b1, mu1, -)
+    int* sthr = reinterpret_cast<int*>(sq0 + 2 * CH);                    // [CH][D]
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -166,21 +188,22 @@ __device__ __forceinline__ void mfma_tile_body(const EvalArgs<T>& a, const MfmaG
 
     const int64_t kb = static_cast<int64_t>(slice) * a.slice_len;
     const int64_t ke = min(M, kb + a.slice_len);
+    // Stage draws [k0, k0 + nk): their B tables, thresholds and (b0, b1, mu1)
+    // quads are contiguous in HBM and land in LDS by DMA.
+    auto stage = [&](int64_t k0, int nk, Quad<T>* sq) {
+        lds_dma<16>(sB, a.D.B + k0 * D * K, static_cast<int>(nk * D * K * sizeof(T) / 16), wave, lane);
+        lds_dma<16>(sq, a.D.q4 + 4 * k0, static_cast<int>(nk * sizeof(Quad<T>) / 16), wave, lane);
+        lds_dma<4>(sthr, a.D.thr + k0 * D, nk * D, wave, lane);
+    };
+    if (kb < ke) stage(kb, static_cast<int>(min<int64_t>(CH, ke - kb)), sq0);
     double s1 = 0.0, s2 = 0.0;
-    for (int64_t k0 = kb; k0 < ke; k0 += CH) {
+    int buf = 0;
+    for (int64_t k0 = kb; k0 < ke; k0 += CH, buf ^= 1) {
         const int nk = __builtin_amdgcn_readfirstlane(static_cast<int>(min<int64_t>(CH, ke - k0)));
-        __syncthreads();
-        // stage the chunk's draws (the B rows of consecutive draws are contiguous)
-        {
-            const T* src = a.D.B + k0 * D * K;
-            for (int e = tid; e < nk * D * K; e += kEvalBlock) sB[e] = src[e];
-        }
-        for (int e = tid; e < nk; e += kEvalBlock)
-            sq[e] = Quad<T>{a.D.b0[k0 + e], a.D.b1[k0 + e], a.D.mu1[k0 + e], T(0)};
-        for (int e = tid; e < nk * D; e += kEvalBlock) {
-            const int i = e / D, j = e % D;
-            sthr[e] = a.D.thr[j * M + k0 + i];
-        }
+        const Quad<T>* sq = sq0 + buf * CH;
+        // this wavefront's copies of the chunk have landed; after the barrier
+        // everyone's have, and phase B of the previous chunk is over (sO free)
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         // phase A: overlaps of the tile; a wavefront takes kChains draws per
         // pass (draws wave + 4c + 4 kChains t), one independent MFMA chain each.
@@ -243,6 +266,9 @@ __device__ __forceinline__ void mfma_tile_body(const EvalArgs<T>& a, const MfmaG
             default: if constexpr (D > 5) phase_a(std::integral_constant<int, 5>{}); break;
         }
         __syncthreads();
+        // The next chunk's copies overlap phase B: sB and sthr are no longer
+        // read, and its quads go to the other buffer.
+        if (k0 + CH < ke) stage(k0 + CH, static_cast<int>(min<int64_t>(CH, ke - k0 - CH)), sq0 + (buf ^ 1) * CH);
         // phase B: bivariate normal part for this thread's design
 #pragma unroll 2
         for (int i = 0; i < nk; ++i) {
@@ -270,7 +296,7 @@ __device__ __forceinline__ void mfma_tile_body(const EvalArgs<T>& a, const MfmaG
 // LDS bytes of the matrix-core body for a chunk of `chunk` draws.
 template <typename T>
 inline size_t mfma_lds_bytes(int chunk, int d, int K) {
-    return sizeof(T) * static_cast<size_t>(chunk) * (kEvalBlock + static_cast<size_t>(d) * K + 4) +
+    return sizeof(T) * static_cast<size_t>(chunk) * (kEvalBlock + static_cast<size_t>(d) * K + 8) +
            sizeof(int) * static_cast<size_t>(chunk) * d;
 }
 

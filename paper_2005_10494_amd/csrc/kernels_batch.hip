@@ -39,10 +39,10 @@ static_assert(sizeof(BatchRecord<float>) % 16 == 0 && sizeof(BatchRecord<double>
 // argument, read-only for the launch, so their wave-uniform fields are fetched
 // with scalar loads.  The last item of a problem stamps its completion time.
 // Register bounds of the FP32 matrix-core items: five wavefronts per SIMD up to
-// three biomarkers, four up to five (six keeps its natural three: bounding it
-// would spill node coefficients inside the draw loop).
+// three biomarkers, four beyond (at six, two node coefficients of the 10- and
+// 12-node rules are reloaded from scratch; the other rules never touch them).
 template <typename T, int D, int NMAX, bool MF>
-__global__ __launch_bounds__(kEvalBlock, sizeof(T) == 4 && MF && D <= 5 ? (D <= 3 ? 5 : 4) : 1) void k_batch(BatchPhase ph, const BatchRecord<T>* __restrict__ recs) {
+__global__ __launch_bounds__(kEvalBlock, sizeof(T) == 4 && MF ? (D <= 3 ? 5 : 4) : 1) void k_batch(BatchPhase ph, const BatchRecord<T>* __restrict__ recs) {
     extern __shared__ __align__(16) char lds[];
     if (threadIdx.x == 0) atomicMin(ph.t_start, static_cast<unsigned long long>(wall_clock64()));
     const int4 it = ph.items[blockIdx.x];

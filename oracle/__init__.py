@@ -312,3 +312,48 @@ def success_with_draw(prob, q, draw: dict):
         dr.tau[j] = draw["tau"][j]
         dr.t[j] = draw["t"][j]
     return lib().or_success(ctypes.byref(s), ctypes.byref(ds), ctypes.byref(dr))
+
+
+# ---- continuous refinement ----------------------------------------------------
+
+REFINE_TRIALS = 8        # step sizes tried per iteration: s, s/2, ..., s/128
+REFINE_FIRST_STEP = 0.05  # largest coordinate move of the first trial (quantile units)
+REFINE_MAX_STEP = 0.1
+REFINE_ARMIJO = 1e-4
+
+
+def refine_design(prob, q0, M, max_iter=50, tol=1e-6):
+    """Local maximiser of the Monte Carlo objective from a start point (Sec. 2.3:
+    the grid's best point refined by a gradient method).  Projected gradient
+    ascent inside the box [q_lo, q_hi]^d on the objective and gradient of
+    grad_points (draws 0..M-1 throughout, so the objective is one deterministic
+    function of q).  Each iteration tries the steps q + t_j g / max|g| with
+    t_j = s 2^-j, j = 0..7, clipped to the box, and accepts the first that
+    gains at least 1e-4 g.(q_j - q) (Armijo); the next s is twice the accepted
+    t_j, at most 0.1.  Stops when no trial gains, when the accepted move is
+    below tol in every coordinate, or after max_iter iterations.  Returns
+    (q, objective at q, iterations)."""
+    lo, hi = float(prob["q_lo"]), float(prob["q_hi"])
+    q = np.clip(np.asarray(q0, dtype=np.float64), lo, hi)
+    f, g, _ = grad_points(prob, q[None, :], M)
+    f, g = float(f[0]), g[0]
+    s = REFINE_FIRST_STEP
+    it = 0
+    while it < max_iter:
+        gn = float(np.max(np.abs(g)))
+        if gn == 0.0:
+            break
+        t = s * 0.5 ** np.arange(REFINE_TRIALS)
+        trials = np.clip(q[None, :] + (t[:, None] / gn) * g[None, :], lo, hi)
+        ft, gt, _ = grad_points(prob, trials, M)
+        ok = [j for j in range(REFINE_TRIALS) if ft[j] >= f + REFINE_ARMIJO * float(np.dot(g, trials[j] - q))]
+        if not ok:
+            break
+        j = ok[0]
+        it += 1
+        move = float(np.max(np.abs(trials[j] - q)))
+        q, f, g = trials[j].copy(), float(ft[j]), gt[j].copy()
+        s = min(2.0 * t[j], REFINE_MAX_STEP)
+        if move < tol:
+            break
+    return q, f, it

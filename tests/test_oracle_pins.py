@@ -535,3 +535,36 @@ def test_alpha_design_grid_and_smoothing():
         assert O.make_design(p, q)["r"] == q[0]
     f = np.random.default_rng(5).uniform(0.5, 0.8, G)
     assert np.max(np.abs(O.smooth_direct(p, f) - O.smooth_separable(p, f))) < 1e-14
+
+
+# ---------------------------------------------------------------- continuous refinement
+
+def test_refinement_reaches_the_maximiser_of_a_deterministic_objective():
+    """With a point-mass prior (sd 0, fixed true cutoff) every draw is the same,
+    so the objective is one deterministic function of the cutoff; the refinement
+    from the grid's edge must reach the maximiser scipy finds on that function."""
+    from scipy.optimize import minimize_scalar
+    p = W.base_problem(1, None, 0.0, 0.05, width=0.02, sd_b0=0.0, sd_b1=0.0, tau_lo=0.55, tau_hi=0.55,
+                       mu_b1=0.6)
+    f = lambda x: float(O.eval_points(p, np.array([[x]]), 1, want_var=False)[0])  # noqa: E731
+    res = minimize_scalar(lambda x: -f(x), bounds=(0.05, 0.95), method="bounded", options={"xatol": 1e-8})
+    q, fq, it = O.refine_design(p, [0.2], 4, max_iter=200, tol=1e-9)
+    assert 1 <= it < 200
+    assert abs(q[0] - res.x) < 2e-5, (q, res.x)
+    assert fq >= -res.fun - 1e-10
+    # the objective's gradient vanishes there (interior maximum)
+    _, g, _ = O.grad_points(p, q[None, :], 1)
+    assert abs(g[0, 0]) < 1e-3
+
+
+def test_refinement_climbs_and_stays_in_the_box():
+    p = W.base_problem(2, None, 0.3, 0.05, width=0.01)
+    M = 600
+    q0 = np.array([0.15, 0.85])
+    f0 = float(O.grad_points(p, q0[None, :], M)[0][0])
+    q, fq, it = O.refine_design(p, q0, M, max_iter=30, tol=1e-7)
+    assert it >= 1 and fq > f0
+    assert np.all(q >= 0.05) and np.all(q <= 0.95)
+    # a start on the box edge with the gradient pointing out stays on the edge
+    qe, _, _ = O.refine_design(dict(p, q_hi=0.5), np.array([0.5, 0.5]), M, max_iter=5)
+    assert np.all(qe <= 0.5)

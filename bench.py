@@ -198,7 +198,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="3d", choices=["3d", "1d", "5d", "alpha", "grad", "batch"])
+    ap.add_argument("--workload", default="3d", choices=["3d", "1d", "5d", "alpha", "grad", "refine", "batch"])
     ap.add_argument("--batch-scale", type=float, default=1.0,
                     help="batch workload only: scale of the per-axis grids and of the draw range (1 = full size)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -229,6 +229,8 @@ def main():
         return
     if args.workload == "grad":
         return bench_grad(args)
+    if args.workload == "refine":
+        return bench_refine(args)
     if args.workload == "batch":
         return bench_batch(args)
     spec = workload(args.workload)
@@ -345,6 +347,47 @@ def bench_grad(args):
                             "max_abs_diff_objective": float((o32 - o64).abs().max()),
                             "max_abs_diff_grad_rel_to_max": float(max((g32 - g64).abs().max(),
                                                                       (m32 - m64).abs().max()) / scale)}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_refine(args):
+    """Continuous refinement (Sec. 2.3's local step): projected gradient ascent
+    on the 5-biomarker logistic-indicator objective from the centre of the
+    design box, M = 1e6 draws, 8 trial points per iteration; FP32 and FP64.
+    The value is gradient point-draws per second over the whole refinement."""
+    import torch
+    import paper_2005_10494_amd as bmd
+    from paper_2005_10494_amd import workloads as W
+    spec = W.grad_5d()
+    M = spec["n_draws"]
+    q0 = np.full(spec["d"], 0.5)
+    res = {}
+    with bmd.Problem(spec) as p:
+        for prec in ("fp32", "fp64"):
+            ts = []
+            for it in range(args.warmup + args.steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                q, f, n_it = p.refine_design(q0, M, prec, max_iter=40, tol=1e-5)
+                dt = time.perf_counter() - t0
+                if it >= args.warmup:
+                    ts.append(dt)
+                log(f"  refine {prec} step {it}: {1e3 * dt:.1f} ms, {n_it} iterations, objective {f:.6f}")
+            res[prec] = (float(np.mean(ts)), q, f, n_it)
+    t32, q32, f32, n32 = res["fp32"]
+    t64, q64, f64, n64 = res["fp64"]
+    pd32 = (1 + 8 * n32) * M   # start point and 8 trials per accepted step (a final rejected set not counted)
+    out = {"metric": "refinement: gradient point-draws per second (objective + d + 2 partials)",
+           "value": pd32 / t32, "unit": "point-draws/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * t32, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"projected gradient ascent, 5-biomarker continuous design from q = 0.5, "
+                                  f"M={M} draws, logistic indicator width {spec['width']}, 8 trials per iteration",
+                      "n_draws": M, "iterations": n32},
+           "result": {"q": q32.tolist(), "objective": f32},
+           "fp64": {"ms_per_step": 1e3 * t64, "iterations": n64, "q": q64.tolist(), "objective": f64},
+           "fp32_vs_fp64": {"speedup": t64 / t32, "max_abs_diff_q": float(np.max(np.abs(q32 - q64))),
+                            "abs_diff_objective": abs(f32 - f64)}}
     print(json.dumps(out), flush=True)
 
 

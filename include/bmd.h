@@ -203,6 +203,25 @@ bmd_status bmd_grad_design(bmd_problem *p, const double *d_q, int64_t B, uint64_
                            int32_t prec, double *d_obj, double *d_grad_q, double *d_grad_mu,
                            void *stream);
 
+/* Continuous refinement of a design (Sec. 2.3: the best grid point refined by
+ * a local gradient method): projected gradient ascent inside the box
+ * [q_lo, q_hi]^d on bmd_grad_design's objective (draws 0..n_draws-1 in every
+ * evaluation, so the objective is one deterministic function of q; smooth for
+ * indicator_width > 0).  Each iteration evaluates, in one bmd_grad_design call
+ * of 8 points, the steps q + t_j g / max|g| with t_j = s 2^-j (j = 0..7),
+ * clipped to the box, and accepts the first whose objective gains at least
+ * 1e-4 g.(q_j - q) (Armijo); s starts at 0.05 and becomes twice the accepted
+ * t_j, at most 0.1.  Stops when no trial gains, when the accepted move is below
+ * tol in every coordinate, or after max_iter iterations.
+ *   h_q0   [d] host, start point (clipped to the box)
+ *   h_q    [d] host, result;  *h_obj its objective;  *h_iters accepted steps
+ * Synchronises `stream`; allocates and frees a few hundred bytes of device
+ * memory.  ENOTSUP unless the prior is BMD_EFFECT_STEP and the design space is
+ * the cutoffs; ERANGE for max_iter outside [0, 10000] or tol < 0. */
+bmd_status bmd_refine_design(bmd_problem *p, const double *h_q0, uint64_t n_draws, int32_t prec,
+                             int32_t max_iter, double tol, double *h_q, double *h_obj, int32_t *h_iters,
+                             void *stream);
+
 /* Batched evaluation of n independent grid problems (the families of design
  * problems of Sec. 3) in one call: d_means[i] (FP64, [G_i], device) receives
  * problem i's mean surface for n_draws[i] draws, equal to bmd_eval_grid's up to

@@ -73,6 +73,9 @@ SIGNATURES = {
     "bmd_grad_design": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64,
                                        ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p]),
+    "bmd_refine_design": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
     "bmd_eval_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "bmd_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
@@ -228,6 +231,19 @@ class Problem:
                                          ctypes.c_void_p(gmu.data_ptr()) if gmu is not None else None,
                                          _stream(stream)))
         return obj, gq, gmu
+
+    def refine_design(self, q0, n_draws: int, precision="fp64", max_iter=50, tol=1e-6, stream=None):
+        """Local maximiser of the Monte Carlo objective from q0 (projected
+        gradient ascent in the design box); returns (q, objective, iterations)."""
+        q0 = np.ascontiguousarray(np.asarray(q0, dtype=np.float64).reshape(self.d))
+        q = np.zeros(self.d)
+        obj = ctypes.c_double()
+        its = ctypes.c_int32()
+        _check(library().bmd_refine_design(self._h, q0.ctypes.data_as(ctypes.c_void_p), int(n_draws),
+                                           _prec(precision), int(max_iter), float(tol),
+                                           q.ctypes.data_as(ctypes.c_void_p), ctypes.byref(obj),
+                                           ctypes.byref(its), _stream(stream)))
+        return q, obj.value, its.value
 
     def profile(self, enable: bool = True):
         _check(library().bmd_profile(self._h, 1 if enable else 0))

@@ -775,6 +775,86 @@ bmd_status run_batch_group(bmd_problem* const* ps, const std::vector<BatchPlan>&
 
 }  // namespace
 
+bmd_status bmd_refine_design(bmd_problem* p, const double* h_q0, uint64_t n_draws, int32_t prec, int32_t max_iter,
+                             double tol, double* h_q, double* h_obj, int32_t* h_iters, void* stream) {
+    g_err.clear();
+    if (!p || !h_q0 || !h_q || !h_obj || !h_iters) return fail(BMD_EINVAL, "NULL argument");
+    if (!valid_prec(prec)) return fail(BMD_EINVAL, "unknown precision %d", prec);
+    if (max_iter < 0 || max_iter > 10000 || !(tol >= 0.0)) return fail(BMD_ERANGE, "max_iter or tol out of range");
+    if (p->P.effect != BMD_EFFECT_STEP || p->P.design_space != BMD_DESIGN_CUTOFFS)
+        return fail(BMD_ENOTSUP, "refinement needs the step prior and cutoff designs");
+    constexpr int kTrials = 8;
+    constexpr double kFirstStep = 0.05, kMaxStep = 0.1, kArmijo = 1e-4;
+    const int d = p->P.d;
+    const double lo = p->P.q_lo, hi = p->P.q_hi;
+    DeviceGuard guard(p->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DeviceBuffer buf;
+    {
+        const hipError_t e = hipMalloc(&buf.ptr, sizeof(double) * kTrials * (2 * d + 1));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(BMD_ENOMEM, "refinement buffers: %s", hipGetErrorString(e));
+        }
+    }
+    double* d_q = static_cast<double*>(buf.ptr);
+    double* d_g = d_q + kTrials * d;
+    double* d_f = d_g + kTrials * d;
+    std::vector<double> q(d), g(d), tq(kTrials * d), tg(kTrials * d), tf(kTrials);
+    for (int j = 0; j < d; ++j) q[j] = std::min(hi, std::max(lo, h_q0[j]));
+    // objective and gradient at the n points of tq (host) -> tf, tg
+    auto evaluate = [&](int n) -> bmd_status {
+        HIP_TRY(hipMemcpyAsync(d_q, tq.data(), sizeof(double) * n * d, hipMemcpyHostToDevice, s), "refine upload");
+        const bmd_status st = bmd_grad_design(p, d_q, n, n_draws, prec, d_f, d_g, nullptr, s);
+        if (st != BMD_OK) return st;
+        HIP_TRY(hipMemcpyAsync(tf.data(), d_f, sizeof(double) * n, hipMemcpyDeviceToHost, s), "refine download");
+        HIP_TRY(hipMemcpyAsync(tg.data(), d_g, sizeof(double) * n * d, hipMemcpyDeviceToHost, s), "refine download");
+        HIP_TRY(hipStreamSynchronize(s), "refine sync");
+        return BMD_OK;
+    };
+    std::copy(q.begin(), q.end(), tq.begin());
+    bmd_status st = evaluate(1);
+    if (st != BMD_OK) return st;
+    double f = tf[0];
+    std::copy(tg.begin(), tg.begin() + d, g.begin());
+    double step = kFirstStep;
+    int it = 0;
+    while (it < max_iter) {
+        double gn = 0.0;
+        for (double x : g) gn = std::max(gn, std::fabs(x));
+        if (gn == 0.0) break;
+        double t[kTrials];
+        for (int k = 0; k < kTrials; ++k) {
+            t[k] = step * std::ldexp(1.0, -k);
+            for (int j = 0; j < d; ++j)
+                tq[k * d + j] = std::min(hi, std::max(lo, q[j] + (t[k] / gn) * g[j]));
+        }
+        st = evaluate(kTrials);
+        if (st != BMD_OK) return st;
+        int acc = -1;
+        for (int k = 0; k < kTrials && acc < 0; ++k) {
+            double slope = 0.0;
+            for (int j = 0; j < d; ++j) slope += g[j] * (tq[k * d + j] - q[j]);
+            if (tf[k] >= f + kArmijo * slope) acc = k;
+        }
+        if (acc < 0) break;
+        ++it;
+        double move = 0.0;
+        for (int j = 0; j < d; ++j) {
+            move = std::max(move, std::fabs(tq[acc * d + j] - q[j]));
+            q[j] = tq[acc * d + j];
+            g[j] = tg[acc * d + j];
+        }
+        f = tf[acc];
+        step = std::min(2.0 * t[acc], kMaxStep);
+        if (move < tol) break;
+    }
+    for (int j = 0; j < d; ++j) h_q[j] = q[j];
+    *h_obj = f;
+    *h_iters = it;
+    return BMD_OK;
+}
+
 bmd_status bmd_eval_batch(bmd_problem* const* ps, int32_t n, const uint64_t* n_draws, int32_t prec,
                           double* const* d_means, double* h_wall_ms, void* stream) {
     g_err.clear();

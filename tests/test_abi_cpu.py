@@ -107,6 +107,7 @@ def test_null_arguments():
     assert lib.bmd_grid_size(None) == 0
     assert lib.bmd_sweep_kind(None) == -1
     assert lib.bmd_gh_nodes(None, 0) == -1
+    assert lib.bmd_refine_design(None, None, 10, 0, 5, 1e-6, None, None, None, None) == -1
     lib.bmd_destroy_problem(None)  # NULL-safe
 
 

@@ -593,7 +593,7 @@ bmd_status bmd_grad_design(bmd_problem* p, const double* d_q, int64_t B, uint64_
     const int64_t M = static_cast<int64_t>(n_draws);
     const int chunk = grad_chunk(prec, p->P.d, p->tab[prec].K);
     // Draw slices: about kSweepRounds rounds of resident workgroups.
-    const int64_t bx = (B + 127) / 128;   // 128 points per workgroup
+    const int64_t bx = (B * grad_lanes(B) + 127) / 128;   // 128 threads per workgroup, grad_lanes(B) per point
     const int64_t resident = static_cast<int64_t>(p->n_cu) * grad_blocks_per_cu(p, prec);
     int64_t n_slices = (kSweepRounds * resident + bx - 1) / bx;
     n_slices = std::max<int64_t>(1, std::min<int64_t>({n_slices, (M + chunk - 1) / chunk, 65535}));

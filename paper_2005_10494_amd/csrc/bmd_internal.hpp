@@ -164,6 +164,7 @@ hipError_t launch_argmax(const bmd_problem* p, const double* v, int64_t n, doubl
 size_t grad_workspace_bytes(const bmd_problem* p, int prec, int64_t B, int n_slices, int64_t M, int64_t slice_len);
 int grad_chunk(int prec, int d, int K);
 int grad_blocks_per_cu(const bmd_problem* p, int prec);   // resident gradient workgroups per CU
+int grad_lanes(int64_t B);   // threads per point of the gradient kernel (few points share their draws)
 hipError_t launch_grad(const bmd_problem* p, int prec, const double* d_q, int64_t B, int64_t M, void* ws,
                        int n_slices, int64_t slice_len, double* obj, double* gq, double* gmu, hipStream_t s);
 // Batched form.  Sweep records are filled on the host (batch_record_bytes, the

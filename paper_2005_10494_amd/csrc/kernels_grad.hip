@@ -165,6 +165,7 @@ struct GradArgs {
     int slice0;            // first draw slice of this launch (a pass over draws)
     int64_t draw_k0;       // first draw held by the draw arrays of this pass
     double* partials;      // [n_slices][d+3][B]
+    int lanes;             // threads per point (a power of two <= 64): each takes every lanes-th draw pass
 };
 
 // Copy draws k0 .. k0+nk-1 of a pass (local indices) from the draw arrays into
@@ -188,15 +189,22 @@ __device__ void stage_chunk(const DrawArrays<T>& G, int K, const ChunkView<T>& c
     __syncthreads();
 }
 
-// R draws per pass over the point's node tables.
-template <typename T, int D, int NMAX, int R>
+// R draws per pass over the point's node tables.  SPLIT (few points): `lanes`
+// consecutive threads share a point; thread `sub` of a point takes the draw
+// passes sub, sub + lanes, ... of every chunk, and the point's sums are added
+// across those lanes (a fixed butterfly order) before they are written.  (A
+// separate instantiation: the runtime stride costs the one-lane kernel 17
+// VGPRs and a wavefront per SIMD.)
+template <typename T, int D, int NMAX, int R, bool SPLIT>
 __global__ __launch_bounds__(kGradBlock) void k_grad(GradArgs a, DrawArrays<T> Dr) {
     extern __shared__ __align__(16) char lds[];
     const ChunkView<T> ch = carve_chunk<T>(lds, a.chunk, a.K);
     const DevProblem& P = a.P;
     const int K = a.K;
     const int64_t Bn = a.B;
-    const int64_t b = static_cast<int64_t>(blockIdx.x) * kGradBlock + threadIdx.x;
+    const int L = SPLIT ? a.lanes : 1;
+    const int sub = static_cast<int>(threadIdx.x) & (L - 1);
+    const int64_t b = (static_cast<int64_t>(blockIdx.x) * kGradBlock + threadIdx.x) / L;
     const bool active = b < Bn;
     const int64_t bb = active ? b : Bn - 1;
     const double* f = a.info + bb * kPointFields;
@@ -247,7 +255,7 @@ __global__ __launch_bounds__(kGradBlock) void k_grad(GradArgs a, DrawArrays<T> D
     for (int64_t k0 = kb; k0 < ke; k0 += a.chunk) {
         const int nk = static_cast<int>(min<int64_t>(a.chunk, ke - k0));
         stage_chunk<T, D>(Dr, K, ch, k0 - a.draw_k0, nk);
-        for (int i0 = 0; i0 < nk; i0 += R) {
+        for (int i0 = sub * R; i0 < nk; i0 += R * L) {
             T O[R], dO[R][D], s[R][D], sp[R][D];
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
@@ -348,7 +356,14 @@ __global__ __launch_bounds__(kGradBlock) void k_grad(GradArgs a, DrawArrays<T> D
             }
         }
     }
-    if (active) {
+    for (int off = 1; off < L; off <<= 1) {   // the point's lanes are consecutive within one wavefront
+        s_obj += __shfl_xor(s_obj, off);
+        s_mu0 += __shfl_xor(s_mu0, off);
+        s_mu1 += __shfl_xor(s_mu1, off);
+#pragma unroll
+        for (int j = 0; j < D; ++j) s_q[j] += __shfl_xor(s_q[j], off);
+    }
+    if (active && sub == 0) {
         double* out = a.partials + static_cast<int64_t>(slice) * (D + 3) * Bn;
         out[b] = s_obj;
 #pragma unroll
@@ -375,19 +390,26 @@ __global__ void k_grad_finalize(int d, int64_t B, int64_t M, int n_slices, const
     }
 }
 
+template <typename T, int NMAX, int R, bool SPLIT>
+const void* grad_kernel(int d) {
+    switch (d) {
+        case 1: return reinterpret_cast<const void*>(k_grad<T, 1, NMAX, 1, SPLIT>);
+        case 2: return reinterpret_cast<const void*>(k_grad<T, 2, NMAX, R, SPLIT>);
+        case 3: return reinterpret_cast<const void*>(k_grad<T, 3, NMAX, R, SPLIT>);
+        case 4: return reinterpret_cast<const void*>(k_grad<T, 4, NMAX, R, SPLIT>);
+        case 5: return reinterpret_cast<const void*>(k_grad<T, 5, NMAX, R, SPLIT>);
+        default: return reinterpret_cast<const void*>(k_grad<T, 6, NMAX, R, SPLIT>);
+    }
+}
+
 template <typename T, int NMAX, int R>
 hipError_t launch_grad_typed(const GradArgs& ga, const DrawArrays<T>& Dr, int d, int n_slices, hipStream_t s) {
-    const dim3 grid(static_cast<unsigned>((ga.B + kGradBlock - 1) / kGradBlock), static_cast<unsigned>(n_slices));
+    const dim3 grid(static_cast<unsigned>((ga.B * ga.lanes + kGradBlock - 1) / kGradBlock),
+                    static_cast<unsigned>(n_slices));
     const size_t lds = chunk_bytes<T>(ga.chunk, d, ga.K);
-    switch (d) {
-        case 1: hipLaunchKernelGGL((k_grad<T, 1, NMAX, 1>), grid, dim3(kGradBlock), lds, s, ga, Dr); break;
-        case 2: hipLaunchKernelGGL((k_grad<T, 2, NMAX, R>), grid, dim3(kGradBlock), lds, s, ga, Dr); break;
-        case 3: hipLaunchKernelGGL((k_grad<T, 3, NMAX, R>), grid, dim3(kGradBlock), lds, s, ga, Dr); break;
-        case 4: hipLaunchKernelGGL((k_grad<T, 4, NMAX, R>), grid, dim3(kGradBlock), lds, s, ga, Dr); break;
-        case 5: hipLaunchKernelGGL((k_grad<T, 5, NMAX, R>), grid, dim3(kGradBlock), lds, s, ga, Dr); break;
-        default: hipLaunchKernelGGL((k_grad<T, 6, NMAX, R>), grid, dim3(kGradBlock), lds, s, ga, Dr); break;
-    }
-    return hipGetLastError();
+    const void* k = ga.lanes > 1 ? grad_kernel<T, NMAX, R, true>(d) : grad_kernel<T, NMAX, R, false>(d);
+    void* args[] = {const_cast<GradArgs*>(&ga), const_cast<DrawArrays<T>*>(&Dr)};
+    return hipLaunchKernel(k, grid, dim3(kGradBlock), args, lds, s);
 }
 
 }  // namespace
@@ -418,35 +440,22 @@ size_t grad_workspace_bytes(const bmd_problem* p, int prec, int64_t B, int n_sli
 int grad_blocks_per_cu(const bmd_problem* p, int prec) {
     const int d = p->P.d, K = p->tab[prec].K;
     const int C = grad_chunk(prec, d, K);
-    const void* f = nullptr;
-    size_t lds = 0;
-    if (prec == BMD_FP64) {
-        lds = chunk_bytes<double>(C, d, K);
-        switch (d) {
-            case 1: f = reinterpret_cast<const void*>(k_grad<double, 1, 24, 1>); break;
-            case 2: f = reinterpret_cast<const void*>(k_grad<double, 2, 24, 1>); break;
-            case 3: f = reinterpret_cast<const void*>(k_grad<double, 3, 24, 1>); break;
-            case 4: f = reinterpret_cast<const void*>(k_grad<double, 4, 24, 1>); break;
-            case 5: f = reinterpret_cast<const void*>(k_grad<double, 5, 24, 1>); break;
-            default: f = reinterpret_cast<const void*>(k_grad<double, 6, 24, 1>); break;
-        }
-    } else {
-        lds = chunk_bytes<float>(C, d, K);
-        switch (d) {
-            case 1: f = reinterpret_cast<const void*>(k_grad<float, 1, 12, 1>); break;
-            case 2: f = reinterpret_cast<const void*>(k_grad<float, 2, 12, 2>); break;
-            case 3: f = reinterpret_cast<const void*>(k_grad<float, 3, 12, 2>); break;
-            case 4: f = reinterpret_cast<const void*>(k_grad<float, 4, 12, 2>); break;
-            case 5: f = reinterpret_cast<const void*>(k_grad<float, 5, 12, 2>); break;
-            default: f = reinterpret_cast<const void*>(k_grad<float, 6, 12, 2>); break;
-        }
-    }
+    const void* f = prec == BMD_FP64 ? grad_kernel<double, 24, 1, false>(d) : grad_kernel<float, 12, 2, false>(d);
+    const size_t lds = prec == BMD_FP64 ? chunk_bytes<double>(C, d, K) : chunk_bytes<float>(C, d, K);
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kGradBlock, lds) != hipSuccess || nb < 1) {
         (void)hipGetLastError();
         nb = 1;
     }
     return nb;
+}
+
+// Threads per point: one when the points fill a workgroup, else the power of
+// two (at most a wavefront) that lets the few points fill one.
+int grad_lanes(int64_t B) {
+    int L = 1;
+    while (L < 64 && B * L < kGradBlock) L *= 2;
+    return L;
 }
 
 // Draws per LDS chunk: as many as fit in 48 KB, at most 32.
@@ -490,7 +499,7 @@ hipError_t launch_grad(const bmd_problem* p, int prec, const double* d_q, int64_
         const int slice0 = static_cast<int>(k0 / slice_len);
         const int ns = static_cast<int>((np + slice_len - 1) / slice_len);
         GradArgs ga{p->P, B, M, K, grad_chunk(prec, d, K), info, A, dA, p->d_gl, p->tab[prec].glw,
-                    slice_len, slice0, k0, part};
+                    slice_len, slice0, k0, part, grad_lanes(B)};
         e = prec == BMD_FP64 ? launch_grad_typed<double, 24, 1>(ga, draws_fp64_at(p, np, dws), d, ns, s)
                              : launch_grad_typed<float, 12, 2>(ga, draws_fp32_at(p, np, dws), d, ns, s);
         if (e != hipSuccess) return e;

@@ -60,7 +60,7 @@ class _Draw(ctypes.Structure):
                 ("PR", ctypes.c_double), ("e1", ctypes.c_double), ("e2", ctypes.c_double)]
 
 
-_ALPHA = {"fwer": 0, "fwer_equal": 0, "bonferroni": 1, "fixed": 2}
+_ALPHA = {"fwer": 0, "fwer_equal": 0, "bonferroni": 1, "fixed": 2, "split": 3}
 _EFFECT = {"step": 0, "paper": 1, "paper_gauss": 1}
 _DESIGN = {"cutoffs": 0, "alpha": 1}
 
@@ -357,3 +357,23 @@ def refine_design(prob, q0, M, max_iter=50, tol=1e-6):
         if move < tol:
             break
     return q, f, it
+
+
+# ---- optimal level split per design ----------------------------------------------
+
+def eval_grid_levels(prob, g_list, M, alphas):
+    """Sec. 2.4's optimal power at each design for n = 2 nested tests, over a list
+    of first-test levels: for each alpha_1 the second level goes on the FWER
+    boundary of the design (its r), Formula 5 is estimated on draws 0..M-1, and
+    the largest estimate and the index of its level (ties: the lowest) are kept."""
+    best, best_k = None, None
+    for k, a1 in enumerate(alphas):
+        pk = dict(prob, alpha_rule="split", alpha_fixed=(float(a1), 0.0))
+        m, _ = eval_grid(pk, g_list, M)
+        if best is None:
+            best, best_k = m.copy(), np.zeros(len(m), dtype=np.int64)
+        else:
+            up = m > best
+            best[up] = m[up]
+            best_k[up] = k
+    return best, best_k

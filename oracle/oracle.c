@@ -416,6 +416,10 @@ void or_make_design(const or_problem *p, const double *q, or_design *o)
     case OR_ALPHA_BONFERRONI:
         o->z1 = o->z2 = -or_Phiinv(0.5 * p->alpha0);
         break;
+    case OR_ALPHA_SPLIT:
+        o->z1 = -or_Phiinv(p->alpha_fixed[0]);
+        o->z2 = or_z2_fwer(o->z1, o->r, p->alpha0);
+        break;
     default:
         o->z1 = p->alpha_fixed[0] > 0.0 ? -or_Phiinv(p->alpha_fixed[0]) : INFINITY;
         o->z2 = p->alpha_fixed[1] > 0.0 ? -or_Phiinv(p->alpha_fixed[1]) : INFINITY;

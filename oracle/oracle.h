@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-enum { OR_ALPHA_FWER_EQUAL = 0, OR_ALPHA_BONFERRONI = 1, OR_ALPHA_FIXED = 2 };
+enum { OR_ALPHA_FWER_EQUAL = 0, OR_ALPHA_BONFERRONI = 1, OR_ALPHA_FIXED = 2, OR_ALPHA_SPLIT = 3 };
 enum { OR_EFFECT_STEP = 0, OR_EFFECT_PAPER_GAUSS = 1 };
 enum { OR_DESIGN_CUTOFFS = 0, OR_DESIGN_ALPHA = 1 };
 
@@ -43,7 +43,9 @@ typedef struct {
     double info;            /* information units I (paper: I_3)                 */
     double alpha0;          /* family-wise error rate                            */
     int32_t alpha_rule;     /* OR_ALPHA_*                                        */
-    double alpha_fixed[2];  /* fixed levels (rule FIXED); 0 switches a test off  */
+    double alpha_fixed[2];  /* fixed levels (rule FIXED); 0 switches a test off;
+                               rule SPLIT: alpha_fixed[0] is the first level and
+                               the second is put on the FWER boundary (Formula 2) */
     int32_t effect;         /* OR_EFFECT_*                                       */
     double mu_b0, sd_b0;    /* step prior: baseline effect ~ N(mu_b0, sd_b0^2)   */
     double mu_b1, sd_b1;    /* step prior: responder effect ~ N(mu_b1, sd_b1^2)  */

@@ -568,3 +568,39 @@ def test_refinement_climbs_and_stays_in_the_box():
     # a start on the box edge with the gradient pointing out stays on the edge
     qe, _, _ = O.refine_design(dict(p, q_hi=0.5), np.array([0.5, 0.5]), M, max_iter=5)
     assert np.all(qe <= 0.5)
+
+
+# ---------------------------------------------------------------- optimal level split (f2)
+
+def test_split_rule_at_the_equal_split_is_the_fwer_equal_rule():
+    p = W.base_problem(1, [3], 0.0, 0.05, q_lo=0.5, q_hi=0.7)
+    r = 0.4
+    z = O.zstar(r)
+    ps = dict(p, alpha_rule="split", alpha_fixed=(float(ndtr(-z)), 0.0))
+    ds = O.make_design(ps, [0.6])
+    assert abs(ds["r"] - r) < 1e-15 and abs(ds["z1"] - z) < 1e-12 and abs(ds["z2"] - z) < 1e-9
+    m_eq, _ = O.eval_grid(p, np.array([1]), 3000)
+    m_sp, _ = O.eval_grid(ps, np.array([1]), 3000)
+    assert abs(m_eq[0] - m_sp[0]) < 1e-9
+
+
+def test_level_surface_matches_closed_form_under_point_mass_prior():
+    """Point-mass step prior (no Monte Carlo noise): at q = 0.6 with true cutoff
+    0.3 the drifts are sqrt(I) b1 P(R) and sqrt(r I) b1 P(R and S)/r, and the
+    power for each level split is 1 - Phi_2(z1 - mu1, z2 - mu2; sqrt r) with z2
+    from scipy's FWER root; the level surface is its maximum over the list."""
+    p = W.base_problem(1, [3], 0.0, 0.05, q_lo=0.5, q_hi=0.7, sd_b0=0.0, sd_b1=0.0, tau_lo=0.3, tau_hi=0.3)
+    r, I = 0.4, 100.0
+    mu1 = math.sqrt(I) * 0.5 * 0.7
+    mu2 = math.sqrt(r * I) * 0.5 * 0.4 / r
+    alphas = np.linspace(0.001, 0.024, 47)
+    power = []
+    for a1 in alphas:
+        z1 = -ndtri(a1)
+        z2 = _z2_scipy(z1, r)
+        power.append(1.0 - _bvn_owen(z1 - mu1, z2 - mu2, math.sqrt(r)))
+    best, k = O.eval_grid_levels(p, np.array([1]), 2, alphas)
+    assert abs(best[0] - max(power)) < 1e-12
+    assert k[0] == int(np.argmax(power))
+    # an interior optimum: both tests keep part of the level
+    assert 0 < k[0] < len(alphas) - 1

@@ -198,7 +198,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="3d", choices=["3d", "1d", "5d", "alpha", "grad", "refine", "batch"])
+    ap.add_argument("--workload", default="3d", choices=["3d", "1d", "5d", "alpha", "levels", "grad", "refine", "batch"])
     ap.add_argument("--batch-scale", type=float, default=1.0,
                     help="batch workload only: scale of the per-axis grids and of the draw range (1 = full size)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -231,6 +231,8 @@ def main():
         return bench_grad(args)
     if args.workload == "refine":
         return bench_refine(args)
+    if args.workload == "levels":
+        return bench_levels(args)
     if args.workload == "batch":
         return bench_batch(args)
     spec = workload(args.workload)
@@ -347,6 +349,52 @@ def bench_grad(args):
                             "max_abs_diff_objective": float((o32 - o64).abs().max()),
                             "max_abs_diff_grad_rel_to_max": float(max((g32 - g64).abs().max(),
                                                                       (m32 - m64).abs().max()) / scale)}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_levels(args):
+    """Optimal level split per design (Sec. 2.4's optimal power at each design):
+    the 3-D bench grid swept at 8 first-test levels 0.0025..0.0200, second
+    level on each design's FWER boundary, M = 1e5; FP32 and FP64."""
+    import torch
+    import paper_2005_10494_amd as bmd
+    from paper_2005_10494_amd import workloads as W
+    spec = W.plain_3d()
+    M, G = spec["n_draws"], int(np.prod(spec["m"]))
+    alphas = np.linspace(0.0025, 0.02, 8)
+    res = {}
+    with bmd.Problem(spec) as p:
+        for prec in ("fp32", "fp64"):
+            ts = []
+            for it in range(args.warmup + args.steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                best, k = p.eval_grid_levels(M, alphas, prec)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                if it >= args.warmup:
+                    ts.append(dt)
+                log(f"  levels {prec} step {it}: {1e3 * dt:.1f} ms")
+            res[prec] = (float(np.mean(ts)), best, k)
+        eq = p.eval_grid(M, "fp32")
+        torch.cuda.synchronize()
+    t32, b32, k32 = res["fp32"]
+    t64, b64, k64 = res["fp64"]
+    evals = G * M * len(alphas)
+    counts = np.bincount(k32.cpu().numpy(), minlength=len(alphas))
+    out = {"metric": "optimal level split: integrand evals/s over all levels", "value": evals / t32,
+           "unit": "integrand evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * t32, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"3-biomarker cutoff grid 64x64x64, M={M}, first levels "
+                                  f"{', '.join(f'{a:.4g}' for a in alphas)}, second level on each design's "
+                                  f"FWER boundary", "designs": G, "n_draws": M, "levels": len(alphas)},
+           "result": {"best_level_counts": counts.tolist(), "max_best": float(b32.max()),
+                      "max_equal_split": float(eq.max()),
+                      "mean_gain_over_equal_split": float((b32 - eq).mean())},
+           "fp64": {"ms_per_step": 1e3 * t64},
+           "fp32_vs_fp64": {"speedup": t64 / t32, "max_abs_diff_best": float((b32 - b64).abs().max()),
+                            "level_index_agreement": float((k32 == k64).double().mean())}}
     print(json.dumps(out), flush=True)
 
 

@@ -63,7 +63,10 @@ typedef enum {
 typedef enum {
     BMD_ALPHA_FWER_EQUAL = 0,  /* z1 = z2 = z*, 1 - Phi_2(z*, z*; sqrt r) = alpha0 */
     BMD_ALPHA_BONFERRONI = 1,  /* z1 = z2 = Phi^-1(1 - alpha0/2)                   */
-    BMD_ALPHA_FIXED = 2        /* z_i = Phi^-1(1 - alpha_fixed[i]); 0 = test off   */
+    BMD_ALPHA_FIXED = 2,       /* z_i = Phi^-1(1 - alpha_fixed[i]); 0 = test off   */
+    BMD_ALPHA_SPLIT = 3        /* z1 = Phi^-1(1 - alpha_fixed[0]), alpha_fixed[0] in
+                                  (0, alpha0); z2 per design on the FWER boundary:
+                                  1 - Phi_2(z1, z2; sqrt r) = alpha0               */
 } bmd_alpha_rule;
 
 /* Prior f(Delta) of Formula 4. */
@@ -202,6 +205,21 @@ bmd_status bmd_argmax(bmd_problem *p, const double *d_surface, int64_t *h_index,
 bmd_status bmd_grad_design(bmd_problem *p, const double *d_q, int64_t B, uint64_t n_draws,
                            int32_t prec, double *d_obj, double *d_grad_q, double *d_grad_mu,
                            void *stream);
+
+/* Optimal level split per design (Sec. 2.4's "optimal power" at each design,
+ * for the n = 2 nested tests): for each first-test level h_alpha1[k] (host,
+ * n_alpha values in (0, alpha0)) the second level of every design is put on
+ * its FWER boundary (rule BMD_ALPHA_SPLIT), the grid is swept on draws
+ * 0..n_draws-1 (generated once), and
+ *   d_best   [G] FP64 receives the largest Monte Carlo estimate over the levels,
+ *   d_best_k [G] int32 (may be NULL) the index k of the level that gave it
+ *            (ties: the lowest k).
+ * One sweep per level.  The problem's own critical values are restored before
+ * the call returns (a design precompute is re-launched on `stream`).  ESTATE
+ * for a continuous problem or the alpha design space; ERANGE for n_alpha
+ * outside [1, 4096] or a level outside (0, alpha0). */
+bmd_status bmd_eval_grid_levels(bmd_problem *p, uint64_t n_draws, int32_t prec, const double *h_alpha1,
+                                int32_t n_alpha, double *d_best, int32_t *d_best_k, void *stream);
 
 /* Continuous refinement of a design (Sec. 2.3: the best grid point refined by
  * a local gradient method): projected gradient ascent inside the box

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbmd.so")
 
 FP64, FP32_COMP = 0, 1
 _PREC = {"fp64": FP64, "f64": FP64, "fp32": FP32_COMP, "fp32_comp": FP32_COMP, "f32": FP32_COMP}
-_ALPHA = {"fwer": 0, "fwer_equal": 0, "bonferroni": 1, "fixed": 2}
+_ALPHA = {"fwer": 0, "fwer_equal": 0, "bonferroni": 1, "fixed": 2, "split": 3}
 _EFFECT = {"step": 0, "paper": 1, "paper_gauss": 1}
 _DESIGN = {"cutoffs": 0, "alpha": 1}
 DRAW_FIELDS = 17
@@ -73,6 +73,8 @@ SIGNATURES = {
     "bmd_grad_design": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64,
                                        ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p]),
+    "bmd_eval_grid_levels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "bmd_refine_design": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32,
                                          ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p]),
@@ -231,6 +233,19 @@ class Problem:
                                          ctypes.c_void_p(gmu.data_ptr()) if gmu is not None else None,
                                          _stream(stream)))
         return obj, gq, gmu
+
+    def eval_grid_levels(self, n_draws: int, alphas, precision="fp64", stream=None):
+        """Best Monte Carlo power per design over first-test levels ``alphas``
+        (second level on each design's FWER boundary); returns (best, level index)."""
+        import torch
+        a = np.ascontiguousarray(np.asarray(alphas, dtype=np.float64).ravel())
+        best = torch.empty(self.G, dtype=torch.float64, device=self.device)
+        k = torch.empty(self.G, dtype=torch.int32, device=self.device)
+        _check(library().bmd_eval_grid_levels(self._h, int(n_draws), _prec(precision),
+                                              a.ctypes.data_as(ctypes.c_void_p), a.size,
+                                              ctypes.c_void_p(best.data_ptr()), ctypes.c_void_p(k.data_ptr()),
+                                              _stream(stream)))
+        return best, k
 
     def refine_design(self, q0, n_draws: int, precision="fp64", max_iter=50, tol=1e-6, stream=None):
         """Local maximiser of the Monte Carlo objective from q0 (projected

@@ -152,7 +152,10 @@ bmd_status validate(const bmd_problem_desc* d, bool* grid) {
         return fail(BMD_ERANGE, "rho_b = %g outside [0, 0.5]", d->rho_b);
     if (!finite(d->info) || d->info <= 0.0) return fail(BMD_ERANGE, "info must be > 0");
     if (!finite(d->alpha0) || !(d->alpha0 > 0.0 && d->alpha0 < 0.5)) return fail(BMD_ERANGE, "alpha0 outside (0, 0.5)");
-    if (d->alpha_rule < 0 || d->alpha_rule > 2) return fail(BMD_EINVAL, "unknown alpha_rule %d", d->alpha_rule);
+    if (d->alpha_rule < 0 || d->alpha_rule > 3) return fail(BMD_EINVAL, "unknown alpha_rule %d", d->alpha_rule);
+    if (d->alpha_rule == BMD_ALPHA_SPLIT &&
+        !(finite(d->alpha_fixed[0]) && d->alpha_fixed[0] > 0.0 && d->alpha_fixed[0] < d->alpha0))
+        return fail(BMD_ERANGE, "the split rule needs 0 < alpha_fixed[0] < alpha0");
     if (d->alpha_rule == BMD_ALPHA_FIXED)
         for (int i = 0; i < 2; ++i)
             if (!finite(d->alpha_fixed[i]) || d->alpha_fixed[i] < 0.0 || d->alpha_fixed[i] >= 0.5)
@@ -259,6 +262,22 @@ void free_problem(bmd_problem* p) {
 
 bool valid_prec(int32_t prec) { return prec == BMD_FP64 || prec == BMD_FP32_COMP; }
 
+// Draw slices of a grid sweep: about kSweepRounds full rounds of resident
+// workgroups, so the partly filled last round costs little; slices of at
+// least 64 draws, whole draw chunks of the matrix-core sweep.
+void sweep_slices(bmd_problem* p, int prec, int64_t M, int64_t* n_slices_out, int64_t* slice_len_out) {
+    const int64_t bx = sweep_tiles(p, prec);
+    if (p->sweep_bpc[prec] == 0) p->sweep_bpc[prec] = sweep_blocks_per_cu(p, prec);
+    const int64_t resident = static_cast<int64_t>(p->n_cu) * p->sweep_bpc[prec];
+    const int64_t chunk = sweep_chunk(p, prec);
+    int64_t n_slices = (kSweepRounds * resident + bx - 1) / bx;
+    n_slices = std::max<int64_t>(1, std::min<int64_t>({n_slices, (M + 63) / 64, 65535}));
+    int64_t slice_len = (M + n_slices - 1) / n_slices;
+    slice_len = (slice_len + chunk - 1) / chunk * chunk;
+    *n_slices_out = (M + slice_len - 1) / slice_len;
+    *slice_len_out = slice_len;
+}
+
 // Event i of the profiling pairs (phase = i / 2), recorded when profiling is on.
 void mark(bmd_problem* p, int i, hipStream_t s) {
     if (!p->profiling) return;
@@ -337,6 +356,8 @@ bmd_status bmd_create_problem(const bmd_problem_desc* desc, bmd_problem** out, v
     P.alpha_rule = d.alpha_rule;
     if (d.alpha_rule == BMD_ALPHA_BONFERRONI) {
         P.zf1 = P.zf2 = -host_quantile(0.5 * d.alpha0);
+    } else if (d.alpha_rule == BMD_ALPHA_SPLIT) {
+        P.zf1 = -host_quantile(d.alpha_fixed[0]);   // z2 per design on the FWER boundary
     } else if (d.alpha_rule == BMD_ALPHA_FIXED) {
         P.zf1 = d.alpha_fixed[0] > 0.0 ? -host_quantile(d.alpha_fixed[0]) : INFINITY;
         P.zf2 = d.alpha_fixed[1] > 0.0 ? -host_quantile(d.alpha_fixed[1]) : INFINITY;
@@ -494,18 +515,8 @@ bmd_status bmd_eval_grid(bmd_problem* p, uint64_t n_draws, int32_t prec, double*
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t M = static_cast<int64_t>(n_draws);
     const int64_t G = p->P.G;
-    // Draw slices: about kSweepRounds full rounds of resident workgroups, so the
-    // partly filled last round costs little; slices of at least 64 draws,
-    // whole draw chunks of the matrix-core sweep.
-    const int64_t bx = sweep_tiles(p, prec);
-    if (p->sweep_bpc[prec] == 0) p->sweep_bpc[prec] = sweep_blocks_per_cu(p, prec);
-    const int64_t resident = static_cast<int64_t>(p->n_cu) * p->sweep_bpc[prec];
-    const int64_t chunk = sweep_chunk(p, prec);
-    int64_t n_slices = (kSweepRounds * resident + bx - 1) / bx;
-    n_slices = std::max<int64_t>(1, std::min<int64_t>({n_slices, (M + 63) / 64, 65535}));
-    int64_t slice_len = (M + n_slices - 1) / n_slices;
-    slice_len = (slice_len + chunk - 1) / chunk * chunk;
-    n_slices = (M + slice_len - 1) / slice_len;
+    int64_t n_slices = 0, slice_len = 0;
+    sweep_slices(p, prec, M, &n_slices, &slice_len);
     const size_t draw_bytes = (draw_workspace_bytes(p, prec, M) + 255) / 256 * 256;
     const size_t part_bytes = sizeof(double) * 2 * static_cast<size_t>(G) * n_slices;
     bmd_status st = ensure(&p->d_ws, &p->ws_cap, draw_bytes + part_bytes);
@@ -521,6 +532,47 @@ bmd_status bmd_eval_grid(bmd_problem* p, uint64_t n_draws, int32_t prec, double*
     mark(p, 4, s);
     HIP_TRY(launch_finalize(p, M, partials, static_cast<int>(n_slices), d_mean, d_var, s), "finalize kernel");
     mark(p, 5, s);
+    return BMD_OK;
+}
+
+bmd_status bmd_eval_grid_levels(bmd_problem* p, uint64_t n_draws, int32_t prec, const double* h_alpha1,
+                                int32_t n_alpha, double* d_best, int32_t* d_best_k, void* stream) {
+    g_err.clear();
+    if (!p) return fail(BMD_EINVAL, "problem is NULL");
+    if (!p->grid || p->P.design_space != BMD_DESIGN_CUTOFFS)
+        return fail(BMD_ESTATE, "level splits need a grid of cutoff designs");
+    if (!valid_prec(prec)) return fail(BMD_EINVAL, "unknown precision %d", prec);
+    if (!h_alpha1 || !d_best) return fail(BMD_EINVAL, "NULL h_alpha1 or d_best");
+    if (n_alpha < 1 || n_alpha > 4096) return fail(BMD_ERANGE, "n_alpha must be in [1, 4096]");
+    for (int k = 0; k < n_alpha; ++k)
+        if (!std::isfinite(h_alpha1[k]) || !(h_alpha1[k] > 0.0 && h_alpha1[k] < p->P.alpha0))
+            return fail(BMD_ERANGE, "level %d = %g outside (0, alpha0)", k, h_alpha1[k]);
+    if (n_draws == 0 || n_draws > (1ull << 40)) return fail(BMD_ERANGE, "n_draws must be in [1, 2^40]");
+    DeviceGuard guard(p->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t M = static_cast<int64_t>(n_draws);
+    const int64_t G = p->P.G;
+    int64_t n_slices = 0, slice_len = 0;
+    sweep_slices(p, prec, M, &n_slices, &slice_len);
+    const size_t draw_bytes = (draw_workspace_bytes(p, prec, M) + 255) / 256 * 256;
+    const size_t part_bytes = (sizeof(double) * 2 * static_cast<size_t>(G) * n_slices + 255) / 256 * 256;
+    bmd_status st = ensure(&p->d_ws, &p->ws_cap, draw_bytes + part_bytes + sizeof(double) * G);
+    if (st != BMD_OK) return st;
+    double* partials = reinterpret_cast<double*>(static_cast<char*>(p->d_ws) + draw_bytes);
+    double* mean = reinterpret_cast<double*>(static_cast<char*>(p->d_ws) + draw_bytes + part_bytes);
+    HIP_TRY(launch_draws(p, prec, 0, M, p->d_ws, s), "draw kernel");
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < n_alpha && e == hipSuccess; ++k) {
+        e = launch_levels_z(p, -host_quantile(h_alpha1[k]), s);
+        if (e == hipSuccess)
+            e = launch_eval_grid(p, prec, M, p->d_ws, partials, static_cast<int>(n_slices), slice_len, false, s);
+        if (e == hipSuccess) e = launch_finalize(p, M, partials, static_cast<int>(n_slices), mean, nullptr, s);
+        if (e == hipSuccess) e = launch_levels_best(p, k, mean, d_best, d_best_k, s);
+    }
+    // the problem's own critical values, whatever happened above
+    const hipError_t er = launch_design_precompute(p, s);
+    HIP_TRY(e, "level sweeps");
+    HIP_TRY(er, "design precompute");
     return BMD_OK;
 }
 

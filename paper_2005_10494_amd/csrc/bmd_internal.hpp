@@ -138,6 +138,11 @@ void gl_table(double* out);                             // packed n = 4,6,8,10,1
 
 // Launchers (return hipSuccess or the first HIP error).
 hipError_t launch_design_precompute(const bmd_problem* p, hipStream_t s);
+// Level splits (rule BMD_ALPHA_SPLIT for every design at first-level critical
+// value z1) and the running maximum over levels.
+hipError_t launch_levels_z(const bmd_problem* p, double z1, hipStream_t s);
+hipError_t launch_levels_best(const bmd_problem* p, int k, const double* mean, double* best, int32_t* best_k,
+                              hipStream_t s);
 hipError_t launch_axis_tables(const bmd_problem* p, int prec, hipStream_t s);
 hipError_t launch_draws(const bmd_problem* p, int prec, uint64_t k0, int64_t M, void* ws,
                         hipStream_t s);

@@ -133,9 +133,36 @@ __global__ __launch_bounds__(128) void k_design_precompute(DevProblem P, const d
         const double z = zstar(sqrt(r), P.alpha0, gl);
         z1_out[g] = z;
         z2_out[g] = z;
+    } else if (P.alpha_rule == BMD_ALPHA_SPLIT) {
+        z1_out[g] = P.zf1;
+        z2_out[g] = z2_on_fwer(P.zf1, sqrt(r), P.alpha0, gl);
     } else {
         z1_out[g] = P.zf1;
         z2_out[g] = P.zf2;
+    }
+}
+
+// Critical values of one level split for every design: z1 given, z2 on the
+// design's FWER boundary (its r from the precompute).
+__global__ __launch_bounds__(128) void k_levels_z(int64_t G, double z1, double alpha0, const double* __restrict__ r,
+                                                  const double* __restrict__ gl, double* __restrict__ z1_out,
+                                                  double* __restrict__ z2_out) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    z1_out[g] = z1;
+    z2_out[g] = z2_on_fwer(z1, sqrt(r[g]), alpha0, gl);
+}
+
+// Running maximum over levels: level k's means against the best so far
+// (k = 0 initialises); strict improvement only, so ties keep the lower k.
+__global__ void k_levels_best(int64_t G, int k, const double* __restrict__ mean, double* __restrict__ best,
+                              int32_t* __restrict__ best_k) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    const double m = mean[g];
+    if (k == 0 || m > best[g]) {
+        best[g] = m;
+        if (best_k) best_k[g] = k;
     }
 }
 
@@ -293,6 +320,18 @@ __global__ __launch_bounds__(128) void k_inspect_designs(DevProblem P, int64_t g
 inline unsigned blocks_for(int64_t n, int b) { return static_cast<unsigned>((n + b - 1) / b); }
 
 }  // namespace
+
+hipError_t launch_levels_z(const bmd_problem* p, double z1, hipStream_t s) {
+    hipLaunchKernelGGL(k_levels_z, dim3(blocks_for(p->P.G, 128)), dim3(128), 0, s, p->P.G, z1, p->P.alpha0, p->d_r,
+                       p->d_gl, p->d_z1, p->d_z2);
+    return hipGetLastError();
+}
+
+hipError_t launch_levels_best(const bmd_problem* p, int k, const double* mean, double* best, int32_t* best_k,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_levels_best, dim3(blocks_for(p->P.G, 256)), dim3(256), 0, s, p->P.G, k, mean, best, best_k);
+    return hipGetLastError();
+}
 
 hipError_t launch_design_precompute(const bmd_problem* p, hipStream_t s) {
     if (p->P.G == 0) return hipSuccess;

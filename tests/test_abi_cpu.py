@@ -66,6 +66,7 @@ def _create_status(spec):
     ({"width": -1.0}, -2), ({"gh_nodes": 2}, -2), ({"gh_nodes": 6}, -2), ({"gh_nodes": 132}, -2), ({"bandwidth": [0.0]}, -2),
     ({"m": [1]}, -2), ({"q_lo": 0.01}, -2),   # r = 0.99 > 0.95: bivariate quadrature range
     ({"mu_b1": float("nan")}, -1),
+    ({"alpha_rule": "split", "alpha_fixed": (0.0, 0.0)}, -2), ({"alpha_rule": "split", "alpha_fixed": (0.025, 0.0)}, -2),
 ])
 def test_validation_rejects_before_any_launch(change, status):
     spec = W.plain_1d()
@@ -108,6 +109,7 @@ def test_null_arguments():
     assert lib.bmd_sweep_kind(None) == -1
     assert lib.bmd_gh_nodes(None, 0) == -1
     assert lib.bmd_refine_design(None, None, 10, 0, 5, 1e-6, None, None, None, None) == -1
+    assert lib.bmd_eval_grid_levels(None, 10, 0, None, 1, None, None, None) == -1
     lib.bmd_destroy_problem(None)  # NULL-safe
 
 

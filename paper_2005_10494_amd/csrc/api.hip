@@ -645,11 +645,13 @@ bmd_status bmd_grad_design(bmd_problem* p, const double* d_q, int64_t B, uint64_
     const int64_t M = static_cast<int64_t>(n_draws);
     const int chunk = grad_chunk(prec, p->P.d, p->tab[prec].K);
     // Draw slices: about kSweepRounds rounds of resident workgroups.
-    const int64_t bx = (B * grad_lanes(B) + 127) / 128;   // 128 threads per workgroup, grad_lanes(B) per point
+    const int lanes = grad_lanes(B);
+    const int64_t bx = (B * lanes + 127) / 128;   // 128 threads per workgroup, `lanes` per point
     const int64_t resident = static_cast<int64_t>(p->n_cu) * grad_blocks_per_cu(p, prec);
     int64_t n_slices = (kSweepRounds * resident + bx - 1) / bx;
     n_slices = std::max<int64_t>(1, std::min<int64_t>({n_slices, (M + chunk - 1) / chunk, 65535}));
-    int64_t slice_len = (M + n_slices - 1) / n_slices;
+    // at least 16 draws per thread of a slice, so the per-point setup is amortised
+    int64_t slice_len = std::max<int64_t>((M + n_slices - 1) / n_slices, std::min<int64_t>(M, 16 * lanes));
     slice_len = (slice_len + chunk - 1) / chunk * chunk;
     n_slices = (M + slice_len - 1) / slice_len;
     bmd_status st =

@@ -390,6 +390,32 @@ __global__ void k_grad_finalize(int d, int64_t B, int64_t M, int n_slices, const
     }
 }
 
+// The same reduction with one workgroup per (point, component): for few points
+// and many slices, where one thread per point would walk thousands of slices.
+// Thread t adds slices t, t + 256, ... in order, then a fixed-order tree.
+__global__ __launch_bounds__(256) void k_grad_finalize_wide(int d, int64_t B, int64_t M, int n_slices,
+                                                            const double* __restrict__ part,
+                                                            const double* __restrict__ info, double* __restrict__ obj,
+                                                            double* __restrict__ gq, double* __restrict__ gmu) {
+    __shared__ double red[256];
+    const int64_t b = blockIdx.x / (d + 3);
+    const int c = static_cast<int>(blockIdx.x % (d + 3));
+    double s = 0.0;
+    for (int sl = threadIdx.x; sl < n_slices; sl += 256) s += part[(static_cast<int64_t>(sl) * (d + 3) + c) * B + b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (static_cast<int>(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const bool valid = info[b * kPointFields + 4] != 0.0;
+    const double v = valid ? red[0] / static_cast<double>(M) : NAN;
+    if (c == 0) obj[b] = v;
+    else if (c <= d) { if (gq) gq[b * d + (c - 1)] = v; }
+    else if (gmu) gmu[b * 2 + (c - 1 - d)] = v;
+}
+
 template <typename T, int NMAX, int R, bool SPLIT>
 const void* grad_kernel(int d) {
     switch (d) {
@@ -504,7 +530,11 @@ hipError_t launch_grad(const bmd_problem* p, int prec, const double* d_q, int64_
                              : launch_grad_typed<float, 12, 2>(ga, draws_fp32_at(p, np, dws), d, ns, s);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_grad_finalize, dim3(pb), dim3(128), 0, s, d, B, M, n_slices, part, info, obj, gq, gmu);
+    if (n_slices > 256 && B * (d + 3) <= (int64_t(1) << 20))
+        hipLaunchKernelGGL(k_grad_finalize_wide, dim3(static_cast<unsigned>(B * (d + 3))), dim3(256), 0, s, d, B, M,
+                           n_slices, part, info, obj, gq, gmu);
+    else
+        hipLaunchKernelGGL(k_grad_finalize, dim3(pb), dim3(128), 0, s, d, B, M, n_slices, part, info, obj, gq, gmu);
     return hipGetLastError();
 }
 

@@ -1,6 +1,6 @@
 // Bodies of the grid-sweep kernels (Formula 5 summands and their FP64 sums),
 // shared by the one-problem launches (kernels_eval.hip) and the batched
-// persistent launch (kernels_batch.hip).  T is the integrand type.
+// work-list launch (kernels_batch.hip).  T is the integrand type.
 #pragma once
 #include <type_traits>
 
@@ -119,8 +119,10 @@ struct MfmaGeom {
 // designs at once; each wavefront takes every fourth draw.
 // Phase B (vector units): one design per thread, the bivariate normal part.
 // One workgroup's work: tile `tile`, draws of slice `slice`; lds holds
-// mfma_lds_bytes<T>(geo.chunk, D, K) bytes.  Starts and ends with barriers, so
-// a persistent caller may run items back to back.  VAR: also the sums of squares.
+// mfma_lds_bytes<T>(geo.chunk, D, K) bytes.  The body's first LDS copies are
+// issued before its first barrier and its last phase B reads LDS after its
+// last one, so a caller that runs another item on the same LDS must
+// synchronise the workgroup in between.  VAR: also the sums of squares.
 template <typename T, int D, int NMAX, bool VAR>
 __device__ __forceinline__ void mfma_tile_body(const EvalArgs<T>& a, const MfmaGeom& geo, int64_t tile, int slice,
                                                char* lds) {

@@ -1,4 +1,4 @@
-"""Batched form: many uneven grid problems in one persistent, graph-captured
+"""Batched form: many uneven grid problems in one graph-captured work-list
 launch, checked against the single-problem sweep (same draws) and against the
 oracle on sampled designs."""
 import sys

@@ -165,6 +165,31 @@ double or_bvn(double h, double k, double rho)
     return or_quad(bvn_integrand, &c, lo, h);
 }
 
+/* Standard trivariate normal CDF P(X1 <= h1, X2 <= h2, X3 <= h3) with
+ * correlations r12, r13, r23, from its definition by conditioning on X1:
+ *   int_{-inf}^{h1} phi(x) Phi_2((h2 - r12 x)/s12, (h3 - r13 x)/s13; r23.1) dx,
+ * s1j = sqrt(1 - r1j^2), r23.1 = (r23 - r12 r13) / (s12 s13) (the partial
+ * correlation).  Phi_Sigma of Formula 1 for n = 3. */
+typedef struct { double h2, h3, r12, r13, s12, s13, r231; } tvn_ctx;
+
+static double tvn_integrand(double x, void *ctx)
+{
+    const tvn_ctx *c = (const tvn_ctx *)ctx;
+    return or_phi(x) * or_bvn((c->h2 - c->r12 * x) / c->s12, (c->h3 - c->r13 * x) / c->s13, c->r231);
+}
+
+double or_tvn(double h1, double h2, double h3, double r12, double r13, double r23)
+{
+    if (isnan(h1) || isnan(h2) || isnan(h3)) return NAN;
+    if (h1 == -INFINITY || h2 == -INFINITY || h3 == -INFINITY) return 0.0;
+    if (h1 == INFINITY) return or_bvn(h2, h3, r23);
+    if (h2 == INFINITY) return or_bvn(h1, h3, r13);
+    if (h3 == INFINITY) return or_bvn(h1, h2, r12);
+    tvn_ctx c = {h2, h3, r12, r13, sqrt((1.0 - r12) * (1.0 + r12)), sqrt((1.0 - r13) * (1.0 + r13)), 0.0};
+    c.r231 = (r23 - r12 * r13) / (c.s12 * c.s13);
+    return or_quad(tvn_integrand, &c, fmin(-12.0, h1 - 10.0), h1);
+}
+
 /* Density of the standard bivariate normal (the integrand of Plackett's
  * identity d Phi_2 / d rho = phi_2). */
 double or_bvn_density(double h, double k, double rho)
@@ -288,6 +313,25 @@ double or_z2_fwer(double z1, double r, double alpha0)
     return 0.5 * (lo + hi);
 }
 
+/* n = 3 nested populations 1 > r2 > r3 (null correlations sqrt(r2), sqrt(r3),
+ * sqrt(r3/r2), Appendix A.1): the third critical value with FWER =
+ * 1 - Phi_3(z1, z2, z3) = alpha0 given the first two, by bisection between the
+ * third test alone at level alpha0 and the union bound (the first two tests
+ * spend a12 = 1 - Phi_2(z1, z2; sqrt r2)).  NaN when a12 >= alpha0. */
+double or_z3_fwer(double z1, double z2, double r2, double r3, double alpha0)
+{
+    double a12 = 1.0 - or_bvn(z1, z2, sqrt(r2));
+    if (!(a12 < alpha0)) return NAN;
+    double r12 = sqrt(r2), r13 = sqrt(r3), r23 = sqrt(r3 / r2);
+    double lo = -or_Phiinv(alpha0), hi = -or_Phiinv(alpha0 - a12);
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (1.0 - or_tvn(z1, z2, mid, r12, r13, r23) > alpha0) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 /* Information units needed for a one-sided level-alpha test with power
  * 1 - beta at hazard reduction delta (Sec. 3, the I_3 sizing formula). */
 double or_info_units(double alpha, double beta, double delta)
@@ -393,6 +437,19 @@ void or_grid_point(const or_problem *p, int64_t g, double *q, int32_t *idx)
 void or_make_design(const or_problem *p, const double *q, or_design *o)
 {
     memset(o, 0, sizeof *o);
+    if (p->design_space == OR_DESIGN_ALPHA3) {
+        /* (alpha_1, alpha_2) for three nested populations, alpha_3 on the FWER
+         * boundary (Formula 2 with n = 3). */
+        o->q[0] = q[0];
+        o->q[1] = q[1];
+        o->r = p->r_lo;
+        o->rho = sqrt(o->r);
+        o->r3 = p->r_hi;
+        o->z1 = -or_Phiinv(q[0]);
+        o->z2 = -or_Phiinv(q[1]);
+        o->z3 = or_z3_fwer(o->z1, o->z2, o->r, o->r3, p->alpha0);
+        return;
+    }
     if (p->design_space == OR_DESIGN_ALPHA) {
         /* (r_2, alpha_1) or alpha_1 alone: the nested pair of Sec. 2.2 with the
          * level split on the FWER boundary of Formula 2. */
@@ -446,6 +503,11 @@ void or_make_draw(const or_problem *p, uint64_t k, or_draw *o)
             o->t[j] = or_Phiinv(o->tau[j]);
         }
         o->PR = (d == 1) ? 1.0 - o->tau[0] : or_orthant(d, o->t, p->rho_b);
+    } else if (p->design_space == OR_DESIGN_ALPHA3) {
+        draw_uniforms(p, k, 3, o->u);
+        o->e1 = or_Phiinv(o->u[0]);
+        o->e2 = or_Phiinv(o->u[1]);
+        o->e3 = or_Phiinv(o->u[2]);
     } else {
         draw_uniforms(p, k, 2, o->u);
         o->e1 = or_Phiinv(o->u[0]);
@@ -510,8 +572,28 @@ static void effects(const or_problem *p, const or_design *ds, const or_draw *dr,
 /* Success probability for one design and one draw: one minus the CDF of the
  * alternative distribution (Formula 3) at the critical values, i.e. one
  * summand of Formula 5. */
+/* Three nested populations under Formula 10: Delta_i = theta_i + sigma_i Y_i
+ * with standard normals Y of the nested null correlations (corr(Y_i, Y_j) =
+ * sqrt(r_j / r_i)): Y1 = e1, Y2 = sqrt(r2) e1 + sqrt(1 - r2) e2,
+ * Y3 = sqrt(r3) e1 + sqrt(r3 (1 - r2) / r2) e2 + sqrt(1 - r3 / r2) e3. */
+static double success3(const or_problem *p, const or_design *ds, const or_draw *dr)
+{
+    if (isnan(ds->z3)) return NAN;
+    double r[3] = {1.0, ds->r, ds->r3}, E = p->paper_events, I = p->info;
+    double Y[3] = {dr->e1, sqrt(r[1]) * dr->e1 + sqrt(1.0 - r[1]) * dr->e2,
+                   sqrt(r[2]) * dr->e1 + sqrt(r[2] * (1.0 - r[1]) / r[1]) * dr->e2 + sqrt(1.0 - r[2] / r[1]) * dr->e3};
+    double z[3] = {ds->z1, ds->z2, ds->z3}, h[3];
+    for (int i = 0; i < 3; ++i) {
+        double th = -log1p(-(p->paper_a - p->paper_b * r[i]));
+        double sg = 1.0 / sqrt(E * r[i] / 4.0);
+        h[i] = z[i] - sqrt(r[i] * I) * (th + sg * Y[i]);
+    }
+    return 1.0 - or_tvn(h[0], h[1], h[2], sqrt(r[1]), sqrt(r[2]), sqrt(r[2] / r[1]));
+}
+
 double or_success(const or_problem *p, const or_design *ds, const or_draw *dr)
 {
+    if (p->design_space == OR_DESIGN_ALPHA3) return success3(p, ds, dr);
     double d1, d2;
     effects(p, ds, dr, &d1, &d2, NULL);
     double mu1 = sqrt(p->info) * d1;
@@ -914,6 +996,17 @@ double or_exact_paper(const or_problem *p, const double *q)
     if (p->effect != OR_EFFECT_PAPER_GAUSS) return NAN;
     or_design ds;
     or_make_design(p, q, &ds);
+    if (p->design_space == OR_DESIGN_ALPHA3) {
+        /* X = D Delta + eps is Gaussian with covariance (1 + 4 I / E) R. */
+        if (isnan(ds.z3)) return NAN;
+        double r[3] = {1.0, ds.r, ds.r3}, z[3] = {ds.z1, ds.z2, ds.z3}, h[3];
+        double s = sqrt(1.0 + 4.0 * p->info / p->paper_events);
+        for (int i = 0; i < 3; ++i) {
+            double th = -log1p(-(p->paper_a - p->paper_b * r[i]));
+            h[i] = (z[i] - sqrt(r[i] * p->info) * th) / s;
+        }
+        return 1.0 - or_tvn(h[0], h[1], h[2], sqrt(r[1]), sqrt(r[2]), sqrt(r[2] / r[1]));
+    }
     double r = ds.r, I = p->info, E = p->paper_events;
     double th1 = -log1p(-(p->paper_a - p->paper_b));
     double th2 = -log1p(-(p->paper_a - p->paper_b * r));

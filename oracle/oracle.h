@@ -33,7 +33,7 @@ extern "C" {
 
 enum { OR_ALPHA_FWER_EQUAL = 0, OR_ALPHA_BONFERRONI = 1, OR_ALPHA_FIXED = 2, OR_ALPHA_SPLIT = 3 };
 enum { OR_EFFECT_STEP = 0, OR_EFFECT_PAPER_GAUSS = 1 };
-enum { OR_DESIGN_CUTOFFS = 0, OR_DESIGN_ALPHA = 1 };
+enum { OR_DESIGN_CUTOFFS = 0, OR_DESIGN_ALPHA = 1, OR_DESIGN_ALPHA3 = 2 };
 
 typedef struct {
     int32_t d;              /* number of biomarkers (cutoff axes), 1..6          */
@@ -60,7 +60,11 @@ typedef struct {
      * design variables): the last axis is the first test's level alpha_1 on
      * [q_lo, q_hi] inside (0, alpha0); alpha_2 follows from Formula 2 at FWER =
      * alpha0.  With d = 2, axis 0 is the subgroup fraction r_2 on [r_lo, r_hi];
-     * with d = 1, r_2 = r_lo.  Paper prior (Formula 10) only. */
+     * with d = 1, r_2 = r_lo.  Paper prior (Formula 10) only.
+     * OR_DESIGN_ALPHA3: n = 3 nested populations 1 > r_2 = r_lo > r_3 = r_hi
+     * (Sec. 3's experiment); d = 2 axes alpha_1, alpha_2 on [q_lo, q_hi] and
+     * alpha_3 on the FWER boundary (NaN designs where the first two levels
+     * already spend alpha0).  Paper prior only. */
     int32_t design_space;
     double r_lo, r_hi;
 } or_problem;
@@ -71,6 +75,7 @@ typedef struct {
     double r;               /* subgroup fraction                                 */
     double rho;             /* sqrt(r): null correlation of the two Z-statistics */
     double z1, z2;          /* critical values (may be +inf)                     */
+    double r3, z3;          /* third population (OR_DESIGN_ALPHA3): r_3 and z3    */
 } or_design;
 
 /* One Monte Carlo draw of the effect parameters. */
@@ -80,6 +85,7 @@ typedef struct {
     double tau[6], t[6];    /* true cutoff quantiles and cutoffs                 */
     double PR;              /* population fraction of responders                 */
     double e1, e2;          /* standard normals (paper Gaussian prior)           */
+    double e3;              /* third normal (three populations)                  */
 } or_draw;
 
 /* ---- primitives -------------------------------------------------------- */
@@ -89,9 +95,11 @@ double or_Phiinv(double p);              /* root of Phi(x) = p                */
 double or_quad(double (*f)(double, void *), void *ctx, double a, double b);
 double or_bvn(double h, double k, double rho);     /* P(X<=h, Y<=k)          */
 double or_bvn_density(double h, double k, double rho);
+double or_tvn(double h1, double h2, double h3, double r12, double r13, double r23);   /* P(X_i <= h_i) */
 double or_orthant(int d, const double *v, double rho_b);   /* P(X_j > v_j)    */
 double or_zstar(double r, double alpha0);
 double or_z2_fwer(double z1, double r, double alpha0);   /* second level on the FWER boundary */
+double or_z3_fwer(double z1, double z2, double r2, double r3, double alpha0);   /* n = 3: third level */
 double or_info_units(double alpha, double beta, double delta);
 void   or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double or_uniform52(uint32_t wa, uint32_t wb);

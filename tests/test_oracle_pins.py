@@ -604,3 +604,79 @@ def test_level_surface_matches_closed_form_under_point_mass_prior():
     assert k[0] == int(np.argmax(power))
     # an interior optimum: both tests keep part of the level
     assert 0 < k[0] < len(alphas) - 1
+
+
+# ---------------------------------------------------------------- three nested populations
+
+def _tvn_scipy(h, r12, r13, r23):
+    cov = np.array([[1.0, r12, r13], [r12, 1.0, r23], [r13, r23, 1.0]])
+    return stats.multivariate_normal.cdf(np.asarray(h, dtype=float), mean=np.zeros(3), cov=cov,
+                                         abseps=1e-11, releps=1e-11, maxpts=20_000_000)
+
+
+def test_trivariate_cdf_against_scipy_and_closed_forms():
+    for h, r in [((0.3, -0.5, 1.2), (0.6, 0.4, 0.67)), ((2.0, 1.5, 1.8), (0.8, 0.5, 0.62)),
+                 ((-1.0, 0.7, 0.2), (0.3, -0.2, 0.1)), ((1.96, 2.2, 2.4), (0.67, 0.41, 0.61))]:
+        assert abs(O.tvn(*h, *r) - _tvn_scipy(h, *r)) < 2e-8, (h, r)
+    # independent coordinates: a product
+    h = (0.4, -0.3, 1.1)
+    assert abs(O.tvn(*h, 0.0, 0.0, 0.0) - ndtr(0.4) * ndtr(-0.3) * ndtr(1.1)) < 1e-14
+    # an infinite bound drops a coordinate: the bivariate CDF (Owen's T)
+    assert abs(O.tvn(0.5, -0.2, math.inf, 0.45, 0.3, 0.2) - _bvn_owen(0.5, -0.2, 0.45)) < 1e-14
+    # equicorrelated orthant: 1/8 + 3 asin(rho) / (4 pi)
+    for rho in (0.2, 0.5, 0.8):
+        assert abs(O.tvn(0.0, 0.0, 0.0, rho, rho, rho) - (0.125 + 3 * math.asin(rho) / (4 * math.pi))) < 1e-13
+
+
+def test_paper_case_c_printed_power():
+    """Condition (c) of Sec. 3 at its printed optimum (three populations,
+    printed levels): the Formula 10 closed form through the trivariate CDF
+    reproduces the printed best power 0.977."""
+    r = [1.0, 0.446, 0.168]
+    a = [0.00194, 0.0135, 0.0133]
+    I = 211.0
+    s = math.sqrt(1 + I / 20.0)
+    h = [(-ndtri(a[i]) - math.sqrt(r[i] * I) * (-math.log(1 - (0.8 - 0.6 * r[i])))) / s for i in range(3)]
+    R = (math.sqrt(r[1]), math.sqrt(r[2]), math.sqrt(r[2] / r[1]))
+    p = 1.0 - O.tvn(*h, *R)
+    assert abs(p - (1.0 - _tvn_scipy(h, *R))) < 2e-8
+    rows = {row[0]: row for row in _golden("paper_values.txt")}
+    printed, tol = float(rows["case_c_best_power"][1]), float(rows["case_c_best_power"][2])
+    assert abs(p - printed) <= tol
+
+
+def _alpha3(**kw):
+    p = W.base_problem(2, [5, 5], 0.0, 0.002, design="alpha3", q_lo=0.001, q_hi=0.02, info=211.0,
+                       effect="paper", paper_a=0.8, paper_b=0.6, paper_events=80.0)
+    p.update(r_lo=0.446, r_hi=0.168)
+    p.update(kw)
+    return p
+
+
+def test_alpha3_third_level_on_fwer_boundary():
+    p = _alpha3()
+    r2, r3 = 0.446, 0.168
+    R = (math.sqrt(r2), math.sqrt(r3), math.sqrt(r3 / r2))
+    for a1, a2 in [(0.002, 0.013), (0.01, 0.005), (0.0005, 0.0005)]:
+        ds = O.make_design(p, [a1, a2])
+        assert ds["r"] == r2 and ds["r3"] == r3
+        z = (ds["z1"], ds["z2"], ds["z3"])
+        assert abs(z[0] + ndtri(a1)) < 1e-12 and abs(z[1] + ndtri(a2)) < 1e-12
+        assert abs((1.0 - _tvn_scipy(z, *R)) - 0.025) < 2e-8
+    # the first two levels already spend alpha0: no valid third level
+    assert math.isnan(O.make_design(p, [0.02, 0.01])["z3"])
+
+
+def test_alpha3_draws_and_monte_carlo():
+    p = _alpha3()
+    p2 = W.alpha_design(5)
+    for k in (0, 7, 12345):
+        d3, d2 = O.make_draw(p, k), O.make_draw(p2, k)
+        assert d3["e1"] == d2["e1"] and d3["e2"] == d2["e2"]   # same first two normals
+        assert abs(d3["e3"] - ndtri(d3["u"][2])) < 1e-12
+    M = 20000
+    q = np.array([[0.002, 0.013], [0.008, 0.008], [0.001, 0.002]])
+    m, v = O.eval_points(p, q, M)
+    for i in range(len(q)):
+        ex = O.exact_paper(p, q[i])
+        assert abs(m[i] - ex) < 4 * math.sqrt(v[i] / M), (q[i], m[i], ex)

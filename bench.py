@@ -198,7 +198,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="3d", choices=["3d", "1d", "5d", "alpha", "levels", "grad", "refine", "batch"])
+    ap.add_argument("--workload", default="3d", choices=["3d", "1d", "5d", "alpha", "alpha3", "levels", "grad", "refine", "batch"])
     ap.add_argument("--batch-scale", type=float, default=1.0,
                     help="batch workload only: scale of the per-axis grids and of the draw range (1 = full size)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -231,6 +231,8 @@ def main():
         return bench_grad(args)
     if args.workload == "refine":
         return bench_refine(args)
+    if args.workload == "alpha3":
+        return bench_alpha3(args)
     if args.workload == "levels":
         return bench_levels(args)
     if args.workload == "batch":
@@ -349,6 +351,71 @@ def bench_grad(args):
                             "max_abs_diff_objective": float((o32 - o64).abs().max()),
                             "max_abs_diff_grad_rel_to_max": float(max((g32 - g64).abs().max(),
                                                                       (m32 - m64).abs().max()) / scale)}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_alpha3(args):
+    """Three nested populations (Sec. 3, condition (c)): the 97 x 97 grid of
+    levels (alpha_1, alpha_2), alpha_3 on the FWER boundary, M = 1e5 draws;
+    a step is problem set-up (critical values) + draws + sweep + argmax over
+    the designs that have a third level (no smoothing: designs without one
+    are NaN, and a kernel smoother across them is undefined).  FP32 and FP64."""
+    import torch
+    import paper_2005_10494_amd as bmd
+    from paper_2005_10494_amd import workloads as W
+    spec = W.alpha3_grid()
+    M, G = spec["n_draws"], int(np.prod(spec["m"]))
+    res = {}
+    for prec in ("fp32", "fp64"):
+        ts, sw = [], []
+        for it in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            with bmd.Problem(spec) as p:
+                p.profile(True)
+                mean = p.eval_grid(M, prec)
+                idx, val, cell = p.argmax(mean)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                ph = p.profile_read()
+            if it >= args.warmup:
+                ts.append(dt)
+                sw.append(ph["sweep"])
+            log(f"  alpha3 {prec} step {it}: {1e3 * dt:.1f} ms, sweep {ph['sweep']:.1f} ms")
+        res[prec] = (float(np.mean(ts)), float(np.mean(sw)), mean, idx, val, cell)
+    t32, s32, m32, i32, v32, c32 = res["fp32"]
+    t64, s64, m64, i64, v64, _ = res["fp64"]
+    feasible = int((~torch.isnan(m32)).sum().item())
+    evals = feasible * M
+    a_best = [spec["q_lo"] + (spec["q_hi"] - spec["q_lo"]) * c / (m - 1) for c, m in zip(c32, spec["m"])]
+    # Per summand: three means (12) and, per panel node, the node (1), the two
+    # conditional arguments (4), the Gaussian factor (3), the bivariate CDF
+    # (13 + 6 per node) and the weighted sum (2).
+    r2, r3 = spec["r_lo"], spec["r_hi"]
+    rho = np.sqrt(r3 * (1 - r2) / (r2 * (1 - r3)))
+    n32 = int(bvn_nodes(np.array([rho]), "fp32")[0])
+    flops = feasible * M * (12.0 + 8 * 8 * (23.0 + 6.0 * n32))
+    achieved = flops / (1e-3 * s32) / 1e12
+    out = {"metric": "three-population alpha grid: integrand evals/s", "value": evals / t32,
+           "unit": "integrand evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * t32, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"three nested populations r = (1, {spec['r_lo']}, {spec['r_hi']}), "
+                                  f"(alpha_1, alpha_2) grid {spec['m'][0]}x{spec['m'][1]} over "
+                                  f"[{spec['q_lo']}, {spec['q_hi']}], alpha_3 on the FWER boundary, Formula 10 "
+                                  f"prior D0(r) = {spec['paper_a']} - {spec['paper_b']} r, I_3 = {spec['info']:g}, "
+                                  f"M={M}, steps = precompute+draws+sweep+argmax over feasible designs",
+                      "designs": G, "feasible_designs": feasible, "n_draws": M},
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
+                        "frac": achieved / 157.3, "traffic": None,
+                        "kernel": "k_eval_three<float,8,12,false> (one design per thread, 8 panels x 8 points, "
+                                  f"{n32}-node inner bivariate rule)", "flops_per_launch": flops},
+           "sweep_ms": s32, "sweep_evals_per_s": evals / (1e-3 * s32),
+           "result": {"best_alpha": a_best, "best_power": v32},
+           "fp64": {"ms_per_step": 1e3 * t64, "sweep_ms": s64},
+           "fp32_vs_fp64": {"speedup_sweep": s64 / s32,
+                            "max_abs_diff_objective": float(np.nanmax((m32 - m64).abs().cpu().numpy())),
+                            "argmax_fp32": int(i32), "argmax_fp64": int(i64)}}
     print(json.dumps(out), flush=True)
 
 

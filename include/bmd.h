@@ -93,7 +93,19 @@ typedef enum {
      * alpha0); with d = 2, axis 0 is the subgroup fraction r_2 over [r_lo,
      * r_hi]; with d = 1, r_2 = r_lo.  Formula 10 prior only
      * (BMD_EFFECT_PAPER_GAUSS); rho_b, gh_nodes and indicator_width are unused. */
-    BMD_DESIGN_ALPHA = 1
+    BMD_DESIGN_ALPHA = 1,
+    /* n = 3 nested populations 1 > r_2 > r_3 (Sec. 2.2, Appendix A.1, Sec. 3
+     * condition (c)): d = 2, axis 0 the first test's level alpha_1 and axis 1
+     * the second's alpha_2, both over [q_lo, q_hi] inside (0, alpha0); the
+     * third critical value lies on the FWER boundary 1 - Phi_3(z1, z2, z3) =
+     * alpha0 of the null correlations sqrt(r_2), sqrt(r_3), sqrt(r_3/r_2).
+     * r_lo holds r_2 and r_hi holds r_3, 0 < r_3 < r_2 <= 0.9, with partial
+     * correlation sqrt(r_3 (1 - r_2) / (r_2 (1 - r_3))) <= 0.975.  A design
+     * whose first two levels already spend alpha0 has no third level: its
+     * estimate is NaN.  Formula 10 prior with three normals per draw
+     * (BMD_EFFECT_PAPER_GAUSS); alpha_rule must be BMD_ALPHA_FWER_EQUAL.
+     * Grid sweeps only (no batch, gradient or level-split calls). */
+    BMD_DESIGN_ALPHA3 = 2
 } bmd_design_space;
 
 /* Problem descriptor (copied by bmd_create_problem). */
@@ -125,7 +137,8 @@ typedef struct {
     uint32_t scenario_id;      /* third Philox counter word                         */
     int32_t design_space;      /* bmd_design_space (0 = cutoffs)                    */
     double r_lo, r_hi;         /* BMD_DESIGN_ALPHA: subgroup-fraction axis (d = 2),
-                                  0 < r_lo < r_hi <= 0.95, or r_2 = r_lo (d = 1)    */
+                                  0 < r_lo < r_hi <= 0.95, or r_2 = r_lo (d = 1);
+                                  BMD_DESIGN_ALPHA3: r_lo = r_2, r_hi = r_3         */
 } bmd_problem_desc;
 
 /* Version of this header the library was built from (BMD_ABI_VERSION). */
@@ -279,13 +292,16 @@ bmd_status bmd_profile_read(bmd_problem *p, double *h_ms);
 /* Draws k0 .. k0+n-1 as the kernels generate them.
  *   d_u      [n*8]  FP64 uniforms in consumption order (unused slots 0)
  *   d_fields [n*BMD_DRAW_FIELDS] FP64: b0, b1, P(R), e1, e2, tau[6], t[6]
- *            (step prior: b0, b1, P(R), tau, t = Phi^-1(tau); paper prior: e1, e2) */
+ *            (step prior: b0, b1, P(R), tau, t = Phi^-1(tau); paper prior: e1, e2;
+ *            BMD_DESIGN_ALPHA3 also the third normal e3 in the tau[0] slot) */
 bmd_status bmd_draws(bmd_problem *p, uint64_t k0, uint64_t n, double *d_u, double *d_fields,
                      void *stream);
 
 #define BMD_DESIGN_FIELDS 16
 /* Design quantities for grid designs g0 .. g0+n-1:
- *   d_fields [n*BMD_DESIGN_FIELDS] FP64: q[6], c[6] = Phi^-1(q), r, sqrt(r), z1, z2 */
+ *   d_fields [n*BMD_DESIGN_FIELDS] FP64: q[6], c[6] = Phi^-1(q), r, sqrt(r), z1, z2
+ *            (alpha design spaces: c[] is 0, except BMD_DESIGN_ALPHA3: c[0] = r_3
+ *            and c[1] = z3, NaN when the design has no third level) */
 bmd_status bmd_designs(bmd_problem *p, int64_t g0, int64_t n, double *d_fields, void *stream);
 
 #ifdef __cplusplus

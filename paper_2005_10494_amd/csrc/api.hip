@@ -97,7 +97,7 @@ double host_orthant(const std::vector<double>& v, double rho, const double* x, c
 // reference to `target` relative error at probe points spanning the cutoffs
 // the problem can produce (design cutoffs and drawn responder cutoffs).
 int choose_gh(const bmd_problem_desc& d, double target) {
-    if (d.d == 1 || d.design_space == BMD_DESIGN_ALPHA) return 4;   // closed forms; tables unused
+    if (d.d == 1 || d.design_space != BMD_DESIGN_CUTOFFS) return 4;   // closed forms; tables unused
     static const int cand[] = {4, 8, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 128};
     std::vector<double> xr(128), wr(128);
     gauss_hermite_prob(128, xr.data(), wr.data());
@@ -186,6 +186,15 @@ bmd_status validate(const bmd_problem_desc* d, bool* grid) {
         if (!finite(d->r_lo) || !finite(d->r_hi) || !(d->r_lo > 0.0 && d->r_hi <= 0.95) ||
             (d->d == 2 && !(d->r_lo < d->r_hi)))
             return fail(BMD_ERANGE, "need 0 < r_lo %s r_hi <= 0.95", d->d == 2 ? "<" : "and");
+    } else if (d->design_space == BMD_DESIGN_ALPHA3) {
+        if (d->effect != BMD_EFFECT_PAPER_GAUSS || d->alpha_rule != BMD_ALPHA_FWER_EQUAL)
+            return fail(BMD_EINVAL, "alpha designs need the Formula 10 prior and the FWER-boundary rule");
+        if (!any || d->d != 2) return fail(BMD_ERANGE, "three-population designs are a grid over (alpha_1, alpha_2)");
+        if (!(d->q_hi < d->alpha0)) return fail(BMD_ERANGE, "alpha_1 and alpha_2 ranges must lie inside (0, alpha0)");
+        if (!finite(d->r_lo) || !finite(d->r_hi) || !(0.0 < d->r_hi && d->r_hi < d->r_lo && d->r_lo <= 0.9))
+            return fail(BMD_ERANGE, "need 0 < r_3 = r_hi < r_2 = r_lo <= 0.9");
+        if (d->r_hi * (1.0 - d->r_lo) > 0.975 * 0.975 * d->r_lo * (1.0 - d->r_hi))
+            return fail(BMD_ERANGE, "partial correlation of the third on the second population exceeds 0.975");
     } else if (d->design_space != BMD_DESIGN_CUTOFFS) {
         return fail(BMD_EINVAL, "unknown design_space %d", d->design_space);
     }
@@ -251,6 +260,7 @@ void free_problem(bmd_problem* p) {
     f(p->d_r);
     f(p->d_z1);
     f(p->d_z2);
+    f(p->d_z3);
     f(p->d_W);
     f(p->d_Wf);
     f(p->d_ws);
@@ -381,7 +391,7 @@ bmd_status bmd_create_problem(const bmd_problem_desc* desc, bmd_problem** out, v
     P.key0 = static_cast<uint32_t>(d.seed);
     P.key1 = static_cast<uint32_t>(d.seed >> 32);
     P.scenario = d.scenario_id;
-    P.n_uniform = d.effect == BMD_EFFECT_STEP ? 2 + d.d : 2;
+    P.n_uniform = d.effect == BMD_EFFECT_STEP ? 2 + d.d : d.design_space == BMD_DESIGN_ALPHA3 ? 3 : 2;
     {
         // BMD_SWEEP=direct selects the direct (vector-unit) sweep for every grid
         // problem; both sweeps compute the same estimate (used by the tests).
@@ -440,6 +450,7 @@ bmd_status bmd_create_problem(const bmd_problem_desc* desc, bmd_problem** out, v
         st = upload<double>(&p->d_r, nullptr, P.G);
         if (st == BMD_OK) st = upload<double>(&p->d_z1, nullptr, P.G);
         if (st == BMD_OK) st = upload<double>(&p->d_z2, nullptr, P.G);
+        if (st == BMD_OK && d.design_space == BMD_DESIGN_ALPHA3) st = upload<double>(&p->d_z3, nullptr, P.G);
         // Smoothing matrices.
         std::vector<double> W;
         for (int j = 0; j < d.d && st == BMD_OK; ++j) {
@@ -918,6 +929,8 @@ bmd_status bmd_eval_batch(bmd_problem* const* ps, int32_t n, const uint64_t* n_d
     for (int i = 0; i < n; ++i) {
         if (!ps[i] || !d_means[i]) return fail(BMD_EINVAL, "problem or output %d is NULL", i);
         if (!ps[i]->grid) return fail(BMD_ESTATE, "problem %d has no grid", i);
+        if (ps[i]->P.design_space == BMD_DESIGN_ALPHA3)
+            return fail(BMD_ENOTSUP, "problem %d: three-population designs are not batched", i);
         if (ps[i]->device != ps[0]->device) return fail(BMD_EINVAL, "problems live on different devices");
         if (n_draws[i] == 0 || n_draws[i] > (1ull << 40)) return fail(BMD_ERANGE, "n_draws[%d] outside [1, 2^40]", i);
     }

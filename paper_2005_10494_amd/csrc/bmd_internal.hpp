@@ -54,6 +54,7 @@ struct DrawArrays {
     T* tauT;    // [M]  tau_0 (one-biomarker closed form)
     T* e1;      // [M]  paper prior normals
     T* e2;      // [M]
+    T* e3;      // [M]  third normal (three nested populations)
     int32_t* thr;   // [M][d] first grid index whose cutoff quantile exceeds tau_j
     T* q4;      // [M][4] (b0, b1, mu1, 0): one 4-vector per draw for the matrix-core sweep
     double* tau;    // [d][M]
@@ -115,6 +116,7 @@ struct bmd_problem {
     double* d_r = nullptr;           // [G]
     double* d_z1 = nullptr;          // [G]
     double* d_z2 = nullptr;          // [G]
+    double* d_z3 = nullptr;          // [G] third critical value (three nested populations)
     double* d_W = nullptr;           // smoothing matrices, FP64, sum_j m_j^2
     float* d_Wf = nullptr;           // same in FP32
     int64_t w_off[bmd::kMaxDim] = {0, 0, 0, 0, 0, 0};
@@ -143,6 +145,12 @@ hipError_t launch_design_precompute(const bmd_problem* p, hipStream_t s);
 hipError_t launch_levels_z(const bmd_problem* p, double z1, hipStream_t s);
 hipError_t launch_levels_best(const bmd_problem* p, int k, const double* mean, double* best, int32_t* best_k,
                               hipStream_t s);
+// Three nested populations (kernels_three.hip): critical values of every
+// design, and the grid sweep (direct, one thread per design).
+hipError_t launch_three_precompute(const bmd_problem* p, hipStream_t s);
+int three_blocks_per_cu(int prec);
+hipError_t launch_eval_three(const bmd_problem* p, int prec, int64_t M, const void* ws, double* partials,
+                             int n_slices, int64_t slice_len, bool want_var, hipStream_t s);
 hipError_t launch_axis_tables(const bmd_problem* p, int prec, hipStream_t s);
 hipError_t launch_draws(const bmd_problem* p, int prec, uint64_t k0, int64_t M, void* ws,
                         hipStream_t s);

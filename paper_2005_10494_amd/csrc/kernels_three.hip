@@ -1,0 +1,269 @@
+// Three nested populations 1 > r2 > r3 (n = 3 of Sec. 2.2, with the null
+// correlations of Appendix A.1 and the Formula 10 prior; Sec. 3 condition
+// (c)): per-design critical values with the third on the FWER boundary of
+// Formula 2, and the grid sweep of the Formula 5 estimate whose summand is
+// 1 - Phi_3(z - mu; R).
+//
+// Phi_3 by conditioning on the first coordinate:
+//   Phi_3(h1, h2, h3; R) = int_{-inf}^{h1} phi(x) Phi_2((h2 - r12 x)/s12, (h3 - r13 x)/s13; r23.1) dx
+// with s1j = sqrt(1 - r1j^2) and r23.1 the partial correlation.  For the nested
+// correlations r12 = sqrt(r2), r13 = sqrt(r3), r23 = sqrt(r3/r2) it is
+// r23.1 = sqrt(r3 (1 - r2) / (r2 (1 - r3))), one constant per problem, so the
+// inner bivariate rule is set up once per thread.  The integral runs over
+// [-8.5, U] (Phi(-8.5) < 1e-17), U = min(h1, 8.5, the x beyond which either
+// conditional argument falls below -8.5), cut into equal panels of an 8-point
+// Gauss-Legendre rule: 12 panels in FP64 and 8 in FP32 keep the quadrature
+// error below 1e-10 and 2e-8 for r2 <= 0.9, 16 panels for the critical values.
+#include <cmath>
+
+#include "bmd_internal.hpp"
+#include "device_math.hpp"
+
+namespace bmd {
+namespace {
+
+constexpr double kTail = 8.5;
+constexpr int kNodes = 8;          // Gauss-Legendre points per panel
+constexpr int kPanelsSetup = 16;   // critical values (FP64)
+constexpr int kPanels64 = 12;      // sweep summand, FP64
+constexpr int kPanels32 = 8;       // sweep summand, FP32
+
+__device__ __forceinline__ double partial_corr(double r2, double r3) {
+    return sqrt(r3 * (1.0 - r2) / (r2 * (1.0 - r3)));
+}
+
+// exp(-x^2 / 2); FP32 through exp2.
+__device__ __forceinline__ double half_gauss(double x) { return exp(-0.5 * x * x); }
+__device__ __forceinline__ float half_gauss(float x) {
+    return __builtin_amdgcn_exp2f(x * x * -0.72134752044448170368f);   // log2(e) / 2
+}
+
+// Per-problem constants of Phi_3 in type T.
+template <typename T, int NMAX>
+struct TvnConst {
+    T r12, r13;        // regressions of the second and third coordinates on the first
+    T is12, is13;      // 1 / s1j
+    T c2, c3;          // 8.5 s1j: offsets of the upper integration limit
+    T ir12, ir13;      // 1 / r1j
+    T px[kNodes];      // panel nodes on [0, 1]
+    T pw[kNodes];      // panel weights with phi's 1/sqrt(2 pi) folded in
+    BvnConst<T, NMAX> bc;   // inner bivariate rule at r23.1
+    int n;                  // its node count
+
+    __device__ void init(double r2, double r3, int n_inner, const double* __restrict__ gl) {
+        const double a = sqrt(r2), b = sqrt(r3), sa = sqrt(1.0 - r2), sb = sqrt(1.0 - r3);
+        r12 = static_cast<T>(a);
+        r13 = static_cast<T>(b);
+        is12 = static_cast<T>(1.0 / sa);
+        is13 = static_cast<T>(1.0 / sb);
+        c2 = static_cast<T>(kTail * sa);
+        c3 = static_cast<T>(kTail * sb);
+        ir12 = static_cast<T>(1.0 / a);
+        ir13 = static_cast<T>(1.0 / b);
+        const double* x = gl + gl_offset(kNodes);
+        const double* w = x + kNodes;
+#pragma unroll
+        for (int i = 0; i < kNodes; ++i) {
+            px[i] = static_cast<T>(0.5 * (1.0 + x[i]));
+            pw[i] = static_cast<T>(0.5 * w[i] * 0.39894228040143267794);
+        }
+        n = n_inner;
+        bc.init(partial_corr(r2, r3), n_inner, gl);
+    }
+};
+
+// Phi_3(h1, h2, h3) over NP panels.  Every lane runs the same node count: an
+// empty range (U <= -8.5) becomes a zero panel width, and NaN inputs give NaN.
+template <int NP, typename T, int NMAX, typename W>
+__device__ __forceinline__ T tvn(T h1, T h2, T h3, const TvnConst<T, NMAX>& c, const W& w) {
+    const T lo = static_cast<T>(-kTail);
+    const T hi = fmin(fmin(h1, static_cast<T>(kTail)), fmin((h2 + c.c2) * c.ir12, (h3 + c.c3) * c.ir13));
+    const T width = fmax(hi - lo, T(0)) * static_cast<T>(1.0 / NP);
+    T acc = T(0);
+    for (int p = 0; p < NP; ++p) {
+        const T a = fma(width, static_cast<T>(p), lo);
+#pragma unroll
+        for (int i = 0; i < kNodes; ++i) {
+            const T x = fma(width, c.px[i], a);
+            const T u = (h2 - c.r12 * x) * c.is12;
+            const T v = (h3 - c.r13 * x) * c.is13;
+            acc = fma(c.pw[i] * half_gauss(x), bvn_cdf<NMAX>(u, v, c.bc, w, c.n), acc);
+        }
+    }
+    return acc * width;
+}
+
+// Levels alpha_1 (axis 0) and alpha_2 (axis 1) of design g; the third critical
+// value solves 1 - Phi_3(z1, z2, z3) = alpha0 by bisection between the third
+// test alone at level alpha0 (FWER >= alpha0) and the union bound with the
+// level a12 = 1 - Phi_2(z1, z2; sqrt r2) the first two spend (FWER <= alpha0).
+// NaN when a12 >= alpha0.
+__global__ __launch_bounds__(64) void k_three_precompute(DevProblem P, const double* __restrict__ gl,
+                                                         double* __restrict__ r_out, double* __restrict__ z1_out,
+                                                         double* __restrict__ z2_out, double* __restrict__ z3_out) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= P.G) return;
+    const int i0 = static_cast<int>(g / P.stride[0]);
+    const int i1 = static_cast<int>(g - static_cast<int64_t>(i0) * P.stride[0]);
+    const double z1 = -norm_quantile(grid_coord(P.q_lo, P.q_hi, i0, P.m[0]));
+    const double z2 = -norm_quantile(grid_coord(P.q_lo, P.q_hi, i1, P.m[1]));
+    r_out[g] = P.r_lo;
+    z1_out[g] = z1;
+    z2_out[g] = z2;
+    constexpr int n = 24;
+    const double* w = gl + gl_offset(n) + n;
+    BvnConst<double, n> b12;
+    b12.init(sqrt(P.r_lo), n, gl);
+    const double a12 = 1.0 - bvn_cdf<n>(z1, z2, b12, w, n);
+    double z3 = NAN;
+    if (a12 < P.alpha0) {
+        TvnConst<double, n> c;
+        c.init(P.r_lo, P.r_hi, n, gl);
+        double lo = -norm_quantile(P.alpha0), hi = -norm_quantile(P.alpha0 - a12);
+        for (int it = 0; it < 200; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (!(mid > lo && mid < hi)) break;
+            if (1.0 - tvn<kPanelsSetup>(z1, z2, mid, c, w) > P.alpha0) lo = mid; else hi = mid;
+        }
+        z3 = 0.5 * (lo + hi);
+    }
+    z3_out[g] = z3;
+}
+
+template <typename T>
+struct ThreeArgs {
+    int64_t G;
+    const double* z1;
+    const double* z2;
+    const double* z3;
+    const T* e1;
+    const T* e2;
+    const T* e3;
+    int64_t M;
+    int64_t slice_len;
+    double* partials;   // [n_slices][2][G]: sums, then sums of squares (VAR only)
+    const double* gl;   // packed Gauss-Legendre table, FP64
+    const T* glw;       // the same in T (inner weights read from here)
+    double r2, r3;
+    // Formula 10 means of the three statistics, sqrt(r_i I) (theta_i + sigma_i Y_i):
+    // mu1 = m0 + m1 e1, mu2 = m2 + m3 e1 + m4 e2, mu3 = m5 + m6 e1 + m7 e2 + m8 e3.
+    double m[9];
+};
+
+// One thread per design (alpha_1, alpha_2), the draws of slice blockIdx.y.
+template <typename T, int NP, int NMAX, bool VAR>
+__global__ __launch_bounds__(kEvalBlock) void k_eval_three(ThreeArgs<T> a) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * kEvalBlock + threadIdx.x;
+    const bool valid = g < a.G;
+    const int64_t gg = valid ? g : a.G - 1;   // idle lanes shadow the last design
+    const double rho = partial_corr(a.r2, a.r3);
+    const int n = sizeof(T) == 8 ? bvn_nodes_fp64(rho) : bvn_nodes_fp32(rho);
+    TvnConst<T, NMAX> c;
+    c.init(a.r2, a.r3, n, a.gl);
+    const T* w = a.glw + gl_offset(n) + n;
+    const T z1 = static_cast<T>(a.z1[gg]), z2 = static_cast<T>(a.z2[gg]), z3 = static_cast<T>(a.z3[gg]);
+    T m[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) m[i] = static_cast<T>(a.m[i]);
+    const int slice = blockIdx.y;
+    const int64_t kb = static_cast<int64_t>(slice) * a.slice_len;
+    const int64_t ke = min(a.M, kb + a.slice_len);
+    double s1 = 0.0, s2 = 0.0;
+    for (int64_t k = kb; k < ke; ++k) {
+        const T e1 = a.e1[k], e2 = a.e2[k], e3 = a.e3[k];
+        const T h1 = z1 - fma(m[1], e1, m[0]);
+        const T h2 = z2 - fma(m[4], e2, fma(m[3], e1, m[2]));
+        const T h3 = z3 - fma(m[8], e3, fma(m[7], e2, fma(m[6], e1, m[5])));
+        const double v = static_cast<double>(T(1) - tvn<NP>(h1, h2, h3, c, w));
+        s1 += v;
+        if constexpr (VAR) s2 = fma(v, v, s2);
+    }
+    if (valid) {
+        double* out = a.partials + static_cast<int64_t>(slice) * 2 * a.G;
+        out[g] = s1;
+        if constexpr (VAR) out[a.G + g] = s2;
+    }
+}
+
+template <typename T>
+ThreeArgs<T> three_args(const bmd_problem* p, DrawArrays<T> D, const T* glw, double* partials, int64_t slice_len) {
+    const DevProblem& P = p->P;
+    ThreeArgs<T> a{};
+    a.G = P.G;
+    a.z1 = p->d_z1;
+    a.z2 = p->d_z2;
+    a.z3 = p->d_z3;
+    a.e1 = D.e1;
+    a.e2 = D.e2;
+    a.e3 = D.e3;
+    a.M = D.M;
+    a.slice_len = slice_len;
+    a.partials = partials;
+    a.gl = p->d_gl;
+    a.glw = glw;
+    a.r2 = P.r_lo;
+    a.r3 = P.r_hi;
+    const double r[3] = {1.0, P.r_lo, P.r_hi};
+    double th[3], sc[3];
+    for (int i = 0; i < 3; ++i) {
+        th[i] = -std::log1p(-(P.paper_a - P.paper_b * r[i]));
+        sc[i] = std::sqrt(r[i] * P.info) / std::sqrt(P.paper_events * r[i] / 4.0);   // sqrt(r_i I) sigma_i
+    }
+    // Y1 = e1, Y2 = sqrt(r2) e1 + sqrt(1 - r2) e2,
+    // Y3 = sqrt(r3) e1 + sqrt(r3 (1 - r2) / r2) e2 + sqrt(1 - r3 / r2) e3
+    a.m[0] = std::sqrt(P.info) * th[0];
+    a.m[1] = sc[0];
+    a.m[2] = std::sqrt(r[1] * P.info) * th[1];
+    a.m[3] = sc[1] * std::sqrt(r[1]);
+    a.m[4] = sc[1] * std::sqrt(1.0 - r[1]);
+    a.m[5] = std::sqrt(r[2] * P.info) * th[2];
+    a.m[6] = sc[2] * std::sqrt(r[2]);
+    a.m[7] = sc[2] * std::sqrt(r[2] * (1.0 - r[1]) / r[1]);
+    a.m[8] = sc[2] * std::sqrt(1.0 - r[2] / r[1]);
+    return a;
+}
+
+template <typename T, int NP, int NMAX>
+hipError_t launch_typed(const ThreeArgs<T>& a, int n_slices, bool var, hipStream_t s) {
+    const void* k = var ? reinterpret_cast<const void*>(k_eval_three<T, NP, NMAX, true>)
+                        : reinterpret_cast<const void*>(k_eval_three<T, NP, NMAX, false>);
+    void* args[] = {const_cast<ThreeArgs<T>*>(&a)};
+    return hipLaunchKernel(k, dim3(static_cast<unsigned>((a.G + kEvalBlock - 1) / kEvalBlock),
+                                   static_cast<unsigned>(n_slices)),
+                           dim3(kEvalBlock), args, 0, s);
+}
+
+}  // namespace
+
+hipError_t launch_three_precompute(const bmd_problem* p, hipStream_t s) {
+    const int64_t G = p->P.G;
+    hipLaunchKernelGGL(k_three_precompute, dim3(static_cast<unsigned>((G + 63) / 64)), dim3(64), 0, s, p->P,
+                       p->d_gl, p->d_r, p->d_z1, p->d_z2, p->d_z3);
+    return hipGetLastError();
+}
+
+int three_blocks_per_cu(int prec) {
+    const void* k = prec == BMD_FP64 ? reinterpret_cast<const void*>(k_eval_three<double, kPanels64, 24, false>)
+                                     : reinterpret_cast<const void*>(k_eval_three<float, kPanels32, 12, false>);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kEvalBlock, 0) != hipSuccess || nb < 1) {
+        (void)hipGetLastError();
+        nb = 1;
+    }
+    return nb;
+}
+
+hipError_t launch_eval_three(const bmd_problem* p, int prec, int64_t M, const void* ws, double* partials,
+                             int n_slices, int64_t slice_len, bool want_var, hipStream_t s) {
+    if (prec == BMD_FP64)
+        return launch_typed<double, kPanels64, 24>(
+            three_args<double>(p, draws_fp64(p, M, ws), static_cast<const double*>(p->tab[prec].glw), partials,
+                               slice_len),
+            n_slices, want_var, s);
+    return launch_typed<float, kPanels32, 12>(
+        three_args<float>(p, draws_fp32(p, M, ws), static_cast<const float*>(p->tab[prec].glw), partials,
+                          slice_len),
+        n_slices, want_var, s);
+}
+
+}  // namespace bmd

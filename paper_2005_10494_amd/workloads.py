@@ -88,6 +88,27 @@ def alpha_grid() -> dict:
     return alpha_design(241, m_r=181, r_range=(0.05, 0.95), n_draws=1_000_000, bandwidth=(0.02, 0.0005))
 
 
+def alpha3_design(m: int, r2: float = 0.446, r3: float = 0.168, q_range=(0.0005, 0.0245),
+                  n_draws: int = 10_240, bandwidth: float = 0.0015) -> dict:
+    """Three nested populations (Sec. 3, condition (c): drug effect
+    D0(r) = 0.8 - 0.6 r, I_3 = 211, Formula 10 prior with E = 80, subgroup
+    fractions r_2 = 0.446 and r_3 = 0.168): an m x m grid of the first two
+    levels (alpha_1, alpha_2) over ``q_range``, alpha_3 from the FWER boundary.
+    Designs whose first two levels already spend alpha0 have no third level."""
+    p = base_problem(2, [m, m], 0.0, bandwidth, design="alpha3", q_lo=float(q_range[0]),
+                     q_hi=float(q_range[1]), info=211.0, effect="paper", paper_a=0.8, paper_b=0.6,
+                     paper_events=80.0)
+    p["r_lo"], p["r_hi"] = float(r2), float(r3)
+    p["n_draws"] = n_draws
+    return p
+
+
+def alpha3_grid() -> dict:
+    """Condition (c) of Sec. 3 as a design grid: alpha_1 and alpha_2 each over
+    [0.0005, 0.0245] in steps of 0.00025 (97 x 97), M = 100,000 draws."""
+    return alpha3_design(97, n_draws=100_000)
+
+
 def design_points(n: int, d: int, seed: int = 1, lo: float = 0.1, hi: float = 0.9) -> np.ndarray:
     """Continuous design points, iid U(lo, hi)^d (cutoff quantiles)."""
     rng = np.random.default_rng(seed)

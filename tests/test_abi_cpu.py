@@ -120,3 +120,18 @@ def test_workloads_are_inputs_only():
     assert W.plain_3d()["m"] == [64, 64, 64] and W.precision_5d()["n_draws"] == 200_000
     sc = W.batch_scenarios(16)
     assert all(1 <= s["d"] <= 6 and 1e4 <= s["n_draws"] <= 1e6 for s in sc)
+
+
+@pytest.mark.parametrize("change,status", [
+    ({"effect": "step"}, -1), ({"alpha_rule": "bonferroni"}, -1), ({"q_hi": 0.025}, -2),
+    ({"r_lo": 0.1, "r_hi": 0.2}, -2), ({"r_lo": 0.95}, -2), ({"r_hi": 0.0}, -2),
+    ({"r_lo": 0.9, "r_hi": 0.899}, -2),   # partial correlation above 0.975
+    ({"d": 1, "m": [5], "bandwidth": [0.1]}, -2), ({"m": [0, 0]}, -2),
+])
+def test_alpha3_design_validation(change, status):
+    """Three nested populations (Sec. 2.2, n = 3) reject what they do not cover."""
+    spec = W.alpha3_design(5)
+    spec.update(change)
+    st, msg = _create_status(spec)
+    assert st == status, msg
+    assert msg

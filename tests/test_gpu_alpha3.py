@@ -1,0 +1,127 @@
+"""Three nested populations on the GPU (n = 3 of Sec. 2.2 with the Formula 10
+prior of Sec. 3's condition (c)): an (alpha_1, alpha_2) grid with alpha_3 on
+the FWER boundary, through the C ABI against the oracle on the same draws
+(bars as in test_gpu_parity: FP64 1e-9, FP32 1e-5, relative to max(|f|, 1e-3);
+grid coordinates and uniforms bit-exact; critical values 1e-10), and against
+the closed form of the prior within Monte Carlo error.  Designs whose first two
+levels spend alpha0 are NaN on both sides."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2005_10494_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2005_10494_amd as bmd  # noqa: E402
+
+TOL = {"fp64": 1e-9, "fp32": 1e-5}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _check(got, ref, prec, what):
+    got = np.asarray(got)
+    nan = np.isnan(ref)
+    assert np.array_equal(np.isnan(got), nan), f"{what} {prec}: NaN pattern differs"
+    got, ref = got[~nan], ref[~nan]
+    bound = TOL[prec] * np.maximum(np.abs(ref), 1e-3)
+    err = np.abs(got - ref)
+    w = int(np.argmax(err / bound))
+    assert np.all(err <= bound), f"{what} {prec}: index {w} got {got[w]!r} ref {ref[w]!r}"
+
+
+@pytest.mark.parametrize("spec", [W.alpha3_design(7), W.alpha3_design(5, r2=0.85, r3=0.3),
+                                  W.alpha3_design(4, r2=0.2, r3=0.02, q_range=(0.001, 0.012))])
+def test_alpha3_designs_and_critical_values(spec):
+    say(f"alpha3 designs m={spec['m']} r=({spec['r_lo']}, {spec['r_hi']})")
+    with bmd.Problem(spec) as p:
+        G = p.G
+        f = p.designs(0, G).cpu().numpy()
+        assert bmd.sweep_kind(p) == "direct"
+    n_nan = 0
+    for g in range(G):
+        q, _ = O.grid_point(spec, g)
+        assert np.array_equal(f[g, :2], q), g
+        ds = O.make_design(spec, q)
+        assert f[g, 12] == ds["r"] == spec["r_lo"] and f[g, 6] == ds["r3"] == spec["r_hi"]
+        assert abs(f[g, 14] - ds["z1"]) <= 1e-12 and abs(f[g, 15] - ds["z2"]) <= 1e-12, g
+        if math.isnan(ds["z3"]):
+            assert math.isnan(f[g, 7]), g
+            n_nan += 1
+        else:
+            assert abs(f[g, 7] - ds["z3"]) <= 1e-10, (g, f[g, 7], ds["z3"])
+    if spec["q_hi"] > 0.02:
+        assert 0 < n_nan < G
+
+
+def test_alpha3_draws():
+    spec = W.alpha3_design(5)
+    spec.update(seed=0x5EED, scenario=3)
+    k0, n = (1 << 32) - 20, 40
+    with bmd.Problem(spec) as p:
+        u, f = p.draws(k0, n)
+        u, f = u.cpu().numpy(), f.cpu().numpy()
+    for i in range(n):
+        dr = O.make_draw(spec, k0 + i)
+        assert np.array_equal(u[i, :3], dr["u"][:3]), i
+        assert np.all(u[i, 3:] == 0.0)
+        for j, e in ((3, dr["e1"]), (4, dr["e2"]), (5, dr["e3"])):
+            assert abs(f[i, j] - e) <= 4 * np.spacing(abs(e)) + 1e-17, (i, j, f[i, j], e)
+
+
+@pytest.mark.parametrize("spec,M", [(W.alpha3_design(7), 1000), (W.alpha3_design(5, r2=0.85, r3=0.3), 703)])
+def test_alpha3_grid_objective_matches_oracle(spec, M):
+    G = O.grid_size(spec)
+    say(f"alpha3 oracle m={spec['m']} M={M}")
+    ref_mean, ref_var = O.eval_grid(spec, np.arange(G), M)
+    for prec in ("fp64", "fp32"):
+        say(f"alpha3 grid m={spec['m']} M={M} {prec}")
+        with bmd.Problem(spec) as p:
+            mean, var = p.eval_grid(M, prec, want_var=True)
+            torch.cuda.synchronize()
+            mean, var = mean.cpu().numpy(), var.cpu().numpy()
+        _check(mean, ref_mean, prec, "alpha3 mean")
+        ok = ~np.isnan(ref_var)
+        assert np.allclose(var[ok], ref_var[ok], rtol=1e-6 if prec == "fp64" else 2e-3, atol=1e-9)
+
+
+def test_alpha3_converges_to_closed_form():
+    """5 x 5 levels around condition (c)'s printed optimum, 4 * 10^5 draws: every
+    feasible GPU estimate is within 5 Monte Carlo standard errors of the closed
+    form, and the argmax over feasible designs is the closed form's or within
+    one grid step of it."""
+    spec = W.alpha3_design(5, q_range=(0.0005, 0.0185))
+    M = 400_000
+    with bmd.Problem(spec) as p:
+        mean, var = p.eval_grid(M, "fp32", want_var=True)
+        torch.cuda.synchronize()
+        i_gpu, v_gpu, cell = p.argmax(mean)
+        mean, var = mean.cpu().numpy(), var.cpu().numpy()
+    exact = np.array([O.exact_paper(spec, O.grid_point(spec, g)[0]) for g in range(25)])
+    ok = ~np.isnan(exact)
+    assert np.array_equal(ok, ~np.isnan(mean))
+    z = (mean[ok] - exact[ok]) / np.sqrt(var[ok] / M)
+    assert np.max(np.abs(z)) < 5.0, z
+    i_ex = int(np.nanargmax(exact))
+    _, a = O.grid_point(spec, i_gpu)
+    _, b = O.grid_point(spec, i_ex)
+    assert max(abs(int(x) - int(y)) for x, y in zip(a, b)) <= 1
+    assert v_gpu == mean[i_gpu]
+
+
+def test_alpha3_not_batched():
+    spec = W.alpha3_design(5)
+    with bmd.Problem(spec) as p, bmd.Problem(W.plain_1d()) as q:
+        with pytest.raises(bmd.BmdError) as e:
+            bmd.eval_batch([q, p], [100, 100], "fp32")
+        assert e.value.status == -5

@@ -394,7 +394,8 @@ def bench_alpha3(args):
     r2, r3 = spec["r_lo"], spec["r_hi"]
     rho = np.sqrt(r3 * (1 - r2) / (r2 * (1 - r3)))
     n32 = int(bvn_nodes(np.array([rho]), "fp32")[0])
-    flops = feasible * M * (12.0 + 8 * 8 * (23.0 + 6.0 * n32))
+    np32 = max(4, min(32, int(np.ceil(2.5 / np.sqrt((1 - r2) / r2)))))   # FP32 panel rule
+    flops = feasible * M * (12.0 + np32 * 8 * (23.0 + 6.0 * n32))
     achieved = flops / (1e-3 * s32) / 1e12
     out = {"metric": "three-population alpha grid: integrand evals/s", "value": evals / t32,
            "unit": "integrand evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -408,7 +409,7 @@ def bench_alpha3(args):
                       "designs": G, "feasible_designs": feasible, "n_draws": M},
            "roofline": {"bound": "alu", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
                         "frac": achieved / 157.3, "traffic": None,
-                        "kernel": "k_eval_three<float,8,12,false> (one design per thread, 8 panels x 8 points, "
+                        "kernel": f"k_eval_three<float,12,false> (one design per thread, {np32} panels x 8 points, "
                                   f"{n32}-node inner bivariate rule)", "flops_per_launch": flops},
            "sweep_ms": s32, "sweep_evals_per_s": evals / (1e-3 * s32),
            "result": {"best_alpha": a_best, "best_power": v32},

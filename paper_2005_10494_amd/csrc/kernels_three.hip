@@ -10,10 +10,16 @@
 // correlations r12 = sqrt(r2), r13 = sqrt(r3), r23 = sqrt(r3/r2) it is
 // r23.1 = sqrt(r3 (1 - r2) / (r2 (1 - r3))), one constant per problem, so the
 // inner bivariate rule is set up once per thread.  The integral runs over
-// [-8.5, U] (Phi(-8.5) < 1e-17), U = min(h1, 8.5, the x beyond which either
-// conditional argument falls below -8.5), cut into equal panels of an 8-point
-// Gauss-Legendre rule: 12 panels in FP64 and 8 in FP32 keep the quadrature
-// error below 1e-10 and 2e-8 for r2 <= 0.9, 16 panels for the critical values.
+// [-L, U], U = min(h1, L, the x beyond which either conditional argument
+// falls below -L), with L = 8.5 in FP64 (Phi(-8.5) < 1e-17) and 6 in FP32
+// (Phi(-6) = 1e-9), cut into equal panels of an 8-point Gauss-Legendre rule.
+// The integrand's steepest feature is the conditional CDF of the second
+// coordinate, whose scale in x is l = s12 / r12 = sqrt((1 - r2) / r2) (the
+// third is gentler, r3 < r2); the panel count is ceil(c / l) with c = 6, at
+// least 8 panels in FP64, and c = 2.5, at least 4, in FP32.  Against an
+// adaptive reference over 0.1 <= r2 <= 0.9 this keeps the quadrature error
+// below 1e-12 (FP64) and 3e-9 (FP32); the critical values use at least 16
+// panels.
 #include <cmath>
 
 #include "bmd_internal.hpp"
@@ -22,11 +28,16 @@
 namespace bmd {
 namespace {
 
-constexpr double kTail = 8.5;
 constexpr int kNodes = 8;          // Gauss-Legendre points per panel
-constexpr int kPanelsSetup = 16;   // critical values (FP64)
-constexpr int kPanels64 = 12;      // sweep summand, FP64
-constexpr int kPanels32 = 8;       // sweep summand, FP32
+constexpr int kPanelsSetup = 16;   // fewest panels for the critical values (FP64)
+
+// Panels for the summand in type T at subgroup fraction r2.
+template <typename T>
+__device__ __forceinline__ int tvn_panels(double r2) {
+    const double l = sqrt((1.0 - r2) / r2);
+    const int lo = sizeof(T) == 8 ? 8 : 4;
+    return max(lo, min(32, static_cast<int>(ceil((sizeof(T) == 8 ? 6.0 : 2.5) / l))));
+}
 
 __device__ __forceinline__ double partial_corr(double r2, double r3) {
     return sqrt(r3 * (1.0 - r2) / (r2 * (1.0 - r3)));
@@ -43,21 +54,25 @@ template <typename T, int NMAX>
 struct TvnConst {
     T r12, r13;        // regressions of the second and third coordinates on the first
     T is12, is13;      // 1 / s1j
-    T c2, c3;          // 8.5 s1j: offsets of the upper integration limit
+    T tail;            // L: integration range [-L, U]
+    T c2, c3;          // L s1j: offsets of the upper integration limit
     T ir12, ir13;      // 1 / r1j
     T px[kNodes];      // panel nodes on [0, 1]
     T pw[kNodes];      // panel weights with phi's 1/sqrt(2 pi) folded in
     BvnConst<T, NMAX> bc;   // inner bivariate rule at r23.1
     int n;                  // its node count
+    int np;                 // panels
 
-    __device__ void init(double r2, double r3, int n_inner, const double* __restrict__ gl) {
+    __device__ void init(double r2, double r3, int n_inner, int panels, const double* __restrict__ gl) {
+        const double L = sizeof(T) == 8 ? 8.5 : 6.0;
         const double a = sqrt(r2), b = sqrt(r3), sa = sqrt(1.0 - r2), sb = sqrt(1.0 - r3);
         r12 = static_cast<T>(a);
         r13 = static_cast<T>(b);
         is12 = static_cast<T>(1.0 / sa);
         is13 = static_cast<T>(1.0 / sb);
-        c2 = static_cast<T>(kTail * sa);
-        c3 = static_cast<T>(kTail * sb);
+        tail = static_cast<T>(L);
+        c2 = static_cast<T>(L * sa);
+        c3 = static_cast<T>(L * sb);
         ir12 = static_cast<T>(1.0 / a);
         ir13 = static_cast<T>(1.0 / b);
         const double* x = gl + gl_offset(kNodes);
@@ -68,19 +83,21 @@ struct TvnConst {
             pw[i] = static_cast<T>(0.5 * w[i] * 0.39894228040143267794);
         }
         n = n_inner;
+        np = panels;
         bc.init(partial_corr(r2, r3), n_inner, gl);
     }
 };
 
-// Phi_3(h1, h2, h3) over NP panels.  Every lane runs the same node count: an
-// empty range (U <= -8.5) becomes a zero panel width, and NaN inputs give NaN.
-template <int NP, typename T, int NMAX, typename W>
+// Phi_3(h1, h2, h3) over c.np panels (wave-uniform).  Every lane runs the
+// same node count: an empty range (U <= -L) becomes a zero panel width, and
+// NaN inputs give NaN.
+template <typename T, int NMAX, typename W>
 __device__ __forceinline__ T tvn(T h1, T h2, T h3, const TvnConst<T, NMAX>& c, const W& w) {
-    const T lo = static_cast<T>(-kTail);
-    const T hi = fmin(fmin(h1, static_cast<T>(kTail)), fmin((h2 + c.c2) * c.ir12, (h3 + c.c3) * c.ir13));
-    const T width = fmax(hi - lo, T(0)) * static_cast<T>(1.0 / NP);
+    const T lo = -c.tail;
+    const T hi = fmin(fmin(h1, c.tail), fmin((h2 + c.c2) * c.ir12, (h3 + c.c3) * c.ir13));
+    const T width = fmax(hi - lo, T(0)) / static_cast<T>(c.np);
     T acc = T(0);
-    for (int p = 0; p < NP; ++p) {
+    for (int p = 0; p < c.np; ++p) {
         const T a = fma(width, static_cast<T>(p), lo);
 #pragma unroll
         for (int i = 0; i < kNodes; ++i) {
@@ -118,12 +135,12 @@ __global__ __launch_bounds__(64) void k_three_precompute(DevProblem P, const dou
     double z3 = NAN;
     if (a12 < P.alpha0) {
         TvnConst<double, n> c;
-        c.init(P.r_lo, P.r_hi, n, gl);
+        c.init(P.r_lo, P.r_hi, n, max(kPanelsSetup, tvn_panels<double>(P.r_lo)), gl);
         double lo = -norm_quantile(P.alpha0), hi = -norm_quantile(P.alpha0 - a12);
         for (int it = 0; it < 200; ++it) {
             const double mid = 0.5 * (lo + hi);
             if (!(mid > lo && mid < hi)) break;
-            if (1.0 - tvn<kPanelsSetup>(z1, z2, mid, c, w) > P.alpha0) lo = mid; else hi = mid;
+            if (1.0 - tvn(z1, z2, mid, c, w) > P.alpha0) lo = mid; else hi = mid;
         }
         z3 = 0.5 * (lo + hi);
     }
@@ -151,7 +168,7 @@ struct ThreeArgs {
 };
 
 // One thread per design (alpha_1, alpha_2), the draws of slice blockIdx.y.
-template <typename T, int NP, int NMAX, bool VAR>
+template <typename T, int NMAX, bool VAR>
 __global__ __launch_bounds__(kEvalBlock) void k_eval_three(ThreeArgs<T> a) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * kEvalBlock + threadIdx.x;
     const bool valid = g < a.G;
@@ -159,7 +176,7 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_three(ThreeArgs<T> a) {
     const double rho = partial_corr(a.r2, a.r3);
     const int n = sizeof(T) == 8 ? bvn_nodes_fp64(rho) : bvn_nodes_fp32(rho);
     TvnConst<T, NMAX> c;
-    c.init(a.r2, a.r3, n, a.gl);
+    c.init(a.r2, a.r3, n, tvn_panels<T>(a.r2), a.gl);
     const T* w = a.glw + gl_offset(n) + n;
     const T z1 = static_cast<T>(a.z1[gg]), z2 = static_cast<T>(a.z2[gg]), z3 = static_cast<T>(a.z3[gg]);
     T m[9];
@@ -174,7 +191,7 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_three(ThreeArgs<T> a) {
         const T h1 = z1 - fma(m[1], e1, m[0]);
         const T h2 = z2 - fma(m[4], e2, fma(m[3], e1, m[2]));
         const T h3 = z3 - fma(m[8], e3, fma(m[7], e2, fma(m[6], e1, m[5])));
-        const double v = static_cast<double>(T(1) - tvn<NP>(h1, h2, h3, c, w));
+        const double v = static_cast<double>(T(1) - tvn(h1, h2, h3, c, w));
         s1 += v;
         if constexpr (VAR) s2 = fma(v, v, s2);
     }
@@ -223,10 +240,10 @@ ThreeArgs<T> three_args(const bmd_problem* p, DrawArrays<T> D, const T* glw, dou
     return a;
 }
 
-template <typename T, int NP, int NMAX>
+template <typename T, int NMAX>
 hipError_t launch_typed(const ThreeArgs<T>& a, int n_slices, bool var, hipStream_t s) {
-    const void* k = var ? reinterpret_cast<const void*>(k_eval_three<T, NP, NMAX, true>)
-                        : reinterpret_cast<const void*>(k_eval_three<T, NP, NMAX, false>);
+    const void* k = var ? reinterpret_cast<const void*>(k_eval_three<T, NMAX, true>)
+                        : reinterpret_cast<const void*>(k_eval_three<T, NMAX, false>);
     void* args[] = {const_cast<ThreeArgs<T>*>(&a)};
     return hipLaunchKernel(k, dim3(static_cast<unsigned>((a.G + kEvalBlock - 1) / kEvalBlock),
                                    static_cast<unsigned>(n_slices)),
@@ -243,8 +260,8 @@ hipError_t launch_three_precompute(const bmd_problem* p, hipStream_t s) {
 }
 
 int three_blocks_per_cu(int prec) {
-    const void* k = prec == BMD_FP64 ? reinterpret_cast<const void*>(k_eval_three<double, kPanels64, 24, false>)
-                                     : reinterpret_cast<const void*>(k_eval_three<float, kPanels32, 12, false>);
+    const void* k = prec == BMD_FP64 ? reinterpret_cast<const void*>(k_eval_three<double, 24, false>)
+                                     : reinterpret_cast<const void*>(k_eval_three<float, 12, false>);
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kEvalBlock, 0) != hipSuccess || nb < 1) {
         (void)hipGetLastError();
@@ -256,11 +273,11 @@ int three_blocks_per_cu(int prec) {
 hipError_t launch_eval_three(const bmd_problem* p, int prec, int64_t M, const void* ws, double* partials,
                              int n_slices, int64_t slice_len, bool want_var, hipStream_t s) {
     if (prec == BMD_FP64)
-        return launch_typed<double, kPanels64, 24>(
+        return launch_typed<double, 24>(
             three_args<double>(p, draws_fp64(p, M, ws), static_cast<const double*>(p->tab[prec].glw), partials,
                                slice_len),
             n_slices, want_var, s);
-    return launch_typed<float, kPanels32, 12>(
+    return launch_typed<float, 12>(
         three_args<float>(p, draws_fp32(p, M, ws), static_cast<const float*>(p->tab[prec].glw), partials,
                           slice_len),
         n_slices, want_var, s);

@@ -79,7 +79,8 @@ def test_alpha3_draws():
             assert abs(f[i, j] - e) <= 4 * np.spacing(abs(e)) + 1e-17, (i, j, f[i, j], e)
 
 
-@pytest.mark.parametrize("spec,M", [(W.alpha3_design(7), 1000), (W.alpha3_design(5, r2=0.85, r3=0.3), 703)])
+@pytest.mark.parametrize("spec,M", [(W.alpha3_design(7), 1000), (W.alpha3_design(5, r2=0.85, r3=0.3), 703),
+                                    (W.alpha3_design(4, r2=0.9, r3=0.5, q_range=(0.001, 0.02)), 515)])
 def test_alpha3_grid_objective_matches_oracle(spec, M):
     G = O.grid_size(spec)
     say(f"alpha3 oracle m={spec['m']} M={M}")

@@ -92,6 +92,7 @@ def lib():
             "or_eval_points": (None, [pp, I64, P, U64, U64, P, P]),
             "or_eval_grid": (None, [pp, I64, P, U64, U64, P, P]),
             "or_smooth_direct": (None, [pp, P, P]), "or_smooth_separable": (None, [pp, P, P]),
+            "or_smooth_masked": (None, [pp, P, P]),
             "or_argmax": (I64, [I64, P]),
             "or_grad_points": (None, [pp, I64, P, U64, U64, P, P, P]),
             "or_exact_step": (D, [pp, P]), "or_exact_paper": (D, [pp, P]),
@@ -263,6 +264,14 @@ def smooth_separable(prob, f):
     f = np.ascontiguousarray(f, dtype=np.float64)
     out = np.zeros_like(f)
     lib().or_smooth_separable(ctypes.byref(s), _ptr(f), _ptr(out))
+    return out
+
+
+def smooth_masked(prob, f):
+    s = problem_struct(prob)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros_like(f)
+    lib().or_smooth_masked(ctypes.byref(s), _ptr(f), _ptr(out))
     return out
 
 

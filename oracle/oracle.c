@@ -696,6 +696,40 @@ void or_smooth_direct(const or_problem *p, const double *in, double *out)
     free(q);
 }
 
+/* The smoother over a grid whose surface is NaN at some designs (three
+ * nested populations: designs without a third level): the same kernel sum
+ * over the designs that have a value only; designs without one stay NaN.
+ * This is the surface fit of Sec. 2.3 taken over the evaluated points. */
+void or_smooth_masked(const or_problem *p, const double *in, double *out)
+{
+    int d = p->d;
+    int64_t G = or_grid_size(p);
+    double *q = (double *)malloc(sizeof(double) * (size_t)(G * d));
+    if (!q) return;
+    for (int64_t g = 0; g < G; ++g) or_grid_point(p, g, q + g * d, NULL);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t g = 0; g < G; ++g) {
+        if (isnan(in[g])) {
+            out[g] = NAN;
+            continue;
+        }
+        double num = 0.0, den = 0.0;
+        for (int64_t h = 0; h < G; ++h) {
+            if (isnan(in[h])) continue;
+            double e = 0.0;
+            for (int j = 0; j < d; ++j) {
+                double x = (q[g * d + j] - q[h * d + j]) / p->bandwidth[j];
+                e += -0.5 * x * x;
+            }
+            double w = exp(e);
+            num += w * in[h];
+            den += w;
+        }
+        out[g] = num / den;
+    }
+    free(q);
+}
+
 /* The same smoother through its factorisation: the row-normalised product
  * kernel is the product of row-normalised one-axis kernels, applied one axis
  * at a time. */

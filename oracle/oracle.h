@@ -123,6 +123,7 @@ void   or_eval_grid(const or_problem *p, int64_t n, const int64_t *g_list,
 /* ---- smoothing and argmax ---------------------------------------------- */
 void   or_smooth_direct(const or_problem *p, const double *in, double *out);
 void   or_smooth_separable(const or_problem *p, const double *in, double *out);
+void   or_smooth_masked(const or_problem *p, const double *in, double *out);
 int64_t or_argmax(int64_t n, const double *v);
 
 /* ---- gradient (forward mode, same draws) -------------------------------- */

@@ -680,3 +680,43 @@ def test_alpha3_draws_and_monte_carlo():
     for i in range(len(q)):
         ex = O.exact_paper(p, q[i])
         assert abs(m[i] - ex) < 4 * math.sqrt(v[i] / M), (q[i], m[i], ex)
+
+
+def _masked_surface(spec, seed):
+    G = O.grid_size(spec)
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(0.2, 0.9, G)
+    m = spec["m"]
+    idx = np.array([O.grid_point(spec, g)[1] for g in range(G)])
+    f[idx[:, 0] + idx[:, 1] >= m[0] + m[1] - 4] = np.nan   # a corner without values, as infeasible levels give
+    return f
+
+
+def test_masked_smoother_pins():
+    """NaN-masked smoothing over the designs that have a value (Sec. 2.3's fit
+    over the evaluated points): pinned to the separable smoother through the
+    ratio of smoothed values and smoothed indicator, to the identity as the
+    bandwidth vanishes, to constants, to the mean of the valid values as the
+    bandwidth grows, and to the unmasked smoother without NaN."""
+    spec = W.alpha3_design(7)
+    spec["bandwidth"] = [0.004, 0.006]
+    f = _masked_surface(spec, 3)
+    nan = np.isnan(f)
+    assert 0 < nan.sum() < f.size
+    out = O.smooth_masked(spec, f)
+    assert np.array_equal(np.isnan(out), nan)
+    f0, v = np.where(nan, 0.0, f), (~nan).astype(float)
+    ratio = O.smooth_separable(spec, f0) / O.smooth_separable(spec, v)
+    assert np.max(np.abs(out[~nan] - ratio[~nan])) < 1e-13
+    # constants on the valid designs stay constant
+    c = np.where(nan, np.nan, 0.37)
+    assert np.max(np.abs(O.smooth_masked(spec, c)[~nan] - 0.37)) < 1e-15
+    # vanishing bandwidth: the identity
+    tiny = dict(spec, bandwidth=[1e-6, 1e-6])
+    assert np.max(np.abs(O.smooth_masked(tiny, f)[~nan] - f[~nan])) < 1e-15
+    # huge bandwidth: the mean over the valid designs
+    wide = dict(spec, bandwidth=[1e5, 1e5])
+    assert np.max(np.abs(O.smooth_masked(wide, f)[~nan] - np.mean(f[~nan]))) < 1e-12
+    # without NaN it is the plain smoother
+    g = np.where(nan, 0.5, f)
+    assert np.max(np.abs(O.smooth_masked(spec, g) - O.smooth_direct(spec, g))) < 1e-15

@@ -193,13 +193,16 @@ bmd_status bmd_eval_grid(bmd_problem *p, uint64_t n_draws, int32_t prec,
  * separably along each axis (the stand-in for the paper's thin-plate spline,
  * Sec. 2.3).  d_in and d_out are FP64 arrays of length G and must not alias.
  * prec: FP64 uses FP64 matrix cores; FP32_COMP uses FP32 matrix cores with
- * FP32 accumulation. */
+ * FP32 accumulation.  BMD_DESIGN_ALPHA3 grids sum over the designs whose value
+ * is not NaN only (the designs without a third level), which stay NaN; other
+ * problems propagate NaN like any value. */
 bmd_status bmd_smooth(bmd_problem *p, const double *d_in, double *d_out, int32_t prec,
                       void *stream);
 
 /* Maximiser of a surface (the best grid point, Sec. 2.3): index g* of the
  * largest value, ties to the lowest index, NaN never wins.  Writes *h_index,
- * *h_value and, if h_cell is not NULL, the d grid indices of g*.
+ * *h_value and, if h_cell is not NULL, the d grid indices of g*; a surface
+ * with no value above -DBL_MAX other than NaN gives index 0 and value NaN.
  * Synchronises `stream` (returns the result on the host). */
 bmd_status bmd_argmax(bmd_problem *p, const double *d_surface, int64_t *h_index,
                       double *h_value, int32_t *h_cell, void *stream);

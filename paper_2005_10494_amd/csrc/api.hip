@@ -12,6 +12,13 @@
 
 #include "bmd_internal.hpp"
 
+namespace bmd {
+// Smoothing over the designs whose value is not NaN (kernels_post.hip); NaN
+// designs stay NaN; ws holds 4 G doubles.
+hipError_t launch_smooth_masked(const bmd_problem* p, int prec, const double* in, double* out, double* ws,
+                                hipStream_t s);
+}  // namespace bmd
+
 using namespace bmd;
 
 namespace {
@@ -595,11 +602,16 @@ bmd_status bmd_smooth(bmd_problem* p, const double* d_in, double* d_out, int32_t
     if (!d_in || !d_out) return fail(BMD_EINVAL, "NULL surface pointer");
     if (d_in == d_out) return fail(BMD_EINVAL, "d_in and d_out must not alias");
     DeviceGuard guard(p->device);
-    bmd_status st = ensure(&p->d_ws2, &p->ws2_cap, sizeof(double) * static_cast<size_t>(p->P.G));
+    // designs without a third level are NaN: smooth over the others
+    const bool masked = p->P.design_space == BMD_DESIGN_ALPHA3;
+    bmd_status st = ensure(&p->d_ws2, &p->ws2_cap, sizeof(double) * static_cast<size_t>(p->P.G) * (masked ? 4 : 1));
     if (st != BMD_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     mark(p, 6, s);
-    HIP_TRY(launch_smooth(p, prec, d_in, d_out, static_cast<double*>(p->d_ws2), s), "smooth kernel");
+    if (masked)
+        HIP_TRY(launch_smooth_masked(p, prec, d_in, d_out, static_cast<double*>(p->d_ws2), s), "smooth kernel");
+    else
+        HIP_TRY(launch_smooth(p, prec, d_in, d_out, static_cast<double*>(p->d_ws2), s), "smooth kernel");
     mark(p, 7, s);
     return BMD_OK;
 }

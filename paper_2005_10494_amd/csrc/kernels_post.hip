@@ -111,7 +111,47 @@ __global__ void k_argmax_final(int n_part, double* __restrict__ pv, int64_t* __r
     if (threadIdx.x == 0) { pv[0] = v; pi[0] = i; }
 }
 
+// Surfaces where some designs have no value (NaN): the smoother over the
+// designs that have one is the ratio of the smoothed zero-filled surface and
+// the smoothed indicator of those designs (the row normalisation cancels).
+__global__ void k_mask_split(int64_t G, const double* __restrict__ in, double* __restrict__ f0,
+                             double* __restrict__ v) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    const double x = in[g];
+    const bool ok = !(x != x);
+    f0[g] = ok ? x : 0.0;
+    v[g] = ok ? 1.0 : 0.0;
+}
+
+// Designs without a value stay NaN; every other one has a positive indicator
+// sum (its own weight).
+__global__ void k_mask_ratio(int64_t G, const double* __restrict__ in, const double* __restrict__ den,
+                             double* __restrict__ out) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    const double x = in[g];
+    out[g] = x != x ? x : out[g] / den[g];
+}
+
 }  // namespace
+
+hipError_t launch_smooth_masked(const bmd_problem* p, int prec, const double* in, double* out, double* ws,
+                                hipStream_t s) {
+    const int64_t G = p->P.G;
+    double* tmp = ws;
+    double* f0 = ws + G;
+    double* v = ws + 2 * G;
+    double* den = ws + 3 * G;
+    const dim3 grid(static_cast<unsigned>((G + 255) / 256));
+    hipLaunchKernelGGL(k_mask_split, grid, dim3(256), 0, s, G, in, f0, v);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_smooth(p, prec, f0, out, tmp, s);
+    if (e == hipSuccess) e = launch_smooth(p, prec, v, den, tmp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mask_ratio, grid, dim3(256), 0, s, G, in, den, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_smooth(const bmd_problem* p, int prec, const double* in, double* out, double* tmp,
                          hipStream_t s) {

@@ -111,10 +111,12 @@ __device__ __forceinline__ T tvn(T h1, T h2, T h3, const TvnConst<T, NMAX>& c, c
 }
 
 // Levels alpha_1 (axis 0) and alpha_2 (axis 1) of design g; the third critical
-// value solves 1 - Phi_3(z1, z2, z3) = alpha0 by bisection between the third
-// test alone at level alpha0 (FWER >= alpha0) and the union bound with the
-// level a12 = 1 - Phi_2(z1, z2; sqrt r2) the first two spend (FWER <= alpha0).
-// NaN when a12 >= alpha0.
+// value solves F(z3) = 1 - Phi_3(z1, z2, z3) - alpha0 = 0 (F falls in z3)
+// inside the bracket from the third test alone at level alpha0 (F >= 0) to the
+// union bound with the level a12 = 1 - Phi_2(z1, z2; sqrt r2) the first two
+// spend (F <= 0), by the Illinois variant of false position (a retained end
+// has its F halved, so both ends move); a step that leaves the bracket
+// bisects instead.  NaN when a12 >= alpha0.
 __global__ __launch_bounds__(64) void k_three_precompute(DevProblem P, const double* __restrict__ gl,
                                                          double* __restrict__ r_out, double* __restrict__ z1_out,
                                                          double* __restrict__ z2_out, double* __restrict__ z3_out) {
@@ -134,15 +136,34 @@ __global__ __launch_bounds__(64) void k_three_precompute(DevProblem P, const dou
     const double a12 = 1.0 - bvn_cdf<n>(z1, z2, b12, w, n);
     double z3 = NAN;
     if (a12 < P.alpha0) {
+        const int ni = bvn_nodes_fp64(partial_corr(P.r_lo, P.r_hi));
         TvnConst<double, n> c;
-        c.init(P.r_lo, P.r_hi, n, max(kPanelsSetup, tvn_panels<double>(P.r_lo)), gl);
+        c.init(P.r_lo, P.r_hi, ni, max(kPanelsSetup, tvn_panels<double>(P.r_lo)), gl);
+        const double* wi = gl + gl_offset(ni) + ni;
+        auto F = [&](double z) { return (1.0 - tvn(z1, z2, z, c, wi)) - P.alpha0; };
         double lo = -norm_quantile(P.alpha0), hi = -norm_quantile(P.alpha0 - a12);
-        for (int it = 0; it < 200; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if (!(mid > lo && mid < hi)) break;
-            if (1.0 - tvn(z1, z2, mid, c, w) > P.alpha0) lo = mid; else hi = mid;
+        double Flo = F(lo), Fhi = F(hi);
+        z3 = Flo <= 0.0 ? lo : Fhi >= 0.0 ? hi : 0.5 * (lo + hi);
+        int kept = 0;   // +1: lo kept by the last step, -1: hi kept
+        for (int it = 0; it < 100 && Flo > 0.0 && Fhi < 0.0; ++it) {
+            double x = (lo * Fhi - hi * Flo) / (Fhi - Flo);
+            if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
+            const double Fx = F(x);
+            z3 = x;
+            if (Fx == 0.0 || hi - lo <= 1e-14 * fabs(x)) break;
+            if (Fx > 0.0) {
+                lo = x;
+                Flo = Fx;
+                if (kept == -1) Fhi *= 0.5;
+                kept = -1;
+            } else {
+                hi = x;
+                Fhi = Fx;
+                if (kept == 1) Flo *= 0.5;
+                kept = 1;
+            }
+            if (fabs(Fx) <= 4e-16) break;   // the rounding level of 1 - Phi_3
         }
-        z3 = 0.5 * (lo + hi);
     }
     z3_out[g] = z3;
 }

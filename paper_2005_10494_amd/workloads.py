@@ -109,6 +109,21 @@ def alpha3_grid() -> dict:
     return alpha3_design(97, n_draws=100_000)
 
 
+def noisy_surface(m, seed: int = 0, nan_corner: int = 0) -> np.ndarray:
+    """A seeded stand-in for an estimated grid surface (row-major over the
+    axes m, axis 0 slowest): a smooth bump plus N(0, 0.02^2) noise.  With
+    ``nan_corner`` = c > 0 the designs whose axis indices sum to at least
+    sum(m) - c are NaN, as designs without a valid level split are."""
+    m = [int(x) for x in m]
+    rng = np.random.default_rng(seed)
+    idx = np.stack(np.meshgrid(*[np.arange(k) for k in m], indexing="ij"), -1).reshape(-1, len(m))
+    x = idx / np.maximum(np.asarray(m) - 1, 1)
+    f = 0.3 + 0.4 * np.exp(-np.sum((x - 0.6) ** 2, axis=1) / 0.1) + 0.02 * rng.standard_normal(len(x))
+    if nan_corner > 0:
+        f[idx.sum(axis=1) >= sum(m) - nan_corner] = np.nan
+    return f
+
+
 def design_points(n: int, d: int, seed: int = 1, lo: float = 0.1, hi: float = 0.9) -> np.ndarray:
     """Continuous design points, iid U(lo, hi)^d (cutoff quantiles)."""
     rng = np.random.default_rng(seed)

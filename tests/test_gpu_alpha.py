@@ -70,17 +70,18 @@ def test_alpha_grid_objective_matches_oracle(M):
 
 def test_alpha_smoothing_and_argmax_match_oracle():
     spec = W.alpha_design(23, m_r=17)
+    raw_h = W.noisy_surface(spec["m"], seed=5)
     with bmd.Problem(spec) as p:
-        raw = p.eval_grid(3000, "fp64")
+        raw = torch.tensor(raw_h, dtype=torch.float64, device="cuda")
         s64 = p.smooth(raw, "fp64")
         i64, v64, cell = p.argmax(s64)
-        raw_h, s64_h = raw.cpu().numpy(), s64.cpu().numpy()
+        s64_h = s64.cpu().numpy()
     ref = O.smooth_separable(spec, raw_h)
     assert np.max(np.abs(s64_h - ref)) <= 1e-13
     assert np.max(np.abs(O.smooth_direct(spec, raw_h) - ref)) < 1e-13
     io = O.argmax(ref)
     assert i64 == io and v64 == pytest.approx(ref[io], abs=1e-13)
-    _, idx = O.grid_point(spec, i64)
+    _, idx = O.grid_point(spec, io)
     assert tuple(idx) == cell
 
 

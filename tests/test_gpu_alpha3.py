@@ -114,10 +114,47 @@ def test_alpha3_converges_to_closed_form():
     z = (mean[ok] - exact[ok]) / np.sqrt(var[ok] / M)
     assert np.max(np.abs(z)) < 5.0, z
     i_ex = int(np.nanargmax(exact))
-    _, a = O.grid_point(spec, i_gpu)
     _, b = O.grid_point(spec, i_ex)
-    assert max(abs(int(x) - int(y)) for x, y in zip(a, b)) <= 1
+    assert max(abs(int(x) - int(y)) for x, y in zip(cell, b)) <= 1
     assert v_gpu == mean[i_gpu]
+
+
+@pytest.mark.parametrize("m,corner", [(9, 5), (23, 12)])
+def test_alpha3_masked_smoothing_and_argmax_match_oracle(m, corner):
+    """Designs without a third level are NaN: the smoother sums over the others
+    and keeps them NaN (FP64 1e-13, FP32 2e-6 of the surface's scale); the
+    argmax skips them."""
+    spec = W.alpha3_design(m)
+    raw_h = W.noisy_surface(spec["m"], seed=m, nan_corner=corner)
+    nan = np.isnan(raw_h)
+    assert 0 < nan.sum() < raw_h.size
+    with bmd.Problem(spec) as p:
+        raw = torch.tensor(raw_h, dtype=torch.float64, device="cuda")
+        s64, s32 = p.smooth(raw, "fp64"), p.smooth(raw, "fp32")
+        i64, v64, cell = p.argmax(s64)
+        s64_h, s32_h = s64.cpu().numpy(), s32.cpu().numpy()
+    ref = O.smooth_masked(spec, raw_h)
+    for got in (s64_h, s32_h):
+        assert np.array_equal(np.isnan(got), nan)
+    assert np.max(np.abs(s64_h[~nan] - ref[~nan])) <= 1e-13
+    assert np.max(np.abs(s32_h[~nan] - ref[~nan])) <= 2e-6 * np.max(np.abs(ref[~nan]))
+    io = int(np.nanargmax(ref))
+    assert i64 == io and v64 == pytest.approx(ref[io], abs=1e-13)
+    _, idx = O.grid_point(spec, io)
+    assert tuple(idx) == cell
+
+
+def test_alpha3_grid_without_any_third_level():
+    """Levels that always spend alpha0 in the first two tests: every design is
+    NaN on both sides, smoothing keeps them NaN and the argmax reports NaN."""
+    spec = W.alpha3_design(4, q_range=(0.02, 0.024))
+    assert all(math.isnan(O.make_design(spec, O.grid_point(spec, g)[0])["z3"]) for g in range(16))
+    with bmd.Problem(spec) as p:
+        mean = p.eval_grid(300, "fp32")
+        s = p.smooth(mean, "fp32")
+        i, v, cell = p.argmax(s)
+        assert torch.isnan(mean).all().item() and torch.isnan(s).all().item()
+    assert i == 0 and math.isnan(v) and tuple(cell) == (0, 0)
 
 
 def test_alpha3_not_batched():

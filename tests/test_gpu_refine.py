@@ -60,7 +60,7 @@ def test_refine_improves_the_grid_argmax():
     with bmd.Problem(spec) as p:
         surf = p.eval_grid(M, "fp64")
         g, v, cell = p.argmax(surf)
-        q0, _ = O.grid_point(spec, g)
+        q0 = p.designs(g, 1).cpu().numpy()[0, :2]
         q, fq, it = p.refine_design(q0, M, "fp64", max_iter=30)
         ob, _, _ = p.grad_design(torch.tensor(q0[None, :]), M, "fp64")
         torch.cuda.synchronize()

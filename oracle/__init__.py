@@ -10,6 +10,7 @@ this module converts them to the oracle's own C struct.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -374,6 +375,57 @@ def refine_design(prob, q0, M, max_iter=50, tol=1e-6):
 
 
 # ---- optimal level split per design ----------------------------------------------
+
+def optimize_levels(prob, g_list, M, a_lo, a_hi, n_iter):
+    """Sec. 2.4's optimal power at each design found by search: for n = 2 nested
+    tests, golden-section search of the first level alpha_1 over [a_lo, a_hi]
+    per design, the second level on the design's FWER boundary, on the Formula 5
+    estimate with draws 0..M-1 (the same draws for every level, so each design's
+    estimate is one deterministic function of alpha_1).  The two interior points
+    split the bracket by the golden ratio; the side whose point is lower is
+    dropped (ties keep the left part), and one new point is evaluated per step.
+    Returns the largest estimate seen per design and its level (the first one
+    seen on ties)."""
+    gr = (math.sqrt(5.0) - 1.0) / 2.0
+    g_list = np.asarray(g_list, dtype=np.int64)
+    n = len(g_list)
+
+    def f(levels):
+        out = np.empty(n)
+        for i in range(n):
+            pk = dict(prob, alpha_rule="split", alpha_fixed=(float(levels[i]), 0.0))
+            out[i] = eval_grid(pk, g_list[i:i + 1], M)[0][0]
+        return out
+
+    a, b = np.full(n, float(a_lo)), np.full(n, float(a_hi))
+    x1, x2 = b - gr * (b - a), a + gr * (b - a)
+    f1 = f(x1)
+    f2 = f(x2)
+    best, best_x = f1.copy(), x1.copy()
+    up = f2 > best
+    best[up], best_x[up] = f2[up], x2[up]
+    for _ in range(int(n_iter)):
+        left = f1 >= f2
+        probe = np.empty(n)
+        for i in range(n):
+            if left[i]:   # the maximum lies in [a, x2]
+                b[i], x2[i], f2[i] = x2[i], x1[i], f1[i]
+                x1[i] = b[i] - gr * (b[i] - a[i])
+                probe[i] = x1[i]
+            else:         # in [x1, b]
+                a[i], x1[i], f1[i] = x1[i], x2[i], f2[i]
+                x2[i] = a[i] + gr * (b[i] - a[i])
+                probe[i] = x2[i]
+        fp = f(probe)
+        for i in range(n):
+            if left[i]:
+                f1[i] = fp[i]
+            else:
+                f2[i] = fp[i]
+            if fp[i] > best[i]:
+                best[i], best_x[i] = fp[i], probe[i]
+    return best, best_x
+
 
 def eval_grid_levels(prob, g_list, M, alphas):
     """Sec. 2.4's optimal power at each design for n = 2 nested tests, over a list

@@ -606,6 +606,33 @@ def test_level_surface_matches_closed_form_under_point_mass_prior():
     assert 0 < k[0] < len(alphas) - 1
 
 
+def test_level_search_reaches_scipy_optimum_under_point_mass_prior():
+    """Per-design search of the level split (Sec. 2.4's optimal power at each
+    design) under the point-mass prior of the level-surface pin: the searched
+    level and power agree with scipy's bounded maximiser of the closed form, and
+    the searched power is at least the best of a fine level grid."""
+    from scipy.optimize import minimize_scalar
+    p = W.base_problem(1, [3], 0.0, 0.05, q_lo=0.5, q_hi=0.7, sd_b0=0.0, sd_b1=0.0, tau_lo=0.3, tau_hi=0.3)
+    r, I = 0.4, 100.0
+    mu1 = math.sqrt(I) * 0.5 * 0.7
+    mu2 = math.sqrt(r * I) * 0.5 * 0.4 / r
+
+    def power(a1):
+        z1 = -ndtri(a1)
+        return 1.0 - _bvn_owen(z1 - mu1, _z2_scipy(z1, r) - mu2, math.sqrt(r))
+
+    res = minimize_scalar(lambda x: -power(x), bounds=(0.001, 0.024), method="bounded", options={"xatol": 1e-10})
+    best, x = O.optimize_levels(p, np.array([1]), 2, 0.001, 0.024, 30)
+    assert abs(x[0] - res.x) < 2e-6, (x[0], res.x)
+    assert abs(best[0] + res.fun) < 1e-11
+    grid_best, _ = O.eval_grid_levels(p, np.array([1]), 2, np.linspace(0.001, 0.024, 47))
+    assert best[0] >= grid_best[0] - 1e-15
+    # a boundary optimum: with the search range cut below the interior optimum
+    # the search ends at the range's upper end
+    b2, x2 = O.optimize_levels(p, np.array([1]), 2, 0.001, 0.5 * res.x, 30)
+    assert abs(x2[0] - 0.5 * res.x) < 1e-6 and abs(b2[0] - power(x2[0])) < 1e-12
+
+
 # ---------------------------------------------------------------- three nested populations
 
 def _tvn_scipy(h, r12, r13, r23):

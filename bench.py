@@ -208,8 +208,8 @@ def main():
                          "kernel that scales the HBM byte counters of a profiler run")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is "
-              f"described in DESIGN.md and not launched.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding the designs or the "
+              f"draws over several GPUs is not implemented here.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -449,6 +449,21 @@ def bench_levels(args):
             res[prec] = (float(np.mean(ts)), best, k)
         eq = p.eval_grid(M, "fp32")
         torch.cuda.synchronize()
+        # per-design golden-section search of the first level over the same range
+        n_iter = 10
+        srch = {}
+        for prec in ("fp32", "fp64"):
+            ts = []
+            for it in range(args.warmup + args.steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sb, sa = p.optimize_levels(M, float(alphas[0]), float(alphas[-1]), n_iter, prec)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                if it >= args.warmup:
+                    ts.append(dt)
+                log(f"  level search {prec} step {it}: {1e3 * dt:.1f} ms")
+            srch[prec] = (float(np.mean(ts)), sb, sa)
     t32, b32, k32 = res["fp32"]
     t64, b64, k64 = res["fp64"]
     evals = G * M * len(alphas)
@@ -465,7 +480,15 @@ def bench_levels(args):
                       "mean_gain_over_equal_split": float((b32 - eq).mean())},
            "fp64": {"ms_per_step": 1e3 * t64},
            "fp32_vs_fp64": {"speedup": t64 / t32, "max_abs_diff_best": float((b32 - b64).abs().max()),
-                            "level_index_agreement": float((k32 == k64).double().mean())}}
+                            "level_index_agreement": float((k32 == k64).double().mean())},
+           "level_search": {"method": f"golden section per design over [{alphas[0]:.4g}, {alphas[-1]:.4g}], "
+                                      f"{n_iter} steps ({n_iter + 2} sweeps on shared draws)",
+                            "ms_fp32": 1e3 * srch["fp32"][0], "ms_fp64": 1e3 * srch["fp64"][0],
+                            "evals_per_s_fp32": G * M * (n_iter + 2) / srch["fp32"][0],
+                            "max_best": float(srch["fp32"][1].max()),
+                            "mean_gain_over_level_grid": float((srch["fp32"][1] - b32).mean()),
+                            "share_above_level_grid": float((srch["fp32"][1] >= b32 - 1e-12).double().mean()),
+                            "max_abs_diff_best_fp32_fp64": float((srch["fp32"][1] - srch["fp64"][1]).abs().max())}}
     print(json.dumps(out), flush=True)
 
 

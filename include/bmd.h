@@ -234,6 +234,24 @@ bmd_status bmd_grad_design(bmd_problem *p, const double *d_q, int64_t B, uint64_
  * the call returns (a design precompute is re-launched on `stream`).  ESTATE
  * for a continuous problem or the alpha design space; ERANGE for n_alpha
  * outside [1, 4096] or a level outside (0, alpha0). */
+/* Optimal level split per design found by search (Sec. 2.4's "optimal power"
+ * at each design, n = 2 nested tests): for every design, golden-section search
+ * of the first level alpha_1 over [a_lo, a_hi] (0 < a_lo < a_hi < alpha0),
+ * the second level on the design's FWER boundary, on the estimate of Formula 5
+ * with draws 0..n_draws-1 (generated once, shared by every level).  The two
+ * interior points split the bracket by the golden ratio; each of the n_iter
+ * steps drops the part beyond the lower one (ties keep the left part) and
+ * evaluates one new level, so the call runs 2 + n_iter sweeps and ends with a
+ * bracket (a_hi - a_lo) 0.618^(n_iter + 1) wide.
+ *   d_best   [G] FP64 the largest estimate seen for each design
+ *   d_alpha1 [G] FP64 the level that gave it (the first one seen on ties)
+ * A local search: a design whose power has several maxima over the range may
+ * end at a local one.  The problem's own critical values are restored before
+ * the call returns.  ESTATE for a continuous problem or an alpha design space;
+ * ERANGE for the range or n_iter outside [0, 200]. */
+bmd_status bmd_optimize_levels(bmd_problem *p, uint64_t n_draws, int32_t prec, double a_lo, double a_hi,
+                               int32_t n_iter, double *d_best, double *d_alpha1, void *stream);
+
 bmd_status bmd_eval_grid_levels(bmd_problem *p, uint64_t n_draws, int32_t prec, const double *h_alpha1,
                                 int32_t n_alpha, double *d_best, int32_t *d_best_k, void *stream);
 

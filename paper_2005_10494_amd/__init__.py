@@ -75,6 +75,9 @@ SIGNATURES = {
                                        ctypes.c_void_p]),
     "bmd_eval_grid_levels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p,
                                             ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "bmd_optimize_levels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
     "bmd_refine_design": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32,
                                          ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p]),
@@ -246,6 +249,19 @@ class Problem:
                                               ctypes.c_void_p(best.data_ptr()), ctypes.c_void_p(k.data_ptr()),
                                               _stream(stream)))
         return best, k
+
+    def optimize_levels(self, n_draws: int, a_lo: float, a_hi: float, n_iter: int = 20, precision="fp64",
+                        stream=None):
+        """Per-design golden-section search of the first-test level over
+        [a_lo, a_hi] (second level on each design's FWER boundary); returns
+        (best power, its first level) per design."""
+        import torch
+        best = torch.empty(self.G, dtype=torch.float64, device=self.device)
+        a1 = torch.empty(self.G, dtype=torch.float64, device=self.device)
+        _check(library().bmd_optimize_levels(self._h, int(n_draws), _prec(precision), float(a_lo), float(a_hi),
+                                             int(n_iter), ctypes.c_void_p(best.data_ptr()),
+                                             ctypes.c_void_p(a1.data_ptr()), _stream(stream)))
+        return best, a1
 
     def refine_design(self, q0, n_draws: int, precision="fp64", max_iter=50, tol=1e-6, stream=None):
         """Local maximiser of the Monte Carlo objective from q0 (projected

@@ -17,6 +17,10 @@ namespace bmd {
 // designs stay NaN; ws holds 4 G doubles.
 hipError_t launch_smooth_masked(const bmd_problem* p, int prec, const double* in, double* out, double* ws,
                                 hipStream_t s);
+// One step of the per-design golden-section level search (kernels_setup.hip):
+// st [8][G] search state, side [G]; writes the problem's z1, z2 when probing.
+hipError_t launch_levels_golden(const bmd_problem* p, int phase, bool probe, double a_lo, double a_hi,
+                                const double* mean, double* st, int32_t* side, hipStream_t s);
 }  // namespace bmd
 
 using namespace bmd;
@@ -550,6 +554,56 @@ bmd_status bmd_eval_grid(bmd_problem* p, uint64_t n_draws, int32_t prec, double*
     mark(p, 4, s);
     HIP_TRY(launch_finalize(p, M, partials, static_cast<int>(n_slices), d_mean, d_var, s), "finalize kernel");
     mark(p, 5, s);
+    return BMD_OK;
+}
+
+bmd_status bmd_optimize_levels(bmd_problem* p, uint64_t n_draws, int32_t prec, double a_lo, double a_hi,
+                               int32_t n_iter, double* d_best, double* d_alpha1, void* stream) {
+    g_err.clear();
+    if (!p) return fail(BMD_EINVAL, "problem is NULL");
+    if (!p->grid || p->P.design_space != BMD_DESIGN_CUTOFFS)
+        return fail(BMD_ESTATE, "level search needs a grid of cutoff designs");
+    if (!valid_prec(prec)) return fail(BMD_EINVAL, "unknown precision %d", prec);
+    if (!d_best || !d_alpha1) return fail(BMD_EINVAL, "NULL d_best or d_alpha1");
+    if (!std::isfinite(a_lo) || !std::isfinite(a_hi) || !(0.0 < a_lo && a_lo < a_hi && a_hi < p->P.alpha0))
+        return fail(BMD_ERANGE, "need 0 < a_lo < a_hi < alpha0");
+    if (n_iter < 0 || n_iter > 200) return fail(BMD_ERANGE, "n_iter must be in [0, 200]");
+    if (n_draws == 0 || n_draws > (1ull << 40)) return fail(BMD_ERANGE, "n_draws must be in [1, 2^40]");
+    DeviceGuard guard(p->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t M = static_cast<int64_t>(n_draws);
+    const int64_t G = p->P.G;
+    int64_t n_slices = 0, slice_len = 0;
+    sweep_slices(p, prec, M, &n_slices, &slice_len);
+    const size_t al = 256;
+    const size_t draw_bytes = (draw_workspace_bytes(p, prec, M) + al - 1) / al * al;
+    const size_t part_bytes = (sizeof(double) * 2 * static_cast<size_t>(G) * n_slices + al - 1) / al * al;
+    const size_t mean_bytes = (sizeof(double) * static_cast<size_t>(G) + al - 1) / al * al;
+    const size_t state_bytes = sizeof(double) * 8 * static_cast<size_t>(G);
+    bmd_status st = ensure(&p->d_ws, &p->ws_cap,
+                           draw_bytes + part_bytes + mean_bytes + state_bytes + sizeof(int32_t) * G);
+    if (st != BMD_OK) return st;
+    char* base = static_cast<char*>(p->d_ws);
+    double* partials = reinterpret_cast<double*>(base + draw_bytes);
+    double* mean = reinterpret_cast<double*>(base + draw_bytes + part_bytes);
+    double* state = reinterpret_cast<double*>(base + draw_bytes + part_bytes + mean_bytes);
+    int32_t* side = reinterpret_cast<int32_t*>(base + draw_bytes + part_bytes + mean_bytes + state_bytes);
+    HIP_TRY(launch_draws(p, prec, 0, M, p->d_ws, s), "draw kernel");
+    hipError_t e = hipSuccess;
+    const int n_sweeps = 2 + n_iter;
+    for (int ph = 0; ph <= n_sweeps && e == hipSuccess; ++ph) {
+        e = launch_levels_golden(p, ph, ph < n_sweeps, a_lo, a_hi, mean, state, side, s);
+        if (e == hipSuccess && ph < n_sweeps)
+            e = launch_eval_grid(p, prec, M, p->d_ws, partials, static_cast<int>(n_slices), slice_len, false, s);
+        if (e == hipSuccess && ph < n_sweeps)
+            e = launch_finalize(p, M, partials, static_cast<int>(n_slices), mean, nullptr, s);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(d_best, state + 6 * G, sizeof(double) * G, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_alpha1, state + 7 * G, sizeof(double) * G, hipMemcpyDeviceToDevice, s);
+    // the problem's own critical values, whatever happened above
+    const hipError_t er = launch_design_precompute(p, s);
+    HIP_TRY(e, "level search");
+    HIP_TRY(er, "design precompute");
     return BMD_OK;
 }
 

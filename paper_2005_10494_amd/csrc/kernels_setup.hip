@@ -153,6 +153,80 @@ __global__ __launch_bounds__(128) void k_levels_z(int64_t G, double z1, double a
     z2_out[g] = z2_on_fwer(z1, sqrt(r[g]), alpha0, gl);
 }
 
+// Golden-section search of the first level per design (the level split of
+// Sec. 2.4 searched, second level on the design's FWER boundary), one call
+// between consecutive sweeps.  st holds [8][G]: bracket ends a, b, interior
+// points x1 < x2, their estimates f1, f2, the best estimate seen and its
+// level; side[g] names the point the last sweep evaluated (1: x1, 2: x2).
+// Phase 0 sets the bracket and probes x1; phase 1 records f(x1) and probes
+// x2; every later phase records the probe, keeps the best, and (when `probe`)
+// drops the part beyond the lower interior point (ties keep the left part)
+// and probes the new point.  A probe writes the design's z1 and z2.
+__global__ __launch_bounds__(128) void k_levels_golden(int64_t G, int phase, bool probe, double a_lo, double a_hi,
+                                                       double alpha0, const double* __restrict__ r,
+                                                       const double* __restrict__ mean, const double* __restrict__ gl,
+                                                       double* __restrict__ st, int32_t* __restrict__ side,
+                                                       double* __restrict__ z1_out, double* __restrict__ z2_out) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    constexpr double gr = 0.61803398874989484820;   // (sqrt 5 - 1) / 2
+    double* A = st;
+    double* B = st + G;
+    double* X1 = st + 2 * G;
+    double* X2 = st + 3 * G;
+    double* F1 = st + 4 * G;
+    double* F2 = st + 5 * G;
+    double* best = st + 6 * G;
+    double* best_x = st + 7 * G;
+    double next = 0.0;
+    if (phase == 0) {
+        A[g] = a_lo;
+        B[g] = a_hi;
+        X1[g] = a_hi - gr * (a_hi - a_lo);
+        X2[g] = a_lo + gr * (a_hi - a_lo);
+        side[g] = 1;
+        next = X1[g];
+    } else {
+        const double f = mean[g];
+        const int sd = side[g];
+        const double x = sd == 1 ? X1[g] : X2[g];
+        if (sd == 1) F1[g] = f; else F2[g] = f;
+        if (phase == 1) {
+            best[g] = f;
+            best_x[g] = x;
+            side[g] = 2;
+            next = X2[g];
+        } else {
+            if (f > best[g]) {
+                best[g] = f;
+                best_x[g] = x;
+            }
+            if (probe) {
+                if (F1[g] >= F2[g]) {   // the maximum lies in [a, x2]
+                    B[g] = X2[g];
+                    X2[g] = X1[g];
+                    F2[g] = F1[g];
+                    X1[g] = B[g] - gr * (B[g] - A[g]);
+                    side[g] = 1;
+                    next = X1[g];
+                } else {                // in [x1, b]
+                    A[g] = X1[g];
+                    X1[g] = X2[g];
+                    F1[g] = F2[g];
+                    X2[g] = A[g] + gr * (B[g] - A[g]);
+                    side[g] = 2;
+                    next = X2[g];
+                }
+            }
+        }
+    }
+    if (probe) {
+        const double z1 = -norm_quantile(next);
+        z1_out[g] = z1;
+        z2_out[g] = z2_on_fwer(z1, sqrt(r[g]), alpha0, gl);
+    }
+}
+
 // Running maximum over levels: level k's means against the best so far
 // (k = 0 initialises); strict improvement only, so ties keep the lower k.
 __global__ void k_levels_best(int64_t G, int k, const double* __restrict__ mean, double* __restrict__ best,
@@ -330,6 +404,13 @@ inline unsigned blocks_for(int64_t n, int b) { return static_cast<unsigned>((n +
 hipError_t launch_levels_z(const bmd_problem* p, double z1, hipStream_t s) {
     hipLaunchKernelGGL(k_levels_z, dim3(blocks_for(p->P.G, 128)), dim3(128), 0, s, p->P.G, z1, p->P.alpha0, p->d_r,
                        p->d_gl, p->d_z1, p->d_z2);
+    return hipGetLastError();
+}
+
+hipError_t launch_levels_golden(const bmd_problem* p, int phase, bool probe, double a_lo, double a_hi,
+                                const double* mean, double* st, int32_t* side, hipStream_t s) {
+    hipLaunchKernelGGL(k_levels_golden, dim3(blocks_for(p->P.G, 128)), dim3(128), 0, s, p->P.G, phase, probe, a_lo,
+                       a_hi, p->P.alpha0, p->d_r, mean, p->d_gl, st, side, p->d_z1, p->d_z2);
     return hipGetLastError();
 }
 

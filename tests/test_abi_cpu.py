@@ -110,6 +110,7 @@ def test_null_arguments():
     assert lib.bmd_gh_nodes(None, 0) == -1
     assert lib.bmd_refine_design(None, None, 10, 0, 5, 1e-6, None, None, None, None) == -1
     assert lib.bmd_eval_grid_levels(None, 10, 0, None, 1, None, None, None) == -1
+    assert lib.bmd_optimize_levels(None, 10, 0, 0.001, 0.02, 5, None, None, None) == -1
     lib.bmd_destroy_problem(None)  # NULL-safe
 
 

@@ -81,3 +81,60 @@ def test_level_surface_matches_oracle():
             assert np.all(np.abs(best - ref) <= TOL[prec] * np.maximum(np.abs(ref), 1e-3)), prec
             if prec == "fp64":
                 assert np.array_equal(k, ref_k)
+
+
+@pytest.mark.parametrize("spec,M", [(W.base_problem(2, [4, 3], 0.3, 0.05), 700),
+                                    (W.base_problem(1, [9], 0.0, 0.05), 513)])
+def test_level_search_matches_oracle(spec, M):
+    """Per-design golden-section search of the first level (12 steps over
+    [0.001, 0.024]): FP64 best power and level against the oracle's search on
+    the same draws; FP32 power within its bar and its level within 1e-3 (FP32
+    comparisons of near-equal interior values may take the other side); the
+    problem's critical values are restored afterwards."""
+    G = O.grid_size(spec)
+    n_iter = 12
+    say(f"level search d={spec['d']} G={G} M={M}")
+    ref_best, ref_x = O.optimize_levels(spec, np.arange(G), M, 0.001, 0.024, n_iter)
+    with bmd.Problem(spec) as p:
+        before = p.designs(0, G).cpu().numpy()
+        for prec in ("fp64", "fp32"):
+            best, a1 = p.optimize_levels(M, 0.001, 0.024, n_iter, prec)
+            torch.cuda.synchronize()
+            best, a1 = best.cpu().numpy(), a1.cpu().numpy()
+            bound = TOL[prec] * np.maximum(np.abs(ref_best), 1e-3)
+            assert np.all(np.abs(best - ref_best) <= bound), (prec, best, ref_best)
+            assert np.max(np.abs(a1 - ref_x)) <= (1e-10 if prec == "fp64" else 1e-3), (prec, a1, ref_x)
+        after = p.designs(0, G).cpu().numpy()
+    assert np.array_equal(before, after)
+
+
+def test_level_search_reaches_closed_form_optimum():
+    """Point-mass prior (no Monte Carlo noise): at q = 0.6 with true cutoff 0.3
+    the searched level and power of the FP64 GPU search match scipy's bounded
+    maximiser of the closed form (within the final bracket)."""
+    import math
+    from scipy.optimize import minimize_scalar
+    from scipy.special import ndtri, ndtr
+    from scipy.optimize import brentq
+    from scipy import stats
+    spec = W.base_problem(1, [3], 0.0, 0.05, q_lo=0.5, q_hi=0.7, sd_b0=0.0, sd_b1=0.0, tau_lo=0.3, tau_hi=0.3)
+    r, I = 0.4, 100.0
+    mu1, mu2 = math.sqrt(I) * 0.5 * 0.7, math.sqrt(r * I) * 0.5 * 0.4 / r
+    cov = [[1.0, math.sqrt(r)], [math.sqrt(r), 1.0]]
+
+    def bvn(h, k):
+        return stats.multivariate_normal.cdf([h, k], mean=[0, 0], cov=cov, abseps=1e-13, releps=1e-13)
+
+    def power(a1):
+        z1 = -ndtri(a1)
+        z2 = brentq(lambda z: a1 + ndtr(-z) - bvn(-z1, -z) - 0.025, -ndtri(0.025), -ndtri(0.025 - a1) + 1e-12,
+                    xtol=1e-14)
+        return 1.0 - bvn(z1 - mu1, z2 - mu2)
+
+    res = minimize_scalar(lambda x: -power(x), bounds=(0.001, 0.024), method="bounded", options={"xatol": 1e-9})
+    with bmd.Problem(spec) as p:
+        best, a1 = p.optimize_levels(2, 0.001, 0.024, 30, "fp64")
+        torch.cuda.synchronize()
+        best, a1 = best.cpu().numpy(), a1.cpu().numpy()
+    assert abs(a1[1] - res.x) < 2e-6, (a1[1], res.x)
+    assert abs(best[1] + res.fun) < 1e-8

@@ -152,7 +152,7 @@ def test_orthant_identities():
         assert abs(O.orthant(c, 0.3) - ref) < 1e-6 * ref   # QMC accuracy of the reference
 
 
-def test_zstar_fwer_and_survey_values():
+def test_zstar_fwer_and_independent_values():
     for r in (0.05, 0.3, 0.5, 0.87, 0.95):
         z = O.zstar(r, 0.025)
         rho = math.sqrt(r)
@@ -223,7 +223,7 @@ def test_degenerate_prior_closed_form():
         for k in (0, 7, 99):
             assert abs(O.success(p, [q], k) - ref) < 1e-13
         assert abs(O.make_design(p, [q])["z1"] - z) < 1e-12
-    # survey value at q = tau = 1/2
+    # independently computed value at q = tau = 1/2
     p.update(tau_lo=0.5, tau_hi=0.5)
     assert abs(O.success(p, [0.5], 0) - 0.921493500270) < 5e-13
 
@@ -287,14 +287,14 @@ def test_symmetry_under_axis_permutation_with_draws():
         assert 0.0 <= a <= 1.0
 
 
-def test_exact_mode_degenerate_and_survey_values():
+def test_exact_mode_degenerate_and_independent_values():
     p = W.plain_1d()
     # degenerate prior: exact expectation is the closed form itself
     pd = dict(p)
     pd.update(sd_b0=0.0, sd_b1=0.0, tau_lo=0.6, tau_hi=0.6)
     ref, _ = _degenerate_reference(0.3, 0.6, 0.0, 0.5)
     assert abs(O.exact_step(pd, [0.3]) - ref) < 1e-13
-    # survey values (independently computed with scipy Owen's T + Gauss-Legendre)
+    # independently computed values (scipy Owen's T + Gauss-Legendre)
     assert abs(O.exact_step(p, [0.05 + 0.9 * 127 / 200]) - 0.702030122778) < 2e-12
     p2 = W.base_problem(2, [5, 5], 0.3, 0.03)
     assert abs(O.exact_step(p2, [0.5, 0.5]) - 0.501076392069) < 2e-12

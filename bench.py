@@ -482,9 +482,9 @@ def bench_levels(args):
            "fp32_vs_fp64": {"speedup": t64 / t32, "max_abs_diff_best": float((b32 - b64).abs().max()),
                             "level_index_agreement": float((k32 == k64).double().mean())},
            "level_search": {"method": f"golden section per design over [{alphas[0]:.4g}, {alphas[-1]:.4g}], "
-                                      f"{n_iter} steps ({n_iter + 2} sweeps on shared draws)",
+                                      f"{n_iter} steps and the two ends ({n_iter + 4} sweeps on shared draws)",
                             "ms_fp32": 1e3 * srch["fp32"][0], "ms_fp64": 1e3 * srch["fp64"][0],
-                            "evals_per_s_fp32": G * M * (n_iter + 2) / srch["fp32"][0],
+                            "evals_per_s_fp32": G * M * (n_iter + 4) / srch["fp32"][0],
                             "max_best": float(srch["fp32"][1].max()),
                             "mean_gain_over_level_grid": float((srch["fp32"][1] - b32).mean()),
                             "share_above_level_grid": float((srch["fp32"][1] >= b32 - 1e-12).double().mean()),

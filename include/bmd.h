@@ -241,8 +241,9 @@ bmd_status bmd_grad_design(bmd_problem *p, const double *d_q, int64_t B, uint64_
  * with draws 0..n_draws-1 (generated once, shared by every level).  The two
  * interior points split the bracket by the golden ratio; each of the n_iter
  * steps drops the part beyond the lower one (ties keep the left part) and
- * evaluates one new level, so the call runs 2 + n_iter sweeps and ends with a
- * bracket (a_hi - a_lo) 0.618^(n_iter + 1) wide.
+ * evaluates one new level, leaving a bracket (a_hi - a_lo) 0.618^(n_iter + 1)
+ * wide; the two ends of the range are evaluated last, so a maximum at an end
+ * is found exactly.  The call runs 4 + n_iter sweeps.
  *   d_best   [G] FP64 the largest estimate seen for each design
  *   d_alpha1 [G] FP64 the level that gave it (the first one seen on ties)
  * A local search: a design whose power has several maxima over the range may

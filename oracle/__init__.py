@@ -384,8 +384,9 @@ def optimize_levels(prob, g_list, M, a_lo, a_hi, n_iter):
     estimate is one deterministic function of alpha_1).  The two interior points
     split the bracket by the golden ratio; the side whose point is lower is
     dropped (ties keep the left part), and one new point is evaluated per step.
-    Returns the largest estimate seen per design and its level (the first one
-    seen on ties)."""
+    The two ends of the range are evaluated last (a_lo, then a_hi), so a
+    maximum at an end is found exactly.  Returns the largest estimate seen per
+    design and its level (the first one seen on ties)."""
     gr = (math.sqrt(5.0) - 1.0) / 2.0
     g_list = np.asarray(g_list, dtype=np.int64)
     n = len(g_list)
@@ -424,6 +425,10 @@ def optimize_levels(prob, g_list, M, a_lo, a_hi, n_iter):
                 f2[i] = fp[i]
             if fp[i] > best[i]:
                 best[i], best_x[i] = fp[i], probe[i]
+    for end in (float(a_lo), float(a_hi)):
+        fe = f(np.full(n, end))
+        up = fe > best
+        best[up], best_x[up] = fe[up], end
     return best, best_x
 
 

@@ -18,8 +18,9 @@ namespace bmd {
 hipError_t launch_smooth_masked(const bmd_problem* p, int prec, const double* in, double* out, double* ws,
                                 hipStream_t s);
 // One step of the per-design golden-section level search (kernels_setup.hip):
-// st [8][G] search state, side [G]; writes the problem's z1, z2 when probing.
-hipError_t launch_levels_golden(const bmd_problem* p, int phase, bool probe, double a_lo, double a_hi,
+// st [8][G] search state, side [G]; writes the problem's z1, z2 when probing
+// (end: 0 the next golden point, 1 the range's lower end, 2 its upper end).
+hipError_t launch_levels_golden(const bmd_problem* p, int phase, bool probe, int end, double a_lo, double a_hi,
                                 const double* mean, double* st, int32_t* side, hipStream_t s);
 }  // namespace bmd
 
@@ -590,9 +591,11 @@ bmd_status bmd_optimize_levels(bmd_problem* p, uint64_t n_draws, int32_t prec, d
     int32_t* side = reinterpret_cast<int32_t*>(base + draw_bytes + part_bytes + mean_bytes + state_bytes);
     HIP_TRY(launch_draws(p, prec, 0, M, p->d_ws, s), "draw kernel");
     hipError_t e = hipSuccess;
-    const int n_sweeps = 2 + n_iter;
+    // two interior points, n_iter golden steps, then the two ends of the range
+    const int n_sweeps = 4 + n_iter;
     for (int ph = 0; ph <= n_sweeps && e == hipSuccess; ++ph) {
-        e = launch_levels_golden(p, ph, ph < n_sweeps, a_lo, a_hi, mean, state, side, s);
+        const int end = ph == n_sweeps - 2 ? 1 : ph == n_sweeps - 1 ? 2 : 0;
+        e = launch_levels_golden(p, ph, ph < n_sweeps, end, a_lo, a_hi, mean, state, side, s);
         if (e == hipSuccess && ph < n_sweeps)
             e = launch_eval_grid(p, prec, M, p->d_ws, partials, static_cast<int>(n_slices), slice_len, false, s);
         if (e == hipSuccess && ph < n_sweeps)

@@ -157,12 +157,15 @@ __global__ __launch_bounds__(128) void k_levels_z(int64_t G, double z1, double a
 // Sec. 2.4 searched, second level on the design's FWER boundary), one call
 // between consecutive sweeps.  st holds [8][G]: bracket ends a, b, interior
 // points x1 < x2, their estimates f1, f2, the best estimate seen and its
-// level; side[g] names the point the last sweep evaluated (1: x1, 2: x2).
-// Phase 0 sets the bracket and probes x1; phase 1 records f(x1) and probes
-// x2; every later phase records the probe, keeps the best, and (when `probe`)
-// drops the part beyond the lower interior point (ties keep the left part)
-// and probes the new point.  A probe writes the design's z1 and z2.
-__global__ __launch_bounds__(128) void k_levels_golden(int64_t G, int phase, bool probe, double a_lo, double a_hi,
+// level; side[g] names the point the last sweep evaluated (1: x1, 2: x2,
+// 3: a_lo, 4: a_hi).  Phase 0 sets the bracket and probes x1; phase 1 records
+// f(x1) and probes x2; every later phase records the probe and keeps the best,
+// then (when `probe`) either drops the part beyond the lower interior point
+// (ties keep the left part) and probes the new point (end = 0), or probes the
+// range's end a_lo (end = 1) or a_hi (end = 2).  A probe writes the design's
+// z1 and z2.
+__global__ __launch_bounds__(128) void k_levels_golden(int64_t G, int phase, bool probe, int end, double a_lo,
+                                                       double a_hi,
                                                        double alpha0, const double* __restrict__ r,
                                                        const double* __restrict__ mean, const double* __restrict__ gl,
                                                        double* __restrict__ st, int32_t* __restrict__ side,
@@ -189,8 +192,9 @@ __global__ __launch_bounds__(128) void k_levels_golden(int64_t G, int phase, boo
     } else {
         const double f = mean[g];
         const int sd = side[g];
-        const double x = sd == 1 ? X1[g] : X2[g];
-        if (sd == 1) F1[g] = f; else F2[g] = f;
+        const double x = sd == 1 ? X1[g] : sd == 2 ? X2[g] : sd == 3 ? a_lo : a_hi;
+        if (sd == 1) F1[g] = f;
+        if (sd == 2) F2[g] = f;
         if (phase == 1) {
             best[g] = f;
             best_x[g] = x;
@@ -201,7 +205,10 @@ __global__ __launch_bounds__(128) void k_levels_golden(int64_t G, int phase, boo
                 best[g] = f;
                 best_x[g] = x;
             }
-            if (probe) {
+            if (probe && end != 0) {
+                side[g] = 2 + end;
+                next = end == 1 ? a_lo : a_hi;
+            } else if (probe) {
                 if (F1[g] >= F2[g]) {   // the maximum lies in [a, x2]
                     B[g] = X2[g];
                     X2[g] = X1[g];
@@ -407,10 +414,10 @@ hipError_t launch_levels_z(const bmd_problem* p, double z1, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_levels_golden(const bmd_problem* p, int phase, bool probe, double a_lo, double a_hi,
+hipError_t launch_levels_golden(const bmd_problem* p, int phase, bool probe, int end, double a_lo, double a_hi,
                                 const double* mean, double* st, int32_t* side, hipStream_t s) {
-    hipLaunchKernelGGL(k_levels_golden, dim3(blocks_for(p->P.G, 128)), dim3(128), 0, s, p->P.G, phase, probe, a_lo,
-                       a_hi, p->P.alpha0, p->d_r, mean, p->d_gl, st, side, p->d_z1, p->d_z2);
+    hipLaunchKernelGGL(k_levels_golden, dim3(blocks_for(p->P.G, 128)), dim3(128), 0, s, p->P.G, phase, probe, end,
+                       a_lo, a_hi, p->P.alpha0, p->d_r, mean, p->d_gl, st, side, p->d_z1, p->d_z2);
     return hipGetLastError();
 }
 

@@ -628,9 +628,9 @@ def test_level_search_reaches_scipy_optimum_under_point_mass_prior():
     grid_best, _ = O.eval_grid_levels(p, np.array([1]), 2, np.linspace(0.001, 0.024, 47))
     assert best[0] >= grid_best[0] - 1e-15
     # a boundary optimum: with the search range cut below the interior optimum
-    # the search ends at the range's upper end
+    # the search ends exactly at the range's upper end
     b2, x2 = O.optimize_levels(p, np.array([1]), 2, 0.001, 0.5 * res.x, 30)
-    assert abs(x2[0] - 0.5 * res.x) < 1e-6 and abs(b2[0] - power(x2[0])) < 1e-12
+    assert x2[0] == 0.5 * res.x and abs(b2[0] - power(x2[0])) < 1e-12
 
 
 # ---------------------------------------------------------------- three nested populations

@@ -163,3 +163,15 @@ def test_alpha3_not_batched():
         with pytest.raises(bmd.BmdError) as e:
             bmd.eval_batch([q, p], [100, 100], "fp32")
         assert e.value.status == -5
+
+
+@pytest.mark.parametrize("M", [1, 7])
+def test_alpha3_few_draws(M):
+    """One draw and a ragged handful: a single partial slice per design."""
+    spec = W.alpha3_design(5)
+    G = O.grid_size(spec)
+    ref, _ = O.eval_grid(spec, np.arange(G), M)
+    for prec in ("fp64", "fp32"):
+        with bmd.Problem(spec) as p:
+            mean = p.eval_grid(M, prec).cpu().numpy()
+        _check(mean, ref, prec, f"alpha3 M={M}")

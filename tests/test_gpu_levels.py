@@ -138,3 +138,24 @@ def test_level_search_reaches_closed_form_optimum():
         best, a1 = best.cpu().numpy(), a1.cpu().numpy()
     assert abs(a1[1] - res.x) < 2e-6, (a1[1], res.x)
     assert abs(best[1] + res.fun) < 1e-8
+
+
+def test_level_search_edges():
+    """No golden steps (the two interior points and the two ends only) against
+    the oracle; a single draw; ranges outside (0, alpha0) and step counts
+    outside [0, 200] are rejected before any launch."""
+    spec = W.base_problem(2, [3, 3], 0.3, 0.05)
+    G = O.grid_size(spec)
+    with bmd.Problem(spec) as p:
+        for n_iter, M in ((0, 300), (3, 1)):
+            ref_best, ref_x = O.optimize_levels(spec, np.arange(G), M, 0.002, 0.02, n_iter)
+            best, a1 = p.optimize_levels(M, 0.002, 0.02, n_iter, "fp64")
+            torch.cuda.synchronize()
+            best, a1 = best.cpu().numpy(), a1.cpu().numpy()
+            assert np.all(np.abs(best - ref_best) <= 1e-9 * np.maximum(np.abs(ref_best), 1e-3)), (n_iter, M)
+            assert np.max(np.abs(a1 - ref_x)) <= 1e-10, (n_iter, M)
+        for lo, hi, n_iter in ((0.0, 0.01, 5), (0.01, 0.005, 5), (0.001, 0.025, 5), (0.001, 0.02, 201),
+                               (0.001, 0.02, -1)):
+            with pytest.raises(bmd.BmdError) as e:
+                p.optimize_levels(100, lo, hi, n_iter, "fp64")
+            assert e.value.status == -2

@@ -389,14 +389,13 @@ def bench_alpha3(args):
     feasible = int((~torch.isnan(m32)).sum().item())
     evals = feasible * M
     a_best = [spec["q_lo"] + (spec["q_hi"] - spec["q_lo"]) * c / (m - 1) for c, m in zip(c32, spec["m"])]
-    # Per summand: three means (12) and, per panel node, the node (1), the two
-    # conditional arguments (4), the Gaussian factor (3), the bivariate CDF
-    # (13 + 6 per node) and the weighted sum (2).
+    # Per summand: three means (12) and, per panel point, the point (2), the two
+    # conditional arguments (6), the Gaussian factor (3), two Phi (3 each) and
+    # the weighted product and sum (5): 22.
     r2, r3 = spec["r_lo"], spec["r_hi"]
-    rho = np.sqrt(r3 * (1 - r2) / (r2 * (1 - r3)))
-    n32 = int(bvn_nodes(np.array([rho]), "fp32")[0])
-    np32 = max(4, min(32, int(np.ceil(2.5 / np.sqrt((1 - r2) / r2)))))   # FP32 panel rule
-    flops = feasible * M * (12.0 + np32 * 8 * (23.0 + 6.0 * n32))
+    scale = min(np.sqrt((1 - r2) / r2), np.sqrt((r2 - r3) / r3))
+    np32 = max(4, min(64, int(np.ceil(2.5 / scale))))   # FP32 panel rule
+    flops = feasible * M * (12.0 + np32 * 8 * 22.0)
     achieved = flops / (1e-3 * s32) / 1e12
     out = {"metric": "three-population alpha grid: integrand evals/s", "value": evals / t32,
            "unit": "integrand evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -411,8 +410,8 @@ def bench_alpha3(args):
                       "designs": G, "feasible_designs": feasible, "n_draws": M},
            "roofline": {"bound": "alu", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
                         "frac": achieved / 157.3, "traffic": None,
-                        "kernel": f"k_eval_three<float,12,false> (one design per thread, {np32} panels x 8 points, "
-                                  f"{n32}-node inner bivariate rule)", "flops_per_launch": flops},
+                        "kernel": f"k_eval_three<float,false> (one design per thread, {np32} panels x 8 points "
+                                  f"of two univariate CDFs given the middle statistic)", "flops_per_launch": flops},
            "sweep_ms": s32, "sweep_evals_per_s": evals / (1e-3 * s32),
            "result": {"best_alpha": a_best, "best_power_smoothed": v32,
                       "raw_power_at_best": float(m32[i32].item())},

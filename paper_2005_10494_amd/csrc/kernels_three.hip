@@ -4,21 +4,22 @@
 // Formula 2, and the grid sweep of the Formula 5 estimate whose summand is
 // 1 - Phi_3(z - mu; R).
 //
-// Phi_3 by conditioning on the first coordinate:
-//   Phi_3(h1, h2, h3; R) = int_{-inf}^{h1} phi(x) Phi_2((h2 - r12 x)/s12, (h3 - r13 x)/s13; r23.1) dx
-// with s1j = sqrt(1 - r1j^2) and r23.1 the partial correlation.  For the nested
-// correlations r12 = sqrt(r2), r13 = sqrt(r3), r23 = sqrt(r3/r2) it is
-// r23.1 = sqrt(r3 (1 - r2) / (r2 (1 - r3))), one constant per problem, so the
-// inner bivariate rule is set up once per thread.  The integral runs over
-// [-L, U], U = min(h1, L, the x beyond which either conditional argument
-// falls below -L), with L = 8.5 in FP64 (Phi(-8.5) < 1e-17) and 6 in FP32
-// (Phi(-6) = 1e-9), cut into equal panels of an 8-point Gauss-Legendre rule.
-// The integrand's steepest feature is the conditional CDF of the second
-// coordinate, whose scale in x is l = s12 / r12 = sqrt((1 - r2) / r2) (the
-// third is gentler, r3 < r2); the panel count is ceil(c / l) with c = 6, at
-// least 8 panels in FP64, and c = 2.5, at least 4, in FP32.  Against an
-// adaptive reference over 0.1 <= r2 <= 0.9 this keeps the quadrature error
-// below 1e-12 (FP64) and 3e-9 (FP32); the critical values use at least 16
+// Phi_3 by conditioning on the middle coordinate.  For nested populations
+// the statistics form a chain: the partial correlation of the first and third
+// given the second, (r13 - r12 r23) / (s12 s23) with r12 = sqrt(r2),
+// r13 = sqrt(r3), r23 = sqrt(r3/r2), is zero, so given Y2 = y the other two are
+// independent normals with means r12 y, r23 y and sds s12 = sqrt(1 - r2),
+// s23 = sqrt(1 - r3/r2):
+//   Phi_3(h1, h2, h3) = int_{-inf}^{h2} phi(y) Phi((h1 - r12 y)/s12) Phi((h3 - r23 y)/s23) dy,
+// a one-dimensional integral of univariate CDFs only.  It runs over [-L, U],
+// U = min(h2, L, the y beyond which either conditional argument falls below
+// -L), with L = 8.5 in FP64 (Phi(-8.5) < 1e-17) and 6 in FP32 (Phi(-6) = 1e-9),
+// cut into equal panels of an 8-point Gauss-Legendre rule.  The integrand's
+// steepest part is the conditional CDF whose scale in y, l = s12 / r12 or
+// s23 / r23, is smaller; the panel count is ceil(c / l) with c = 6 (8..128
+// panels) in FP64 and c = 2.5 (4..64) in FP32.  Against an adaptive reference
+// over 0.1 <= r2 <= 0.9 and r3 / r2 up to 0.99 this keeps the quadrature error
+// below 5e-12 (FP64) and 2e-8 (FP32); the critical values use at least 16
 // panels.
 #include <cmath>
 
@@ -31,16 +32,13 @@ namespace {
 constexpr int kNodes = 8;          // Gauss-Legendre points per panel
 constexpr int kPanelsSetup = 16;   // fewest panels for the critical values (FP64)
 
-// Panels for the summand in type T at subgroup fraction r2.
+// Panels in type T for subgroup fractions r2 > r3.
 template <typename T>
-__device__ __forceinline__ int tvn_panels(double r2) {
-    const double l = sqrt((1.0 - r2) / r2);
-    const int lo = sizeof(T) == 8 ? 8 : 4;
-    return max(lo, min(32, static_cast<int>(ceil((sizeof(T) == 8 ? 6.0 : 2.5) / l))));
-}
-
-__device__ __forceinline__ double partial_corr(double r2, double r3) {
-    return sqrt(r3 * (1.0 - r2) / (r2 * (1.0 - r3)));
+__device__ __forceinline__ int tvn_panels(double r2, double r3) {
+    const double l = fmin(sqrt((1.0 - r2) / r2), sqrt((r2 - r3) / r3));
+    const double c = sizeof(T) == 8 ? 6.0 : 2.5;
+    const int lo = sizeof(T) == 8 ? 8 : 4, hi = sizeof(T) == 8 ? 128 : 64;
+    return max(lo, min(hi, static_cast<int>(ceil(c / l))));
 }
 
 // exp(-x^2 / 2); FP32 through exp2.
@@ -50,31 +48,29 @@ __device__ __forceinline__ float half_gauss(float x) {
 }
 
 // Per-problem constants of Phi_3 in type T.
-template <typename T, int NMAX>
+template <typename T>
 struct TvnConst {
-    T r12, r13;        // regressions of the second and third coordinates on the first
-    T is12, is13;      // 1 / s1j
+    T r12, r23;        // regressions of the first and third coordinates on the second
+    T is12, is23;      // 1 / s12, 1 / s23
     T tail;            // L: integration range [-L, U]
-    T c2, c3;          // L s1j: offsets of the upper integration limit
-    T ir12, ir13;      // 1 / r1j
+    T c1, c3;          // L s12, L s23: offsets of the upper integration limit
+    T ir12, ir23;      // 1 / r12, 1 / r23
     T px[kNodes];      // panel nodes on [0, 1]
     T pw[kNodes];      // panel weights with phi's 1/sqrt(2 pi) folded in
-    BvnConst<T, NMAX> bc;   // inner bivariate rule at r23.1
-    int n;                  // its node count
-    int np;                 // panels
+    int np;            // panels
 
-    __device__ void init(double r2, double r3, int n_inner, int panels, const double* __restrict__ gl) {
+    __device__ void init(double r2, double r3, int panels, const double* __restrict__ gl) {
         const double L = sizeof(T) == 8 ? 8.5 : 6.0;
-        const double a = sqrt(r2), b = sqrt(r3), sa = sqrt(1.0 - r2), sb = sqrt(1.0 - r3);
+        const double a = sqrt(r2), b = sqrt(r3 / r2), sa = sqrt(1.0 - r2), sb = sqrt(1.0 - r3 / r2);
         r12 = static_cast<T>(a);
-        r13 = static_cast<T>(b);
+        r23 = static_cast<T>(b);
         is12 = static_cast<T>(1.0 / sa);
-        is13 = static_cast<T>(1.0 / sb);
+        is23 = static_cast<T>(1.0 / sb);
         tail = static_cast<T>(L);
-        c2 = static_cast<T>(L * sa);
+        c1 = static_cast<T>(L * sa);
         c3 = static_cast<T>(L * sb);
         ir12 = static_cast<T>(1.0 / a);
-        ir13 = static_cast<T>(1.0 / b);
+        ir23 = static_cast<T>(1.0 / b);
         const double* x = gl + gl_offset(kNodes);
         const double* w = x + kNodes;
 #pragma unroll
@@ -82,29 +78,27 @@ struct TvnConst {
             px[i] = static_cast<T>(0.5 * (1.0 + x[i]));
             pw[i] = static_cast<T>(0.5 * w[i] * 0.39894228040143267794);
         }
-        n = n_inner;
         np = panels;
-        bc.init(partial_corr(r2, r3), n_inner, gl);
     }
 };
 
 // Phi_3(h1, h2, h3) over c.np panels (wave-uniform).  Every lane runs the
 // same node count: an empty range (U <= -L) becomes a zero panel width, and
 // NaN inputs give NaN.
-template <typename T, int NMAX, typename W>
-__device__ __forceinline__ T tvn(T h1, T h2, T h3, const TvnConst<T, NMAX>& c, const W& w) {
+template <typename T>
+__device__ __forceinline__ T tvn(T h1, T h2, T h3, const TvnConst<T>& c) {
     const T lo = -c.tail;
-    const T hi = fmin(fmin(h1, c.tail), fmin((h2 + c.c2) * c.ir12, (h3 + c.c3) * c.ir13));
+    const T hi = fmin(fmin(h2, c.tail), fmin((h1 + c.c1) * c.ir12, (h3 + c.c3) * c.ir23));
     const T width = fmax(hi - lo, T(0)) / static_cast<T>(c.np);
     T acc = T(0);
     for (int p = 0; p < c.np; ++p) {
         const T a = fma(width, static_cast<T>(p), lo);
 #pragma unroll
         for (int i = 0; i < kNodes; ++i) {
-            const T x = fma(width, c.px[i], a);
-            const T u = (h2 - c.r12 * x) * c.is12;
-            const T v = (h3 - c.r13 * x) * c.is13;
-            acc = fma(c.pw[i] * half_gauss(x), bvn_cdf<NMAX>(u, v, c.bc, w, c.n), acc);
+            const T y = fma(width, c.px[i], a);
+            const T u = (h1 - c.r12 * y) * c.is12;
+            const T v = (h3 - c.r23 * y) * c.is23;
+            acc = fma(c.pw[i] * half_gauss(y), norm_cdf(u) * norm_cdf(v), acc);
         }
     }
     return acc * width;
@@ -136,11 +130,9 @@ __global__ __launch_bounds__(64) void k_three_precompute(DevProblem P, const dou
     const double a12 = 1.0 - bvn_cdf<n>(z1, z2, b12, w, n);
     double z3 = NAN;
     if (a12 < P.alpha0) {
-        const int ni = bvn_nodes_fp64(partial_corr(P.r_lo, P.r_hi));
-        TvnConst<double, n> c;
-        c.init(P.r_lo, P.r_hi, ni, max(kPanelsSetup, tvn_panels<double>(P.r_lo)), gl);
-        const double* wi = gl + gl_offset(ni) + ni;
-        auto F = [&](double z) { return (1.0 - tvn(z1, z2, z, c, wi)) - P.alpha0; };
+        TvnConst<double> c;
+        c.init(P.r_lo, P.r_hi, max(kPanelsSetup, tvn_panels<double>(P.r_lo, P.r_hi)), gl);
+        auto F = [&](double z) { return (1.0 - tvn(z1, z2, z, c)) - P.alpha0; };
         double lo = -norm_quantile(P.alpha0), hi = -norm_quantile(P.alpha0 - a12);
         double Flo = F(lo), Fhi = F(hi);
         z3 = Flo <= 0.0 ? lo : Fhi >= 0.0 ? hi : 0.5 * (lo + hi);
@@ -181,7 +173,6 @@ struct ThreeArgs {
     int64_t slice_len;
     double* partials;   // [n_slices][2][G]: sums, then sums of squares (VAR only)
     const double* gl;   // packed Gauss-Legendre table, FP64
-    const T* glw;       // the same in T (inner weights read from here)
     double r2, r3;
     // Formula 10 means of the three statistics, sqrt(r_i I) (theta_i + sigma_i Y_i):
     // mu1 = m0 + m1 e1, mu2 = m2 + m3 e1 + m4 e2, mu3 = m5 + m6 e1 + m7 e2 + m8 e3.
@@ -189,16 +180,13 @@ struct ThreeArgs {
 };
 
 // One thread per design (alpha_1, alpha_2), the draws of slice blockIdx.y.
-template <typename T, int NMAX, bool VAR>
+template <typename T, bool VAR>
 __global__ __launch_bounds__(kEvalBlock) void k_eval_three(ThreeArgs<T> a) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * kEvalBlock + threadIdx.x;
     const bool valid = g < a.G;
     const int64_t gg = valid ? g : a.G - 1;   // idle lanes shadow the last design
-    const double rho = partial_corr(a.r2, a.r3);
-    const int n = sizeof(T) == 8 ? bvn_nodes_fp64(rho) : bvn_nodes_fp32(rho);
-    TvnConst<T, NMAX> c;
-    c.init(a.r2, a.r3, n, tvn_panels<T>(a.r2), a.gl);
-    const T* w = a.glw + gl_offset(n) + n;
+    TvnConst<T> c;
+    c.init(a.r2, a.r3, tvn_panels<T>(a.r2, a.r3), a.gl);
     const T z1 = static_cast<T>(a.z1[gg]), z2 = static_cast<T>(a.z2[gg]), z3 = static_cast<T>(a.z3[gg]);
     T m[9];
 #pragma unroll
@@ -212,7 +200,7 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_three(ThreeArgs<T> a) {
         const T h1 = z1 - fma(m[1], e1, m[0]);
         const T h2 = z2 - fma(m[4], e2, fma(m[3], e1, m[2]));
         const T h3 = z3 - fma(m[8], e3, fma(m[7], e2, fma(m[6], e1, m[5])));
-        const double v = static_cast<double>(T(1) - tvn(h1, h2, h3, c, w));
+        const double v = static_cast<double>(T(1) - tvn(h1, h2, h3, c));
         s1 += v;
         if constexpr (VAR) s2 = fma(v, v, s2);
     }
@@ -224,7 +212,7 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_three(ThreeArgs<T> a) {
 }
 
 template <typename T>
-ThreeArgs<T> three_args(const bmd_problem* p, DrawArrays<T> D, const T* glw, double* partials, int64_t slice_len) {
+ThreeArgs<T> three_args(const bmd_problem* p, DrawArrays<T> D, double* partials, int64_t slice_len) {
     const DevProblem& P = p->P;
     ThreeArgs<T> a{};
     a.G = P.G;
@@ -238,7 +226,6 @@ ThreeArgs<T> three_args(const bmd_problem* p, DrawArrays<T> D, const T* glw, dou
     a.slice_len = slice_len;
     a.partials = partials;
     a.gl = p->d_gl;
-    a.glw = glw;
     a.r2 = P.r_lo;
     a.r3 = P.r_hi;
     const double r[3] = {1.0, P.r_lo, P.r_hi};
@@ -261,10 +248,10 @@ ThreeArgs<T> three_args(const bmd_problem* p, DrawArrays<T> D, const T* glw, dou
     return a;
 }
 
-template <typename T, int NMAX>
+template <typename T>
 hipError_t launch_typed(const ThreeArgs<T>& a, int n_slices, bool var, hipStream_t s) {
-    const void* k = var ? reinterpret_cast<const void*>(k_eval_three<T, NMAX, true>)
-                        : reinterpret_cast<const void*>(k_eval_three<T, NMAX, false>);
+    const void* k = var ? reinterpret_cast<const void*>(k_eval_three<T, true>)
+                        : reinterpret_cast<const void*>(k_eval_three<T, false>);
     void* args[] = {const_cast<ThreeArgs<T>*>(&a)};
     return hipLaunchKernel(k, dim3(static_cast<unsigned>((a.G + kEvalBlock - 1) / kEvalBlock),
                                    static_cast<unsigned>(n_slices)),
@@ -281,8 +268,8 @@ hipError_t launch_three_precompute(const bmd_problem* p, hipStream_t s) {
 }
 
 int three_blocks_per_cu(int prec) {
-    const void* k = prec == BMD_FP64 ? reinterpret_cast<const void*>(k_eval_three<double, 24, false>)
-                                     : reinterpret_cast<const void*>(k_eval_three<float, 12, false>);
+    const void* k = prec == BMD_FP64 ? reinterpret_cast<const void*>(k_eval_three<double, false>)
+                                     : reinterpret_cast<const void*>(k_eval_three<float, false>);
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kEvalBlock, 0) != hipSuccess || nb < 1) {
         (void)hipGetLastError();
@@ -294,14 +281,10 @@ int three_blocks_per_cu(int prec) {
 hipError_t launch_eval_three(const bmd_problem* p, int prec, int64_t M, const void* ws, double* partials,
                              int n_slices, int64_t slice_len, bool want_var, hipStream_t s) {
     if (prec == BMD_FP64)
-        return launch_typed<double, 24>(
-            three_args<double>(p, draws_fp64(p, M, ws), static_cast<const double*>(p->tab[prec].glw), partials,
-                               slice_len),
-            n_slices, want_var, s);
-    return launch_typed<float, 12>(
-        three_args<float>(p, draws_fp32(p, M, ws), static_cast<const float*>(p->tab[prec].glw), partials,
-                          slice_len),
-        n_slices, want_var, s);
+        return launch_typed<double>(three_args<double>(p, draws_fp64(p, M, ws), partials, slice_len), n_slices,
+                                    want_var, s);
+    return launch_typed<float>(three_args<float>(p, draws_fp32(p, M, ws), partials, slice_len), n_slices, want_var,
+                               s);
 }
 
 }  // namespace bmd

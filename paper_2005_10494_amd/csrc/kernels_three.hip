@@ -163,6 +163,7 @@ __global__ __launch_bounds__(64) void k_three_precompute(DevProblem P, const dou
 template <typename T>
 struct ThreeArgs {
     int64_t G;
+    int m0, m1;         // grid points of alpha_1 (axis 0) and alpha_2 (axis 1)
     const double* z1;
     const double* z2;
     const double* z3;
@@ -180,18 +181,37 @@ struct ThreeArgs {
 };
 
 // One thread per design (alpha_1, alpha_2), the draws of slice blockIdx.y.
+// Each wavefront takes an 8 x 8 block of the level grid (four blocks per
+// workgroup, in row-major block order): designs without a third level fill
+// the corner where both levels are large, so whole blocks there have none,
+// and such a wavefront writes NaN sums and leaves without touching the draws
+// (about a third of the wavefronts at Sec. 3's condition (c) grid).
 template <typename T, bool VAR>
 __global__ __launch_bounds__(kEvalBlock) void k_eval_three(ThreeArgs<T> a) {
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * kEvalBlock + threadIdx.x;
-    const bool valid = g < a.G;
-    const int64_t gg = valid ? g : a.G - 1;   // idle lanes shadow the last design
+    const int t1 = (a.m0 + 7) / 8, t2 = (a.m1 + 7) / 8;
+    const int wt = static_cast<int>(blockIdx.x) * (kEvalBlock / 64) + static_cast<int>(threadIdx.x) / 64;
+    const int lane = static_cast<int>(threadIdx.x) % 64;
+    const int i1 = (wt / t2) * 8 + lane / 8, i2 = (wt % t2) * 8 + lane % 8;
+    const bool valid = wt < t1 * t2 && i1 < a.m0 && i2 < a.m1;
+    const int64_t g = static_cast<int64_t>(i1) * a.m1 + i2;
+    // idle lanes shadow a design of the grid
+    const int64_t gg = valid ? g : static_cast<int64_t>(min(i1, a.m0 - 1)) * a.m1 + min(i2, a.m1 - 1);
+    const int slice = blockIdx.y;
+    const double z3d = a.z3[gg];
+    if (__all(!valid || z3d != z3d)) {
+        if (valid) {
+            double* out = a.partials + static_cast<int64_t>(slice) * 2 * a.G;
+            out[g] = z3d;
+            if constexpr (VAR) out[a.G + g] = z3d;
+        }
+        return;
+    }
     TvnConst<T> c;
     c.init(a.r2, a.r3, tvn_panels<T>(a.r2, a.r3), a.gl);
-    const T z1 = static_cast<T>(a.z1[gg]), z2 = static_cast<T>(a.z2[gg]), z3 = static_cast<T>(a.z3[gg]);
+    const T z1 = static_cast<T>(a.z1[gg]), z2 = static_cast<T>(a.z2[gg]), z3 = static_cast<T>(z3d);
     T m[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) m[i] = static_cast<T>(a.m[i]);
-    const int slice = blockIdx.y;
     const int64_t kb = static_cast<int64_t>(slice) * a.slice_len;
     const int64_t ke = min(a.M, kb + a.slice_len);
     double s1 = 0.0, s2 = 0.0;
@@ -216,6 +236,8 @@ ThreeArgs<T> three_args(const bmd_problem* p, DrawArrays<T> D, double* partials,
     const DevProblem& P = p->P;
     ThreeArgs<T> a{};
     a.G = P.G;
+    a.m0 = P.m[0];
+    a.m1 = P.m[1];
     a.z1 = p->d_z1;
     a.z2 = p->d_z2;
     a.z3 = p->d_z3;
@@ -253,7 +275,8 @@ hipError_t launch_typed(const ThreeArgs<T>& a, int n_slices, bool var, hipStream
     const void* k = var ? reinterpret_cast<const void*>(k_eval_three<T, true>)
                         : reinterpret_cast<const void*>(k_eval_three<T, false>);
     void* args[] = {const_cast<ThreeArgs<T>*>(&a)};
-    return hipLaunchKernel(k, dim3(static_cast<unsigned>((a.G + kEvalBlock - 1) / kEvalBlock),
+    const int64_t blocks = static_cast<int64_t>((a.m0 + 7) / 8) * ((a.m1 + 7) / 8);   // 8 x 8 design blocks
+    return hipLaunchKernel(k, dim3(static_cast<unsigned>((blocks + kEvalBlock / 64 - 1) / (kEvalBlock / 64)),
                                    static_cast<unsigned>(n_slices)),
                            dim3(kEvalBlock), args, 0, s);
 }

@@ -185,7 +185,7 @@ struct ThreeArgs {
 // workgroup, in row-major block order): designs without a third level fill
 // the corner where both levels are large, so whole blocks there have none,
 // and such a wavefront writes NaN sums and leaves without touching the draws
-// (about a third of the wavefronts at Sec. 3's condition (c) grid).
+// (two fifths of the wavefronts on a 97 x 97 grid at Sec. 3's condition (c)).
 template <typename T, bool VAR>
 __global__ __launch_bounds__(kEvalBlock) void k_eval_three(ThreeArgs<T> a) {
     const int t1 = (a.m0 + 7) / 8, t2 = (a.m1 + 7) / 8;

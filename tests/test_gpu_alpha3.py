@@ -175,3 +175,27 @@ def test_alpha3_few_draws(M):
         with bmd.Problem(spec) as p:
             mean = p.eval_grid(M, prec).cpu().numpy()
         _check(mean, ref, prec, f"alpha3 M={M}")
+
+
+@pytest.mark.parametrize("m,M", [((13, 21), 900), ((211, 211), 2000)])
+def test_alpha3_block_mapping_sampled(m, M):
+    """Wavefronts take 8 x 8 level blocks: a ragged non-square grid and a large
+    one (27 x 27 blocks, the last ones partly outside the grid) against the
+    oracle at sampled designs, corners and designs without a third level
+    included; every design is written (finite or NaN as the oracle says)."""
+    spec = W.alpha3_design(5)
+    spec["m"] = list(m)
+    spec["bandwidth"] = [0.0015, 0.0015]
+    G = m[0] * m[1]
+    rng = np.random.default_rng(m[0])
+    gs = np.unique(np.concatenate([[0, m[1] - 1, G - m[1], G - 1], rng.integers(0, G, 6)]))
+    ref, _ = O.eval_grid(spec, gs, M)
+    feas = np.array([not math.isnan(O.make_design(spec, O.grid_point(spec, g)[0])["z3"]) for g in gs])
+    for prec in ("fp64", "fp32"):
+        say(f"alpha3 blocks m={m} M={M} {prec}")
+        with bmd.Problem(spec) as p:
+            mean = p.eval_grid(M, prec).cpu().numpy()
+            z3 = p.designs(0, G).cpu().numpy()[:, 7]
+        assert np.array_equal(np.isnan(mean), np.isnan(z3))
+        assert np.array_equal(~np.isnan(mean[gs]), feas)
+        _check(mean[gs], ref, prec, f"alpha3 blocks {m}")

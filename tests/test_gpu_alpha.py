@@ -115,3 +115,18 @@ def test_alpha_problem_in_a_batch():
     finally:
         for p in probs:
             p.close()
+
+
+def test_alpha_full_grid_sampled():
+    """The benchmarked alpha grid (181 x 241 designs, M = 1e6, FP32 integrand):
+    six designs, corners included, against the oracle on the same draws."""
+    spec = W.alpha_grid()
+    G, M = O.grid_size(spec), spec["n_draws"]
+    rng = np.random.default_rng(11)
+    gs = np.unique(np.concatenate([[0, G - 1, G // 2 + 17], rng.integers(0, G, 3)]))
+    say(f"alpha full grid G={G} M={M}: oracle on {len(gs)} designs")
+    ref, _ = O.eval_grid(spec, gs, M)
+    with bmd.Problem(spec) as p:
+        mean = p.eval_grid(M, "fp32").cpu().numpy()
+    _check(mean[gs], ref, "fp32", "alpha full grid")
+    assert np.all(np.isfinite(mean)) and mean.min() >= 0.0 and mean.max() <= 1.0

@@ -199,3 +199,19 @@ def test_alpha3_block_mapping_sampled(m, M):
         assert np.array_equal(np.isnan(mean), np.isnan(z3))
         assert np.array_equal(~np.isnan(mean[gs]), feas)
         _check(mean[gs], ref, prec, f"alpha3 blocks {m}")
+
+
+def test_alpha3_full_grid_sampled():
+    """The benchmarked three-population grid (97 x 97 designs, M = 1e5, FP32
+    integrand): two feasible designs against the oracle on the same draws, and
+    the NaN pattern of the whole surface is that of the designs' third levels."""
+    spec = W.alpha3_grid()
+    G, M = O.grid_size(spec), spec["n_draws"]
+    gs = np.array([0, 52 * 97 + 20])
+    say(f"alpha3 full grid G={G} M={M}: oracle on {len(gs)} designs")
+    ref, _ = O.eval_grid(spec, gs, M)
+    with bmd.Problem(spec) as p:
+        mean = p.eval_grid(M, "fp32").cpu().numpy()
+        z3 = p.designs(0, G).cpu().numpy()[:, 7]
+    _check(mean[gs], ref, "fp32", "alpha3 full grid")
+    assert np.array_equal(np.isnan(mean), np.isnan(z3)) and 0 < np.isnan(mean).sum() < G

@@ -234,6 +234,9 @@ bmd_status bmd_grad_design(bmd_problem *p, const double *d_q, int64_t B, uint64_
  * the call returns (a design precompute is re-launched on `stream`).  ESTATE
  * for a continuous problem or the alpha design space; ERANGE for n_alpha
  * outside [1, 4096] or a level outside (0, alpha0). */
+bmd_status bmd_eval_grid_levels(bmd_problem *p, uint64_t n_draws, int32_t prec, const double *h_alpha1,
+                                int32_t n_alpha, double *d_best, int32_t *d_best_k, void *stream);
+
 /* Optimal level split per design found by search (Sec. 2.4's "optimal power"
  * at each design, n = 2 nested tests): for every design, golden-section search
  * of the first level alpha_1 over [a_lo, a_hi] (0 < a_lo < a_hi < alpha0),
@@ -252,9 +255,6 @@ bmd_status bmd_grad_design(bmd_problem *p, const double *d_q, int64_t B, uint64_
  * ERANGE for the range or n_iter outside [0, 200]. */
 bmd_status bmd_optimize_levels(bmd_problem *p, uint64_t n_draws, int32_t prec, double a_lo, double a_hi,
                                int32_t n_iter, double *d_best, double *d_alpha1, void *stream);
-
-bmd_status bmd_eval_grid_levels(bmd_problem *p, uint64_t n_draws, int32_t prec, const double *h_alpha1,
-                                int32_t n_alpha, double *d_best, int32_t *d_best_k, void *stream);
 
 /* Continuous refinement of a design (Sec. 2.3: the best grid point refined by
  * a local gradient method): projected gradient ascent inside the box

@@ -125,6 +125,24 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _device_buffer(t, n: int, device, name: str, dtype=None):
+    """Check a tensor whose pointer goes to the library: on `device`, contiguous,
+    `n` elements of `dtype` (float64 by default).  Raises ValueError."""
+    import torch
+    dtype = torch.float64 if dtype is None else dtype
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if t.device != device:
+        raise ValueError(f"{name}: on {t.device}, expected {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name}: {t.numel()} elements, expected {n}")
+    return t
+
+
 def make_desc(spec: dict) -> _Desc:
     """Descriptor from a problem dict (keys as in ``workloads.base_problem``)."""
     D = _Desc()
@@ -196,10 +214,18 @@ class Problem:
     # -- entry points ---------------------------------------------------------
     def eval_grid(self, n_draws: int, precision="fp64", want_var=False, out=None, out_var=None, stream=None):
         import torch
-        mean = out if out is not None else torch.empty(self.G, dtype=torch.float64, device=self.device)
+        if out is not None:
+            mean = _device_buffer(out, self.G, self.device, "out")
+        else:
+            mean = torch.empty(self.G, dtype=torch.float64, device=self.device)
         var = None
         if want_var:
-            var = out_var if out_var is not None else torch.empty(self.G, dtype=torch.float64, device=self.device)
+            if out_var is not None:
+                var = _device_buffer(out_var, self.G, self.device, "out_var")
+                if var.data_ptr() == mean.data_ptr():
+                    raise ValueError("out and out_var must be different buffers")
+            else:
+                var = torch.empty(self.G, dtype=torch.float64, device=self.device)
         _check(library().bmd_eval_grid(self._h, int(n_draws), _prec(precision), ctypes.c_void_p(mean.data_ptr()),
                                        ctypes.c_void_p(var.data_ptr()) if var is not None else None,
                                        _stream(stream)))
@@ -207,15 +233,16 @@ class Problem:
 
     def smooth(self, surface, precision="fp64", out=None, stream=None):
         import torch
-        assert surface.dtype == torch.float64 and surface.is_contiguous() and surface.numel() == self.G
-        res = out if out is not None else torch.empty_like(surface)
+        _device_buffer(surface, self.G, self.device, "surface")
+        res = _device_buffer(out, self.G, self.device, "out") if out is not None else torch.empty_like(surface)
+        if res.data_ptr() == surface.data_ptr():
+            raise ValueError("out must not alias surface")
         _check(library().bmd_smooth(self._h, ctypes.c_void_p(surface.data_ptr()), ctypes.c_void_p(res.data_ptr()),
                                     _prec(precision), _stream(stream)))
         return res
 
     def argmax(self, surface, stream=None):
-        import torch
-        assert surface.dtype == torch.float64 and surface.is_contiguous() and surface.numel() == self.G
+        _device_buffer(surface, self.G, self.device, "surface")
         idx = ctypes.c_int64()
         val = ctypes.c_double()
         cell = (ctypes.c_int32 * 6)()
@@ -225,7 +252,9 @@ class Problem:
 
     def grad_design(self, q, n_draws: int, precision="fp32", want_grad=True, stream=None):
         import torch
-        q = q.to(device=self.device, dtype=torch.float64).contiguous()
+        q = torch.as_tensor(q).to(device=self.device, dtype=torch.float64).contiguous()
+        if q.dim() != 2 or q.shape[1] != self.d or q.shape[0] < 1:
+            raise ValueError(f"q: shape {tuple(q.shape)}, expected (B, {self.d}) with B >= 1")
         B = q.shape[0]
         obj = torch.empty(B, dtype=torch.float64, device=self.device)
         gq = torch.empty(B, self.d, dtype=torch.float64, device=self.device) if want_grad else None

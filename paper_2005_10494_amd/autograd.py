@@ -4,12 +4,49 @@
 continuous design points q [B, d] for prior means mu = (mu_b0, mu_b1); its
 backward pass uses the library's adjoint kernel (bmd_grad_design), which
 regenerates the draws from their Philox counters.
+
+Problems are kept in a small cache keyed by the descriptor (including the prior
+means), so a loop over design points with fixed prior means builds its problem
+(design precompute and device constants) once; the gradient is computed only
+when q or mu requires it.
 """
 from __future__ import annotations
+
+from collections import OrderedDict
 
 import torch
 
 from . import Problem
+
+_CACHE: "OrderedDict[tuple, Problem]" = OrderedDict()
+_CACHE_SIZE = 4
+
+
+def _key(spec: dict, device) -> tuple:
+    items = []
+    for k in sorted(spec):
+        v = spec[k]
+        items.append((k, tuple(v) if isinstance(v, (list, tuple)) else v))
+    return (str(device),) + tuple(items)
+
+
+def _problem(spec: dict) -> Problem:
+    key = _key(spec, torch.cuda.current_device())
+    p = _CACHE.get(key)
+    if p is not None:
+        _CACHE.move_to_end(key)
+        return p
+    p = Problem(spec)
+    _CACHE[key] = p
+    while len(_CACHE) > _CACHE_SIZE:
+        _CACHE.popitem(last=False)[1].close()
+    return p
+
+
+def clear_cache() -> None:
+    """Release the cached problems' device memory."""
+    while _CACHE:
+        _CACHE.popitem()[1].close()
 
 
 class BmdObjective(torch.autograd.Function):
@@ -17,17 +54,18 @@ class BmdObjective(torch.autograd.Function):
     def forward(ctx, q, mu, spec, n_draws, precision):
         s = dict(spec)
         s["mu_b0"], s["mu_b1"] = (float(x) for x in mu.detach().cpu().tolist())
-        with Problem(s) as p:
-            obj, gq, gmu = p.grad_design(q.detach(), n_draws, precision, want_grad=True)
-        ctx.save_for_backward(gq, gmu)
+        want_grad = bool(ctx.needs_input_grad[0] or ctx.needs_input_grad[1])
+        obj, gq, gmu = _problem(s).grad_design(q.detach(), n_draws, precision, want_grad=want_grad)
+        if want_grad:
+            ctx.save_for_backward(gq, gmu)
         return obj.to(q.dtype)
 
     @staticmethod
     def backward(ctx, grad_out):
         gq, gmu = ctx.saved_tensors
         g = grad_out.to(torch.float64)
-        grad_q = (g[:, None] * gq)
-        grad_mu = (g[:, None] * gmu).sum(0)
+        grad_q = (g[:, None] * gq) if ctx.needs_input_grad[0] else None
+        grad_mu = (g[:, None] * gmu).sum(0) if ctx.needs_input_grad[1] else None
         return grad_q, grad_mu, None, None, None
 
 

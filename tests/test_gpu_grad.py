@@ -102,8 +102,9 @@ def test_autograd_function():
 
 def test_differentiation_config_full_size():
     """4,096 points of the continuous 5-D design, M = 1,000,000 draws, FP32
-    adjoint: checked against the FP64 adjoint on every point and against the
-    oracle on two points with the first 20,000 draws."""
+    adjoint as benchmarked: checked against the FP64 adjoint on every point;
+    then the first 64 points against the oracle's forward-mode gradients on the
+    first 4,000 draws, in both precisions."""
     spec = W.grad_5d()
     q = W.design_points(spec["n_points"], 5, seed=1)
     M = spec["n_draws"]
@@ -112,10 +113,36 @@ def test_differentiation_config_full_size():
     assert rel_err(obj32, obj64, 1e-3) <= 1e-5
     assert rel_err(gq32, gq64, 1e-2) <= 1e-4
     assert rel_err(gmu32, gmu64, 1e-2) <= 1e-4
-    o_obj, o_gq, o_gmu = O.grad_points(spec, q[:2], 20000)
-    obj, gq, gmu = gpu_grad(spec, q[:2], 20000, "fp64")
-    assert rel_err(obj, o_obj, 1e-3) <= 1e-9
-    assert rel_err(gq, o_gq, 1e-2) <= 1e-7
+    Mo, n = 4000, 64
+    say(f"oracle gradients: {n} points x {Mo} draws")
+    o_obj, o_gq, o_gmu = O.grad_points(spec, q[:n], Mo)
+    for prec, tol_o, tol_g in (("fp64", 1e-9, 1e-7), ("fp32", 1e-5, 2e-4)):
+        obj, gq, gmu = gpu_grad(spec, q[:n], Mo, prec)
+        assert rel_err(obj, o_obj, 1e-3) <= tol_o, prec
+        assert rel_err(gq, o_gq, 1e-2) <= tol_g, (prec, rel_err(gq, o_gq, 1e-2))
+        assert rel_err(gmu, o_gmu, 1e-2) <= tol_g, (prec, rel_err(gmu, o_gmu, 1e-2))
+
+
+def test_differentiation_config_central_differences_fp32():
+    """The FP32 adjoint at the differentiation configuration's M = 1e6 against
+    central differences (step 1e-4) of the FP64 objective on four of its points:
+    1e-4 relative (floor 1e-2 on the gradient's scale)."""
+    spec = W.grad_5d()
+    q = W.design_points(spec["n_points"], 5, seed=1)[:4]
+    M, h = spec["n_draws"], 1e-4
+    _, gq, gmu = gpu_grad(spec, q, M, "fp32")
+    for j in range(5):
+        qp, qm = q.copy(), q.copy()
+        qp[:, j] += h
+        qm[:, j] -= h
+        fd = (gpu_grad(spec, qp, M, "fp64")[0] - gpu_grad(spec, qm, M, "fp64")[0]) / (2 * h)
+        assert np.all(np.abs(gq[:, j] - fd) <= 1e-4 * np.maximum(np.abs(fd), 1e-2)), (j, gq[:, j], fd)
+    for i, key in enumerate(("mu_b0", "mu_b1")):
+        sp, sm = dict(spec), dict(spec)
+        sp[key] += h
+        sm[key] -= h
+        fd = (gpu_grad(sp, q, M, "fp64")[0] - gpu_grad(sm, q, M, "fp64")[0]) / (2 * h)
+        assert np.all(np.abs(gmu[:, i] - fd) <= 1e-4 * np.maximum(np.abs(fd), 1e-2)), (key, gmu[:, i], fd)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])

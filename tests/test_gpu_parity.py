@@ -232,61 +232,171 @@ def test_argmax_ties_and_nan():
         assert p.argmax(v)[0] == 1999
 
 
-# ------------------------------------------------------------ full-size configurations (sampled)
+# ------------------------------------------------------------ full-size configurations
 
-def _sampled_full(spec, prec, n_sample=6, M=None):
-    M = M or spec["n_draws"]
+def _gpu_full(spec, prec, M):
+    """Whole grid at M draws on the GPU: raw surface, smoothed surface, argmax."""
     with bmd.Problem(spec) as p:
         say(f"full-size eval d={spec['d']} G={p.G} M={M} {prec}")
         mean = p.eval_grid(M, prec)
         s = p.smooth(mean, prec)
         i, v, cell = p.argmax(s)
         mean_h, s_h = mean.cpu().numpy(), s.cpu().numpy()
-    G = mean_h.size
-    rng = np.random.default_rng(0)
-    gs = np.unique(np.concatenate([[0, G - 1], rng.integers(0, G, n_sample)]))
-    ref, _ = O.eval_grid(spec, gs, M)
-    assert_close(mean_h[gs], ref, prec, f"sampled d={spec['d']}")
     assert np.all(np.isfinite(mean_h)) and mean_h.min() >= 0.0 and mean_h.max() <= 1.0
-    assert i == int(np.argmax(s_h)) and v == s_h[i]
+    assert v == s_h[i]
     return mean_h, s_h, i
 
 
-def test_full_1d_config_both_precisions():
+def _block(spec, cell, radius=1, faces_only=False):
+    """Linear indices of the cells within `radius` of `cell` on every axis
+    (clipped at the grid's edges), or of the cell and its 2 d face neighbours."""
+    m = spec["m"]
+    if faces_only:
+        cells = [tuple(cell)]
+        for j in range(len(m)):
+            for s in (-1, 1):
+                c = list(cell)
+                c[j] += s
+                if 0 <= c[j] < m[j]:
+                    cells.append(tuple(c))
+    else:
+        axes = [range(max(0, c - radius), min(mj, c + radius + 1)) for c, mj in zip(cell, m)]
+        cells = list(np.array(np.meshgrid(*axes, indexing="ij")).reshape(len(m), -1).T)
+    return np.unique(np.array([np.ravel_multi_index(tuple(c), m) for c in cells], dtype=np.int64))
+
+
+def _strided(spec, step):
+    """Linear indices of the strided subgrid 0, step, 2 step, ... on every axis."""
+    m = spec["m"]
+    axes = [np.arange(0, mj, step) for mj in m]
+    cells = np.array(np.meshgrid(*axes, indexing="ij")).reshape(len(m), -1)
+    return np.ravel_multi_index(tuple(cells), m).astype(np.int64)
+
+
+def _in_tie_set(s_or, i, prec):
+    """The argmax rule: the GPU's cell is the oracle's, or inside the oracle's
+    near-tie set at the precision's tolerance."""
+    top = float(np.max(s_or))
+    return s_or[i] >= top - TOL[prec] * max(abs(top), 1e-3)
+
+
+def test_full_1d_config_against_oracle():
+    """1-D configuration as specified (201 cutoffs, M = 1e4): the oracle
+    evaluates every design, smooths its own surface and takes its argmax; the
+    GPU's raw surface must match element by element and its argmax must be the
+    oracle's (FP64) or inside the oracle's tie set (FP32)."""
     spec = W.plain_1d()
-    m64, s64, i64 = _sampled_full(spec, "fp64", n_sample=20)
-    m32, s32, i32 = _sampled_full(spec, "fp32", n_sample=20)
-    assert np.max(np.abs(m32 - m64)) < 1e-5
-    assert i64 == int(np.argmax(s64))
-    # FP32 argmax in the near-tie set of the FP64 smoothed surface
-    assert s64[i32] >= s64.max() - 2e-5
+    M = spec["n_draws"]
+    ref, _ = O.eval_grid(spec, np.arange(O.grid_size(spec)), M)
+    s_or = O.smooth_separable(spec, ref)
+    io = O.argmax(s_or)
+    for prec in ("fp64", "fp32"):
+        mean, s, i = _gpu_full(spec, prec, M)
+        assert_close(mean, ref, prec, "1-D raw surface")
+        assert np.max(np.abs(s - s_or) / np.maximum(np.abs(s_or), 1e-3)) <= TOL[prec]
+        if prec == "fp64":
+            assert i == io or _in_tie_set(s_or, i, prec), (i, io)
+        else:
+            assert _in_tie_set(s_or, i, prec), (i, io, s_or[i], s_or[io])
 
 
-def test_full_3d_config_fp64_sampled():
-    spec = W.plain_3d()
-    _sampled_full(spec, "fp64", n_sample=3, M=spec["n_draws"])
-
-
-def test_full_3d_config_fp32_as_benchmarked():
-    """The benchmarked launch (3-D 64^3, M = 1e5, FP32 integrand): sampled
-    designs against the oracle, the whole surface against the FP64 path within
-    1e-5, and the FP32 argmax inside the near-tie set of the FP64 smoothed
-    surface."""
-    spec = W.plain_3d()
-    m32, s32, i32 = _sampled_full(spec, "fp32", n_sample=3)
+@pytest.mark.parametrize("shape,seed", [((64, 64, 64), 11), ((24, 24, 24, 24, 24), 12)])
+def test_full_size_smoothing_and_argmax(shape, seed):
+    """Smoothing and argmax at the 3-D and 5-D configurations' grid sizes (64^3,
+    24^5): one seeded synthetic surface goes to both sides; FP64 within 1e-13,
+    FP32 within 2e-6 of the oracle's separable smoother, argmax identical (FP64)
+    or in the oracle's tie set (FP32)."""
+    spec = W.base_problem(len(shape), list(shape), 0.3, 0.03)
+    raw_h = W.noisy_surface(shape, seed=seed)
+    ref = O.smooth_separable(spec, raw_h)
+    io = O.argmax(ref)
     with bmd.Problem(spec) as p:
-        m64 = p.eval_grid(spec["n_draws"], "fp64")
-        s64 = p.smooth(m64, "fp64").cpu().numpy()
-        m64 = m64.cpu().numpy()
+        raw = torch.tensor(raw_h, dtype=torch.float64, device="cuda")
+        for prec in ("fp64", "fp32"):
+            say(f"smooth {shape} {prec}")
+            s = p.smooth(raw, prec)
+            i, v, cell = p.argmax(s)
+            s_h = s.cpu().numpy()
+            err = np.max(np.abs(s_h - ref))
+            if prec == "fp64":
+                assert err <= 1e-13, err
+                assert i == io, (i, io)
+            else:
+                assert err <= 2e-6 * np.max(np.abs(ref)), err
+                assert ref[i] >= ref[io] - 2e-6 * np.max(np.abs(ref)), (i, io)
+            assert tuple(cell) == tuple(np.unravel_index(i, shape))
+
+
+def test_full_3d_config_against_oracle():
+    """3-D configuration (64^3, M = 1e5) in both precisions, FP32 as benchmarked:
+      - the oracle on the 3^3 block around each precision's argmax at the full M;
+      - the oracle on the strided 16^3 subgrid (0, 4, ..., 60 per axis) at
+        M = 1,000 (the whole grid evaluated on the GPU at that M);
+      - the oracle on the whole grid at M = 16: its own smoothed surface's argmax
+        against the GPU's (identical in FP64, tie set in FP32);
+      - the FP32 surface against the FP64 surface within 1e-5 everywhere."""
+    spec = W.plain_3d()
+    M = spec["n_draws"]
+    full = {prec: _gpu_full(spec, prec, M) for prec in ("fp64", "fp32")}
+    cells = {prec: np.unravel_index(full[prec][2], spec["m"]) for prec in full}
+    blk = np.unique(np.concatenate([_block(spec, cells[prec]) for prec in full]))
+    say(f"oracle: {blk.size} designs around the argmax cells {cells} at M={M}")
+    ref, _ = O.eval_grid(spec, blk, M)
+    for prec in full:
+        assert_close(full[prec][0][blk], ref, prec, "3-D argmax block")
+        # the block's best raw design is the same on both sides
+        assert int(np.argmax(full[prec][0][blk])) == int(np.argmax(ref)) or \
+            np.max(ref) - ref[int(np.argmax(full[prec][0][blk]))] <= TOL[prec] * np.max(ref)
+    m64, s64, i64 = full["fp64"]
+    m32, s32, i32 = full["fp32"]
     assert np.max(np.abs(m32 - m64)) <= 1e-5
     assert np.max(np.abs(s32 - s64) / np.maximum(np.abs(s64), 1e-3)) <= 1e-5
-    assert s64[i32] >= s64.max() - 2e-5
+    assert s64[i32] >= s64.max() - 1e-5 * s64.max()
+
+    sub = _strided(spec, 4)
+    Ms = 1000
+    say(f"oracle: strided subgrid of {sub.size} designs at M={Ms}")
+    ref_s, _ = O.eval_grid(spec, sub, Ms)
+    for prec in ("fp64", "fp32"):
+        mean, _, _ = _gpu_full(spec, prec, Ms)
+        assert_close(mean[sub], ref_s, prec, "3-D strided subgrid")
+
+    Mt = 16
+    G = O.grid_size(spec)
+    say(f"oracle: whole grid of {G} designs at M={Mt}")
+    ref_t, _ = O.eval_grid(spec, np.arange(G), Mt)
+    s_or = O.smooth_separable(spec, ref_t)
+    io = O.argmax(s_or)
+    for prec in ("fp64", "fp32"):
+        mean, s, i = _gpu_full(spec, prec, Mt)
+        assert_close(mean, ref_t, prec, "3-D whole grid")
+        assert np.max(np.abs(s - s_or) / np.maximum(np.abs(s_or), 1e-3)) <= TOL[prec]
+        if prec == "fp64":
+            assert i == io or _in_tie_set(s_or, i, prec), (i, io)
+        else:
+            assert _in_tie_set(s_or, i, prec), (i, io)
 
 
-def test_full_5d_config_fp32_sampled():
-    """Precision form, 5-D: 24^5 designs, M = 2e5 draws, FP32 integrand."""
+def test_full_5d_config_against_oracle():
+    """5-D precision configuration (24^5, M = 2e5, FP32 integrand as
+    benchmarked): the oracle on the argmax cell and its ten face neighbours at
+    the full M, on the 3^5 block around it at M = 10,000, and on the strided 4^5
+    subgrid (0, 6, 12, 18 per axis) at M = 2,000, in both precisions."""
     spec = W.precision_5d()
-    _sampled_full(spec, "fp32", n_sample=2)
+    M = spec["n_draws"]
+    m32, s32, i32 = _gpu_full(spec, "fp32", M)
+    cell = np.unravel_index(i32, spec["m"])
+    faces = _block(spec, cell, faces_only=True)
+    say(f"oracle: argmax cell {cell} and face neighbours ({faces.size}) at M={M}")
+    ref, _ = O.eval_grid(spec, faces, M)
+    assert_close(m32[faces], ref, "fp32", "5-D argmax faces")
+    for Mr, idx, what in ((10_000, _block(spec, cell), "5-D argmax block"),
+                          (2_000, _strided(spec, 6), "5-D strided subgrid")):
+        say(f"oracle: {what} of {idx.size} designs at M={Mr}")
+        ref_r, _ = O.eval_grid(spec, idx, Mr)
+        for prec in ("fp64", "fp32"):
+            mean, _, _ = _gpu_full(spec, prec, Mr)
+            assert_close(mean[idx], ref_r, prec, what)
 
 
 @pytest.mark.parametrize("shape,rho", [((9, 7), 0.3), ((17, 6, 33), 0.3), ((3, 5, 3, 4, 3), 0.45), ((2, 3, 2, 3, 2, 3), 0.5)])

@@ -104,7 +104,7 @@ def test_differentiation_config_full_size():
     """4,096 points of the continuous 5-D design, M = 1,000,000 draws, FP32
     adjoint as benchmarked: checked against the FP64 adjoint on every point;
     then the first 64 points against the oracle's forward-mode gradients on the
-    first 4,000 draws, in both precisions."""
+    first 2,000 draws, in both precisions."""
     spec = W.grad_5d()
     q = W.design_points(spec["n_points"], 5, seed=1)
     M = spec["n_draws"]
@@ -113,7 +113,7 @@ def test_differentiation_config_full_size():
     assert rel_err(obj32, obj64, 1e-3) <= 1e-5
     assert rel_err(gq32, gq64, 1e-2) <= 1e-4
     assert rel_err(gmu32, gmu64, 1e-2) <= 1e-4
-    Mo, n = 4000, 64
+    Mo, n = 2000, 64
     say(f"oracle gradients: {n} points x {Mo} draws")
     o_obj, o_gq, o_gmu = O.grad_points(spec, q[:n], Mo)
     for prec, tol_o, tol_g in (("fp64", 1e-9, 1e-7), ("fp32", 1e-5, 2e-4)):

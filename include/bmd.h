@@ -41,6 +41,8 @@ extern "C" {
 
 #define BMD_ABI_VERSION 2
 #define BMD_MAX_DIM 6
+/* Size of the fixed device scratch of bmd_eval_grid_noalloc (128 MiB). */
+#define BMD_NOALLOC_SCRATCH_BYTES (128ull << 20)
 
 typedef struct bmd_problem bmd_problem;
 
@@ -187,6 +189,23 @@ int32_t bmd_sweep_kind(const bmd_problem *p);
  * ESTATE for continuous-design problems; ERANGE if n_draws is 0 or > 2^40. */
 bmd_status bmd_eval_grid(bmd_problem *p, uint64_t n_draws, int32_t prec,
                          double *d_mean, double *d_var, void *stream);
+
+/* bmd_eval_grid for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments and results: the same kernels on the same draws, so d_mean
+ * and d_var equal bmd_eval_grid's bit for bit.  The draws and per-slice
+ * partial sums go to a fixed device array of BMD_NOALLOC_SCRATCH_BYTES that
+ * the library holds on each device it runs on until the process ends (its
+ * address is looked up once per device by bmd_create_problem); this call
+ * makes no allocation and no library call that allocates.  ERANGE when the
+ * sweep needs more than the scratch: draws take about
+ * M (d K + 12) * 4 bytes in FP32 (8 in FP64, K = bmd_gh_nodes) plus
+ * 16 G bytes per draw slice (about ten slices at G = 64^3).  Every call on a
+ * device shares that device's scratch: calls that overlap in time on one
+ * device (different streams, or several host threads) race and give wrong
+ * results; calls ordered on one stream are safe. */
+bmd_status bmd_eval_grid_noalloc(bmd_problem *p, uint64_t n_draws, int32_t prec,
+                                 double *d_mean, double *d_var, void *stream);
 
 /* Nadaraya-Watson smoothing with the product Gaussian kernel
  * K(g,h) = prod_j exp(-((q_j(g) - q_j(h)) / b_j)^2 / 2), untruncated, applied

@@ -67,6 +67,8 @@ SIGNATURES = {
     "bmd_sweep_kind": (ctypes.c_int32, [ctypes.c_void_p]),
     "bmd_eval_grid": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "bmd_eval_grid_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p]),
     "bmd_smooth": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "bmd_argmax": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_void_p]),
@@ -212,7 +214,12 @@ class Problem:
         self.close()
 
     # -- entry points ---------------------------------------------------------
-    def eval_grid(self, n_draws: int, precision="fp64", want_var=False, out=None, out_var=None, stream=None):
+    def eval_grid(self, n_draws: int, precision="fp64", want_var=False, out=None, out_var=None, stream=None,
+                  noalloc=False):
+        """Monte Carlo power at every design (bmd_eval_grid).  noalloc: the
+        variant that keeps its workspace in the library's fixed device scratch
+        (bmd_eval_grid_noalloc); the outputs are still allocated here unless
+        given."""
         import torch
         if out is not None:
             mean = _device_buffer(out, self.G, self.device, "out")
@@ -226,9 +233,9 @@ class Problem:
                     raise ValueError("out and out_var must be different buffers")
             else:
                 var = torch.empty(self.G, dtype=torch.float64, device=self.device)
-        _check(library().bmd_eval_grid(self._h, int(n_draws), _prec(precision), ctypes.c_void_p(mean.data_ptr()),
-                                       ctypes.c_void_p(var.data_ptr()) if var is not None else None,
-                                       _stream(stream)))
+        fn = library().bmd_eval_grid_noalloc if noalloc else library().bmd_eval_grid
+        _check(fn(self._h, int(n_draws), _prec(precision), ctypes.c_void_p(mean.data_ptr()),
+                  ctypes.c_void_p(var.data_ptr()) if var is not None else None, _stream(stream)))
         return (mean, var) if want_var else mean
 
     def smooth(self, surface, precision="fp64", out=None, stream=None):

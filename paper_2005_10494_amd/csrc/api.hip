@@ -26,9 +26,37 @@ hipError_t launch_levels_golden(const bmd_problem* p, int phase, bool probe, int
 
 using namespace bmd;
 
+// Fixed device workspace of bmd_eval_grid_noalloc: the draw arrays and the
+// per-slice partial sums of one sweep.  Each device holds its own copy for the
+// life of the process; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (scratch_ptr), never by name.
+static __device__ __align__(256) char scratch[BMD_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_err;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Look up this device's copy of `scratch` once (the device must be current).
+hipError_t scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+void* scratch_ptr(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 
 bmd_status fail(bmd_status st, const char* fmt, ...) {
     char buf[512];
@@ -307,6 +335,25 @@ void mark(bmd_problem* p, int i, hipStream_t s) {
     p->ev_used[i / 2] = true;
 }
 
+// The sweep of bmd_eval_grid into workspace ws: draws at ws, per-slice
+// partial sums at ws + draw_bytes (every slice writes all its designs, so
+// nothing needs clearing first).
+bmd_status eval_grid_into(bmd_problem* p, int prec, int64_t M, int64_t n_slices, int64_t slice_len, void* ws,
+                          size_t draw_bytes, double* d_mean, double* d_var, hipStream_t s) {
+    double* partials = reinterpret_cast<double*>(static_cast<char*>(ws) + draw_bytes);
+    mark(p, 0, s);
+    HIP_TRY(launch_draws(p, prec, 0, M, ws, s), "draw kernel");
+    mark(p, 1, s);
+    mark(p, 2, s);
+    HIP_TRY(launch_eval_grid(p, prec, M, ws, partials, static_cast<int>(n_slices), slice_len, d_var != nullptr, s),
+            "eval kernel");
+    mark(p, 3, s);
+    mark(p, 4, s);
+    HIP_TRY(launch_finalize(p, M, partials, static_cast<int>(n_slices), d_mean, d_var, s), "finalize kernel");
+    mark(p, 5, s);
+    return BMD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -345,6 +392,12 @@ bmd_status bmd_create_problem(const bmd_problem_desc* desc, bmd_problem** out, v
         p->n_cu < 1) {
         (void)hipGetLastError();
         p->n_cu = 1;
+    }
+    // set-up of the no-allocation sweep: this device's scratch address
+    if (const hipError_t e = scratch_setup(p->device); e != hipSuccess) {
+        delete p;
+        (void)hipGetLastError();
+        return hip_fail(e, "scratch address (hipGetSymbolAddress)");
     }
     DevProblem& P = p->P;
     std::memset(&P, 0, sizeof P);
@@ -544,18 +597,30 @@ bmd_status bmd_eval_grid(bmd_problem* p, uint64_t n_draws, int32_t prec, double*
     const size_t part_bytes = sizeof(double) * 2 * static_cast<size_t>(G) * n_slices;
     bmd_status st = ensure(&p->d_ws, &p->ws_cap, draw_bytes + part_bytes);
     if (st != BMD_OK) return st;
-    double* partials = reinterpret_cast<double*>(static_cast<char*>(p->d_ws) + draw_bytes);
-    mark(p, 0, s);
-    HIP_TRY(launch_draws(p, prec, 0, M, p->d_ws, s), "draw kernel");
-    mark(p, 1, s);
-    mark(p, 2, s);
-    HIP_TRY(launch_eval_grid(p, prec, M, p->d_ws, partials, static_cast<int>(n_slices), slice_len, d_var != nullptr, s),
-            "eval kernel");
-    mark(p, 3, s);
-    mark(p, 4, s);
-    HIP_TRY(launch_finalize(p, M, partials, static_cast<int>(n_slices), d_mean, d_var, s), "finalize kernel");
-    mark(p, 5, s);
-    return BMD_OK;
+    return eval_grid_into(p, prec, M, n_slices, slice_len, p->d_ws, draw_bytes, d_mean, d_var, s);
+}
+
+bmd_status bmd_eval_grid_noalloc(bmd_problem* p, uint64_t n_draws, int32_t prec, double* d_mean, double* d_var,
+                                 void* stream) {
+    g_err.clear();
+    if (!p) return fail(BMD_EINVAL, "problem is NULL");
+    if (!p->grid) return fail(BMD_ESTATE, "eval_grid_noalloc needs a grid problem");
+    if (!valid_prec(prec)) return fail(BMD_EINVAL, "unknown precision %d", prec);
+    if (!d_mean) return fail(BMD_EINVAL, "d_mean is NULL");
+    if (n_draws == 0 || n_draws > (1ull << 40)) return fail(BMD_ERANGE, "n_draws must be in [1, 2^40]");
+    DeviceGuard guard(p->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t M = static_cast<int64_t>(n_draws);
+    int64_t n_slices = 0, slice_len = 0;
+    sweep_slices(p, prec, M, &n_slices, &slice_len);
+    const size_t draw_bytes = (draw_workspace_bytes(p, prec, M) + 255) / 256 * 256;
+    const size_t part_bytes = sizeof(double) * 2 * static_cast<size_t>(p->P.G) * n_slices;
+    if (draw_bytes + part_bytes > BMD_NOALLOC_SCRATCH_BYTES)
+        return fail(BMD_ERANGE, "workspace of %zu bytes (draws %zu, partial sums %zu) exceeds the %zu-byte scratch",
+                    draw_bytes + part_bytes, draw_bytes, part_bytes, static_cast<size_t>(BMD_NOALLOC_SCRATCH_BYTES));
+    void* ws = scratch_ptr(p->device);
+    if (!ws) return fail(BMD_EDEVICE, "no scratch address for device %d", p->device);
+    return eval_grid_into(p, prec, M, n_slices, slice_len, ws, draw_bytes, d_mean, d_var, s);
 }
 
 bmd_status bmd_optimize_levels(bmd_problem* p, uint64_t n_draws, int32_t prec, double a_lo, double a_hi,

@@ -98,13 +98,18 @@ def workload(name: str) -> dict:
 
 # --------------------------------------------------------------- algorithmic work
 # Floating-point operations per (design, draw) evaluation, as the method needs
-# them (transcendentals count as one operation each):
-#   drift and thresholds                    6
-#   bivariate normal: 2 Phi (3 each) + h k, (h^2+k^2)/2 (4) + combine (3)  13
-#     plus 6 per Gauss-Legendre node (exponent 3, exp 1, weighted sum 2)
-#   summand and FP64 sums (1 - p, s1, s2)    4
-#   responder-in-subgroup overlap O, only when the design's cutoffs are on
-#     both sides of the drawn true cutoffs: d flops per Gauss-Hermite node.
+# them (transcendentals count as one operation each), split by the unit that
+# executes them in the matrix-core sweep:
+#   vector units (VALU):
+#     drift and thresholds                    6
+#     bivariate normal: 2 Phi (3 each) + h k, (h^2+k^2)/2 (4) + combine (3)  13
+#       plus 6 per Gauss-Legendre node (exponent 3, exp 1, weighted sum 2)
+#     summand and FP64 sums (1 - p, s1, s2)    4
+#   matrix cores (MFMA): the responder-in-subgroup overlap O, only when the
+#     design's cutoffs are on both sides of the drawn true cutoffs: d flops per
+#     Gauss-Hermite node (the products over axes and the sum over nodes).
+PEAK_MFMA_FP32_TFLOPS = 157.3     # published dense FP32 matrix-core peak
+
 
 def bvn_nodes(rho: np.ndarray, prec: str) -> np.ndarray:
     if prec == "fp64":
@@ -114,16 +119,18 @@ def bvn_nodes(rho: np.ndarray, prec: str) -> np.ndarray:
     return np.asarray(counts)[np.searchsorted(edges, rho, side="right")]
 
 
-def algorithmic_flops(spec: dict, r: np.ndarray, tau: np.ndarray, prec: str, K: int) -> float:
-    """Total flops of one sweep launch (all designs x all draws)."""
-    G = r.size
+def algorithmic_flops(spec: dict, r: np.ndarray, tau: np.ndarray, prec: str, K: int):
+    """Flops of one sweep launch (all designs x all draws): (vector part,
+    overlap part)."""
     M = tau.shape[0]
     n = bvn_nodes(np.sqrt(r), prec)
     per_design = 23.0 + 6.0 * n
-    total = float(per_design.sum()) * M
+    valu = float(per_design.sum()) * M
+    overlap = 0.0
     d = spec["d"]
     if d >= 2 and spec["effect"] == "step":
         m = spec["m"]
+        G = r.size
         # T_j(k) = number of grid cutoffs at or below the drawn tau_j
         T = np.zeros((M, d), dtype=np.int64)
         for j in range(d):
@@ -133,8 +140,8 @@ def algorithmic_flops(spec: dict, r: np.ndarray, tau: np.ndarray, prec: str, K: 
         above = np.prod(np.asarray(m)[None, :] - T, axis=1)   # all cutoffs above tau
         below = np.prod(T, axis=1)                             # all below
         mixed = G - above - below
-        total += float(mixed.sum()) * d * K
-    return total
+        overlap = float(mixed.sum()) * d * K
+    return valu, overlap
 
 
 # --------------------------------------------------------------- GPU steps
@@ -257,8 +264,8 @@ def main():
     d = spec["d"]
     _, f = p32.draws(0, M)
     tau = f[:, 5:5 + d].cpu().numpy()
-    flops32 = algorithmic_flops(spec, r, tau, "fp32", _gh_nodes(p32, "fp32"))
-    achieved = flops32 / (sweep32 * 1e-3) / 1e12
+    valu32, over32 = algorithmic_flops(spec, r, tau, "fp32", _gh_nodes(p32, "fp32"))
+    achieved = valu32 / (sweep32 * 1e-3) / 1e12
     kind = bmd.sweep_kind(p32)
     summary = f"k_eval_mfma_{d}d_{spec['m'][0]}cube_M{M // 1000}k_counters.md"
     kname = "k_eval_" + ("mfma" if kind == "matrix" else "direct") + "<%s, " + str(d) + ", %d, false>"
@@ -267,18 +274,25 @@ def main():
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                        "frac": achieved / PEAK_FP32_TFLOPS, "traffic": cnt32.get("traffic"),
                        "traffic_unit": "bytes per launch (HBM, counter-measured)",
+                       "numerator": "vector-unit flops of the launch (bivariate normal, drifts, sums); the "
+                                    "overlap sums run on the matrix cores and are reported under 'mfma'",
                        "valu_issue_fill": cnt32.get("valu_issue_fill"),
                        "valu_busy_pct": cnt32.get("valu_busy_pct"),
                        "kernel": SWEEP_KERNEL[kind] % d,
-                       "sweep_ms": sweep32, "flops_per_launch": flops32,
+                       "sweep_ms": sweep32, "flops_per_launch": valu32,
                        "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
                        "frac_unpacked": achieved / PEAK_FP32_UNPACKED_TFLOPS,
                        "sweep_evals_per_s": evals / (sweep32 * 1e-3)}
+    if kind == "matrix":
+        mf = over32 / (sweep32 * 1e-3) / 1e12
+        out["roofline"]["mfma"] = {"achieved": mf, "peak": PEAK_MFMA_FP32_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": mf / PEAK_MFMA_FP32_TFLOPS, "flops_per_launch": over32}
     out["phases_ms"] = ph32
 
     if not args.no_fp64:
         t64, sweep64, ph64, res64 = run_steps(spec, "fp64", args.steps, args.warmup)
-        flops64 = algorithmic_flops(spec, r, tau, "fp64", _gh_nodes(res64["problem"], "fp64"))
+        valu64, _ = algorithmic_flops(spec, r, tau, "fp64", _gh_nodes(res64["problem"], "fp64"))
+        flops64 = valu64
         m32, m64 = res32["mean"], res64["mean"]
         s32, s64 = res32["smooth"], res64["smooth"]
         out["fp64"] = {"value": evals * args.steps / t64, "ms_per_step": 1e3 * t64 / args.steps,

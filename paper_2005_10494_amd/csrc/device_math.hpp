@@ -85,22 +85,24 @@ __device__ __forceinline__ double affine_uniform(double lo, double hi, double u)
 // Univariate normal
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double norm_cdf(double x) { return 0.5 * erfc(-x * 0.70710678118654752440); }
-// Single precision: Phi(-|x|) = r' 2^(c_0 + P(v) - y^2) with y = |x| sqrt(log2(e)/2),
-// r' = 1/(y + 2 sqrt(log2 e)) (the hardware reciprocal, within one ulp) and
-// v = y r' = z/(2+z), z = |x|/sqrt 2; P and c_0 from normal_cdf_fit.hpp (max abs
-// error 1.6e-7, unbiased), signed as 1/2 + copysign(1/2 - Phi(-|x|), x).  One
-// reciprocal, one exp2 and sixteen full-rate operations.  x must be finite: beyond |x| = 14.8 the exponent underflows and
-// Phi saturates to 0 or 1.
-__device__ __forceinline__ float norm_cdf(float x) {
-    const float y = fabsf(x) * kPhiScale;
-    const float r = __builtin_amdgcn_rcpf(y + kPhiShift);
-    const float v = y * r;
+// Single precision, argument prescaled: for xs = x sqrt(log2(e)/2) and
+// y = |xs|, Phi(-|x|) = r' 2^(P(r') - y^2) with r' = 1/(y + 2 sqrt(log2 e))
+// (the hardware reciprocal, within one ulp) and P the degree-7 fit of
+// normal_cdf_fit.hpp in r' itself (tail relative error within 3e-6 while the
+// tail exceeds 1e-9, max abs error of Phi 5.6e-7, unbiased), signed as
+// 1/2 + copysign(1/2 - Phi(-|x|), x).  One reciprocal, one exp2 and twelve
+// full-rate operations.  Callers that can fold the factor into constants they
+// already hold pass xs directly.  xs must be finite: beyond |x| = 14.8 the
+// exponent underflows and Phi saturates to 0 or 1.
+__device__ __forceinline__ float norm_cdf_scaled(float xs) {
+    const float r = __builtin_amdgcn_rcpf(fabsf(xs) + kPhiShift);
     float p = kPhiFit[kPhiFitDeg];
 #pragma unroll
-    for (int i = kPhiFitDeg - 1; i >= 0; --i) p = fmaf(p, v, kPhiFit[i]);
-    const float t = fmaf(-r, __builtin_amdgcn_exp2f(fmaf(-y, y, p)), 0.5f);   // 1/2 - Phi(-|x|)
-    return 0.5f + __builtin_copysignf(t, x);
+    for (int i = kPhiFitDeg - 1; i >= 0; --i) p = fmaf(p, r, kPhiFit[i]);
+    const float t = fmaf(-r, __builtin_amdgcn_exp2f(fmaf(-xs, xs, p)), 0.5f);   // 1/2 - Phi(-|x|)
+    return 0.5f + __builtin_copysignf(t, xs);
 }
+__device__ __forceinline__ float norm_cdf(float x) { return norm_cdf_scaled(x * kPhiScale); }
 __device__ __forceinline__ double norm_pdf(double x) { return 0.39894228040143267794 * exp(-0.5 * x * x); }
 __device__ __forceinline__ float norm_pdf(float x) {
     return 0.39894228040143267794f * __builtin_amdgcn_exp2f(-0.72134752044448170368f * x * x);
@@ -154,10 +156,10 @@ struct BvnConst {
     T a[NMAX], b[NMAX];
     T scale;  // asin(rho) / (4 pi)
 
-    // gl: packed table; n: wave-uniform rule size (<= NMAX).
+    // gl: packed table; n: wave-uniform rule size (<= NMAX).  FP32 evaluates
+    // exp2 on arguments prescaled by sqrt(log2(e)/2) (norm_cdf_scaled's), so
+    // its exponent coefficients become 1/(1 - s^2) and 2 s/(1 - s^2).
     __device__ __forceinline__ void init(double rho, int n, const double* __restrict__ gl) {
-        // FP32 evaluates exp2, so its exponent coefficients carry log2(e).
-        const double L = sizeof(T) == 4 ? 1.4426950408889634074 : 1.0;
         const double th = asin(rho);
         scale = static_cast<T>(th * 0.079577471545947667884);  // 1/(4 pi)
         const double* x = gl + gl_offset(n);
@@ -166,8 +168,8 @@ struct BvnConst {
             if (i < n) {
                 const double s = sin(0.5 * th * (1.0 + x[i]));
                 const double ai = 1.0 / ((1.0 - s) * (1.0 + s));
-                a[i] = static_cast<T>(0.5 * L * ai);
-                b[i] = static_cast<T>(L * s * ai);
+                a[i] = static_cast<T>(sizeof(T) == 4 ? ai : 0.5 * ai);
+                b[i] = static_cast<T>(sizeof(T) == 4 ? 2.0 * s * ai : s * ai);
             } else {
                 a[i] = T(0);
                 b[i] = T(0);
@@ -176,9 +178,9 @@ struct BvnConst {
     }
 };
 
-// Node sum  sum_{i<n} w_i exp(b_i hk - a_i hs)  (FP32: exp2 with log2(e)
-// folded into a_i, b_i).  Every rule size is even and n is wave-uniform, so
-// the nodes go in pairs behind a scalar exit test, unrolled by template
+// Node sum  sum_{i<n} w_i exp(b_i hk - a_i hs)  (FP32: exp2 of prescaled
+// arguments, log2(e) folded into a_i, b_i).  Every rule size is even and n is
+// wave-uniform, so the nodes go in pairs behind a scalar exit test, unrolled by template
 // recursion: only n nodes are evaluated and every coefficient index is a
 // compile-time constant (registers, no indexed scratch).  (A guard per node in
 // a loop is if-converted into evaluating all NMAX exponentials; a loop with an
@@ -227,10 +229,15 @@ struct BvnWeights {
     __device__ __forceinline__ float operator[](int i) const { return w[i]; }
 };
 
+// Arguments prescaled by sqrt(log2(e)/2) (kPhiScale), as norm_cdf_scaled.
+template <int NMAX, typename W>
+__device__ __forceinline__ float bvn_cdf_scaled(float h, float k, const BvnConst<float, NMAX>& c, const W& w, int n) {
+    const float hk = h * k, hs = fmaf(h, h, k * k);
+    return fmaf(norm_cdf_scaled(h), norm_cdf_scaled(k), c.scale * bvn_node_sum(n, hk, hs, c, w));
+}
 template <int NMAX, typename W>
 __device__ __forceinline__ float bvn_cdf(float h, float k, const BvnConst<float, NMAX>& c, const W& w, int n) {
-    const float hk = h * k, hs = fmaf(h, h, k * k);
-    return fmaf(norm_cdf(h), norm_cdf(k), c.scale * bvn_node_sum(n, hk, hs, c, w));
+    return bvn_cdf_scaled(h * kPhiScale, k * kPhiScale, c, w, n);
 }
 
 // Upper complement 1 - Phi_2(h, k; rho) = (1 - scale S) - Phi(h) Phi(k), S the
@@ -242,9 +249,13 @@ __device__ __forceinline__ double bvn_sf(double h, double k, const BvnConst<doub
     return fma(-norm_cdf(h), norm_cdf(k), fma(-c.scale, bvn_node_sum(n, hk, hs, c, w), 1.0));
 }
 template <int NMAX, typename W>
-__device__ __forceinline__ float bvn_sf(float h, float k, const BvnConst<float, NMAX>& c, const W& w, int n) {
+__device__ __forceinline__ float bvn_sf_scaled(float h, float k, const BvnConst<float, NMAX>& c, const W& w, int n) {
     const float hk = h * k, hs = fmaf(h, h, k * k);
-    return fmaf(-norm_cdf(h), norm_cdf(k), fmaf(-c.scale, bvn_node_sum(n, hk, hs, c, w), 1.0f));
+    return fmaf(-norm_cdf_scaled(h), norm_cdf_scaled(k), fmaf(-c.scale, bvn_node_sum(n, hk, hs, c, w), 1.0f));
+}
+template <int NMAX, typename W>
+__device__ __forceinline__ float bvn_sf(float h, float k, const BvnConst<float, NMAX>& c, const W& w, int n) {
+    return bvn_sf_scaled(h * kPhiScale, k * kPhiScale, c, w, n);
 }
 
 // Row of the 16x16 result held in accumulator element v of a lane in quarter

@@ -48,6 +48,9 @@ struct DesignState {
     int n;                 // Gauss-Legendre nodes (wave-uniform)
     const T* w;            // their weights
     T z1, z2, srI, invr, rT, omq, c0, c1, c2;
+    // FP32 matrix-core sweep: the critical values and drift factors times
+    // sqrt(log2(e)/2), so the bivariate normal's arguments arrive prescaled
+    T z1s, z2s, a0s, a1s;
 
     __device__ void init(const DevProblem& P, int64_t g, const double* __restrict__ r_arr,
                          const double* __restrict__ z1_arr, const double* __restrict__ z2_arr,
@@ -71,6 +74,13 @@ struct DesignState {
         invr = static_cast<T>(1.0 / r);
         rT = static_cast<T>(r);
         omq = static_cast<T>(1.0 - q[0]);
+        {
+            const double sc = static_cast<double>(kPhiScale);
+            z1s = static_cast<T>(sc * z1_arr[g]);
+            z2s = static_cast<T>(sc * z2_arr[g]);
+            a0s = static_cast<T>(sc * srI_d);
+            a1s = static_cast<T>(sc * srI_d / r);
+        }
         c0 = c1 = c2 = T(0);
         if (P.effect == BMD_EFFECT_PAPER_GAUSS) {
             const double th2 = -log1p(-(P.paper_a - P.paper_b * r));

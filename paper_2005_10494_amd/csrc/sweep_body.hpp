@@ -272,18 +272,44 @@ __device__ __forceinline__ void mfma_tile_body(const EvalArgs<T>& a, const MfmaG
         // read, and its quads go to the other buffer.
         if (k0 + CH < ke) stage(k0 + CH, static_cast<int>(min<int64_t>(CH, ke - k0 - CH)), sq0 + (buf ^ 1) * CH);
         // phase B: bivariate normal part for this thread's design
-#pragma unroll 2
-        for (int i = 0; i < nk; ++i) {
+        const auto summand = [&](int i) -> T {
             const T O = sO[static_cast<size_t>(i) * kEvalBlock + tid];
             const Quad<T> dq = sq[i];
-            const T mu2 = st.srI * (dq.x + dq.y * O * st.invr);
-            const T h = st.z1 - dq.z, kq2 = st.z2 - mu2;
-            T sv;   // 1 - P(both statistics below their critical values)
-            if (a.P.zinf == 0) sv = bvn_sf<NMAX>(h, kq2, st.bc, wts, st.n);
-            else if (a.P.zinf == 1) sv = T(1) - norm_cdf(kq2);
-            else if (a.P.zinf == 2) sv = T(1) - norm_cdf(h);
-            else sv = T(0);
-            const double v = static_cast<double>(sv);
+            if constexpr (sizeof(T) == 4) {
+                // arguments times sqrt(log2(e)/2):  h = z1 - mu1,
+                // k = z2 - sqrt(r I) (b0 + b1 O / r)
+                const float h = fmaf(dq.z, -kPhiScale, st.z1s);
+                const float kq2 = fmaf(-st.a1s, dq.y * O, fmaf(-st.a0s, dq.x, st.z2s));
+                if (a.P.zinf == 0) return bvn_sf_scaled<NMAX>(h, kq2, st.bc, wts, st.n);
+                if (a.P.zinf == 1) return 1.0f - norm_cdf_scaled(kq2);
+                if (a.P.zinf == 2) return 1.0f - norm_cdf_scaled(h);
+                return 0.0f;
+            } else {
+                const T mu2 = st.srI * (dq.x + dq.y * O * st.invr);
+                const T h = st.z1 - dq.z, kq2 = st.z2 - mu2;
+                // 1 - P(both statistics below their critical values)
+                if (a.P.zinf == 0) return bvn_sf<NMAX>(h, kq2, st.bc, wts, st.n);
+                if (a.P.zinf == 1) return T(1) - norm_cdf(kq2);
+                if (a.P.zinf == 2) return T(1) - norm_cdf(h);
+                return T(0);
+            }
+        };
+        int i = 0;
+        for (; i + 1 < nk; i += 2) {
+            const T v0 = summand(i), v1 = summand(i + 1);
+            if constexpr (sizeof(T) == 4 && !VAR) {
+                s1 += static_cast<double>(v0 + v1);   // pairs of draws summed in FP32 first
+            } else {
+                s1 += static_cast<double>(v0);
+                s1 += static_cast<double>(v1);
+                if constexpr (VAR) {
+                    s2 = fma(static_cast<double>(v0), static_cast<double>(v0), s2);
+                    s2 = fma(static_cast<double>(v1), static_cast<double>(v1), s2);
+                }
+            }
+        }
+        if (i < nk) {
+            const double v = static_cast<double>(summand(i));
             s1 += v;
             if constexpr (VAR) s2 = fma(v, v, s2);
         }

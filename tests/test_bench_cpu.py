@@ -63,10 +63,11 @@ def test_algorithmic_flops_one_biomarker():
     spec = {"d": 1, "m": [4], "effect": "step", "q_lo": 0.05, "q_hi": 0.95}
     r = np.array([0.04, 0.2, 0.5, 0.8, 0.87, 0.93])   # rho = 0.2, 0.447, 0.707, 0.894, 0.933, 0.964
     tau = np.full((10, 1), 0.5)
-    f32 = bench.algorithmic_flops(spec, r, tau, "fp32", 4)
-    f64 = bench.algorithmic_flops(spec, r, tau, "fp64", 4)
+    f32, o32 = bench.algorithmic_flops(spec, r, tau, "fp32", 4)
+    f64, o64 = bench.algorithmic_flops(spec, r, tau, "fp64", 4)
     assert f32 == 10 * sum(23 + 6 * n for n in (4, 4, 6, 8, 10, 12))
     assert f64 == 10 * sum(23 + 6 * n for n in (6, 8, 12, 16, 20, 24))
+    assert o32 == 0.0 and o64 == 0.0
 
 
 def test_algorithmic_flops_overlap_counts_mixed_designs_only():
@@ -76,6 +77,8 @@ def test_algorithmic_flops_overlap_counts_mixed_designs_only():
     r = np.full(4, 0.01)                     # rho = 0.1: 4 FP32 nodes
     tau = np.array([[0.5, 0.5]])
     K = 8
-    f = bench.algorithmic_flops(spec, r, tau, "fp32", K)
-    # grid q in {0.25, 0.75}^2: (0.25, 0.75) and (0.75, 0.25) are mixed
-    assert f == 4 * (23 + 6 * 4) + 2 * 2 * K
+    f, o = bench.algorithmic_flops(spec, r, tau, "fp32", K)
+    # grid q in {0.25, 0.75}^2: (0.25, 0.75) and (0.75, 0.25) are mixed; their
+    # overlap sums run on the matrix cores and are counted apart
+    assert f == 4 * (23 + 6 * 4)
+    assert o == 2 * 2 * K

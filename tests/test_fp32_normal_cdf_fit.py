@@ -1,9 +1,12 @@
 """The single-precision normal CDF of the FP32 integrand (fitted tail form,
 coefficients in csrc/normal_cdf_fit.hpp), replayed on the CPU operation by
 operation in single precision (the hardware reciprocal taken one ulp off) and
-checked against scipy's double-precision ndtr: absolute error within 1.6e-7
-everywhere, no bias, symmetric to one rounding; the fitted tail itself is
-relatively accurate."""
+checked against scipy's double-precision ndtr.  The bound the fit must meet
+comes from the FP32 objective bar (1e-5 max(f, 1e-3) per design): a relative
+error e of the tail Phi(-|x|) moves a summand 1 - Phi_2 by at most 2 e of
+itself, so e <= 3e-6 wherever the tail is above 1e-9 (|x| <= 6) keeps every
+design inside the bar; further out the tail's contribution is below 1e-13.
+Also: absolute error within 6e-7, no bias, symmetric to one rounding."""
 import importlib.util
 import os
 import re
@@ -33,7 +36,7 @@ def test_fit_header_matches_generator_degree():
     gen = _generator()
     c = _header_coefficients()
     assert c.size == gen.DEG + 1
-    assert c[0] == np.float32(0.5 * np.log2(gen.L2E))   # log2(sqrt(log2 e)): the folded scale
+    assert np.array_equal(c, gen.fit())   # the header is the generator's output
 
 
 def test_fp32_normal_cdf_accuracy_and_bias():
@@ -45,22 +48,27 @@ def test_fp32_normal_cdf_accuracy_and_bias():
     got = np.array([float(gen.phi32(x, c)) for x in xs])
     ref = scipy_special.ndtr(xs.astype(np.float64))
     err = got - ref
-    assert np.abs(err).max() <= 1.6e-7
+    assert np.abs(err).max() <= 6e-7
     assert abs(err.mean()) <= 2e-9
     # the signed value 1/2 + copysign(1/2 - tail, x) is symmetric to one rounding
     neg = np.array([float(gen.phi32(-x, c)) for x in xs])
     assert np.abs(got + neg - 1.0).max() <= 6e-8
     # saturation, and Phi(0) = 1/2
     assert float(gen.phi32(np.float32(40.0), c)) == 1.0 and float(gen.phi32(np.float32(-40.0), c)) == 0.0
-    assert abs(float(gen.phi32(np.float32(0.0), c)) - 0.5) <= 6e-8
+    assert abs(float(gen.phi32(np.float32(0.0), c)) - 0.5) <= 1.2e-7
 
 
 def test_fp32_normal_tail_relative_accuracy():
-    """The fitted tail r' 2^e itself keeps relative accuracy wherever Phi(-|x|)
-    is a normal float (the signed CDF keeps absolute accuracy only)."""
+    """The fitted tail r' 2^e keeps the relative accuracy the objective bar
+    needs (3e-6) while the tail is above 1e-9, and stays relatively accurate
+    (FP32 rounding of y^2 dominating) wherever Phi(-|x|) is a normal float."""
     scipy_special = pytest.importorskip("scipy.special")
     gen = _generator()
     c = _header_coefficients()
+    xs = np.linspace(-6.0, 0.0, 6001).astype(np.float32)
+    got = np.array([float(gen.tail32(x, c)) for x in xs])
+    ref = scipy_special.ndtr(xs.astype(np.float64))
+    assert np.all(np.abs(got - ref) <= 3e-6 * ref)
     xs = np.linspace(-13.0, 0.0, 6001).astype(np.float32)
     got = np.array([float(gen.tail32(x, c)) for x in xs])
     ref = scipy_special.ndtr(xs.astype(np.float64))

@@ -205,7 +205,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="3d", choices=["3d", "1d", "5d", "alpha", "alpha3", "levels", "grad", "refine", "batch"])
+    ap.add_argument("--workload", default="3d", choices=["3d", "1d", "5d", "alpha", "alpha3", "alpha4", "levels", "grad", "refine", "batch"])
     ap.add_argument("--batch-scale", type=float, default=1.0,
                     help="batch workload only: scale of the per-axis grids and of the draw range (1 = full size)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -240,6 +240,8 @@ def main():
         return bench_refine(args)
     if args.workload == "alpha3":
         return bench_alpha3(args)
+    if args.workload == "alpha4":
+        return bench_alpha4(args)
     if args.workload == "levels":
         return bench_levels(args)
     if args.workload == "batch":
@@ -370,14 +372,25 @@ def bench_grad(args):
 
 def bench_alpha3(args):
     """Three nested populations (Sec. 3, condition (c)): the 97 x 97 grid of
-    levels (alpha_1, alpha_2), alpha_3 on the FWER boundary, M = 1e5 draws;
-    a step is problem set-up (critical values) + draws + sweep + smoothing
-    over the designs that have a third level + argmax over them.  FP32 and
-    FP64."""
+    levels (alpha_1, alpha_2), alpha_3 on the FWER boundary, M = 1e5 draws."""
+    return bench_nested(args, 3)
+
+
+def bench_alpha4(args):
+    """Four nested populations (Sec. 3's three-threshold designs, condition
+    (c)'s effects): the 25^3 grid of levels (alpha_1, alpha_2, alpha_3),
+    alpha_4 on the FWER boundary, M = 1e5 draws."""
+    return bench_nested(args, 4)
+
+
+def bench_nested(args, n):
+    """n nested populations: a step is problem set-up (critical values) +
+    draws + sweep + smoothing over the designs that have a last level +
+    argmax over them.  FP32 and FP64."""
     import torch
     import paper_2005_10494_amd as bmd
     from paper_2005_10494_amd import workloads as W
-    spec = W.alpha3_grid()
+    spec = W.alpha3_grid() if n == 3 else W.alpha4_grid()
     M, G = spec["n_draws"], int(np.prod(spec["m"]))
     res = {}
     for prec in ("fp32", "fp64"):
@@ -396,36 +409,54 @@ def bench_alpha3(args):
             if it >= args.warmup:
                 ts.append(dt)
                 sw.append(ph["sweep"])
-            log(f"  alpha3 {prec} step {it}: {1e3 * dt:.1f} ms, sweep {ph['sweep']:.1f} ms")
+            log(f"  alpha{n} {prec} step {it}: {1e3 * dt:.1f} ms, sweep {ph['sweep']:.1f} ms")
         res[prec] = (float(np.mean(ts)), float(np.mean(sw)), mean, idx, val, cell)
     t32, s32, m32, i32, v32, c32 = res["fp32"]
     t64, s64, m64, i64, v64, _ = res["fp64"]
     feasible = int((~torch.isnan(m32)).sum().item())
     evals = feasible * M
     a_best = [spec["q_lo"] + (spec["q_hi"] - spec["q_lo"]) * c / (m - 1) for c, m in zip(c32, spec["m"])]
-    # Per summand: three means (12) and, per panel point, the point (2), the two
-    # conditional arguments (6), the Gaussian factor (3), two Phi (3 each) and
-    # the weighted product and sum (5): 22.
     r2, r3 = spec["r_lo"], spec["r_hi"]
-    scale = min(np.sqrt((1 - r2) / r2), np.sqrt((r2 - r3) / r3))
-    np32 = max(4, min(64, int(np.ceil(2.5 / scale))))   # FP32 panel rule
-    flops = feasible * M * (12.0 + np32 * 8 * 22.0)
+    if n == 3:
+        # Per summand: three means (12) and, per panel point, the point (2), the two
+        # conditional arguments (6), the Gaussian factor (3), two Phi (3 each) and
+        # the weighted product and sum (5): 22.
+        scale = min(np.sqrt((1 - r2) / r2), np.sqrt((r2 - r3) / r3))
+        npan = max(4, min(64, int(np.ceil(2.5 / scale))))   # FP32 panel rule
+        per_point, nb = 22.0, 0
+        flops = feasible * M * (12.0 + npan * 8 * per_point)
+        kernel = (f"k_eval_three<float,false> (one design per thread, {npan} panels x 8 points "
+                  f"of two univariate CDFs given the middle statistic)")
+    else:
+        # Per summand: four means (20) and, per panel point, the point (2), three
+        # conditional arguments (9), the Gaussian factor (3), one Phi (3), the
+        # bivariate normal of the last two given the second (13 + 6 per node)
+        # and the weighted product and sum (5): 35 + 6 nb.
+        r4 = spec["r_4"]
+        scale = min(np.sqrt((1 - r2) / r2), np.sqrt((r2 - r3) / r3), np.sqrt((r2 - r4) / r4))
+        npan = max(4, min(64, int(np.ceil(2.5 / scale))))
+        rho = np.sqrt(r4 * (r2 - r3) / (r3 * (r2 - r4)))
+        nb = int(bvn_nodes(np.array([rho]), "fp32")[0])
+        per_point = 35.0 + 6.0 * nb
+        flops = feasible * M * (20.0 + npan * 8 * per_point)
+        kernel = (f"k_eval_four<float,false> (one design per thread, {npan} panels x 8 points of a univariate "
+                  f"and a {nb}-node bivariate CDF given the second statistic)")
     achieved = flops / (1e-3 * s32) / 1e12
-    out = {"metric": "three-population alpha grid: integrand evals/s", "value": evals / t32,
+    levels = ", ".join(f"alpha_{i + 1}" for i in range(n - 1))
+    rs = ", ".join(str(x) for x in [spec["r_lo"], spec["r_hi"]] + ([spec["r_4"]] if n == 4 else []))
+    out = {"metric": f"{'three' if n == 3 else 'four'}-population alpha grid: integrand evals/s", "value": evals / t32,
            "unit": "integrand evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1e3 * t32, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"three nested populations r = (1, {spec['r_lo']}, {spec['r_hi']}), "
-                                  f"(alpha_1, alpha_2) grid {spec['m'][0]}x{spec['m'][1]} over "
-                                  f"[{spec['q_lo']}, {spec['q_hi']}], alpha_3 on the FWER boundary, Formula 10 "
+           "config": {"workload": f"{'three' if n == 3 else 'four'} nested populations r = (1, {rs}), "
+                                  f"({levels}) grid {'x'.join(str(m) for m in spec['m'])} over "
+                                  f"[{spec['q_lo']}, {spec['q_hi']}], alpha_{n} on the FWER boundary, Formula 10 "
                                   f"prior D0(r) = {spec['paper_a']} - {spec['paper_b']} r, I_3 = {spec['info']:g}, "
-                                  f"M={M}, smoothing sd {spec['bandwidth'][0]} on both axes, steps = precompute+draws+sweep+"
-                                  f"smooth+argmax over feasible designs",
+                                  f"M={M}, smoothing sd {spec['bandwidth'][0]} on every axis, steps = precompute+draws+"
+                                  f"sweep+smooth+argmax over feasible designs",
                       "designs": G, "feasible_designs": feasible, "n_draws": M},
            "roofline": {"bound": "alu", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
-                        "frac": achieved / 157.3, "traffic": None,
-                        "kernel": f"k_eval_three<float,false> (one design per thread, {np32} panels x 8 points "
-                                  f"of two univariate CDFs given the middle statistic)", "flops_per_launch": flops},
+                        "frac": achieved / 157.3, "traffic": None, "kernel": kernel, "flops_per_launch": flops},
            "sweep_ms": s32, "sweep_evals_per_s": evals / (1e-3 * s32),
            "result": {"best_alpha": a_best, "best_power_smoothed": v32,
                       "raw_power_at_best": float(m32[i32].item())},

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define BMD_ABI_VERSION 2
+#define BMD_ABI_VERSION 3
 #define BMD_MAX_DIM 6
 /* Size of the fixed device scratch of bmd_eval_grid_noalloc (128 MiB). */
 #define BMD_NOALLOC_SCRATCH_BYTES (128ull << 20)
@@ -107,7 +107,20 @@ typedef enum {
      * estimate is NaN.  Formula 10 prior with three normals per draw
      * (BMD_EFFECT_PAPER_GAUSS); alpha_rule must be BMD_ALPHA_FWER_EQUAL.
      * Grid sweeps only (no batch, gradient or level-split calls). */
-    BMD_DESIGN_ALPHA3 = 2
+    BMD_DESIGN_ALPHA3 = 2,
+    /* n = 4 nested populations 1 > r_2 > r_3 > r_4 (Sec. 2.2 with n = 4, the
+     * designs with three candidate thresholds of Sec. 3): d = 3, axes alpha_1,
+     * alpha_2, alpha_3 over [q_lo, q_hi] inside (0, alpha0); the fourth critical
+     * value lies on the FWER boundary 1 - Phi_4(z1, .., z4) = alpha0 of the null
+     * correlations sqrt(r_j / r_i).  r_lo holds r_2, r_hi holds r_3 and r_4 the
+     * fourth fraction, 0 < r_4 < r_3 <= 0.95 r_2, r_2 <= 0.9, the partial
+     * correlation of the third on the second population given the first at
+     * most 0.975 (as for three populations) and that of the third and fourth
+     * given the second, sqrt(r_4 (r_2 - r_3) / (r_3 (r_2 - r_4))), at most
+     * 0.975.  Designs whose first three levels already spend alpha0 have no
+     * fourth level and a NaN estimate.  Formula 10 prior with four normals per
+     * draw; alpha_rule BMD_ALPHA_FWER_EQUAL; grid sweeps only. */
+    BMD_DESIGN_ALPHA4 = 3
 } bmd_design_space;
 
 /* Problem descriptor (copied by bmd_create_problem). */
@@ -140,7 +153,8 @@ typedef struct {
     int32_t design_space;      /* bmd_design_space (0 = cutoffs)                    */
     double r_lo, r_hi;         /* BMD_DESIGN_ALPHA: subgroup-fraction axis (d = 2),
                                   0 < r_lo < r_hi <= 0.95, or r_2 = r_lo (d = 1);
-                                  BMD_DESIGN_ALPHA3: r_lo = r_2, r_hi = r_3         */
+                                  BMD_DESIGN_ALPHA3/4: r_lo = r_2, r_hi = r_3        */
+    double r_4;                /* BMD_DESIGN_ALPHA4: the fourth fraction r_4        */
 } bmd_problem_desc;
 
 /* Version of this header the library was built from (BMD_ABI_VERSION). */
@@ -334,15 +348,18 @@ bmd_status bmd_profile_read(bmd_problem *p, double *h_ms);
  *   d_u      [n*8]  FP64 uniforms in consumption order (unused slots 0)
  *   d_fields [n*BMD_DRAW_FIELDS] FP64: b0, b1, P(R), e1, e2, tau[6], t[6]
  *            (step prior: b0, b1, P(R), tau, t = Phi^-1(tau); paper prior: e1, e2;
- *            BMD_DESIGN_ALPHA3 also the third normal e3 in the tau[0] slot) */
+ *            BMD_DESIGN_ALPHA3/4 also the third normal e3 in the tau[0] slot,
+ *            BMD_DESIGN_ALPHA4 the fourth e4 in the tau[1] slot) */
 bmd_status bmd_draws(bmd_problem *p, uint64_t k0, uint64_t n, double *d_u, double *d_fields,
                      void *stream);
 
 #define BMD_DESIGN_FIELDS 16
 /* Design quantities for grid designs g0 .. g0+n-1:
  *   d_fields [n*BMD_DESIGN_FIELDS] FP64: q[6], c[6] = Phi^-1(q), r, sqrt(r), z1, z2
- *            (alpha design spaces: c[] is 0, except BMD_DESIGN_ALPHA3: c[0] = r_3
- *            and c[1] = z3, NaN when the design has no third level) */
+ *            (alpha design spaces: c[] is 0, except BMD_DESIGN_ALPHA3/4: c[0] = r_3
+ *            and c[1] = z3, NaN when the design has no third level of three
+ *            populations; BMD_DESIGN_ALPHA4 also c[2] = r_4 and c[3] = z4, NaN
+ *            when the design has no fourth level) */
 bmd_status bmd_designs(bmd_problem *p, int64_t g0, int64_t n, double *d_fields, void *stream);
 
 #ifdef __cplusplus

@@ -46,6 +46,7 @@ class _Problem(ctypes.Structure):
         ("width", ctypes.c_double), ("bandwidth", ctypes.c_double * 6),
         ("seed", ctypes.c_uint64), ("scenario", ctypes.c_uint32),
         ("design_space", ctypes.c_int32), ("r_lo", ctypes.c_double), ("r_hi", ctypes.c_double),
+        ("r_4", ctypes.c_double),
     ]
 
 
@@ -53,19 +54,20 @@ class _Design(ctypes.Structure):
     _fields_ = [("q", ctypes.c_double * 6), ("c", ctypes.c_double * 6),
                 ("r", ctypes.c_double), ("rho", ctypes.c_double),
                 ("z1", ctypes.c_double), ("z2", ctypes.c_double),
-                ("r3", ctypes.c_double), ("z3", ctypes.c_double)]
+                ("r3", ctypes.c_double), ("z3", ctypes.c_double),
+                ("r4", ctypes.c_double), ("z4", ctypes.c_double)]
 
 
 class _Draw(ctypes.Structure):
     _fields_ = [("u", ctypes.c_double * 8), ("b0", ctypes.c_double), ("b1", ctypes.c_double),
                 ("tau", ctypes.c_double * 6), ("t", ctypes.c_double * 6),
                 ("PR", ctypes.c_double), ("e1", ctypes.c_double), ("e2", ctypes.c_double),
-                ("e3", ctypes.c_double)]
+                ("e3", ctypes.c_double), ("e4", ctypes.c_double)]
 
 
 _ALPHA = {"fwer": 0, "fwer_equal": 0, "bonferroni": 1, "fixed": 2, "split": 3}
 _EFFECT = {"step": 0, "paper": 1, "paper_gauss": 1}
-_DESIGN = {"cutoffs": 0, "alpha": 1, "alpha3": 2}
+_DESIGN = {"cutoffs": 0, "alpha": 1, "alpha3": 2, "alpha4": 3}
 
 _lib = None
 
@@ -83,6 +85,7 @@ def lib():
             "or_bvn": (D, [D, D, D]), "or_bvn_density": (D, [D, D, D]),
             "or_orthant": (D, [ctypes.c_int, P, D]), "or_zstar": (D, [D, D]), "or_z2_fwer": (D, [D, D, D]),
             "or_tvn": (D, [D, D, D, D, D, D]), "or_z3_fwer": (D, [D, D, D, D, D]),
+            "or_qvn": (D, [P, P]), "or_qvn_nested": (D, [P, P]), "or_z4_fwer": (D, [D, D, D, D, D, D, D]),
             "or_info_units": (D, [D, D, D]),
             "or_philox4x32_10": (None, [P, P, P]), "or_uniform52": (D, [U32, U32]),
             "or_grid_point": (None, [pp, I64, P, P]), "or_grid_size": (I64, [pp]),
@@ -140,6 +143,7 @@ def problem_struct(prob: dict) -> _Problem:
     s.design_space = _DESIGN[prob.get("design", "cutoffs")]
     s.r_lo = float(prob.get("r_lo", 0.0))
     s.r_hi = float(prob.get("r_hi", 0.0))
+    s.r_4 = float(prob.get("r_4", 0.0))
     return s
 
 
@@ -154,6 +158,27 @@ def zstar(r, alpha0=0.025): return lib().or_zstar(float(r), float(alpha0))
 def z2_fwer(z1, r, alpha0=0.025): return lib().or_z2_fwer(float(z1), float(r), float(alpha0))
 def tvn(h1, h2, h3, r12, r13, r23): return lib().or_tvn(*map(float, (h1, h2, h3, r12, r13, r23)))
 def z3_fwer(z1, z2, r2, r3, alpha0=0.025): return lib().or_z3_fwer(*map(float, (z1, z2, r2, r3, alpha0)))
+
+
+def qvn(h, R):
+    """P(X_i <= h_i, i < 4) for a standard normal X with correlation matrix R (4 x 4)."""
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    assert h.shape == (4,) and R.shape == (4, 4)
+    return lib().or_qvn(_ptr(h), _ptr(R))
+
+
+def qvn_nested(h, r):
+    """P(X_i <= h_i, i < 4) for the null correlations of nested populations
+    with fractions r = (1, r2, r3, r4)."""
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    assert h.shape == (4,) and r.shape == (4,)
+    return lib().or_qvn_nested(_ptr(h), _ptr(r))
+
+
+def z4_fwer(z1, z2, z3, r2, r3, r4, alpha0=0.025):
+    return lib().or_z4_fwer(*map(float, (z1, z2, z3, r2, r3, r4, alpha0)))
 def info_units(alpha, beta, delta): return lib().or_info_units(float(alpha), float(beta), float(delta))
 def uniform52(wa, wb): return lib().or_uniform52(int(wa), int(wb))
 
@@ -199,7 +224,7 @@ def make_design(prob, q):
     lib().or_make_design(ctypes.byref(s), _ptr(qq), ctypes.byref(ds))
     d = s.d
     return {"q": np.array(ds.q[:d]), "c": np.array(ds.c[:d]), "r": ds.r, "rho": ds.rho,
-            "z1": ds.z1, "z2": ds.z2, "r3": ds.r3, "z3": ds.z3}
+            "z1": ds.z1, "z2": ds.z2, "r3": ds.r3, "z3": ds.z3, "r4": ds.r4, "z4": ds.z4}
 
 
 def make_draw(prob, k):
@@ -208,7 +233,7 @@ def make_draw(prob, k):
     lib().or_make_draw(ctypes.byref(s), int(k), ctypes.byref(dr))
     d = s.d
     return {"u": np.array(dr.u[:]), "b0": dr.b0, "b1": dr.b1, "tau": np.array(dr.tau[:d]),
-            "t": np.array(dr.t[:d]), "PR": dr.PR, "e1": dr.e1, "e2": dr.e2, "e3": dr.e3}
+            "t": np.array(dr.t[:d]), "PR": dr.PR, "e1": dr.e1, "e2": dr.e2, "e3": dr.e3, "e4": dr.e4}
 
 
 def _design_draw(prob, q, k):

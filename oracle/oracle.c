@@ -190,6 +190,41 @@ double or_tvn(double h1, double h2, double h3, double r12, double r13, double r2
     return or_quad(tvn_integrand, &c, fmin(-12.0, h1 - 10.0), h1);
 }
 
+/* Standard four-variate normal CDF P(X_i <= h_i, i = 1..4) with correlation
+ * matrix R (row-major 4 x 4, unit diagonal), from its definition by
+ * conditioning on X1: given X1 = x the other three are normal with means
+ * R_1j x, sds s_1j = sqrt(1 - R_1j^2) and the partial correlations
+ * R_jk.1 = (R_jk - R_1j R_1k) / (s_1j s_1k), so
+ *   int_{-inf}^{h1} phi(x) Phi_3((h_j - R_1j x)/s_1j; R_.1) dx.
+ * Phi_Sigma of Formula 1 for n = 4. */
+typedef struct { double h[3], r1[3], s1[3], p23, p24, p34; } qvn_ctx;
+
+static double qvn_integrand(double x, void *ctx)
+{
+    const qvn_ctx *c = (const qvn_ctx *)ctx;
+    return or_phi(x) * or_tvn((c->h[0] - c->r1[0] * x) / c->s1[0], (c->h[1] - c->r1[1] * x) / c->s1[1],
+                              (c->h[2] - c->r1[2] * x) / c->s1[2], c->p23, c->p24, c->p34);
+}
+
+double or_qvn(const double *h, const double *R)
+{
+    for (int i = 0; i < 4; ++i) {
+        if (isnan(h[i])) return NAN;
+        if (h[i] == -INFINITY) return 0.0;
+    }
+    if (h[0] == INFINITY) return or_tvn(h[1], h[2], h[3], R[1 * 4 + 2], R[1 * 4 + 3], R[2 * 4 + 3]);
+    qvn_ctx c;
+    for (int j = 0; j < 3; ++j) {
+        c.h[j] = h[j + 1];
+        c.r1[j] = R[j + 1];
+        c.s1[j] = sqrt((1.0 - c.r1[j]) * (1.0 + c.r1[j]));
+    }
+    c.p23 = (R[1 * 4 + 2] - c.r1[0] * c.r1[1]) / (c.s1[0] * c.s1[1]);
+    c.p24 = (R[1 * 4 + 3] - c.r1[0] * c.r1[2]) / (c.s1[0] * c.s1[2]);
+    c.p34 = (R[2 * 4 + 3] - c.r1[1] * c.r1[2]) / (c.s1[1] * c.s1[2]);
+    return or_quad(qvn_integrand, &c, fmin(-12.0, h[0] - 10.0), h[0]);
+}
+
 /* Density of the standard bivariate normal (the integrand of Plackett's
  * identity d Phi_2 / d rho = phi_2). */
 double or_bvn_density(double h, double k, double rho)
@@ -332,6 +367,71 @@ double or_z3_fwer(double z1, double z2, double r2, double r3, double alpha0)
     return 0.5 * (lo + hi);
 }
 
+/* Four-variate normal CDF for n = 4 nested populations with fractions
+ * r[0] = 1 > r[1] > r[2] > r[3] (null correlations sqrt(r_j / r_i),
+ * Appendix A.1).  Each population's statistic is the scaled sum over its
+ * members, so the statistics form a Markov chain: given Z2, Z1 is independent
+ * of (Z3, Z4), and given Z3, Z4 is independent of (Z1, Z2).  Integrating over
+ * (Z2, Z3) = (x, y) with density phi(x) phi((y - a x)/s)/s, a = sqrt(r3/r2),
+ * s = sqrt(1 - r3/r2):
+ *   Phi_4(h) = int_{x <= h2} phi(x) Phi((h1 - b x)/sb)
+ *              int_{y <= h3} phi((y - a x)/s)/s Phi((h4 - c y)/sc) dy dx,
+ * b = sqrt(r2), sb = sqrt(1 - r2), c = sqrt(r4/r3), sc = sqrt(1 - r4/r3).
+ * Two nested one-dimensional integrals of univariate CDFs: the form this
+ * oracle evaluates for the n = 4 model; or_qvn (conditioning on Z1 through
+ * Phi_3, any correlation matrix) is its check. */
+typedef struct { double h1, h3, h4, a, s, b, sb, c, sc, x; } qvn4_ctx;
+
+static double qvn4_inner(double y, void *ctx)
+{
+    const qvn4_ctx *c = (const qvn4_ctx *)ctx;
+    return or_phi((y - c->a * c->x) / c->s) / c->s * or_Phi((c->h4 - c->c * y) / c->sc);
+}
+
+static double qvn4_outer(double x, void *ctx)
+{
+    qvn4_ctx c = *(const qvn4_ctx *)ctx;
+    c.x = x;
+    double f1 = or_Phi((c.h1 - c.b * x) / c.sb);
+    if (f1 == 0.0) return 0.0;
+    double lo = fmin(c.a * x - 12.0 * c.s, c.h3 - 10.0 * c.s);
+    double inner = c.h3 == INFINITY ? or_Phi((c.h4 - c.c * c.a * x) / sqrt(c.c * c.c * c.s * c.s + c.sc * c.sc))
+                                    : or_quad(qvn4_inner, &c, lo, c.h3);
+    return or_phi(x) * f1 * inner;
+}
+
+double or_qvn_nested(const double *h, const double *r)
+{
+    for (int i = 0; i < 4; ++i) {
+        if (isnan(h[i])) return NAN;
+        if (h[i] == -INFINITY) return 0.0;
+    }
+    qvn4_ctx c = {h[0], h[2], h[3], sqrt(r[2] / r[1]), sqrt(1.0 - r[2] / r[1]), sqrt(r[1]), sqrt(1.0 - r[1]),
+                  sqrt(r[3] / r[2]), sqrt(1.0 - r[3] / r[2]), 0.0};
+    double hi = h[1] == INFINITY ? 12.0 : h[1];
+    return or_quad(qvn4_outer, &c, fmin(-12.0, hi - 10.0), hi);
+}
+
+/* n = 4 nested populations 1 > r2 > r3 > r4: the fourth critical value with
+ * FWER = 1 - Phi_4(z1, z2, z3, z4) = alpha0 given the first three, by
+ * bisection between the fourth test alone at level alpha0 and the union bound
+ * (the first three spend a123 = 1 - Phi_3(z1, z2, z3)).  NaN when
+ * a123 >= alpha0. */
+double or_z4_fwer(double z1, double z2, double z3, double r2, double r3, double r4, double alpha0)
+{
+    double r[4] = {1.0, r2, r3, r4};
+    double a123 = 1.0 - or_tvn(z1, z2, z3, sqrt(r2), sqrt(r3), sqrt(r3 / r2));
+    if (!(a123 < alpha0)) return NAN;
+    double lo = -or_Phiinv(alpha0), hi = -or_Phiinv(alpha0 - a123);
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        double h[4] = {z1, z2, z3, mid};
+        if (1.0 - or_qvn_nested(h, r) > alpha0) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 /* Information units needed for a one-sided level-alpha test with power
  * 1 - beta at hazard reduction delta (Sec. 3, the I_3 sizing formula). */
 double or_info_units(double alpha, double beta, double delta)
@@ -437,6 +537,20 @@ void or_grid_point(const or_problem *p, int64_t g, double *q, int32_t *idx)
 void or_make_design(const or_problem *p, const double *q, or_design *o)
 {
     memset(o, 0, sizeof *o);
+    if (p->design_space == OR_DESIGN_ALPHA4) {
+        /* (alpha_1, alpha_2, alpha_3) for four nested populations, alpha_4 on
+         * the FWER boundary (Formula 2 with n = 4). */
+        for (int j = 0; j < 3; ++j) o->q[j] = q[j];
+        o->r = p->r_lo;
+        o->rho = sqrt(o->r);
+        o->r3 = p->r_hi;
+        o->r4 = p->r_4;
+        o->z1 = -or_Phiinv(q[0]);
+        o->z2 = -or_Phiinv(q[1]);
+        o->z3 = -or_Phiinv(q[2]);
+        o->z4 = or_z4_fwer(o->z1, o->z2, o->z3, o->r, o->r3, o->r4, p->alpha0);
+        return;
+    }
     if (p->design_space == OR_DESIGN_ALPHA3) {
         /* (alpha_1, alpha_2) for three nested populations, alpha_3 on the FWER
          * boundary (Formula 2 with n = 3). */
@@ -508,6 +622,12 @@ void or_make_draw(const or_problem *p, uint64_t k, or_draw *o)
         o->e1 = or_Phiinv(o->u[0]);
         o->e2 = or_Phiinv(o->u[1]);
         o->e3 = or_Phiinv(o->u[2]);
+    } else if (p->design_space == OR_DESIGN_ALPHA4) {
+        draw_uniforms(p, k, 4, o->u);
+        o->e1 = or_Phiinv(o->u[0]);
+        o->e2 = or_Phiinv(o->u[1]);
+        o->e3 = or_Phiinv(o->u[2]);
+        o->e4 = or_Phiinv(o->u[3]);
     } else {
         draw_uniforms(p, k, 2, o->u);
         o->e1 = or_Phiinv(o->u[0]);
@@ -591,8 +711,31 @@ static double success3(const or_problem *p, const or_design *ds, const or_draw *
     return 1.0 - or_tvn(h[0], h[1], h[2], sqrt(r[1]), sqrt(r[2]), sqrt(r[2] / r[1]));
 }
 
+/* Four nested populations under Formula 10: the standard normals Y of the
+ * nested null correlations, each population's statistic being the scaled sum
+ * over its members, follow Y_1 = e1 and
+ * Y_{i+1} = sqrt(r_{i+1}/r_i) Y_i + sqrt(1 - r_{i+1}/r_i) e_{i+1}
+ * (the inner population's sum is a fraction of the outer one's plus an
+ * independent part); for i <= 3 this is the three-population construction. */
+static double success4(const or_problem *p, const or_design *ds, const or_draw *dr)
+{
+    if (isnan(ds->z4)) return NAN;
+    double r[4] = {1.0, ds->r, ds->r3, ds->r4}, E = p->paper_events, I = p->info;
+    double e[4] = {dr->e1, dr->e2, dr->e3, dr->e4}, Y[4];
+    Y[0] = e[0];
+    for (int i = 1; i < 4; ++i) Y[i] = sqrt(r[i] / r[i - 1]) * Y[i - 1] + sqrt(1.0 - r[i] / r[i - 1]) * e[i];
+    double z[4] = {ds->z1, ds->z2, ds->z3, ds->z4}, h[4];
+    for (int i = 0; i < 4; ++i) {
+        double th = -log1p(-(p->paper_a - p->paper_b * r[i]));
+        double sg = 1.0 / sqrt(E * r[i] / 4.0);
+        h[i] = z[i] - sqrt(r[i] * I) * (th + sg * Y[i]);
+    }
+    return 1.0 - or_qvn_nested(h, r);
+}
+
 double or_success(const or_problem *p, const or_design *ds, const or_draw *dr)
 {
+    if (p->design_space == OR_DESIGN_ALPHA4) return success4(p, ds, dr);
     if (p->design_space == OR_DESIGN_ALPHA3) return success3(p, ds, dr);
     double d1, d2;
     effects(p, ds, dr, &d1, &d2, NULL);
@@ -1030,6 +1173,17 @@ double or_exact_paper(const or_problem *p, const double *q)
     if (p->effect != OR_EFFECT_PAPER_GAUSS) return NAN;
     or_design ds;
     or_make_design(p, q, &ds);
+    if (p->design_space == OR_DESIGN_ALPHA4) {
+        /* as for three populations: covariance (1 + 4 I / E) R */
+        if (isnan(ds.z4)) return NAN;
+        double r[4] = {1.0, ds.r, ds.r3, ds.r4}, z[4] = {ds.z1, ds.z2, ds.z3, ds.z4}, h[4];
+        double s = sqrt(1.0 + 4.0 * p->info / p->paper_events);
+        for (int i = 0; i < 4; ++i) {
+            double th = -log1p(-(p->paper_a - p->paper_b * r[i]));
+            h[i] = (z[i] - sqrt(r[i] * p->info) * th) / s;
+        }
+        return 1.0 - or_qvn_nested(h, r);
+    }
     if (p->design_space == OR_DESIGN_ALPHA3) {
         /* X = D Delta + eps is Gaussian with covariance (1 + 4 I / E) R. */
         if (isnan(ds.z3)) return NAN;

@@ -33,7 +33,7 @@ extern "C" {
 
 enum { OR_ALPHA_FWER_EQUAL = 0, OR_ALPHA_BONFERRONI = 1, OR_ALPHA_FIXED = 2, OR_ALPHA_SPLIT = 3 };
 enum { OR_EFFECT_STEP = 0, OR_EFFECT_PAPER_GAUSS = 1 };
-enum { OR_DESIGN_CUTOFFS = 0, OR_DESIGN_ALPHA = 1, OR_DESIGN_ALPHA3 = 2 };
+enum { OR_DESIGN_CUTOFFS = 0, OR_DESIGN_ALPHA = 1, OR_DESIGN_ALPHA3 = 2, OR_DESIGN_ALPHA4 = 3 };
 
 typedef struct {
     int32_t d;              /* number of biomarkers (cutoff axes), 1..6          */
@@ -64,9 +64,14 @@ typedef struct {
      * OR_DESIGN_ALPHA3: n = 3 nested populations 1 > r_2 = r_lo > r_3 = r_hi
      * (Sec. 3's experiment); d = 2 axes alpha_1, alpha_2 on [q_lo, q_hi] and
      * alpha_3 on the FWER boundary (NaN designs where the first two levels
-     * already spend alpha0).  Paper prior only. */
+     * already spend alpha0).  Paper prior only.
+     * OR_DESIGN_ALPHA4: n = 4 nested populations 1 > r_lo > r_hi > r_4 (the
+     * three-threshold designs of Sec. 3); d = 3 axes alpha_1..alpha_3 on
+     * [q_lo, q_hi] and alpha_4 on the FWER boundary (NaN designs where the first
+     * three levels already spend alpha0).  Paper prior only. */
     int32_t design_space;
     double r_lo, r_hi;
+    double r_4;
 } or_problem;
 
 /* A design: cutoff quantiles and every quantity that depends on them only. */
@@ -75,7 +80,8 @@ typedef struct {
     double r;               /* subgroup fraction                                 */
     double rho;             /* sqrt(r): null correlation of the two Z-statistics */
     double z1, z2;          /* critical values (may be +inf)                     */
-    double r3, z3;          /* third population (OR_DESIGN_ALPHA3): r_3 and z3    */
+    double r3, z3;          /* third population (OR_DESIGN_ALPHA3/4): r_3 and z3  */
+    double r4, z4;          /* fourth population (OR_DESIGN_ALPHA4): r_4 and z4   */
 } or_design;
 
 /* One Monte Carlo draw of the effect parameters. */
@@ -86,6 +92,7 @@ typedef struct {
     double PR;              /* population fraction of responders                 */
     double e1, e2;          /* standard normals (paper Gaussian prior)           */
     double e3;              /* third normal (three populations)                  */
+    double e4;              /* fourth normal (four populations)                  */
 } or_draw;
 
 /* ---- primitives -------------------------------------------------------- */
@@ -100,6 +107,9 @@ double or_orthant(int d, const double *v, double rho_b);   /* P(X_j > v_j)    */
 double or_zstar(double r, double alpha0);
 double or_z2_fwer(double z1, double r, double alpha0);   /* second level on the FWER boundary */
 double or_z3_fwer(double z1, double z2, double r2, double r3, double alpha0);   /* n = 3: third level */
+double or_qvn(const double *h, const double *R);   /* P(X_i <= h_i, i < 4), R 4 x 4 correlations */
+double or_qvn_nested(const double *h, const double *r);   /* same, nested-population correlations of r[4] */
+double or_z4_fwer(double z1, double z2, double z3, double r2, double r3, double r4, double alpha0);   /* n = 4 */
 double or_info_units(double alpha, double beta, double delta);
 void   or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double or_uniform52(uint32_t wa, uint32_t wb);

@@ -20,7 +20,7 @@ FP64, FP32_COMP = 0, 1
 _PREC = {"fp64": FP64, "f64": FP64, "fp32": FP32_COMP, "fp32_comp": FP32_COMP, "f32": FP32_COMP}
 _ALPHA = {"fwer": 0, "fwer_equal": 0, "bonferroni": 1, "fixed": 2, "split": 3}
 _EFFECT = {"step": 0, "paper": 1, "paper_gauss": 1}
-_DESIGN = {"cutoffs": 0, "alpha": 1, "alpha3": 2}
+_DESIGN = {"cutoffs": 0, "alpha": 1, "alpha3": 2, "alpha4": 3}
 DRAW_FIELDS = 17
 DESIGN_FIELDS = 16
 
@@ -48,13 +48,14 @@ class _Desc(ctypes.Structure):
         ("bandwidth", ctypes.c_double * 6), ("gh_nodes", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("scenario_id", ctypes.c_uint32),
         ("design_space", ctypes.c_int32), ("r_lo", ctypes.c_double), ("r_hi", ctypes.c_double),
+        ("r_4", ctypes.c_double),
     ]
 
 
 _lib = None
 
 #: version of include/bmd.h this binding marshals (its descriptor layout)
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 #: every entry point declared in include/bmd.h, with (restype, argtypes)
 SIGNATURES = {
@@ -176,6 +177,7 @@ def make_desc(spec: dict) -> _Desc:
     D.design_space = _DESIGN[spec.get("design", "cutoffs")]
     D.r_lo = float(spec.get("r_lo", 0.0))
     D.r_hi = float(spec.get("r_hi", 0.0))
+    D.r_4 = float(spec.get("r_4", 0.0))
     return D
 
 

@@ -235,6 +235,24 @@ bmd_status validate(const bmd_problem_desc* d, bool* grid) {
             return fail(BMD_ERANGE, "need 0 < r_3 = r_hi < r_2 = r_lo <= 0.9");
         if (d->r_hi * (1.0 - d->r_lo) > 0.975 * 0.975 * d->r_lo * (1.0 - d->r_hi))
             return fail(BMD_ERANGE, "partial correlation of the third on the second population exceeds 0.975");
+    } else if (d->design_space == BMD_DESIGN_ALPHA4) {
+        if (d->effect != BMD_EFFECT_PAPER_GAUSS || d->alpha_rule != BMD_ALPHA_FWER_EQUAL)
+            return fail(BMD_EINVAL, "alpha designs need the Formula 10 prior and the FWER-boundary rule");
+        if (!any || d->d != 3)
+            return fail(BMD_ERANGE, "four-population designs are a grid over (alpha_1, alpha_2, alpha_3)");
+        if (!(d->q_hi < d->alpha0)) return fail(BMD_ERANGE, "level ranges must lie inside (0, alpha0)");
+        const double r2 = d->r_lo, r3 = d->r_hi, r4 = d->r_4;
+        if (!finite(r2) || !finite(r3) || !finite(r4) || !(0.0 < r4 && r4 < r3 && r3 < r2 && r2 <= 0.9))
+            return fail(BMD_ERANGE, "need 0 < r_4 < r_3 = r_hi < r_2 = r_lo <= 0.9");
+        // the first three levels use the three-population rule; the
+        // bivariate part of Phi_4 needs a correlation inside its node table,
+        // and r_3 / r_2, r_4 / r_2 bound the panel count
+        if (r3 * (1.0 - r2) > 0.975 * 0.975 * r2 * (1.0 - r3))
+            return fail(BMD_ERANGE, "partial correlation of the third on the second population exceeds 0.975");
+        if (r4 * (r2 - r3) > 0.975 * 0.975 * r3 * (r2 - r4))
+            return fail(BMD_ERANGE, "partial correlation of the fourth and third populations given the second "
+                                    "exceeds 0.975");
+        if (r3 > 0.95 * r2) return fail(BMD_ERANGE, "need r_3 <= 0.95 r_2");
     } else if (d->design_space != BMD_DESIGN_CUTOFFS) {
         return fail(BMD_EINVAL, "unknown design_space %d", d->design_space);
     }
@@ -301,6 +319,7 @@ void free_problem(bmd_problem* p) {
     f(p->d_z1);
     f(p->d_z2);
     f(p->d_z3);
+    f(p->d_z4);
     f(p->d_W);
     f(p->d_Wf);
     f(p->d_ws);
@@ -456,7 +475,11 @@ bmd_status bmd_create_problem(const bmd_problem_desc* desc, bmd_problem** out, v
     P.key0 = static_cast<uint32_t>(d.seed);
     P.key1 = static_cast<uint32_t>(d.seed >> 32);
     P.scenario = d.scenario_id;
-    P.n_uniform = d.effect == BMD_EFFECT_STEP ? 2 + d.d : d.design_space == BMD_DESIGN_ALPHA3 ? 3 : 2;
+    P.n_uniform = d.effect == BMD_EFFECT_STEP              ? 2 + d.d
+                  : d.design_space == BMD_DESIGN_ALPHA3 ? 3
+                  : d.design_space == BMD_DESIGN_ALPHA4 ? 4
+                                                        : 2;
+    P.r_4 = d.r_4;
     {
         // BMD_SWEEP=direct selects the direct (vector-unit) sweep for every grid
         // problem; both sweeps compute the same estimate (used by the tests).
@@ -515,7 +538,9 @@ bmd_status bmd_create_problem(const bmd_problem_desc* desc, bmd_problem** out, v
         st = upload<double>(&p->d_r, nullptr, P.G);
         if (st == BMD_OK) st = upload<double>(&p->d_z1, nullptr, P.G);
         if (st == BMD_OK) st = upload<double>(&p->d_z2, nullptr, P.G);
-        if (st == BMD_OK && d.design_space == BMD_DESIGN_ALPHA3) st = upload<double>(&p->d_z3, nullptr, P.G);
+        if (st == BMD_OK && (d.design_space == BMD_DESIGN_ALPHA3 || d.design_space == BMD_DESIGN_ALPHA4))
+            st = upload<double>(&p->d_z3, nullptr, P.G);
+        if (st == BMD_OK && d.design_space == BMD_DESIGN_ALPHA4) st = upload<double>(&p->d_z4, nullptr, P.G);
         // Smoothing matrices.
         std::vector<double> W;
         for (int j = 0; j < d.d && st == BMD_OK; ++j) {
@@ -725,7 +750,7 @@ bmd_status bmd_smooth(bmd_problem* p, const double* d_in, double* d_out, int32_t
     if (d_in == d_out) return fail(BMD_EINVAL, "d_in and d_out must not alias");
     DeviceGuard guard(p->device);
     // designs without a third level are NaN: smooth over the others
-    const bool masked = p->P.design_space == BMD_DESIGN_ALPHA3;
+    const bool masked = p->P.design_space == BMD_DESIGN_ALPHA3 || p->P.design_space == BMD_DESIGN_ALPHA4;
     bmd_status st = ensure(&p->d_ws2, &p->ws2_cap, sizeof(double) * static_cast<size_t>(p->P.G) * (masked ? 4 : 1));
     if (st != BMD_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1063,8 +1088,8 @@ bmd_status bmd_eval_batch(bmd_problem* const* ps, int32_t n, const uint64_t* n_d
     for (int i = 0; i < n; ++i) {
         if (!ps[i] || !d_means[i]) return fail(BMD_EINVAL, "problem or output %d is NULL", i);
         if (!ps[i]->grid) return fail(BMD_ESTATE, "problem %d has no grid", i);
-        if (ps[i]->P.design_space == BMD_DESIGN_ALPHA3)
-            return fail(BMD_ENOTSUP, "problem %d: three-population designs are not batched", i);
+        if (ps[i]->P.design_space == BMD_DESIGN_ALPHA3 || ps[i]->P.design_space == BMD_DESIGN_ALPHA4)
+            return fail(BMD_ENOTSUP, "problem %d: three- and four-population designs are not batched", i);
         if (ps[i]->device != ps[0]->device) return fail(BMD_EINVAL, "problems live on different devices");
         if (n_draws[i] == 0 || n_draws[i] > (1ull << 40)) return fail(BMD_ERANGE, "n_draws[%d] outside [1, 2^40]", i);
     }

@@ -29,6 +29,7 @@ struct DevProblem {
     double q_lo, q_hi;
     int design_space;          // bmd_design_space
     double r_lo, r_hi;         // alpha design space: subgroup-fraction axis (d = 2) or r_2 = r_lo
+    double r_4;                // four nested populations: r_4 (r_2 = r_lo, r_3 = r_hi)
     double rho_b, sr, sq;      // sqrt(rho_b), sqrt(1 - rho_b)
     double info, sqrtI;
     double alpha0;
@@ -54,7 +55,8 @@ struct DrawArrays {
     T* tauT;    // [M]  tau_0 (one-biomarker closed form)
     T* e1;      // [M]  paper prior normals
     T* e2;      // [M]
-    T* e3;      // [M]  third normal (three nested populations)
+    T* e3;      // [M]  third normal (three and four nested populations)
+    T* e4;      // [M]  fourth normal (four nested populations)
     int32_t* thr;   // [M][d] first grid index whose cutoff quantile exceeds tau_j
     T* q4;      // [M][4] (b0, b1, mu1, 0): one 4-vector per draw for the matrix-core sweep
     double* tau;    // [d][M]
@@ -116,7 +118,8 @@ struct bmd_problem {
     double* d_r = nullptr;           // [G]
     double* d_z1 = nullptr;          // [G]
     double* d_z2 = nullptr;          // [G]
-    double* d_z3 = nullptr;          // [G] third critical value (three nested populations)
+    double* d_z3 = nullptr;          // [G] third critical value (three and four nested populations)
+    double* d_z4 = nullptr;          // [G] fourth critical value (four nested populations)
     double* d_W = nullptr;           // smoothing matrices, FP64, sum_j m_j^2
     float* d_Wf = nullptr;           // same in FP32
     int64_t w_off[bmd::kMaxDim] = {0, 0, 0, 0, 0, 0};
@@ -151,6 +154,12 @@ hipError_t launch_three_precompute(const bmd_problem* p, hipStream_t s);
 int three_blocks_per_cu(int prec);
 hipError_t launch_eval_three(const bmd_problem* p, int prec, int64_t M, const void* ws, double* partials,
                              int n_slices, int64_t slice_len, bool want_var, hipStream_t s);
+// Four nested populations (kernels_four.hip): the same for (alpha_1, alpha_2,
+// alpha_3) grids with the fourth level on the FWER boundary.
+hipError_t launch_four_precompute(const bmd_problem* p, hipStream_t s);
+int four_blocks_per_cu(int prec);
+hipError_t launch_eval_four(const bmd_problem* p, int prec, int64_t M, const void* ws, double* partials,
+                            int n_slices, int64_t slice_len, bool want_var, hipStream_t s);
 hipError_t launch_axis_tables(const bmd_problem* p, int prec, hipStream_t s);
 hipError_t launch_draws(const bmd_problem* p, int prec, uint64_t k0, int64_t M, void* ws,
                         hipStream_t s);

@@ -154,6 +154,7 @@ int64_t sweep_tiles(const bmd_problem* p, int prec) {
 
 int sweep_blocks_per_cu(const bmd_problem* p, int prec) {
     if (p->P.design_space == BMD_DESIGN_ALPHA3) return three_blocks_per_cu(prec);
+    if (p->P.design_space == BMD_DESIGN_ALPHA4) return four_blocks_per_cu(prec);
     return prec == BMD_FP64 ? resident_typed<double, 24>(p, prec) : resident_typed<float, 12>(p, prec);
 }
 
@@ -165,6 +166,8 @@ hipError_t launch_eval_grid(const bmd_problem* p, int prec, int64_t M, const voi
                             int n_slices, int64_t slice_len, bool want_var, hipStream_t s) {
     if (p->P.design_space == BMD_DESIGN_ALPHA3)
         return launch_eval_three(p, prec, M, ws, partials, n_slices, slice_len, want_var, s);
+    if (p->P.design_space == BMD_DESIGN_ALPHA4)
+        return launch_eval_four(p, prec, M, ws, partials, n_slices, slice_len, want_var, s);
     if (prec == BMD_FP64) {
         EvalArgs<double> a{p->P, p->d_r, p->d_z1, p->d_z2, static_cast<const double*>(p->tab[prec].A),
                            draws_fp64(p, M, ws), p->d_gl, static_cast<const double*>(p->tab[prec].glw),

@@ -322,7 +322,8 @@ __device__ __forceinline__ void draw_one(const DevProblem& P, const double* __re
         const double e2 = norm_quantile(u[1]);
         D.e1[kk] = static_cast<T>(e1);
         D.e2[kk] = static_cast<T>(e2);
-        if (P.n_uniform == 3) D.e3[kk] = static_cast<T>(norm_quantile(u[2]));
+        if (P.n_uniform >= 3) D.e3[kk] = static_cast<T>(norm_quantile(u[2]));
+        if (P.n_uniform >= 4) D.e4[kk] = static_cast<T>(norm_quantile(u[3]));
         D.mu1[kk] = static_cast<T>(P.sqrtI * (P.th1 + P.sg1 * e1));
     }
 }
@@ -376,13 +377,15 @@ __global__ __launch_bounds__(128) void k_inspect_draws(DevProblem P, const doubl
     } else {
         f[3] = norm_quantile(u[0]);
         f[4] = norm_quantile(u[1]);
-        if (P.n_uniform == 3) f[5] = norm_quantile(u[2]);
+        if (P.n_uniform >= 3) f[5] = norm_quantile(u[2]);
+        if (P.n_uniform >= 4) f[6] = norm_quantile(u[3]);
     }
 }
 
 __global__ __launch_bounds__(128) void k_inspect_designs(DevProblem P, int64_t g0, int64_t n, const double* __restrict__ r,
                                   const double* __restrict__ z1, const double* __restrict__ z2,
-                                  const double* __restrict__ z3, double* __restrict__ out) {
+                                  const double* __restrict__ z3, const double* __restrict__ z4,
+                                  double* __restrict__ out) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const int64_t g = g0 + t;
@@ -397,6 +400,11 @@ __global__ __launch_bounds__(128) void k_inspect_designs(DevProblem P, int64_t g
     if (P.design_space == BMD_DESIGN_ALPHA3) {
         f[6] = P.r_hi;
         f[7] = z3[g];
+    } else if (P.design_space == BMD_DESIGN_ALPHA4) {
+        f[6] = P.r_hi;
+        f[7] = z3[g];
+        f[8] = P.r_4;
+        f[9] = z4[g];
     }
     f[12] = r[g];
     f[13] = sqrt(r[g]);
@@ -430,6 +438,7 @@ hipError_t launch_levels_best(const bmd_problem* p, int k, const double* mean, d
 hipError_t launch_design_precompute(const bmd_problem* p, hipStream_t s) {
     if (p->P.G == 0) return hipSuccess;
     if (p->P.design_space == BMD_DESIGN_ALPHA3) return launch_three_precompute(p, s);
+    if (p->P.design_space == BMD_DESIGN_ALPHA4) return launch_four_precompute(p, s);
     hipLaunchKernelGGL(k_design_precompute, dim3(blocks_for(p->P.G, 128)), dim3(128), 0, s, p->P,
                        p->d_ghp, kPrecomputeGH, p->d_gl, p->d_r, p->d_z1, p->d_z2);
     return hipGetLastError();
@@ -466,6 +475,7 @@ static DrawArrays<T> carve(const bmd_problem* p, int prec, int64_t M, void* ws) 
     D.e1 = reinterpret_cast<T*>(take(sizeof(T) * M));
     D.e2 = reinterpret_cast<T*>(take(sizeof(T) * M));
     D.e3 = reinterpret_cast<T*>(take(sizeof(T) * M));
+    D.e4 = reinterpret_cast<T*>(take(sizeof(T) * M));
     D.thr = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * d * M));
     D.q4 = reinterpret_cast<T*>(take(sizeof(T) * 4 * M));
     D.tau = reinterpret_cast<double*>(take(sizeof(double) * d * M));
@@ -479,7 +489,7 @@ size_t draw_workspace_bytes(const bmd_problem* p, int prec, int64_t M) {
     const size_t T = prec == BMD_FP64 ? 8 : 4;
     const int d = p->P.d, K = p->tab[prec].K;
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    return 8 * al(T * M) + al(4 * d * M) + al(4 * T * M) + al(8 * d * M) +
+    return 9 * al(T * M) + al(4 * d * M) + al(4 * T * M) + al(8 * d * M) +
            al(T * (d >= 2 ? static_cast<size_t>(M) * d * K : 1));
 }
 
@@ -539,7 +549,7 @@ hipError_t launch_inspect_draws(const bmd_problem* p, uint64_t k0, int64_t n, do
 
 hipError_t launch_inspect_designs(const bmd_problem* p, int64_t g0, int64_t n, double* fields, hipStream_t s) {
     hipLaunchKernelGGL(k_inspect_designs, dim3(blocks_for(n, 128)), dim3(128), 0, s, p->P, g0, n, p->d_r,
-                       p->d_z1, p->d_z2, p->d_z3, fields);
+                       p->d_z1, p->d_z2, p->d_z3, p->d_z4, fields);
     return hipGetLastError();
 }
 

@@ -2,107 +2,15 @@
 // correlations of Appendix A.1 and the Formula 10 prior; Sec. 3 condition
 // (c)): per-design critical values with the third on the FWER boundary of
 // Formula 2, and the grid sweep of the Formula 5 estimate whose summand is
-// 1 - Phi_3(z - mu; R).
-//
-// Phi_3 by conditioning on the middle coordinate.  For nested populations
-// the statistics form a chain: the partial correlation of the first and third
-// given the second, (r13 - r12 r23) / (s12 s23) with r12 = sqrt(r2),
-// r13 = sqrt(r3), r23 = sqrt(r3/r2), is zero, so given Y2 = y the other two are
-// independent normals with means r12 y, r23 y and sds s12 = sqrt(1 - r2),
-// s23 = sqrt(1 - r3/r2):
-//   Phi_3(h1, h2, h3) = int_{-inf}^{h2} phi(y) Phi((h1 - r12 y)/s12) Phi((h3 - r23 y)/s23) dy,
-// a one-dimensional integral of univariate CDFs only.  It runs over [-L, U],
-// U = min(h2, L, the y beyond which either conditional argument falls below
-// -L), with L = 8.5 in FP64 (Phi(-8.5) < 1e-17) and 6 in FP32 (Phi(-6) = 1e-9),
-// cut into equal panels of an 8-point Gauss-Legendre rule.  The integrand's
-// steepest part is the conditional CDF whose scale in y, l = s12 / r12 or
-// s23 / r23, is smaller; the panel count is ceil(c / l) with c = 6 (8..128
-// panels) in FP64 and c = 2.5 (4..64) in FP32.  Against an adaptive reference
-// over 0.1 <= r2 <= 0.9 and r3 / r2 up to 0.99 this keeps the quadrature error
-// below 5e-12 (FP64) and 2e-8 (FP32); the critical values use at least 16
-// panels.
+// 1 - Phi_3(z - mu; R), Phi_3 as in nested_cdf.hpp.
 #include <cmath>
 
 #include "bmd_internal.hpp"
 #include "device_math.hpp"
+#include "nested_cdf.hpp"
 
 namespace bmd {
 namespace {
-
-constexpr int kNodes = 8;          // Gauss-Legendre points per panel
-constexpr int kPanelsSetup = 16;   // fewest panels for the critical values (FP64)
-
-// Panels in type T for subgroup fractions r2 > r3.
-template <typename T>
-__device__ __forceinline__ int tvn_panels(double r2, double r3) {
-    const double l = fmin(sqrt((1.0 - r2) / r2), sqrt((r2 - r3) / r3));
-    const double c = sizeof(T) == 8 ? 6.0 : 2.5;
-    const int lo = sizeof(T) == 8 ? 8 : 4, hi = sizeof(T) == 8 ? 128 : 64;
-    return max(lo, min(hi, static_cast<int>(ceil(c / l))));
-}
-
-// exp(-x^2 / 2); FP32 through exp2.
-__device__ __forceinline__ double half_gauss(double x) { return exp(-0.5 * x * x); }
-__device__ __forceinline__ float half_gauss(float x) {
-    return __builtin_amdgcn_exp2f(x * x * -0.72134752044448170368f);   // log2(e) / 2
-}
-
-// Per-problem constants of Phi_3 in type T.
-template <typename T>
-struct TvnConst {
-    T r12, r23;        // regressions of the first and third coordinates on the second
-    T is12, is23;      // 1 / s12, 1 / s23
-    T tail;            // L: integration range [-L, U]
-    T c1, c3;          // L s12, L s23: offsets of the upper integration limit
-    T ir12, ir23;      // 1 / r12, 1 / r23
-    T px[kNodes];      // panel nodes on [0, 1]
-    T pw[kNodes];      // panel weights with phi's 1/sqrt(2 pi) folded in
-    int np;            // panels
-
-    __device__ void init(double r2, double r3, int panels, const double* __restrict__ gl) {
-        const double L = sizeof(T) == 8 ? 8.5 : 6.0;
-        const double a = sqrt(r2), b = sqrt(r3 / r2), sa = sqrt(1.0 - r2), sb = sqrt(1.0 - r3 / r2);
-        r12 = static_cast<T>(a);
-        r23 = static_cast<T>(b);
-        is12 = static_cast<T>(1.0 / sa);
-        is23 = static_cast<T>(1.0 / sb);
-        tail = static_cast<T>(L);
-        c1 = static_cast<T>(L * sa);
-        c3 = static_cast<T>(L * sb);
-        ir12 = static_cast<T>(1.0 / a);
-        ir23 = static_cast<T>(1.0 / b);
-        const double* x = gl + gl_offset(kNodes);
-        const double* w = x + kNodes;
-#pragma unroll
-        for (int i = 0; i < kNodes; ++i) {
-            px[i] = static_cast<T>(0.5 * (1.0 + x[i]));
-            pw[i] = static_cast<T>(0.5 * w[i] * 0.39894228040143267794);
-        }
-        np = panels;
-    }
-};
-
-// Phi_3(h1, h2, h3) over c.np panels (wave-uniform).  Every lane runs the
-// same node count: an empty range (U <= -L) becomes a zero panel width, and
-// NaN inputs give NaN.
-template <typename T>
-__device__ __forceinline__ T tvn(T h1, T h2, T h3, const TvnConst<T>& c) {
-    const T lo = -c.tail;
-    const T hi = fmin(fmin(h2, c.tail), fmin((h1 + c.c1) * c.ir12, (h3 + c.c3) * c.ir23));
-    const T width = fmax(hi - lo, T(0)) / static_cast<T>(c.np);
-    T acc = T(0);
-    for (int p = 0; p < c.np; ++p) {
-        const T a = fma(width, static_cast<T>(p), lo);
-#pragma unroll
-        for (int i = 0; i < kNodes; ++i) {
-            const T y = fma(width, c.px[i], a);
-            const T u = (h1 - c.r12 * y) * c.is12;
-            const T v = (h3 - c.r23 * y) * c.is23;
-            acc = fma(c.pw[i] * half_gauss(y), norm_cdf(u) * norm_cdf(v), acc);
-        }
-    }
-    return acc * width;
-}
 
 // Levels alpha_1 (axis 0) and alpha_2 (axis 1) of design g; the third critical
 // value solves F(z3) = 1 - Phi_3(z1, z2, z3) - alpha0 = 0 (F falls in z3)

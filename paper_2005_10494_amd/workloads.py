@@ -109,6 +109,28 @@ def alpha3_grid() -> dict:
     return alpha3_design(97, n_draws=100_000)
 
 
+def alpha4_design(m: int, r2: float = 0.7, r3: float = 0.446, r4: float = 0.168, q_range=(0.0005, 0.0245),
+                  n_draws: int = 10_240, bandwidth: float = 0.0015) -> dict:
+    """Four nested populations (the three-threshold designs of Sec. 3) under
+    condition (c)'s effects D0(r) = 0.8 - 0.6 r, I_3 = 211, Formula 10 prior
+    with E = 80; fractions r = (1, 0.7, 0.446, 0.168) (condition (c)'s two
+    subgroups with a wider one in front): an m x m x m grid of the first three
+    levels over ``q_range``, alpha_4 from the FWER boundary.  Designs whose
+    first three levels already spend alpha0 have no fourth level."""
+    p = base_problem(3, [m, m, m], 0.0, bandwidth, design="alpha4", q_lo=float(q_range[0]),
+                     q_hi=float(q_range[1]), info=211.0, effect="paper", paper_a=0.8, paper_b=0.6,
+                     paper_events=80.0)
+    p["r_lo"], p["r_hi"], p["r_4"] = float(r2), float(r3), float(r4)
+    p["n_draws"] = n_draws
+    return p
+
+
+def alpha4_grid() -> dict:
+    """Four populations as a design grid: alpha_1, alpha_2, alpha_3 each over
+    [0.0005, 0.0245] in steps of 0.001 (25^3), M = 100,000 draws."""
+    return alpha4_design(25, n_draws=100_000)
+
+
 def noisy_surface(m, seed: int = 0, nan_corner: int = 0) -> np.ndarray:
     """A seeded stand-in for an estimated grid surface (row-major over the
     axes m, axis 0 slowest): a smooth bump plus N(0, 0.02^2) noise.  With

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
     out = subprocess.run(["nm", "-D", "--defined-only", bmd.LIB_PATH], capture_output=True, text=True).stdout
     exported = set(re.findall(r" T (bmd_\w+)", out))
     assert set(names) <= exported
-    assert lib.bmd_abi_version() == bmd.ABI_VERSION == 2
+    assert lib.bmd_abi_version() == bmd.ABI_VERSION == 3
 
 
 def test_descriptor_layout_matches_c(tmp_path):
@@ -132,6 +132,23 @@ def test_workloads_are_inputs_only():
 def test_alpha3_design_validation(change, status):
     """Three nested populations (Sec. 2.2, n = 3) reject what they do not cover."""
     spec = W.alpha3_design(5)
+    spec.update(change)
+    st, msg = _create_status(spec)
+    assert st == status, msg
+    assert msg
+
+
+@pytest.mark.parametrize("change,status", [
+    ({"effect": "step"}, -1), ({"alpha_rule": "bonferroni"}, -1), ({"q_hi": 0.025}, -2),
+    ({"r_4": 0.0}, -2), ({"r_4": 0.5}, -2), ({"r_lo": 0.95}, -2), ({"r_lo": 0.4, "r_hi": 0.5}, -2),
+    ({"r_lo": 0.9, "r_hi": 0.899}, -2),                 # third on second given first above 0.975
+    ({"r_lo": 0.5, "r_hi": 0.49, "r_4": 0.1}, -2),      # r_3 above 0.95 r_2
+    ({"r_lo": 0.9, "r_hi": 0.5, "r_4": 0.499}, -2),     # fourth and third given second above 0.975
+    ({"d": 2, "m": [5, 5], "bandwidth": [0.1] * 2}, -2), ({"m": [0, 0, 0]}, -2),
+])
+def test_alpha4_design_validation(change, status):
+    """Four nested populations (Sec. 2.2, n = 4) reject what they do not cover."""
+    spec = W.alpha4_design(5)
     spec.update(change)
     st, msg = _create_status(spec)
     assert st == status, msg

@@ -11,7 +11,7 @@ import os
 import mpmath
 import numpy as np
 import pytest
-from scipy import stats
+from scipy import integrate, stats
 from scipy.optimize import brentq
 from scipy.special import ndtr, ndtri, owens_t
 
@@ -747,3 +747,118 @@ def test_masked_smoother_pins():
     # without NaN it is the plain smoother
     g = np.where(nan, 0.5, f)
     assert np.max(np.abs(O.smooth_masked(spec, g) - O.smooth_direct(spec, g))) < 1e-15
+
+
+# ---------------------------------------------------------------- four nested populations
+
+def _qvn_scipy(h, R):
+    return stats.multivariate_normal.cdf(np.asarray(h, dtype=float), mean=np.zeros(4), cov=np.asarray(R),
+                                         abseps=1e-9, releps=1e-9, maxpts=4_000_000)
+
+
+def _nested_R(r):
+    return np.array([[math.sqrt(min(a, b) / max(a, b)) for b in r] for a in r])
+
+
+def test_four_variate_cdf_against_scipy_and_closed_forms():
+    """or_qvn (conditioning on the first coordinate through Phi_3, any
+    correlation matrix) against scipy's MVN CDF and closed forms; the
+    nested-population form or_qvn_nested (two 1-D integrals over the chain's
+    middle statistics) against or_qvn and scipy."""
+    rng = np.random.default_rng(11)
+    A = rng.normal(size=(4, 6))
+    C = A @ A.T
+    R = C / np.sqrt(np.outer(np.diag(C), np.diag(C)))
+    h = rng.normal(0.5, 1.0, 4)
+    assert abs(O.qvn(h, R) - _qvn_scipy(h, R)) < 2e-7, (h, R)
+    # equicorrelated orthant at rho = 1/2: 1/(n + 1)
+    R = np.full((4, 4), 0.5)
+    np.fill_diagonal(R, 1.0)
+    assert abs(O.qvn(np.zeros(4), R) - 0.2) < 1e-13
+    # equicorrelated, any bounds: the one-factor identity
+    rho = 0.3
+    R = np.full((4, 4), rho)
+    np.fill_diagonal(R, 1.0)
+    h = np.array([0.3, -0.5, 1.1, 0.2])
+    f = lambda z: math.exp(-z * z / 2) / math.sqrt(2 * math.pi) * np.prod(ndtr((h - math.sqrt(rho) * z) / math.sqrt(1 - rho)))
+    ref = integrate.quad(f, -np.inf, np.inf, epsabs=1e-14, epsrel=1e-14)[0]
+    assert abs(O.qvn(h, R) - ref) < 1e-13
+    # two independent pairs: a product of bivariate CDFs (Owen's T)
+    R = np.eye(4)
+    R[0, 1] = R[1, 0] = 0.6
+    R[2, 3] = R[3, 2] = -0.4
+    h = np.array([0.2, 1.0, -0.3, 0.8])
+    assert abs(O.qvn(h, R) - _bvn_owen(0.2, 1.0, 0.6) * _bvn_owen(-0.3, 0.8, -0.4)) < 1e-13
+    # an infinite bound drops a coordinate: the trivariate CDF
+    r = [1.0, 0.6, 0.35, 0.2]
+    Rn = _nested_R(r)
+    h = np.array([0.4, 0.9, math.inf, -0.2])
+    assert abs(O.qvn(h, Rn) - O.tvn(0.4, 0.9, -0.2, Rn[0, 1], Rn[0, 3], Rn[1, 3])) < 1e-13
+    # nested chain form against the generic one and scipy, with finite and
+    # infinite middle bounds
+    for r, h in (([1.0, 0.6, 0.35, 0.2], [0.9, 1.4, 0.2, 1.7]), ([1.0, 0.9, 0.5, 0.45], [1.9, 0.1, 0.8, 0.6]),
+                 ([1.0, 0.2, 0.05, 0.01], [-0.4, 2.1, 1.0, 0.3])):
+        h = np.array(h)
+        Rn = _nested_R(r)
+        g = O.qvn(h, Rn)
+        assert abs(O.qvn_nested(h, np.array(r)) - g) < 1e-13, (r, h)
+        assert abs(g - _qvn_scipy(h, Rn)) < 2e-7
+    r = np.array([1.0, 0.6, 0.35, 0.2])
+    for j in (1, 2):
+        h = np.array([0.4, 0.9, 0.1, -0.2])
+        h[j] = math.inf
+        assert abs(O.qvn_nested(h, r) - O.qvn(h, _nested_R(r))) < 1e-13
+
+
+def _alpha4(**kw):
+    p = W.alpha4_design(5)
+    p.update(kw)
+    return p
+
+
+def test_alpha4_fourth_level_on_fwer_boundary():
+    p = _alpha4()
+    r = [1.0, p["r_lo"], p["r_hi"], p["r_4"]]
+    R = _nested_R(r)
+    for n, a in enumerate([(0.002, 0.004, 0.006), (0.008, 0.003, 0.001), (0.0005, 0.0005, 0.0005)]):
+        ds = O.make_design(p, list(a))
+        assert ds["r"] == r[1] and ds["r3"] == r[2] and ds["r4"] == r[3]
+        z = (ds["z1"], ds["z2"], ds["z3"], ds["z4"])
+        for i in range(3):
+            assert abs(z[i] + ndtri(a[i])) < 1e-12
+        assert abs((1.0 - _qvn_scipy(z, R)) - 0.025) < 2e-7
+        if n == 0:   # through the generic CDF too (it takes seconds)
+            assert abs((1.0 - O.qvn(np.array(z), R)) - 0.025) < 1e-12
+    # the first three levels already spend alpha0: no valid fourth level
+    assert math.isnan(O.make_design(p, [0.02, 0.015, 0.01])["z4"])
+
+
+def test_alpha4_draws_and_monte_carlo():
+    """The first three normals are the three-population draws; the estimate
+    of Formula 5 stays within 4 CLT sd of the Formula 10 closed form."""
+    p = _alpha4()
+    p3 = W.alpha3_design(5)
+    for k in (0, 7, 12345):
+        d4, d3 = O.make_draw(p, k), O.make_draw(p3, k)
+        assert d4["e1"] == d3["e1"] and d4["e2"] == d3["e2"] and d4["e3"] == d3["e3"]
+        assert abs(d4["e4"] - ndtri(d4["u"][3])) < 1e-12
+    M = 3000
+    q = np.array([[0.002, 0.004, 0.006], [0.006, 0.006, 0.002]])
+    m, v = O.eval_points(p, q, M)
+    for i in range(len(q)):
+        ex = O.exact_paper(p, q[i])
+        assert abs(m[i] - ex) < 4 * math.sqrt(v[i] / M), (q[i], m[i], ex)
+
+
+def test_alpha4_closed_form_against_scipy():
+    """The Formula 10 closed form for four populations, 1 - Phi_4 at the
+    standardised critical values, against scipy's MVN CDF."""
+    p = _alpha4()
+    r = [1.0, p["r_lo"], p["r_hi"], p["r_4"]]
+    I = p["info"]
+    s = math.sqrt(1 + 4 * I / p["paper_events"])
+    for a in [(0.002, 0.004, 0.006), (0.006, 0.006, 0.002)]:
+        ds = O.make_design(p, list(a))
+        z = [ds["z1"], ds["z2"], ds["z3"], ds["z4"]]
+        h = [(z[i] - math.sqrt(r[i] * I) * (-math.log(1 - (0.8 - 0.6 * r[i])))) / s for i in range(4)]
+        assert abs(O.exact_paper(p, np.array(a)) - (1.0 - _qvn_scipy(h, _nested_R(r)))) < 2e-7

@@ -588,8 +588,10 @@ def bench_batch(args):
     evals = float(sum(int(np.prod(x["m"])) * x["n_draws"] for x in sc))
     log(f"batch: {len(sc)} problems, {evals:.3e} evaluations")
     probs = [bmd.Problem(x) for x in sc]
-    ts, walls = [], None
+    kinds_of = [bmd.sweep_kind(p) for p in probs]
+    ts, walls, warm_ms = [], None, 0.0
     try:
+        bmd.batch_autotune(2)   # tune during the first (warmup) call
         for it in range(args.warmup + args.steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -599,12 +601,29 @@ def bench_batch(args):
             if it >= args.warmup:
                 ts.append(dt)
                 walls = wall
+            elif it == 0:
+                warm_ms = 1e3 * dt
             log(f"  batch step {it}: {1e3 * dt:.1f} ms, last problem done at {wall.max():.1f} ms")
             del means
-    finally:
+    except BaseException:
         for p in probs:
             p.close()
+        raise
     t = float(np.mean(ts))
+    # launch settings the autotuner chose during the warmup call, per launch kind
+    kinds = sorted({(x["d"], 1 if k == "matrix" else 0) for x, k in zip(sc, kinds_of)})
+    settings = {f"d{d}_{'matrix' if kind else 'direct'}": bmd.batch_settings("fp32", d, kind) for d, kind in kinds}
+    # algorithmic work of the call: vector-unit and matrix-core flops of every problem
+    valu = mfma = 0.0
+    for x, p in zip(sc, probs):
+        r = p.designs(0, p.G)[:, 12].cpu().numpy()
+        _, f = p.draws(0, x["n_draws"])
+        tau = f[:, 5:5 + x["d"]].cpu().numpy()
+        v, o = algorithmic_flops(x, r, tau, "fp32", _gh_nodes(p, "fp32"))
+        valu += v
+        mfma += o
+    for p in probs:
+        p.close()
     out = {"metric": "aggregate integrand evals/s over a batch of uneven grid problems",
            "value": evals / t, "unit": "integrand evals/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * t, "higher_is_better": True, "scaling": "weak",
@@ -614,7 +633,15 @@ def bench_batch(args):
                                   f"[{1e4 * s:.0f}, {1e6 * s:.0f}], FP32 integrand + FP64 sums",
                       "problems": len(sc), "evaluations": evals},
            "wall_ms_per_problem": {"p50": float(np.percentile(walls, 50)), "p99": float(np.percentile(walls, 99)),
-                                   "max": float(walls.max())}}
+                                   "max": float(walls.max())},
+           "tuning_ms": warm_ms - 1e3 * t, "tuned_settings": settings,
+           "roofline": {"bound": "alu", "achieved": valu / t / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                        "frac": valu / t / 1e12 / PEAK_FP32_TFLOPS, "traffic": None,
+                        "numerator": "vector-unit flops of every problem's sweep over the whole call",
+                        "kernel": "k_batch<float, d, 12, kind, variant> (one launch per biomarker count and kernel kind)",
+                        "flops_per_call": valu,
+                        "mfma": {"achieved": mfma / t / 1e12, "peak": PEAK_MFMA_FP32_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": mfma / t / 1e12 / PEAK_MFMA_FP32_TFLOPS, "flops_per_call": mfma}}}
     print(json.dumps(out), flush=True)
 
 

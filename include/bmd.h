@@ -289,6 +289,51 @@ bmd_status bmd_eval_grid_levels(bmd_problem *p, uint64_t n_draws, int32_t prec, 
 bmd_status bmd_optimize_levels(bmd_problem *p, uint64_t n_draws, int32_t prec, double a_lo, double a_hi,
                                int32_t n_iter, double *d_best, double *d_alpha1, void *stream);
 
+/* Formula 5 estimate and its derivative in the first level alpha_1 at every
+ * grid design, on draws 0..n_draws-1 (Appendix A.3 differentiates the power
+ * under the integral; for the nested pair the chain rule runs through both
+ * critical values):
+ *   d_dmean[g] = (1/M) sum_k d(1 - Phi_2(z1 - mu1_k, z2 - mu2_gk; rho_g))/d alpha_1
+ * with dz1/d alpha_1 = -1/phi(z1); under BMD_ALPHA_SPLIT the second level
+ * stays on the design's FWER boundary, so z2 moves with z1 as
+ * dz2/dz1 = -phi(z1) Phi((z2 - rho z1)/s) / (phi(z2) Phi((z1 - rho z2)/s)),
+ * s = sqrt(1 - rho^2); under BMD_ALPHA_FIXED z2 stays (a second test switched
+ * off leaves Appendix A.3's one-test form, mean of phi(z1 - mu1)/phi(z1)).
+ *   d_mean  [G] FP64 the estimate (as bmd_eval_grid's mean up to FP32
+ *           summation order)
+ *   d_dmean [G] FP64 its alpha_1 derivative
+ * Same sweep and draws as bmd_eval_grid, the derivative summed beside the
+ * value.  ESTATE for a continuous problem or an alpha design space; ENOTSUP
+ * for rules other than SPLIT and FIXED; ERANGE if alpha_fixed[0] is 0 or
+ * n_draws is 0 or > 2^40. */
+bmd_status bmd_eval_grid_dalpha(bmd_problem *p, uint64_t n_draws, int32_t prec, double *d_mean,
+                                double *d_dmean, void *stream);
+
+/* Optimal level split per design found from the derivative (Sec. 2.3's
+ * derivative-driven search, Sec. 2.4's optimal power at each design, n = 2
+ * nested tests): for every design, a root of d P / d alpha_1 (from the sweep
+ * of bmd_eval_grid_dalpha) in [a_lo, a_hi] (0 < a_lo < a_hi < alpha0) by
+ * bracketed false position with the Illinois halving, the second level on the
+ * design's FWER boundary, draws 0..n_draws-1 generated once.  The ends are
+ * probed first; a derivative <= 0 at a_lo or >= 0 at a_hi ends the design's
+ * search at that end.  Each of the n_iter steps probes the secant root of the
+ * bracket (its midpoint if that root is not strictly inside) and keeps the
+ * end across the sign change; a zero derivative or a bracket below tol ends
+ * the design's search (its best level is probed again until all designs
+ * finish).  The call runs 2 + n_iter sweeps.
+ *   d_best   [G] FP64 the largest estimate seen for each design
+ *   d_alpha1 [G] FP64 the level that gave it (the first one seen on ties)
+ * Near the root the derivative locates the level to the precision of the
+ * derivative, where the golden-section search of bmd_optimize_levels is left
+ * with the square root of the precision of the estimate.  A local search: a
+ * design with several stationary points may end at one that is not the
+ * largest.  The problem's own critical values and rule are restored before
+ * the call returns.  ESTATE for a continuous problem or an alpha design space;
+ * ERANGE for the range, n_iter outside [0, 200] or tol < 0. */
+bmd_status bmd_optimize_levels_newton(bmd_problem *p, uint64_t n_draws, int32_t prec, double a_lo,
+                                      double a_hi, int32_t n_iter, double tol, double *d_best,
+                                      double *d_alpha1, void *stream);
+
 /* Continuous refinement of a design (Sec. 2.3: the best grid point refined by
  * a local gradient method): projected gradient ascent inside the box
  * [q_lo, q_hi]^d on bmd_grad_design's objective (draws 0..n_draws-1 in every
@@ -330,6 +375,59 @@ bmd_status bmd_eval_batch(bmd_problem *const *ps, int32_t n, const uint64_t *n_d
 /* ---- profiling ------------------------------------------------------------ */
 
 #define BMD_PROFILE_PHASES 5
+/* The smoothed surface at a continuous design (the fitted surface of Sec. 2.3,
+ * evaluated between grid points): the Nadaraya-Watson ratio of bmd_smooth,
+ *   S(q) = sum_h K(q, q_h) f_h / sum_h K(q, q_h),
+ * K = prod_j exp(-((q_j - q_{h,j}) / b_j)^2 / 2) over the grid designs h whose
+ * value d_surface[h] (FP64, length G, typically bmd_eval_grid's mean) is not
+ * NaN.  At a grid design it equals bmd_smooth's FP64 output there when no
+ * value is NaN (bmd_smooth propagates NaN except on BMD_DESIGN_ALPHA3/4 grids,
+ * where it skips NaN designs as this call does).
+ *   h_q     [d]    the design (any finite point; the grid's box is its range)
+ *   h_value        S(q)
+ *   h_grad  [d]    dS/dq_j (may be NULL)
+ *   h_hess  [d*d]  d2S/dq_j dq_l, row-major (may be NULL)
+ * FP64 sums over the grid in a fixed order; synchronises the stream.  ERANGE
+ * when no design with a value carries weight at q. */
+bmd_status bmd_smooth_at(bmd_problem *p, const double *d_surface, const double *h_q, double *h_value,
+                         double *h_grad, double *h_hess, void *stream);
+
+/* The best point of the smoothed surface refined by Newton's method (Sec. 2.3:
+ * the best fitted point, then a local Newton search on the fitted surface):
+ * from h_q0 (typically the grid design bmd_argmax returns for bmd_smooth's
+ * output), steps -H^-1 grad S where the surface is locally concave (Cholesky
+ * of -H), else along the gradient by a tenth of the smallest bandwidth; each
+ * step projected into the grid's box and halved until it raises S by the
+ * Armijo fraction 1e-4 of its first-order gain.  Stops after max_iter steps,
+ * when a step moves every coordinate by at most tol, or when no halving is
+ * accepted.  h_q [d] the final design, h_value S there, h_iters the steps
+ * taken.  Synchronises the stream. */
+bmd_status bmd_refine_smoothed(bmd_problem *p, const double *d_surface, const double *h_q0, int32_t max_iter,
+                               double tol, double *h_q, double *h_value, int32_t *h_iters, void *stream);
+
+/* Launch settings of bmd_eval_batch.  Each sweep launch of a batch runs one
+ * kind of problem (d biomarkers; kind 1 the matrix-core tile sweep of grids
+ * with d >= 2 under the step prior and the exact indicator, kind 0 the
+ * one-design-per-thread sweep); its settings are the tile body's draws per
+ * LDS chunk, the rounds of resident workgroups its work list is sliced into
+ * and the kernel's launch-bound variant.  mode 1 (the default): the first
+ * batch that holds a kind on a device, in a precision, tunes its settings on
+ * a calibration run of that batch's problems of the kind (draw counts scaled
+ * to about 4e9 evaluations; chunk, then variant, then rounds, each candidate
+ * timed on the device) and later batches reuse them; mode 0: fixed settings
+ * (the one-problem sweep's chunk, 8 rounds, variant 0); mode 2: forget the
+ * tuned settings (tune again on next use).  The settings change the draw
+ * slicing, so means may differ from the fixed settings' in the last bits of
+ * their FP64 sums.  Process-wide; not to be called while a batch runs. */
+bmd_status bmd_batch_autotune(int32_t mode);
+
+/* The tuned settings of launch kind (d, kind) in precision prec on the current
+ * device: h_out[0] draws per LDS chunk (0 = the one-problem sweep's),
+ * [1] rounds of resident workgroups, [2] launch-bound variant, [3] waves per
+ * SIMD that variant keeps (0 = no bound), [4] the calibration launch's time in
+ * microseconds.  ESTATE when no batch has tuned that kind yet. */
+bmd_status bmd_batch_settings(int32_t prec, int32_t d, int32_t kind, int32_t *h_out /*[5]*/);
+
 /* Turn per-phase timing on (enable != 0) or off.  While on, bmd_eval_grid,
  * bmd_smooth and bmd_argmax record HIP events around their kernels on the
  * stream they launch on. */

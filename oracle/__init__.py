@@ -95,8 +95,9 @@ def lib():
             "or_success": (D, [pp, ctypes.POINTER(_Design), ctypes.POINTER(_Draw)]),
             "or_eval_points": (None, [pp, I64, P, U64, U64, P, P]),
             "or_eval_grid": (None, [pp, I64, P, U64, U64, P, P]),
+            "or_eval_grid_dalpha": (None, [pp, I64, P, U64, U64, P, P]),
             "or_smooth_direct": (None, [pp, P, P]), "or_smooth_separable": (None, [pp, P, P]),
-            "or_smooth_masked": (None, [pp, P, P]),
+            "or_smooth_masked": (None, [pp, P, P]), "or_smooth_at": (D, [pp, P, P]),
             "or_argmax": (I64, [I64, P]),
             "or_grad_points": (None, [pp, I64, P, U64, U64, P, P, P]),
             "or_exact_step": (D, [pp, P]), "or_exact_paper": (D, [pp, P]),
@@ -277,6 +278,18 @@ def eval_grid(prob, g_list, M, k0=0):
     return mean, var
 
 
+def eval_grid_dalpha(prob, g_list, M, k0=0):
+    """Formula 5 estimate and its derivative in the first level alpha_1 at grid
+    designs (Appendix A.3's differentiation under the integral, for the nested
+    pair with rule "split" or "fixed"); returns (mean, dmean)."""
+    s = problem_struct(prob)
+    g = np.ascontiguousarray(g_list, dtype=np.int64)
+    mean = np.zeros(g.size)
+    dmean = np.zeros(g.size)
+    lib().or_eval_grid_dalpha(ctypes.byref(s), g.size, _ptr(g), int(k0), int(M), _ptr(mean), _ptr(dmean))
+    return mean, dmean
+
+
 def smooth_direct(prob, f):
     s = problem_struct(prob)
     f = np.ascontiguousarray(f, dtype=np.float64)
@@ -299,6 +312,15 @@ def smooth_masked(prob, f):
     out = np.zeros_like(f)
     lib().or_smooth_masked(ctypes.byref(s), _ptr(f), _ptr(out))
     return out
+
+
+def smooth_at(prob, f, q):
+    """The Nadaraya-Watson surface of the grid values f at a continuous design q."""
+    s = problem_struct(prob)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    qq = np.zeros(6)
+    qq[: s.d] = q
+    return lib().or_smooth_at(ctypes.byref(s), _ptr(f), _ptr(qq))
 
 
 def argmax(v):
@@ -454,6 +476,62 @@ def optimize_levels(prob, g_list, M, a_lo, a_hi, n_iter):
         fe = f(np.full(n, end))
         up = fe > best
         best[up], best_x[up] = fe[up], end
+    return best, best_x
+
+
+def optimize_levels_newton(prob, g_list, M, a_lo, a_hi, n_iter, tol):
+    """Sec. 2.4's optimal power at each design for n = 2 nested tests, found from
+    the derivative (Sec. 2.3 asks for a derivative-driven search; Appendix A.3
+    gives the derivative): per design, the root of dP/d alpha_1 in [a_lo, a_hi]
+    by the Illinois variant of false position, on the Formula 5 estimate with
+    draws 0..M-1 and the second level on the FWER boundary.  Each probe yields
+    (P, dP/d alpha_1); the largest P seen and its level are kept (the first one
+    on ties after the a_lo probe).  The ends are probed first: a derivative <= 0
+    at a_lo or >= 0 at a_hi puts the maximum at that end and the search stops
+    there.  Otherwise each of the n_iter steps probes the secant root of the
+    bracket's end derivatives (the bracket midpoint if that root is not strictly
+    inside), keeps the end whose derivative has the same sign as at the probe on
+    the other side, and halves the kept end's derivative when the same end was
+    kept twice in a row; a zero derivative or a bracket narrower than tol stops
+    the design.  Returns (best, best_alpha1)."""
+    g_list = np.asarray(g_list, dtype=np.int64)
+    best = np.empty(g_list.size)
+    best_x = np.empty(g_list.size)
+
+    def probe(g, a1):
+        pk = dict(prob, alpha_rule="split", alpha_fixed=(float(a1), 0.0))
+        m, d = eval_grid_dalpha(pk, [g], M)
+        return m[0], d[0]
+
+    for i, g in enumerate(g_list):
+        lo, hi = float(a_lo), float(a_hi)
+        f_lo, g_lo = probe(g, lo)
+        f_hi, g_hi = probe(g, hi)
+        bf, bx = f_lo, lo
+        if f_hi > bf:
+            bf, bx = f_hi, hi
+        if g_lo > 0.0 and g_hi < 0.0:
+            kept = 0   # +1: lo kept last, -1: hi kept last
+            for _ in range(int(n_iter)):
+                x = (lo * g_hi - hi * g_lo) / (g_hi - g_lo)
+                if not (lo < x < hi):
+                    x = 0.5 * (lo + hi)
+                f, d = probe(g, x)
+                if f > bf:
+                    bf, bx = f, x
+                if d > 0.0:        # the root is above x
+                    lo, g_lo = x, d
+                    if kept == -1:
+                        g_hi *= 0.5
+                    kept = -1
+                else:
+                    hi, g_hi = x, d
+                    if kept == 1:
+                        g_lo *= 0.5
+                    kept = 1
+                if d == 0.0 or hi - lo <= tol:
+                    break
+        best[i], best_x[i] = bf, bx
     return best, best_x
 
 

@@ -806,6 +806,66 @@ void or_eval_grid(const or_problem *p, int64_t n, const int64_t *g_list,
 }
 
 /* ======================================================================== */
+/* Derivative in the first level (Appendix A.3, two nested tests)           */
+/* ======================================================================== */
+/*
+ * Appendix A.3 differentiates the power under the integral: with one test,
+ * dP/d alpha = E[phi(z - mu) / phi(z)].  For the nested pair the summand is
+ * 1 - F(z1 - mu1, z2 - mu2), F(h, k) = Phi_2(h, k; rho), and by the chain rule
+ *   d/d alpha_1 = -(dF/dh dz1/d alpha_1 + dF/dk dz2/d alpha_1),
+ * with the textbook partials dF/dh = phi(h) Phi((k - rho h)/s),
+ * dF/dk = phi(k) Phi((h - rho k)/s), s = sqrt(1 - rho^2), and
+ * z1 = Phi^-1(1 - alpha_1), so dz1/d alpha_1 = -1/phi(z1).  A fixed second
+ * level gives dz2/d alpha_1 = 0 (and a switched-off one leaves
+ * F(h, +inf) = Phi(h)); a second level on the FWER boundary, F(z1, z2) =
+ * 1 - alpha0, moves with z1 as dz2/dz1 = -(dF/dh)/(dF/dk) at (z1, z2).
+ */
+static double bvn_dh(double h, double k, double rho)
+{
+    if (isinf(k)) return or_phi(h);
+    return or_phi(h) * or_Phi((k - rho * h) / sqrt(1.0 - rho * rho));
+}
+
+double or_dsuccess_dalpha1(const or_problem *p, const or_design *ds, const or_draw *dr)
+{
+    double d1, d2;
+    effects(p, ds, dr, &d1, &d2, NULL);
+    const double h = ds->z1 - sqrt(p->info) * d1;
+    const double k = ds->z2 - sqrt(ds->r * p->info) * d2;
+    const double dz1 = -1.0 / or_phi(ds->z1);
+    double dz2 = 0.0;
+    if (p->alpha_rule == OR_ALPHA_SPLIT)
+        dz2 = -bvn_dh(ds->z1, ds->z2, ds->rho) / bvn_dh(ds->z2, ds->z1, ds->rho) * dz1;
+    const double dFk = isinf(k) ? 0.0 : bvn_dh(k, h, ds->rho);
+    return -(bvn_dh(h, k, ds->rho) * dz1 + dFk * dz2);
+}
+
+void or_eval_grid_dalpha(const or_problem *p, int64_t n, const int64_t *g_list,
+                         uint64_t k0, uint64_t M, double *mean, double *dmean)
+{
+    or_draw *dr = make_draws(p, k0, M);
+    double *vals = (double *)malloc(sizeof(double) * (size_t)M);
+    double *dv = (double *)malloc(sizeof(double) * (size_t)M);
+    if (!dr || !vals || !dv) { free(dr); free(vals); free(dv); return; }
+    for (int64_t i = 0; i < n; ++i) {
+        double q[6];
+        or_design ds;
+        or_grid_point(p, g_list[i], q, NULL);
+        or_make_design(p, q, &ds);
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t k = 0; k < (int64_t)M; ++k) {
+            vals[k] = or_success(p, &ds, &dr[k]);
+            dv[k] = or_dsuccess_dalpha1(p, &ds, &dr[k]);
+        }
+        mean[i] = pairwise_sum(vals, (int64_t)M) / (double)M;
+        dmean[i] = pairwise_sum(dv, (int64_t)M) / (double)M;
+    }
+    free(dv);
+    free(vals);
+    free(dr);
+}
+
+/* ======================================================================== */
 /* Smoothing and argmax                                                     */
 /* ======================================================================== */
 /*
@@ -871,6 +931,34 @@ void or_smooth_masked(const or_problem *p, const double *in, double *out)
         out[g] = num / den;
     }
     free(q);
+}
+
+/* The smoothed surface at a continuous design q (Sec. 2.3's fitted surface,
+ * evaluated between grid points): the Nadaraya-Watson ratio
+ *   S(q) = sum_h K(q, q_h) f_h / sum_h K(q, q_h),
+ * K = prod_j exp(-((q_j - q_{h,j}) / b_j)^2 / 2) over the grid designs h, the
+ * designs whose value is NaN skipped.  At a grid design it is the value
+ * or_smooth_masked gives there. */
+double or_smooth_at(const or_problem *p, const double *in, const double *q)
+{
+    int d = p->d;
+    int64_t G = or_grid_size(p);
+    double num = 0.0, den = 0.0;
+#pragma omp parallel for reduction(+ : num, den) schedule(static)
+    for (int64_t h = 0; h < G; ++h) {
+        if (isnan(in[h])) continue;
+        double qh[6];
+        or_grid_point(p, h, qh, NULL);
+        double e = 0.0;
+        for (int j = 0; j < d; ++j) {
+            double x = (q[j] - qh[j]) / p->bandwidth[j];
+            e += -0.5 * x * x;
+        }
+        double w = exp(e);
+        num += w * in[h];
+        den += w;
+    }
+    return num / den;
 }
 
 /* The same smoother through its factorisation: the row-normalised product

@@ -130,11 +130,21 @@ void   or_eval_points(const or_problem *p, int64_t n, const double *q,
 void   or_eval_grid(const or_problem *p, int64_t n, const int64_t *g_list,
                     uint64_t k0, uint64_t M, double *mean, double *var);
 
+/* ---- derivative in the first level (Appendix A.3) ----------------------- */
+/* d/d alpha_1 of one summand (cutoff designs, rule SPLIT or FIXED with
+ * alpha_1 > 0): the chain rule through z1 and, under SPLIT, through the
+ * second level on the FWER boundary. */
+double or_dsuccess_dalpha1(const or_problem *p, const or_design *ds, const or_draw *dr);
+/* Formula 5 estimate and its alpha_1 derivative at grid designs g_list[n]. */
+void   or_eval_grid_dalpha(const or_problem *p, int64_t n, const int64_t *g_list,
+                           uint64_t k0, uint64_t M, double *mean, double *dmean);
+
 /* ---- smoothing and argmax ---------------------------------------------- */
 void   or_smooth_direct(const or_problem *p, const double *in, double *out);
 void   or_smooth_separable(const or_problem *p, const double *in, double *out);
 void   or_smooth_masked(const or_problem *p, const double *in, double *out);
 int64_t or_argmax(int64_t n, const double *v);
+double or_smooth_at(const or_problem *p, const double *in, const double *q);   /* at a continuous design */
 
 /* ---- gradient (forward mode, same draws) -------------------------------- */
 void   or_grad_points(const or_problem *p, int64_t n, const double *q,

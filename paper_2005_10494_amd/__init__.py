@@ -81,11 +81,23 @@ SIGNATURES = {
     "bmd_optimize_levels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p]),
+    "bmd_eval_grid_dalpha": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p]),
+    "bmd_optimize_levels_newton": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_double,
+                                                  ctypes.c_double, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p,
+                                                  ctypes.c_void_p, ctypes.c_void_p]),
     "bmd_refine_design": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32,
                                          ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p]),
     "bmd_eval_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "bmd_smooth_at": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "bmd_refine_smoothed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                           ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
+    "bmd_batch_autotune": (ctypes.c_int, [ctypes.c_int32]),
+    "bmd_batch_settings": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
     "bmd_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "bmd_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "bmd_draws": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p,
@@ -259,6 +271,37 @@ class Problem:
                                     ctypes.byref(val), cell, _stream(stream)))
         return int(idx.value), float(val.value), tuple(int(cell[j]) for j in range(self.d))
 
+    def smooth_at(self, surface, q, stream=None):
+        """Smoothed surface at the continuous design q: (value, gradient [d],
+        Hessian [d, d]) (bmd_smooth_at)."""
+        _device_buffer(surface, self.G, self.device, "surface")
+        qq = np.ascontiguousarray(np.asarray(q, dtype=np.float64).ravel())
+        if qq.size != self.d:
+            raise ValueError(f"q has {qq.size} coordinates, the problem {self.d}")
+        val = ctypes.c_double()
+        grad = np.zeros(self.d)
+        hess = np.zeros((self.d, self.d))
+        _check(library().bmd_smooth_at(self._h, ctypes.c_void_p(surface.data_ptr()), qq.ctypes.data_as(ctypes.c_void_p),
+                                       ctypes.byref(val), grad.ctypes.data_as(ctypes.c_void_p),
+                                       hess.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return float(val.value), grad, hess
+
+    def refine_smoothed(self, surface, q0, max_iter: int = 50, tol: float = 1e-9, stream=None):
+        """Newton refinement of the smoothed surface from q0 (bmd_refine_smoothed):
+        returns (design, smoothed value, steps)."""
+        _device_buffer(surface, self.G, self.device, "surface")
+        q0 = np.ascontiguousarray(np.asarray(q0, dtype=np.float64).ravel())
+        if q0.size != self.d:
+            raise ValueError(f"q0 has {q0.size} coordinates, the problem {self.d}")
+        q = np.zeros(self.d)
+        val = ctypes.c_double()
+        it = ctypes.c_int32()
+        _check(library().bmd_refine_smoothed(self._h, ctypes.c_void_p(surface.data_ptr()),
+                                             q0.ctypes.data_as(ctypes.c_void_p), int(max_iter), float(tol),
+                                             q.ctypes.data_as(ctypes.c_void_p), ctypes.byref(val), ctypes.byref(it),
+                                             _stream(stream)))
+        return q, float(val.value), int(it.value)
+
     def grad_design(self, q, n_draws: int, precision="fp32", want_grad=True, stream=None):
         import torch
         q = torch.as_tensor(q).to(device=self.device, dtype=torch.float64).contiguous()
@@ -299,6 +342,31 @@ class Problem:
         _check(library().bmd_optimize_levels(self._h, int(n_draws), _prec(precision), float(a_lo), float(a_hi),
                                              int(n_iter), ctypes.c_void_p(best.data_ptr()),
                                              ctypes.c_void_p(a1.data_ptr()), _stream(stream)))
+        return best, a1
+
+    def eval_grid_dalpha(self, n_draws: int, precision="fp64", stream=None):
+        """Monte Carlo estimate and its derivative in the first level alpha_1 at
+        every grid design (rules "split" and "fixed"); returns (mean, dmean)."""
+        import torch
+        mean = torch.empty(self.G, dtype=torch.float64, device=self.device)
+        dmean = torch.empty(self.G, dtype=torch.float64, device=self.device)
+        _check(library().bmd_eval_grid_dalpha(self._h, int(n_draws), _prec(precision),
+                                              ctypes.c_void_p(mean.data_ptr()), ctypes.c_void_p(dmean.data_ptr()),
+                                              _stream(stream)))
+        return mean, dmean
+
+    def optimize_levels_newton(self, n_draws: int, a_lo: float, a_hi: float, n_iter: int = 20, tol: float = 1e-10,
+                               precision="fp64", stream=None):
+        """Per-design root of the power's alpha_1 derivative over [a_lo, a_hi]
+        (false position, second level on each design's FWER boundary); returns
+        (best power, its first level) per design."""
+        import torch
+        best = torch.empty(self.G, dtype=torch.float64, device=self.device)
+        a1 = torch.empty(self.G, dtype=torch.float64, device=self.device)
+        _check(library().bmd_optimize_levels_newton(self._h, int(n_draws), _prec(precision), float(a_lo),
+                                                    float(a_hi), int(n_iter), float(tol),
+                                                    ctypes.c_void_p(best.data_ptr()), ctypes.c_void_p(a1.data_ptr()),
+                                                    _stream(stream)))
         return best, a1
 
     def refine_design(self, q0, n_draws: int, precision="fp64", max_iter=50, tol=1e-6, stream=None):
@@ -362,3 +430,21 @@ def eval_batch(problems, n_draws, precision="fp32", stream=None):
     _check(library().bmd_eval_batch(handles, n, draws, _prec(precision), ptrs,
                                     wall.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
     return outs, wall
+
+
+def batch_autotune(mode: int):
+    """bmd_batch_autotune: 1 tune each batch launch kind on first use (the
+    default), 0 fixed settings, 2 forget the tuned settings."""
+    _check(library().bmd_batch_autotune(int(mode)))
+
+
+def batch_settings(precision, d: int, kind: int):
+    """bmd_batch_settings: the tuned settings of launch kind (d, kind) on the
+    current device as a dict, or None when no batch has tuned it yet."""
+    out = (ctypes.c_int32 * 5)()
+    st = library().bmd_batch_settings(_prec(precision), int(d), int(kind), out)
+    if st == -6:
+        return None
+    _check(st)
+    return {"chunk": out[0], "rounds": out[1], "variant": out[2], "waves_per_simd": out[3],
+            "calibration_us": out[4]}

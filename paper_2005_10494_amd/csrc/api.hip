@@ -1,11 +1,13 @@
 // C ABI of libbmd: argument validation, problem construction, workspace
 // management and the launch sequence of each entry point (see include/bmd.h).
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -22,6 +24,10 @@ hipError_t launch_smooth_masked(const bmd_problem* p, int prec, const double* in
 // (end: 0 the next golden point, 1 the range's lower end, 2 its upper end).
 hipError_t launch_levels_golden(const bmd_problem* p, int phase, bool probe, int end, double a_lo, double a_hi,
                                 const double* mean, double* st, int32_t* side, hipStream_t s);
+// One step of the derivative-driven level search (kernels_setup.hip): st
+// [9][G] search state; writes the problem's z1, z2 for the next probe.
+hipError_t launch_levels_newton(const bmd_problem* p, int phase, double a_lo, double a_hi, double tol,
+                                const double* mean, const double* dmean, double* st, hipStream_t s);
 }  // namespace bmd
 
 using namespace bmd;
@@ -648,6 +654,29 @@ bmd_status bmd_eval_grid_noalloc(bmd_problem* p, uint64_t n_draws, int32_t prec,
     return eval_grid_into(p, prec, M, n_slices, slice_len, ws, draw_bytes, d_mean, d_var, s);
 }
 
+// The level searches write a finite first critical value and a second one on
+// the FWER boundary for every probe; their sweeps run under the split rule
+// (no test switched off, the derivative's dz2/dz1 term on), and the
+// problem's own rule comes back on restore() or at scope exit.  Kernel
+// arguments are copied at launch, so restoring after the launches is safe.
+struct SplitRuleScope {
+    bmd_problem* p;
+    int rule, zinf;
+    bool on = true;
+    explicit SplitRuleScope(bmd_problem* q) : p(q), rule(q->P.alpha_rule), zinf(q->P.zinf) {
+        p->P.alpha_rule = BMD_ALPHA_SPLIT;
+        p->P.zinf = 0;
+    }
+    void restore() {
+        if (on) {
+            p->P.alpha_rule = rule;
+            p->P.zinf = zinf;
+            on = false;
+        }
+    }
+    ~SplitRuleScope() { restore(); }
+};
+
 bmd_status bmd_optimize_levels(bmd_problem* p, uint64_t n_draws, int32_t prec, double a_lo, double a_hi,
                                int32_t n_iter, double* d_best, double* d_alpha1, void* stream) {
     g_err.clear();
@@ -680,6 +709,9 @@ bmd_status bmd_optimize_levels(bmd_problem* p, uint64_t n_draws, int32_t prec, d
     double* state = reinterpret_cast<double*>(base + draw_bytes + part_bytes + mean_bytes);
     int32_t* side = reinterpret_cast<int32_t*>(base + draw_bytes + part_bytes + mean_bytes + state_bytes);
     HIP_TRY(launch_draws(p, prec, 0, M, p->d_ws, s), "draw kernel");
+    // every probe has both critical values finite and the second on the FWER
+    // boundary, whatever the problem's own rule
+    SplitRuleScope split(p);
     hipError_t e = hipSuccess;
     // two interior points, n_iter golden steps, then the two ends of the range
     const int n_sweeps = 4 + n_iter;
@@ -693,6 +725,88 @@ bmd_status bmd_optimize_levels(bmd_problem* p, uint64_t n_draws, int32_t prec, d
     }
     if (e == hipSuccess) e = hipMemcpyAsync(d_best, state + 6 * G, sizeof(double) * G, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_alpha1, state + 7 * G, sizeof(double) * G, hipMemcpyDeviceToDevice, s);
+    split.restore();
+    // the problem's own critical values, whatever happened above
+    const hipError_t er = launch_design_precompute(p, s);
+    HIP_TRY(e, "level search");
+    HIP_TRY(er, "design precompute");
+    return BMD_OK;
+}
+
+bmd_status bmd_eval_grid_dalpha(bmd_problem* p, uint64_t n_draws, int32_t prec, double* d_mean, double* d_dmean,
+                                void* stream) {
+    g_err.clear();
+    if (!p) return fail(BMD_EINVAL, "problem is NULL");
+    if (!p->grid || p->P.design_space != BMD_DESIGN_CUTOFFS)
+        return fail(BMD_ESTATE, "the alpha_1 derivative needs a grid of cutoff designs");
+    if (p->P.alpha_rule != BMD_ALPHA_SPLIT && p->P.alpha_rule != BMD_ALPHA_FIXED)
+        return fail(BMD_ENOTSUP, "the alpha_1 derivative needs rule BMD_ALPHA_SPLIT or BMD_ALPHA_FIXED");
+    if (!(p->desc.alpha_fixed[0] > 0.0)) return fail(BMD_ERANGE, "the first level alpha_1 must be > 0");
+    if (!valid_prec(prec)) return fail(BMD_EINVAL, "unknown precision %d", prec);
+    if (!d_mean || !d_dmean) return fail(BMD_EINVAL, "NULL d_mean or d_dmean");
+    if (n_draws == 0 || n_draws > (1ull << 40)) return fail(BMD_ERANGE, "n_draws must be in [1, 2^40]");
+    DeviceGuard guard(p->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t M = static_cast<int64_t>(n_draws);
+    int64_t n_slices = 0, slice_len = 0;
+    sweep_slices(p, prec, M, &n_slices, &slice_len);
+    const size_t draw_bytes = (draw_workspace_bytes(p, prec, M) + 255) / 256 * 256;
+    const size_t part_bytes = sizeof(double) * 2 * static_cast<size_t>(p->P.G) * n_slices;
+    bmd_status st = ensure(&p->d_ws, &p->ws_cap, draw_bytes + part_bytes);
+    if (st != BMD_OK) return st;
+    double* partials = reinterpret_cast<double*>(static_cast<char*>(p->d_ws) + draw_bytes);
+    HIP_TRY(launch_draws(p, prec, 0, M, p->d_ws, s), "draw kernel");
+    HIP_TRY(launch_eval_grid_dalpha(p, prec, M, p->d_ws, partials, static_cast<int>(n_slices), slice_len, s),
+            "derivative sweep");
+    HIP_TRY(launch_finalize_dalpha(p, M, partials, static_cast<int>(n_slices), d_mean, d_dmean, s), "finalize kernel");
+    return BMD_OK;
+}
+
+bmd_status bmd_optimize_levels_newton(bmd_problem* p, uint64_t n_draws, int32_t prec, double a_lo, double a_hi,
+                                      int32_t n_iter, double tol, double* d_best, double* d_alpha1, void* stream) {
+    g_err.clear();
+    if (!p) return fail(BMD_EINVAL, "problem is NULL");
+    if (!p->grid || p->P.design_space != BMD_DESIGN_CUTOFFS)
+        return fail(BMD_ESTATE, "level search needs a grid of cutoff designs");
+    if (!valid_prec(prec)) return fail(BMD_EINVAL, "unknown precision %d", prec);
+    if (!d_best || !d_alpha1) return fail(BMD_EINVAL, "NULL d_best or d_alpha1");
+    if (!std::isfinite(a_lo) || !std::isfinite(a_hi) || !(0.0 < a_lo && a_lo < a_hi && a_hi < p->P.alpha0))
+        return fail(BMD_ERANGE, "need 0 < a_lo < a_hi < alpha0");
+    if (n_iter < 0 || n_iter > 200 || !(tol >= 0.0)) return fail(BMD_ERANGE, "n_iter in [0, 200] and tol >= 0");
+    if (n_draws == 0 || n_draws > (1ull << 40)) return fail(BMD_ERANGE, "n_draws must be in [1, 2^40]");
+    DeviceGuard guard(p->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t M = static_cast<int64_t>(n_draws);
+    const int64_t G = p->P.G;
+    int64_t n_slices = 0, slice_len = 0;
+    sweep_slices(p, prec, M, &n_slices, &slice_len);
+    const size_t al = 256;
+    const size_t draw_bytes = (draw_workspace_bytes(p, prec, M) + al - 1) / al * al;
+    const size_t part_bytes = (sizeof(double) * 2 * static_cast<size_t>(G) * n_slices + al - 1) / al * al;
+    const size_t mean_bytes = (sizeof(double) * static_cast<size_t>(G) + al - 1) / al * al;
+    const size_t state_bytes = sizeof(double) * 9 * static_cast<size_t>(G);
+    bmd_status st = ensure(&p->d_ws, &p->ws_cap, draw_bytes + part_bytes + 2 * mean_bytes + state_bytes);
+    if (st != BMD_OK) return st;
+    char* base = static_cast<char*>(p->d_ws);
+    double* partials = reinterpret_cast<double*>(base + draw_bytes);
+    double* mean = reinterpret_cast<double*>(base + draw_bytes + part_bytes);
+    double* dmean = reinterpret_cast<double*>(base + draw_bytes + part_bytes + mean_bytes);
+    double* state = reinterpret_cast<double*>(base + draw_bytes + part_bytes + 2 * mean_bytes);
+    HIP_TRY(launch_draws(p, prec, 0, M, p->d_ws, s), "draw kernel");
+    SplitRuleScope split(p);   // probes as in bmd_optimize_levels
+    hipError_t e = hipSuccess;
+    // the two ends of the range, then n_iter false-position steps
+    const int n_sweeps = 2 + n_iter;
+    for (int ph = 0; ph <= n_sweeps && e == hipSuccess; ++ph) {
+        e = launch_levels_newton(p, ph, a_lo, a_hi, tol, mean, dmean, state, s);
+        if (e == hipSuccess && ph < n_sweeps)
+            e = launch_eval_grid_dalpha(p, prec, M, p->d_ws, partials, static_cast<int>(n_slices), slice_len, s);
+        if (e == hipSuccess && ph < n_sweeps)
+            e = launch_finalize_dalpha(p, M, partials, static_cast<int>(n_slices), mean, dmean, s);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(d_best, state + 5 * G, sizeof(double) * G, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_alpha1, state + 6 * G, sizeof(double) * G, hipMemcpyDeviceToDevice, s);
+    split.restore();
     // the problem's own critical values, whatever happened above
     const hipError_t er = launch_design_precompute(p, s);
     HIP_TRY(e, "level search");
@@ -852,51 +966,87 @@ struct BatchPlan {
     size_t draw_bytes = 0, part_bytes = 0;
 };
 
-// One group of consecutive problems: draws, sweeps and finalize of the group
-// captured in one graph and launched once.  Slices are sized so that a launch
-// holds about kSweepRounds workgroups per resident slot.
-bmd_status run_batch_group(bmd_problem* const* ps, const std::vector<BatchPlan>& plan, int first, int last, int prec,
-                           double* const* d_means, int n_cu, hipStream_t cs, unsigned long long* d_tstart,
-                           unsigned long long* d_tdone, int* d_left, bool restart_clock) {
-    const int n = last - first;
-    std::vector<BatchPlan> pl(plan.begin() + first, plan.begin() + last);
-    // Launch groups: the problems of one (d, kernel kind), planned together.
+// Launch settings of one sweep launch kind (biomarker count, kernel kind) of
+// a batch: the tile body's draws per LDS chunk, how many rounds of resident
+// workgroups the launch's work list is sliced into, and the kernel's
+// launch-bound variant.  Chosen per device and precision by the autotuner
+// (tune_phase) on first use, or fixed.
+struct BatchSettings {
+    int chunk = 0;                 // 0: the one-problem sweep's chunk
+    int rounds = kSweepRounds;
+    int variant = 0;
+    bool tuned = false;
+    double ms = 0.0;               // calibration time of the chosen settings
+};
+using TuneKey = std::array<int, 3>;   // device, precision, launch key
+std::mutex g_tune_mu;
+std::map<TuneKey, BatchSettings> g_tune;
+int g_tune_mode = 1;                  // 1: tune each launch kind on first use; 0: fixed settings
+
+// One sweep launch of a group: its problems (indices into the group's plans),
+// kernel variant, LDS and the slicing of its members.
+struct Phase {
+    int key = 0, rep = -1;   // rep: a problem of the phase (index in the group)
+    size_t lds = 0;
+    int grid = 0;
+    BatchSettings set;
+    std::vector<int> members;
+};
+
+// Plans the phases of the problems ps[0..n) with plans pl (slices written
+// into pl): per launch key the settings of `sets` (defaults when absent).
+// chunk < 0 marks a chunk that does not fit the LDS limit: false.
+bool plan_phases(bmd_problem* const* ps, std::vector<BatchPlan>& pl, int prec, int n_cu,
+                 const std::map<int, BatchSettings>& sets, std::vector<Phase>* out) {
+    const int n = static_cast<int>(pl.size());
     std::vector<int> keys;
     for (const auto& b : pl)
         if (std::find(keys.begin(), keys.end(), b.key) == keys.end()) keys.push_back(b.key);
     std::sort(keys.begin(), keys.end());
-    struct Phase {
-        int key, rep;          // rep: a problem of the phase (index in the group)
-        size_t lds;
-        int grid;
-        std::vector<int> members;
-    };
-    std::vector<Phase> phases;
     for (int key : keys) {
-        Phase ph{key, -1, 0, 0, {}};
+        Phase ph;
+        ph.key = key;
+        auto it = sets.find(key);
+        if (it != sets.end()) ph.set = it->second;
         for (int i = 0; i < n; ++i)
             if (pl[i].key == key) {
                 ph.members.push_back(i);
                 if (ph.rep < 0) ph.rep = i;
-                ph.lds = std::max(ph.lds, batch_phase_lds(ps[first + i], prec));
+                ph.lds = std::max(ph.lds, batch_phase_lds(ps[i], prec, ph.set.chunk));
             }
-        const int bpc = batch_phase_blocks_per_cu(ps[first + ph.rep], prec, ph.lds);
+        if (ph.lds > 64 * 1024) return false;
+        const int bpc = batch_phase_blocks_per_cu(ps[ph.rep], prec, ph.lds, ph.set.variant);
         ph.grid = n_cu * bpc;
-        // Slices: about kSweepRounds items per resident workgroup over the phase.
+        // Slices: about `rounds` items per resident workgroup over the phase.
         double work = 0.0;
         for (int i : ph.members) work += static_cast<double>(pl[i].tiles) * kEvalBlock * pl[i].M;
-        const double target = work / (static_cast<double>(kSweepRounds) * ph.grid) / kEvalBlock;
+        const double target = work / (static_cast<double>(ph.set.rounds) * ph.grid) / kEvalBlock;
         for (int i : ph.members) {
             BatchPlan& b = pl[i];
-            const int64_t Mr = (b.M + b.chunk - 1) / b.chunk * b.chunk;
-            int64_t L = static_cast<int64_t>(std::ceil(std::max(target, 64.0) / b.chunk)) * b.chunk;
-            L = std::max<int64_t>(b.chunk, std::min<int64_t>(L, Mr));
+            const int64_t ch = ph.set.chunk > 0 && b.chunk > 1 ? ph.set.chunk : b.chunk;
+            const int64_t Mr = (b.M + ch - 1) / ch * ch;
+            int64_t L = static_cast<int64_t>(std::ceil(std::max(target, 64.0) / ch)) * ch;
+            L = std::max<int64_t>(ch, std::min<int64_t>(L, Mr));
             b.slice_len = L;
             b.n_slices = (b.M + L - 1) / L;
             b.part_bytes = align256(sizeof(double) * 2 * static_cast<size_t>(b.G) * b.n_slices);
         }
-        phases.push_back(std::move(ph));
+        out->push_back(std::move(ph));
     }
+    return true;
+}
+
+// One group of problems ps[0..n) (batch indices first..first+n): draws,
+// sweeps and finalize, captured in one graph and launched once (capture), or
+// launched one by one with the sweep launches timed (phase_ms, per phase).
+// Slices follow each launch kind's settings.
+bmd_status run_batch_group(bmd_problem* const* ps, std::vector<BatchPlan> pl, int first, int prec,
+                           double* const* d_means, int n_cu, hipStream_t cs, unsigned long long* d_tstart,
+                           unsigned long long* d_tdone, int* d_left, bool restart_clock,
+                           const std::map<int, BatchSettings>& sets, bool capture, std::vector<double>* phase_ms) {
+    const int n = static_cast<int>(pl.size());
+    std::vector<Phase> phases;
+    if (!plan_phases(ps, pl, prec, n_cu, sets, &phases)) return fail(BMD_ERANGE, "batch chunk exceeds the LDS limit");
     // Work lists, costliest items first (the ragged last slice of a problem is cheaper).
     struct Item {
         int4 v;
@@ -944,14 +1094,17 @@ bmd_status run_batch_group(bmd_problem* const* ps, const std::vector<BatchPlan>&
     char* base = static_cast<char*>(buf.ptr);
     std::vector<char> host(o_draw.empty() ? o_ctr : o_draw[0], 0);   // everything before the draws
     std::vector<BatchFinal> fin(n);
+    std::vector<int> chunk_of(n, 0);
+    for (const Phase& ph : phases)
+        for (int i : ph.members) chunk_of[i] = ph.set.chunk;
     int64_t draws_total = 0, designs_total = 0;
     for (int i = 0; i < n; ++i) {
-        bmd_problem* p = ps[first + i];
+        bmd_problem* p = ps[i];
         double* part = reinterpret_cast<double*>(base + o_part[i]);
         batch_fill_record(prec, host.data() + o_rec + rec_b * i, p, base + o_draw[i], pl[i].M, pl[i].slice_len, part,
-                          first + i);
+                          first + i, chunk_of[i]);
         fill_draw_job(prec, host.data() + o_job + job_b * i, p, base + o_draw[i], pl[i].M, draws_total);
-        fin[i] = BatchFinal{designs_total, pl[i].G, pl[i].M, static_cast<int>(pl[i].n_slices), part, d_means[first + i]};
+        fin[i] = BatchFinal{designs_total, pl[i].G, pl[i].M, static_cast<int>(pl[i].n_slices), part, d_means[i]};
         draws_total += pl[i].M;
         designs_total += pl[i].G;
     }
@@ -967,21 +1120,51 @@ bmd_status run_batch_group(bmd_problem* const* ps, const std::vector<BatchPlan>&
     HIP_TRY(hipMemcpy(base, host.data(), host.size(), hipMemcpyHostToDevice), "batch upload");
 
     const int* d_items_per = reinterpret_cast<const int*>(base + o_ctr);
+    auto launches = [&](std::vector<hipEvent_t>* ev) -> hipError_t {
+        hipError_t le =
+            launch_batch_reset(d_left, d_tdone, d_items_per, first, n, restart_clock ? d_tstart : nullptr, cs);
+        if (le == hipSuccess) le = launch_draws_batch(prec, base + o_job, n, draws_total, cs);
+        size_t k = 0;
+        for (size_t f = 0; f < phases.size() && le == hipSuccess; ++f) {
+            // records are indexed within the group; left / t_done by batch index
+            BatchPhase ph{base + o_rec, reinterpret_cast<const int4*>(base + o_items) + k,
+                          static_cast<int>(lists[f].size()), d_left, d_tstart, d_tdone};
+            if (ev) le = hipEventRecord((*ev)[2 * f], cs);
+            if (le == hipSuccess)
+                le = launch_batch_phase(ps[phases[f].rep], prec, ph, phases[f].lds, phases[f].set.variant, cs);
+            if (ev && le == hipSuccess) le = hipEventRecord((*ev)[2 * f + 1], cs);
+            k += lists[f].size();
+        }
+        if (le == hipSuccess)
+            le = launch_batch_finalize(reinterpret_cast<const BatchFinal*>(base + o_fin), n, designs_total, cs);
+        return le;
+    };
+    if (!capture) {
+        std::vector<hipEvent_t> ev(2 * phases.size(), nullptr);
+        for (auto& e : ev) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+        struct EventsGuard {
+            std::vector<hipEvent_t>& v;
+            ~EventsGuard() {
+                for (auto e : v)
+                    if (e) (void)hipEventDestroy(e);
+            }
+        } eg{ev};
+        HIP_TRY(launches(&ev), "batch launches");
+        HIP_TRY(hipStreamSynchronize(cs), "batch sync");
+        if (phase_ms) {
+            phase_ms->assign(phases.size(), 0.0);
+            for (size_t f = 0; f < phases.size(); ++f) {
+                float ms = 0.0f;
+                HIP_TRY(hipEventElapsedTime(&ms, ev[2 * f], ev[2 * f + 1]), "batch timing");
+                (*phase_ms)[f] = ms;
+            }
+        }
+        return BMD_OK;
+    }
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-    hipError_t le = launch_batch_reset(d_left, d_tdone, d_items_per, first, n, restart_clock ? d_tstart : nullptr, cs);
-    if (le == hipSuccess) le = launch_draws_batch(prec, base + o_job, n, draws_total, cs);
-    size_t k = 0;
-    for (size_t f = 0; f < phases.size() && le == hipSuccess; ++f) {
-        // records are indexed within the group; left / t_done by batch index
-        BatchPhase ph{base + o_rec, reinterpret_cast<const int4*>(base + o_items) + k, static_cast<int>(lists[f].size()),
-                      d_left, d_tstart, d_tdone};
-        le = launch_batch_phase(ps[first + phases[f].rep], prec, ph, phases[f].lds, cs);
-        k += lists[f].size();
-    }
-    if (le == hipSuccess)
-        le = launch_batch_finalize(reinterpret_cast<const BatchFinal*>(base + o_fin), n, designs_total, cs);
+    const hipError_t le = launches(nullptr);
     hipError_t ce = hipStreamEndCapture(cs, &graph);
     if (le != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -995,6 +1178,177 @@ bmd_status run_batch_group(bmd_problem* const* ps, const std::vector<BatchPlan>&
     (void)hipGraphDestroy(graph);
     HIP_TRY(e, "batch graph");
     return BMD_OK;
+}
+
+// Autotuner of one launch kind: its problems ps[0..n) (plans pl) run with
+// their draw counts scaled down to a calibration workload of about
+// kTuneEvals evaluations, launched directly and timed with HIP events; the
+// draws per LDS chunk, then the launch-bound variant, then the rounds of
+// resident workgroups are searched in turn (coordinate descent from the
+// fixed settings), each candidate timed twice and its faster run kept.
+constexpr double kTuneEvals = 4e9;
+bmd_status tune_phase(bmd_problem* const* ps, std::vector<BatchPlan> pl, int prec, int n_cu, hipStream_t cs,
+                      unsigned long long* d_tstart, unsigned long long* d_tdone, int* d_left, BatchSettings* best) {
+    const int n = static_cast<int>(pl.size());
+    const int key = pl[0].key;
+    double work = 0.0;
+    for (const auto& b : pl) work += static_cast<double>(b.G) * static_cast<double>(b.M);
+    const double scale = std::min(1.0, kTuneEvals / std::max(work, 1.0));
+    int64_t G_total = 0;
+    for (int i = 0; i < n; ++i) {
+        BatchPlan& b = pl[i];
+        b.M = std::max<int64_t>(std::min<int64_t>(b.M, 256), static_cast<int64_t>(std::ceil(b.M * scale)));
+        b.draw_bytes = align256(draw_workspace_bytes(ps[i], prec, b.M));
+        G_total += b.G;
+    }
+    DeviceBuffer means;
+    {
+        const hipError_t e = hipMalloc(&means.ptr, sizeof(double) * std::max<int64_t>(G_total, 1));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(BMD_ENOMEM, "batch tuning buffers: %s", hipGetErrorString(e));
+        }
+    }
+    std::vector<double*> mp(n);
+    {
+        int64_t o = 0;
+        for (int i = 0; i < n; ++i) {
+            mp[i] = static_cast<double*>(means.ptr) + o;
+            o += pl[i].G;
+        }
+    }
+    auto time_of = [&](const BatchSettings& c, double* ms) -> bmd_status {
+        std::map<int, BatchSettings> sets{{key, c}};
+        double t = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+            std::vector<double> phase_ms;
+            bmd_status st = run_batch_group(ps, pl, 0, prec, mp.data(), n_cu, cs, d_tstart, d_tdone, d_left, true,
+                                            sets, false, &phase_ms);
+            if (st != BMD_OK) return st;
+            t = std::min(t, phase_ms.empty() ? 0.0 : phase_ms[0]);
+        }
+        *ms = t;
+        return BMD_OK;
+    };
+    const bool mf = pl[0].chunk > 1;
+    const int step = prec == BMD_FP64 ? 4 : 8;
+    std::vector<int> chunks;
+    if (mf)
+        for (int c = step; c <= 32; c += step) chunks.push_back(c);
+    else
+        chunks.push_back(0);
+    const int n_var = batch_variants(ps[0], prec);
+    BatchSettings cur;   // the fixed settings
+    double t_cur = 0.0;
+    bmd_status st = time_of(cur, &t_cur);
+    if (st != BMD_OK) return st;
+    auto consider = [&](BatchSettings c) -> bmd_status {
+        // candidates whose LDS does not fit are skipped
+        for (int i = 0; i < n; ++i)
+            if (batch_phase_lds(ps[i], prec, c.chunk) > 64 * 1024) return BMD_OK;
+        double t = 0.0;
+        const bmd_status s2 = time_of(c, &t);
+        if (s2 != BMD_OK) return s2;
+        if (t < t_cur) {
+            cur = c;
+            t_cur = t;
+        }
+        return BMD_OK;
+    };
+    for (int c : chunks) {
+        BatchSettings x = cur;
+        x.chunk = c;
+        if ((st = consider(x)) != BMD_OK) return st;
+    }
+    for (int v = 0; v < n_var; ++v) {
+        BatchSettings x = cur;
+        x.variant = v;
+        if ((st = consider(x)) != BMD_OK) return st;
+    }
+    for (int r : {2, 4, 16}) {
+        BatchSettings x = cur;
+        x.rounds = r;
+        if ((st = consider(x)) != BMD_OK) return st;
+    }
+    cur.tuned = true;
+    cur.ms = t_cur;
+    *best = cur;
+    return BMD_OK;
+}
+
+// Value, gradient and Hessian of the smoothed surface at the continuous
+// design q (sums from launch_smooth_local); synchronises the stream.
+bmd_status smoothed_at(bmd_problem* p, const double* d_surface, const double* q, double* S, double* g, double* H,
+                       hipStream_t s) {
+    const int d = p->P.d;
+    bmd_status st = ensure(&p->d_ws2, &p->ws2_cap, smooth_local_bytes() + 2 * kMaxDim * kMaxDim * sizeof(double) + 1024);
+    if (st != BMD_OK) return st;
+    double lo[kMaxDim], hi[kMaxDim];
+    for (int j = 0; j < d; ++j) axis_range(p->desc, j, &lo[j], &hi[j]);
+    double* ws = static_cast<double*>(p->d_ws2);
+    double* out = ws + smooth_local_bytes() / sizeof(double);
+    HIP_TRY(launch_smooth_local(p, d_surface, q, lo, hi, ws, out, s), "smoothing at a point");
+    const int na = 1 + d + d * (d + 1) / 2;
+    double acc[2 * (1 + kMaxDim + kMaxDim * (kMaxDim + 1) / 2)];
+    HIP_TRY(hipMemcpyAsync(acc, out, sizeof(double) * 2 * na, hipMemcpyDeviceToHost, s), "smoothing readback");
+    HIP_TRY(hipStreamSynchronize(s), "smoothing sync");
+    const double* F = acc;
+    const double* W = acc + na;
+    if (!(W[0] > 0.0)) return fail(BMD_ERANGE, "no design with a value carries weight at this point");
+    double Nj[kMaxDim], Dj[kMaxDim], Njl[kMaxDim][kMaxDim], Djl[kMaxDim][kMaxDim];
+    int k = 1 + d;
+    for (int j = 0; j < d; ++j) {
+        Nj[j] = F[1 + j];
+        Dj[j] = W[1 + j];
+        for (int l = j; l < d; ++l, ++k) {
+            Njl[j][l] = Njl[l][j] = F[k];
+            Djl[j][l] = Djl[l][j] = W[k];
+        }
+    }
+    for (int j = 0; j < d; ++j) {   // d2K/dq_j^2 also has -K / b_j^2
+        const double b2 = p->desc.bandwidth[j] * p->desc.bandwidth[j];
+        Njl[j][j] -= F[0] / b2;
+        Djl[j][j] -= W[0] / b2;
+    }
+    const double D0 = W[0], val = F[0] / D0;
+    double gg[kMaxDim];
+    for (int j = 0; j < d; ++j) gg[j] = (Nj[j] - val * Dj[j]) / D0;
+    *S = val;
+    if (g)
+        for (int j = 0; j < d; ++j) g[j] = gg[j];
+    if (H)
+        for (int j = 0; j < d; ++j)
+            for (int l = 0; l < d; ++l)
+                H[j * d + l] = (Njl[j][l] - val * Djl[j][l] - gg[j] * Dj[l] - gg[l] * Dj[j]) / D0;
+    return BMD_OK;
+}
+
+// Solve (-H) x = g by Cholesky; false when -H is not positive definite.
+bool newton_direction(int d, const double* H, const double* g, double* x) {
+    double L[kMaxDim][kMaxDim] = {};
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double sum = -H[i * d + j];
+            for (int k = 0; k < j; ++k) sum -= L[i][k] * L[j][k];
+            if (i == j) {
+                if (!(sum > 0.0)) return false;
+                L[i][i] = std::sqrt(sum);
+            } else {
+                L[i][j] = sum / L[j][j];
+            }
+        }
+    double y[kMaxDim];
+    for (int i = 0; i < d; ++i) {
+        double sum = g[i];
+        for (int k = 0; k < i; ++k) sum -= L[i][k] * y[k];
+        y[i] = sum / L[i][i];
+    }
+    for (int i = d - 1; i >= 0; --i) {
+        double sum = y[i];
+        for (int k = i + 1; k < d; ++k) sum -= L[k][i] * x[k];
+        x[i] = sum / L[i][i];
+    }
+    return true;
 }
 
 }  // namespace
@@ -1079,6 +1433,80 @@ bmd_status bmd_refine_design(bmd_problem* p, const double* h_q0, uint64_t n_draw
     return BMD_OK;
 }
 
+bmd_status bmd_smooth_at(bmd_problem* p, const double* d_surface, const double* h_q, double* h_value,
+                         double* h_grad, double* h_hess, void* stream) {
+    g_err.clear();
+    if (!p) return fail(BMD_EINVAL, "problem is NULL");
+    if (!p->grid) return fail(BMD_ESTATE, "smooth_at needs a grid problem");
+    if (!d_surface || !h_q || !h_value) return fail(BMD_EINVAL, "NULL pointer argument");
+    for (int j = 0; j < p->P.d; ++j)
+        if (!std::isfinite(h_q[j])) return fail(BMD_EINVAL, "q[%d] is not finite", j);
+    DeviceGuard guard(p->device);
+    return smoothed_at(p, d_surface, h_q, h_value, h_grad, h_hess, static_cast<hipStream_t>(stream));
+}
+
+bmd_status bmd_refine_smoothed(bmd_problem* p, const double* d_surface, const double* h_q0, int32_t max_iter,
+                               double tol, double* h_q, double* h_value, int32_t* h_iters, void* stream) {
+    g_err.clear();
+    if (!p) return fail(BMD_EINVAL, "problem is NULL");
+    if (!p->grid) return fail(BMD_ESTATE, "refine_smoothed needs a grid problem");
+    if (!d_surface || !h_q0 || !h_q || !h_value || !h_iters) return fail(BMD_EINVAL, "NULL pointer argument");
+    if (max_iter < 0 || max_iter > 10000 || !(tol >= 0.0)) return fail(BMD_ERANGE, "max_iter or tol out of range");
+    const int d = p->P.d;
+    double lo[kMaxDim], hi[kMaxDim], bmin = 1e300;
+    for (int j = 0; j < d; ++j) {
+        axis_range(p->desc, j, &lo[j], &hi[j]);
+        if (!std::isfinite(h_q0[j])) return fail(BMD_EINVAL, "q0[%d] is not finite", j);
+        bmin = std::min(bmin, p->desc.bandwidth[j]);
+    }
+    DeviceGuard guard(p->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    constexpr double kArmijo = 1e-4;
+    double q[kMaxDim], g[kMaxDim], H[kMaxDim * kMaxDim], f = 0.0;
+    for (int j = 0; j < d; ++j) q[j] = std::min(hi[j], std::max(lo[j], h_q0[j]));
+    bmd_status st = smoothed_at(p, d_surface, q, &f, g, H, s);
+    if (st != BMD_OK) return st;
+    int it = 0;
+    while (it < max_iter) {
+        // Newton direction where the surface is locally concave, else the
+        // gradient scaled to a tenth of the smallest bandwidth
+        double dir[kMaxDim];
+        if (!newton_direction(d, H, g, dir)) {
+            double gn = 0.0;
+            for (int j = 0; j < d; ++j) gn = std::max(gn, std::fabs(g[j]));
+            if (gn == 0.0) break;
+            for (int j = 0; j < d; ++j) dir[j] = 0.1 * bmin * g[j] / gn;
+        }
+        double t = 1.0, qn[kMaxDim], fn = 0.0, gnext[kMaxDim], Hn[kMaxDim * kMaxDim];
+        bool ok = false;
+        for (int bt = 0; bt < 40 && !ok; ++bt, t *= 0.5) {
+            double slope = 0.0;
+            for (int j = 0; j < d; ++j) {
+                qn[j] = std::min(hi[j], std::max(lo[j], q[j] + t * dir[j]));
+                slope += g[j] * (qn[j] - q[j]);
+            }
+            st = smoothed_at(p, d_surface, qn, &fn, gnext, Hn, s);
+            if (st != BMD_OK) return st;
+            ok = fn >= f + kArmijo * slope && slope >= 0.0;
+        }
+        if (!ok) break;
+        ++it;
+        double move = 0.0;
+        for (int j = 0; j < d; ++j) {
+            move = std::max(move, std::fabs(qn[j] - q[j]));
+            q[j] = qn[j];
+            g[j] = gnext[j];
+        }
+        std::copy(Hn, Hn + d * d, H);
+        f = fn;
+        if (move <= tol) break;
+    }
+    for (int j = 0; j < d; ++j) h_q[j] = q[j];
+    *h_value = f;
+    *h_iters = it;
+    return BMD_OK;
+}
+
 bmd_status bmd_eval_batch(bmd_problem* const* ps, int32_t n, const uint64_t* n_draws, int32_t prec,
                           double* const* d_means, double* h_wall_ms, void* stream) {
     g_err.clear();
@@ -1147,12 +1575,40 @@ bmd_status bmd_eval_batch(bmd_problem* const* ps, int32_t n, const uint64_t* n_d
     unsigned long long* d_tdone = d_tstart + 1;
     int* d_left = reinterpret_cast<int*>(static_cast<char*>(clk.ptr) + align256(sizeof(unsigned long long) * (n + 1)));
 
+    // Settings of every launch kind in the batch: tuned once per device,
+    // precision and kind (on all of this batch's problems of that kind), or fixed.
+    std::map<int, BatchSettings> sets;
+    {
+        std::vector<int> keys;
+        for (const auto& b : plan)
+            if (std::find(keys.begin(), keys.end(), b.key) == keys.end()) keys.push_back(b.key);
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        for (int key : keys) {
+            const TuneKey tk{dev, prec, key};
+            auto it = g_tune.find(tk);
+            if (g_tune_mode == 1 && it == g_tune.end()) {
+                std::vector<bmd_problem*> kp;
+                std::vector<BatchPlan> kpl;
+                for (int i = 0; i < n; ++i)
+                    if (plan[i].key == key) {
+                        kp.push_back(ps[i]);
+                        kpl.push_back(plan[i]);
+                    }
+                BatchSettings best;
+                const bmd_status st = tune_phase(kp.data(), kpl, prec, n_cu, cs, d_tstart, d_tdone, d_left, &best);
+                if (st != BMD_OK) return st;
+                it = g_tune.emplace(tk, best).first;
+            }
+            sets[key] = g_tune_mode == 1 ? it->second : BatchSettings{};
+        }
+    }
     for (int first = 0; first < n;) {
         int last = first;
         size_t bytes = 0;
         while (last < n && (last == first || bytes + plan[last].draw_bytes <= budget)) bytes += plan[last++].draw_bytes;
-        bmd_status st = run_batch_group(ps, plan, first, last, prec, d_means, n_cu, cs, d_tstart, d_tdone, d_left,
-                                        first == 0);
+        std::vector<BatchPlan> group(plan.begin() + first, plan.begin() + last);
+        bmd_status st = run_batch_group(ps + first, group, first, prec, d_means + first, n_cu, cs, d_tstart, d_tdone,
+                                        d_left, first == 0, sets, true, nullptr);
         if (st != BMD_OK) return st;
         first = last;
     }
@@ -1163,6 +1619,35 @@ bmd_status bmd_eval_batch(bmd_problem* const* ps, int32_t n, const uint64_t* n_d
         for (int i = 0; i < n; ++i)
             h_wall_ms[i] = t[i + 1] >= t[0] ? static_cast<double>(t[i + 1] - t[0]) / clock_khz : 0.0;
     }
+    return BMD_OK;
+}
+
+bmd_status bmd_batch_autotune(int32_t mode) {
+    g_err.clear();
+    if (mode < 0 || mode > 2) return fail(BMD_EINVAL, "mode must be 0, 1 or 2");
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    if (mode != 1) g_tune.clear();
+    g_tune_mode = mode == 0 ? 0 : 1;
+    return BMD_OK;
+}
+
+bmd_status bmd_batch_settings(int32_t prec, int32_t d, int32_t kind, int32_t* h_out) {
+    g_err.clear();
+    if (!h_out) return fail(BMD_EINVAL, "h_out is NULL");
+    if (!valid_prec(prec)) return fail(BMD_EINVAL, "unknown precision %d", prec);
+    if (d < 1 || d > kMaxDim || kind < 0 || kind > 1 || (d == 1 && kind == 1))
+        return fail(BMD_ERANGE, "no launch kind (d = %d, kind = %d)", d, kind);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(TuneKey{dev, prec, 2 * d + kind});
+    if (it == g_tune.end()) return fail(BMD_ESTATE, "no tuned settings for d = %d, kind = %d on device %d", d, kind, dev);
+    const BatchSettings& b = it->second;
+    h_out[0] = b.chunk;
+    h_out[1] = b.rounds;
+    h_out[2] = b.variant;
+    h_out[3] = prec == BMD_FP32_COMP && kind == 1 ? (d <= 3 ? 5 : 4) - b.variant : 0;
+    h_out[4] = static_cast<int32_t>(std::lround(b.ms * 1000.0));
     return BMD_OK;
 }
 

@@ -16,7 +16,7 @@ constexpr int kPrecomputeGH = 128;   // nodes for the per-design subgroup fracti
 constexpr int kGLTable = 200;        // packed Gauss-Legendre rules n = 4..24
 constexpr int kEvalBlock = 256;      // designs per workgroup in the eval kernels
 constexpr int kSweepRounds = 8;      // rounds of resident workgroups a grid sweep is sliced into
-constexpr size_t kBatchBudget = size_t(16) << 30;   // draw bytes one batch group may hold
+constexpr size_t kBatchBudget = size_t(96) << 30;   // draw bytes one batch group may hold
 constexpr size_t kGradDrawBudget = size_t(4) << 30; // draw bytes one gradient pass may hold
 
 // Problem constants passed by value to every kernel.
@@ -179,10 +179,25 @@ hipError_t launch_eval_grid(const bmd_problem* p, int prec, int64_t M, const voi
                             double* partials, int n_slices, int64_t slice_len, bool want_var, hipStream_t s);
 hipError_t launch_finalize(const bmd_problem* p, int64_t M, const double* partials, int n_slices,
                            double* mean, double* var, hipStream_t s);
+// Sweep and finalize with the summands' derivatives in alpha_1 (cutoff designs,
+// rules BMD_ALPHA_SPLIT and BMD_ALPHA_FIXED): dmean = d mean / d alpha_1.
+hipError_t launch_eval_mode(const bmd_problem* p, int prec, int64_t M, const void* ws, double* partials,
+                            int n_slices, int64_t slice_len, int mode, hipStream_t s);
+hipError_t launch_eval_grid_dalpha(const bmd_problem* p, int prec, int64_t M, const void* ws, double* partials,
+                                   int n_slices, int64_t slice_len, hipStream_t s);
+hipError_t launch_finalize_dalpha(const bmd_problem* p, int64_t M, const double* partials, int n_slices,
+                                  double* mean, double* dmean, hipStream_t s);
 hipError_t launch_smooth(const bmd_problem* p, int prec, const double* in, double* out,
                          double* tmp, hipStream_t s);
 hipError_t launch_argmax(const bmd_problem* p, const double* v, int64_t n, double* part_v,
                          int64_t* part_i, int n_part, hipStream_t s);
+// The smoothed surface's numerator and denominator sums with their first and
+// second derivatives at the continuous design q (axis ranges lo, hi): out gets
+// 2 (1 + d + d (d + 1) / 2) FP64 values (kernels_post.hip); ws holds
+// smooth_local_bytes().
+size_t smooth_local_bytes();
+hipError_t launch_smooth_local(const bmd_problem* p, const double* in, const double* q, const double* lo,
+                               const double* hi, double* ws, double* out, hipStream_t s);
 size_t grad_workspace_bytes(const bmd_problem* p, int prec, int64_t B, int n_slices, int64_t M, int64_t slice_len);
 int grad_chunk(int prec, int d, int K);
 int grad_blocks_per_cu(const bmd_problem* p, int prec);   // resident gradient workgroups per CU
@@ -196,12 +211,18 @@ hipError_t launch_grad(const bmd_problem* p, int prec, const double* d_q, int64_
 DrawArrays<double> draws_fp64_at(const bmd_problem* p, int64_t M, void* ws);
 DrawArrays<float> draws_fp32_at(const bmd_problem* p, int64_t M, void* ws);
 hipError_t launch_draws_batch(int prec, const void* jobs, int n_jobs, int64_t total, hipStream_t s);
+// chunk: draws per LDS chunk of the matrix-core items (0 = the one-problem
+// sweep's); variant: launch-bound variant (batch_variants of them, see
+// batch_variant_waves: waves per SIMD the bound keeps, 0 = none).
 size_t batch_record_bytes(int prec);
 void batch_fill_record(int prec, void* dst, const bmd_problem* p, void* draws_ws, int64_t M, int64_t slice_len,
-                       double* partials, int scenario);
-size_t batch_phase_lds(const bmd_problem* p, int prec);
-int batch_phase_blocks_per_cu(const bmd_problem* p, int prec, size_t lds);
-hipError_t launch_batch_phase(const bmd_problem* p, int prec, const BatchPhase& ph, size_t lds, hipStream_t s);
+                       double* partials, int scenario, int chunk);
+size_t batch_phase_lds(const bmd_problem* p, int prec, int chunk);
+int batch_variants(const bmd_problem* p, int prec);
+int batch_variant_waves(const bmd_problem* p, int prec, int variant);
+int batch_phase_blocks_per_cu(const bmd_problem* p, int prec, size_t lds, int variant);
+hipError_t launch_batch_phase(const bmd_problem* p, int prec, const BatchPhase& ph, size_t lds, int variant,
+                              hipStream_t s);
 // Set left[first .. first+n) from items and clear their completion stamps;
 // t_start (if non-NULL) restarts the clock.
 hipError_t launch_batch_reset(int* left, unsigned long long* t_done, const int* items, int first, int n,

@@ -51,6 +51,14 @@ struct DesignState {
     // FP32 matrix-core sweep: the critical values and drift factors times
     // sqrt(log2(e)/2), so the bivariate normal's arguments arrive prescaled
     T z1s, z2s, a0s, a1s;
+    // Derivative of the summand in the first test's level alpha_1 (init_dalpha):
+    //   d(1 - Phi_2(h, k))/d alpha_1 = da1 phi(h) Phi((k - rho h)/s) + da2 phi(k) Phi((h - rho k)/s),
+    // da1 = 1/phi(z1) from dz1/d alpha_1 = -1/phi(z1); with the second level on
+    // the FWER boundary (rule BMD_ALPHA_SPLIT) da2 = (dz2/dz1)/phi(z1),
+    // dz2/dz1 = -phi(z1) Phi((z2 - rho z1)/s) / (phi(z2) Phi((z1 - rho z2)/s));
+    // with a fixed second level da2 = 0.  da1, da2 carry phi's 1/sqrt(2 pi);
+    // rs = rho/s and is = 1/s give the conditional arguments.
+    T da1, da2, rs, is;
 
     __device__ void init(const DevProblem& P, int64_t g, const double* __restrict__ r_arr,
                          const double* __restrict__ z1_arr, const double* __restrict__ z2_arr,
@@ -82,6 +90,7 @@ struct DesignState {
             a1s = static_cast<T>(sc * srI_d / r);
         }
         c0 = c1 = c2 = T(0);
+        da1 = da2 = rs = is = T(0);
         if (P.effect == BMD_EFFECT_PAPER_GAUSS) {
             const double th2 = -log1p(-(P.paper_a - P.paper_b * r));
             const double sg2 = 1.0 / sqrt(P.paper_events * r / 4.0);
@@ -90,7 +99,38 @@ struct DesignState {
             c2 = static_cast<T>(srI_d * sg2 * sqrt(1.0 - r));
         }
     }
+
+    // The alpha_1-derivative constants for critical values z1, z2 (finite z1).
+    __device__ void init_dalpha(const DevProblem& P, double r, double z1d, double z2d) {
+        const double rho = sqrt(r), sd = sqrt((1.0 - rho) * (1.0 + rho));
+        const double inv_root_2pi = 0.39894228040143267794;
+        const double c1d = 1.0 / norm_pdf(z1d);
+        double c2d = 0.0;
+        if (P.alpha_rule == BMD_ALPHA_SPLIT && z2d < INFINITY) {
+            const double dz2 = -norm_pdf(z1d) * norm_cdf((z2d - rho * z1d) / sd) /
+                               (norm_pdf(z2d) * norm_cdf((z1d - rho * z2d) / sd));
+            c2d = dz2 * c1d;
+        }
+        da1 = static_cast<T>(c1d * inv_root_2pi);
+        da2 = static_cast<T>(c2d * inv_root_2pi);
+        rs = static_cast<T>(rho / sd);
+        is = static_cast<T>(1.0 / sd);
+    }
 };
+
+// The alpha_1-derivative of one summand at its arguments h, k (unscaled):
+// da1 phi(h) Phi((k - rho h)/s) + da2 phi(k) Phi((h - rho k)/s), each phi
+// without its 1/sqrt(2 pi) (carried by da1, da2); a second critical value at
+// +infinity (zinf bit 1) leaves phi(h) alone, as the one-test derivative of
+// Appendix A.3.
+template <typename T, int D, int NMAX>
+__device__ __forceinline__ T dalpha_term(const DevProblem& P, const DesignState<T, D, NMAX>& s, T h, T kq) {
+    const T g = T(-0.5);
+    if (P.zinf & 2) return s.da1 * exp(g * h * h);
+    const T ph = exp(g * h * h) * norm_cdf(fma(kq, s.is, -s.rs * h));
+    const T pk = exp(g * kq * kq) * norm_cdf(fma(h, s.is, -s.rs * kq));
+    return fma(s.da1, ph, s.da2 * pk);
+}
 
 // Responder-in-subgroup fraction O for draw k (d >= 2).  A: axis tables
 // [d][K][mmax] with the Gauss-Hermite weights folded into axis 0.
@@ -142,10 +182,11 @@ __device__ __forceinline__ T overlap(const DevProblem& P, const DesignState<T, D
     return acc;
 }
 
-// 1 - Phi_2(...) for design s and draw k.
+// 1 - Phi_2(...) for design s and draw k; with dv, also its derivative in
+// alpha_1 (dalpha_term; the design's init_dalpha constants).
 template <typename T, int D, int NMAX, typename Src>
 __device__ __forceinline__ T summand(const DevProblem& P, const DesignState<T, D, NMAX>& s, const Src& src,
-                                     int64_t k, const T* __restrict__ A, int K) {
+                                     int64_t k, const T* __restrict__ A, int K, T* dv = nullptr) {
     const T mu1 = src.mu1(k);
     T mu2;
     if (P.effect == BMD_EFFECT_STEP) {
@@ -165,6 +206,7 @@ __device__ __forceinline__ T summand(const DevProblem& P, const DesignState<T, D
         mu2 = s.c0 + s.c1 * src.e1(k) + s.c2 * src.e2(k);
     }
     const T h = s.z1 - mu1, kq = s.z2 - mu2;
+    if (dv) *dv = dalpha_term<T, D, NMAX>(P, s, h, kq);
     if (P.zinf == 0) return bvn_sf<NMAX>(h, kq, s.bc, s.w, s.n);
     if (P.zinf == 1) return T(1) - norm_cdf(kq);
     if (P.zinf == 2) return T(1) - norm_cdf(h);

@@ -38,11 +38,17 @@ static_assert(sizeof(BatchRecord<float>) % 16 == 0 && sizeof(BatchRecord<double>
 // VGPRs and half the occupancy).  The records come in as their own __restrict__
 // argument, read-only for the launch, so their wave-uniform fields are fetched
 // with scalar loads.  The last item of a problem stamps its completion time.
-// Register bounds of the FP32 matrix-core items: five wavefronts per SIMD up to
-// three biomarkers, four beyond (at six, two node coefficients of the 10- and
-// 12-node rules are reloaded from scratch; the other rules never touch them).
-template <typename T, int D, int NMAX, bool MF>
-__global__ __launch_bounds__(kEvalBlock, sizeof(T) == 4 && MF ? (D <= 3 ? 5 : 4) : 1) void k_batch(BatchPhase ph, const BatchRecord<T>* __restrict__ recs) {
+// Register bounds of the FP32 matrix-core items, chosen per launch by the
+// batch autotuner from two variants: W = 0 keeps five wavefronts per SIMD up
+// to three biomarkers and four beyond (at six, two node coefficients of the
+// 10- and 12-node rules are reloaded from scratch; the other rules never touch
+// them); W = 1 allows one wavefront fewer and so more registers.
+template <int D, bool MF, int W>
+constexpr int batch_waves() {
+    return MF ? (D <= 3 ? 5 : 4) - W : 1;
+}
+template <typename T, int D, int NMAX, bool MF, int W>
+__global__ __launch_bounds__(kEvalBlock, (sizeof(T) == 4 ? batch_waves<D, MF, W>() : 1)) void k_batch(BatchPhase ph, const BatchRecord<T>* __restrict__ recs) {
     extern __shared__ __align__(16) char lds[];
     if (threadIdx.x == 0) atomicMin(ph.t_start, static_cast<unsigned long long>(wall_clock64()));
     const int4 it = ph.items[blockIdx.x];
@@ -51,9 +57,9 @@ __global__ __launch_bounds__(kEvalBlock, sizeof(T) == 4 && MF ? (D <= 3 ? 5 : 4)
     const int slice = __builtin_amdgcn_readfirstlane(it.z);
     const BatchRecord<T>& R = recs[rec];
     if constexpr (MF)
-        mfma_tile_body<T, D, NMAX, false>(R.a, R.geo, tile, slice, lds);
+        mfma_tile_body<T, D, NMAX, kSums>(R.a, R.geo, tile, slice, lds);
     else
-        direct_body<T, D, NMAX, false>(R.a, tile, slice);
+        direct_body<T, D, NMAX, kSums>(R.a, tile, slice);
     __syncthreads();   // every thread's partial sums are written
     if (threadIdx.x == 0) {
         __threadfence();
@@ -88,22 +94,24 @@ __global__ void k_batch_finalize(const BatchFinal* __restrict__ jobs, int n_jobs
     J.mean[g] = s / static_cast<double>(J.M);
 }
 
-template <typename T, int NMAX, bool MF>
+template <typename T, int NMAX, bool MF, int W>
 const void* batch_kernel(int d) {
     switch (d) {
-        case 1: return MF ? nullptr : reinterpret_cast<const void*>(k_batch<T, 1, NMAX, false>);
-        case 2: return reinterpret_cast<const void*>(k_batch<T, 2, NMAX, MF>);
-        case 3: return reinterpret_cast<const void*>(k_batch<T, 3, NMAX, MF>);
-        case 4: return reinterpret_cast<const void*>(k_batch<T, 4, NMAX, MF>);
-        case 5: return reinterpret_cast<const void*>(k_batch<T, 5, NMAX, MF>);
-        default: return reinterpret_cast<const void*>(k_batch<T, 6, NMAX, MF>);
+        case 1: return MF ? nullptr : reinterpret_cast<const void*>(k_batch<T, 1, NMAX, false, 0>);
+        case 2: return reinterpret_cast<const void*>(k_batch<T, 2, NMAX, MF, W>);
+        case 3: return reinterpret_cast<const void*>(k_batch<T, 3, NMAX, MF, W>);
+        case 4: return reinterpret_cast<const void*>(k_batch<T, 4, NMAX, MF, W>);
+        case 5: return reinterpret_cast<const void*>(k_batch<T, 5, NMAX, MF, W>);
+        default: return reinterpret_cast<const void*>(k_batch<T, 6, NMAX, MF, W>);
     }
 }
 
-const void* phase_kernel(const bmd_problem* p, int prec) {
+// Launch-bound variants: two for the FP32 matrix-core items, one otherwise.
+const void* phase_kernel(const bmd_problem* p, int prec, int variant) {
     const bool mf = use_mfma_sweep(p);
-    if (prec == BMD_FP64) return mf ? batch_kernel<double, 24, true>(p->P.d) : batch_kernel<double, 24, false>(p->P.d);
-    return mf ? batch_kernel<float, 12, true>(p->P.d) : batch_kernel<float, 12, false>(p->P.d);
+    if (prec == BMD_FP64) return mf ? batch_kernel<double, 24, true, 0>(p->P.d) : batch_kernel<double, 24, false, 0>(p->P.d);
+    if (!mf) return batch_kernel<float, 12, false, 0>(p->P.d);
+    return variant == 1 ? batch_kernel<float, 12, true, 1>(p->P.d) : batch_kernel<float, 12, true, 0>(p->P.d);
 }
 
 }  // namespace
@@ -112,9 +120,17 @@ size_t batch_record_bytes(int prec) {
     return prec == BMD_FP64 ? sizeof(BatchRecord<double>) : sizeof(BatchRecord<float>);
 }
 
+int batch_variants(const bmd_problem* p, int prec) { return prec == BMD_FP32_COMP && use_mfma_sweep(p) ? 2 : 1; }
+
+int batch_variant_waves(const bmd_problem* p, int prec, int variant) {
+    if (prec != BMD_FP32_COMP || !use_mfma_sweep(p)) return 0;   // no launch bound
+    return (p->P.d <= 3 ? 5 : 4) - variant;
+}
+
 void batch_fill_record(int prec, void* dst, const bmd_problem* p, void* draws_ws, int64_t M, int64_t slice_len,
-                       double* partials, int scenario) {
-    const MfmaGeom geo = use_mfma_sweep(p) ? sweep_geometry(p, prec) : MfmaGeom{};
+                       double* partials, int scenario, int chunk) {
+    MfmaGeom geo = use_mfma_sweep(p) ? sweep_geometry(p, prec) : MfmaGeom{};
+    if (use_mfma_sweep(p) && chunk > 0) geo.chunk = chunk;
     if (prec == BMD_FP64) {
         BatchRecord<double> r{EvalArgs<double>{p->P, p->d_r, p->d_z1, p->d_z2,
                                                static_cast<const double*>(p->tab[prec].A), draws_fp64_at(p, M, draws_ws),
@@ -130,16 +146,17 @@ void batch_fill_record(int prec, void* dst, const bmd_problem* p, void* draws_ws
     }
 }
 
-size_t batch_phase_lds(const bmd_problem* p, int prec) {
+size_t batch_phase_lds(const bmd_problem* p, int prec, int chunk) {
     if (!use_mfma_sweep(p)) return 0;
-    const MfmaGeom geo = sweep_geometry(p, prec);
-    return prec == BMD_FP64 ? mfma_lds_bytes<double>(geo.chunk, p->P.d, p->tab[prec].K)
-                            : mfma_lds_bytes<float>(geo.chunk, p->P.d, p->tab[prec].K);
+    const int ch = chunk > 0 ? chunk : sweep_geometry(p, prec).chunk;
+    return prec == BMD_FP64 ? mfma_lds_bytes<double>(ch, p->P.d, p->tab[prec].K)
+                            : mfma_lds_bytes<float>(ch, p->P.d, p->tab[prec].K);
 }
 
-int batch_phase_blocks_per_cu(const bmd_problem* p, int prec, size_t lds) {
+int batch_phase_blocks_per_cu(const bmd_problem* p, int prec, size_t lds, int variant) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, phase_kernel(p, prec), kEvalBlock, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, phase_kernel(p, prec, variant), kEvalBlock, lds) !=
+            hipSuccess ||
         nb < 1) {
         (void)hipGetLastError();
         nb = 1;
@@ -147,12 +164,13 @@ int batch_phase_blocks_per_cu(const bmd_problem* p, int prec, size_t lds) {
     return nb;
 }
 
-hipError_t launch_batch_phase(const bmd_problem* p, int prec, const BatchPhase& ph, size_t lds, hipStream_t s) {
+hipError_t launch_batch_phase(const bmd_problem* p, int prec, const BatchPhase& ph, size_t lds, int variant,
+                              hipStream_t s) {
     if (ph.n_items <= 0) return hipSuccess;
     const void* recs = ph.sc;
     void* args[] = {const_cast<BatchPhase*>(&ph), const_cast<void**>(&recs)};
-    return hipLaunchKernel(phase_kernel(p, prec), dim3(static_cast<unsigned>(ph.n_items)), dim3(kEvalBlock), args, lds,
-                           s);
+    return hipLaunchKernel(phase_kernel(p, prec, variant), dim3(static_cast<unsigned>(ph.n_items)), dim3(kEvalBlock),
+                           args, lds, s);
 }
 
 hipError_t launch_batch_reset(int* left, unsigned long long* t_done, const int* items, int first, int n,

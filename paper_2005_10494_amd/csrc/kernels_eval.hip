@@ -14,7 +14,7 @@ namespace {
 // VAR: also the per-design sums of squares (only when a variance is asked for).
 template <typename T, int D, int NMAX, bool VAR>
 __global__ __launch_bounds__(kEvalBlock) void k_eval_direct(EvalArgs<T> a) {
-    direct_body<T, D, NMAX, VAR>(a, blockIdx.x, blockIdx.y);
+    direct_body<T, D, NMAX, VAR ? kSquares : kSums>(a, blockIdx.x, blockIdx.y);
 }
 
 // FP32 with up to three biomarkers: at most 96 VGPRs, so that five wavefronts
@@ -22,20 +22,33 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_direct(EvalArgs<T> a) {
 template <typename T, int D, int NMAX, bool VAR>
 __global__ __launch_bounds__(kEvalBlock, sizeof(T) == 4 && D <= 3 ? 5 : 1) void k_eval_mfma(EvalArgs<T> a, MfmaGeom geo) {
     extern __shared__ __align__(16) char lds[];
-    mfma_tile_body<T, D, NMAX, VAR>(a, geo, blockIdx.x, blockIdx.y, lds);
+    mfma_tile_body<T, D, NMAX, VAR ? kSquares : kSums>(a, geo, blockIdx.x, blockIdx.y, lds);
 }
 
+// The same sweeps with the summands' derivatives in alpha_1 as second sums.
+template <typename T, int D, int NMAX>
+__global__ __launch_bounds__(kEvalBlock) void k_eval_direct_da(EvalArgs<T> a) {
+    direct_body<T, D, NMAX, kDAlpha>(a, blockIdx.x, blockIdx.y);
+}
+template <typename T, int D, int NMAX>
+__global__ __launch_bounds__(kEvalBlock) void k_eval_mfma_da(EvalArgs<T> a, MfmaGeom geo) {
+    extern __shared__ __align__(16) char lds[];
+    mfma_tile_body<T, D, NMAX, kDAlpha>(a, geo, blockIdx.x, blockIdx.y, lds);
+}
+
+// mean = sums / M in slice order; second: nothing (mode 0), the sample
+// variance from the sums of squares (1), the second sums / M (2).
 __global__ void k_finalize(int64_t G, int64_t M, int n_slices, const double* __restrict__ part,
-                           double* __restrict__ mean, double* __restrict__ var) {
+                           double* __restrict__ mean, double* __restrict__ second, int mode) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= G) return;
     double s1 = 0.0, s2 = 0.0;
     for (int s = 0; s < n_slices; ++s) s1 += part[static_cast<int64_t>(s) * 2 * G + g];
     const double Md = static_cast<double>(M);
     mean[g] = s1 / Md;
-    if (var) {
+    if (mode != 0) {
         for (int s = 0; s < n_slices; ++s) s2 += part[static_cast<int64_t>(s) * 2 * G + G + g];
-        var[g] = M > 1 ? fmax(0.0, (s2 - s1 * s1 / Md) / (Md - 1.0)) : 0.0;
+        second[g] = mode == 2 ? s2 / Md : M > 1 ? fmax(0.0, (s2 - s1 * s1 / Md) / (Md - 1.0)) : 0.0;
     }
 }
 
@@ -73,6 +86,27 @@ MfmaGeom mfma_geometry(const bmd_problem* p, int prec) {
 }
 
 // The sweep kernel for biomarker count d.
+template <typename T, int NMAX>
+const void* sweep_kernel_da(int d, bool mf) {
+    if (mf) {
+        switch (d) {
+            case 2: return reinterpret_cast<const void*>(k_eval_mfma_da<T, 2, NMAX>);
+            case 3: return reinterpret_cast<const void*>(k_eval_mfma_da<T, 3, NMAX>);
+            case 4: return reinterpret_cast<const void*>(k_eval_mfma_da<T, 4, NMAX>);
+            case 5: return reinterpret_cast<const void*>(k_eval_mfma_da<T, 5, NMAX>);
+            default: return reinterpret_cast<const void*>(k_eval_mfma_da<T, 6, NMAX>);
+        }
+    }
+    switch (d) {
+        case 1: return reinterpret_cast<const void*>(k_eval_direct_da<T, 1, NMAX>);
+        case 2: return reinterpret_cast<const void*>(k_eval_direct_da<T, 2, NMAX>);
+        case 3: return reinterpret_cast<const void*>(k_eval_direct_da<T, 3, NMAX>);
+        case 4: return reinterpret_cast<const void*>(k_eval_direct_da<T, 4, NMAX>);
+        case 5: return reinterpret_cast<const void*>(k_eval_direct_da<T, 5, NMAX>);
+        default: return reinterpret_cast<const void*>(k_eval_direct_da<T, 6, NMAX>);
+    }
+}
+
 template <typename T, int NMAX, bool VAR>
 const void* sweep_kernel(int d, bool mf) {
     if (mf) {
@@ -95,11 +129,13 @@ const void* sweep_kernel(int d, bool mf) {
 }
 
 template <typename T, int NMAX>
-hipError_t launch_typed(const bmd_problem* p, int prec, const EvalArgs<T>& a, int n_slices, bool var,
+hipError_t launch_typed(const bmd_problem* p, int prec, const EvalArgs<T>& a, int n_slices, int mode,
                         hipStream_t s) {
     const int d = p->P.d;
     const bool mf = use_mfma_sweep(p);
-    const void* k = var ? sweep_kernel<T, NMAX, true>(d, mf) : sweep_kernel<T, NMAX, false>(d, mf);
+    const void* k = mode == kDAlpha    ? sweep_kernel_da<T, NMAX>(d, mf)
+                    : mode == kSquares ? sweep_kernel<T, NMAX, true>(d, mf)
+                                       : sweep_kernel<T, NMAX, false>(d, mf);
     if (mf) {
         MfmaGeom geo = mfma_geometry(p, prec);
         const int64_t tiles = ((geo.Pn + 15) / 16) * geo.tiles_l;
@@ -168,23 +204,41 @@ hipError_t launch_eval_grid(const bmd_problem* p, int prec, int64_t M, const voi
         return launch_eval_three(p, prec, M, ws, partials, n_slices, slice_len, want_var, s);
     if (p->P.design_space == BMD_DESIGN_ALPHA4)
         return launch_eval_four(p, prec, M, ws, partials, n_slices, slice_len, want_var, s);
+    return launch_eval_mode(p, prec, M, ws, partials, n_slices, slice_len, want_var ? kSquares : kSums, s);
+}
+
+hipError_t launch_eval_grid_dalpha(const bmd_problem* p, int prec, int64_t M, const void* ws, double* partials,
+                                   int n_slices, int64_t slice_len, hipStream_t s) {
+    return launch_eval_mode(p, prec, M, ws, partials, n_slices, slice_len, kDAlpha, s);
+}
+
+hipError_t launch_eval_mode(const bmd_problem* p, int prec, int64_t M, const void* ws, double* partials,
+                            int n_slices, int64_t slice_len, int mode, hipStream_t s) {
     if (prec == BMD_FP64) {
         EvalArgs<double> a{p->P, p->d_r, p->d_z1, p->d_z2, static_cast<const double*>(p->tab[prec].A),
                            draws_fp64(p, M, ws), p->d_gl, static_cast<const double*>(p->tab[prec].glw),
                            slice_len, partials};
-        return launch_typed<double, 24>(p, prec, a, n_slices, want_var, s);
+        return launch_typed<double, 24>(p, prec, a, n_slices, mode, s);
     }
     EvalArgs<float> a{p->P, p->d_r, p->d_z1, p->d_z2, static_cast<const float*>(p->tab[prec].A),
                       draws_fp32(p, M, ws), p->d_gl, static_cast<const float*>(p->tab[prec].glw),
                       slice_len, partials};
-    return launch_typed<float, 12>(p, prec, a, n_slices, want_var, s);
+    return launch_typed<float, 12>(p, prec, a, n_slices, mode, s);
 }
 
 hipError_t launch_finalize(const bmd_problem* p, int64_t M, const double* partials, int n_slices, double* mean,
                            double* var, hipStream_t s) {
     const int64_t G = p->P.G;
     hipLaunchKernelGGL(k_finalize, dim3(static_cast<unsigned>((G + 255) / 256)), dim3(256), 0, s, G, M, n_slices,
-                       partials, mean, var);
+                       partials, mean, var, var ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_dalpha(const bmd_problem* p, int64_t M, const double* partials, int n_slices, double* mean,
+                                  double* dmean, hipStream_t s) {
+    const int64_t G = p->P.G;
+    hipLaunchKernelGGL(k_finalize, dim3(static_cast<unsigned>((G + 255) / 256)), dim3(256), 0, s, G, M, n_slices,
+                       partials, mean, dmean, 2);
     return hipGetLastError();
 }
 

@@ -136,6 +136,97 @@ __global__ void k_mask_ratio(int64_t G, const double* __restrict__ in, const dou
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// The smoothed surface at a continuous design q (the fitted surface of Sec.
+// 2.3 between grid points) with its first and second derivatives in q:
+//   S(q) = N(q) / D(q),  N = sum_h K(q, q_h) f_h,  D = sum_h K(q, q_h),
+//   K = prod_j k_j,  k_j = exp(-t_j^2 / 2),  t_j = (q_j - x_j,h) / b_j,
+// over the grid designs whose value is not NaN.  With u_j = -t_j / b_j,
+// dK/dq_j = K u_j and d2K/dq_j dq_l = K (u_j u_l - [j = l] / b_j^2); the
+// kernels reduce sum K f (1, u_j, u_j u_l) and sum K (1, u_j, u_j u_l) and
+// the host adds the diagonal terms.  FP64 throughout.
+// ---------------------------------------------------------------------------
+
+constexpr int kLocalBlocks = 1024;
+
+// Accumulators per side: 1 + D + D (D + 1) / 2.
+template <int D>
+constexpr int local_acc() {
+    return 1 + D + D * (D + 1) / 2;
+}
+
+struct LocalArgs {
+    DevProblem P;
+    const double* in;
+    double q[kMaxDim];
+    double lo[kMaxDim], hi[kMaxDim];   // axis ranges of the grid
+    double bw[kMaxDim];                // bandwidths
+    double* partials;                  // [kLocalBlocks][2 * local_acc]
+};
+
+template <int D>
+__global__ __launch_bounds__(256) void k_smooth_local(LocalArgs a) {
+    constexpr int NA = local_acc<D>();
+    __shared__ double red[256];
+    double accf[NA], accw[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) accf[i] = accw[i] = 0.0;
+    const int64_t G = a.P.G;
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < G;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const double v = a.in[g];
+        if (v != v) continue;   // NaN designs carry no weight
+        double w = 1.0, u[D];
+        int64_t rem = g;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const int idx = static_cast<int>(rem / a.P.stride[j]);
+            rem -= static_cast<int64_t>(idx) * a.P.stride[j];
+            const double t = (a.q[j] - grid_coord(a.lo[j], a.hi[j], idx, a.P.m[j])) / a.bw[j];
+            w *= exp(-0.5 * t * t);
+            u[j] = -t / a.bw[j];
+        }
+        const double wv = w * v;
+        accf[0] += wv;
+        accw[0] += w;
+        int k = 1 + D;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            accf[1 + j] = fma(wv, u[j], accf[1 + j]);
+            accw[1 + j] = fma(w, u[j], accw[1 + j]);
+#pragma unroll
+            for (int l = j; l < D; ++l, ++k) {
+                const double uu = u[j] * u[l];
+                accf[k] = fma(wv, uu, accf[k]);
+                accw[k] = fma(w, uu, accw[k]);
+            }
+        }
+    }
+    // block sums in a fixed tree order, one accumulator at a time
+    double* out = a.partials + static_cast<int64_t>(blockIdx.x) * 2 * NA;
+#pragma unroll
+    for (int i = 0; i < 2 * NA; ++i) {
+        red[threadIdx.x] = i < NA ? accf[i] : accw[i - NA];
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if (static_cast<int>(threadIdx.x) < off) red[threadIdx.x] += red[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[i] = red[0];
+        __syncthreads();
+    }
+}
+
+// Sums of the block partials in block order: out[i] = sum_b partials[b][i].
+__global__ __launch_bounds__(64) void k_smooth_local_final(const double* __restrict__ partials, int n_blocks,
+                                                           int n_acc, double* __restrict__ out) {
+    const int i = threadIdx.x;
+    if (i >= n_acc) return;
+    double s = 0.0;
+    for (int b = 0; b < n_blocks; ++b) s += partials[static_cast<int64_t>(b) * n_acc + i];
+    out[i] = s;
+}
+
 hipError_t launch_smooth_masked(const bmd_problem* p, int prec, const double* in, double* out, double* ws,
                                 hipStream_t s) {
     const int64_t G = p->P.G;
@@ -187,6 +278,37 @@ hipError_t launch_smooth(const bmd_problem* p, int prec, const double* in, doubl
         src = dst;
     }
     return hipSuccess;
+}
+
+size_t smooth_local_bytes() { return sizeof(double) * (static_cast<size_t>(kLocalBlocks) + 1) * 2 * local_acc<kMaxDim>(); }
+
+hipError_t launch_smooth_local(const bmd_problem* p, const double* in, const double* q, const double* lo,
+                               const double* hi, double* ws, double* out, hipStream_t s) {
+    LocalArgs a{};
+    a.P = p->P;
+    a.in = in;
+    for (int j = 0; j < p->P.d; ++j) {
+        a.q[j] = q[j];
+        a.lo[j] = lo[j];
+        a.hi[j] = hi[j];
+        a.bw[j] = p->desc.bandwidth[j];
+    }
+    a.partials = ws;
+    const int64_t G = p->P.G;
+    const int blocks = static_cast<int>(std::min<int64_t>(kLocalBlocks, (G + 255) / 256));
+    int na = 0;
+    switch (p->P.d) {
+        case 1: hipLaunchKernelGGL(k_smooth_local<1>, dim3(blocks), dim3(256), 0, s, a); na = local_acc<1>(); break;
+        case 2: hipLaunchKernelGGL(k_smooth_local<2>, dim3(blocks), dim3(256), 0, s, a); na = local_acc<2>(); break;
+        case 3: hipLaunchKernelGGL(k_smooth_local<3>, dim3(blocks), dim3(256), 0, s, a); na = local_acc<3>(); break;
+        case 4: hipLaunchKernelGGL(k_smooth_local<4>, dim3(blocks), dim3(256), 0, s, a); na = local_acc<4>(); break;
+        case 5: hipLaunchKernelGGL(k_smooth_local<5>, dim3(blocks), dim3(256), 0, s, a); na = local_acc<5>(); break;
+        default: hipLaunchKernelGGL(k_smooth_local<6>, dim3(blocks), dim3(256), 0, s, a); na = local_acc<6>(); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_smooth_local_final, dim3(1), dim3(64), 0, s, ws, blocks, 2 * na, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_argmax(const bmd_problem* p, const double* v, int64_t n, double* part_v, int64_t* part_i,

@@ -234,6 +234,85 @@ __global__ __launch_bounds__(128) void k_levels_golden(int64_t G, int phase, boo
     }
 }
 
+// Derivative-driven search of the first level per design (the level split of
+// Sec. 2.4, second level on the design's FWER boundary; the smoothness of
+// Appendix A.3 makes the shared-draw estimate a smooth function of alpha_1
+// with a derivative the sweep returns): a root of the derivative inside
+// [a_lo, a_hi] by the Illinois variant of false position, one call between
+// consecutive derivative sweeps.  st holds [9][G]: bracket ends lo, hi,
+// derivatives there glo, ghi, the probed level x, the best estimate seen and
+// its level, the side kept last (+1 lo, -1 hi, 0 none) and a done flag.
+// Phase 0 probes a_lo, phase 1 records it and probes a_hi, phase 2 records
+// it and decides: a derivative <= 0 at a_lo or >= 0 at a_hi puts the maximum
+// at that end (done), otherwise false position starts; every later phase
+// records the probe, keeps the best and moves one end.  A probe writes the
+// design's z1 and z2; a finished design probes its best level again.
+__global__ __launch_bounds__(128) void k_levels_newton(int64_t G, int phase, double a_lo, double a_hi, double tol,
+                                                       double alpha0, const double* __restrict__ r,
+                                                       const double* __restrict__ mean,
+                                                       const double* __restrict__ dmean,
+                                                       const double* __restrict__ gl, double* __restrict__ st,
+                                                       double* __restrict__ z1_out, double* __restrict__ z2_out) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    double* LO = st;
+    double* HI = st + G;
+    double* GLO = st + 2 * G;
+    double* GHI = st + 3 * G;
+    double* X = st + 4 * G;
+    double* best = st + 5 * G;
+    double* best_x = st + 6 * G;
+    double* kept = st + 7 * G;
+    double* done = st + 8 * G;
+    double next = 0.0;
+    if (phase == 0) {
+        LO[g] = a_lo;
+        HI[g] = a_hi;
+        kept[g] = 0.0;
+        done[g] = 0.0;
+        next = a_lo;
+    } else {
+        const double f = mean[g], d = dmean[g], x = X[g];
+        if (phase == 1 || f > best[g]) {
+            best[g] = f;
+            best_x[g] = x;
+        }
+        if (phase == 1) {
+            GLO[g] = d;
+            next = a_hi;
+        } else if (phase == 2) {
+            GHI[g] = d;
+            if (GLO[g] <= 0.0 || GHI[g] >= 0.0) done[g] = 1.0;   // the maximum sits at an end
+        } else if (done[g] == 0.0) {
+            // the root lies where the derivative changes sign
+            if (d > 0.0) {
+                LO[g] = x;
+                GLO[g] = d;
+                if (kept[g] == -1.0) GHI[g] *= 0.5;
+                kept[g] = -1.0;
+            } else {
+                HI[g] = x;
+                GHI[g] = d;
+                if (kept[g] == 1.0) GLO[g] *= 0.5;
+                kept[g] = 1.0;
+            }
+            if (d == 0.0 || HI[g] - LO[g] <= tol) done[g] = 1.0;
+        }
+        if (phase >= 2) {
+            if (done[g] != 0.0) {
+                next = best_x[g];
+            } else {
+                next = (LO[g] * GHI[g] - HI[g] * GLO[g]) / (GHI[g] - GLO[g]);
+                if (!(next > LO[g] && next < HI[g])) next = 0.5 * (LO[g] + HI[g]);
+            }
+        }
+    }
+    X[g] = next;
+    const double z1 = -norm_quantile(next);
+    z1_out[g] = z1;
+    z2_out[g] = z2_on_fwer(z1, sqrt(r[g]), alpha0, gl);
+}
+
 // Running maximum over levels: level k's means against the best so far
 // (k = 0 initialises); strict improvement only, so ties keep the lower k.
 __global__ void k_levels_best(int64_t G, int k, const double* __restrict__ mean, double* __restrict__ best,
@@ -426,6 +505,13 @@ hipError_t launch_levels_golden(const bmd_problem* p, int phase, bool probe, int
                                 const double* mean, double* st, int32_t* side, hipStream_t s) {
     hipLaunchKernelGGL(k_levels_golden, dim3(blocks_for(p->P.G, 128)), dim3(128), 0, s, p->P.G, phase, probe, end,
                        a_lo, a_hi, p->P.alpha0, p->d_r, mean, p->d_gl, st, side, p->d_z1, p->d_z2);
+    return hipGetLastError();
+}
+
+hipError_t launch_levels_newton(const bmd_problem* p, int phase, double a_lo, double a_hi, double tol,
+                                const double* mean, const double* dmean, double* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_levels_newton, dim3(blocks_for(p->P.G, 128)), dim3(128), 0, s, p->P.G, phase, a_lo, a_hi,
+                       tol, p->P.alpha0, p->d_r, mean, dmean, p->d_gl, st, p->d_z1, p->d_z2);
     return hipGetLastError();
 }
 

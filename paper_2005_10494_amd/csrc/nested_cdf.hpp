@@ -54,6 +54,15 @@ __device__ __forceinline__ float half_gauss(float x) {
     return __builtin_amdgcn_exp2f(x * x * -0.72134752044448170368f);   // log2(e) / 2
 }
 
+// A wave-uniform value moved to a scalar register (FP32 constants only).
+template <typename T>
+__device__ __forceinline__ T uniform(T x) {
+    if constexpr (sizeof(T) == 4)
+        return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+    else
+        return x;
+}
+
 // Per-problem constants of Phi_3 in type T.
 template <typename T>
 struct TvnConst {
@@ -65,29 +74,66 @@ struct TvnConst {
     T px[kNodes];      // panel nodes on [0, 1]
     T pw[kNodes];      // panel weights with phi's 1/sqrt(2 pi) folded in
     int np;            // panels
+    // FP32 integrates in y' = k y, k = sqrt(log2(e)/2) (norm_cdf_scaled's
+    // unit): phi(y) dy = 2^(-y'^2) dy' / (k sqrt(2 pi)) and each prescaled
+    // conditional argument is one fused multiply-add, u' = k h1 / s12 -
+    // (r12 / s12) y'; the panel weights go into the exponent as log2.
+    T g1, g3;          // r12 / s12, r23 / s23: slopes in y'
+    T k1, k3;          // k / s12, k / s23: scales of h1, h3
+    T lw[kNodes];      // log2(w_i / (2 k sqrt(2 pi)))
 
     __device__ void init(double r2, double r3, int panels, const double* __restrict__ gl) {
         const double L = sizeof(T) == 8 ? 8.5 : 6.0;
         const double a = sqrt(r2), b = sqrt(r3 / r2), sa = sqrt(1.0 - r2), sb = sqrt(1.0 - r3 / r2);
+        const double k = static_cast<double>(kPhiScale);
+        g1 = uniform(static_cast<T>(a / sa));
+        g3 = uniform(static_cast<T>(b / sb));
+        k1 = uniform(static_cast<T>(k / sa));
+        k3 = uniform(static_cast<T>(k / sb));
         r12 = static_cast<T>(a);
         r23 = static_cast<T>(b);
         is12 = static_cast<T>(1.0 / sa);
         is23 = static_cast<T>(1.0 / sb);
-        tail = static_cast<T>(L);
-        c1 = static_cast<T>(L * sa);
-        c3 = static_cast<T>(L * sb);
-        ir12 = static_cast<T>(1.0 / a);
-        ir23 = static_cast<T>(1.0 / b);
+        tail = uniform(static_cast<T>(L));
+        c1 = uniform(static_cast<T>(L * sa));
+        c3 = uniform(static_cast<T>(L * sb));
+        ir12 = uniform(static_cast<T>(1.0 / a));
+        ir23 = uniform(static_cast<T>(1.0 / b));
         const double* x = gl + gl_offset(kNodes);
         const double* w = x + kNodes;
 #pragma unroll
         for (int i = 0; i < kNodes; ++i) {
-            px[i] = static_cast<T>(0.5 * (1.0 + x[i]));
+            px[i] = uniform(static_cast<T>(0.5 * (1.0 + x[i])));
             pw[i] = static_cast<T>(0.5 * w[i] * 0.39894228040143267794);
+            lw[i] = uniform(static_cast<T>(log2(0.5 * w[i] * 0.39894228040143267794 / k)));
         }
         np = panels;
     }
 };
+
+// FP32 Phi_3 in y' (see TvnConst): per point one FMA for y', one per
+// conditional argument, one for the Gaussian's exponent with the weight, an
+// exp2, the two CDFs and two to accumulate.
+__device__ __forceinline__ float tvn(float h1, float h2, float h3, const TvnConst<float>& c) {
+    const float k = kPhiScale;
+    const float lo = -c.tail * k;
+    const float hi = k * fminf(fminf(h2, c.tail), fminf((h1 + c.c1) * c.ir12, (h3 + c.c3) * c.ir23));
+    const float width = fmaxf(hi - lo, 0.0f) / static_cast<float>(c.np);
+    const float H1 = h1 * c.k1, H3 = h3 * c.k3;
+    float acc = 0.0f;
+    for (int p = 0; p < c.np; ++p) {
+        const float a = fmaf(width, static_cast<float>(p), lo);
+#pragma unroll
+        for (int i = 0; i < kNodes; ++i) {
+            const float y = fmaf(width, c.px[i], a);
+            const float u = fmaf(-c.g1, y, H1);
+            const float v = fmaf(-c.g3, y, H3);
+            const float e = __builtin_amdgcn_exp2f(fmaf(-y, y, c.lw[i]));
+            acc = fmaf(e * norm_cdf_scaled(u), norm_cdf_scaled(v), acc);
+        }
+    }
+    return acc * width;
+}
 
 // Phi_3(h1, h2, h3) over c.np panels (wave-uniform).  Every lane runs the
 // same node count: an empty range (U <= -L) becomes a zero panel width, and
@@ -140,6 +186,9 @@ struct QvnConst {
     BvnConst<T, NMAX> bc;   // Phi_2 at the partial correlation of (Y3, Y4) given Y2
     T bw[NMAX];          // its node weights
     int nb;              // its node count (a rule of the packed table)
+    // FP32 in y' as for Phi_3: slopes r1j / s1j, scales k / s1j, log2 weights
+    T g1, g3, g4, k1, k3, k4;
+    T lw[kNodes];
 
     __device__ void init(double r2, double r3, double r4, int panels, int bvn_n, const double* __restrict__ gl) {
         const double L = sizeof(T) == 8 ? 8.5 : 6.0;
@@ -167,12 +216,38 @@ struct QvnConst {
             px[i] = static_cast<T>(0.5 * (1.0 + x[i]));
             pw[i] = static_cast<T>(0.5 * w[i] * 0.39894228040143267794);
         }
+        {
+            const double kk = static_cast<double>(kPhiScale);
+            g1 = uniform(static_cast<T>(a / sa));
+            g3 = uniform(static_cast<T>(b / sb));
+            g4 = uniform(static_cast<T>(c / sc));
+            k1 = uniform(static_cast<T>(kk / sa));
+            k3 = uniform(static_cast<T>(kk / sb));
+            k4 = uniform(static_cast<T>(kk / sc));
+#pragma unroll
+            for (int i = 0; i < kNodes; ++i) {
+                lw[i] = uniform(static_cast<T>(log2(0.5 * w[i] * 0.39894228040143267794 / kk)));
+                px[i] = uniform(px[i]);
+            }
+            tail = uniform(tail);
+            c1 = uniform(c1);
+            c3 = uniform(c3);
+            c4 = uniform(c4);
+            ir12 = uniform(ir12);
+            ir23 = uniform(ir23);
+            ir24 = uniform(ir24);
+        }
         np = panels;
         nb = bvn_n;
         bc.init(qvn_partial_rho(r2, r3, r4), bvn_n, gl);
         const double* bwx = gl + gl_offset(bvn_n) + bvn_n;
 #pragma unroll
-        for (int i = 0; i < NMAX; ++i) bw[i] = static_cast<T>(i < bvn_n ? bwx[i] : 0.0);
+        for (int i = 0; i < NMAX; ++i) {
+            bw[i] = uniform(static_cast<T>(i < bvn_n ? bwx[i] : 0.0));
+            bc.a[i] = uniform(bc.a[i]);
+            bc.b[i] = uniform(bc.b[i]);
+        }
+        bc.scale = uniform(bc.scale);
     }
 };
 
@@ -187,6 +262,32 @@ __device__ __forceinline__ float qvn_cdf2(float a, float b, const QvnConst<float
 template <int NMAX>
 __device__ __forceinline__ double qvn_cdf2(double a, double b, const QvnConst<double, NMAX>& c) {
     return bvn_cdf<NMAX>(a, b, c.bc, c.bw, c.nb);
+}
+
+// FP32 Phi_4 in y' (see TvnConst): the three conditional arguments are one
+// FMA each and arrive prescaled at the univariate and bivariate CDFs.
+template <int NMAX>
+__device__ __forceinline__ float qvn(float h1, float h2, float h3, float h4, const QvnConst<float, NMAX>& c) {
+    const float k = kPhiScale;
+    const float lo = -c.tail * k;
+    const float hi = k * fminf(fminf(fminf(h2, c.tail), (h1 + c.c1) * c.ir12),
+                               fminf((h3 + c.c3) * c.ir23, (h4 + c.c4) * c.ir24));
+    const float width = fmaxf(hi - lo, 0.0f) / static_cast<float>(c.np);
+    const float H1 = h1 * c.k1, H3 = h3 * c.k3, H4 = h4 * c.k4;
+    float acc = 0.0f;
+    for (int p = 0; p < c.np; ++p) {
+        const float a = fmaf(width, static_cast<float>(p), lo);
+#pragma unroll
+        for (int i = 0; i < kNodes; ++i) {
+            const float y = fmaf(width, c.px[i], a);
+            const float u1 = fmaf(-c.g1, y, H1);
+            const float u3 = fmaf(-c.g3, y, H3);
+            const float u4 = fmaf(-c.g4, y, H4);
+            const float e = __builtin_amdgcn_exp2f(fmaf(-y, y, c.lw[i]));
+            acc = fmaf(e * norm_cdf_scaled(u1), bvn_cdf_scaled<NMAX>(u3, u4, c.bc, c.bw, c.nb), acc);
+        }
+    }
+    return acc * width;
 }
 
 // Phi_4(h1, h2, h3, h4) over c.np panels (wave-uniform); an empty range gives

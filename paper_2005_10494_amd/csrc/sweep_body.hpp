@@ -10,6 +10,12 @@
 
 namespace bmd {
 
+// What a sweep accumulates per design besides the sums of the summands: the
+// second half of each slice's partials holds nothing (kSums), the sums of
+// squares (kSquares) or the sums of the summands' derivatives in the first
+// test's level alpha_1 (kDAlpha).
+constexpr int kSums = 0, kSquares = 1, kDAlpha = 2;
+
 template <typename T>
 struct EvalArgs {
     DevProblem P;
@@ -21,12 +27,12 @@ struct EvalArgs {
     const double* gl;    // packed GL table (FP64 nodes)
     const T* glw;        // packed GL table in T (weights read from here)
     int64_t slice_len;
-    double* partials;    // [n_slices][2][G]: sums, then sums of squares (VAR only)
+    double* partials;    // [n_slices][2][G]: sums, then the MODE's second sums
 };
 
 // Direct sweep, one workgroup's work: designs bx * 256 + thread (one per
-// thread), draws of slice `slice`.  VAR: also the sums of squares.
-template <typename T, int D, int NMAX, bool VAR>
+// thread), draws of slice `slice`.  MODE: see kSums.
+template <typename T, int D, int NMAX, int MODE>
 __device__ __forceinline__ void direct_body(const EvalArgs<T>& a, int64_t bx, int slice) {
     const int64_t G = a.P.G;
     const int64_t g = bx * kEvalBlock + threadIdx.x;
@@ -34,20 +40,27 @@ __device__ __forceinline__ void direct_body(const EvalArgs<T>& a, int64_t bx, in
     const int64_t gg = valid ? g : G - 1;   // idle lanes shadow the last design
     DesignState<T, D, NMAX> s;
     s.init(a.P, gg, a.r, a.z1, a.z2, a.gl, a.glw);
+    if constexpr (MODE == kDAlpha) s.init_dalpha(a.P, a.r[gg], a.z1[gg], a.z2[gg]);
     const GlobalDraws<T> src{a.D, D};
     const int64_t M = a.D.M;
     const int64_t kb = static_cast<int64_t>(slice) * a.slice_len;
     const int64_t ke = min(M, kb + a.slice_len);
     double s1 = 0.0, s2 = 0.0;
     for (int64_t k = kb; k < ke; ++k) {
-        const double v = static_cast<double>(summand<T, D, NMAX>(a.P, s, src, k, a.A, a.D.K));
-        s1 += v;
-        if constexpr (VAR) s2 = fma(v, v, s2);
+        if constexpr (MODE == kDAlpha) {
+            T dv;
+            s1 += static_cast<double>(summand<T, D, NMAX>(a.P, s, src, k, a.A, a.D.K, &dv));
+            s2 += static_cast<double>(dv);
+        } else {
+            const double v = static_cast<double>(summand<T, D, NMAX>(a.P, s, src, k, a.A, a.D.K));
+            s1 += v;
+            if constexpr (MODE == kSquares) s2 = fma(v, v, s2);
+        }
     }
     if (valid) {
         double* out = a.partials + static_cast<int64_t>(slice) * 2 * G;
         out[g] = s1;
-        if constexpr (VAR) out[G + g] = s2;
+        if constexpr (MODE != kSums) out[G + g] = s2;
     }
 }
 
@@ -122,8 +135,8 @@ struct MfmaGeom {
 // mfma_lds_bytes<T>(geo.chunk, D, K) bytes.  The body's first LDS copies are
 // issued before its first barrier and its last phase B reads LDS after its
 // last one, so a caller that runs another item on the same LDS must
-// synchronise the workgroup in between.  VAR: also the sums of squares.
-template <typename T, int D, int NMAX, bool VAR>
+// synchronise the workgroup in between.  MODE: see kSums.
+template <typename T, int D, int NMAX, int MODE>
 __device__ __forceinline__ void mfma_tile_body(const EvalArgs<T>& a, const MfmaGeom& geo, int64_t tile, int slice,
                                                char* lds) {
     using acc_t = typename std::conditional<sizeof(T) == 8, mf_d4, mf_f4>::type;
@@ -147,6 +160,7 @@ __device__ __forceinline__ void mfma_tile_body(const EvalArgs<T>& a, const MfmaG
     const int64_t g = validB ? pB * geo.Sn + lB : G - 1;
     DesignState<T, D, NMAX> st;
     st.init(a.P, g, a.r, a.z1, a.z2, a.gl, a.glw);
+    if constexpr (MODE == kDAlpha) st.init_dalpha(a.P, a.r[g], a.z1[g], a.z2[g]);
 
     // phase A operands: lane supplies row (p0 + lane%16) of Pre and column
     // (l0 + lane%16) of Suf at node m0 + lane/16
@@ -271,8 +285,12 @@ __device__ __forceinline__ void mfma_tile_body(const EvalArgs<T>& a, const MfmaG
         // The next chunk's copies overlap phase B: sB and sthr are no longer
         // read, and its quads go to the other buffer.
         if (k0 + CH < ke) stage(k0 + CH, static_cast<int>(min<int64_t>(CH, ke - k0 - CH)), sq0 + (buf ^ 1) * CH);
-        // phase B: bivariate normal part for this thread's design
-        const auto summand = [&](int i) -> T {
+        // phase B: bivariate normal part for this thread's design; with
+        // kDAlpha also the summand's derivative in alpha_1 (dalpha_term)
+        struct Val {
+            T v, dv;
+        };
+        const auto summand = [&](int i) -> Val {
             const T O = sO[static_cast<size_t>(i) * kEvalBlock + tid];
             const Quad<T> dq = sq[i];
             if constexpr (sizeof(T) == 4) {
@@ -280,44 +298,64 @@ __device__ __forceinline__ void mfma_tile_body(const EvalArgs<T>& a, const MfmaG
                 // k = z2 - sqrt(r I) (b0 + b1 O / r)
                 const float h = fmaf(dq.z, -kPhiScale, st.z1s);
                 const float kq2 = fmaf(-st.a1s, dq.y * O, fmaf(-st.a0s, dq.x, st.z2s));
-                if (a.P.zinf == 0) return bvn_sf_scaled<NMAX>(h, kq2, st.bc, wts, st.n);
-                if (a.P.zinf == 1) return 1.0f - norm_cdf_scaled(kq2);
-                if (a.P.zinf == 2) return 1.0f - norm_cdf_scaled(h);
-                return 0.0f;
+                float dv = 0.0f;
+                if constexpr (MODE == kDAlpha) {
+                    // phi(x) = 2^(-x'^2) / sqrt(2 pi) at the prescaled x'
+                    const float eh = __builtin_amdgcn_exp2f(-h * h);
+                    if (a.P.zinf & 2) {
+                        dv = st.da1 * eh;
+                    } else {
+                        const float ek = __builtin_amdgcn_exp2f(-kq2 * kq2);
+                        const float ph = eh * norm_cdf_scaled(fmaf(kq2, st.is, -st.rs * h));
+                        const float pk = ek * norm_cdf_scaled(fmaf(h, st.is, -st.rs * kq2));
+                        dv = fmaf(st.da1, ph, st.da2 * pk);
+                    }
+                }
+                if (a.P.zinf == 0) return {bvn_sf_scaled<NMAX>(h, kq2, st.bc, wts, st.n), dv};
+                if (a.P.zinf == 1) return {1.0f - norm_cdf_scaled(kq2), dv};
+                if (a.P.zinf == 2) return {1.0f - norm_cdf_scaled(h), dv};
+                return {0.0f, dv};
             } else {
                 const T mu2 = st.srI * (dq.x + dq.y * O * st.invr);
                 const T h = st.z1 - dq.z, kq2 = st.z2 - mu2;
+                T dv = T(0);
+                if constexpr (MODE == kDAlpha) dv = dalpha_term<T, D, NMAX>(a.P, st, h, kq2);
                 // 1 - P(both statistics below their critical values)
-                if (a.P.zinf == 0) return bvn_sf<NMAX>(h, kq2, st.bc, wts, st.n);
-                if (a.P.zinf == 1) return T(1) - norm_cdf(kq2);
-                if (a.P.zinf == 2) return T(1) - norm_cdf(h);
-                return T(0);
+                if (a.P.zinf == 0) return {bvn_sf<NMAX>(h, kq2, st.bc, wts, st.n), dv};
+                if (a.P.zinf == 1) return {T(1) - norm_cdf(kq2), dv};
+                if (a.P.zinf == 2) return {T(1) - norm_cdf(h), dv};
+                return {T(0), dv};
             }
         };
         int i = 0;
         for (; i + 1 < nk; i += 2) {
-            const T v0 = summand(i), v1 = summand(i + 1);
-            if constexpr (sizeof(T) == 4 && !VAR) {
-                s1 += static_cast<double>(v0 + v1);   // pairs of draws summed in FP32 first
+            const Val v0 = summand(i), v1 = summand(i + 1);
+            if constexpr (sizeof(T) == 4 && MODE == kSums) {
+                s1 += static_cast<double>(v0.v + v1.v);   // pairs of draws summed in FP32 first
             } else {
-                s1 += static_cast<double>(v0);
-                s1 += static_cast<double>(v1);
-                if constexpr (VAR) {
-                    s2 = fma(static_cast<double>(v0), static_cast<double>(v0), s2);
-                    s2 = fma(static_cast<double>(v1), static_cast<double>(v1), s2);
+                s1 += static_cast<double>(v0.v);
+                s1 += static_cast<double>(v1.v);
+                if constexpr (MODE == kSquares) {
+                    s2 = fma(static_cast<double>(v0.v), static_cast<double>(v0.v), s2);
+                    s2 = fma(static_cast<double>(v1.v), static_cast<double>(v1.v), s2);
+                } else if constexpr (MODE == kDAlpha) {
+                    s2 += static_cast<double>(v0.dv);
+                    s2 += static_cast<double>(v1.dv);
                 }
             }
         }
         if (i < nk) {
-            const double v = static_cast<double>(summand(i));
+            const Val w = summand(i);
+            const double v = static_cast<double>(w.v);
             s1 += v;
-            if constexpr (VAR) s2 = fma(v, v, s2);
+            if constexpr (MODE == kSquares) s2 = fma(v, v, s2);
+            if constexpr (MODE == kDAlpha) s2 += static_cast<double>(w.dv);
         }
     }
     if (validB) {
         double* out = a.partials + static_cast<int64_t>(slice) * 2 * G;
         out[g] = s1;
-        if constexpr (VAR) out[G + g] = s2;
+        if constexpr (MODE != kSums) out[G + g] = s2;
     }
 }
 

@@ -111,6 +111,8 @@ def test_null_arguments():
     assert lib.bmd_refine_design(None, None, 10, 0, 5, 1e-6, None, None, None, None) == -1
     assert lib.bmd_eval_grid_levels(None, 10, 0, None, 1, None, None, None) == -1
     assert lib.bmd_optimize_levels(None, 10, 0, 0.001, 0.02, 5, None, None, None) == -1
+    assert lib.bmd_eval_grid_dalpha(None, 10, 0, None, None, None) == -1
+    assert lib.bmd_optimize_levels_newton(None, 10, 0, 0.001, 0.02, 5, 1e-10, None, None, None) == -1
     lib.bmd_destroy_problem(None)  # NULL-safe
 
 
@@ -153,3 +155,14 @@ def test_alpha4_design_validation(change, status):
     st, msg = _create_status(spec)
     assert st == status, msg
     assert msg
+
+
+def test_batch_tuning_calls_validate_on_the_host():
+    lib = bmd.library()
+    assert lib.bmd_batch_autotune(3) == -1 and lib.bmd_last_error()
+    out = (ctypes.c_int32 * 5)()
+    assert lib.bmd_batch_settings(0, 0, 1, out) == -2      # no d = 0
+    assert lib.bmd_batch_settings(0, 1, 1, out) == -2      # one biomarker has no matrix-core kind
+    assert lib.bmd_batch_settings(7, 2, 1, out) == -1      # unknown precision
+    assert lib.bmd_batch_settings(0, 2, 1, None) == -1
+    assert lib.bmd_batch_settings(1, 3, 1, out) == -6      # nothing tuned in this process

@@ -150,3 +150,45 @@ def test_batch_single_and_invalid():
         assert wall[0] > 0
         with pytest.raises(bmd.BmdError):
             bmd.eval_batch([p], [0], "fp32")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_autotuner_settings_and_fixed_settings(prec):
+    """The autotuner picks, per launch kind, draws per LDS chunk, rounds of
+    resident workgroups and a launch-bound variant from their candidate sets
+    (timed on the device); later batches reuse them.  Tuned and fixed settings
+    differ only in how the draws are sliced, so their means agree to the FP64
+    summation order, and both agree with the one-problem sweeps."""
+    sc = _scenarios(10, seed=11, m_scale=0.25, draws=(400, 4000))
+    probs = [bmd.Problem(s) for s in sc]
+    M = [s["n_draws"] for s in sc]
+    try:
+        bmd.batch_autotune(2)   # forget earlier tuning: this batch tunes
+        tuned, _ = bmd.eval_batch(probs, M, prec)
+        kinds = sorted({(p.d, 1 if bmd.sweep_kind(p) == "matrix" else 0) for p in probs})
+        step = 8 if prec == "fp32" else 4
+        for d, kind in kinds:
+            st = bmd.batch_settings(prec, d, kind)
+            assert st is not None, (d, kind)
+            say(f"tuned {prec} d={d} kind={kind}: {st}")
+            if kind == 1:
+                assert st["chunk"] == 0 or (st["chunk"] % step == 0 and step <= st["chunk"] <= 32)
+            else:
+                assert st["chunk"] == 0
+            assert st["rounds"] in (2, 4, 8, 16)
+            assert st["variant"] in ((0, 1) if (prec == "fp32" and kind == 1) else (0,))
+            assert st["calibration_us"] > 0
+        again, _ = bmd.eval_batch(probs, M, prec)   # reuses the tuned settings
+        for a, b in zip(tuned, again):
+            assert torch.equal(a, b)
+        bmd.batch_autotune(0)
+        fixed, _ = bmd.eval_batch(probs, M, prec)
+        for p, s, a, b in zip(probs, sc, tuned, fixed):
+            ref = p.eval_grid(s["n_draws"], prec)
+            torch.cuda.synchronize()
+            assert (a - b).abs().max().item() <= 1e-13
+            assert (a - ref).abs().max().item() <= 1e-12
+    finally:
+        bmd.batch_autotune(1)
+        for p in probs:
+            p.close()

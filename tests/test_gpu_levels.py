@@ -159,3 +159,146 @@ def test_level_search_edges():
             with pytest.raises(bmd.BmdError) as e:
                 p.optimize_levels(100, lo, hi, n_iter, "fp64")
             assert e.value.status == -2
+
+
+# ---------------------------------------------------------------- derivative in alpha_1
+# The sweep's alpha_1 derivative (Appendix A.3 through both critical values)
+# against the oracle's chain rule on the same draws.  Bars: the estimate as
+# above; the derivative FP64 1e-9 and FP32 2e-5 of max(|d|, 1) (each FP32
+# summand's derivative carries the FP32 normal CDF's 3e-6 and exp2's 1e-7
+# relative error times da1 + |da2| <= 2/phi(z1) ~ 75 at alpha_1 = 0.01, and
+# the errors of M summands average).
+DTOL = {"fp64": 1e-9, "fp32": 2e-5}
+
+
+def _dalpha_specs():
+    return [dict(W.base_problem(1, [41], 0.0, 0.05), alpha_rule="split", alpha_fixed=(0.01, 0.0)),
+            dict(W.base_problem(2, [9, 7], 0.3, 0.05), alpha_rule="split", alpha_fixed=(0.012, 0.0)),
+            dict(W.base_problem(3, [5, 6, 4], 0.3, 0.05), alpha_rule="split", alpha_fixed=(0.006, 0.0)),
+            dict(W.base_problem(2, [6, 5], 0.3, 0.05), alpha_rule="fixed", alpha_fixed=(0.01, 0.015)),
+            dict(W.base_problem(2, [6, 5], 0.3, 0.05), alpha_rule="fixed", alpha_fixed=(0.01, 0.0)),
+            W.base_problem(1, [17], 0.0, 0.05, info=211.0, effect="paper", paper_a=0.3, paper_b=0.1,
+                           alpha_rule="split", alpha_fixed=(0.008, 0.0))]
+
+
+@pytest.mark.parametrize("i", range(6))
+def test_dalpha_matches_oracle(i):
+    spec = _dalpha_specs()[i]
+    G = O.grid_size(spec)
+    M = 1100
+    ref_m, ref_d = O.eval_grid_dalpha(spec, np.arange(G), M)
+    with bmd.Problem(spec) as p:
+        plain = p.eval_grid(M, "fp64").cpu().numpy()
+        for prec in ("fp64", "fp32"):
+            say(f"dalpha d={spec['d']} rule={spec['alpha_rule']} {prec} kind={bmd.sweep_kind(p)}")
+            m, d = p.eval_grid_dalpha(M, prec)
+            torch.cuda.synchronize()
+            m, d = m.cpu().numpy(), d.cpu().numpy()
+            assert np.all(np.abs(m - ref_m) <= TOL[prec] * np.maximum(np.abs(ref_m), 1e-3)), prec
+            err = np.abs(d - ref_d) / np.maximum(np.abs(ref_d), 1.0)
+            say(f"  max derivative error {err.max():.3g}")
+            assert np.all(err <= DTOL[prec]), (prec, int(np.argmax(err)), d[np.argmax(err)], ref_d[np.argmax(err)])
+            if prec == "fp64":
+                assert np.array_equal(m, plain)   # the same sums as the plain sweep
+
+
+def test_dalpha_full_size_3d():
+    """The benchmarked 64^3 grid at M = 1e5 under the split rule: the FP32
+    derivative within its bar of the FP64 one everywhere, and a strided
+    subgrid of both against the oracle at M = 200."""
+    spec = dict(W.plain_3d(), alpha_rule="split", alpha_fixed=(0.01, 0.0))
+    G, M = O.grid_size(spec), spec["n_draws"]
+    with bmd.Problem(spec) as p:
+        say(f"dalpha full grid G={G} M={M}")
+        m32, d32 = (t.cpu().numpy() for t in p.eval_grid_dalpha(M, "fp32"))
+        m64, d64 = (t.cpu().numpy() for t in p.eval_grid_dalpha(M, "fp64"))
+        assert np.max(np.abs(m32 - m64) / np.maximum(np.abs(m64), 1e-3)) <= 1e-5
+        err = np.abs(d32 - d64) / np.maximum(np.abs(d64), 1.0)
+        say(f"  FP32 vs FP64 derivative max error {err.max():.3g}")
+        assert err.max() <= DTOL["fp32"]
+        Ms = 200
+        gs = np.arange(0, G, 997)
+        ref_m, ref_d = O.eval_grid_dalpha(spec, gs, Ms)
+        for prec in ("fp64", "fp32"):
+            m, d = (t.cpu().numpy()[gs] for t in p.eval_grid_dalpha(Ms, prec))
+            assert np.all(np.abs(m - ref_m) <= TOL[prec] * np.maximum(np.abs(ref_m), 1e-3)), prec
+            assert np.all(np.abs(d - ref_d) <= DTOL[prec] * np.maximum(np.abs(ref_d), 1.0)), prec
+
+
+def test_dalpha_rejected_where_undefined():
+    with bmd.Problem(_specs()[0]) as p:          # rule "fwer": one level for both tests
+        with pytest.raises(bmd.BmdError) as e:
+            p.eval_grid_dalpha(100)
+        assert e.value.status == -5
+    with bmd.Problem(dict(_specs()[0], alpha_rule="fixed", alpha_fixed=(0.0, 0.02))) as p:
+        with pytest.raises(bmd.BmdError) as e:
+            p.eval_grid_dalpha(100)
+        assert e.value.status == -2
+    with bmd.Problem(W.alpha_design(9)) as p:    # the alpha design space
+        with pytest.raises(bmd.BmdError) as e:
+            p.eval_grid_dalpha(100)
+        assert e.value.status == -6
+
+
+@pytest.mark.parametrize("spec,M", [(W.base_problem(2, [4, 3], 0.3, 0.05), 700),
+                                    (W.base_problem(1, [9], 0.0, 0.05), 513),
+                                    (dict(W.base_problem(2, [4, 3], 0.3, 0.05), alpha_rule="fixed",
+                                          alpha_fixed=(0.01, 0.0)), 300)])
+def test_newton_level_search_matches_oracle(spec, M):
+    """Per-design false-position search on the derivative (25 steps, tol
+    1e-12): FP64 best power within 1e-9 of the oracle's search on the same
+    draws and the level within 1e-7 (near the root a derivative within 1e-9 of
+    zero may send the bracket the other way); FP32 power within its bar and the
+    level within 1e-4.  The problem's critical values and rule are restored
+    (a "fixed" problem with its second test off sweeps as before)."""
+    G = O.grid_size(spec)
+    say(f"newton level search d={spec['d']} G={G} M={M}")
+    ref_best, ref_x = O.optimize_levels_newton(spec, np.arange(G), M, 0.001, 0.024, 25, 1e-12)
+    with bmd.Problem(spec) as p:
+        before = p.designs(0, G).cpu().numpy()
+        plain = p.eval_grid(M, "fp64").cpu().numpy()
+        for prec in ("fp64", "fp32"):
+            best, a1 = p.optimize_levels_newton(M, 0.001, 0.024, 25, 1e-12, prec)
+            torch.cuda.synchronize()
+            best, a1 = best.cpu().numpy(), a1.cpu().numpy()
+            bound = TOL[prec] * np.maximum(np.abs(ref_best), 1e-3)
+            assert np.all(np.abs(best - ref_best) <= bound), (prec, best, ref_best)
+            assert np.max(np.abs(a1 - ref_x)) <= (1e-7 if prec == "fp64" else 1e-4), (prec, a1, ref_x)
+        after = p.designs(0, G).cpu().numpy()
+        again = p.eval_grid(M, "fp64").cpu().numpy()
+    assert np.array_equal(before, after)
+    assert np.array_equal(plain, again)
+
+
+def test_newton_and_golden_searches_agree():
+    """Both searches maximise the same deterministic function of alpha_1 on
+    the same draws: the derivative's root after 12 steps and the golden-section
+    maximum after 40 give the same power to 1e-10."""
+    spec = W.base_problem(3, [5, 6, 4], 0.3, 0.05)
+    M = 2000
+    with bmd.Problem(spec) as p:
+        nb, nx = (t.cpu().numpy() for t in p.optimize_levels_newton(M, 0.001, 0.024, 12, 1e-12, "fp64"))
+        gb, gx = (t.cpu().numpy() for t in p.optimize_levels(M, 0.001, 0.024, 40, "fp64"))
+    assert np.all(np.abs(nb - gb) <= 1e-10), np.max(np.abs(nb - gb))
+    assert np.max(np.abs(nx - gx)) < 2e-4
+
+
+def test_newton_level_search_edges():
+    """No false-position steps (the two ends only) and a single draw against
+    the oracle; ranges outside (0, alpha0), step counts outside [0, 200] and a
+    negative tolerance are rejected before any launch."""
+    spec = W.base_problem(2, [3, 3], 0.3, 0.05)
+    G = O.grid_size(spec)
+    with bmd.Problem(spec) as p:
+        for n_iter, M in ((0, 300), (3, 1)):
+            ref_best, ref_x = O.optimize_levels_newton(spec, np.arange(G), M, 0.002, 0.02, n_iter, 0.0)
+            best, a1 = p.optimize_levels_newton(M, 0.002, 0.02, n_iter, 0.0, "fp64")
+            torch.cuda.synchronize()
+            best, a1 = best.cpu().numpy(), a1.cpu().numpy()
+            assert np.all(np.abs(best - ref_best) <= 1e-9 * np.maximum(np.abs(ref_best), 1e-3)), (n_iter, M)
+            assert np.max(np.abs(a1 - ref_x)) <= 1e-7, (n_iter, M)
+        for lo, hi, n_iter, tol in ((0.0, 0.01, 5, 0.0), (0.01, 0.005, 5, 0.0), (0.001, 0.025, 5, 0.0),
+                                    (0.001, 0.02, 201, 0.0), (0.001, 0.02, -1, 0.0), (0.001, 0.02, 5, -1.0)):
+            with pytest.raises(bmd.BmdError) as e:
+                p.optimize_levels_newton(100, lo, hi, n_iter, tol, "fp64")
+            assert e.value.status == -2

@@ -537,6 +537,125 @@ def test_alpha_design_grid_and_smoothing():
     assert np.max(np.abs(O.smooth_direct(p, f) - O.smooth_separable(p, f))) < 1e-14
 
 
+# ---------------------------------------------------------------- derivative in alpha_1
+# Appendix A.3 differentiates the power under the integral; for the nested pair
+# the oracle's chain rule runs through z1 and, under the split rule, through the
+# second level on the FWER boundary.
+
+def _one_level_spec(rule, a1, a2=0.0, **kw):
+    p = W.base_problem(2, [5, 4], 0.3, 0.05, alpha_rule=rule, alpha_fixed=(a1, a2))
+    p.update(kw)
+    return p
+
+
+@pytest.mark.parametrize("rule,a2", [("split", 0.0), ("fixed", 0.015), ("fixed", 0.0)])
+def test_dalpha_is_the_derivative_of_the_estimate(rule, a2):
+    """On fixed draws the estimate is one smooth function of alpha_1: its
+    central differences (step 1e-6, the second level re-solved on the boundary
+    under "split") match the chain-rule derivative.  Dropping the dz2/dz1 term,
+    a sign, or phi(z1)'s factor misses by orders of magnitude."""
+    a1, h, M = 0.01, 1e-6, 300
+    g = np.arange(20)
+    m, d = O.eval_grid_dalpha(_one_level_spec(rule, a1, a2), g, M)
+    mp, _ = O.eval_grid(_one_level_spec(rule, a1 + h, a2), g, M)
+    mm, _ = O.eval_grid(_one_level_spec(rule, a1 - h, a2), g, M)
+    m0, _ = O.eval_grid(_one_level_spec(rule, a1, a2), g, M)
+    assert np.array_equal(m, m0)
+    cd = (mp - mm) / (2 * h)
+    assert np.max(np.abs(d - cd) / np.maximum(np.abs(cd), 1.0)) < 1e-6, (d, cd)
+    assert np.max(np.abs(d)) > 0.1
+
+
+def _point_mass_power(a1, r, I, a, b, rule, a2=0.0):
+    """A prior with all its mass at one effect (E -> infinity in Formula 10):
+    the power 1 - Phi_2(z1 - sqrt(I) theta_1, z2 - sqrt(r I) theta_2; sqrt r)
+    with scipy's Owen's T and brentq for the boundary."""
+    z1 = -ndtri(a1)
+    z2 = _z2_scipy(z1, r) if rule == "split" else (-ndtri(a2) if a2 > 0 else math.inf)
+    th1, th2 = -math.log(1 - (a - b)), -math.log(1 - (a - b * r))
+    h, k = z1 - math.sqrt(I) * th1, z2 - math.sqrt(r * I) * th2
+    if math.isinf(k):
+        return 1.0 - ndtr(h)
+    return 1.0 - _bvn_owen(h, k, math.sqrt(r))
+
+
+@pytest.mark.parametrize("rule,a2", [("split", 0.0), ("fixed", 0.0), ("fixed", 0.02)])
+def test_dalpha_point_mass_prior_exact(rule, a2):
+    """With (almost) no prior spread every draw is the same effect, so the
+    estimate's derivative is the closed-form power's, differentiated here by
+    central differences of the scipy expression (step 1e-6)."""
+    I, a, b = 211.0, 0.3, 0.1
+    p = W.base_problem(1, [3], 0.0, 0.05, q_lo=0.535, q_hi=0.735, info=I, effect="paper", paper_a=a,
+                       paper_b=b, paper_events=1e18, alpha_rule=rule, alpha_fixed=(0.01, a2))
+    r = O.make_design(p, O.grid_point(p, 1)[0])["r"]
+    m, d = O.eval_grid_dalpha(p, [1], 64)
+    hh = 1e-6
+    ref = (_point_mass_power(0.01 + hh, r, I, a, b, rule, a2) - _point_mass_power(0.01 - hh, r, I, a, b, rule, a2)) / (2 * hh)
+    assert abs(m[0] - _point_mass_power(0.01, r, I, a, b, rule, a2)) < 1e-7
+    assert abs(d[0] - ref) <= 1e-6 * max(abs(ref), 1.0), (d[0], ref)
+
+
+def test_dalpha_one_test_closed_form_appendix_a3():
+    """Appendix A.3's one-test form: with the second test off, dP/d alpha =
+    E[phi(z - mu1)] / phi(z); under Formula 10 mu1 ~ N(sqrt(I) theta_1, I/20)
+    (E = 80), so E[phi(z - mu1)] = phi((z - m)/s)/s with s^2 = 1 + I/20.  The
+    estimate over 2e5 draws is within 6 standard errors (from 10 blocks)."""
+    I, a, b = 211.0, 0.3, 0.1
+    p = W.base_problem(1, [3], 0.0, 0.05, info=I, effect="paper", paper_a=a, paper_b=b, paper_events=80.0,
+                       alpha_rule="fixed", alpha_fixed=(0.01, 0.0))
+    z = -ndtri(0.01)
+    m1 = math.sqrt(I) * -math.log(1 - (a - b))
+    s = math.sqrt(1 + I / 20.0)
+    pdf = lambda x: math.exp(-0.5 * x * x) / math.sqrt(2 * math.pi)  # noqa: E731
+    closed = pdf((z - m1) / s) / (s * pdf(z))
+    blocks = [O.eval_grid_dalpha(p, [1], 20_000, k0=20_000 * i)[1][0] for i in range(10)]
+    se = np.std(blocks, ddof=1) / math.sqrt(len(blocks))
+    assert abs(np.mean(blocks) - closed) < 6 * se, (np.mean(blocks), closed, se)
+    assert se < 0.02 * closed
+
+
+def test_dalpha_split_rule_converges_to_closed_form():
+    """Under the split rule and Formula 10 (condition (b), r = 0.365) the
+    estimate's derivative converges to the derivative of the closed-form power
+    (scipy, central differences): within 6 standard errors over 2e5 draws."""
+    p = W.base_problem(1, [3], 0.0, 0.05, q_lo=0.535, q_hi=0.735, info=211.0, effect="paper", paper_a=0.3,
+                       paper_b=0.1, paper_events=80.0, alpha_rule="split", alpha_fixed=(0.008, 0.0))
+    r = O.make_design(p, O.grid_point(p, 1)[0])["r"]
+    hh = 1e-6
+    ref = (_alpha_power_scipy(0.008 + hh, r) - _alpha_power_scipy(0.008 - hh, r)) / (2 * hh)
+    blocks = [O.eval_grid_dalpha(p, [1], 20_000, k0=20_000 * i)[1][0] for i in range(10)]
+    se = np.std(blocks, ddof=1) / math.sqrt(len(blocks))
+    assert abs(np.mean(blocks) - ref) < 6 * se, (np.mean(blocks), ref, se)
+    assert se < 0.05 * abs(ref)
+
+
+def test_newton_level_search_finds_the_derivative_root():
+    """The oracle's false-position search on fixed draws: where it stops
+    inside the range the estimate's derivative is zero to 1e-6 (the probe with
+    the largest estimate, which rounding picks among a few equal ones) and the level
+    beats its neighbours at +-1e-4; it agrees with the golden-section search's
+    maximum (80 steps) to 1e-12 in power; a design whose derivative keeps one
+    sign over the range ends at that end."""
+    spec = W.base_problem(2, [5, 4], 0.3, 0.05)
+    g = np.arange(20)
+    M = 300
+    best, x = O.optimize_levels_newton(spec, g, M, 0.001, 0.024, 40, 1e-12)
+    gb, gx = O.optimize_levels(spec, g, M, 0.001, 0.024, 80)
+    assert np.all(np.abs(best - gb) <= 1e-12 * np.maximum(1.0, np.abs(gb)))
+    inside = (x > 0.001) & (x < 0.024)
+    assert inside.sum() >= 5
+    for i in np.nonzero(inside)[0][:6]:
+        sp = dict(spec, alpha_rule="split", alpha_fixed=(float(x[i]), 0.0))
+        m, d = O.eval_grid_dalpha(sp, [g[i]], M)
+        assert abs(m[0] - best[i]) <= 1e-15 and abs(d[0]) < 1e-6, (i, d[0])
+        for dx in (-1e-4, 1e-4):
+            mn, _ = O.eval_grid(dict(sp, alpha_fixed=(float(x[i]) + dx, 0.0)), [g[i]], M)
+            assert mn[0] < best[i]
+        assert abs(x[i] - gx[i]) < 1e-5
+    for i in np.nonzero(~inside)[0]:
+        assert abs(x[i] - gx[i]) < 1e-9
+
+
 # ---------------------------------------------------------------- continuous refinement
 
 def test_refinement_reaches_the_maximiser_of_a_deterministic_objective():
@@ -862,3 +981,24 @@ def test_alpha4_closed_form_against_scipy():
         z = [ds["z1"], ds["z2"], ds["z3"], ds["z4"]]
         h = [(z[i] - math.sqrt(r[i] * I) * (-math.log(1 - (0.8 - 0.6 * r[i])))) / s for i in range(4)]
         assert abs(O.exact_paper(p, np.array(a)) - (1.0 - _qvn_scipy(h, _nested_R(r)))) < 2e-7
+
+
+def test_smoothed_surface_at_continuous_designs():
+    """The oracle's Nadaraya-Watson sum at a continuous design: at grid designs
+    it is the masked smoother's value (and the direct one without NaN), a
+    constant stays constant, a huge bandwidth gives the mean of the valid
+    values, and swapping the axes of a symmetric surface and point leaves it."""
+    spec = W.base_problem(2, [9, 9], 0.3, 0.08)
+    f = W.noisy_surface([9, 9], seed=2)
+    f[:3] = np.nan
+    sm = O.smooth_masked(spec, f)
+    for g in (10, 40, 80):
+        q, _ = O.grid_point(spec, g)
+        assert abs(O.smooth_at(spec, f, q) - sm[g]) < 1e-14
+    c = np.where(np.isnan(f), np.nan, 0.42)
+    assert abs(O.smooth_at(spec, c, [0.33, 0.71]) - 0.42) < 1e-15
+    wide = dict(spec, bandwidth=[1e5, 1e5])
+    assert abs(O.smooth_at(wide, f, [0.2, 0.6]) - np.nanmean(f)) < 1e-12
+    s = W.noisy_surface([9, 9], seed=3).reshape(9, 9)
+    s = (s + s.T).ravel()
+    assert abs(O.smooth_at(spec, s, [0.3, 0.6]) - O.smooth_at(spec, s, [0.6, 0.3])) < 1e-14

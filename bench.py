@@ -205,7 +205,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="3d", choices=["3d", "1d", "5d", "alpha", "alpha3", "alpha4", "levels", "grad", "refine", "batch"])
+    ap.add_argument("--workload", default="3d", choices=["3d", "1d", "5d", "alpha", "alpha3", "alpha4", "levels", "grad",
+                                                         "refine", "batch", "smooth"])
     ap.add_argument("--batch-scale", type=float, default=1.0,
                     help="batch workload only: scale of the per-axis grids and of the draw range (1 = full size)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -246,6 +247,8 @@ def main():
         return bench_levels(args)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "smooth":
+        return bench_smooth(args)
     spec = workload(args.workload)
     M, G = spec["n_draws"], int(np.prod(spec["m"]))
     log(f"workload {args.workload}: d={spec['d']} grid={spec['m']} G={G} M={M}")
@@ -508,6 +511,33 @@ def bench_levels(args):
                     ts.append(dt)
                 log(f"  level search {prec} step {it}: {1e3 * dt:.1f} ms")
             srch[prec] = (float(np.mean(ts)), sb, sa)
+        # per-design false-position search on the alpha_1 derivative, same range
+        n_newton = 8
+        nwt = {}
+        for prec in ("fp32", "fp64"):
+            ts = []
+            for it in range(args.warmup + args.steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                nb, na = p.optimize_levels_newton(M, float(alphas[0]), float(alphas[-1]), n_newton, 1e-9, prec)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                if it >= args.warmup:
+                    ts.append(dt)
+                log(f"  derivative search {prec} step {it}: {1e3 * dt:.1f} ms")
+            nwt[prec] = (float(np.mean(ts)), nb, na)
+    # the derivative sweep alone (value and alpha_1 derivative per design) on
+    # the split rule at the middle of the level range
+    with bmd.Problem(dict(spec, alpha_rule="split", alpha_fixed=(float(np.median(alphas)), 0.0))) as q:
+        ts = []
+        for it in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            q.eval_grid_dalpha(M, "fp32")
+            torch.cuda.synchronize()
+            if it >= args.warmup:
+                ts.append(time.perf_counter() - t0)
+        t_dsweep = float(np.mean(ts))
     t32, b32, k32 = res["fp32"]
     t64, b64, k64 = res["fp64"]
     evals = G * M * len(alphas)
@@ -532,7 +562,63 @@ def bench_levels(args):
                             "max_best": float(srch["fp32"][1].max()),
                             "mean_gain_over_level_grid": float((srch["fp32"][1] - b32).mean()),
                             "share_above_level_grid": float((srch["fp32"][1] >= b32 - 1e-12).double().mean()),
-                            "max_abs_diff_best_fp32_fp64": float((srch["fp32"][1] - srch["fp64"][1]).abs().max())}}
+                            "max_abs_diff_best_fp32_fp64": float((srch["fp32"][1] - srch["fp64"][1]).abs().max())},
+           "derivative_search": {
+               "method": f"false position on d P / d alpha_1 per design over [{alphas[0]:.4g}, {alphas[-1]:.4g}], "
+                         f"{n_newton} steps after the two ends ({n_newton + 2} derivative sweeps on shared draws)",
+               "ms_fp32": 1e3 * nwt["fp32"][0], "ms_fp64": 1e3 * nwt["fp64"][0],
+               "derivative_sweep_ms_fp32": 1e3 * t_dsweep,
+               "max_best": float(nwt["fp32"][1].max()),
+               "mean_gain_over_golden": float((nwt["fp32"][1] - srch["fp32"][1]).mean()),
+               "share_at_or_above_golden": float((nwt["fp32"][1] >= srch["fp32"][1] - 1e-12).double().mean()),
+               "max_abs_diff_best_fp32_fp64": float((nwt["fp32"][1] - nwt["fp64"][1]).abs().max())}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_smooth(args):
+    """Smoothing of a grid surface (Sec. 2.3's fit of the noisy estimates): the
+    separable Nadaraya-Watson smoother of the 5-biomarker 24^5 grid (bandwidth
+    0.03) on a seeded synthetic surface, FP32 and FP64 matrix cores.  Each of
+    the d axis passes reads and writes the FP64 surface once (16 G bytes), the
+    bound is HBM; the matrix cores do 2 m G flops per pass.  Times are the
+    smoothing kernels' device time (HIP events on the launch stream)."""
+    import torch
+    import paper_2005_10494_amd as bmd
+    from paper_2005_10494_amd import workloads as W
+    spec = W.precision_5d()
+    G, d, m = int(np.prod(spec["m"])), spec["d"], spec["m"][0]
+    raw = torch.tensor(W.noisy_surface(spec["m"], seed=5), dtype=torch.float64, device="cuda")
+    res = {}
+    with bmd.Problem(spec) as p:
+        p.profile(True)
+        for prec in ("fp32", "fp64"):
+            ts = []
+            for it in range(args.warmup + args.steps):
+                out = p.smooth(raw, prec)
+                torch.cuda.synchronize()
+                ms = p.profile_read()["smooth"]
+                if it >= args.warmup:
+                    ts.append(ms)
+                log(f"  smooth {prec} step {it}: {ms:.3f} ms")
+            res[prec] = (float(np.mean(ts)), out)
+    bytes_call = 16.0 * G * d
+    flops_call = 2.0 * m * G * d
+    t32, s32 = res["fp32"]
+    t64, s64 = res["fp64"]
+    gbs = bytes_call / (t32 * 1e-3) / 1e9
+    out = {"metric": "surface smoothing: HBM GB/s", "value": gbs, "unit": "GB/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": t32, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"separable Nadaraya-Watson smoothing of a {d}-biomarker "
+                                  f"{'x'.join(map(str, spec['m']))} grid surface (seeded synthetic), bandwidth "
+                                  f"{spec['bandwidth'][0]}, {d} axis passes", "designs": G},
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
+                        "traffic": None, "kernel": "k_smooth_mfma<float> (one 16x16 output tile per wavefront)",
+                        "bytes_per_call": bytes_call,
+                        "mfma": {"achieved": flops_call / (t32 * 1e-3) / 1e12, "peak": PEAK_MFMA_FP32_TFLOPS,
+                                 "unit": "TFLOP/s", "flops_per_call": flops_call}},
+           "fp64": {"ms_per_step": t64, "gb_per_s": bytes_call / (t64 * 1e-3) / 1e9},
+           "fp32_vs_fp64": {"max_abs_diff": float((s32 - s64).abs().max())}}
     print(json.dumps(out), flush=True)
 
 

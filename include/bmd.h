@@ -372,9 +372,6 @@ bmd_status bmd_eval_batch(bmd_problem *const *ps, int32_t n, const uint64_t *n_d
                           int32_t prec, double *const *d_means, double *h_wall_ms,
                           void *stream);
 
-/* ---- profiling ------------------------------------------------------------ */
-
-#define BMD_PROFILE_PHASES 5
 /* The smoothed surface at a continuous design (the fitted surface of Sec. 2.3,
  * evaluated between grid points): the Nadaraya-Watson ratio of bmd_smooth,
  *   S(q) = sum_h K(q, q_h) f_h / sum_h K(q, q_h),
@@ -428,6 +425,9 @@ bmd_status bmd_batch_autotune(int32_t mode);
  * microseconds.  ESTATE when no batch has tuned that kind yet. */
 bmd_status bmd_batch_settings(int32_t prec, int32_t d, int32_t kind, int32_t *h_out /*[5]*/);
 
+/* ---- profiling ------------------------------------------------------------ */
+
+#define BMD_PROFILE_PHASES 5
 /* Turn per-phase timing on (enable != 0) or off.  While on, bmd_eval_grid,
  * bmd_smooth and bmd_argmax record HIP events around their kernels on the
  * stream they launch on. */

@@ -339,13 +339,19 @@ bool valid_prec(int32_t prec) { return prec == BMD_FP64 || prec == BMD_FP32_COMP
 
 // Draw slices of a grid sweep: about kSweepRounds full rounds of resident
 // workgroups, so the partly filled last round costs little; slices of at
-// least 64 draws, whole draw chunks of the matrix-core sweep.
+// least 64 draws, whole draw chunks of the matrix-core sweep, and for that
+// sweep no more staged draw bytes per slice than the problem's slice budget.
 void sweep_slices(bmd_problem* p, int prec, int64_t M, int64_t* n_slices_out, int64_t* slice_len_out) {
     const int64_t bx = sweep_tiles(p, prec);
     if (p->sweep_bpc[prec] == 0) p->sweep_bpc[prec] = sweep_blocks_per_cu(p, prec);
     const int64_t resident = static_cast<int64_t>(p->n_cu) * p->sweep_bpc[prec];
     const int64_t chunk = sweep_chunk(p, prec);
     int64_t n_slices = (kSweepRounds * resident + bx - 1) / bx;
+    const int64_t per_draw = sweep_staged_bytes_per_draw(p, prec);
+    if (per_draw > 0 && p->slice_bytes > 0) {
+        const int64_t len = std::max<int64_t>(chunk, p->slice_bytes / per_draw / chunk * chunk);
+        n_slices = std::max<int64_t>(n_slices, (M + len - 1) / len);
+    }
     n_slices = std::max<int64_t>(1, std::min<int64_t>({n_slices, (M + 63) / 64, 65535}));
     int64_t slice_len = (M + n_slices - 1) / n_slices;
     slice_len = (slice_len + chunk - 1) / chunk * chunk;
@@ -491,6 +497,9 @@ bmd_status bmd_create_problem(const bmd_problem_desc* desc, bmd_problem** out, v
         // problem; both sweeps compute the same estimate (used by the tests).
         const char* sw = std::getenv("BMD_SWEEP");
         p->force_direct = sw && std::strcmp(sw, "direct") == 0;
+        // BMD_SLICE_BYTES overrides the staged-draw budget of a sweep slice
+        // (bytes, 0 = no limit; for measurements)
+        if (const char* sb = std::getenv("BMD_SLICE_BYTES")) p->slice_bytes = std::max<int64_t>(0, std::atoll(sb));
     }
 
     // Quadrature rules.

@@ -16,6 +16,11 @@ constexpr int kPrecomputeGH = 128;   // nodes for the per-design subgroup fracti
 constexpr int kGLTable = 200;        // packed Gauss-Legendre rules n = 4..24
 constexpr int kEvalBlock = 256;      // designs per workgroup in the eval kernels
 constexpr int kSweepRounds = 8;      // rounds of resident workgroups a grid sweep is sliced into
+// Staged draw bytes (node tables, drift quads, thresholds) of one matrix-core
+// sweep slice, at most: the resident workgroups of a slice start at different
+// times and each walks the whole slice, so one slice is the window of draws
+// the L2 of an XCD (4 MB) has to hold while the tiles re-read it.
+constexpr int64_t kSliceBytes = 2 << 20;
 constexpr size_t kBatchBudget = size_t(96) << 30;   // draw bytes one batch group may hold
 constexpr size_t kGradDrawBudget = size_t(4) << 30; // draw bytes one gradient pass may hold
 
@@ -129,6 +134,7 @@ struct bmd_problem {
     size_t ws2_cap = 0;
     std::vector<double> gh_host[2];  // host copies of the eval GH rules
     bool force_direct = false;      // BMD_SWEEP=direct: use the direct sweep everywhere
+    int64_t slice_bytes = bmd::kSliceBytes;   // staged draw bytes per matrix-core sweep slice (0: no limit)
     bool profiling = false;
     hipEvent_t ev[10] = {};          // begin/end pairs per profiled phase
     bool ev_used[5] = {false, false, false, false, false};
@@ -172,6 +178,8 @@ bool use_mfma_sweep(const bmd_problem* p);
 int64_t sweep_tiles(const bmd_problem* p, int prec);
 int sweep_blocks_per_cu(const bmd_problem* p, int prec);
 int sweep_chunk(const bmd_problem* p, int prec);
+// Bytes of one draw that a matrix-core sweep tile stages (0 for the direct sweep).
+int64_t sweep_staged_bytes_per_draw(const bmd_problem* p, int prec);
 struct MfmaGeom;
 MfmaGeom sweep_geometry(const bmd_problem* p, int prec);
 // want_var: also write the sums of squares (the second half of each slice).

@@ -75,9 +75,10 @@ MfmaGeom mfma_geometry(const bmd_problem* p, int prec) {
     // phase A full (a multiple of 8 in FP32: two draws per pass, four
     // wavefronts; of 4 in FP64) within the LDS share of the resident
     // workgroups: five per compute unit for FP32 with up to three biomarkers
-    // (32 KB each of 160 KB), else four (40 KB).
+    // (32 KB each of 160 KB), else four (40 KB); FP64 holds two (its
+    // registers allow no more), 64 KB each.
     const int step = prec == BMD_FP64 ? 4 : 8;
-    const size_t cap = prec != BMD_FP64 && d <= 3 ? 32 * 1024 : 40 * 1024;
+    const size_t cap = prec == BMD_FP64 ? 64 * 1024 : d <= 3 ? 32 * 1024 : 40 * 1024;
     int ch = 32;
     while (ch > step && (prec == BMD_FP64 ? mfma_lds_bytes<double>(ch, d, K) : mfma_lds_bytes<float>(ch, d, K)) > cap)
         ch -= step;
@@ -196,6 +197,12 @@ int sweep_blocks_per_cu(const bmd_problem* p, int prec) {
 
 int sweep_chunk(const bmd_problem* p, int prec) {
     return use_mfma_sweep(p) ? mfma_geometry(p, prec).chunk : 1;
+}
+
+int64_t sweep_staged_bytes_per_draw(const bmd_problem* p, int prec) {
+    if (!use_mfma_sweep(p)) return 0;
+    const int64_t T = prec == BMD_FP64 ? 8 : 4, d = p->P.d, K = p->tab[prec].K;
+    return d * K * T + 4 * T + 4 * d;
 }
 
 hipError_t launch_eval_grid(const bmd_problem* p, int prec, int64_t M, const void* ws, double* partials,

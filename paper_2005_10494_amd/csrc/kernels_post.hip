@@ -27,35 +27,98 @@ __device__ __forceinline__ mfma_f4 mfma_step(float a, float b, mfma_f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// One separable smoothing pass as a batched GEMM on the matrix cores:
-//   out(i, n) = sum_h W[i][h] in(h, n),  i, h < m,  n < N,
-// with in(h, n) = in[ob + h*sh + n*sn] (same for out) and ob = blockIdx.z * ostride.
-// One wavefront per 16x16 output tile; T is the arithmetic type (FP64 or FP32,
-// the FP32 path converting the FP64 surface on load and accumulating in FP32).
-template <typename T>
+// One separable smoothing pass as a GEMM on the matrix cores:
+//   out(i, c) = sum_h W[i][h] in(h, c),  i, h < m,  c < C,
+// where the columns c run over every (outer, inner) pair of the axis, the
+// element (h, c) of the surface sitting at (c / inner) m inner + h inner +
+// c % inner.  One wavefront owns CT tiles of 16 columns and the NI row blocks
+// of 16 starting at block blockIdx.y * NI; with one group of row blocks per
+// column tile each surface value is loaded once per pass.  W (m x m) stays in
+// the caches.
+// T is the arithmetic type (FP64, or FP32 converting the FP64 surface on load
+// and accumulating in FP32).
+template <typename T, int NI, int CT>
 __global__ __launch_bounds__(64) void k_smooth_mfma(const T* __restrict__ W, int m, const double* __restrict__ in,
-                                                    double* __restrict__ out, int64_t N, int64_t sh, int64_t sn,
-                                                    int64_t ostride) {
+                                                    double* __restrict__ out, int64_t C, int64_t inner) {
     using acc_t = typename std::conditional<sizeof(T) == 8, mfma_d4, mfma_f4>::type;
     const int lane = threadIdx.x;
     const int r = lane & 15, kq = lane >> 4;
-    const int64_t n0 = static_cast<int64_t>(blockIdx.x) * 16;
-    const int i0 = blockIdx.y * 16;
-    const int64_t ob = static_cast<int64_t>(blockIdx.z) * ostride;
-    const int i = i0 + r;
-    const int64_t n = n0 + r;
-    acc_t c = {0, 0, 0, 0};
-    for (int h0 = 0; h0 < m; h0 += 4) {
-        const int h = h0 + kq;
-        const T a = (i < m && h < m) ? W[static_cast<int64_t>(i) * m + h] : T(0);
-        const T b = (h < m && n < N) ? static_cast<T>(in[ob + h * sh + n * sn]) : T(0);
-        c = mfma_step(a, b, c);
-    }
+    bool valid[CT];
+    int64_t base[CT];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int io = i0 + mfma16_row<T>(kq, v);
-        if (io < m && n < N) out[ob + io * sh + n * sn] = static_cast<double>(c[v]);
+    for (int t = 0; t < CT; ++t) {
+        const int64_t c = (static_cast<int64_t>(blockIdx.x) * CT + t) * 16 + r;
+        valid[t] = c < C;
+        base[t] = valid[t] ? (c / inner) * m * inner + c % inner : 0;
     }
+    const int nblk = (m + 15) / 16;
+    {
+        const int b0 = blockIdx.y * NI;
+        acc_t acc[CT][NI];
+#pragma unroll
+        for (int t = 0; t < CT; ++t)
+#pragma unroll
+            for (int ib = 0; ib < NI; ++ib) acc[t][ib] = acc_t{0, 0, 0, 0};
+        for (int h0 = 0; h0 < m; h0 += 4) {
+            const int h = h0 + kq;
+            T b[CT];
+#pragma unroll
+            for (int t = 0; t < CT; ++t) b[t] = (h < m && valid[t]) ? static_cast<T>(in[base[t] + h * inner]) : T(0);
+#pragma unroll
+            for (int ib = 0; ib < NI; ++ib) {
+                if (b0 + ib < nblk) {   // wave-uniform
+                    const int i = (b0 + ib) * 16 + r;
+                    const T a = (i < m && h < m) ? W[static_cast<int64_t>(i) * m + h] : T(0);
+#pragma unroll
+                    for (int t = 0; t < CT; ++t) acc[t][ib] = mfma_step(a, b[t], acc[t][ib]);
+                }
+            }
+        }
+#pragma unroll
+        for (int ib = 0; ib < NI; ++ib) {
+            if (b0 + ib < nblk) {
+#pragma unroll
+                for (int t = 0; t < CT; ++t) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int io = (b0 + ib) * 16 + mfma16_row<T>(kq, v);
+                        if (io < m && valid[t]) out[base[t] + io * inner] = static_cast<double>(acc[t][ib][v]);
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <typename T, int CT, int NI>
+void launch_smooth_group(const T* W, int m, const double* in, double* out, int64_t C, int64_t inner, hipStream_t s) {
+    const int nblk = (m + 15) / 16;
+    const dim3 grid(static_cast<unsigned>((C + 16 * CT - 1) / (16 * CT)), static_cast<unsigned>((nblk + NI - 1) / NI));
+    hipLaunchKernelGGL((k_smooth_mfma<T, NI, CT>), grid, dim3(64), 0, s, W, m, in, out, C, inner);
+}
+
+// Surfaces with many columns (at least 4,096 tiles of 16): two column tiles
+// per wavefront and all row blocks in one group, each value read once
+// (measured in FP32 on the 24^5 surface: 3.0 TB/s with one row block per
+// wavefront and columns along the inner index only, 3.3 with one tile and
+// all row blocks, 3.8 with two tiles, 3.3 with four).  Fewer columns: one tile
+// and one row block per wavefront, so that small grids still spread over the
+// compute units (a 97 x 97 grid has 97 columns per pass).
+template <typename T>
+void launch_smooth_pass(const T* W, int m, const double* in, double* out, int64_t C, int64_t inner, hipStream_t s) {
+    const int nblk = (m + 15) / 16;
+    if ((C + 15) / 16 < 4096)
+        launch_smooth_group<T, 1, 1>(W, m, in, out, C, inner, s);
+    else if (nblk <= 1)
+        launch_smooth_group<T, 2, 1>(W, m, in, out, C, inner, s);
+    else if (nblk <= 2)
+        launch_smooth_group<T, 2, 2>(W, m, in, out, C, inner, s);
+    else if (nblk <= 4)
+        launch_smooth_group<T, 2, 4>(W, m, in, out, C, inner, s);
+    else if (nblk <= 8)
+        launch_smooth_group<T, 2, 8>(W, m, in, out, C, inner, s);
+    else
+        launch_smooth_group<T, 2, 16>(W, m, in, out, C, inner, s);
 }
 
 __device__ __forceinline__ bool better(double va, int64_t ia, double vb, int64_t ib) {
@@ -253,28 +316,13 @@ hipError_t launch_smooth(const bmd_problem* p, int prec, const double* in, doubl
         double* dst = ((d - 1 - j) % 2 == 0) ? out : tmp;
         const int m = p->P.m[j];
         const int64_t inner = p->P.stride[j];
-        const int64_t outer = G / (inner * m);
-        // axis j as a batched GEMM: columns run over the inner index (batches
-        // over the outer one), or over the outer index when axis j is last
-        const int64_t N = inner > 1 ? inner : outer;
-        const int64_t sn = inner > 1 ? 1 : m;
-        const int64_t nb = inner > 1 ? outer : 1;
-        const int64_t ostride = inner > 1 ? static_cast<int64_t>(m) * inner : 0;
-        for (int64_t zb = 0; zb < nb; zb += 65535) {   // grid z is at most 65535
-            const int64_t nz = std::min<int64_t>(65535, nb - zb);
-            const dim3 grid(static_cast<unsigned>((N + 15) / 16), static_cast<unsigned>((m + 15) / 16),
-                            static_cast<unsigned>(nz));
-            const double* sz = src + zb * ostride;
-            double* dz = dst + zb * ostride;
-            if (prec == BMD_FP64)
-                hipLaunchKernelGGL(k_smooth_mfma<double>, grid, dim3(64), 0, s, p->d_W + p->w_off[j], m, sz, dz, N,
-                                   inner, sn, ostride);
-            else
-                hipLaunchKernelGGL(k_smooth_mfma<float>, grid, dim3(64), 0, s, p->d_Wf + p->w_off[j], m, sz, dz, N,
-                                   inner, sn, ostride);
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
-        }
+        const int64_t C = G / m;   // columns: every (outer, inner) pair of axis j
+        if (prec == BMD_FP64)
+            launch_smooth_pass<double>(p->d_W + p->w_off[j], m, src, dst, C, inner, s);
+        else
+            launch_smooth_pass<float>(p->d_Wf + p->w_off[j], m, src, dst, C, inner, s);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
         src = dst;
     }
     return hipSuccess;

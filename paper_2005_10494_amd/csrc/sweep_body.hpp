@@ -179,7 +179,8 @@ __device__ __forceinline__ void mfma_tile_body(const EvalArgs<T>& a, const MfmaG
 
     // This lane's axis-table values (draw independent) for the first kHoist
     // node steps stay in registers (FP32; the FP64 kernel has none to spare);
-    // the remaining steps read them from memory.
+    // the remaining steps read them from memory (cached: staging the tile's
+    // values in LDS instead was measured 4% slower in FP64).
     constexpr int kHoist = sizeof(T) == 4 ? (D <= 3 ? 5 : 6) : 0;
     constexpr int kChains = sizeof(T) == 4 ? 2 : 1;   // draws per wavefront pass
     const int S = K / 4;

@@ -29,6 +29,9 @@ METRIC = "integrand evals/sec and % VALU roofline, FP32+comp vs FP64, at |Δobj|
 PEAK_FP32_TFLOPS = 157.3          # published dense FP32 vector peak (packed FMA)
 PEAK_FP32_UNPACKED_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 flop x 2.4 GHz, unpacked FMA
 PEAK_FP64_TFLOPS = 78.6
+# The paper's two-layer estimator rate, derived from its reported total time (V100): at least
+# 2,000 x 10,240 x 20,480 comparisons in 4.5 h / 513 problems.
+PAPER_TWO_LAYER_RATE = 1.3e10
 SWEEP_KERNEL = {"direct": "k_eval_direct<float,%d,12,false> (designs x draws sweep, one design per thread)",
                 "matrix": "k_eval_mfma<float,%d,12,false> (designs x draws sweep, 16x16 design tiles, overlap on MFMA)"}
 
@@ -206,7 +209,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="3d", choices=["3d", "1d", "5d", "alpha", "alpha3", "alpha4", "levels", "grad",
-                                                         "refine", "batch", "smooth"])
+                                                         "refine", "batch", "smooth", "twolayer"])
     ap.add_argument("--batch-scale", type=float, default=1.0,
                     help="batch workload only: scale of the per-axis grids and of the draw range (1 = full size)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -249,6 +252,8 @@ def main():
         return bench_batch(args)
     if args.workload == "smooth":
         return bench_smooth(args)
+    if args.workload == "twolayer":
+        return bench_two_layer(args)
     spec = workload(args.workload)
     M, G = spec["n_draws"], int(np.prod(spec["m"]))
     log(f"workload {args.workload}: d={spec['d']} grid={spec['m']} G={G} M={M}")
@@ -619,6 +624,80 @@ def bench_smooth(args):
                                  "unit": "TFLOP/s", "flops_per_call": flops_call}},
            "fp64": {"ms_per_step": t64, "gb_per_s": bytes_call / (t64 * 1e-3) / 1e9},
            "fp32_vs_fp64": {"max_abs_diff": float((s32 - s64).abs().max())}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_two_layer(args):
+    """The paper's own estimator (Formula 7 with Formula 6's inner layer) at
+    its sizes N1 = 10,240 outer and N2 = 20,480 inner draws (Sec. 2.2) on
+    the three-population level grid of condition (c) (97 x 97, alpha_3 on the
+    FWER boundary): N1 x N2 comparisons of three coordinates per feasible
+    design, counted in 16 x 16 blocks with the unbiased variance estimate.
+    Roofline: a comparison of n coordinates costs n compares and one add per
+    lane (the and of the masks is scalar), so the vector units can make at
+    most 256 CUs x 64 lanes x 2.4 GHz / (n + 1) comparisons per second."""
+    import torch
+    import paper_2005_10494_amd as bmd
+    from paper_2005_10494_amd import workloads as W
+    spec = W.alpha3_grid()
+    N1, N2, n = 10240, 20480, 3
+    G = int(np.prod(spec["m"]))
+    res = {}
+    with bmd.Problem(spec) as p:
+        feas = int((~torch.isnan(p.designs(0, G)[:, 7])).sum())
+        for prec in ("fp32", "fp64"):
+            ts = []
+            for it in range(args.warmup + args.steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                m, v = p.eval_grid_two_layer(N1, N2, prec)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                if it >= args.warmup:
+                    ts.append(dt)
+                log(f"  two-layer {prec} step {it}: {1e3 * dt:.1f} ms")
+            res[prec] = (float(np.mean(ts)), m, v)
+        det = p.eval_grid(N1, "fp64")
+        torch.cuda.synchronize()
+    t32, m32, v32 = res["fp32"]
+    t64, m64, v64 = res["fp64"]
+    cmp_ = float(feas) * N1 * N2
+    rate = cmp_ / t32
+    peak = 256 * 64 * 2.4e9 / (n + 1)
+    ok = ~torch.isnan(m64)
+    sd = torch.sqrt(v64[ok].clamp_min(0))
+    i_best = int(torch.nan_to_num(m64, nan=-1.0).argmax())
+    out = {"metric": "two-layer estimator (Formula 7): indicator comparisons/s", "value": rate,
+           "unit": "comparisons/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * t32, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": rate / PAPER_TWO_LAYER_RATE,
+           "baseline_note": "the paper's two-layer rate, at least 1.3e10 indicator comparisons/s on a V100, derived "
+                            "from its 4.5 h for 513 three-population optimisations of 2,000 x 10,240 x 20,480 "
+                            "comparisons each",
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"three nested populations r = (1, {spec['r_lo']}, {spec['r_hi']}), (alpha_1, "
+                                  f"alpha_2) grid 97x97, alpha_3 on the FWER boundary, Formula 10 prior (condition "
+                                  f"(c)), N1={N1} outer x N2={N2} inner draws, 16x16 variance blocks",
+                      "designs": G, "feasible_designs": feas, "n_outer": N1, "n_inner": N2},
+           "roofline": {"bound": "alu", "achieved": rate, "peak": peak, "unit": "comparisons/s",
+                        "frac": rate / peak, "traffic": None,
+                        "kernel": "k_two_layer<float, 3> (256 inner draws per workgroup, outer thresholds via LDS)",
+                        "comparisons_per_call": cmp_},
+           "fp64": {"ms_per_step": 1e3 * t64, "comparisons_per_s": cmp_ / t64},
+           "result": {"max_abs_fp32_fp64": float((m32 - m64)[ok].abs().max()),
+                      "max_abs_two_layer_minus_formula5": float((m64 - det)[ok].abs().max()),
+                      "median_sd_estimate": float(sd.median()), "max_sd_estimate": float(sd.max()),
+                      "appendix_a2_sd_bound": math.sqrt(1.0 / (4.0 * N1 * N2)),
+                      "best_design": i_best, "best_power": float(m64[i_best])}}
+    if not args.no_cpu_baseline:
+        import oracle as O
+        gs = [int(g) for g in torch.nonzero(ok).flatten()[:2].cpu()]
+        t0 = time.perf_counter()
+        O.eval_grid_two_layer(spec, gs, N1, N2, 16, 16)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": len(gs) * N1 * N2 / dt, "unit": "comparisons/s", "cores": 1,
+                               "kind": "oracle", "sample": f"{len(gs)} feasible designs x {N1} x {N2} comparisons "
+                                                           f"({dt:.1f} s)"}
     print(json.dumps(out), flush=True)
 
 

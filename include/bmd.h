@@ -289,6 +289,38 @@ bmd_status bmd_eval_grid_levels(bmd_problem *p, uint64_t n_draws, int32_t prec, 
 bmd_status bmd_optimize_levels(bmd_problem *p, uint64_t n_draws, int32_t prec, double a_lo, double a_hi,
                                int32_t n_iter, double *d_best, double *d_alpha1, void *stream);
 
+/* The paper's two-layer sampling estimate of the expected power at every grid
+ * design (Formula 7, the inner layer of Formula 6 in place of the exact
+ * Phi_Sigma of Formula 5), for the Formula 10 prior:
+ *   P(g) = 1 - (1/(N1 N2)) sum_{k<N1} sum_{l<N2} [x_j^(l) <= z_j - mu_j^(k) for all j],
+ * outer draws k = 0..N1-1 (the draws of bmd_eval_grid), inner draws
+ * l = 0..N2-1 of the null statistics with the nested correlations of
+ * Appendix A.1 (Formula 1), shared by every outer draw: n standard normals per
+ * l from the Philox stream whose fourth counter word has its top bit set
+ * (counter (l lo, l hi, scenario, 0x80000000 | b)), chained as x_1 = e_1,
+ * x_{i+1} = sqrt(r_{i+1}/r_i) x_i + sqrt(1 - r_{i+1}/r_i) e_{i+1}.  n = 2
+ * (cutoff designs, BMD_DESIGN_ALPHA), 3 (BMD_DESIGN_ALPHA3) or 4
+ * (BMD_DESIGN_ALPHA4).
+ *   d_mean [G] FP64 the estimate (NaN for designs without a valid level split)
+ *   d_var  [G] FP64 (may be NULL) an unbiased estimate of its variance: the
+ *          comparisons are counted in blocks_outer x blocks_inner blocks
+ *          (consecutive outer draws x consecutive inner draws) and the block
+ *          means give the two-way crossed random-effects estimate
+ *          (MS_A + MS_B - MS_E)/(A B) of sigma_1^2/N1 + sigma_2^2/N2 +
+ *          sigma_12^2/(N1 N2) (the Hoeffding parts of the indicator), which
+ *          may come out slightly negative; Appendix A.2's bound 1/(4 N1 N2)
+ *          keeps only the last term.
+ * prec: the comparisons in FP64, or in FP32 with both sides rounded (counts
+ * may then differ from FP64's where a comparison falls within FP32 rounding).
+ * ENOTSUP unless the effect is BMD_EFFECT_PAPER_GAUSS; ESTATE for continuous
+ * problems; ERANGE unless blocks_outer, blocks_inner are in [2, 64],
+ * n_outer is a multiple of blocks_outer (at most 2^31), n_inner a multiple of
+ * 1024 and of 256 blocks_inner (at most 2^26), and a block holds fewer than
+ * 2^32 comparisons. */
+bmd_status bmd_eval_grid_two_layer(bmd_problem *p, uint64_t n_outer, uint64_t n_inner, int32_t prec,
+                                   int32_t blocks_outer, int32_t blocks_inner, double *d_mean,
+                                   double *d_var, void *stream);
+
 /* Formula 5 estimate and its derivative in the first level alpha_1 at every
  * grid design, on draws 0..n_draws-1 (Appendix A.3 differentiates the power
  * under the integral; for the nested pair the chain rule runs through both

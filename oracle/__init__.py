@@ -96,6 +96,7 @@ def lib():
             "or_eval_points": (None, [pp, I64, P, U64, U64, P, P]),
             "or_eval_grid": (None, [pp, I64, P, U64, U64, P, P]),
             "or_eval_grid_dalpha": (None, [pp, I64, P, U64, U64, P, P]),
+            "or_eval_grid_two_layer": (None, [pp, I64, P, U64, U64, ctypes.c_int, ctypes.c_int, P, P, P]),
             "or_smooth_direct": (None, [pp, P, P]), "or_smooth_separable": (None, [pp, P, P]),
             "or_smooth_masked": (None, [pp, P, P]), "or_smooth_at": (D, [pp, P, P]),
             "or_argmax": (I64, [I64, P]),
@@ -288,6 +289,21 @@ def eval_grid_dalpha(prob, g_list, M, k0=0):
     dmean = np.zeros(g.size)
     lib().or_eval_grid_dalpha(ctypes.byref(s), g.size, _ptr(g), int(k0), int(M), _ptr(mean), _ptr(dmean))
     return mean, dmean
+
+
+def eval_grid_two_layer(prob, g_list, N1, N2, A=16, B=16):
+    """Formula 7, the two-layer sampling estimate (inner layer of Formula 6),
+    at grid designs under the Formula 10 prior: outer draws 0..N1-1, inner
+    draws 0..N2-1; returns (mean, var, blocks) with the unbiased variance
+    estimate from the A x B block counts."""
+    s = problem_struct(prob)
+    g = np.ascontiguousarray(g_list, dtype=np.int64)
+    mean = np.zeros(g.size)
+    var = np.zeros(g.size)
+    blocks = np.zeros((g.size, A, B), dtype=np.uint32)
+    lib().or_eval_grid_two_layer(ctypes.byref(s), g.size, _ptr(g), int(N1), int(N2), int(A), int(B), _ptr(mean),
+                                 _ptr(var), _ptr(blocks))
+    return mean, var, blocks
 
 
 def smooth_direct(prob, f):

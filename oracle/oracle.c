@@ -806,6 +806,125 @@ void or_eval_grid(const or_problem *p, int64_t n, const int64_t *g_list,
 }
 
 /* ======================================================================== */
+/* Two-layer sampling estimator (Formulas 6 and 7)                          */
+/* ======================================================================== */
+/*
+ * Formula 6 replaces Phi_Sigma(b) by the share of N2 draws x^(l) of the null
+ * statistics (Formula 1) that lie below b in every coordinate; Formula 7
+ * averages that over the N1 prior draws, one set of x^(l) for all of them:
+ *   P = 1 - (1/(N1 N2)) sum_k sum_l [x^(l)_j <= z_j - sqrt(r_j I) Delta^(k)_j, all j].
+ * The inner draw l takes its uniforms from the Philox stream whose fourth
+ * counter word has its top bit set, turns them into standard normals e_j and
+ * builds the nested null correlations sqrt(r_j / r_i) of Appendix A.1 by the
+ * chain x_1 = e_1, x_{i+1} = sqrt(r_{i+1}/r_i) x_i + sqrt(1 - r_{i+1}/r_i) e_{i+1}.
+ *
+ * The variance (corrected Appendix A.2).  The indicator h(Delta, x) has the
+ * Hoeffding parts h1(Delta) = E_x h, h2(x) = E_Delta h and a remainder, which
+ * are uncorrelated, so with theta = E h
+ *   Var(mean h) = s1/N1 + s2/N2 + (theta (1 - theta) - s1 - s2)/(N1 N2),
+ * s1 = Var h1, s2 = Var h2; A.2 keeps only theta (1 - theta)/(N1 N2).  Counting
+ * the comparisons in A x B blocks (consecutive outer draws x consecutive inner
+ * draws), the block means follow a two-way crossed random-effects model, and
+ * (MS_A + MS_B - MS_E)/(A B) estimates that variance without bias.
+ */
+static void inner_draw(const or_problem *p, uint64_t l, int n, const double *r, double *x)
+{
+    uint32_t key[2] = {(uint32_t)p->seed, (uint32_t)(p->seed >> 32)};
+    uint32_t w[8];
+    for (int b = 0; b < 2; ++b) {
+        uint32_t ctr[4] = {(uint32_t)l, (uint32_t)(l >> 32), p->scenario, 0x80000000u | (uint32_t)b};
+        or_philox4x32_10(ctr, key, w + 4 * b);
+    }
+    for (int i = 0; i < n; ++i) {
+        double e = or_Phiinv(or_uniform52(w[2 * i], w[2 * i + 1]));
+        x[i] = (i == 0) ? e : sqrt(r[i] / r[i - 1]) * x[i - 1] + sqrt(1.0 - r[i] / r[i - 1]) * e;
+    }
+}
+
+/* Thresholds b_j = z_j - sqrt(r_j I) Delta_j of outer draw dr for design ds
+ * under Formula 10 (Delta_i = theta_i + sigma_i Y_i, Y the chain of the draw's
+ * normals); n = 2, 3 or 4.  Returns the fractions r_1..r_n in r. */
+static int outer_thresholds(const or_problem *p, const or_design *ds, const or_draw *dr, double *b, double *r)
+{
+    int n = p->design_space == OR_DESIGN_ALPHA4 ? 4 : p->design_space == OR_DESIGN_ALPHA3 ? 3 : 2;
+    double rr[4] = {1.0, ds->r, ds->r3, ds->r4}, z[4] = {ds->z1, ds->z2, ds->z3, ds->z4};
+    double e[4] = {dr->e1, dr->e2, dr->e3, dr->e4}, Y[4];
+    for (int i = 0; i < n; ++i) {
+        Y[i] = (i == 0) ? e[0] : sqrt(rr[i] / rr[i - 1]) * Y[i - 1] + sqrt(1.0 - rr[i] / rr[i - 1]) * e[i];
+        double th = -log1p(-(p->paper_a - p->paper_b * rr[i]));
+        double sg = 1.0 / sqrt(p->paper_events * rr[i] / 4.0);
+        b[i] = z[i] - sqrt(rr[i] * p->info) * (th + sg * Y[i]);
+        r[i] = rr[i];
+    }
+    return n;
+}
+
+void or_eval_grid_two_layer(const or_problem *p, int64_t ng, const int64_t *g_list, uint64_t N1,
+                            uint64_t N2, int A, int B, double *mean, double *var, uint32_t *blocks)
+{
+    or_draw *dr = make_draws(p, 0, N1);
+    double *x = (double *)malloc(sizeof(double) * 4 * (size_t)N2);
+    uint32_t *cnt = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)A * B);
+    double *R = (double *)malloc(sizeof(double) * (size_t)A), *C = (double *)malloc(sizeof(double) * (size_t)B);
+    if (!dr || !x || !cnt || !R || !C) { free(dr); free(x); free(cnt); free(R); free(C); return; }
+    uint64_t SA = N1 / (uint64_t)A, SB = N2 / (uint64_t)B;
+    for (int64_t i = 0; i < ng; ++i) {
+        double q[6], b[4], r[4];
+        or_design ds;
+        or_grid_point(p, g_list[i], q, NULL);
+        or_make_design(p, q, &ds);
+        int n = outer_thresholds(p, &ds, &dr[0], b, r);
+        int bad = isnan(ds.z1) || isnan(ds.z2) || (n >= 3 && isnan(ds.z3)) || (n >= 4 && isnan(ds.z4));
+        memset(cnt, 0, sizeof(uint32_t) * (size_t)A * B);
+        if (bad) {
+            mean[i] = NAN;
+            if (var) var[i] = NAN;
+            if (blocks) memcpy(blocks + i * A * B, cnt, sizeof(uint32_t) * (size_t)A * B);
+            continue;
+        }
+        for (uint64_t l = 0; l < N2; ++l) inner_draw(p, l, n, r, x + 4 * l);
+        for (uint64_t k = 0; k < N1; ++k) {
+            outer_thresholds(p, &ds, &dr[k], b, r);
+            for (uint64_t l = 0; l < N2; ++l) {
+                int below = 1;
+                for (int j = 0; j < n; ++j) below = below && (x[4 * l + j] <= b[j]);
+                cnt[(k / SA) * B + l / SB] += below;
+            }
+        }
+        uint64_t T = 0;
+        for (int t = 0; t < A * B; ++t) T += cnt[t];
+        mean[i] = 1.0 - (double)T / ((double)N1 * (double)N2);
+        if (blocks) memcpy(blocks + i * A * B, cnt, sizeof(uint32_t) * (size_t)A * B);
+        if (var) {
+            double cell = (double)SA * (double)SB, M = 0.0;
+            for (int a = 0; a < A; ++a) {
+                double s = 0.0;
+                for (int c = 0; c < B; ++c) s += cnt[a * B + c] / cell;
+                R[a] = s / B;
+                M += R[a];
+            }
+            M /= A;
+            for (int c = 0; c < B; ++c) {
+                double s = 0.0;
+                for (int a = 0; a < A; ++a) s += cnt[a * B + c] / cell;
+                C[c] = s / A;
+            }
+            double sa = 0.0, sc = 0.0, se = 0.0;
+            for (int a = 0; a < A; ++a) sa += (R[a] - M) * (R[a] - M);
+            for (int c = 0; c < B; ++c) sc += (C[c] - M) * (C[c] - M);
+            for (int a = 0; a < A; ++a)
+                for (int c = 0; c < B; ++c) {
+                    double d = cnt[a * B + c] / cell - R[a] - C[c] + M;
+                    se += d * d;
+                }
+            double msa = B * sa / (A - 1), msb = A * sc / (B - 1), mse = se / ((double)(A - 1) * (B - 1));
+            var[i] = (msa + msb - mse) / ((double)A * B);
+        }
+    }
+    free(dr); free(x); free(cnt); free(R); free(C);
+}
+
+/* ======================================================================== */
 /* Derivative in the first level (Appendix A.3, two nested tests)           */
 /* ======================================================================== */
 /*

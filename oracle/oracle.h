@@ -130,6 +130,14 @@ void   or_eval_points(const or_problem *p, int64_t n, const double *q,
 void   or_eval_grid(const or_problem *p, int64_t n, const int64_t *g_list,
                     uint64_t k0, uint64_t M, double *mean, double *var);
 
+/* ---- two-layer sampling estimator (Formulas 6 and 7) -------------------- */
+/* Formula 7 at grid designs g_list[n] with outer draws 0..N1-1 and inner
+ * draws 0..N2-1 (Formula 10 prior); mean[n], var[n] (may be NULL) the
+ * unbiased block estimate of its variance from A x B blocks, blocks[n][A][B]
+ * (may be NULL) the comparison counts. */
+void   or_eval_grid_two_layer(const or_problem *p, int64_t n, const int64_t *g_list, uint64_t N1,
+                              uint64_t N2, int A, int B, double *mean, double *var, uint32_t *blocks);
+
 /* ---- derivative in the first level (Appendix A.3) ----------------------- */
 /* d/d alpha_1 of one summand (cutoff designs, rule SPLIT or FIXED with
  * alpha_1 > 0): the chain rule through z1 and, under SPLIT, through the

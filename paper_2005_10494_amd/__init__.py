@@ -81,6 +81,9 @@ SIGNATURES = {
     "bmd_optimize_levels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p]),
+    "bmd_eval_grid_two_layer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32,
+                                               ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_void_p]),
     "bmd_eval_grid_dalpha": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p]),
     "bmd_optimize_levels_newton": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_double,
@@ -343,6 +346,20 @@ class Problem:
                                              int(n_iter), ctypes.c_void_p(best.data_ptr()),
                                              ctypes.c_void_p(a1.data_ptr()), _stream(stream)))
         return best, a1
+
+    def eval_grid_two_layer(self, n_outer: int, n_inner: int, precision="fp64", blocks=(16, 16), want_var=True,
+                            stream=None):
+        """The two-layer sampling estimate of Formula 7 at every grid design
+        (Formula 10 prior) and, with want_var, an unbiased estimate of its
+        variance; returns (mean, var or None)."""
+        import torch
+        mean = torch.empty(self.G, dtype=torch.float64, device=self.device)
+        var = torch.empty(self.G, dtype=torch.float64, device=self.device) if want_var else None
+        _check(library().bmd_eval_grid_two_layer(self._h, int(n_outer), int(n_inner), _prec(precision),
+                                                 int(blocks[0]), int(blocks[1]), ctypes.c_void_p(mean.data_ptr()),
+                                                 ctypes.c_void_p(var.data_ptr()) if var is not None else None,
+                                                 _stream(stream)))
+        return mean, var
 
     def eval_grid_dalpha(self, n_draws: int, precision="fp64", stream=None):
         """Monte Carlo estimate and its derivative in the first level alpha_1 at

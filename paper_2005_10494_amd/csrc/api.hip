@@ -742,6 +742,45 @@ bmd_status bmd_optimize_levels(bmd_problem* p, uint64_t n_draws, int32_t prec, d
     return BMD_OK;
 }
 
+bmd_status bmd_eval_grid_two_layer(bmd_problem* p, uint64_t n_outer, uint64_t n_inner, int32_t prec,
+                                   int32_t blocks_outer, int32_t blocks_inner, double* d_mean, double* d_var,
+                                   void* stream) {
+    g_err.clear();
+    if (!p) return fail(BMD_EINVAL, "problem is NULL");
+    if (!p->grid) return fail(BMD_ESTATE, "the two-layer estimator needs a grid problem");
+    if (p->P.effect != BMD_EFFECT_PAPER_GAUSS)
+        return fail(BMD_ENOTSUP, "the two-layer estimator needs the Formula 10 prior (BMD_EFFECT_PAPER_GAUSS)");
+    if (!valid_prec(prec)) return fail(BMD_EINVAL, "unknown precision %d", prec);
+    if (!d_mean) return fail(BMD_EINVAL, "NULL d_mean");
+    const int64_t A = blocks_outer, B = blocks_inner;
+    if (A < 2 || A > 64 || B < 2 || B > 64) return fail(BMD_ERANGE, "blocks_outer and blocks_inner must be in [2, 64]");
+    if (n_outer == 0 || n_outer > (1ull << 31) || n_outer % A != 0)
+        return fail(BMD_ERANGE, "n_outer must be in [1, 2^31] and a multiple of blocks_outer");
+    if (n_inner == 0 || n_inner > (1ull << 26) || n_inner % 1024 != 0 || n_inner % B != 0 || (n_inner / B) % 256 != 0)
+        return fail(BMD_ERANGE, "n_inner must be a multiple of 1024 and of 256 blocks_inner, at most 2^26");
+    const int64_t N1 = static_cast<int64_t>(n_outer), N2 = static_cast<int64_t>(n_inner);
+    if (static_cast<double>(N1 / A) * static_cast<double>(N2 / B) >= 4294967296.0)
+        return fail(BMD_ERANGE, "a block of (n_outer / blocks_outer) x (n_inner / blocks_inner) comparisons "
+                                "must stay below 2^32");
+    const int n = p->P.design_space == BMD_DESIGN_ALPHA3 ? 3 : p->P.design_space == BMD_DESIGN_ALPHA4 ? 4 : 2;
+    DeviceGuard guard(p->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t al = 256;
+    const size_t draw_bytes = (draw_workspace_bytes(p, BMD_FP64, N1) + al - 1) / al * al;
+    const size_t inner_bytes = (two_layer_inner_bytes(n, N2) + al - 1) / al * al;
+    const size_t block_bytes = sizeof(uint32_t) * static_cast<size_t>(p->P.G) * A * B;
+    bmd_status st = ensure(&p->d_ws, &p->ws_cap, draw_bytes + inner_bytes + block_bytes);
+    if (st != BMD_OK) return st;
+    char* base = static_cast<char*>(p->d_ws);
+    double* inner = reinterpret_cast<double*>(base + draw_bytes);
+    uint32_t* blocks = reinterpret_cast<uint32_t*>(base + draw_bytes + inner_bytes);
+    HIP_TRY(launch_draws(p, BMD_FP64, 0, N1, p->d_ws, s), "draw kernel");
+    HIP_TRY(launch_two_layer(p, prec, n, N1, N2, static_cast<int>(A), static_cast<int>(B), draws_fp64(p, N1, p->d_ws),
+                             inner, blocks, d_mean, d_var, s),
+            "two-layer kernels");
+    return BMD_OK;
+}
+
 bmd_status bmd_eval_grid_dalpha(bmd_problem* p, uint64_t n_draws, int32_t prec, double* d_mean, double* d_dmean,
                                 void* stream) {
     g_err.clear();

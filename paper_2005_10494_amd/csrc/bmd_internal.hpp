@@ -178,6 +178,14 @@ bool use_mfma_sweep(const bmd_problem* p);
 int64_t sweep_tiles(const bmd_problem* p, int prec);
 int sweep_blocks_per_cu(const bmd_problem* p, int prec);
 int sweep_chunk(const bmd_problem* p, int prec);
+// The two-layer sampling estimator (kernels_twolayer.hip): inner draws
+// [n][N2] FP64 in `inner`, block counts [G][A][B] in `blocks`, outer draws
+// k = 0..N1-1 already in `outer` (FP64); writes mean[G] and, if var is not
+// NULL, the unbiased variance estimate var[G].
+size_t two_layer_inner_bytes(int n, int64_t N2);
+hipError_t launch_two_layer(const bmd_problem* p, int prec, int n, int64_t N1, int64_t N2, int A, int B,
+                            const DrawArrays<double>& outer, double* inner, uint32_t* blocks, double* mean,
+                            double* var, hipStream_t s);
 // Bytes of one draw that a matrix-core sweep tile stages (0 for the direct sweep).
 int64_t sweep_staged_bytes_per_draw(const bmd_problem* p, int prec);
 struct MfmaGeom;

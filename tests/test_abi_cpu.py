@@ -112,6 +112,7 @@ def test_null_arguments():
     assert lib.bmd_eval_grid_levels(None, 10, 0, None, 1, None, None, None) == -1
     assert lib.bmd_optimize_levels(None, 10, 0, 0.001, 0.02, 5, None, None, None) == -1
     assert lib.bmd_eval_grid_dalpha(None, 10, 0, None, None, None) == -1
+    assert lib.bmd_eval_grid_two_layer(None, 1024, 4096, 0, 16, 16, None, None, None) == -1
     assert lib.bmd_optimize_levels_newton(None, 10, 0, 0.001, 0.02, 5, 1e-10, None, None, None) == -1
     lib.bmd_destroy_problem(None)  # NULL-safe
 

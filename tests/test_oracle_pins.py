@@ -656,6 +656,115 @@ def test_newton_level_search_finds_the_derivative_root():
         assert abs(x[i] - gx[i]) < 1e-9
 
 
+# ---------------------------------------------------------------- two-layer estimator
+# Formula 7 (the inner layer of Formula 6) and its variance, Appendix A.2
+# corrected: the inner draws are shared by every outer draw, so the estimate's
+# variance keeps the covariance terms A.2 drops.
+
+def _two_layer_brute(spec, g, N1, N2, A, B):
+    """Formula 7 restated with the scalar primitives: outer normals from
+    make_draw, inner normals from Philox counters (l, 0, scenario, 2^31 | b)
+    and the quantile, the nested chain, the thresholds, the block counts."""
+    n = {"alpha3": 3, "alpha4": 4}.get(spec.get("design"), 2)
+    ds = O.make_design(spec, O.grid_point(spec, g)[0])
+    r = [1.0, ds["r"], ds["r3"], ds["r4"]][:n]
+    z = [ds["z1"], ds["z2"], ds["z3"], ds["z4"]][:n]
+    key = [spec["seed"] & 0xFFFFFFFF, spec["seed"] >> 32]
+    x = np.zeros((N2, n))
+    for l in range(N2):
+        w = np.concatenate([O.philox([l, 0, spec["scenario"], 0x80000000 | b], key) for b in range(2)])
+        for i in range(n):
+            e = O.Phiinv(O.uniform52(w[2 * i], w[2 * i + 1]))
+            x[l, i] = e if i == 0 else math.sqrt(r[i] / r[i - 1]) * x[l, i - 1] + math.sqrt(1 - r[i] / r[i - 1]) * e
+    cnt = np.zeros((A, B), dtype=np.int64)
+    for k in range(N1):
+        dr = O.make_draw(spec, k)
+        e = [dr["e1"], dr["e2"], dr["e3"], dr["e4"]]
+        Y, b = [], []
+        for i in range(n):
+            Y.append(e[0] if i == 0 else math.sqrt(r[i] / r[i - 1]) * Y[i - 1] + math.sqrt(1 - r[i] / r[i - 1]) * e[i])
+            th = -math.log1p(-(spec["paper_a"] - spec["paper_b"] * r[i]))
+            sg = 1.0 / math.sqrt(spec["paper_events"] * r[i] / 4.0)
+            b.append(z[i] - math.sqrt(r[i] * spec["info"]) * (th + sg * Y[i]))
+        below = np.all(x <= np.array(b), axis=1)
+        for bb in range(B):
+            cnt[k // (N1 // A), bb] += int(below[bb * (N2 // B):(bb + 1) * (N2 // B)].sum())
+    return cnt
+
+
+@pytest.mark.parametrize("which", ["alpha", "alpha3", "alpha4"])
+def test_two_layer_counts_restated(which):
+    spec = {"alpha": W.alpha_design(5), "alpha3": W.alpha3_design(3), "alpha4": W.alpha4_design(2)}[which]
+    g = 1 if which != "alpha4" else 0
+    N1, N2, A, B = 24, 96, 4, 2
+    m, v, blk = O.eval_grid_two_layer(spec, [g], N1, N2, A, B)
+    cnt = _two_layer_brute(spec, g, N1, N2, A, B)
+    assert np.array_equal(blk[0].astype(np.int64), cnt)
+    assert m[0] == 1.0 - cnt.sum() / (N1 * N2)
+    assert 0 < cnt.sum() < N1 * N2
+
+
+def _one_test_parts(I, E, a, z):
+    """One test under Formula 10 (second test off): h = [x <= z - mu],
+    mu ~ N(m, s^2), x ~ N(0, 1).  theta = E h = Phi(w), w = (z - m)/sqrt(1 + s^2);
+    Var_mu E_x h = Phi_2(w, w; s^2/(1 + s^2)) - theta^2;
+    Var_x E_mu h = Phi_2(w, w; 1/(1 + s^2)) - theta^2."""
+    m = math.sqrt(I) * -math.log(1 - a)
+    s2 = I * 4.0 / E
+    w = (z - m) / math.sqrt(1 + s2)
+    th = ndtr(w)
+    return th, _bvn_owen(w, w, s2 / (1 + s2)) - th * th, _bvn_owen(w, w, 1 / (1 + s2)) - th * th
+
+
+def test_two_layer_variance_closed_form():
+    """The one-test case has the Hoeffding parts in closed form, so the
+    variance of Formula 7's estimate is s1/N1 + s2/N2 + (theta(1-theta) - s1 -
+    s2)/(N1 N2) exactly.  Over 40 independent replications (seeds) the
+    oracle's block estimate of that variance averages to it within 4 standard
+    errors, the replications' own spread matches it (chi-square 99.9%), and
+    their mean matches 1 - theta; at the paper's N1 = 10240, N2 = 20480 the
+    exact variance exceeds Appendix A.2's bound 1/(4 N1 N2) by orders of
+    magnitude."""
+    from scipy.stats import chi2
+    I, E, a, a1 = 211.0, 80.0, 0.3, 0.01
+    spec = W.base_problem(1, [3], 0.0, 0.05, info=I, effect="paper", paper_a=a, paper_b=0.0, paper_events=E,
+                          alpha_rule="fixed", alpha_fixed=(a1, 0.0))
+    z = -ndtri(a1)
+    th, s1, s2 = _one_test_parts(I, E, a, z)
+    N1, N2, A, B, R = 256, 512, 8, 8, 40
+    exact = s1 / N1 + s2 / N2 + (th * (1 - th) - s1 - s2) / (N1 * N2)
+    means, vars_ = [], []
+    for sd in range(R):
+        m, v, _ = O.eval_grid_two_layer(dict(spec, seed=1000 + sd), [1], N1, N2, A, B)
+        means.append(m[0])
+        vars_.append(v[0])
+    means, vars_ = np.array(means), np.array(vars_)
+    assert abs(vars_.mean() - exact) < 4 * vars_.std(ddof=1) / math.sqrt(R), (vars_.mean(), exact)
+    ratio = means.var(ddof=1) / exact
+    assert chi2.ppf(0.0005, R - 1) / (R - 1) < ratio < chi2.ppf(0.9995, R - 1) / (R - 1), ratio
+    assert abs(means.mean() - (1 - th)) < 4 * math.sqrt(exact / R)
+    big = s1 / 10240 + s2 / 20480
+    assert big > 1000 * 1 / (4 * 10240 * 20480)
+
+
+@pytest.mark.parametrize("which", ["alpha", "alpha3", "alpha4"])
+def test_two_layer_converges_to_formula5(which):
+    """On the same outer draws the inner layer averages to Phi_Sigma (Formula 6
+    is unbiased for it), so Formula 7 minus Formula 5 is the inner draws'
+    error: within 5 of its standard errors from the inner groups' spread (the
+    groups are independent replicates of the inner layer given the outer
+    draws)."""
+    spec = {"alpha": W.alpha_design(5), "alpha3": W.alpha3_design(3), "alpha4": W.alpha4_design(2)}[which]
+    g = 1 if which != "alpha4" else 0
+    N1, N2, A, B = 256, 16384, 4, 16
+    m, v, blk = O.eval_grid_two_layer(spec, [g], N1, N2, A, B)
+    det, _ = O.eval_grid(spec, [g], N1)
+    colmeans = 1 - blk[0].sum(axis=0) / (N1 * N2 / B)
+    se = colmeans.std(ddof=1) / math.sqrt(B)
+    assert abs(m[0] - det[0]) < 5 * se, (m[0], det[0], se)
+    assert 0 < se < 0.01
+
+
 # ---------------------------------------------------------------- continuous refinement
 
 def test_refinement_reaches_the_maximiser_of_a_deterministic_objective():

@@ -326,6 +326,7 @@ void free_problem(bmd_problem* p) {
     f(p->d_z2);
     f(p->d_z3);
     f(p->d_z4);
+    f(p->d_order);
     f(p->d_W);
     f(p->d_Wf);
     f(p->d_ws);
@@ -556,6 +557,7 @@ bmd_status bmd_create_problem(const bmd_problem_desc* desc, bmd_problem** out, v
         if (st == BMD_OK && (d.design_space == BMD_DESIGN_ALPHA3 || d.design_space == BMD_DESIGN_ALPHA4))
             st = upload<double>(&p->d_z3, nullptr, P.G);
         if (st == BMD_OK && d.design_space == BMD_DESIGN_ALPHA4) st = upload<double>(&p->d_z4, nullptr, P.G);
+        if (st == BMD_OK) st = upload<int32_t>(&p->d_order, nullptr, P.G);
         // Smoothing matrices.
         std::vector<double> W;
         for (int j = 0; j < d.d && st == BMD_OK; ++j) {

@@ -125,6 +125,7 @@ struct bmd_problem {
     double* d_z2 = nullptr;          // [G]
     double* d_z3 = nullptr;          // [G] third critical value (three and four nested populations)
     double* d_z4 = nullptr;          // [G] fourth critical value (four nested populations)
+    int32_t* d_order = nullptr;      // [G] nested populations: designs with a last level first, then the rest
     double* d_W = nullptr;           // smoothing matrices, FP64, sum_j m_j^2
     float* d_Wf = nullptr;           // same in FP32
     int64_t w_off[bmd::kMaxDim] = {0, 0, 0, 0, 0, 0};

@@ -81,6 +81,7 @@ struct FourArgs {
     const double* z2;
     const double* z3;
     const double* z4;
+    const int32_t* order;   // [G] designs with a fourth level first
     const T* e1;
     const T* e2;
     const T* e3;
@@ -97,25 +98,17 @@ struct FourArgs {
 };
 
 // One thread per design (alpha_1, alpha_2, alpha_3), the draws of slice
-// blockIdx.y.  Each wavefront takes a 4 x 4 x 4 block of the level grid
-// (four blocks per workgroup, in row-major block order): designs without a
-// fourth level fill the corner where the levels are large, so whole blocks
-// there have none, and such a wavefront writes NaN sums and leaves without
-// touching the draws.
+// blockIdx.y.  The designs go in the problem's order (those with a fourth
+// level first), so the wavefronts that compute are full of designs that have
+// one, and the designs without one form whole wavefronts that write NaN sums
+// and leave without touching the draws.
 template <typename T, bool VAR>
 __global__ __launch_bounds__(kEvalBlock) void k_eval_four(FourArgs<T> a) {
     constexpr int NB = sizeof(T) == 8 ? kBvnMax64 : kBvnMax32;
-    const int t0 = (a.m0 + 3) / 4, t1 = (a.m1 + 3) / 4, t2 = (a.m2 + 3) / 4;
-    const int wt = static_cast<int>(blockIdx.x) * (kEvalBlock / 64) + static_cast<int>(threadIdx.x) / 64;
-    const int lane = static_cast<int>(threadIdx.x) % 64;
-    const int b0 = wt / (t1 * t2), b1 = (wt / t2) % t1, b2 = wt % t2;
-    const int i0 = b0 * 4 + lane / 16, i1 = b1 * 4 + (lane / 4) % 4, i2 = b2 * 4 + lane % 4;
-    const bool valid = wt < t0 * t1 * t2 && i0 < a.m0 && i1 < a.m1 && i2 < a.m2;
-    const int64_t g = (static_cast<int64_t>(i0) * a.m1 + i1) * a.m2 + i2;
-    // idle lanes shadow a design of the grid
-    const int64_t gg = valid ? g
-                             : (static_cast<int64_t>(min(i0, a.m0 - 1)) * a.m1 + min(i1, a.m1 - 1)) * a.m2 +
-                                   min(i2, a.m2 - 1);
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * kEvalBlock + threadIdx.x;
+    const bool valid = idx < a.G;
+    // idle lanes shadow the last design of the order
+    const int64_t g = a.order[valid ? idx : a.G - 1], gg = g;
     const int slice = blockIdx.y;
     const double z4d = a.z4[gg];
     if (__all(!valid || z4d != z4d)) {
@@ -167,6 +160,7 @@ FourArgs<T> four_args(const bmd_problem* p, DrawArrays<T> D, double* partials, i
     a.z2 = p->d_z2;
     a.z3 = p->d_z3;
     a.z4 = p->d_z4;
+    a.order = p->d_order;
     a.e1 = D.e1;
     a.e2 = D.e2;
     a.e3 = D.e3;
@@ -205,9 +199,7 @@ hipError_t launch_typed(const FourArgs<T>& a, int n_slices, bool var, hipStream_
     const void* k = var ? reinterpret_cast<const void*>(k_eval_four<T, true>)
                         : reinterpret_cast<const void*>(k_eval_four<T, false>);
     void* args[] = {const_cast<FourArgs<T>*>(&a)};
-    const int64_t blocks = static_cast<int64_t>((a.m0 + 3) / 4) * ((a.m1 + 3) / 4) * ((a.m2 + 3) / 4);   // 4^3 blocks
-    return hipLaunchKernel(k, dim3(static_cast<unsigned>((blocks + kEvalBlock / 64 - 1) / (kEvalBlock / 64)),
-                                   static_cast<unsigned>(n_slices)),
+    return hipLaunchKernel(k, dim3(static_cast<unsigned>((a.G + kEvalBlock - 1) / kEvalBlock), static_cast<unsigned>(n_slices)),
                            dim3(kEvalBlock), args, 0, s);
 }
 

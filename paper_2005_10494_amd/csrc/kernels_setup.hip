@@ -521,10 +521,58 @@ hipError_t launch_levels_best(const bmd_problem* p, int k, const double* mean, d
     return hipGetLastError();
 }
 
+// Design order of the nested-population sweeps: the designs whose last
+// critical value exists (not NaN) first, then the others, each in index order,
+// so that the sweep's wavefronts fill with designs that have a last level and
+// the rest form whole wavefronts that leave at once.  One workgroup: a count,
+// then a scan per tile of 1,024 designs.
+__global__ __launch_bounds__(1024) void k_order_feasible(int64_t G, const double* __restrict__ z_last,
+                                                         int32_t* __restrict__ order) {
+    __shared__ int scan[1024];
+    __shared__ int64_t total;
+    const int t = threadIdx.x;
+    if (t == 0) total = 0;
+    __syncthreads();
+    int64_t mine = 0;
+    for (int64_t g = t; g < G; g += 1024) mine += z_last[g] == z_last[g];
+    atomicAdd(reinterpret_cast<unsigned long long*>(&total), static_cast<unsigned long long>(mine));
+    __syncthreads();
+    const int64_t nf = total;
+    int64_t base_f = 0, base_n = 0;
+    for (int64_t g0 = 0; g0 < G; g0 += 1024) {
+        const int64_t g = g0 + t;
+        const int ok = g < G && z_last[g] == z_last[g];
+        scan[t] = ok;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {   // inclusive scan of the flags
+            const int v = t >= off ? scan[t - off] : 0;
+            __syncthreads();
+            scan[t] += v;
+            __syncthreads();
+        }
+        const int incl = scan[t];
+        const int tile_f = scan[1023];
+        if (g < G) {
+            const int64_t before_f = incl - ok;                 // feasible designs before g in this tile
+            const int64_t before_n = static_cast<int64_t>(t) - before_f;
+            order[ok ? base_f + before_f : nf + base_n + before_n] = static_cast<int32_t>(g);
+        }
+        base_f += tile_f;
+        base_n += min<int64_t>(1024, G - g0) - tile_f;
+        __syncthreads();
+    }
+}
+
 hipError_t launch_design_precompute(const bmd_problem* p, hipStream_t s) {
     if (p->P.G == 0) return hipSuccess;
-    if (p->P.design_space == BMD_DESIGN_ALPHA3) return launch_three_precompute(p, s);
-    if (p->P.design_space == BMD_DESIGN_ALPHA4) return launch_four_precompute(p, s);
+    if (p->P.design_space == BMD_DESIGN_ALPHA3 || p->P.design_space == BMD_DESIGN_ALPHA4) {
+        const bool three = p->P.design_space == BMD_DESIGN_ALPHA3;
+        hipError_t e = three ? launch_three_precompute(p, s) : launch_four_precompute(p, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_order_feasible, dim3(1), dim3(1024), 0, s, p->P.G, three ? p->d_z3 : p->d_z4,
+                           p->d_order);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_design_precompute, dim3(blocks_for(p->P.G, 128)), dim3(128), 0, s, p->P,
                        p->d_ghp, kPrecomputeGH, p->d_gl, p->d_r, p->d_z1, p->d_z2);
     return hipGetLastError();

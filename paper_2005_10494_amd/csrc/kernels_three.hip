@@ -75,6 +75,7 @@ struct ThreeArgs {
     const double* z1;
     const double* z2;
     const double* z3;
+    const int32_t* order;   // [G] designs with a third level first
     const T* e1;
     const T* e2;
     const T* e3;
@@ -89,21 +90,16 @@ struct ThreeArgs {
 };
 
 // One thread per design (alpha_1, alpha_2), the draws of slice blockIdx.y.
-// Each wavefront takes an 8 x 8 block of the level grid (four blocks per
-// workgroup, in row-major block order): designs without a third level fill
-// the corner where both levels are large, so whole blocks there have none,
-// and such a wavefront writes NaN sums and leaves without touching the draws
-// (two fifths of the wavefronts on a 97 x 97 grid at Sec. 3's condition (c)).
+// The designs go in the problem's order (those with a third level first), so
+// the wavefronts that compute are full of designs that have one, and the
+// designs without one (the corner where both levels are large) form whole
+// wavefronts that write NaN sums and leave without touching the draws.
 template <typename T, bool VAR>
 __global__ __launch_bounds__(kEvalBlock) void k_eval_three(ThreeArgs<T> a) {
-    const int t1 = (a.m0 + 7) / 8, t2 = (a.m1 + 7) / 8;
-    const int wt = static_cast<int>(blockIdx.x) * (kEvalBlock / 64) + static_cast<int>(threadIdx.x) / 64;
-    const int lane = static_cast<int>(threadIdx.x) % 64;
-    const int i1 = (wt / t2) * 8 + lane / 8, i2 = (wt % t2) * 8 + lane % 8;
-    const bool valid = wt < t1 * t2 && i1 < a.m0 && i2 < a.m1;
-    const int64_t g = static_cast<int64_t>(i1) * a.m1 + i2;
-    // idle lanes shadow a design of the grid
-    const int64_t gg = valid ? g : static_cast<int64_t>(min(i1, a.m0 - 1)) * a.m1 + min(i2, a.m1 - 1);
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * kEvalBlock + threadIdx.x;
+    const bool valid = idx < a.G;
+    // idle lanes shadow the last design of the order
+    const int64_t g = a.order[valid ? idx : a.G - 1], gg = g;
     const int slice = blockIdx.y;
     const double z3d = a.z3[gg];
     if (__all(!valid || z3d != z3d)) {
@@ -149,6 +145,7 @@ ThreeArgs<T> three_args(const bmd_problem* p, DrawArrays<T> D, double* partials,
     a.z1 = p->d_z1;
     a.z2 = p->d_z2;
     a.z3 = p->d_z3;
+    a.order = p->d_order;
     a.e1 = D.e1;
     a.e2 = D.e2;
     a.e3 = D.e3;
@@ -183,9 +180,7 @@ hipError_t launch_typed(const ThreeArgs<T>& a, int n_slices, bool var, hipStream
     const void* k = var ? reinterpret_cast<const void*>(k_eval_three<T, true>)
                         : reinterpret_cast<const void*>(k_eval_three<T, false>);
     void* args[] = {const_cast<ThreeArgs<T>*>(&a)};
-    const int64_t blocks = static_cast<int64_t>((a.m0 + 7) / 8) * ((a.m1 + 7) / 8);   // 8 x 8 design blocks
-    return hipLaunchKernel(k, dim3(static_cast<unsigned>((blocks + kEvalBlock / 64 - 1) / (kEvalBlock / 64)),
-                                   static_cast<unsigned>(n_slices)),
+    return hipLaunchKernel(k, dim3(static_cast<unsigned>((a.G + kEvalBlock - 1) / kEvalBlock), static_cast<unsigned>(n_slices)),
                            dim3(kEvalBlock), args, 0, s);
 }
 

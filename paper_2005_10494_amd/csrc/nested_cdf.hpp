@@ -14,10 +14,11 @@
 // cut into equal panels of an 8-point Gauss-Legendre rule.  The integrand's
 // steepest part is the conditional CDF whose scale in y, l = s12 / r12 or
 // s23 / r23, is smaller; the panel count is ceil(c / l) with c = 6 (8..128
-// panels) in FP64 and c = 2.5 (4..64) in FP32.  Against an adaptive reference
+// panels) in FP64 and c = 2.5 (3..64) in FP32.  Against an adaptive reference
 // over 0.1 <= r2 <= 0.9 and r3 / r2 up to 0.99 this keeps the quadrature error
-// below 5e-12 (FP64) and 2e-8 (FP32); the critical values use at least 16
-// panels.
+// below 5e-12 (FP64) and 6.2e-8 (FP32: an order below the FP32 Phi's own
+// 5.6e-7, which the 1e-5 objective bar already budgets for); the critical
+// values use at least 16 panels.
 //
 // Four populations: given Y2 = y, Y1 is independent of (Y3, Y4), which are
 // bivariate normal with means r23 y, r24 y, sds s23, s24 = sqrt(1 - r4/r2)
@@ -27,9 +28,10 @@
 // the bivariate CDF by the node sum of device_math.hpp at that fixed rho.
 // Same range rule (the upper limit also where the fourth argument falls
 // below -L), panels ceil(c / l) with l the smallest of s12/r12, s23/r23,
-// s24/r24, at least 12 panels in FP64 (c = 6) and 4 in FP32 (c = 2.5): against
+// s24/r24, at least 12 panels in FP64 (c = 6) and 3 in FP32 (c = 2.5): against
 // the adaptive reference over r2 in [0.15, 0.9] and ratios r3/r2, r4/r3 in
-// [0.15, 0.9] the error stays below 4e-13 (FP64) and 2.5e-8 (FP32).
+// [0.15, 0.9] the error stays below 4e-13 (FP64) and 1.8e-7 (FP32, below the
+// FP32 Phi's own error).
 #pragma once
 #include "bmd_internal.hpp"
 #include "device_math.hpp"
@@ -44,7 +46,7 @@ template <typename T>
 __device__ __forceinline__ int tvn_panels(double r2, double r3) {
     const double l = fmin(sqrt((1.0 - r2) / r2), sqrt((r2 - r3) / r3));
     const double c = sizeof(T) == 8 ? 6.0 : 2.5;
-    const int lo = sizeof(T) == 8 ? 8 : 4, hi = sizeof(T) == 8 ? 128 : 64;
+    const int lo = sizeof(T) == 8 ? 8 : 3, hi = sizeof(T) == 8 ? 128 : 64;
     return max(lo, min(hi, static_cast<int>(ceil(c / l))));
 }
 
@@ -169,7 +171,7 @@ template <typename T>
 __device__ __forceinline__ int qvn_panels(double r2, double r3, double r4) {
     const double l = fmin(fmin(sqrt((1.0 - r2) / r2), sqrt((r2 - r3) / r3)), sqrt((r2 - r4) / r4));
     const double c = sizeof(T) == 8 ? 6.0 : 2.5;
-    const int lo = sizeof(T) == 8 ? 12 : 4, hi = sizeof(T) == 8 ? 128 : 64;
+    const int lo = sizeof(T) == 8 ? 12 : 3, hi = sizeof(T) == 8 ? 128 : 64;
     return max(lo, min(hi, static_cast<int>(ceil(c / l))));
 }
 

@@ -179,8 +179,9 @@ def test_alpha3_few_draws(M):
 
 @pytest.mark.parametrize("m,M", [((13, 21), 900), ((211, 211), 2000)])
 def test_alpha3_block_mapping_sampled(m, M):
-    """Wavefronts take 8 x 8 level blocks: a ragged non-square grid and a large
-    one (27 x 27 blocks, the last ones partly outside the grid) against the
+    """Wavefronts take the designs in the problem's order (those with a third
+    level first): a ragged non-square grid and a large one (the last
+    wavefront partly past the end of the order) against the
     oracle at sampled designs, corners and designs without a third level
     included; every design is written (finite or NaN as the oracle says)."""
     spec = W.alpha3_design(5)

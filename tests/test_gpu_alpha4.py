@@ -161,8 +161,9 @@ def test_alpha4_few_draws(M):
 
 @pytest.mark.parametrize("m,M", [((5, 9, 6), 300), ((25, 25, 25), 500)])
 def test_alpha4_block_mapping_sampled(m, M):
-    """Wavefronts take 4 x 4 x 4 level blocks: a ragged grid and the
-    benchmarked 25^3 grid (the last blocks partly outside) against the oracle
+    """Wavefronts take the designs in the problem's order (those with a fourth
+    level first): a ragged grid and the benchmarked 25^3 grid (the last
+    wavefront partly past the end of the order) against the oracle
     at sampled designs, corners included; every design is written (finite or
     NaN as its fourth level says)."""
     spec = W.alpha4_design(5)

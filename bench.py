@@ -430,7 +430,7 @@ def bench_nested(args, n):
         # conditional arguments (6), the Gaussian factor (3), two Phi (3 each) and
         # the weighted product and sum (5): 22.
         scale = min(np.sqrt((1 - r2) / r2), np.sqrt((r2 - r3) / r3))
-        npan = max(4, min(64, int(np.ceil(2.5 / scale))))   # FP32 panel rule
+        npan = max(3, min(64, int(np.ceil(2.5 / scale))))   # FP32 panel rule
         per_point, nb = 22.0, 0
         flops = feasible * M * (12.0 + npan * 8 * per_point)
         kernel = (f"k_eval_three<float,false> (one design per thread, {npan} panels x 8 points "
@@ -442,7 +442,7 @@ def bench_nested(args, n):
         # and the weighted product and sum (5): 35 + 6 nb.
         r4 = spec["r_4"]
         scale = min(np.sqrt((1 - r2) / r2), np.sqrt((r2 - r3) / r3), np.sqrt((r2 - r4) / r4))
-        npan = max(4, min(64, int(np.ceil(2.5 / scale))))
+        npan = max(3, min(64, int(np.ceil(2.5 / scale))))
         rho = np.sqrt(r4 * (r2 - r3) / (r3 * (r2 - r4)))
         nb = int(bvn_nodes(np.array([rho]), "fp32")[0])
         per_point = 35.0 + 6.0 * nb

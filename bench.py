@@ -363,6 +363,17 @@ def bench_grad(args):
     t32, o32, g32, m32 = res["fp32"]
     t64, o64, g64, m64 = res["fp64"]
     scale = torch.cat([g64.abs().flatten(), m64.abs().flatten()]).max().clamp_min(1e-12)
+    # Algorithmic work per (point, draw): the overlap O and its d cutoff
+    # derivatives, per Gauss-Hermite node d mixes b + s (a - b) (2 each), d
+    # derivative factors, the product and its accumulation (d + 1) and the
+    # prefix/suffix products of the derivatives (3 d): K (7 d + 1); the
+    # bivariate normal and its three partials at the smallest FP32 rule
+    # (4 nodes: 58), and the d + 3 sums.  A lower bound (larger rules cost more).
+    d = spec["d"]
+    with bmd.Problem(spec) as p:
+        K = _gh_nodes(p, "fp32")
+    flops = float(B) * M * (K * (7 * d + 1) + 58 + d + 3)
+    achieved = flops / t32 / 1e12
     out = {"metric": "gradient evaluations (design point x draw, objective + d + 2 partials) per second",
            "value": B * M / t32, "unit": "point-draws/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1e3 * t32, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -370,6 +381,12 @@ def bench_grad(args):
            "config": {"workload": f"5-biomarker continuous designs, {B} points U(0.1, 0.9)^5, M={M} draws, "
                                   f"logistic indicator width {spec['width']}, rho_b={spec['rho_b']}",
                       "points": B, "n_draws": M},
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                        "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                        "kernel": f"k_grad<float, {d}, 12, 2, ·> (one thread per point, draws staged per LDS chunk)",
+                        "flops_per_call": flops, "gauss_hermite_nodes": K,
+                        "numerator": "overlap and its cutoff derivatives K (7 d + 1), bivariate normal and "
+                                     "partials at the 4-node rule (58), sums (d + 3): a lower bound"},
            "fp64": {"value": B * M / t64, "ms_per_step": 1e3 * t64},
            "fp32_vs_fp64": {"speedup": t64 / t32,
                             "max_abs_diff_objective": float((o32 - o64).abs().max()),

@@ -656,6 +656,77 @@ def test_newton_level_search_finds_the_derivative_root():
         assert abs(x[i] - gx[i]) < 1e-9
 
 
+# ---------------------------------------------------------------- two cutoffs on one biomarker
+# Three nested populations cut from one biomarker (n = 3 in the cutoff design
+# space): all, x > Phi^-1(q_1), x > Phi^-1(q_2).
+
+@pytest.mark.parametrize("r2,r3", [(0.8, 0.5), (0.6, 0.15), (0.9, 0.85), (0.3, 0.1)])
+def test_nested3_zstar_on_fwer_boundary(r2, r3):
+    z = O.zstar3(r2, r3)
+    fwer = 1.0 - _tvn_scipy([z, z, z], math.sqrt(r2), math.sqrt(r3), math.sqrt(r3 / r2))
+    assert abs(fwer - 0.025) < 2e-8, (r2, r3, z, fwer)
+    assert -ndtri(0.025) < z < -ndtri(0.025 / 3)
+
+
+def test_nested3_designs_and_null_prior():
+    """Designs exist only for q_1 < q_2 within the partial-correlation bound;
+    under a null prior (no effect) every existing design rejects with
+    probability alpha0 exactly (FWER-equal rule) or 1 - Phi_3 at the
+    Bonferroni value (scipy)."""
+    spec = W.nested3_design(6, mu_b0=0.0, sd_b0=0.0, mu_b1=0.0, sd_b1=0.0)
+    G = O.grid_size(spec)
+    m, _ = O.eval_grid(spec, np.arange(G), 20)
+    n_ok = 0
+    for g in range(G):
+        q, _ = O.grid_point(spec, g)
+        r2, r3 = 1 - q[0], 1 - q[1]
+        exists = q[0] < q[1] and r3 * (1 - r2) <= 0.975 ** 2 * r2 * (1 - r3)
+        assert np.isnan(m[g]) == (not exists), (g, q)
+        if exists:
+            n_ok += 1
+            assert abs(m[g] - 0.025) < 1e-9, (g, m[g])
+    assert n_ok >= 10
+    bon = dict(spec, alpha_rule="bonferroni")
+    mb, _ = O.eval_grid(bon, np.arange(G), 5)
+    g = 3   # q = (0.1, 0.74)
+    q, _ = O.grid_point(bon, g)
+    zb = -ndtri(0.025 / 3)
+    ref = 1.0 - _tvn_scipy([zb] * 3, math.sqrt(1 - q[0]), math.sqrt(1 - q[1]), math.sqrt((1 - q[1]) / (1 - q[0])))
+    assert abs(mb[g] - ref) < 2e-8, (mb[g], ref)
+
+
+def test_nested3_one_draw_against_a_simulated_trial():
+    """One draw (no prior spread, the true cutoff fixed) computed from the
+    definitions by simulation: the responders inside each population from 4e6
+    simulated biomarker values, the drifts sqrt(r_i I) Delta_i, and the
+    rejection probability P(some Z_i > z*) from 4e6 draws of the three
+    statistics with the nested correlations; the oracle's summand is within 5
+    standard errors."""
+    tau = 0.35
+    spec = W.nested3_design(5, mu_b0=0.05, sd_b0=0.0, mu_b1=0.45, sd_b1=0.0, tau_lo=tau, tau_hi=tau)
+    g = 1 * 5 + 3   # q = (0.3, 0.7)
+    q, _ = O.grid_point(spec, g)
+    m, _ = O.eval_grid(spec, [g], 3)
+    ds = O.make_design(spec, q)
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(4_000_000)
+    resp = x > ndtri(tau)
+    I = spec["info"]
+    mu, r = [], []
+    for c in (None, ndtri(q[0]), ndtri(q[1])):
+        inside = np.ones_like(x, dtype=bool) if c is None else x > c
+        ri = inside.mean()
+        delta = 0.05 + 0.45 * (resp & inside).mean() / ri
+        mu.append(math.sqrt(ri * I) * delta)
+        r.append(ri)
+    R = np.array([[1, math.sqrt(r[1]), math.sqrt(r[2])], [math.sqrt(r[1]), 1, math.sqrt(r[2] / r[1])],
+                  [math.sqrt(r[2]), math.sqrt(r[2] / r[1]), 1]])
+    Z = rng.multivariate_normal(mu, R, size=4_000_000)
+    hit = (Z > ds["z1"]).any(axis=1)
+    p, se = hit.mean(), hit.std() / math.sqrt(hit.size)
+    assert abs(m[0] - p) < 5 * se + 2e-4, (m[0], p, se)
+
+
 # ---------------------------------------------------------------- two-layer estimator
 # Formula 7 (the inner layer of Formula 6) and its variance, Appendix A.2
 # corrected: the inner draws are shared by every outer draw, so the estimate's
@@ -980,8 +1051,13 @@ def test_masked_smoother_pins():
 # ---------------------------------------------------------------- four nested populations
 
 def _qvn_scipy(h, R):
-    return stats.multivariate_normal.cdf(np.asarray(h, dtype=float), mean=np.zeros(4), cov=np.asarray(R),
-                                         abseps=1e-9, releps=1e-9, maxpts=4_000_000)
+    """scipy's four-variate normal CDF: a randomised quasi-Monte Carlo estimate
+    (Genz), seeded so that the pins are deterministic; over seeds its error at
+    4e6 points spreads with a standard deviation near 1e-7, so the pins that
+    use it compare at 5e-7."""
+    f = stats.multivariate_normal(mean=np.zeros(4), cov=np.asarray(R), seed=20200521)
+    f.maxpts, f.abseps, f.releps = 4_000_000, 1e-9, 1e-9
+    return f.cdf(np.asarray(h, dtype=float))
 
 
 def _nested_R(r):
@@ -998,7 +1074,7 @@ def test_four_variate_cdf_against_scipy_and_closed_forms():
     C = A @ A.T
     R = C / np.sqrt(np.outer(np.diag(C), np.diag(C)))
     h = rng.normal(0.5, 1.0, 4)
-    assert abs(O.qvn(h, R) - _qvn_scipy(h, R)) < 2e-7, (h, R)
+    assert abs(O.qvn(h, R) - _qvn_scipy(h, R)) < 5e-7, (h, R)
     # equicorrelated orthant at rho = 1/2: 1/(n + 1)
     R = np.full((4, 4), 0.5)
     np.fill_diagonal(R, 1.0)
@@ -1030,7 +1106,7 @@ def test_four_variate_cdf_against_scipy_and_closed_forms():
         Rn = _nested_R(r)
         g = O.qvn(h, Rn)
         assert abs(O.qvn_nested(h, np.array(r)) - g) < 1e-13, (r, h)
-        assert abs(g - _qvn_scipy(h, Rn)) < 2e-7
+        assert abs(g - _qvn_scipy(h, Rn)) < 5e-7
     r = np.array([1.0, 0.6, 0.35, 0.2])
     for j in (1, 2):
         h = np.array([0.4, 0.9, 0.1, -0.2])
@@ -1054,7 +1130,7 @@ def test_alpha4_fourth_level_on_fwer_boundary():
         z = (ds["z1"], ds["z2"], ds["z3"], ds["z4"])
         for i in range(3):
             assert abs(z[i] + ndtri(a[i])) < 1e-12
-        assert abs((1.0 - _qvn_scipy(z, R)) - 0.025) < 2e-7
+        assert abs((1.0 - _qvn_scipy(z, R)) - 0.025) < 5e-7
         if n == 0:   # through the generic CDF too (it takes seconds)
             assert abs((1.0 - O.qvn(np.array(z), R)) - 0.025) < 1e-12
     # the first three levels already spend alpha0: no valid fourth level
@@ -1089,7 +1165,7 @@ def test_alpha4_closed_form_against_scipy():
         ds = O.make_design(p, list(a))
         z = [ds["z1"], ds["z2"], ds["z3"], ds["z4"]]
         h = [(z[i] - math.sqrt(r[i] * I) * (-math.log(1 - (0.8 - 0.6 * r[i])))) / s for i in range(4)]
-        assert abs(O.exact_paper(p, np.array(a)) - (1.0 - _qvn_scipy(h, _nested_R(r)))) < 2e-7
+        assert abs(O.exact_paper(p, np.array(a)) - (1.0 - _qvn_scipy(h, _nested_R(r)))) < 5e-7
 
 
 def test_smoothed_surface_at_continuous_designs():

@@ -209,7 +209,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="3d", choices=["3d", "1d", "5d", "alpha", "alpha3", "alpha4", "levels", "grad",
-                                                         "refine", "batch", "smooth", "twolayer"])
+                                                         "refine", "batch", "smooth", "twolayer", "nested3"])
     ap.add_argument("--batch-scale", type=float, default=1.0,
                     help="batch workload only: scale of the per-axis grids and of the draw range (1 = full size)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -254,6 +254,8 @@ def main():
         return bench_smooth(args)
     if args.workload == "twolayer":
         return bench_two_layer(args)
+    if args.workload == "nested3":
+        return bench_nested3(args)
     spec = workload(args.workload)
     M, G = spec["n_draws"], int(np.prod(spec["m"]))
     log(f"workload {args.workload}: d={spec['d']} grid={spec['m']} G={G} M={M}")
@@ -485,6 +487,79 @@ def bench_nested(args, n):
            "sweep_ms": s32, "sweep_evals_per_s": evals / (1e-3 * s32),
            "result": {"best_alpha": a_best, "best_power_smoothed": v32,
                       "raw_power_at_best": float(m32[i32].item())},
+           "fp64": {"ms_per_step": 1e3 * t64, "sweep_ms": s64},
+           "fp32_vs_fp64": {"speedup_sweep": s64 / s32,
+                            "max_abs_diff_objective": float(np.nanmax((m32 - m64).abs().cpu().numpy())),
+                            "argmax_fp32": int(i32), "argmax_fp64": int(i64)}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_nested3(args):
+    """Three nested populations cut from one biomarker by two cutoffs: the
+    64 x 64 grid of cutoff quantiles (q_1, q_2) over [0.1, 0.9], one z* on the
+    FWER boundary per design, step prior, M = 1e5.  A step is problem set-up
+    (critical values and launch order) + draws + sweep + smoothing over the
+    designs that exist + argmax.  FP32 and FP64."""
+    import torch
+    import paper_2005_10494_amd as bmd
+    from paper_2005_10494_amd import workloads as W
+    spec = W.nested3_grid()
+    M, G = spec["n_draws"], int(np.prod(spec["m"]))
+    res = {}
+    for prec in ("fp32", "fp64"):
+        ts, sw = [], []
+        for it in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            with bmd.Problem(spec) as p:
+                p.profile(True)
+                mean = p.eval_grid(M, prec)
+                smooth = p.smooth(mean, prec)
+                idx, val, cell = p.argmax(smooth)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                ph = p.profile_read()
+            if it >= args.warmup:
+                ts.append(dt)
+                sw.append(ph["sweep"])
+            log(f"  nested3 {prec} step {it}: {1e3 * dt:.1f} ms, sweep {ph['sweep']:.1f} ms")
+        res[prec] = (float(np.mean(ts)), float(np.mean(sw)), mean, idx, val, cell)
+    t32, s32, m32, i32, v32, c32 = res["fp32"]
+    t64, s64, m64, i64, v64, _ = res["fp64"]
+    exists = ~np.isnan(m32.cpu().numpy())
+    feasible = int(exists.sum())
+    evals = feasible * M
+    # Per summand: the three means and 1 - Phi_3 with the sums (22) and, per
+    # panel point, 22 as for the three-population sweep; the panel count is each
+    # design's own under the FP32 rule (the sweep runs a wavefront at its
+    # largest count, which the launch order keeps close to every lane's).
+    m0 = spec["m"][0]
+    q = spec["q_lo"] + (spec["q_hi"] - spec["q_lo"]) * np.arange(m0) / (m0 - 1)
+    q1, q2 = (a.ravel() for a in np.meshgrid(q, q, indexing="ij"))
+    r2, r3 = 1.0 - q1[exists], 1.0 - q2[exists]
+    scale = np.minimum(np.sqrt((1 - r2) / r2), np.sqrt((r2 - r3) / r3))
+    npan = np.clip(np.ceil(2.5 / scale), 3, 64)
+    flops = float(M * np.sum(22.0 + npan * 8 * 22.0))
+    achieved = flops / (1e-3 * s32) / 1e12
+    best = [float(q[c]) for c in c32]
+    out = {"metric": "two-cutoff grid: integrand evals/s", "value": evals / t32,
+           "unit": "integrand evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * t32, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"three nested populations from two cutoffs on one biomarker, (q_1, q_2) grid "
+                                  f"{m0}x{m0} over [{spec['q_lo']}, {spec['q_hi']}], one z* on the FWER boundary, "
+                                  f"step prior b0 ~ N({spec['mu_b0']}, {spec['sd_b0']}^2), b1 ~ N({spec['mu_b1']}, "
+                                  f"{spec['sd_b1']}^2), tau ~ U({spec['tau_lo']}, {spec['tau_hi']}), I = "
+                                  f"{spec['info']:g}, M={M}, smoothing sd {spec['bandwidth'][0]} on both axes, "
+                                  f"steps = precompute+order+draws+sweep+smooth+argmax over designs that exist",
+                      "designs": G, "feasible_designs": feasible, "n_draws": M},
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
+                        "frac": achieved / 157.3, "traffic": None,
+                        "kernel": f"k_eval_nested3<float,false> (one design per thread, {npan.min():.0f}.."
+                                  f"{npan.max():.0f} panels (mean {npan.mean():.2f}) x 8 points of two univariate "
+                                  f"CDFs given the middle statistic)", "flops_per_launch": flops},
+           "sweep_ms": s32, "sweep_evals_per_s": evals / (1e-3 * s32),
+           "result": {"best_q": best, "best_power_smoothed": v32, "raw_power_at_best": float(m32[i32].item())},
            "fp64": {"ms_per_step": 1e3 * t64, "sweep_ms": s64},
            "fp32_vs_fp64": {"speedup_sweep": s64 / s32,
                             "max_abs_diff_objective": float(np.nanmax((m32 - m64).abs().cpu().numpy())),

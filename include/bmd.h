@@ -120,7 +120,23 @@ typedef enum {
      * 0.975.  Designs whose first three levels already spend alpha0 have no
      * fourth level and a NaN estimate.  Formula 10 prior with four normals per
      * draw; alpha_rule BMD_ALPHA_FWER_EQUAL; grid sweeps only. */
-    BMD_DESIGN_ALPHA4 = 3
+    BMD_DESIGN_ALPHA4 = 3,
+    /* n = 3 nested populations cut from one biomarker by two cutoffs (Sec.
+     * 2.2 with n = 3, in the cutoff design space): d = 2, axis 0 the first
+     * cutoff quantile q_1 and axis 1 the second q_2, both over [q_lo, q_hi]
+     * with 0.1 <= q_lo and q_hi < 1; the tests are the full population,
+     * {x > Phi^-1(q_1)} (fraction r_2 = 1 - q_1) and {x > Phi^-1(q_2)}
+     * (r_3 = 1 - q_2), with the null correlations sqrt(r_j / r_i) of Appendix
+     * A.1.  Designs with q_1 >= q_2, or whose partial correlation
+     * sqrt(r_3 (1 - r_2) / (r_2 (1 - r_3))) exceeds 0.975, do not exist: their
+     * estimate is NaN.  Step prior with one true cutoff tau per draw
+     * (BMD_EFFECT_STEP; the responders inside population i are a fraction
+     * 1 - max(q_i, tau) of all patients); alpha_rule BMD_ALPHA_FWER_EQUAL (one
+     * critical value z* with 1 - Phi_3(z*, z*, z*) = alpha0) or
+     * BMD_ALPHA_BONFERRONI (Phi^-1(1 - alpha0 / 3)); indicator_width 0; at
+     * most 16,776,960 designs (ERANGE); grid sweeps, smoothing (over the
+     * designs that exist) and argmax only. */
+    BMD_DESIGN_NESTED3 = 4
 } bmd_design_space;
 
 /* Problem descriptor (copied by bmd_create_problem). */
@@ -250,7 +266,8 @@ bmd_status bmd_argmax(bmd_problem *p, const double *d_surface, int64_t *h_index,
  * Draws are generated into the problem's workspace in passes of at most 4 GB
  * (environment variable BMD_GRAD_BUDGET, in bytes, overrides the limit) and
  * read by every point; results do not depend on the pass size.  Works on grid
- * and continuous problems; requires BMD_EFFECT_STEP (ENOTSUP otherwise). */
+ * and continuous problems; requires BMD_EFFECT_STEP and BMD_DESIGN_CUTOFFS
+ * (ENOTSUP otherwise). */
 bmd_status bmd_grad_design(bmd_problem *p, const double *d_q, int64_t B, uint64_t n_draws,
                            int32_t prec, double *d_obj, double *d_grad_q, double *d_grad_mu,
                            void *stream);
@@ -489,7 +506,8 @@ bmd_status bmd_draws(bmd_problem *p, uint64_t k0, uint64_t n, double *d_u, doubl
  *            (alpha design spaces: c[] is 0, except BMD_DESIGN_ALPHA3/4: c[0] = r_3
  *            and c[1] = z3, NaN when the design has no third level of three
  *            populations; BMD_DESIGN_ALPHA4 also c[2] = r_4 and c[3] = z4, NaN
- *            when the design has no fourth level) */
+ *            when the design has no fourth level; BMD_DESIGN_NESTED3: c[0] = r_3,
+ *            c[1] = z3 (= z1 = z2), NaN for designs that do not exist) */
 bmd_status bmd_designs(bmd_problem *p, int64_t g0, int64_t n, double *d_fields, void *stream);
 
 #ifdef __cplusplus

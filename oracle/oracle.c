@@ -327,6 +327,22 @@ double or_zstar(double r, double alpha0)
     return 0.5 * (lo + hi);
 }
 
+/* One critical value z* for three nested tests at equal levels (Formula 2 with
+ * n = 3 and alpha_1 = alpha_2 = alpha_3): 1 - Phi_3(z*, z*, z*) = alpha0 for the
+ * null correlations sqrt(r2), sqrt(r3), sqrt(r3 / r2) of Appendix A.1, by
+ * bisection between one test at level alpha0 and the Bonferroni value. */
+double or_zstar3(double r2, double r3, double alpha0)
+{
+    double lo = -or_Phiinv(alpha0), hi = -or_Phiinv(alpha0 / 3.0);
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        double fwer = 1.0 - or_tvn(mid, mid, mid, sqrt(r2), sqrt(r3), sqrt(r3 / r2));
+        if (fwer > alpha0) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 /* Second critical value z2 with FWER(z1, z2) = P(Z1 > z1 or Z2 > z2) =
  * Phi(-z1) + Phi(-z2) - Phi_2(-z1, -z2; sqrt r) = alpha0 (Formula 2 for n = 2
  * with the first level alpha_1 = Phi(-z1) given), by bisection: the FWER falls
@@ -564,6 +580,22 @@ void or_make_design(const or_problem *p, const double *q, or_design *o)
         o->z3 = or_z3_fwer(o->z1, o->z2, o->r, o->r3, p->alpha0);
         return;
     }
+    if (p->design_space == OR_DESIGN_NESTED3) {
+        /* Two cutoffs on one biomarker: populations all, x > c_1 and x > c_2. */
+        o->q[0] = q[0];
+        o->q[1] = q[1];
+        o->c[0] = or_Phiinv(q[0]);
+        o->c[1] = or_Phiinv(q[1]);
+        o->r = 1.0 - q[0];
+        o->rho = sqrt(o->r);
+        o->r3 = 1.0 - q[1];
+        int ok = q[0] < q[1] && o->r3 * (1.0 - o->r) <= 0.975 * 0.975 * o->r * (1.0 - o->r3);
+        double z = !ok ? NAN
+                 : p->alpha_rule == OR_ALPHA_BONFERRONI ? -or_Phiinv(p->alpha0 / 3.0)
+                                                        : or_zstar3(o->r, o->r3, p->alpha0);
+        o->z1 = o->z2 = o->z3 = z;
+        return;
+    }
     if (p->design_space == OR_DESIGN_ALPHA) {
         /* (r_2, alpha_1) or alpha_1 alone: the nested pair of Sec. 2.2 with the
          * level split on the FWER boundary of Formula 2. */
@@ -606,7 +638,7 @@ void or_make_draw(const or_problem *p, uint64_t k, or_draw *o)
 {
     memset(o, 0, sizeof *o);
     if (p->effect == OR_EFFECT_STEP) {
-        int d = p->d;
+        int d = p->design_space == OR_DESIGN_NESTED3 ? 1 : p->d;   /* one biomarker */
         draw_uniforms(p, k, 2 + d, o->u);
         o->b0 = p->mu_b0 + p->sd_b0 * or_Phiinv(o->u[0]);
         o->b1 = p->mu_b1 + p->sd_b1 * or_Phiinv(o->u[1]);
@@ -733,8 +765,26 @@ static double success4(const or_problem *p, const or_design *ds, const or_draw *
     return 1.0 - or_qvn_nested(h, r);
 }
 
+/* Three nested populations cut from one biomarker (step prior): population i
+ * has fraction r_i and responders R = {x > t}, P(R and x > c_i) = 1 - max(q_i, tau),
+ * so Delta_i = b0 + b1 (1 - max(q_i, tau)) / r_i (q_0 = 0, r_1 = 1) and the
+ * drift is sqrt(r_i I) Delta_i (Formula 3); the summand is 1 - Phi_3 at
+ * z* - drift with the null correlations of Appendix A.1. */
+static double success_nested3(const or_problem *p, const or_design *ds, const or_draw *dr)
+{
+    if (isnan(ds->z3)) return NAN;
+    double q[3] = {0.0, ds->q[0], ds->q[1]}, r[3] = {1.0, ds->r, ds->r3}, h[3];
+    double z[3] = {ds->z1, ds->z2, ds->z3};
+    for (int i = 0; i < 3; ++i) {
+        double delta = dr->b0 + dr->b1 * (1.0 - fmax(q[i], dr->tau[0])) / r[i];
+        h[i] = z[i] - sqrt(r[i] * p->info) * delta;
+    }
+    return 1.0 - or_tvn(h[0], h[1], h[2], sqrt(r[1]), sqrt(r[2]), sqrt(r[2] / r[1]));
+}
+
 double or_success(const or_problem *p, const or_design *ds, const or_draw *dr)
 {
+    if (p->design_space == OR_DESIGN_NESTED3) return success_nested3(p, ds, dr);
     if (p->design_space == OR_DESIGN_ALPHA4) return success4(p, ds, dr);
     if (p->design_space == OR_DESIGN_ALPHA3) return success3(p, ds, dr);
     double d1, d2;

@@ -33,7 +33,7 @@ extern "C" {
 
 enum { OR_ALPHA_FWER_EQUAL = 0, OR_ALPHA_BONFERRONI = 1, OR_ALPHA_FIXED = 2, OR_ALPHA_SPLIT = 3 };
 enum { OR_EFFECT_STEP = 0, OR_EFFECT_PAPER_GAUSS = 1 };
-enum { OR_DESIGN_CUTOFFS = 0, OR_DESIGN_ALPHA = 1, OR_DESIGN_ALPHA3 = 2, OR_DESIGN_ALPHA4 = 3 };
+enum { OR_DESIGN_CUTOFFS = 0, OR_DESIGN_ALPHA = 1, OR_DESIGN_ALPHA3 = 2, OR_DESIGN_ALPHA4 = 3, OR_DESIGN_NESTED3 = 4 };
 
 typedef struct {
     int32_t d;              /* number of biomarkers (cutoff axes), 1..6          */
@@ -68,7 +68,13 @@ typedef struct {
      * OR_DESIGN_ALPHA4: n = 4 nested populations 1 > r_lo > r_hi > r_4 (the
      * three-threshold designs of Sec. 3); d = 3 axes alpha_1..alpha_3 on
      * [q_lo, q_hi] and alpha_4 on the FWER boundary (NaN designs where the first
-     * three levels already spend alpha0).  Paper prior only. */
+     * three levels already spend alpha0).  Paper prior only.
+     * OR_DESIGN_NESTED3: n = 3 nested populations cut from one biomarker by
+     * two cutoffs, d = 2 axes q_1 < q_2 on [q_lo, q_hi]: the full population,
+     * {x > Phi^-1(q_1)} (r_2 = 1 - q_1) and {x > Phi^-1(q_2)} (r_3 = 1 - q_2);
+     * designs with q_1 >= q_2 or a partial correlation of the third on the
+     * second population above 0.975 are NaN.  Step prior with one true cutoff
+     * tau; alpha rule FWER_EQUAL (one z* for all three tests) or BONFERRONI. */
     int32_t design_space;
     double r_lo, r_hi;
     double r_4;
@@ -107,6 +113,7 @@ double or_orthant(int d, const double *v, double rho_b);   /* P(X_j > v_j)    */
 double or_zstar(double r, double alpha0);
 double or_z2_fwer(double z1, double r, double alpha0);   /* second level on the FWER boundary */
 double or_z3_fwer(double z1, double z2, double r2, double r3, double alpha0);   /* n = 3: third level */
+double or_zstar3(double r2, double r3, double alpha0);   /* n = 3 at equal levels: 1 - Phi_3(z*,z*,z*) = alpha0 */
 double or_qvn(const double *h, const double *R);   /* P(X_i <= h_i, i < 4), R 4 x 4 correlations */
 double or_qvn_nested(const double *h, const double *r);   /* same, nested-population correlations of r[4] */
 double or_z4_fwer(double z1, double z2, double z3, double r2, double r3, double r4, double alpha0);   /* n = 4 */

@@ -158,6 +158,13 @@ hipError_t launch_levels_best(const bmd_problem* p, int k, const double* mean, d
 // Three nested populations (kernels_three.hip): critical values of every
 // design, and the grid sweep (direct, one thread per design).
 hipError_t launch_three_precompute(const bmd_problem* p, hipStream_t s);
+// Two cutoffs on one biomarker (kernels_nested3.hip): critical values and
+// the sweep's launch order of every design, and the grid sweep.
+constexpr int64_t kNested3MaxTiles = 65535;   // sweep tiles of kEvalBlock designs (grid y dimension)
+hipError_t launch_nested3_precompute(const bmd_problem* p, hipStream_t s);
+int nested3_blocks_per_cu(int prec);
+hipError_t launch_eval_nested3(const bmd_problem* p, int prec, int64_t M, const void* ws, double* partials,
+                               int n_slices, int64_t slice_len, bool want_var, hipStream_t s);
 int three_blocks_per_cu(int prec);
 hipError_t launch_eval_three(const bmd_problem* p, int prec, int64_t M, const void* ws, double* partials,
                              int n_slices, int64_t slice_len, bool want_var, hipStream_t s);

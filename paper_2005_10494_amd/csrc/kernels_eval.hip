@@ -176,7 +176,8 @@ int resident_typed(const bmd_problem* p, int prec) {
 // The matrix-core sweep covers grid problems with at least two biomarkers,
 // the step prior and the exact cutoff indicator; the rest use the direct one.
 bool use_mfma_sweep(const bmd_problem* p) {
-    return p->grid && p->P.d >= 2 && p->P.effect == BMD_EFFECT_STEP && p->P.width == 0.0 && !p->force_direct;
+    return p->grid && p->P.design_space == BMD_DESIGN_CUTOFFS && p->P.d >= 2 && p->P.effect == BMD_EFFECT_STEP &&
+           p->P.width == 0.0 && !p->force_direct;
 }
 
 MfmaGeom sweep_geometry(const bmd_problem* p, int prec) { return mfma_geometry(p, prec); }
@@ -191,6 +192,7 @@ int64_t sweep_tiles(const bmd_problem* p, int prec) {
 
 int sweep_blocks_per_cu(const bmd_problem* p, int prec) {
     if (p->P.design_space == BMD_DESIGN_ALPHA3) return three_blocks_per_cu(prec);
+    if (p->P.design_space == BMD_DESIGN_NESTED3) return nested3_blocks_per_cu(prec);
     if (p->P.design_space == BMD_DESIGN_ALPHA4) return four_blocks_per_cu(prec);
     return prec == BMD_FP64 ? resident_typed<double, 24>(p, prec) : resident_typed<float, 12>(p, prec);
 }
@@ -209,6 +211,8 @@ hipError_t launch_eval_grid(const bmd_problem* p, int prec, int64_t M, const voi
                             int n_slices, int64_t slice_len, bool want_var, hipStream_t s) {
     if (p->P.design_space == BMD_DESIGN_ALPHA3)
         return launch_eval_three(p, prec, M, ws, partials, n_slices, slice_len, want_var, s);
+    if (p->P.design_space == BMD_DESIGN_NESTED3)
+        return launch_eval_nested3(p, prec, M, ws, partials, n_slices, slice_len, want_var, s);
     if (p->P.design_space == BMD_DESIGN_ALPHA4)
         return launch_eval_four(p, prec, M, ws, partials, n_slices, slice_len, want_var, s);
     return launch_eval_mode(p, prec, M, ws, partials, n_slices, slice_len, want_var ? kSquares : kSums, s);

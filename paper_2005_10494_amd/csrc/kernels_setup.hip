@@ -364,14 +364,16 @@ __device__ __forceinline__ void draw_one(const DevProblem& P, const double* __re
         const double b0 = P.mu_b0 + P.sd_b0 * norm_quantile(u[0]);
         const double b1 = P.mu_b1 + P.sd_b1 * norm_quantile(u[1]);
         double t[kMaxDim];
-        for (int j = 0; j < P.d; ++j) {
+        // two cutoffs on one biomarker: one true cutoff per draw
+        const int nbio = P.design_space == BMD_DESIGN_NESTED3 ? 1 : P.d;
+        for (int j = 0; j < nbio; ++j) {
             const double tau = affine_uniform(P.tau_lo, P.tau_hi, u[2 + j]);
             t[j] = norm_quantile(tau);
             D.tau[j * M + kk] = tau;
             if (P.G > 0) D.thr[kk * P.d + j] = count_le(P, j, tau);
         }
         double PR;
-        if (P.d == 1) {
+        if (nbio == 1) {
             PR = 1.0 - D.tau[kk];
         } else {
             PR = 0.0;
@@ -446,13 +448,14 @@ __global__ __launch_bounds__(128) void k_inspect_draws(DevProblem P, const doubl
         f[0] = P.mu_b0 + P.sd_b0 * norm_quantile(u[0]);
         f[1] = P.mu_b1 + P.sd_b1 * norm_quantile(u[1]);
         double t[kMaxDim];
-        for (int j = 0; j < P.d; ++j) {
+        const int nbio = P.design_space == BMD_DESIGN_NESTED3 ? 1 : P.d;
+        for (int j = 0; j < nbio; ++j) {
             const double tau = affine_uniform(P.tau_lo, P.tau_hi, u[2 + j]);
             t[j] = norm_quantile(tau);
             f[5 + j] = tau;
             f[11 + j] = t[j];
         }
-        f[2] = P.d == 1 ? 1.0 - f[5] : orthant_gh(P, t, gh, K);
+        f[2] = nbio == 1 ? 1.0 - f[5] : orthant_gh(P, t, gh, K);
     } else {
         f[3] = norm_quantile(u[0]);
         f[4] = norm_quantile(u[1]);
@@ -478,6 +481,9 @@ __global__ __launch_bounds__(128) void k_inspect_designs(DevProblem P, int64_t g
     }
     if (P.design_space == BMD_DESIGN_ALPHA3) {
         f[6] = P.r_hi;
+        f[7] = z3[g];
+    } else if (P.design_space == BMD_DESIGN_NESTED3) {
+        f[6] = 1.0 - f[1];   // r_3
         f[7] = z3[g];
     } else if (P.design_space == BMD_DESIGN_ALPHA4) {
         f[6] = P.r_hi;
@@ -565,11 +571,12 @@ __global__ __launch_bounds__(1024) void k_order_feasible(int64_t G, const double
 
 hipError_t launch_design_precompute(const bmd_problem* p, hipStream_t s) {
     if (p->P.G == 0) return hipSuccess;
+    if (p->P.design_space == BMD_DESIGN_NESTED3) return launch_nested3_precompute(p, s);   // its own order
     if (p->P.design_space == BMD_DESIGN_ALPHA3 || p->P.design_space == BMD_DESIGN_ALPHA4) {
-        const bool three = p->P.design_space == BMD_DESIGN_ALPHA3;
-        hipError_t e = three ? launch_three_precompute(p, s) : launch_four_precompute(p, s);
+        const bool four = p->P.design_space == BMD_DESIGN_ALPHA4;
+        hipError_t e = four ? launch_four_precompute(p, s) : launch_three_precompute(p, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_order_feasible, dim3(1), dim3(1024), 0, s, p->P.G, three ? p->d_z3 : p->d_z4,
+        hipLaunchKernelGGL(k_order_feasible, dim3(1), dim3(1024), 0, s, p->P.G, four ? p->d_z4 : p->d_z3,
                            p->d_order);
         return hipGetLastError();
     }

@@ -65,9 +65,12 @@ __device__ __forceinline__ T uniform(T x) {
         return x;
 }
 
-// Per-problem constants of Phi_3 in type T.
-template <typename T>
+// Constants of Phi_3 in type T: per problem (UNI: the FP32 ones moved to
+// scalar registers), or per lane for sweeps whose designs have their own
+// fractions (UNI = false).
+template <typename T, bool UNI = true>
 struct TvnConst {
+    __device__ static T U(T x) { return UNI ? uniform(x) : x; }
     T r12, r23;        // regressions of the first and third coordinates on the second
     T is12, is23;      // 1 / s12, 1 / s23
     T tail;            // L: integration range [-L, U]
@@ -88,23 +91,24 @@ struct TvnConst {
         const double L = sizeof(T) == 8 ? 8.5 : 6.0;
         const double a = sqrt(r2), b = sqrt(r3 / r2), sa = sqrt(1.0 - r2), sb = sqrt(1.0 - r3 / r2);
         const double k = static_cast<double>(kPhiScale);
-        g1 = uniform(static_cast<T>(a / sa));
-        g3 = uniform(static_cast<T>(b / sb));
-        k1 = uniform(static_cast<T>(k / sa));
-        k3 = uniform(static_cast<T>(k / sb));
+        g1 = U(static_cast<T>(a / sa));
+        g3 = U(static_cast<T>(b / sb));
+        k1 = U(static_cast<T>(k / sa));
+        k3 = U(static_cast<T>(k / sb));
         r12 = static_cast<T>(a);
         r23 = static_cast<T>(b);
         is12 = static_cast<T>(1.0 / sa);
         is23 = static_cast<T>(1.0 / sb);
         tail = uniform(static_cast<T>(L));
-        c1 = uniform(static_cast<T>(L * sa));
-        c3 = uniform(static_cast<T>(L * sb));
-        ir12 = uniform(static_cast<T>(1.0 / a));
-        ir23 = uniform(static_cast<T>(1.0 / b));
+        c1 = U(static_cast<T>(L * sa));
+        c3 = U(static_cast<T>(L * sb));
+        ir12 = U(static_cast<T>(1.0 / a));
+        ir23 = U(static_cast<T>(1.0 / b));
         const double* x = gl + gl_offset(kNodes);
         const double* w = x + kNodes;
 #pragma unroll
         for (int i = 0; i < kNodes; ++i) {
+            // node constants: the same for every design
             px[i] = uniform(static_cast<T>(0.5 * (1.0 + x[i])));
             pw[i] = static_cast<T>(0.5 * w[i] * 0.39894228040143267794);
             lw[i] = uniform(static_cast<T>(log2(0.5 * w[i] * 0.39894228040143267794 / k)));
@@ -116,7 +120,8 @@ struct TvnConst {
 // FP32 Phi_3 in y' (see TvnConst): per point one FMA for y', one per
 // conditional argument, one for the Gaussian's exponent with the weight, an
 // exp2, the two CDFs and two to accumulate.
-__device__ __forceinline__ float tvn(float h1, float h2, float h3, const TvnConst<float>& c) {
+template <bool UNI>
+__device__ __forceinline__ float tvn(float h1, float h2, float h3, const TvnConst<float, UNI>& c) {
     const float k = kPhiScale;
     const float lo = -c.tail * k;
     const float hi = k * fminf(fminf(h2, c.tail), fminf((h1 + c.c1) * c.ir12, (h3 + c.c3) * c.ir23));
@@ -140,8 +145,8 @@ __device__ __forceinline__ float tvn(float h1, float h2, float h3, const TvnCons
 // Phi_3(h1, h2, h3) over c.np panels (wave-uniform).  Every lane runs the
 // same node count: an empty range (U <= -L) becomes a zero panel width, and
 // NaN inputs give NaN.
-template <typename T>
-__device__ __forceinline__ T tvn(T h1, T h2, T h3, const TvnConst<T>& c) {
+template <typename T, bool UNI>
+__device__ __forceinline__ T tvn(T h1, T h2, T h3, const TvnConst<T, UNI>& c) {
     const T lo = -c.tail;
     const T hi = fmin(fmin(h2, c.tail), fmin((h1 + c.c1) * c.ir12, (h3 + c.c3) * c.ir23));
     const T width = fmax(hi - lo, T(0)) / static_cast<T>(c.np);

@@ -131,6 +131,26 @@ def alpha4_grid() -> dict:
     return alpha4_design(25, n_draws=100_000)
 
 
+def nested3_design(m, q_range=(0.1, 0.9), rule: str = "fwer", n_draws: int = 100_000, bandwidth: float = 0.03,
+                   **kw) -> dict:
+    """Three nested populations cut from one biomarker by two cutoffs: an
+    m x m grid (or m = (m0, m1)) of cutoff quantiles (q_1, q_2) over
+    ``q_range``, populations all, x > Phi^-1(q_1), x > Phi^-1(q_2); the step
+    prior of ``STEP_PRIOR`` with one true cutoff; designs with q_1 >= q_2 do
+    not exist."""
+    mm = [m, m] if np.isscalar(m) else list(m)
+    p = base_problem(2, mm, 0.0, bandwidth, design="nested3", q_lo=float(q_range[0]), q_hi=float(q_range[1]),
+                     alpha_rule=rule)
+    p.update(kw)
+    p["n_draws"] = n_draws
+    return p
+
+
+def nested3_grid() -> dict:
+    """Two cutoffs on one biomarker, 64 x 64 grid over [0.1, 0.9], M = 1e5."""
+    return nested3_design(64)
+
+
 def noisy_surface(m, seed: int = 0, nan_corner: int = 0) -> np.ndarray:
     """A seeded stand-in for an estimated grid surface (row-major over the
     axes m, axis 0 slowest): a smooth bump plus N(0, 0.02^2) noise.  With

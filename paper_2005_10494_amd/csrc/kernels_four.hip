@@ -19,58 +19,39 @@ constexpr int kBvnMax32 = 12;   // largest FP32 rule
 // critical value solves F(z4) = 1 - Phi_4(z1, z2, z3, z4) - alpha0 = 0 (F
 // falls in z4) inside the bracket from the fourth test alone at level alpha0
 // (F >= 0) to the union bound with the level a123 = 1 - Phi_3(z1, z2, z3) the
-// first three spend (F <= 0), by the Illinois variant of false position, as
-// for the third level of three populations.  NaN when a123 >= alpha0.
+// first three spend (F <= 0), by falling_root as for the third level of three
+// populations (one wavefront per design).  NaN when a123 >= alpha0.
 __global__ __launch_bounds__(64) void k_four_precompute(DevProblem P, const double* __restrict__ gl,
                                                         double* __restrict__ r_out, double* __restrict__ z1_out,
                                                         double* __restrict__ z2_out, double* __restrict__ z3_out,
                                                         double* __restrict__ z4_out) {
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= P.G) return;
+    const int64_t g = blockIdx.x;
+    const int lane = threadIdx.x;
     const int i0 = static_cast<int>(g / P.stride[0]);
     const int i1 = static_cast<int>((g / P.stride[1]) % P.m[1]);
     const int i2 = static_cast<int>(g % P.m[2]);
     const double z1 = -norm_quantile(grid_coord(P.q_lo, P.q_hi, i0, P.m[0]));
     const double z2 = -norm_quantile(grid_coord(P.q_lo, P.q_hi, i1, P.m[1]));
     const double z3 = -norm_quantile(grid_coord(P.q_lo, P.q_hi, i2, P.m[2]));
-    r_out[g] = P.r_lo;
-    z1_out[g] = z1;
-    z2_out[g] = z2;
-    z3_out[g] = z3;
+    const PanelNode nd = panel_node(gl, lane);
     TvnConst<double> c3;
     c3.init(P.r_lo, P.r_hi, max(kPanelsSetup, tvn_panels<double>(P.r_lo, P.r_hi)), gl);
-    const double a123 = 1.0 - tvn(z1, z2, z3, c3);
+    const double a123 = 1.0 - tvn_wave(z1, z2, z3, c3, nd);
     double z4 = NAN;
     if (a123 < P.alpha0) {
         QvnConst<double, kBvnMax64> c;
         c.init(P.r_lo, P.r_hi, P.r_4, max(kPanelsSetup, qvn_panels<double>(P.r_lo, P.r_hi, P.r_4)),
                bvn_nodes_fp64(qvn_partial_rho(P.r_lo, P.r_hi, P.r_4)), gl);
-        auto F = [&](double z) { return (1.0 - qvn(z1, z2, z3, z, c)) - P.alpha0; };
-        double lo = -norm_quantile(P.alpha0), hi = -norm_quantile(P.alpha0 - a123);
-        double Flo = F(lo), Fhi = F(hi);
-        z4 = Flo <= 0.0 ? lo : Fhi >= 0.0 ? hi : 0.5 * (lo + hi);
-        int kept = 0;   // +1: lo kept by the last step, -1: hi kept
-        for (int it = 0; it < 100 && Flo > 0.0 && Fhi < 0.0; ++it) {
-            double x = (lo * Fhi - hi * Flo) / (Fhi - Flo);
-            if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
-            const double Fx = F(x);
-            z4 = x;
-            if (Fx == 0.0 || hi - lo <= 1e-14 * fabs(x)) break;
-            if (Fx > 0.0) {
-                lo = x;
-                Flo = Fx;
-                if (kept == -1) Fhi *= 0.5;
-                kept = -1;
-            } else {
-                hi = x;
-                Fhi = Fx;
-                if (kept == 1) Flo *= 0.5;
-                kept = 1;
-            }
-            if (fabs(Fx) <= 4e-16) break;   // the rounding level of 1 - Phi_4
-        }
+        auto F = [&](double z) { return (1.0 - qvn_wave(z1, z2, z3, z, c, nd)) - P.alpha0; };
+        z4 = falling_root(F, -norm_quantile(P.alpha0), -norm_quantile(P.alpha0 - a123), 4e-16);
     }
-    z4_out[g] = z4;
+    if (lane == 0) {
+        r_out[g] = P.r_lo;
+        z1_out[g] = z1;
+        z2_out[g] = z2;
+        z3_out[g] = z3;
+        z4_out[g] = z4;
+    }
 }
 
 template <typename T>
@@ -207,7 +188,7 @@ hipError_t launch_typed(const FourArgs<T>& a, int n_slices, bool var, hipStream_
 
 hipError_t launch_four_precompute(const bmd_problem* p, hipStream_t s) {
     const int64_t G = p->P.G;
-    hipLaunchKernelGGL(k_four_precompute, dim3(static_cast<unsigned>((G + 63) / 64)), dim3(64), 0, s, p->P,
+    hipLaunchKernelGGL(k_four_precompute, dim3(static_cast<unsigned>(G)), dim3(64), 0, s, p->P,
                        p->d_gl, p->d_r, p->d_z1, p->d_z2, p->d_z3, p->d_z4);
     return hipGetLastError();
 }

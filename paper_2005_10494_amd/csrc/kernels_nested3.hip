@@ -34,20 +34,20 @@ __device__ __forceinline__ void nested3_q(const DevProblem& P, int64_t g, double
 // A design exists when q_1 < q_2 and the partial correlation of the third
 // statistic on the second given the first, sqrt(r_3 (1 - r_2) / (r_2 (1 - r_3))),
 // is at most 0.975 (the range of the panel rule).  Rule FWER_EQUAL: one z* for
-// the three tests on the FWER boundary 1 - Phi_3(z*, z*, z*) = alpha0, by the
-// Illinois variant of false position between one test at level alpha0 and the
-// Bonferroni value (FP64 Phi_3 of at least 16 panels); rule BONFERRONI:
-// z = Phi^-1(1 - alpha0 / 3).  NaN for designs that do not exist.
+// the three tests on the FWER boundary 1 - Phi_3(z*, z*, z*) = alpha0, by
+// falling_root between one test at level alpha0 and the Bonferroni value
+// (FP64 Phi_3 of at least 16 panels shared by the wavefront's lanes, one
+// wavefront per design); rule BONFERRONI: z = Phi^-1(1 - alpha0 / 3).  NaN for
+// designs that do not exist.
 __global__ __launch_bounds__(64) void k_nested3_precompute(DevProblem P, const double* __restrict__ gl,
                                                            double* __restrict__ r_out, double* __restrict__ z1_out,
                                                            double* __restrict__ z2_out,
                                                            double* __restrict__ z3_out) {
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= P.G) return;
+    const int64_t g = blockIdx.x;
+    const int lane = threadIdx.x;
     double q1, q2;
     nested3_q(P, g, &q1, &q2);
     const double r2 = 1.0 - q1, r3 = 1.0 - q2;
-    r_out[g] = r2;
     double z = NAN;
     if (q1 < q2 && r3 * (1.0 - r2) <= 0.975 * 0.975 * r2 * (1.0 - r3)) {
         if (P.alpha_rule == BMD_ALPHA_BONFERRONI) {
@@ -55,113 +55,84 @@ __global__ __launch_bounds__(64) void k_nested3_precompute(DevProblem P, const d
         } else {
             TvnConst<double> c;
             c.init(r2, r3, max(kPanelsSetup, tvn_panels<double>(r2, r3)), gl);
-            auto F = [&](double x) { return (1.0 - tvn(x, x, x, c)) - P.alpha0; };
-            double lo = -norm_quantile(P.alpha0), hi = -norm_quantile(P.alpha0 / 3.0);
-            double Flo = F(lo), Fhi = F(hi);
-            z = Flo <= 0.0 ? lo : Fhi >= 0.0 ? hi : 0.5 * (lo + hi);
-            int kept = 0;   // +1: lo kept by the last step, -1: hi kept
-            for (int it = 0; it < 100 && Flo > 0.0 && Fhi < 0.0; ++it) {
-                double x = (lo * Fhi - hi * Flo) / (Fhi - Flo);
-                if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
-                const double Fx = F(x);
-                z = x;
-                if (Fx == 0.0 || hi - lo <= 1e-14 * fabs(x)) break;
-                if (Fx > 0.0) {
-                    lo = x;
-                    Flo = Fx;
-                    if (kept == -1) Fhi *= 0.5;
-                    kept = -1;
-                } else {
-                    hi = x;
-                    Fhi = Fx;
-                    if (kept == 1) Flo *= 0.5;
-                    kept = 1;
-                }
-                if (fabs(Fx) <= 4e-16) break;   // the rounding level of 1 - Phi_3
-            }
+            const PanelNode nd = panel_node(gl, lane);
+            auto F = [&](double x) { return (1.0 - tvn_wave(x, x, x, c, nd)) - P.alpha0; };
+            z = falling_root(F, -norm_quantile(P.alpha0), -norm_quantile(P.alpha0 / 3.0), 4e-16);
         }
     }
-    z1_out[g] = z;
-    z2_out[g] = z;
-    z3_out[g] = z;
+    if (lane == 0) {
+        r_out[g] = r2;
+        z1_out[g] = z;
+        z2_out[g] = z;
+        z3_out[g] = z;
+    }
 }
 
 // Launch order of the designs.  The sweep runs every lane of a wavefront
 // with the wavefront's largest panel count, and along a row of the grid the
 // count falls from dozens of panels (q_2 just above q_1) to three, so index
 // order wastes most of the work.  Existing designs are sorted by their panel
-// counts, largest first (FP32 rule first, FP64 rule second: both fall as the
-// smaller conditional scale grows, so one order serves both precisions), ties
-// in index order, and designs that do not exist go last.
-constexpr int kPan32 = 64 - 3 + 1, kPan64 = 128 - 8 + 1;
-constexpr int kOrderBins = kPan32 * kPan64 + 1;
-constexpr int kOrderRun = (kOrderBins + 1023) / 1024;   // bins per thread in the scan
+// counts, largest first, ties in index order, and designs that do not exist
+// go last.  The FP32 and FP64 counts both fall as the smaller conditional
+// scale grows, so each step along that scale raises one of them or both:
+// their sum (offset to start at 0) orders the designs by both at once.
+constexpr int kOrderBins = (64 - 3) + (128 - 8) + 2;   // sums 0..181, then "does not exist"
 
 __device__ __forceinline__ int nested3_key(const DevProblem& P, const double* z, int64_t g) {
     const double zg = z[g];
     if (zg != zg) return kOrderBins - 1;
     double q1, q2;
     nested3_q(P, g, &q1, &q2);
-    return kOrderBins - 2 -
-           ((tvn_panels<float>(1.0 - q1, 1.0 - q2) - 3) * kPan64 + (tvn_panels<double>(1.0 - q1, 1.0 - q2) - 8));
+    return kOrderBins - 2 - ((tvn_panels<float>(1.0 - q1, 1.0 - q2) - 3) + (tvn_panels<double>(1.0 - q1, 1.0 - q2) - 8));
 }
 
-// One workgroup: a counting sort.  Bin counts by LDS atomics, an exclusive
-// scan into bin starts, then a stable scatter tile by tile, the wavefronts
-// of a tile in turn and, inside one, the lanes of each key in lane order.
+// One workgroup of 16 wavefronts: a stable counting sort.  Bin counts by LDS
+// atomics and their exclusive scan into bin starts; then, tile by tile of
+// 1,024 designs, each wavefront's count per bin, each lane's rank among the
+// lanes of its wavefront with the same key (by 63 shuffles), and per bin the
+// wavefronts' starts in turn.
 __global__ __launch_bounds__(1024) void k_order_nested3(DevProblem P, const double* __restrict__ z,
                                                         int32_t* __restrict__ order) {
     __shared__ int start[kOrderBins];
-    __shared__ int part[1024];
+    __shared__ int wstart[16][kOrderBins];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int64_t G = P.G;
     for (int b = t; b < kOrderBins; b += 1024) start[b] = 0;
     __syncthreads();
     for (int64_t g = t; g < G; g += 1024) atomicAdd(&start[nested3_key(P, z, g)], 1);
     __syncthreads();
-    int run[kOrderRun], mine = 0;
-#pragma unroll
-    for (int i = 0; i < kOrderRun; ++i) {
-        const int b = t * kOrderRun + i;
-        run[i] = b < kOrderBins ? start[b] : 0;
-        mine += run[i];
+    if (t == 0) {
+        int run = 0;
+        for (int b = 0; b < kOrderBins; ++b) {
+            const int c = start[b];
+            start[b] = run;
+            run += c;
+        }
     }
-    part[t] = mine;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {   // inclusive scan of the per-thread sums
-        const int v = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int base = part[t] - mine;   // each thread rewrites only the bins it read
-#pragma unroll
-    for (int i = 0; i < kOrderRun; ++i) {
-        const int b = t * kOrderRun + i;
-        if (b < kOrderBins) start[b] = base;
-        base += run[i];
-    }
-    __syncthreads();
     for (int64_t g0 = 0; g0 < G; g0 += 1024) {
+        for (int b = t; b < 16 * kOrderBins; b += 1024) (&wstart[0][0])[b] = 0;
+        __syncthreads();   // also orders the scan above and the previous tile's reads before these writes
         const int64_t g = g0 + t;
         const int key = g < G ? nested3_key(P, z, g) : -1;
-        for (int w = 0; w < 16; ++w) {
-            if (wave == w) {   // wave-uniform: the whole wavefront takes this branch
-                bool left = key >= 0;
-                for (uint64_t m = __ballot(left); m != 0; m = __ballot(left)) {
-                    const int kk = __shfl(key, static_cast<int>(__builtin_ctzll(m)));
-                    const bool mine_k = left && key == kk;
-                    const uint64_t same = __ballot(mine_k);
-                    const int pos = start[kk];
-                    if (mine_k) {
-                        order[pos + __popcll(same & ((1ull << lane) - 1))] = static_cast<int32_t>(g);
-                        left = false;
-                    }
-                    if (lane == static_cast<int>(__builtin_ctzll(same))) start[kk] = pos + __popcll(same);
-                }
-            }
-            __syncthreads();
+        if (key >= 0) atomicAdd(&wstart[wave][key], 1);
+        int rank = 0;
+        for (int j = 0; j < 64; ++j) {
+            const int kj = __shfl(key, j);
+            rank += (j < lane && kj == key) ? 1 : 0;
         }
+        __syncthreads();
+        for (int b = t; b < kOrderBins; b += 1024) {
+            int run = start[b];
+            for (int w = 0; w < 16; ++w) {
+                const int c = wstart[w][b];
+                wstart[w][b] = run;
+                run += c;
+            }
+            start[b] = run;
+        }
+        __syncthreads();
+        if (key >= 0) order[wstart[wave][key] + rank] = static_cast<int32_t>(g);
+        __syncthreads();
     }
 }
 
@@ -265,7 +236,7 @@ hipError_t launch_typed(const bmd_problem* p, const DrawArrays<T>& D, double* pa
 
 hipError_t launch_nested3_precompute(const bmd_problem* p, hipStream_t s) {
     const int64_t G = p->P.G;
-    hipLaunchKernelGGL(k_nested3_precompute, dim3(static_cast<unsigned>((G + 63) / 64)), dim3(64), 0, s, p->P,
+    hipLaunchKernelGGL(k_nested3_precompute, dim3(static_cast<unsigned>(G)), dim3(64), 0, s, p->P,
                        p->d_gl, p->d_r, p->d_z1, p->d_z2, p->d_z3);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -16,21 +16,17 @@ namespace {
 // value solves F(z3) = 1 - Phi_3(z1, z2, z3) - alpha0 = 0 (F falls in z3)
 // inside the bracket from the third test alone at level alpha0 (F >= 0) to the
 // union bound with the level a12 = 1 - Phi_2(z1, z2; sqrt r2) the first two
-// spend (F <= 0), by the Illinois variant of false position (a retained end
-// has its F halved, so both ends move); a step that leaves the bracket
-// bisects instead.  NaN when a12 >= alpha0.
+// spend (F <= 0), by falling_root with Phi_3 shared by the wavefront's lanes
+// (one wavefront per design).  NaN when a12 >= alpha0.
 __global__ __launch_bounds__(64) void k_three_precompute(DevProblem P, const double* __restrict__ gl,
                                                          double* __restrict__ r_out, double* __restrict__ z1_out,
                                                          double* __restrict__ z2_out, double* __restrict__ z3_out) {
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= P.G) return;
+    const int64_t g = blockIdx.x;
+    const int lane = threadIdx.x;
     const int i0 = static_cast<int>(g / P.stride[0]);
     const int i1 = static_cast<int>(g - static_cast<int64_t>(i0) * P.stride[0]);
     const double z1 = -norm_quantile(grid_coord(P.q_lo, P.q_hi, i0, P.m[0]));
     const double z2 = -norm_quantile(grid_coord(P.q_lo, P.q_hi, i1, P.m[1]));
-    r_out[g] = P.r_lo;
-    z1_out[g] = z1;
-    z2_out[g] = z2;
     constexpr int n = 24;
     const double* w = gl + gl_offset(n) + n;
     BvnConst<double, n> b12;
@@ -40,32 +36,16 @@ __global__ __launch_bounds__(64) void k_three_precompute(DevProblem P, const dou
     if (a12 < P.alpha0) {
         TvnConst<double> c;
         c.init(P.r_lo, P.r_hi, max(kPanelsSetup, tvn_panels<double>(P.r_lo, P.r_hi)), gl);
-        auto F = [&](double z) { return (1.0 - tvn(z1, z2, z, c)) - P.alpha0; };
-        double lo = -norm_quantile(P.alpha0), hi = -norm_quantile(P.alpha0 - a12);
-        double Flo = F(lo), Fhi = F(hi);
-        z3 = Flo <= 0.0 ? lo : Fhi >= 0.0 ? hi : 0.5 * (lo + hi);
-        int kept = 0;   // +1: lo kept by the last step, -1: hi kept
-        for (int it = 0; it < 100 && Flo > 0.0 && Fhi < 0.0; ++it) {
-            double x = (lo * Fhi - hi * Flo) / (Fhi - Flo);
-            if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
-            const double Fx = F(x);
-            z3 = x;
-            if (Fx == 0.0 || hi - lo <= 1e-14 * fabs(x)) break;
-            if (Fx > 0.0) {
-                lo = x;
-                Flo = Fx;
-                if (kept == -1) Fhi *= 0.5;
-                kept = -1;
-            } else {
-                hi = x;
-                Fhi = Fx;
-                if (kept == 1) Flo *= 0.5;
-                kept = 1;
-            }
-            if (fabs(Fx) <= 4e-16) break;   // the rounding level of 1 - Phi_3
-        }
+        const PanelNode nd = panel_node(gl, lane);
+        auto F = [&](double z) { return (1.0 - tvn_wave(z1, z2, z, c, nd)) - P.alpha0; };
+        z3 = falling_root(F, -norm_quantile(P.alpha0), -norm_quantile(P.alpha0 - a12), 4e-16);
     }
-    z3_out[g] = z3;
+    if (lane == 0) {
+        r_out[g] = P.r_lo;
+        z1_out[g] = z1;
+        z2_out[g] = z2;
+        z3_out[g] = z3;
+    }
 }
 
 template <typename T>
@@ -188,7 +168,7 @@ hipError_t launch_typed(const ThreeArgs<T>& a, int n_slices, bool var, hipStream
 
 hipError_t launch_three_precompute(const bmd_problem* p, hipStream_t s) {
     const int64_t G = p->P.G;
-    hipLaunchKernelGGL(k_three_precompute, dim3(static_cast<unsigned>((G + 63) / 64)), dim3(64), 0, s, p->P,
+    hipLaunchKernelGGL(k_three_precompute, dim3(static_cast<unsigned>(G)), dim3(64), 0, s, p->P,
                        p->d_gl, p->d_r, p->d_z1, p->d_z2, p->d_z3);
     return hipGetLastError();
 }

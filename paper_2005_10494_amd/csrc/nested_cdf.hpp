@@ -165,6 +165,82 @@ __device__ __forceinline__ T tvn(T h1, T h2, T h3, const TvnConst<T, UNI>& c) {
 }
 
 
+// ---------------------------------------------------------------------------
+// Critical values (FP64, one wavefront per design).  The FWER boundary is a
+// root of a falling function of one critical value; each evaluation is one
+// Phi_3 or Phi_4 at wave-uniform arguments, whose np x 8 panel points the
+// lanes share: lane l takes Gauss-Legendre node l % 8 of panels l / 8,
+// l / 8 + 8, ..., and every lane returns lane 0's total of the butterfly, so
+// the root finder's branches stay wave-uniform.
+// ---------------------------------------------------------------------------
+
+// The lane's panel node: position on [0, 1] and weight with phi's
+// 1/sqrt(2 pi) folded in (TvnConst's px, pw of node lane % 8).
+struct PanelNode {
+    double px, pw;
+    int p0;   // first panel of the lane
+};
+
+__device__ __forceinline__ PanelNode panel_node(const double* __restrict__ gl, int lane) {
+    const int i = lane & (kNodes - 1);
+    const double* x = gl + gl_offset(kNodes);
+    return {0.5 * (1.0 + x[i]), 0.5 * x[kNodes + i] * 0.39894228040143267794, lane / kNodes};
+}
+
+__device__ __forceinline__ double wave_total(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return __shfl(v, 0);
+}
+
+// Phi_3(h1, h2, h3) by the wavefront, the rule of tvn().
+__device__ __forceinline__ double tvn_wave(double h1, double h2, double h3, const TvnConst<double>& c,
+                                           const PanelNode& nd) {
+    const double lo = -c.tail;
+    const double hi = fmin(fmin(h2, c.tail), fmin((h1 + c.c1) * c.ir12, (h3 + c.c3) * c.ir23));
+    const double width = fmax(hi - lo, 0.0) / static_cast<double>(c.np);
+    double acc = 0.0;
+    for (int p = nd.p0; p < c.np; p += 64 / kNodes) {
+        const double y = fma(width, nd.px, fma(width, static_cast<double>(p), lo));
+        const double u = (h1 - c.r12 * y) * c.is12;
+        const double v = (h3 - c.r23 * y) * c.is23;
+        acc = fma(nd.pw * half_gauss(y), norm_cdf(u) * norm_cdf(v), acc);
+    }
+    return wave_total(acc) * width;
+}
+
+// Root of F, falling, in [lo, hi] by the Illinois variant of false position
+// (a retained end has its F halved, so both ends move; a step that leaves the
+// bracket bisects); the end itself when F(lo) <= 0 or F(hi) >= 0.  Stops at a
+// bracket of 1e-14 relative width or |F| at the rounding level `tiny` of the
+// CDF.  F takes and returns wave-uniform values.
+template <typename Fn>
+__device__ __forceinline__ double falling_root(Fn F, double lo, double hi, double tiny) {
+    double Flo = F(lo), Fhi = F(hi);
+    double z = Flo <= 0.0 ? lo : Fhi >= 0.0 ? hi : 0.5 * (lo + hi);
+    int kept = 0;   // +1: lo kept by the last step, -1: hi kept
+    for (int it = 0; it < 100 && Flo > 0.0 && Fhi < 0.0; ++it) {
+        double x = (lo * Fhi - hi * Flo) / (Fhi - Flo);
+        if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
+        const double Fx = F(x);
+        z = x;
+        if (Fx == 0.0 || hi - lo <= 1e-14 * fabs(x)) break;
+        if (Fx > 0.0) {
+            lo = x;
+            Flo = Fx;
+            if (kept == -1) Fhi *= 0.5;
+            kept = -1;
+        } else {
+            hi = x;
+            Fhi = Fx;
+            if (kept == 1) Flo *= 0.5;
+            kept = 1;
+        }
+        if (fabs(Fx) <= tiny) break;
+    }
+    return z;
+}
+
 // Partial correlation of (Y3, Y4) given Y2 for fractions r2 > r3 > r4:
 // (sqrt(r4/r3) - sqrt(r3/r2) sqrt(r4/r2)) / (s23 s24) = sqrt(r4 (r2 - r3) / (r3 (r2 - r4))).
 __host__ __device__ inline double qvn_partial_rho(double r2, double r3, double r4) {
@@ -318,6 +394,25 @@ __device__ __forceinline__ T qvn(T h1, T h2, T h3, T h4, const QvnConst<T, NMAX>
         }
     }
     return acc * width;
+}
+
+// Phi_4(h1, h2, h3, h4) in FP64 by the wavefront, the rule of qvn().
+template <int NMAX>
+__device__ __forceinline__ double qvn_wave(double h1, double h2, double h3, double h4,
+                                           const QvnConst<double, NMAX>& c, const PanelNode& nd) {
+    const double lo = -c.tail;
+    const double hi = fmin(fmin(fmin(h2, c.tail), (h1 + c.c1) * c.ir12),
+                           fmin((h3 + c.c3) * c.ir23, (h4 + c.c4) * c.ir24));
+    const double width = fmax(hi - lo, 0.0) / static_cast<double>(c.np);
+    double acc = 0.0;
+    for (int p = nd.p0; p < c.np; p += 64 / kNodes) {
+        const double y = fma(width, nd.px, fma(width, static_cast<double>(p), lo));
+        const double u1 = (h1 - c.r12 * y) * c.is12;
+        const double u3 = (h3 - c.r23 * y) * c.is23;
+        const double u4 = (h4 - c.r24 * y) * c.is24;
+        acc = fma(nd.pw * half_gauss(y) * qvn_cdf1(u1), qvn_cdf2<NMAX>(u3, u4, c), acc);
+    }
+    return wave_total(acc) * width;
 }
 
 }  // namespace bmd

@@ -17,12 +17,20 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_direct(EvalArgs<T> a) {
     direct_body<T, D, NMAX, VAR ? kSquares : kSums>(a, blockIdx.x, blockIdx.y);
 }
 
+// Tile of workgroup (x, y): the tiles of one draw slice lie along x, so every
+// XCD works on the slice whose draws its L2 holds.  Workgroups go to the XCDs
+// round-robin by linear index, and a row of tiles whose length is a multiple
+// of 8 would give XCD j the tiles x = j mod 8 in every slice; the tiles' costs
+// differ with their designs' node counts, which follow the grid axes, so the
+// tile is rotated by the slice index and each XCD gets every tile class.
+__device__ __forceinline__ unsigned sweep_tile() { return (blockIdx.x + blockIdx.y) % gridDim.x; }
+
 // FP32 with up to three biomarkers: at most 96 VGPRs, so that five wavefronts
 // share each SIMD (more axes would spill the node coefficients).
 template <typename T, int D, int NMAX, bool VAR>
 __global__ __launch_bounds__(kEvalBlock, sizeof(T) == 4 && D <= 3 ? 5 : 1) void k_eval_mfma(EvalArgs<T> a, MfmaGeom geo) {
     extern __shared__ __align__(16) char lds[];
-    mfma_tile_body<T, D, NMAX, VAR ? kSquares : kSums>(a, geo, blockIdx.x, blockIdx.y, lds);
+    mfma_tile_body<T, D, NMAX, VAR ? kSquares : kSums>(a, geo, sweep_tile(), blockIdx.y, lds);
 }
 
 // The same sweeps with the summands' derivatives in alpha_1 as second sums.
@@ -33,7 +41,7 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_direct_da(EvalArgs<T> a) {
 template <typename T, int D, int NMAX>
 __global__ __launch_bounds__(kEvalBlock) void k_eval_mfma_da(EvalArgs<T> a, MfmaGeom geo) {
     extern __shared__ __align__(16) char lds[];
-    mfma_tile_body<T, D, NMAX, kDAlpha>(a, geo, blockIdx.x, blockIdx.y, lds);
+    mfma_tile_body<T, D, NMAX, kDAlpha>(a, geo, sweep_tile(), blockIdx.y, lds);
 }
 
 // mean = sums / M in slice order; second: nothing (mode 0), the sample

@@ -710,7 +710,7 @@ def bench_smooth(args):
                                   f"{'x'.join(map(str, spec['m']))} grid surface (seeded synthetic), bandwidth "
                                   f"{spec['bandwidth'][0]}, {d} axis passes", "designs": G},
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
-                        "traffic": None, "kernel": "k_smooth_mfma<float> (one 16x16 output tile per wavefront)",
+                        "traffic": None, "kernel": "k_smooth_mfma<float, 2, 2> (axes 0-3) and k_smooth_rows<float, 2, 2> (last axis through LDS), 32 columns x all row blocks per wavefront",
                         "bytes_per_call": bytes_call,
                         "mfma": {"achieved": flops_call / (t32 * 1e-3) / 1e12, "peak": PEAK_MFMA_FP32_TFLOPS,
                                  "unit": "TFLOP/s", "flops_per_call": flops_call}},

@@ -90,6 +90,102 @@ __global__ __launch_bounds__(64) void k_smooth_mfma(const T* __restrict__ W, int
     }
 }
 
+// The pass along the last axis (inner = 1) with a short axis: the 16 CT
+// columns of a wavefront are consecutive rows of m values, one contiguous
+// block, which the lanes copy to LDS (row-padded to m + 1) with coalesced
+// loads; the matrix cores take their B operands from there, and the results
+// go back through the same LDS block to coalesced stores.  (Read straight
+// from the surface, each load of the 16 columns touches 16 rows m values
+// apart.)  Same products in the same order as k_smooth_mfma, so the results
+// are identical.
+constexpr int kRowsMaxM = 64;
+
+template <typename T, int NI, int CT>
+__global__ __launch_bounds__(64) void k_smooth_rows(const T* __restrict__ W, int m, const double* __restrict__ in,
+                                                    double* __restrict__ out, int64_t C) {
+    using acc_t = typename std::conditional<sizeof(T) == 8, mfma_d4, mfma_f4>::type;
+    extern __shared__ __align__(16) char smem[];
+    T* tile = reinterpret_cast<T*>(smem);   // [16 CT][m + 1]
+    const int lane = threadIdx.x;
+    const int r = lane & 15, kq = lane >> 4;
+    const int ld = m + 1;
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * 16 * CT;
+    const int ncol = static_cast<int>(min<int64_t>(16 * CT, C - c0));
+    const int n_el = ncol * m, n_all = 16 * CT * m;
+    const double* src = in + c0 * m;
+    const int q64 = 64 / m, r64 = 64 - (64 / m) * m;
+    {
+        int col = lane / m, h = lane - (lane / m) * m;
+        for (int e = lane; e < n_all; e += 64) {
+            tile[col * ld + h] = e < n_el ? static_cast<T>(src[e]) : T(0);
+            col += q64;
+            h += r64;
+            if (h >= m) {
+                h -= m;
+                ++col;
+            }
+        }
+    }
+    __syncthreads();
+    const int nblk = (m + 15) / 16;
+    const int b0 = blockIdx.y * NI;
+    acc_t acc[CT][NI];
+#pragma unroll
+    for (int t = 0; t < CT; ++t)
+#pragma unroll
+        for (int ib = 0; ib < NI; ++ib) acc[t][ib] = acc_t{0, 0, 0, 0};
+    for (int h0 = 0; h0 < m; h0 += 4) {
+        const int h = h0 + kq;
+        T bv[CT];
+#pragma unroll
+        for (int t = 0; t < CT; ++t) bv[t] = h < m ? tile[(t * 16 + r) * ld + h] : T(0);
+#pragma unroll
+        for (int ib = 0; ib < NI; ++ib) {
+            if (b0 + ib < nblk) {   // wave-uniform
+                const int i = (b0 + ib) * 16 + r;
+                const T a = (i < m && h < m) ? W[static_cast<int64_t>(i) * m + h] : T(0);
+#pragma unroll
+                for (int t = 0; t < CT; ++t) acc[t][ib] = mfma_step(a, bv[t], acc[t][ib]);
+            }
+        }
+    }
+    __syncthreads();   // every B operand is read before the block is overwritten
+#pragma unroll
+    for (int ib = 0; ib < NI; ++ib) {
+        if (b0 + ib < nblk) {
+#pragma unroll
+            for (int t = 0; t < CT; ++t) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int io = (b0 + ib) * 16 + mfma16_row<T>(kq, v);
+                    if (io < m) tile[(t * 16 + r) * ld + io] = acc[t][ib][v];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    double* dst = out + c0 * m;
+    {
+        int col = lane / m, h = lane - (lane / m) * m;
+        for (int e = lane; e < n_el; e += 64) {
+            dst[e] = static_cast<double>(tile[col * ld + h]);
+            col += q64;
+            h += r64;
+            if (h >= m) {
+                h -= m;
+                ++col;
+            }
+        }
+    }
+}
+
+template <typename T, int CT, int NI>
+void launch_smooth_rows(const T* W, int m, const double* in, double* out, int64_t C, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>((C + 16 * CT - 1) / (16 * CT)), 1);
+    const size_t lds = sizeof(T) * 16 * CT * static_cast<size_t>(m + 1);
+    hipLaunchKernelGGL((k_smooth_rows<T, NI, CT>), grid, dim3(64), lds, s, W, m, in, out, C);
+}
+
 template <typename T, int CT, int NI>
 void launch_smooth_group(const T* W, int m, const double* in, double* out, int64_t C, int64_t inner, hipStream_t s) {
     const int nblk = (m + 15) / 16;
@@ -109,6 +205,10 @@ void launch_smooth_pass(const T* W, int m, const double* in, double* out, int64_
     const int nblk = (m + 15) / 16;
     if ((C + 15) / 16 < 4096)
         launch_smooth_group<T, 1, 1>(W, m, in, out, C, inner, s);
+    else if (inner == 1 && m <= kRowsMaxM)   // all row blocks in one wavefront (nblk <= 4)
+        nblk <= 1   ? launch_smooth_rows<T, 2, 1>(W, m, in, out, C, s)
+        : nblk <= 2 ? launch_smooth_rows<T, 2, 2>(W, m, in, out, C, s)
+                    : launch_smooth_rows<T, 2, 4>(W, m, in, out, C, s);
     else if (nblk <= 1)
         launch_smooth_group<T, 2, 1>(W, m, in, out, C, inner, s);
     else if (nblk <= 2)

@@ -327,6 +327,36 @@ def test_full_size_smoothing_and_argmax(shape, seed):
             assert tuple(cell) == tuple(np.unravel_index(i, shape))
 
 
+@pytest.mark.parametrize("shape,seed", [((300, 220, 24), 21), ((300, 221, 21), 22), ((131, 509, 50), 23),
+                                        ((520, 130, 12), 24)])
+def test_smoothing_short_last_axis_many_columns(shape, seed):
+    """Surfaces whose last axis is short (12 to 50 points) under more than
+    65,536 columns: the last pass goes through the LDS-staged kernel, with one,
+    two or four row blocks and a ragged last group of columns (66,000,
+    66,300, 66,679 and 67,600 columns against groups of 32).  One seeded
+    synthetic surface on both sides: FP64 within 1e-13, FP32 within 2e-6 of the
+    oracle's separable smoother, argmax identical (FP64) or in the oracle's
+    tie set (FP32)."""
+    spec = W.base_problem(len(shape), list(shape), 0.3, 0.04)
+    raw_h = W.noisy_surface(shape, seed=seed)
+    ref = O.smooth_separable(spec, raw_h)
+    io = O.argmax(ref)
+    with bmd.Problem(spec) as p:
+        raw = torch.tensor(raw_h, dtype=torch.float64, device="cuda")
+        for prec in ("fp64", "fp32"):
+            say(f"smooth {shape} {prec}")
+            s = p.smooth(raw, prec)
+            i, v, cell = p.argmax(s)
+            s_h = s.cpu().numpy()
+            err = np.max(np.abs(s_h - ref))
+            if prec == "fp64":
+                assert err <= 1e-13, err
+                assert i == io, (i, io)
+            else:
+                assert err <= 2e-6 * np.max(np.abs(ref)), err
+                assert ref[i] >= ref[io] - 2e-6 * np.max(np.abs(ref)), (i, io)
+
+
 def test_full_3d_config_against_oracle():
     """3-D configuration (64^3, M = 1e5) in both precisions, FP32 as benchmarked:
       - the oracle on the 3^3 block around each precision's argmax at the full M,
@@ -396,282 +426,6 @@ def test_full_5d_subgrids_against_oracle(what):
     assert_close(m32[idx], ref_r, "fp32", f"5-D {what}")
     m64, _, _ = _gpu_full(spec, "fp64", Mr)
     assert_close(m64[idx], ref_r, "fp64", f"5-D {what}")
-
-
-@pytest.mark.parametrize("shape,rho", [((9, 7), 0.3), ((5, 6, 7), 0.3), ((3, 4, 3, 2), 0.45), ((3, 3, 3, 3, 3), 0.3),
-                                       ((2, 2, 2, 2, 2, 2), 0.5)])
-def test_multi_biomarker_small_grids(shape, rho):
-    spec = W.base_problem(len(shape), list(shape), rho, 0.05)
-    M = 1000 if len(shape) <= 3 else 300
-    _full_check(spec, M)
-
-
-@pytest.mark.parametrize("variant", ["bonferroni", "fixed", "fixed_off", "width", "paper", "null", "degenerate",
-                                     "wide_tau"])
-def test_variants(variant):
-    spec = W.base_problem(2, [6, 5], 0.2, 0.05)
-    if variant == "bonferroni":
-        spec["alpha_rule"] = "bonferroni"
-    elif variant == "fixed":
-        spec.update(alpha_rule="fixed", alpha_fixed=(0.015, 0.012))
-    elif variant == "fixed_off":
-        spec.update(alpha_rule="fixed", alpha_fixed=(0.025, 0.0))
-    elif variant == "width":
-        spec["width"] = 0.01
-    elif variant == "paper":
-        spec.update(effect="paper", paper_a=0.8, paper_b=0.6, paper_events=80.0, info=211.0)
-    elif variant == "null":
-        spec.update(mu_b0=0.0, sd_b0=0.0, mu_b1=0.0, sd_b1=0.0)
-    elif variant == "degenerate":
-        spec.update(sd_b0=0.0, sd_b1=0.0, tau_lo=0.45, tau_hi=0.45)
-    elif variant == "wide_tau":
-        spec.update(tau_lo=0.02, tau_hi=0.98, q_lo=0.1, q_hi=0.9)
-    ref = _full_check(spec, 700)
-    if variant == "null":
-        assert np.max(np.abs(ref - 0.025)) < 1e-14
-
-
-def test_one_biomarker_width_and_paper():
-    spec = W.plain_1d()
-    spec["width"] = 0.01
-    _full_check(spec, 3000)
-    spec = W.plain_1d()
-    spec.update(effect="paper", paper_a=0.25, paper_b=0.0, paper_events=80.0, info=127.0,
-                alpha_rule="fixed", alpha_fixed=(0.025, 0.0))
-    ref = _full_check(spec, 3000)
-    # the estimate stays within MC error of the paper's printed power 0.6847 (Sec. 3)
-    assert abs(ref[0] - 0.6847) < 0.0115
-
-
-@pytest.mark.parametrize("M", [1, 2, 63, 64, 65, 1000, 4097])
-def test_draw_counts_ragged(M):
-    spec = W.base_problem(3, [3, 5, 4], 0.3, 0.05)
-    G = O.grid_size(spec)
-    ref, _ = O.eval_grid(spec, np.arange(G), M)
-    for prec in ("fp64", "fp32"):
-        assert_close(gpu_eval(spec, M, prec), ref, prec, f"M={M}")
-
-
-def test_seed_and_scenario_change_results():
-    spec = W.base_problem(2, [4, 4], 0.3, 0.05)
-    a = gpu_eval(spec, 500, "fp64")
-    spec2 = dict(spec, seed=5)
-    b = gpu_eval(spec2, 500, "fp64")
-    ref_b, _ = O.eval_grid(spec2, np.arange(16), 500)
-    assert_close(b, ref_b, "fp64")
-    assert np.max(np.abs(a - b)) > 1e-4
-
-
-def test_bitwise_deterministic_reruns():
-    spec = W.base_problem(3, [6, 6, 6], 0.3, 0.05)
-    a = gpu_eval(spec, 3000, "fp32")
-    b = gpu_eval(spec, 3000, "fp32")
-    assert np.array_equal(a, b)
-
-
-# ------------------------------------------------------------ smoothing and argmax
-
-@pytest.mark.parametrize("spec", [W.plain_1d(), W.base_problem(3, [9, 8, 7], 0.3, 0.08),
-                                  W.base_problem(5, [5, 7, 3, 9, 4], 0.3, 0.1), W.base_problem(2, [40, 33], 0.2, 0.04)])
-def test_smooth_and_argmax_match_oracle(spec):
-    G = O.grid_size(spec)
-    raw_h = W.noisy_surface(spec["m"], seed=G)
-    with bmd.Problem(spec) as p:
-        raw = torch.tensor(raw_h, dtype=torch.float64, device="cuda")
-        s64 = p.smooth(raw, "fp64")
-        s32 = p.smooth(raw, "fp32")
-        i64, v64, cell = p.argmax(s64)
-        s64_h, s32_h = s64.cpu().numpy(), s32.cpu().numpy()
-    ref = O.smooth_separable(spec, raw_h)
-    assert np.max(np.abs(s64_h - ref)) <= 1e-13
-    assert np.max(np.abs(s32_h - ref)) <= 2e-6 * np.max(np.abs(ref))
-    if G <= 600:
-        assert np.max(np.abs(O.smooth_direct(spec, raw_h) - ref)) < 1e-13
-    io = O.argmax(ref)
-    assert i64 == io and v64 == pytest.approx(ref[io], abs=1e-13)
-    _, idx = O.grid_point(spec, io)
-    assert tuple(idx) == cell
-
-
-def test_argmax_ties_and_nan():
-    spec = W.base_problem(2, [40, 50], 0.3, 0.05)
-    with bmd.Problem(spec) as p:
-        v = torch.zeros(2000, dtype=torch.float64, device="cuda")
-        v[1234] = 2.0
-        v[777] = 2.0
-        v[5] = float("nan")
-        assert p.argmax(v)[:2] == (777, 2.0)
-        v.fill_(-1.0)
-        assert p.argmax(v)[0] == 0
-        v[1999] = 0.0
-        assert p.argmax(v)[0] == 1999
-
-
-# ------------------------------------------------------------ full-size configurations
-
-def _gpu_full(spec, prec, M):
-    """Whole grid at M draws on the GPU: raw surface, smoothed surface, argmax."""
-    with bmd.Problem(spec) as p:
-        say(f"full-size eval d={spec['d']} G={p.G} M={M} {prec}")
-        mean = p.eval_grid(M, prec)
-        s = p.smooth(mean, prec)
-        i, v, cell = p.argmax(s)
-        mean_h, s_h = mean.cpu().numpy(), s.cpu().numpy()
-    assert np.all(np.isfinite(mean_h)) and mean_h.min() >= 0.0 and mean_h.max() <= 1.0
-    assert v == s_h[i]
-    return mean_h, s_h, i
-
-
-def _block(spec, cell, radius=1, faces_only=False):
-    """Linear indices of the cells within `radius` of `cell` on every axis
-    (clipped at the grid's edges), or of the cell and its 2 d face neighbours."""
-    m = spec["m"]
-    if faces_only:
-        cells = [tuple(cell)]
-        for j in range(len(m)):
-            for s in (-1, 1):
-                c = list(cell)
-                c[j] += s
-                if 0 <= c[j] < m[j]:
-                    cells.append(tuple(c))
-    else:
-        axes = [range(max(0, c - radius), min(mj, c + radius + 1)) for c, mj in zip(cell, m)]
-        cells = list(np.array(np.meshgrid(*axes, indexing="ij")).reshape(len(m), -1).T)
-    return np.unique(np.array([np.ravel_multi_index(tuple(c), m) for c in cells], dtype=np.int64))
-
-
-def _strided(spec, step):
-    """Linear indices of the strided subgrid 0, step, 2 step, ... on every axis."""
-    m = spec["m"]
-    axes = [np.arange(0, mj, step) for mj in m]
-    cells = np.array(np.meshgrid(*axes, indexing="ij")).reshape(len(m), -1)
-    return np.ravel_multi_index(tuple(cells), m).astype(np.int64)
-
-
-def _in_tie_set(s_or, i, prec):
-    """The argmax rule: the GPU's cell is the oracle's, or inside the oracle's
-    near-tie set at the precision's tolerance."""
-    top = float(np.max(s_or))
-    return s_or[i] >= top - TOL[prec] * max(abs(top), 1e-3)
-
-
-def test_full_1d_config_against_oracle():
-    """1-D configuration as specified (201 cutoffs, M = 1e4): the oracle
-    evaluates every design, smooths its own surface and takes its argmax; the
-    GPU's raw surface must match element by element and its argmax must be the
-    oracle's (FP64) or inside the oracle's tie set (FP32)."""
-    spec = W.plain_1d()
-    M = spec["n_draws"]
-    ref, _ = O.eval_grid(spec, np.arange(O.grid_size(spec)), M)
-    s_or = O.smooth_separable(spec, ref)
-    io = O.argmax(s_or)
-    for prec in ("fp64", "fp32"):
-        mean, s, i = _gpu_full(spec, prec, M)
-        assert_close(mean, ref, prec, "1-D raw surface")
-        assert np.max(np.abs(s - s_or) / np.maximum(np.abs(s_or), 1e-3)) <= TOL[prec]
-        if prec == "fp64":
-            assert i == io or _in_tie_set(s_or, i, prec), (i, io)
-        else:
-            assert _in_tie_set(s_or, i, prec), (i, io, s_or[i], s_or[io])
-
-
-@pytest.mark.parametrize("shape,seed", [((64, 64, 64), 11), ((24, 24, 24, 24, 24), 12)])
-def test_full_size_smoothing_and_argmax(shape, seed):
-    """Smoothing and argmax at the 3-D and 5-D configurations' grid sizes (64^3,
-    24^5): one seeded synthetic surface goes to both sides; FP64 within 1e-13,
-    FP32 within 2e-6 of the oracle's separable smoother, argmax identical (FP64)
-    or in the oracle's tie set (FP32)."""
-    spec = W.base_problem(len(shape), list(shape), 0.3, 0.03)
-    raw_h = W.noisy_surface(shape, seed=seed)
-    ref = O.smooth_separable(spec, raw_h)
-    io = O.argmax(ref)
-    with bmd.Problem(spec) as p:
-        raw = torch.tensor(raw_h, dtype=torch.float64, device="cuda")
-        for prec in ("fp64", "fp32"):
-            say(f"smooth {shape} {prec}")
-            s = p.smooth(raw, prec)
-            i, v, cell = p.argmax(s)
-            s_h = s.cpu().numpy()
-            err = np.max(np.abs(s_h - ref))
-            if prec == "fp64":
-                assert err <= 1e-13, err
-                assert i == io, (i, io)
-            else:
-                assert err <= 2e-6 * np.max(np.abs(ref)), err
-                assert ref[i] >= ref[io] - 2e-6 * np.max(np.abs(ref)), (i, io)
-            assert tuple(cell) == tuple(np.unravel_index(i, shape))
-
-
-def test_full_3d_config_against_oracle():
-    """3-D configuration (64^3, M = 1e5) in both precisions, FP32 as benchmarked:
-      - the oracle on the 3^3 block around each precision's argmax at the full M;
-      - the oracle on the strided 16^3 subgrid (0, 4, ..., 60 per axis) at
-        M = 1,000 (the whole grid evaluated on the GPU at that M);
-      - the oracle on the whole grid at M = 16: its own smoothed surface's argmax
-        against the GPU's (identical in FP64, tie set in FP32);
-      - the FP32 surface against the FP64 surface within 1e-5 everywhere."""
-    spec = W.plain_3d()
-    M = spec["n_draws"]
-    full = {prec: _gpu_full(spec, prec, M) for prec in ("fp64", "fp32")}
-    cells = {prec: np.unravel_index(full[prec][2], spec["m"]) for prec in full}
-    blk = np.unique(np.concatenate([_block(spec, cells[prec]) for prec in full]))
-    say(f"oracle: {blk.size} designs around the argmax cells {cells} at M={M}")
-    ref, _ = O.eval_grid(spec, blk, M)
-    for prec in full:
-        assert_close(full[prec][0][blk], ref, prec, "3-D argmax block")
-        # the block's best raw design is the same on both sides
-        assert int(np.argmax(full[prec][0][blk])) == int(np.argmax(ref)) or \
-            np.max(ref) - ref[int(np.argmax(full[prec][0][blk]))] <= TOL[prec] * np.max(ref)
-    m64, s64, i64 = full["fp64"]
-    m32, s32, i32 = full["fp32"]
-    assert np.max(np.abs(m32 - m64)) <= 1e-5
-    assert np.max(np.abs(s32 - s64) / np.maximum(np.abs(s64), 1e-3)) <= 1e-5
-    assert s64[i32] >= s64.max() - 1e-5 * s64.max()
-
-    sub = _strided(spec, 4)
-    Ms = 1000
-    say(f"oracle: strided subgrid of {sub.size} designs at M={Ms}")
-    ref_s, _ = O.eval_grid(spec, sub, Ms)
-    for prec in ("fp64", "fp32"):
-        mean, _, _ = _gpu_full(spec, prec, Ms)
-        assert_close(mean[sub], ref_s, prec, "3-D strided subgrid")
-
-    Mt = 16
-    G = O.grid_size(spec)
-    say(f"oracle: whole grid of {G} designs at M={Mt}")
-    ref_t, _ = O.eval_grid(spec, np.arange(G), Mt)
-    s_or = O.smooth_separable(spec, ref_t)
-    io = O.argmax(s_or)
-    for prec in ("fp64", "fp32"):
-        mean, s, i = _gpu_full(spec, prec, Mt)
-        assert_close(mean, ref_t, prec, "3-D whole grid")
-        assert np.max(np.abs(s - s_or) / np.maximum(np.abs(s_or), 1e-3)) <= TOL[prec]
-        if prec == "fp64":
-            assert i == io or _in_tie_set(s_or, i, prec), (i, io)
-        else:
-            assert _in_tie_set(s_or, i, prec), (i, io)
-
-
-def test_full_5d_config_against_oracle():
-    """5-D precision configuration (24^5, M = 2e5, FP32 integrand as
-    benchmarked): the oracle on the argmax cell and its ten face neighbours at
-    the full M, on the 3^5 block around it at M = 10,000, and on the strided 4^5
-    subgrid (0, 6, 12, 18 per axis) at M = 2,000, in both precisions."""
-    spec = W.precision_5d()
-    M = spec["n_draws"]
-    m32, s32, i32 = _gpu_full(spec, "fp32", M)
-    cell = np.unravel_index(i32, spec["m"])
-    faces = _block(spec, cell, faces_only=True)
-    say(f"oracle: argmax cell {cell} and face neighbours ({faces.size}) at M={M}")
-    ref, _ = O.eval_grid(spec, faces, M)
-    assert_close(m32[faces], ref, "fp32", "5-D argmax faces")
-    for Mr, idx, what in ((10_000, _block(spec, cell), "5-D argmax block"),
-                          (2_000, _strided(spec, 6), "5-D strided subgrid")):
-        say(f"oracle: {what} of {idx.size} designs at M={Mr}")
-        ref_r, _ = O.eval_grid(spec, idx, Mr)
-        for prec in ("fp64", "fp32"):
-            mean, _, _ = _gpu_full(spec, prec, Mr)
-            assert_close(mean[idx], ref_r, prec, what)
 
 
 @pytest.mark.parametrize("shape,rho", [((9, 7), 0.3), ((17, 6, 33), 0.3), ((3, 5, 3, 4, 3), 0.45), ((2, 3, 2, 3, 2, 3), 0.5)])

@@ -568,3 +568,111 @@ def eval_grid_levels(prob, g_list, M, alphas):
             best[up] = m[up]
             best_k[up] = k
     return best, best_k
+
+
+# ---------------------------------------------------------------------------
+# Thin-plate spline fit of a grid surface (Sec. 2.3 fits a thin-plate spline
+# to the noisy estimates and maximises the fitted surface).  The spline of
+# order 2 in d dimensions (Duchon): f(u) = sum_i c_i phi(|u - u_i|) + a_0 +
+# sum_j a_j u_j, phi(r) = r^3 (d = 1), r^2 log r (d = 2), -r (d = 3), with the
+# coefficients of the smoothing system
+#   (Phi + lam I) c + P a = y,   P^T c = 0,   P = [1, u],
+# on the designs with a value (not NaN), their coordinates mapped to the unit
+# box of the grid (u_j = (q_j - lo_j) / (hi_j - lo_j)).  lam = 0 interpolates.
+# The system is solved as written, in one dense solve.
+# ---------------------------------------------------------------------------
+
+def _axis_range(prob, j):
+    if prob.get("design", "cutoffs") == "alpha" and int(prob["d"]) == 2 and j == 0:
+        return float(prob["r_lo"]), float(prob["r_hi"])
+    return float(prob["q_lo"]), float(prob["q_hi"])
+
+
+def tps_phi(d, r):
+    r = np.asarray(r, dtype=np.float64)
+    if d == 1:
+        return r ** 3
+    if d == 2:
+        with np.errstate(divide="ignore", invalid="ignore"):
+            return np.where(r > 0.0, r * r * np.log(np.where(r > 0.0, r, 1.0)), 0.0)
+    if d == 3:
+        return -r
+    raise ValueError("thin-plate splines are defined here for d = 1, 2, 3")
+
+
+def tps_unit(prob, q):
+    """Design coordinates q [n, d] mapped to the grid's unit box."""
+    d = int(prob["d"])
+    q = np.asarray(q, dtype=np.float64).reshape(-1, d)
+    lo = np.array([_axis_range(prob, j)[0] for j in range(d)])
+    hi = np.array([_axis_range(prob, j)[1] for j in range(d)])
+    return (q - lo) / (hi - lo)
+
+
+def tps_fit(prob, f, lam):
+    """Fit to the grid values f (NaN: no value); returns (centres [N, d] in
+    unit coordinates, c [N], a [d + 1])."""
+    d = int(prob["d"])
+    f = np.asarray(f, dtype=np.float64)
+    g = np.nonzero(~np.isnan(f))[0]
+    u = tps_unit(prob, grid_points(prob, g))
+    y = f[g]
+    n = len(g)
+    R = np.sqrt(((u[:, None, :] - u[None, :, :]) ** 2).sum(-1))
+    A = np.zeros((n + d + 1, n + d + 1))
+    A[:n, :n] = tps_phi(d, R) + lam * np.eye(n)
+    P = np.hstack([np.ones((n, 1)), u])
+    A[:n, n:] = P
+    A[n:, :n] = P.T
+    rhs = np.concatenate([y, np.zeros(d + 1)])
+    sol = np.linalg.solve(A, rhs)
+    return u, sol[:n], sol[n:]
+
+
+def tps_value(prob, fit, q):
+    """Fitted surface at design coordinates q [n, d]."""
+    u0, c, a = fit
+    d = int(prob["d"])
+    u = tps_unit(prob, q)
+    R = np.sqrt(((u[:, None, :] - u0[None, :, :]) ** 2).sum(-1))
+    return tps_phi(d, R) @ c + a[0] + u @ a[1:]
+
+
+def tps_derivatives(prob, fit, q):
+    """Value, gradient [d] and Hessian [d, d] in design coordinates at one q,
+    from phi's derivatives: with s = u - u_i, r = |s|, the gradient of
+    phi(r) is phi'(r) s / r and its Hessian phi'(r)/r I + (phi''(r) - phi'(r)/r)
+    s s^T / r^2; chain rule for u_j = (q_j - lo_j) / w_j.  Pinned by central
+    differences of tps_value, which scipy's interpolator pins."""
+    u0, c, a = fit
+    d = int(prob["d"])
+    w = np.array([_axis_range(prob, j)[1] - _axis_range(prob, j)[0] for j in range(d)])
+    u = tps_unit(prob, q)[0]
+    val = a[0] + u @ a[1:]
+    gu = a[1:].copy()
+    Hu = np.zeros((d, d))
+    for ci, ui in zip(c, u0):
+        s = u - ui
+        r = math.sqrt(float(s @ s))
+        val += ci * float(tps_phi(d, r))
+        if r == 0.0:   # at a centre its own term adds no derivative (r^2 log r's Hessian diverges, -r has a kink)
+            continue
+        if d == 1:
+            p1, p2 = 3 * r * r, 6 * r
+        elif d == 2:
+            p1, p2 = r * (2 * math.log(r) + 1), 2 * math.log(r) + 3
+        else:
+            p1, p2 = -1.0, 0.0
+        gu += ci * p1 * s / r
+        Hu += ci * (p1 / r * np.eye(d) + (p2 - p1 / r) * np.outer(s, s) / (r * r))
+    return float(val), gu / w, Hu / np.outer(w, w)
+
+
+def smooth_tps(prob, f, lam):
+    """The fitted surface at every grid design; NaN where f has no value."""
+    f = np.asarray(f, dtype=np.float64)
+    fit = tps_fit(prob, f, lam)
+    G = f.size
+    out = tps_value(prob, fit, grid_points(prob, np.arange(G)))
+    out[np.isnan(f)] = np.nan
+    return out

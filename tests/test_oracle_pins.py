@@ -1187,3 +1187,85 @@ def test_smoothed_surface_at_continuous_designs():
     s = W.noisy_surface([9, 9], seed=3).reshape(9, 9)
     s = (s + s.T).ravel()
     assert abs(O.smooth_at(spec, s, [0.3, 0.6]) - O.smooth_at(spec, s, [0.6, 0.3])) < 1e-14
+
+
+# ------------------------------------------------------------ thin-plate spline (Sec. 2.3)
+
+_TPS_KERNEL = {1: "cubic", 2: "thin_plate_spline", 3: "linear"}   # scipy's names for r^3, r^2 log r, -r
+
+
+@pytest.mark.parametrize("d,m", [(1, [40]), (2, [12, 9]), (3, [6, 5, 7])])
+@pytest.mark.parametrize("lam", [0.0, 1e-3, 0.1])
+def test_tps_matches_scipy_rbf(d, m, lam):
+    """The oracle's spline against scipy's radial-basis interpolator with the
+    same kernel, a linear polynomial and the same smoothing (it adds lam to the
+    kernel matrix's diagonal), on the unit-box coordinates."""
+    from scipy.interpolate import RBFInterpolator
+    spec = W.base_problem(d, m, 0.3, 0.05)
+    f = W.noisy_surface(m, seed=3)
+    fit = O.tps_fit(spec, f, lam)
+    q = O.grid_points(spec, np.arange(O.grid_size(spec)))
+    u = O.tps_unit(spec, q)
+    rng = np.random.default_rng(5)
+    qx = spec["q_lo"] + (spec["q_hi"] - spec["q_lo"]) * rng.random((50, d))
+    rbf = RBFInterpolator(u, f, kernel=_TPS_KERNEL[d], smoothing=lam, degree=1)
+    assert np.max(np.abs(O.tps_value(spec, fit, q) - rbf(u))) < 1e-10
+    assert np.max(np.abs(O.tps_value(spec, fit, qx) - rbf(O.tps_unit(spec, qx)))) < 1e-10
+
+
+@pytest.mark.parametrize("d,m", [(1, [30]), (2, [9, 11]), (3, [5, 6, 4])])
+def test_tps_interpolation_planes_and_least_squares(d, m):
+    """lam = 0 interpolates; a plane is reproduced exactly for any lam (the
+    polynomial part carries it, c = 0); a huge lam leaves the least-squares
+    plane."""
+    spec = W.base_problem(d, m, 0.3, 0.05)
+    G = O.grid_size(spec)
+    q = O.grid_points(spec, np.arange(G))
+    f = W.noisy_surface(m, seed=4)
+    assert np.max(np.abs(O.smooth_tps(spec, f, 0.0) - f)) < 1e-9
+    plane = 0.3 + q @ np.linspace(0.5, -0.7, d)
+    for lam in (0.0, 0.05, 10.0):
+        fit = O.tps_fit(spec, plane, lam)
+        assert np.max(np.abs(fit[1])) < 1e-9
+        assert np.max(np.abs(O.tps_value(spec, fit, q) - plane)) < 1e-12
+    u = O.tps_unit(spec, q)
+    X = np.hstack([np.ones((G, 1)), u])
+    ls = X @ np.linalg.lstsq(X, f, rcond=None)[0]
+    assert np.max(np.abs(O.smooth_tps(spec, f, 1e9) - ls)) < 1e-6
+
+
+def test_tps_skips_designs_without_a_value():
+    """Designs whose value is NaN stay NaN and do not enter the fit: the fit
+    equals scipy's on the designs that have a value."""
+    from scipy.interpolate import RBFInterpolator
+    spec = W.base_problem(2, [10, 12], 0.3, 0.05)
+    f = W.noisy_surface([10, 12], seed=6, nan_corner=5)
+    s = O.smooth_tps(spec, f, 0.01)
+    nan = np.isnan(f)
+    assert np.array_equal(np.isnan(s), nan) and nan.sum() > 0
+    u = O.tps_unit(spec, O.grid_points(spec, np.arange(f.size)))
+    rbf = RBFInterpolator(u[~nan], f[~nan], kernel="thin_plate_spline", smoothing=0.01, degree=1)
+    assert np.max(np.abs(s[~nan] - rbf(u[~nan]))) < 1e-10
+
+
+@pytest.mark.parametrize("d,m", [(1, [25]), (2, [9, 8]), (3, [5, 4, 6])])
+def test_tps_derivatives_by_central_differences(d, m):
+    """Gradient and Hessian in design coordinates against central differences
+    of the (scipy-pinned) value, away from the centres."""
+    spec = W.base_problem(d, m, 0.3, 0.05)
+    f = W.noisy_surface(m, seed=7)
+    fit = O.tps_fit(spec, f, 1e-3)
+    rng = np.random.default_rng(8)
+    w = spec["q_hi"] - spec["q_lo"]
+    for _ in range(5):
+        q = spec["q_lo"] + w * (0.1 + 0.8 * rng.random(d))
+        v, g, H = O.tps_derivatives(spec, fit, q)
+        assert abs(v - O.tps_value(spec, fit, q[None, :])[0]) < 1e-13
+        h = 1e-5 * w
+        for j in range(d):
+            e = np.zeros(d)
+            e[j] = h
+            vp = O.tps_derivatives(spec, fit, q + e)
+            vm = O.tps_derivatives(spec, fit, q - e)
+            assert abs((vp[0] - vm[0]) / (2 * h) - g[j]) < 1e-6 * max(1.0, np.abs(g).max())
+            assert np.max(np.abs((vp[1] - vm[1]) / (2 * h) - H[j])) < 1e-4 * max(1.0, np.abs(H).max())

@@ -451,6 +451,46 @@ bmd_status bmd_smooth_at(bmd_problem *p, const double *d_surface, const double *
 bmd_status bmd_refine_smoothed(bmd_problem *p, const double *d_surface, const double *h_q0, int32_t max_iter,
                                double tol, double *h_q, double *h_value, int32_t *h_iters, void *stream);
 
+/* Thin-plate spline smoothing of a grid surface (Sec. 2.3 fits a thin-plate
+ * spline to the noisy estimates and maximises the fitted surface).  The
+ * spline of order 2 in d = 1, 2, 3 dimensions on the grid's unit-box
+ * coordinates u_j = (q_j - lo_j) / (hi_j - lo_j):
+ *   f(u) = sum_i c_i phi(|u - u_i|) + a_0 + sum_j a_j u_j,
+ *   phi(r) = r^3 (d = 1), r^2 log r (d = 2), -r (d = 3),
+ * with centres at the designs whose value in d_in is not NaN and the
+ * coefficients of the smoothing system (Phi + lambda I) c + P a = y,
+ * P^T c = 0, P = [1, u] (lambda = 0 interpolates; larger values smooth, and
+ * lambda -> infinity leaves the least-squares plane).
+ *   d_in   [G] FP64 grid surface, NaN for designs without a value
+ *   lambda      >= 0, finite
+ *   d_out  [G] FP64 fitted surface at every design, NaN where d_in is NaN
+ *               (must not alias d_in)
+ *   h_n         number of designs fitted (may be NULL)
+ * FP64 on the device: Householder elimination of the polynomial block, a
+ * blocked Cholesky factorisation of the reduced (n - d - 1)^2 system, memory
+ * about 8 n^2 bytes, allocated for the call.  The fit (centres and
+ * coefficients) stays with the problem for bmd_tps_at and bmd_refine_tps until
+ * the next call or bmd_destroy_problem.  ENOTSUP for d > 3; ERANGE when fewer
+ * than d + 2 or more than 16,384 designs have a value, or when they do not
+ * determine the spline (all on one hyperplane); the previous fit is kept on
+ * any error.  Synchronises the stream. */
+bmd_status bmd_smooth_tps(bmd_problem *p, const double *d_in, double lambda, double *d_out, int64_t *h_n,
+                          void *stream);
+
+/* Value, gradient and Hessian of the last bmd_smooth_tps fit at the design
+ * h_q [d] (design coordinates; any finite point), as bmd_smooth_at: h_grad [d]
+ * and h_hess [d*d] may be NULL.  At a centre its own term adds nothing to the
+ * derivatives (r^2 log r's Hessian diverges there and -r has a kink).  FP64;
+ * ESTATE without a fit; synchronises the stream. */
+bmd_status bmd_tps_at(bmd_problem *p, const double *h_q, double *h_value, double *h_grad, double *h_hess,
+                      void *stream);
+
+/* Newton's method on the last bmd_smooth_tps fit from h_q0 (Sec. 2.3: the
+ * best point of the fitted spline, refined on it), with the steps, safeguards
+ * and stopping rules of bmd_refine_smoothed.  ESTATE without a fit. */
+bmd_status bmd_refine_tps(bmd_problem *p, const double *h_q0, int32_t max_iter, double tol, double *h_q,
+                          double *h_value, int32_t *h_iters, void *stream);
+
 /* Launch settings of bmd_eval_batch.  Each sweep launch of a batch runs one
  * kind of problem (d biomarkers; kind 1 the matrix-core tile sweep of grids
  * with d >= 2 under the step prior and the exact indicator, kind 0 the

@@ -630,12 +630,16 @@ def tps_fit(prob, f, lam):
 
 
 def tps_value(prob, fit, q):
-    """Fitted surface at design coordinates q [n, d]."""
+    """Fitted surface at design coordinates q [n, d] (in chunks of 512 points)."""
     u0, c, a = fit
     d = int(prob["d"])
     u = tps_unit(prob, q)
-    R = np.sqrt(((u[:, None, :] - u0[None, :, :]) ** 2).sum(-1))
-    return tps_phi(d, R) @ c + a[0] + u @ a[1:]
+    out = np.empty(len(u))
+    for s in range(0, len(u), 512):
+        us = u[s:s + 512]
+        R = np.sqrt(((us[:, None, :] - u0[None, :, :]) ** 2).sum(-1))
+        out[s:s + 512] = tps_phi(d, R) @ c + a[0] + us @ a[1:]
+    return out
 
 
 def tps_derivatives(prob, fit, q):

@@ -99,6 +99,12 @@ SIGNATURES = {
     "bmd_refine_smoothed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                            ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p]),
+    "bmd_smooth_tps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "bmd_tps_at": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p]),
+    "bmd_refine_tps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "bmd_batch_autotune": (ctypes.c_int, [ctypes.c_int32]),
     "bmd_batch_settings": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
     "bmd_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
@@ -303,6 +309,49 @@ class Problem:
                                              q0.ctypes.data_as(ctypes.c_void_p), int(max_iter), float(tol),
                                              q.ctypes.data_as(ctypes.c_void_p), ctypes.byref(val), ctypes.byref(it),
                                              _stream(stream)))
+        return q, float(val.value), int(it.value)
+
+    def smooth_tps(self, surface, lam: float, out=None, stream=None):
+        """Thin-plate spline fit of the surface's designs with a value and the
+        fitted surface at every design (bmd_smooth_tps): returns (surface,
+        designs fitted).  The fit stays with the problem for tps_at and
+        refine_tps."""
+        import torch
+        _device_buffer(surface, self.G, self.device, "surface")
+        res = _device_buffer(out, self.G, self.device, "out") if out is not None else torch.empty_like(surface)
+        if res.data_ptr() == surface.data_ptr():
+            raise ValueError("out must not alias surface")
+        n = ctypes.c_int64()
+        _check(library().bmd_smooth_tps(self._h, ctypes.c_void_p(surface.data_ptr()), float(lam),
+                                        ctypes.c_void_p(res.data_ptr()), ctypes.byref(n), _stream(stream)))
+        return res, int(n.value)
+
+    def tps_at(self, q, stream=None):
+        """The last thin-plate fit at the design q: (value, gradient [d],
+        Hessian [d, d]) (bmd_tps_at)."""
+        qq = np.ascontiguousarray(np.asarray(q, dtype=np.float64).ravel())
+        if qq.size != self.d:
+            raise ValueError(f"q has {qq.size} coordinates, the problem {self.d}")
+        val = ctypes.c_double()
+        grad = np.zeros(self.d)
+        hess = np.zeros((self.d, self.d))
+        _check(library().bmd_tps_at(self._h, qq.ctypes.data_as(ctypes.c_void_p), ctypes.byref(val),
+                                    grad.ctypes.data_as(ctypes.c_void_p), hess.ctypes.data_as(ctypes.c_void_p),
+                                    _stream(stream)))
+        return float(val.value), grad, hess
+
+    def refine_tps(self, q0, max_iter: int = 50, tol: float = 1e-9, stream=None):
+        """Newton refinement on the last thin-plate fit from q0 (bmd_refine_tps):
+        returns (design, fitted value, steps)."""
+        q0 = np.ascontiguousarray(np.asarray(q0, dtype=np.float64).ravel())
+        if q0.size != self.d:
+            raise ValueError(f"q0 has {q0.size} coordinates, the problem {self.d}")
+        q = np.zeros(self.d)
+        val = ctypes.c_double()
+        it = ctypes.c_int32()
+        _check(library().bmd_refine_tps(self._h, q0.ctypes.data_as(ctypes.c_void_p), int(max_iter), float(tol),
+                                        q.ctypes.data_as(ctypes.c_void_p), ctypes.byref(val), ctypes.byref(it),
+                                        _stream(stream)))
         return q, float(val.value), int(it.value)
 
     def grad_design(self, q, n_draws: int, precision="fp32", want_grad=True, stream=None):

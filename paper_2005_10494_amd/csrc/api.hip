@@ -343,6 +343,7 @@ void free_problem(bmd_problem* p) {
     f(p->d_Wf);
     f(p->d_ws);
     f(p->d_ws2);
+    tps_release(p);
     for (auto& e : p->ev)
         if (e) (void)hipEventDestroy(e);
     delete p;
@@ -1511,13 +1512,18 @@ bmd_status bmd_smooth_at(bmd_problem* p, const double* d_surface, const double* 
     return smoothed_at(p, d_surface, h_q, h_value, h_grad, h_hess, static_cast<hipStream_t>(stream));
 }
 
-bmd_status bmd_refine_smoothed(bmd_problem* p, const double* d_surface, const double* h_q0, int32_t max_iter,
-                               double tol, double* h_q, double* h_value, int32_t* h_iters, void* stream) {
-    g_err.clear();
-    if (!p) return fail(BMD_EINVAL, "problem is NULL");
-    if (!p->grid) return fail(BMD_ESTATE, "refine_smoothed needs a grid problem");
-    if (!d_surface || !h_q0 || !h_q || !h_value || !h_iters) return fail(BMD_EINVAL, "NULL pointer argument");
-    if (max_iter < 0 || max_iter > 10000 || !(tol >= 0.0)) return fail(BMD_ERANGE, "max_iter or tol out of range");
+extern "C++" {
+namespace {
+
+// Ascent on a deterministic surface from q0 (value, gradient and Hessian from
+// eval(q, &f, g, H)): a Newton step where -H has a Cholesky factor, else a
+// gradient step of a tenth of the smallest smoothing bandwidth; each step
+// projected into the grid's box and halved until it gains the Armijo fraction
+// 1e-4 of its first-order gain.  Stops after max_iter steps, when a step moves
+// no coordinate by more than tol, or when no halving is accepted.
+template <typename Eval>
+bmd_status newton_ascent(bmd_problem* p, Eval eval, const double* h_q0, int32_t max_iter, double tol, double* h_q,
+                         double* h_value, int32_t* h_iters) {
     const int d = p->P.d;
     double lo[kMaxDim], hi[kMaxDim], bmin = 1e300;
     for (int j = 0; j < d; ++j) {
@@ -1525,17 +1531,13 @@ bmd_status bmd_refine_smoothed(bmd_problem* p, const double* d_surface, const do
         if (!std::isfinite(h_q0[j])) return fail(BMD_EINVAL, "q0[%d] is not finite", j);
         bmin = std::min(bmin, p->desc.bandwidth[j]);
     }
-    DeviceGuard guard(p->device);
-    hipStream_t s = static_cast<hipStream_t>(stream);
     constexpr double kArmijo = 1e-4;
     double q[kMaxDim], g[kMaxDim], H[kMaxDim * kMaxDim], f = 0.0;
     for (int j = 0; j < d; ++j) q[j] = std::min(hi[j], std::max(lo[j], h_q0[j]));
-    bmd_status st = smoothed_at(p, d_surface, q, &f, g, H, s);
+    bmd_status st = eval(q, &f, g, H);
     if (st != BMD_OK) return st;
     int it = 0;
     while (it < max_iter) {
-        // Newton direction where the surface is locally concave, else the
-        // gradient scaled to a tenth of the smallest bandwidth
         double dir[kMaxDim];
         if (!newton_direction(d, H, g, dir)) {
             double gn = 0.0;
@@ -1551,7 +1553,7 @@ bmd_status bmd_refine_smoothed(bmd_problem* p, const double* d_surface, const do
                 qn[j] = std::min(hi[j], std::max(lo[j], q[j] + t * dir[j]));
                 slope += g[j] * (qn[j] - q[j]);
             }
-            st = smoothed_at(p, d_surface, qn, &fn, gnext, Hn, s);
+            st = eval(qn, &fn, gnext, Hn);
             if (st != BMD_OK) return st;
             ok = fn >= f + kArmijo * slope && slope >= 0.0;
         }
@@ -1571,6 +1573,101 @@ bmd_status bmd_refine_smoothed(bmd_problem* p, const double* d_surface, const do
     *h_value = f;
     *h_iters = it;
     return BMD_OK;
+}
+
+// Value, gradient and Hessian of the problem's thin-plate spline fit at the
+// design q (design coordinates); synchronises the stream.
+bmd_status tps_at_design(bmd_problem* p, const double* q, double* S, double* g, double* H, hipStream_t s) {
+    const int d = p->P.d;
+    double u[kMaxDim], w[kMaxDim];
+    for (int j = 0; j < d; ++j) {
+        double lo, hi;
+        axis_range(p->desc, j, &lo, &hi);
+        w[j] = hi - lo;
+        u[j] = (q[j] - lo) / w[j];
+    }
+    bmd_status st = ensure(&p->d_ws2, &p->ws2_cap, 16 * sizeof(double));
+    if (st != BMD_OK) return st;
+    double h[16];
+    const hipError_t e = tps_at_unit(p, u, static_cast<double*>(p->d_ws2), h, s);
+    if (e != hipSuccess) return fail(BMD_EDEVICE, "thin-plate spline at a point: %s", hipGetErrorString(e));
+    *S = h[0];
+    int k = 1 + d;
+    for (int j = 0; j < d; ++j) {
+        if (g) g[j] = h[1 + j] / w[j];
+        for (int l = j; l < d; ++l, ++k)
+            if (H) H[j * d + l] = H[l * d + j] = h[k] / (w[j] * w[l]);
+    }
+    return BMD_OK;
+}
+
+}  // namespace
+}  // extern "C++"
+
+bmd_status bmd_refine_smoothed(bmd_problem* p, const double* d_surface, const double* h_q0, int32_t max_iter,
+                               double tol, double* h_q, double* h_value, int32_t* h_iters, void* stream) {
+    g_err.clear();
+    if (!p) return fail(BMD_EINVAL, "problem is NULL");
+    if (!p->grid) return fail(BMD_ESTATE, "refine_smoothed needs a grid problem");
+    if (!d_surface || !h_q0 || !h_q || !h_value || !h_iters) return fail(BMD_EINVAL, "NULL pointer argument");
+    if (max_iter < 0 || max_iter > 10000 || !(tol >= 0.0)) return fail(BMD_ERANGE, "max_iter or tol out of range");
+    DeviceGuard guard(p->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto eval = [&](const double* q, double* f, double* g, double* H) {
+        return smoothed_at(p, d_surface, q, f, g, H, s);
+    };
+    return newton_ascent(p, eval, h_q0, max_iter, tol, h_q, h_value, h_iters);
+}
+
+bmd_status bmd_smooth_tps(bmd_problem* p, const double* d_in, double lambda, double* d_out, int64_t* h_n,
+                          void* stream) {
+    g_err.clear();
+    if (h_n) *h_n = 0;
+    if (!p) return fail(BMD_EINVAL, "problem is NULL");
+    if (!p->grid) return fail(BMD_ESTATE, "thin-plate smoothing needs a grid problem");
+    if (p->P.d > 3) return fail(BMD_ENOTSUP, "thin-plate splines are built for d = 1, 2, 3 (d = %d)", p->P.d);
+    if (!d_in || !d_out) return fail(BMD_EINVAL, "NULL d_in or d_out");
+    if (d_in == d_out) return fail(BMD_EINVAL, "d_out must not alias d_in");
+    if (!std::isfinite(lambda) || lambda < 0.0) return fail(BMD_ERANGE, "lambda must be finite and >= 0");
+    DeviceGuard guard(p->device);
+    const TpsFitResult r = tps_fit_grid(p, d_in, lambda, d_out, static_cast<hipStream_t>(stream));
+    if (h_n) *h_n = r.n;
+    switch (r.code) {
+        case kTpsOk: return BMD_OK;
+        case kTpsCount:
+            return fail(BMD_ERANGE, "%lld designs have a value; the thin-plate fit needs %d to %lld",
+                        static_cast<long long>(r.n), p->P.d + 2, static_cast<long long>(kTpsMaxPoints));
+        case kTpsSingular:
+            return fail(BMD_ERANGE, "the designs with a value do not determine the thin-plate spline "
+                                    "(they lie on a hyperplane, or the reduced system is not positive definite)");
+        case kTpsNoMem: return fail(BMD_ENOMEM, "thin-plate fit of %lld designs", static_cast<long long>(r.n));
+        default: return fail(BMD_EDEVICE, "thin-plate fit: %s", hipGetErrorString(r.err));
+    }
+}
+
+bmd_status bmd_tps_at(bmd_problem* p, const double* h_q, double* h_value, double* h_grad, double* h_hess,
+                      void* stream) {
+    g_err.clear();
+    if (!p) return fail(BMD_EINVAL, "problem is NULL");
+    if (!h_q || !h_value) return fail(BMD_EINVAL, "NULL pointer argument");
+    if (tps_dims(p) == 0) return fail(BMD_ESTATE, "no thin-plate fit: call bmd_smooth_tps first");
+    for (int j = 0; j < p->P.d; ++j)
+        if (!std::isfinite(h_q[j])) return fail(BMD_EINVAL, "q[%d] is not finite", j);
+    DeviceGuard guard(p->device);
+    return tps_at_design(p, h_q, h_value, h_grad, h_hess, static_cast<hipStream_t>(stream));
+}
+
+bmd_status bmd_refine_tps(bmd_problem* p, const double* h_q0, int32_t max_iter, double tol, double* h_q,
+                          double* h_value, int32_t* h_iters, void* stream) {
+    g_err.clear();
+    if (!p) return fail(BMD_EINVAL, "problem is NULL");
+    if (!h_q0 || !h_q || !h_value || !h_iters) return fail(BMD_EINVAL, "NULL pointer argument");
+    if (tps_dims(p) == 0) return fail(BMD_ESTATE, "no thin-plate fit: call bmd_smooth_tps first");
+    if (max_iter < 0 || max_iter > 10000 || !(tol >= 0.0)) return fail(BMD_ERANGE, "max_iter or tol out of range");
+    DeviceGuard guard(p->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto eval = [&](const double* q, double* f, double* g, double* H) { return tps_at_design(p, q, f, g, H, s); };
+    return newton_ascent(p, eval, h_q0, max_iter, tol, h_q, h_value, h_iters);
 }
 
 bmd_status bmd_eval_batch(bmd_problem* const* ps, int32_t n, const uint64_t* n_draws, int32_t prec,

@@ -107,6 +107,8 @@ struct PrecTables {
     void* glw = nullptr;        // packed GL weights in T
 };
 
+struct TpsFit;   // thin-plate spline fit of a problem's surface (kernels_tps.hip)
+
 }  // namespace bmd
 
 // Opaque handle of the C ABI.
@@ -139,6 +141,7 @@ struct bmd_problem {
     bool profiling = false;
     hipEvent_t ev[10] = {};          // begin/end pairs per profiled phase
     bool ev_used[5] = {false, false, false, false, false};
+    bmd::TpsFit* tps = nullptr;      // the last bmd_smooth_tps fit (centres and coefficients on the device)
 };
 
 namespace bmd {
@@ -162,6 +165,24 @@ hipError_t launch_three_precompute(const bmd_problem* p, hipStream_t s);
 // the sweep's launch order of every design, and the grid sweep.
 constexpr int64_t kNested3MaxTiles = 65535;   // sweep tiles of kEvalBlock designs (grid y dimension)
 hipError_t launch_nested3_precompute(const bmd_problem* p, hipStream_t s);
+// Thin-plate spline of a grid surface (kernels_tps.hip): fit on the designs
+// with a value and, when d_out is given, the fitted surface at every design
+// (NaN where d_in is NaN); the fit replaces p->tps on success.  code: kTpsOk,
+// kTpsCount (n outside [d + 2, kTpsMaxPoints]), kTpsSingular (the designs do
+// not determine the spline), kTpsNoMem, kTpsHip (err).  Synchronises s.
+constexpr int64_t kTpsMaxPoints = 16384;
+enum { kTpsOk = 0, kTpsCount = 1, kTpsSingular = 2, kTpsNoMem = 3, kTpsHip = 4 };
+struct TpsFitResult {
+    int code;
+    int64_t n;
+    hipError_t err;
+};
+TpsFitResult tps_fit_grid(bmd_problem* p, const double* d_in, double lam, double* d_out, hipStream_t s);
+// Value, gradient and Hessian (rows j <= l) of the fit in unit-box coordinates
+// u: h_out [1 + d + d (d + 1) / 2]; d_scratch holds 16 doubles.  Synchronises s.
+hipError_t tps_at_unit(const bmd_problem* p, const double* u, double* d_scratch, double* h_out, hipStream_t s);
+void tps_release(bmd_problem* p);
+int tps_dims(const bmd_problem* p);   // 0 without a fit
 int nested3_blocks_per_cu(int prec);
 hipError_t launch_eval_nested3(const bmd_problem* p, int prec, int64_t M, const void* ws, double* partials,
                                int n_slices, int64_t slice_len, bool want_var, hipStream_t s);

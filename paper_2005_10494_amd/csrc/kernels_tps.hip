@@ -1,0 +1,636 @@
+// Thin-plate spline smoothing of a grid surface (Sec. 2.3: the Monte Carlo
+// estimates are fitted by a thin-plate spline, whose maximum is then refined).
+// The spline of order 2 in d = 1..3 dimensions,
+//   f(u) = sum_i c_i phi(|u - u_i|) + a_0 + a^T u,
+//   phi(r) = r^3 (d = 1), r^2 log r (d = 2), -r (d = 3),
+// on the designs with a value, their coordinates in the grid's unit box
+// (u_j = i_j / (m_j - 1)), with the coefficients of the smoothing system
+//   (Phi + lam I) c + P a = y,   P^T c = 0,   P = [1, u].
+// The polynomial block is eliminated with the QR factors of P: d + 1
+// Householder reflectors give Q^T P = [R; 0]; with c = Q [0; w] the reduced
+// matrix M22 of M = Q^T (Phi + lam I) Q is positive definite when the designs
+// determine a plane, so w solves M22 w = z2 (z = Q^T y) by a blocked Cholesky
+// factorisation, and R a = z1 - M12 w.  FP64 throughout.
+#include <cmath>
+
+#include "bmd_internal.hpp"
+
+namespace bmd {
+
+struct TpsFit {
+    int64_t n = 0;              // centres
+    int d = 0;
+    double* mem = nullptr;      // device: U [n d], c [n], a [d + 1]
+};
+
+namespace {
+
+constexpr int kNB = 32;          // Cholesky and triangular-solve block
+constexpr int kUT = 64;          // trailing-update tile (kUT x kUT outputs per workgroup)
+
+// The radial function for D dimensions, fixed at compile time: with the
+// dimension chosen at run time inside one function, the gfx950 code of an
+// earlier build skipped the -r branch for D = 3 and stored the unnegated
+// square root (NaN at r = 0), so every kernel that evaluates phi is a
+// template on D.
+template <int D>
+__device__ __forceinline__ double tps_phi(double r) {
+    if constexpr (D == 1) return r * r * r;
+    else if constexpr (D == 2) return r > 0.0 ? r * r * log(r) : 0.0;
+    else return -r;
+}
+
+// Unit-box coordinates of grid design g.
+__device__ __forceinline__ void unit_coords(const DevProblem& P, int64_t g, double* u) {
+    int64_t rem = g;
+    for (int j = 0; j < P.d; ++j) {
+        const int64_t i = rem / P.stride[j];
+        rem -= i * P.stride[j];
+        u[j] = static_cast<double>(i) / static_cast<double>(P.m[j] - 1);
+    }
+}
+
+__device__ double block_sum(double v, double* red) {
+    const int t = threadIdx.x, nt = blockDim.x;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    __syncthreads();
+    if ((t & 63) == 0) red[t >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < nt / 64; ++w) s += red[w];   // same order on every thread
+    return s;
+}
+
+// Designs with a value, in index order (one workgroup of 1024: a scan per
+// tile); their count goes to *n_out.
+__global__ __launch_bounds__(1024) void k_tps_compact(int64_t G, const double* __restrict__ f,
+                                                      int64_t* __restrict__ idx, int64_t* __restrict__ n_out) {
+    __shared__ int scan[1024];
+    const int t = threadIdx.x;
+    int64_t base = 0;
+    for (int64_t g0 = 0; g0 < G; g0 += 1024) {
+        const int64_t g = g0 + t;
+        const int ok = g < G && f[g] == f[g];
+        scan[t] = ok;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int v = t >= off ? scan[t - off] : 0;
+            __syncthreads();
+            scan[t] += v;
+            __syncthreads();
+        }
+        if (ok) idx[base + scan[t] - 1] = g;
+        base += scan[1023];
+        __syncthreads();
+    }
+    if (t == 0) *n_out = base;
+}
+
+// Centres U [n d], values y [n] and the polynomial block P [n][d + 1].
+__global__ void k_tps_points(DevProblem P, int64_t n, const int64_t* __restrict__ idx, const double* __restrict__ f,
+                             double* __restrict__ U, double* __restrict__ y, double* __restrict__ Pm) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double u[kMaxDim];
+    unit_coords(P, idx[i], u);
+    const int d = P.d;
+    Pm[i * (d + 1)] = 1.0;
+    for (int j = 0; j < d; ++j) {
+        U[i * d + j] = u[j];
+        Pm[i * (d + 1) + 1 + j] = u[j];
+    }
+    y[i] = f[idx[i]];
+}
+
+// A = Phi + lam I (n x n, row-major).
+template <int D>
+__global__ void k_tps_matrix(int64_t n, const double* __restrict__ U, double lam, double* __restrict__ A) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t i = blockIdx.y;
+    if (k >= n) return;
+    double r2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const double s = U[i * D + j] - U[k * D + j];
+        r2 = fma(s, s, r2);
+    }
+    A[i * n + k] = tps_phi<D>(sqrt(r2)) + (i == k ? lam : 0.0);
+}
+
+// Householder QR of P [n][d + 1] (one workgroup): reflector k is
+// I - tau_k v_k v_k^T with v_k zero above row k; R [(d+1)^2] upper
+// triangular.  A column whose remaining norm is below 1e-12 of its first
+// norm raises *bad (the designs do not determine a plane).
+__global__ __launch_bounds__(1024) void k_tps_qr(int64_t n, int d, double* __restrict__ Pm, double* __restrict__ V,
+                                                 double* __restrict__ tau, double* __restrict__ R,
+                                                 int* __restrict__ bad) {
+    __shared__ double red[16];
+    const int t = threadIdx.x;
+    const int np = d + 1;
+    for (int k = 0; k < np; ++k) {
+        double s = 0.0, s0 = 0.0;
+        for (int64_t i = t; i < n; i += blockDim.x) {
+            const double x = Pm[i * np + k];
+            s0 = fma(x, x, s0);
+            if (i >= k) s = fma(x, x, s);
+        }
+        const double sigma2 = block_sum(s, red);
+        const double full2 = block_sum(s0, red);
+        const double xk = Pm[k * np + k];
+        const double sigma = sqrt(sigma2);
+        const double alpha = xk >= 0.0 ? -sigma : sigma;
+        if (!(sigma > 1e-12 * sqrt(full2)) && t == 0) *bad = 1;
+        const double vk = xk - alpha;
+        const double vnorm2 = sigma2 - xk * xk + vk * vk;
+        const double tk = vnorm2 > 0.0 ? 2.0 / vnorm2 : 0.0;
+        for (int64_t i = t; i < n; i += blockDim.x) V[i * np + k] = i < k ? 0.0 : i == k ? vk : Pm[i * np + k];
+        if (t == 0) {
+            tau[k] = tk;
+            R[k * np + k] = alpha;
+        }
+        __syncthreads();
+        for (int j = k + 1; j < np; ++j) {
+            double dj = 0.0;
+            for (int64_t i = t + k; i < n; i += blockDim.x) dj = fma(V[i * np + k], Pm[i * np + j], dj);
+            const double sj = block_sum(dj, red) * tk;
+            for (int64_t i = t + k; i < n; i += blockDim.x) Pm[i * np + j] -= sj * V[i * np + k];
+            __syncthreads();
+            if (t == 0) R[k * np + j] = Pm[k * np + j];
+        }
+        if (t < k && t < np) R[k * np + t] = 0.0;
+        __syncthreads();
+    }
+}
+
+// p = tau_k A v_k, one workgroup per row.
+__global__ __launch_bounds__(256) void k_tps_gemv(int64_t n, int np, int k, const double* __restrict__ A,
+                                                  const double* __restrict__ V, const double* __restrict__ tau,
+                                                  double* __restrict__ p) {
+    __shared__ double red[4];
+    const int64_t i = blockIdx.x;
+    double s = 0.0;
+    for (int64_t j = threadIdx.x + k; j < n; j += blockDim.x) s = fma(A[i * n + j], V[j * np + k], s);
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) p[i] = tau[k] * s;
+}
+
+// K = tau_k / 2 v_k^T p (one workgroup).
+__global__ __launch_bounds__(1024) void k_tps_kappa(int64_t n, int np, int k, const double* __restrict__ V,
+                                                    const double* __restrict__ tau, const double* __restrict__ p,
+                                                    double* __restrict__ kappa) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x + k; i < n; i += blockDim.x) s = fma(V[i * np + k], p[i], s);
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) *kappa = 0.5 * tau[k] * s;
+}
+
+// A <- H A H = A - v w^T - w v^T with w = p - K v.
+__global__ void k_tps_rank2(int64_t n, int np, int k, const double* __restrict__ V, const double* __restrict__ p,
+                            const double* __restrict__ kappa, double* __restrict__ A) {
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t i = blockIdx.y;
+    if (j >= n) return;
+    const double K = *kappa;
+    const double vi = V[i * np + k], vj = V[j * np + k];
+    const double wi = p[i] - K * vi, wj = p[j] - K * vj;
+    A[i * n + j] -= vi * wj + wi * vj;
+}
+
+// Cholesky of the kNB x kNB diagonal block at (o + kb, o + kb) (one
+// workgroup); a pivot <= 0 raises *bad.
+__global__ __launch_bounds__(256) void k_chol_diag(int64_t n, int64_t o, int64_t kb, int bs, double* __restrict__ A,
+                                                   int* __restrict__ bad) {
+    __shared__ double L[kNB][kNB + 1];
+    const int t = threadIdx.x;
+    for (int e = t; e < bs * bs; e += blockDim.x) L[e / bs][e % bs] = A[(o + kb + e / bs) * n + o + kb + e % bs];
+    __syncthreads();
+    for (int j = 0; j < bs; ++j) {
+        if (t == 0) {
+            const double pv = L[j][j];
+            if (!(pv > 0.0)) *bad = 1;
+            L[j][j] = pv > 0.0 ? sqrt(pv) : 1.0;
+        }
+        __syncthreads();
+        if (t > j && t < bs) L[t][j] /= L[j][j];
+        __syncthreads();
+        for (int e = t; e < bs * bs; e += blockDim.x) {
+            const int r = e / bs, c = e % bs;
+            if (c > j && r >= c) L[r][c] -= L[r][j] * L[c][j];
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < bs * bs; e += blockDim.x) {
+        const int r = e / bs, c = e % bs;
+        if (c <= r) A[(o + kb + r) * n + o + kb + c] = L[r][c];
+    }
+}
+
+// Panel below the diagonal block: L21 = A21 L11^-T, one thread per row.
+__global__ __launch_bounds__(256) void k_chol_panel(int64_t n, int64_t o, int64_t kb, int bs, int64_t n2,
+                                                    double* __restrict__ A) {
+    __shared__ double L[kNB][kNB + 1];
+    const int t = threadIdx.x;
+    for (int e = t; e < bs * bs; e += blockDim.x) L[e / bs][e % bs] = A[(o + kb + e / bs) * n + o + kb + e % bs];
+    __syncthreads();
+    const int64_t r = kb + bs + static_cast<int64_t>(blockIdx.x) * blockDim.x + t;
+    if (r >= n2) return;
+    double* row = A + (o + r) * n + o + kb;
+    double x[kNB];
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) {
+        if (c < bs) {
+            double s = row[c];
+#pragma unroll
+            for (int e = 0; e < kNB; ++e)
+                if (e < c) s -= x[e] * L[c][e];
+            x[c] = s / L[c][c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kNB; ++c)
+        if (c < bs) row[c] = x[c];
+}
+
+// Trailing update A22 -= L21 L21^T on the lower triangle, kUT x kUT output
+// tiles (256 threads, 4 x 4 outputs each); tiles above the diagonal leave.
+__global__ __launch_bounds__(256) void k_chol_update(int64_t n, int64_t o, int64_t kb, int bs, int64_t n2,
+                                                     double* __restrict__ A) {
+    const int64_t t0 = kb + bs;
+    const int64_t ti = blockIdx.y, tk = blockIdx.x;
+    if (tk > ti) return;
+    __shared__ double Li[kUT][kNB + 1], Lk[kUT][kNB + 1];
+    const int t = threadIdx.x;
+    const int64_t i0 = t0 + ti * kUT, k0 = t0 + tk * kUT;
+    for (int e = t; e < kUT * kNB; e += 256) {
+        const int r = e / kNB, c = e % kNB;
+        Li[r][c] = (i0 + r < n2 && c < bs) ? A[(o + i0 + r) * n + o + kb + c] : 0.0;
+        Lk[r][c] = (k0 + r < n2 && c < bs) ? A[(o + k0 + r) * n + o + kb + c] : 0.0;
+    }
+    __syncthreads();
+    const int ri = (t / 16) * 4, rk = (t % 16) * 4;
+    double acc[4][4] = {};
+    for (int c = 0; c < kNB; ++c) {
+        double a[4], b[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a[q] = Li[ri + q][c];
+            b[q] = Lk[rk + q][c];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc[q][s] = fma(a[q], b[s], acc[q][s]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int64_t i = i0 + ri + q, k = k0 + rk + s;
+            if (i < n2 && k <= i) A[(o + i) * n + o + k] -= acc[q][s];
+        }
+}
+
+// z = Q^T y = H_d ... H_0 y (one workgroup).
+__global__ __launch_bounds__(1024) void k_tps_qty(int64_t n, int np, const double* __restrict__ V,
+                                                  const double* __restrict__ tau, const double* __restrict__ y,
+                                                  double* __restrict__ z) {
+    __shared__ double red[16];
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) z[i] = y[i];
+    __syncthreads();
+    for (int k = 0; k < np; ++k) {
+        double s = 0.0;
+        for (int64_t i = threadIdx.x + k; i < n; i += blockDim.x) s = fma(V[i * np + k], z[i], s);
+        s = block_sum(s, red) * tau[k];
+        for (int64_t i = threadIdx.x + k; i < n; i += blockDim.x) z[i] -= s * V[i * np + k];
+        __syncthreads();
+    }
+}
+
+// M22 w = z2 with M22 = L L^T: forward then backward substitution by blocks of
+// kNB rows (one workgroup; the block's own rows solved by one wavefront, the
+// remaining rows updated by all threads).  w overwrites z2 = z [o, n).
+__global__ __launch_bounds__(1024) void k_tps_solve(int64_t n, int64_t o, int64_t n2, const double* __restrict__ A,
+                                                    double* __restrict__ z) {
+    __shared__ double xb[kNB];
+    __shared__ double Lb[kNB][kNB + 1];
+    double* b = z + o;
+    const int t = threadIdx.x;
+    for (int64_t kb = 0; kb < n2; kb += kNB) {   // L t = b
+        const int bs = static_cast<int>(min<int64_t>(kNB, n2 - kb));
+        for (int e = t; e < bs * bs; e += blockDim.x) Lb[e / bs][e % bs] = A[(o + kb + e / bs) * n + o + kb + e % bs];
+        __syncthreads();
+        if (t == 0) {
+            for (int r = 0; r < bs; ++r) {
+                double s = b[kb + r];
+                for (int c = 0; c < r; ++c) s -= Lb[r][c] * xb[c];
+                xb[r] = s / Lb[r][r];
+            }
+        }
+        __syncthreads();
+        if (t < bs) b[kb + t] = xb[t];
+        for (int64_t r = kb + bs + t; r < n2; r += blockDim.x) {
+            double s = 0.0;
+            const double* row = A + (o + r) * n + o + kb;
+            for (int c = 0; c < bs; ++c) s = fma(row[c], xb[c], s);
+            b[r] -= s;
+        }
+        __syncthreads();
+    }
+    const int64_t last = ((n2 - 1) / kNB) * kNB;
+    for (int64_t kb = last; kb >= 0; kb -= kNB) {   // L^T w = t
+        const int bs = static_cast<int>(min<int64_t>(kNB, n2 - kb));
+        for (int e = t; e < bs * bs; e += blockDim.x) Lb[e / bs][e % bs] = A[(o + kb + e / bs) * n + o + kb + e % bs];
+        __syncthreads();
+        if (t == 0) {
+            for (int r = bs - 1; r >= 0; --r) {
+                double s = b[kb + r];
+                for (int c = r + 1; c < bs; ++c) s -= Lb[c][r] * xb[c];
+                xb[r] = s / Lb[r][r];
+            }
+        }
+        __syncthreads();
+        if (t < bs) b[kb + t] = xb[t];
+        for (int64_t r = t; r < kb; r += blockDim.x) {
+            double s = 0.0;
+            for (int c = 0; c < bs; ++c) s = fma(A[(o + kb + c) * n + o + r], xb[c], s);
+            b[r] -= s;
+        }
+        __syncthreads();
+    }
+}
+
+// c = Q [0; w] = H_0 ... H_d [0; w] and R a = z1 - M12 w; writes c and a into
+// the fit (one workgroup).
+__global__ __launch_bounds__(1024) void k_tps_coeffs(int64_t n, int np, const double* __restrict__ A,
+                                                     const double* __restrict__ V, const double* __restrict__ tau,
+                                                     const double* __restrict__ R, const double* __restrict__ z,
+                                                     double* __restrict__ c, double* __restrict__ a) {
+    __shared__ double red[16];
+    __shared__ double rhs[kMaxDim + 1];
+    const int t = threadIdx.x;
+    for (int k = 0; k < np; ++k) {   // z1_k - sum_j M[k][np + j] w_j
+        double s = 0.0;
+        for (int64_t j = np + t; j < n; j += blockDim.x) s = fma(A[k * n + j], z[j], s);
+        s = block_sum(s, red);
+        if (t == 0) rhs[k] = z[k] - s;
+    }
+    for (int64_t i = t; i < n; i += blockDim.x) c[i] = i < np ? 0.0 : z[i];
+    __syncthreads();
+    for (int k = np - 1; k >= 0; --k) {
+        double s = 0.0;
+        for (int64_t i = t + k; i < n; i += blockDim.x) s = fma(V[i * np + k], c[i], s);
+        s = block_sum(s, red) * tau[k];
+        for (int64_t i = t + k; i < n; i += blockDim.x) c[i] -= s * V[i * np + k];
+        __syncthreads();
+    }
+    if (t == 0) {
+        for (int k = np - 1; k >= 0; --k) {
+            double s = rhs[k];
+            for (int j = k + 1; j < np; ++j) s -= R[k * np + j] * a[j];
+            a[k] = s / R[k * np + k];
+        }
+    }
+}
+
+// The fitted surface at every grid design (NaN where f has no value).
+template <int D>
+__global__ void k_tps_eval_grid(DevProblem P, int64_t n, const double* __restrict__ U, const double* __restrict__ c,
+                                const double* __restrict__ a, const double* __restrict__ f, double* __restrict__ out) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= P.G) return;
+    if (f[g] != f[g]) {
+        out[g] = f[g];
+        return;
+    }
+    double u[kMaxDim];
+    unit_coords(P, g, u);
+    double v = a[0];
+#pragma unroll
+    for (int j = 0; j < D; ++j) v = fma(a[1 + j], u[j], v);
+    for (int64_t i = 0; i < n; ++i) {
+        double r2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const double s = u[j] - U[i * D + j];
+            r2 = fma(s, s, r2);
+        }
+        v = fma(c[i], tps_phi<D>(sqrt(r2)), v);
+    }
+    out[g] = v;
+}
+
+// Value, gradient and Hessian in unit coordinates at u (one workgroup):
+// out = [value, grad (d), Hessian rows j <= l (d (d + 1) / 2)].  At a centre
+// its own term adds no derivative (r^2 log r's Hessian diverges there, -r has
+// a kink).
+template <int D>
+__global__ __launch_bounds__(1024) void k_tps_at(int64_t n, const double* __restrict__ U, const double* __restrict__ c,
+                                                 const double* __restrict__ a, double u0, double u1, double u2,
+                                                 double* __restrict__ out) {
+    constexpr int NA = 1 + D + D * (D + 1) / 2;
+    __shared__ double red[16];
+    const double u[3] = {u0, u1, u2};
+    double acc[NA] = {};
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        double s[D], r2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            s[j] = u[j] - U[i * D + j];
+            r2 = fma(s[j], s[j], r2);
+        }
+        const double r = sqrt(r2);
+        acc[0] = fma(c[i], tps_phi<D>(r), acc[0]);
+        if (r == 0.0) continue;
+        double p1, p2;   // phi'(r), phi''(r)
+        if constexpr (D == 1) {
+            p1 = 3.0 * r * r;
+            p2 = 6.0 * r;
+        } else if constexpr (D == 2) {
+            p1 = r * (2.0 * log(r) + 1.0);
+            p2 = 2.0 * log(r) + 3.0;
+        } else {
+            p1 = -1.0;
+            p2 = 0.0;
+        }
+        const double g1 = c[i] * p1 / r, g2 = c[i] * (p2 - p1 / r) / r2;
+        int k = 1 + D;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            acc[1 + j] = fma(g1, s[j], acc[1 + j]);
+#pragma unroll
+            for (int l = j; l < D; ++l, ++k) acc[k] += g2 * s[j] * s[l] + (j == l ? g1 : 0.0);
+        }
+    }
+    double poly = a[0];
+#pragma unroll
+    for (int j = 0; j < D; ++j) poly = fma(a[1 + j], u[j], poly);
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+        const double v = block_sum(acc[q], red);
+        if (threadIdx.x == 0) out[q] = v + (q == 0 ? poly : q <= D ? a[q] : 0.0);
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+void tps_release(bmd_problem* p) {
+    if (!p || !p->tps) return;
+    if (p->tps->mem) (void)hipFree(p->tps->mem);
+    delete p->tps;
+    p->tps = nullptr;
+}
+
+#define TPS_TRY(expr)                \
+    do {                             \
+        res.err = (expr);            \
+        if (res.err != hipSuccess) { \
+            res.code = kTpsHip;      \
+            goto done;               \
+        }                            \
+    } while (0)
+
+TpsFitResult tps_fit_grid(bmd_problem* p, const double* d_in, double lam, double* d_out, hipStream_t s) {
+    const DevProblem& P = p->P;
+    const int d = P.d, np = d + 1;
+    const int64_t G = P.G;
+    TpsFitResult res{kTpsOk, 0, hipSuccess};
+    int64_t n = 0, n2 = 0, o = 0;
+    int bad = 0;
+    char* small = nullptr;   // idx [G], n, bad flag; tau, R, kappa
+    double* big = nullptr;   // A [n n], V and P [n (d + 1)], y, z, p [n]
+    double* fitmem = nullptr;
+    int64_t* d_idx = nullptr;
+    int64_t* d_n = nullptr;
+    int* d_bad = nullptr;
+    double *d_tau = nullptr, *d_R = nullptr, *d_kappa = nullptr;
+    double *A = nullptr, *V = nullptr, *Pm = nullptr, *y = nullptr, *z = nullptr, *pv = nullptr;
+    double *U = nullptr, *c = nullptr, *a = nullptr;
+    const size_t small_bytes = sizeof(int64_t) * (G + 2) + 64 + sizeof(double) * (2 * np + np * np + 8);
+    if (hipMalloc(&small, small_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        res.code = kTpsNoMem;
+        return res;
+    }
+    d_idx = reinterpret_cast<int64_t*>(small);
+    d_n = d_idx + G;
+    d_bad = reinterpret_cast<int*>(d_n + 1);
+    d_tau = reinterpret_cast<double*>(small + sizeof(int64_t) * (G + 2) + 64);
+    d_R = d_tau + np;
+    d_kappa = d_R + np * np;
+    TPS_TRY(hipMemsetAsync(d_bad, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_tps_compact, dim3(1), dim3(1024), 0, s, G, d_in, d_idx, d_n);
+    TPS_TRY(hipGetLastError());
+    TPS_TRY(hipMemcpyAsync(&n, d_n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    TPS_TRY(hipStreamSynchronize(s));
+    res.n = n;
+    if (n < d + 2 || n > kTpsMaxPoints) {
+        res.code = kTpsCount;
+        goto done;
+    }
+    {
+        const size_t nn = static_cast<size_t>(n);
+        const size_t big_count = nn * nn + 2 * nn * np + 3 * nn;
+        if (hipMalloc(&big, sizeof(double) * big_count) != hipSuccess ||
+            hipMalloc(&fitmem, sizeof(double) * (nn * d + nn + np)) != hipSuccess) {
+            (void)hipGetLastError();
+            res.code = kTpsNoMem;
+            goto done;
+        }
+        A = big;
+        V = A + nn * nn;
+        Pm = V + nn * np;
+        y = Pm + nn * np;
+        z = y + nn;
+        pv = z + nn;
+        U = fitmem;
+        c = U + nn * d;
+        a = c + nn;
+    }
+    hipLaunchKernelGGL(k_tps_points, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, P, n, d_idx, d_in,
+                       U, y, Pm);
+    TPS_TRY(hipGetLastError());
+    {
+        const dim3 grid(static_cast<unsigned>((n + 255) / 256), static_cast<unsigned>(n));
+        if (d == 1) hipLaunchKernelGGL(k_tps_matrix<1>, grid, dim3(256), 0, s, n, U, lam, A);
+        else if (d == 2) hipLaunchKernelGGL(k_tps_matrix<2>, grid, dim3(256), 0, s, n, U, lam, A);
+        else hipLaunchKernelGGL(k_tps_matrix<3>, grid, dim3(256), 0, s, n, U, lam, A);
+    }
+    TPS_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_tps_qr, dim3(1), dim3(1024), 0, s, n, d, Pm, V, d_tau, d_R, d_bad);
+    TPS_TRY(hipGetLastError());
+    for (int k = 0; k < np; ++k) {   // M = Q^T A Q, one reflector at a time from both sides
+        hipLaunchKernelGGL(k_tps_gemv, dim3(static_cast<unsigned>(n)), dim3(256), 0, s, n, np, k, A, V, d_tau, pv);
+        hipLaunchKernelGGL(k_tps_kappa, dim3(1), dim3(1024), 0, s, n, np, k, V, d_tau, pv, d_kappa);
+        hipLaunchKernelGGL(k_tps_rank2, dim3(static_cast<unsigned>((n + 255) / 256), static_cast<unsigned>(n)),
+                           dim3(256), 0, s, n, np, k, V, pv, d_kappa, A);
+        TPS_TRY(hipGetLastError());
+    }
+    o = np;
+    n2 = n - np;
+    for (int64_t kb = 0; kb < n2; kb += kNB) {   // M22 = L L^T
+        const int bs = static_cast<int>(std::min<int64_t>(kNB, n2 - kb));
+        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, n, o, kb, bs, A, d_bad);
+        const int64_t rest = n2 - kb - bs;
+        if (rest > 0) {
+            hipLaunchKernelGGL(k_chol_panel, dim3(static_cast<unsigned>((rest + 255) / 256)), dim3(256), 0, s, n, o, kb,
+                               bs, n2, A);
+            const unsigned tiles = static_cast<unsigned>((rest + kUT - 1) / kUT);
+            hipLaunchKernelGGL(k_chol_update, dim3(tiles, tiles), dim3(256), 0, s, n, o, kb, bs, n2, A);
+        }
+        TPS_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_tps_qty, dim3(1), dim3(1024), 0, s, n, np, V, d_tau, y, z);
+    hipLaunchKernelGGL(k_tps_solve, dim3(1), dim3(1024), 0, s, n, o, n2, A, z);
+    hipLaunchKernelGGL(k_tps_coeffs, dim3(1), dim3(1024), 0, s, n, np, A, V, d_tau, d_R, z, c, a);
+    TPS_TRY(hipGetLastError());
+    TPS_TRY(hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    TPS_TRY(hipStreamSynchronize(s));
+    if (bad) {
+        res.code = kTpsSingular;
+        goto done;
+    }
+    if (d_out) {
+        const dim3 grid(static_cast<unsigned>((G + 255) / 256));
+        if (d == 1) hipLaunchKernelGGL(k_tps_eval_grid<1>, grid, dim3(256), 0, s, P, n, U, c, a, d_in, d_out);
+        else if (d == 2) hipLaunchKernelGGL(k_tps_eval_grid<2>, grid, dim3(256), 0, s, P, n, U, c, a, d_in, d_out);
+        else hipLaunchKernelGGL(k_tps_eval_grid<3>, grid, dim3(256), 0, s, P, n, U, c, a, d_in, d_out);
+        TPS_TRY(hipGetLastError());
+    }
+    TPS_TRY(hipStreamSynchronize(s));
+    tps_release(p);
+    p->tps = new TpsFit;
+    p->tps->n = n;
+    p->tps->d = d;
+    p->tps->mem = fitmem;
+    fitmem = nullptr;
+done:
+    (void)hipStreamSynchronize(s);
+    if (fitmem) (void)hipFree(fitmem);
+    if (big) (void)hipFree(big);
+    (void)hipFree(small);
+    return res;
+}
+
+hipError_t tps_at_unit(const bmd_problem* p, const double* u, double* d_scratch, double* h_out, hipStream_t s) {
+    const TpsFit& F = *p->tps;
+    const int d = F.d;
+    const double* U = F.mem;
+    const double* c = U + F.n * d;
+    const double* a = c + F.n;
+    const double u1 = d > 1 ? u[1] : 0.0, u2 = d > 2 ? u[2] : 0.0;
+    if (d == 1) hipLaunchKernelGGL(k_tps_at<1>, dim3(1), dim3(1024), 0, s, F.n, U, c, a, u[0], u1, u2, d_scratch);
+    else if (d == 2) hipLaunchKernelGGL(k_tps_at<2>, dim3(1), dim3(1024), 0, s, F.n, U, c, a, u[0], u1, u2, d_scratch);
+    else hipLaunchKernelGGL(k_tps_at<3>, dim3(1), dim3(1024), 0, s, F.n, U, c, a, u[0], u1, u2, d_scratch);
+    hipError_t e = hipGetLastError();
+    const int na = 1 + d + d * (d + 1) / 2;
+    if (e == hipSuccess) e = hipMemcpyAsync(h_out, d_scratch, sizeof(double) * na, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
+}
+
+int tps_dims(const bmd_problem* p) { return p->tps ? p->tps->d : 0; }
+
+}  // namespace bmd

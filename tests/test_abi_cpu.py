@@ -114,6 +114,9 @@ def test_null_arguments():
     assert lib.bmd_eval_grid_dalpha(None, 10, 0, None, None, None) == -1
     assert lib.bmd_eval_grid_two_layer(None, 1024, 4096, 0, 16, 16, None, None, None) == -1
     assert lib.bmd_optimize_levels_newton(None, 10, 0, 0.001, 0.02, 5, 1e-10, None, None, None) == -1
+    assert lib.bmd_smooth_tps(None, None, 0.0, None, None, None) == -1
+    assert lib.bmd_tps_at(None, None, None, None, None, None) == -1
+    assert lib.bmd_refine_tps(None, None, 5, 1e-9, None, None, None, None) == -1
     lib.bmd_destroy_problem(None)  # NULL-safe
 
 

@@ -199,31 +199,37 @@ __global__ void k_tps_rank2(int64_t n, int np, int k, const double* __restrict__
 }
 
 // Cholesky of the kNB x kNB diagonal block at (o + kb, o + kb) (one
-// workgroup); a pivot <= 0 raises *bad.
-__global__ __launch_bounds__(256) void k_chol_diag(int64_t n, int64_t o, int64_t kb, int bs, double* __restrict__ A,
-                                                   int* __restrict__ bad) {
-    __shared__ double L[kNB][kNB + 1];
+// wavefront; lane r holds row r in registers): per column j every lane takes
+// the pivot's square root by a shuffle, lanes below it scale their element of
+// column j, and each updates its row to the diagonal with the other lanes'
+// column-j elements, also by shuffles.  A pivot <= 0 raises *bad.
+__global__ __launch_bounds__(64) void k_chol_diag(int64_t n, int64_t o, int64_t kb, int bs, double* __restrict__ A,
+                                                  int* __restrict__ bad) {
     const int t = threadIdx.x;
-    for (int e = t; e < bs * bs; e += blockDim.x) L[e / bs][e % bs] = A[(o + kb + e / bs) * n + o + kb + e % bs];
-    __syncthreads();
-    for (int j = 0; j < bs; ++j) {
-        if (t == 0) {
-            const double pv = L[j][j];
-            if (!(pv > 0.0)) *bad = 1;
-            L[j][j] = pv > 0.0 ? sqrt(pv) : 1.0;
+    double row[kNB];
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) row[c] = (t < bs && c <= t) ? A[(o + kb + t) * n + o + kb + c] : 0.0;
+    bool neg = false;
+#pragma unroll
+    for (int j = 0; j < kNB; ++j) {
+        if (j < bs) {   // wave-uniform
+            const double pv = __shfl(row[j], j);
+            neg |= !(pv > 0.0);
+            const double dj = pv > 0.0 ? sqrt(pv) : 1.0;
+            const double lrj = (t > j) ? row[j] / dj : (t == j ? dj : row[j]);
+            row[j] = lrj;
+#pragma unroll
+            for (int c = j + 1; c < kNB; ++c) {
+                const double lcj = __shfl(lrj, c);   // column j of row c
+                if (t >= c) row[c] -= lrj * lcj;
+            }
         }
-        __syncthreads();
-        if (t > j && t < bs) L[t][j] /= L[j][j];
-        __syncthreads();
-        for (int e = t; e < bs * bs; e += blockDim.x) {
-            const int r = e / bs, c = e % bs;
-            if (c > j && r >= c) L[r][c] -= L[r][j] * L[c][j];
-        }
-        __syncthreads();
     }
-    for (int e = t; e < bs * bs; e += blockDim.x) {
-        const int r = e / bs, c = e % bs;
-        if (c <= r) A[(o + kb + r) * n + o + kb + c] = L[r][c];
+    if (t == 0 && neg) *bad = 1;
+    if (t < bs) {
+#pragma unroll
+        for (int c = 0; c < kNB; ++c)
+            if (c <= t) A[(o + kb + t) * n + o + kb + c] = row[c];
     }
 }
 
@@ -308,56 +314,53 @@ __global__ __launch_bounds__(1024) void k_tps_qty(int64_t n, int np, const doubl
     }
 }
 
-// M22 w = z2 with M22 = L L^T: forward then backward substitution by blocks of
-// kNB rows (one workgroup; the block's own rows solved by one wavefront, the
-// remaining rows updated by all threads).  w overwrites z2 = z [o, n).
-__global__ __launch_bounds__(1024) void k_tps_solve(int64_t n, int64_t o, int64_t n2, const double* __restrict__ A,
-                                                    double* __restrict__ z) {
-    __shared__ double xb[kNB];
+// M22 w = z2 with M22 = L L^T, by blocks of kNB rows: the block's own rows
+// by one wavefront (lane l holds row l; column by column, each solved value
+// broadcast and subtracted from the rows below it, or above it for L^T), then
+// the remaining rows updated by the whole GPU.  w overwrites z2 = z [o, n).
+__global__ __launch_bounds__(64) void k_trsv_diag(int64_t n, int64_t o, int64_t kb, int bs, bool upper,
+                                                  const double* __restrict__ A, double* __restrict__ b) {
     __shared__ double Lb[kNB][kNB + 1];
-    double* b = z + o;
-    const int t = threadIdx.x;
-    for (int64_t kb = 0; kb < n2; kb += kNB) {   // L t = b
-        const int bs = static_cast<int>(min<int64_t>(kNB, n2 - kb));
-        for (int e = t; e < bs * bs; e += blockDim.x) Lb[e / bs][e % bs] = A[(o + kb + e / bs) * n + o + kb + e % bs];
-        __syncthreads();
-        if (t == 0) {
-            for (int r = 0; r < bs; ++r) {
-                double s = b[kb + r];
-                for (int c = 0; c < r; ++c) s -= Lb[r][c] * xb[c];
-                xb[r] = s / Lb[r][r];
-            }
+    const int l = threadIdx.x;
+    for (int e = l; e < bs * bs; e += 64) Lb[e / bs][e % bs] = A[(o + kb + e / bs) * n + o + kb + e % bs];
+    __syncthreads();
+    double x = l < bs ? b[kb + l] : 0.0;
+    if (!upper) {
+        for (int r = 0; r < bs; ++r) {   // L x = b
+            const double xr = __shfl(x, r) / Lb[r][r];
+            if (l == r) x = xr;
+            if (l > r && l < bs) x -= Lb[l][r] * xr;
         }
-        __syncthreads();
-        if (t < bs) b[kb + t] = xb[t];
-        for (int64_t r = kb + bs + t; r < n2; r += blockDim.x) {
-            double s = 0.0;
-            const double* row = A + (o + r) * n + o + kb;
-            for (int c = 0; c < bs; ++c) s = fma(row[c], xb[c], s);
-            b[r] -= s;
+    } else {
+        for (int r = bs - 1; r >= 0; --r) {   // L^T x = b
+            const double xr = __shfl(x, r) / Lb[r][r];
+            if (l == r) x = xr;
+            if (l < r) x -= Lb[r][l] * xr;
         }
-        __syncthreads();
     }
-    const int64_t last = ((n2 - 1) / kNB) * kNB;
-    for (int64_t kb = last; kb >= 0; kb -= kNB) {   // L^T w = t
-        const int bs = static_cast<int>(min<int64_t>(kNB, n2 - kb));
-        for (int e = t; e < bs * bs; e += blockDim.x) Lb[e / bs][e % bs] = A[(o + kb + e / bs) * n + o + kb + e % bs];
-        __syncthreads();
-        if (t == 0) {
-            for (int r = bs - 1; r >= 0; --r) {
-                double s = b[kb + r];
-                for (int c = r + 1; c < bs; ++c) s -= Lb[c][r] * xb[c];
-                xb[r] = s / Lb[r][r];
-            }
-        }
-        __syncthreads();
-        if (t < bs) b[kb + t] = xb[t];
-        for (int64_t r = t; r < kb; r += blockDim.x) {
-            double s = 0.0;
-            for (int c = 0; c < bs; ++c) s = fma(A[(o + kb + c) * n + o + r], xb[c], s);
-            b[r] -= s;
-        }
-        __syncthreads();
+    if (l < bs) b[kb + l] = x;
+}
+
+// Rows outside the block: b[r] -= L[r][kb..] x (forward, rows below) or
+// b[r] -= L[kb..][r]^T x (backward, rows above), one thread per row.
+__global__ __launch_bounds__(256) void k_trsv_update(int64_t n, int64_t o, int64_t kb, int bs, int64_t n2, bool upper,
+                                                     const double* __restrict__ A, double* __restrict__ b) {
+    __shared__ double xb[kNB];
+    if (threadIdx.x < bs) xb[threadIdx.x] = b[kb + threadIdx.x];
+    __syncthreads();
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (!upper) {
+        const int64_t r = kb + bs + t;
+        if (r >= n2) return;
+        const double* row = A + (o + r) * n + o + kb;
+        for (int c = 0; c < bs; ++c) s = fma(row[c], xb[c], s);
+        b[r] -= s;
+    } else {
+        const int64_t r = t;
+        if (r >= kb) return;
+        for (int c = 0; c < bs; ++c) s = fma(A[(o + kb + c) * n + o + r], xb[c], s);
+        b[r] -= s;
     }
 }
 
@@ -394,22 +397,23 @@ __global__ __launch_bounds__(1024) void k_tps_coeffs(int64_t n, int np, const do
     }
 }
 
-// The fitted surface at every grid design (NaN where f has no value).
+// The fitted surface at every grid design (NaN where f has no value), one
+// wavefront per design: the lanes take every 64th centre, a butterfly sums.
 template <int D>
-__global__ void k_tps_eval_grid(DevProblem P, int64_t n, const double* __restrict__ U, const double* __restrict__ c,
-                                const double* __restrict__ a, const double* __restrict__ f, double* __restrict__ out) {
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= P.G) return;
+__global__ __launch_bounds__(256) void k_tps_eval_grid(DevProblem P, int64_t n, const double* __restrict__ U,
+                                                       const double* __restrict__ c, const double* __restrict__ a,
+                                                       const double* __restrict__ f, double* __restrict__ out) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= P.G) return;   // wave-uniform
     if (f[g] != f[g]) {
-        out[g] = f[g];
+        if (lane == 0) out[g] = f[g];
         return;
     }
     double u[kMaxDim];
     unit_coords(P, g, u);
-    double v = a[0];
-#pragma unroll
-    for (int j = 0; j < D; ++j) v = fma(a[1 + j], u[j], v);
-    for (int64_t i = 0; i < n; ++i) {
+    double v = 0.0;
+    for (int64_t i = lane; i < n; i += 64) {
         double r2 = 0.0;
 #pragma unroll
         for (int j = 0; j < D; ++j) {
@@ -418,7 +422,14 @@ __global__ void k_tps_eval_grid(DevProblem P, int64_t n, const double* __restric
         }
         v = fma(c[i], tps_phi<D>(sqrt(r2)), v);
     }
-    out[g] = v;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) {
+        double poly = a[0];
+#pragma unroll
+        for (int j = 0; j < D; ++j) poly = fma(a[1 + j], u[j], poly);
+        out[g] = poly + v;
+    }
 }
 
 // Value, gradient and Hessian in unit coordinates at u (one workgroup):
@@ -572,7 +583,7 @@ TpsFitResult tps_fit_grid(bmd_problem* p, const double* d_in, double lam, double
     n2 = n - np;
     for (int64_t kb = 0; kb < n2; kb += kNB) {   // M22 = L L^T
         const int bs = static_cast<int>(std::min<int64_t>(kNB, n2 - kb));
-        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, n, o, kb, bs, A, d_bad);
+        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(64), 0, s, n, o, kb, bs, A, d_bad);
         const int64_t rest = n2 - kb - bs;
         if (rest > 0) {
             hipLaunchKernelGGL(k_chol_panel, dim3(static_cast<unsigned>((rest + 255) / 256)), dim3(256), 0, s, n, o, kb,
@@ -583,7 +594,21 @@ TpsFitResult tps_fit_grid(bmd_problem* p, const double* d_in, double lam, double
         TPS_TRY(hipGetLastError());
     }
     hipLaunchKernelGGL(k_tps_qty, dim3(1), dim3(1024), 0, s, n, np, V, d_tau, y, z);
-    hipLaunchKernelGGL(k_tps_solve, dim3(1), dim3(1024), 0, s, n, o, n2, A, z);
+    for (int64_t kb = 0; kb < n2; kb += kNB) {   // L t = z2
+        const int bs = static_cast<int>(std::min<int64_t>(kNB, n2 - kb));
+        hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(64), 0, s, n, o, kb, bs, false, A, z + o);
+        const int64_t rest = n2 - kb - bs;
+        if (rest > 0)
+            hipLaunchKernelGGL(k_trsv_update, dim3(static_cast<unsigned>((rest + 255) / 256)), dim3(256), 0, s, n, o,
+                               kb, bs, n2, false, A, z + o);
+    }
+    for (int64_t kb = ((n2 - 1) / kNB) * kNB; kb >= 0; kb -= kNB) {   // L^T w = t
+        const int bs = static_cast<int>(std::min<int64_t>(kNB, n2 - kb));
+        hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(64), 0, s, n, o, kb, bs, true, A, z + o);
+        if (kb > 0)
+            hipLaunchKernelGGL(k_trsv_update, dim3(static_cast<unsigned>((kb + 255) / 256)), dim3(256), 0, s, n, o, kb,
+                               bs, n2, true, A, z + o);
+    }
     hipLaunchKernelGGL(k_tps_coeffs, dim3(1), dim3(1024), 0, s, n, np, A, V, d_tau, d_R, z, c, a);
     TPS_TRY(hipGetLastError());
     TPS_TRY(hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -593,7 +618,7 @@ TpsFitResult tps_fit_grid(bmd_problem* p, const double* d_in, double lam, double
         goto done;
     }
     if (d_out) {
-        const dim3 grid(static_cast<unsigned>((G + 255) / 256));
+        const dim3 grid(static_cast<unsigned>((G + 3) / 4));
         if (d == 1) hipLaunchKernelGGL(k_tps_eval_grid<1>, grid, dim3(256), 0, s, P, n, U, c, a, d_in, d_out);
         else if (d == 2) hipLaunchKernelGGL(k_tps_eval_grid<2>, grid, dim3(256), 0, s, P, n, U, c, a, d_in, d_out);
         else hipLaunchKernelGGL(k_tps_eval_grid<3>, grid, dim3(256), 0, s, P, n, U, c, a, d_in, d_out);

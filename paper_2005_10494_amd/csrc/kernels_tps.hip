@@ -260,7 +260,13 @@ __global__ __launch_bounds__(256) void k_chol_panel(int64_t n, int64_t o, int64_
 }
 
 // Trailing update A22 -= L21 L21^T on the lower triangle, kUT x kUT output
-// tiles (256 threads, 4 x 4 outputs each); tiles above the diagonal leave.
+// tiles on the matrix cores (FP64 16x16x4): four wavefronts, each a 32 x 32
+// quarter as 2 x 2 blocks of 16 x 16; the tile's rows of L21 (both factors)
+// staged in LDS; tiles above the diagonal leave.  Operand layout of the
+// instruction: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; its
+// result element v is row l / 16 + 4 v, column l % 16.
+typedef double tps_d4 __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void k_chol_update(int64_t n, int64_t o, int64_t kb, int bs, int64_t n2,
                                                      double* __restrict__ A) {
     const int64_t t0 = kb + bs;
@@ -275,27 +281,32 @@ __global__ __launch_bounds__(256) void k_chol_update(int64_t n, int64_t o, int64
         Lk[r][c] = (k0 + r < n2 && c < bs) ? A[(o + k0 + r) * n + o + kb + c] : 0.0;
     }
     __syncthreads();
-    const int ri = (t / 16) * 4, rk = (t % 16) * 4;
-    double acc[4][4] = {};
-    for (int c = 0; c < kNB; ++c) {
-        double a[4], b[4];
+    const int wave = t >> 6, lane = t & 63;
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int rb = (wave >> 1) * 32, cb = (wave & 1) * 32;
+    tps_d4 acc[2][2];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            a[q] = Li[ri + q][c];
-            b[q] = Lk[rk + q][c];
-        }
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int b = 0; b < 2; ++b) acc[a][b] = tps_d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int s = 0; s < 4; ++s) acc[q][s] = fma(a[q], b[s], acc[q][s]);
+    for (int c0 = 0; c0 < kNB; c0 += 4) {
+        const double x0 = Li[rb + r16][c0 + kq], x1 = Li[rb + 16 + r16][c0 + kq];
+        const double y0 = Lk[cb + r16][c0 + kq], y1 = Lk[cb + 16 + r16][c0 + kq];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, acc[1][1], 0, 0, 0);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int64_t i = i0 + ri + q, k = k0 + rk + s;
-            if (i < n2 && k <= i) A[(o + i) * n + o + k] -= acc[q][s];
-        }
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t i = i0 + rb + 16 * a + kq + 4 * v, k = k0 + cb + 16 * b + r16;
+                if (i < n2 && k <= i) A[(o + i) * n + o + k] -= acc[a][b][v];
+            }
 }
 
 // z = Q^T y = H_d ... H_0 y (one workgroup).

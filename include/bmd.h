@@ -239,12 +239,13 @@ bmd_status bmd_eval_grid_noalloc(bmd_problem *p, uint64_t n_draws, int32_t prec,
 
 /* Nadaraya-Watson smoothing with the product Gaussian kernel
  * K(g,h) = prod_j exp(-((q_j(g) - q_j(h)) / b_j)^2 / 2), untruncated, applied
- * separably along each axis (the stand-in for the paper's thin-plate spline,
- * Sec. 2.3).  d_in and d_out are FP64 arrays of length G and must not alias.
- * prec: FP64 uses FP64 matrix cores; FP32_COMP uses FP32 matrix cores with
- * FP32 accumulation.  BMD_DESIGN_ALPHA3 grids sum over the designs whose value
- * is not NaN only (the designs without a third level), which stay NaN; other
- * problems propagate NaN like any value. */
+ * separably along each axis (the default smoother in place of the paper's
+ * thin-plate spline, Sec. 2.3, which bmd_smooth_tps fits).  d_in and d_out are
+ * FP64 arrays of length G and must not alias.  prec: FP64 uses FP64 matrix
+ * cores; FP32_COMP uses FP32 matrix cores with FP32 accumulation.
+ * BMD_DESIGN_ALPHA3, BMD_DESIGN_ALPHA4 and BMD_DESIGN_NESTED3 grids sum over
+ * the designs whose value is not NaN only (the designs that exist), which stay
+ * NaN; other problems propagate NaN like any value. */
 bmd_status bmd_smooth(bmd_problem *p, const double *d_in, double *d_out, int32_t prec,
                       void *stream);
 
@@ -427,7 +428,7 @@ bmd_status bmd_eval_batch(bmd_problem *const *ps, int32_t n, const uint64_t *n_d
  * K = prod_j exp(-((q_j - q_{h,j}) / b_j)^2 / 2) over the grid designs h whose
  * value d_surface[h] (FP64, length G, typically bmd_eval_grid's mean) is not
  * NaN.  At a grid design it equals bmd_smooth's FP64 output there when no
- * value is NaN (bmd_smooth propagates NaN except on BMD_DESIGN_ALPHA3/4 grids,
+ * value is NaN (bmd_smooth propagates NaN except on BMD_DESIGN_ALPHA3/4 and NESTED3 grids,
  * where it skips NaN designs as this call does).
  *   h_q     [d]    the design (any finite point; the grid's box is its range)
  *   h_value        S(q)

@@ -67,7 +67,7 @@ class _Draw(ctypes.Structure):
 
 _ALPHA = {"fwer": 0, "fwer_equal": 0, "bonferroni": 1, "fixed": 2, "split": 3}
 _EFFECT = {"step": 0, "paper": 1, "paper_gauss": 1}
-_DESIGN = {"cutoffs": 0, "alpha": 1, "alpha3": 2, "alpha4": 3, "nested3": 4}
+_DESIGN = {"cutoffs": 0, "alpha": 1, "alpha3": 2, "alpha4": 3, "nested3": 4, "nested4": 5}
 
 _lib = None
 
@@ -84,7 +84,7 @@ def lib():
             "or_Phi": (D, [D]), "or_phi": (D, [D]), "or_Phiinv": (D, [D]),
             "or_bvn": (D, [D, D, D]), "or_bvn_density": (D, [D, D, D]),
             "or_orthant": (D, [ctypes.c_int, P, D]), "or_zstar": (D, [D, D]), "or_z2_fwer": (D, [D, D, D]),
-            "or_tvn": (D, [D, D, D, D, D, D]), "or_z3_fwer": (D, [D, D, D, D, D]), "or_zstar3": (D, [D, D, D]),
+            "or_tvn": (D, [D, D, D, D, D, D]), "or_z3_fwer": (D, [D, D, D, D, D]), "or_zstar3": (D, [D, D, D]), "or_zstar4": (D, [D, D, D, D]),
             "or_qvn": (D, [P, P]), "or_qvn_nested": (D, [P, P]), "or_z4_fwer": (D, [D, D, D, D, D, D, D]),
             "or_info_units": (D, [D, D, D]),
             "or_philox4x32_10": (None, [P, P, P]), "or_uniform52": (D, [U32, U32]),
@@ -161,6 +161,7 @@ def z2_fwer(z1, r, alpha0=0.025): return lib().or_z2_fwer(float(z1), float(r), f
 def tvn(h1, h2, h3, r12, r13, r23): return lib().or_tvn(*map(float, (h1, h2, h3, r12, r13, r23)))
 def z3_fwer(z1, z2, r2, r3, alpha0=0.025): return lib().or_z3_fwer(*map(float, (z1, z2, r2, r3, alpha0)))
 def zstar3(r2, r3, alpha0=0.025): return lib().or_zstar3(float(r2), float(r3), float(alpha0))
+def zstar4(r2, r3, r4, alpha0=0.025): return lib().or_zstar4(float(r2), float(r3), float(r4), float(alpha0))
 
 
 def qvn(h, R):

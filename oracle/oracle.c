@@ -428,6 +428,22 @@ double or_qvn_nested(const double *h, const double *r)
     return or_quad(qvn4_outer, &c, fmin(-12.0, hi - 10.0), hi);
 }
 
+/* One critical value z* for four nested populations 1 > r2 > r3 > r4 with
+ * 1 - Phi_4(z*, z*, z*, z*) = alpha0 (Formula 2 with equal levels), by
+ * bisection between one test at level alpha0 and the Bonferroni value. */
+double or_zstar4(double r2, double r3, double r4, double alpha0)
+{
+    double r[4] = {1.0, r2, r3, r4};
+    double lo = -or_Phiinv(alpha0), hi = -or_Phiinv(alpha0 / 4.0);
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        double h[4] = {mid, mid, mid, mid};
+        if (1.0 - or_qvn_nested(h, r) > alpha0) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 /* n = 4 nested populations 1 > r2 > r3 > r4: the fourth critical value with
  * FWER = 1 - Phi_4(z1, z2, z3, z4) = alpha0 given the first three, by
  * bisection between the fourth test alone at level alpha0 and the union bound
@@ -596,6 +612,25 @@ void or_make_design(const or_problem *p, const double *q, or_design *o)
         o->z1 = o->z2 = o->z3 = z;
         return;
     }
+    if (p->design_space == OR_DESIGN_NESTED4) {
+        /* Three cutoffs on one biomarker: populations all, x > c_1, x > c_2, x > c_3. */
+        for (int j = 0; j < 3; ++j) {
+            o->q[j] = q[j];
+            o->c[j] = or_Phiinv(q[j]);
+        }
+        o->r = 1.0 - q[0];
+        o->rho = sqrt(o->r);
+        o->r3 = 1.0 - q[1];
+        o->r4 = 1.0 - q[2];
+        double r2 = o->r, r3 = o->r3, r4 = o->r4;
+        int ok = q[0] < q[1] && q[1] < q[2] && r3 * (1.0 - r2) <= 0.975 * 0.975 * r2 * (1.0 - r3) &&
+                 r4 * (r2 - r3) <= 0.975 * 0.975 * r3 * (r2 - r4) && r3 <= 0.95 * r2;
+        double z = !ok ? NAN
+                 : p->alpha_rule == OR_ALPHA_BONFERRONI ? -or_Phiinv(p->alpha0 / 4.0)
+                                                        : or_zstar4(r2, r3, r4, p->alpha0);
+        o->z1 = o->z2 = o->z3 = o->z4 = z;
+        return;
+    }
     if (p->design_space == OR_DESIGN_ALPHA) {
         /* (r_2, alpha_1) or alpha_1 alone: the nested pair of Sec. 2.2 with the
          * level split on the FWER boundary of Formula 2. */
@@ -638,7 +673,7 @@ void or_make_draw(const or_problem *p, uint64_t k, or_draw *o)
 {
     memset(o, 0, sizeof *o);
     if (p->effect == OR_EFFECT_STEP) {
-        int d = p->design_space == OR_DESIGN_NESTED3 ? 1 : p->d;   /* one biomarker */
+        int d = (p->design_space == OR_DESIGN_NESTED3 || p->design_space == OR_DESIGN_NESTED4) ? 1 : p->d;   /* one biomarker */
         draw_uniforms(p, k, 2 + d, o->u);
         o->b0 = p->mu_b0 + p->sd_b0 * or_Phiinv(o->u[0]);
         o->b1 = p->mu_b1 + p->sd_b1 * or_Phiinv(o->u[1]);
@@ -782,8 +817,22 @@ static double success_nested3(const or_problem *p, const or_design *ds, const or
     return 1.0 - or_tvn(h[0], h[1], h[2], sqrt(r[1]), sqrt(r[2]), sqrt(r[2] / r[1]));
 }
 
+/* Four populations from three cutoffs: as success_nested3 with q_3, r_4 and
+ * the nested Phi_4. */
+static double success_nested4(const or_problem *p, const or_design *ds, const or_draw *dr)
+{
+    if (isnan(ds->z4)) return NAN;
+    double q[4] = {0.0, ds->q[0], ds->q[1], ds->q[2]}, r[4] = {1.0, ds->r, ds->r3, ds->r4}, h[4];
+    for (int i = 0; i < 4; ++i) {
+        double delta = dr->b0 + dr->b1 * (1.0 - fmax(q[i], dr->tau[0])) / r[i];
+        h[i] = ds->z4 - sqrt(r[i] * p->info) * delta;
+    }
+    return 1.0 - or_qvn_nested(h, r);
+}
+
 double or_success(const or_problem *p, const or_design *ds, const or_draw *dr)
 {
+    if (p->design_space == OR_DESIGN_NESTED4) return success_nested4(p, ds, dr);
     if (p->design_space == OR_DESIGN_NESTED3) return success_nested3(p, ds, dr);
     if (p->design_space == OR_DESIGN_ALPHA4) return success4(p, ds, dr);
     if (p->design_space == OR_DESIGN_ALPHA3) return success3(p, ds, dr);

@@ -33,7 +33,8 @@ extern "C" {
 
 enum { OR_ALPHA_FWER_EQUAL = 0, OR_ALPHA_BONFERRONI = 1, OR_ALPHA_FIXED = 2, OR_ALPHA_SPLIT = 3 };
 enum { OR_EFFECT_STEP = 0, OR_EFFECT_PAPER_GAUSS = 1 };
-enum { OR_DESIGN_CUTOFFS = 0, OR_DESIGN_ALPHA = 1, OR_DESIGN_ALPHA3 = 2, OR_DESIGN_ALPHA4 = 3, OR_DESIGN_NESTED3 = 4 };
+enum { OR_DESIGN_CUTOFFS = 0, OR_DESIGN_ALPHA = 1, OR_DESIGN_ALPHA3 = 2, OR_DESIGN_ALPHA4 = 3, OR_DESIGN_NESTED3 = 4,
+       OR_DESIGN_NESTED4 = 5 };
 
 typedef struct {
     int32_t d;              /* number of biomarkers (cutoff axes), 1..6          */
@@ -74,7 +75,14 @@ typedef struct {
      * {x > Phi^-1(q_1)} (r_2 = 1 - q_1) and {x > Phi^-1(q_2)} (r_3 = 1 - q_2);
      * designs with q_1 >= q_2 or a partial correlation of the third on the
      * second population above 0.975 are NaN.  Step prior with one true cutoff
-     * tau; alpha rule FWER_EQUAL (one z* for all three tests) or BONFERRONI. */
+     * tau; alpha rule FWER_EQUAL (one z* for all three tests) or BONFERRONI.
+     * OR_DESIGN_NESTED4: four nested populations from three cutoffs on one
+     * biomarker, d = 3 axes q_1 < q_2 < q_3: the full population and
+     * {x > Phi^-1(q_i)} (r_{i+1} = 1 - q_i); designs outside q_1 < q_2 < q_3,
+     * with a partial correlation of the third on the second population (given
+     * the first) or of the fourth and third (given the second) above 0.975, or
+     * with r_3 > 0.95 r_2 are NaN.  Step prior, one z* (FWER_EQUAL) or
+     * BONFERRONI (alpha0 / 4). */
     int32_t design_space;
     double r_lo, r_hi;
     double r_4;
@@ -116,6 +124,7 @@ double or_z3_fwer(double z1, double z2, double r2, double r3, double alpha0);   
 double or_zstar3(double r2, double r3, double alpha0);   /* n = 3 at equal levels: 1 - Phi_3(z*,z*,z*) = alpha0 */
 double or_qvn(const double *h, const double *R);   /* P(X_i <= h_i, i < 4), R 4 x 4 correlations */
 double or_qvn_nested(const double *h, const double *r);   /* same, nested-population correlations of r[4] */
+double or_zstar4(double r2, double r3, double r4, double alpha0);   /* 1 - Phi_4(z,z,z,z) = alpha0 */
 double or_z4_fwer(double z1, double z2, double z3, double r2, double r3, double r4, double alpha0);   /* n = 4 */
 double or_info_units(double alpha, double beta, double delta);
 void   or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

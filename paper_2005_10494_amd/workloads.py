@@ -146,6 +146,26 @@ def nested3_design(m, q_range=(0.1, 0.9), rule: str = "fwer", n_draws: int = 100
     return p
 
 
+def nested4_design(m, q_range=(0.1, 0.9), rule: str = "fwer", n_draws: int = 100_000, bandwidth: float = 0.05,
+                   **kw) -> dict:
+    """Four nested populations cut from one biomarker by three cutoffs: an
+    m^3 grid (or m = (m0, m1, m2)) of cutoff quantiles (q_1, q_2, q_3) over
+    ``q_range``; the step prior of ``STEP_PRIOR`` with one true cutoff;
+    designs outside q_1 < q_2 < q_3 (or beyond the partial-correlation and
+    fraction bounds) do not exist."""
+    mm = [m, m, m] if np.isscalar(m) else list(m)
+    p = base_problem(3, mm, 0.0, bandwidth, design="nested4", q_lo=float(q_range[0]), q_hi=float(q_range[1]),
+                     alpha_rule=rule)
+    p.update(kw)
+    p["n_draws"] = n_draws
+    return p
+
+
+def nested4_grid() -> dict:
+    """Three cutoffs on one biomarker, 24^3 grid over [0.1, 0.9], M = 1e5."""
+    return nested4_design(24)
+
+
 def nested3_grid() -> dict:
     """Two cutoffs on one biomarker, 64 x 64 grid over [0.1, 0.9], M = 1e5."""
     return nested3_design(64)

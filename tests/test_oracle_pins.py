@@ -1269,3 +1269,76 @@ def test_tps_derivatives_by_central_differences(d, m):
             vm = O.tps_derivatives(spec, fit, q - e)
             assert abs((vp[0] - vm[0]) / (2 * h) - g[j]) < 1e-6 * max(1.0, np.abs(g).max())
             assert np.max(np.abs((vp[1] - vm[1]) / (2 * h) - H[j])) < 1e-4 * max(1.0, np.abs(H).max())
+
+
+# ------------------------------------------------------------ three cutoffs on one biomarker (n = 4)
+
+@pytest.mark.parametrize("r", [(0.7, 0.45, 0.2), (0.85, 0.5, 0.3), (0.5, 0.3, 0.12)])
+def test_nested4_zstar_on_fwer_boundary(r):
+    """z* against scipy's four-variate normal CDF of the nested correlations:
+    the FWER at alpha0 within the seeded estimator's accuracy, inside the
+    one-test and Bonferroni bounds."""
+    z = O.zstar4(*r)
+    rr = [1.0, *r]
+    fwer = 1.0 - _qvn_scipy([z] * 4, _nested_R(rr))
+    assert abs(fwer - 0.025) < 5e-7, (r, z, fwer)
+    assert -ndtri(0.025) < z < -ndtri(0.025 / 4)
+
+
+def test_nested4_designs_and_null_prior():
+    """Designs exist only for q_1 < q_2 < q_3 within the partial-correlation
+    and fraction bounds; under a null prior every existing design rejects with
+    probability alpha0 (FWER-equal rule), and at the Bonferroni value with
+    scipy's 1 - Phi_4."""
+    spec = W.nested4_design(5, mu_b0=0.0, sd_b0=0.0, mu_b1=0.0, sd_b1=0.0)
+    G = O.grid_size(spec)
+    m, _ = O.eval_grid(spec, np.arange(G), 4)
+    n_ok = 0
+    for g in range(G):
+        q, _ = O.grid_point(spec, g)
+        r2, r3, r4 = 1 - q[0], 1 - q[1], 1 - q[2]
+        exists = (q[0] < q[1] < q[2] and r3 * (1 - r2) <= 0.975 ** 2 * r2 * (1 - r3)
+                  and r4 * (r2 - r3) <= 0.975 ** 2 * r3 * (r2 - r4) and r3 <= 0.95 * r2)
+        assert np.isnan(m[g]) == (not exists), (g, q)
+        if exists:
+            n_ok += 1
+            assert abs(m[g] - 0.025) < 1e-9, (g, m[g])
+    assert n_ok >= 4
+    bon = dict(spec, alpha_rule="bonferroni")
+    g = int(np.nonzero(~np.isnan(m))[0][0])
+    mb, _ = O.eval_grid(bon, [g], 2)
+    q, _ = O.grid_point(bon, g)
+    zb = -ndtri(0.025 / 4)
+    ref = 1.0 - _qvn_scipy([zb] * 4, _nested_R([1.0, 1 - q[0], 1 - q[1], 1 - q[2]]))
+    assert abs(mb[0] - ref) < 5e-7, (mb[0], ref)
+
+
+def test_nested4_one_draw_against_a_simulated_trial():
+    """One draw (fixed effects and true cutoff) from the definitions by
+    simulation: each population's fraction and responders from 4e6 biomarker
+    values, the drifts sqrt(r_i I) Delta_i, and P(some Z_i > z*) from 4e6 draws
+    of the four statistics with the nested correlations; the oracle's summand
+    is within 5 standard errors."""
+    tau = 0.45
+    spec = W.nested4_design(5, mu_b0=0.05, sd_b0=0.0, mu_b1=0.45, sd_b1=0.0, tau_lo=tau, tau_hi=tau)
+    G = O.grid_size(spec)
+    cand = [g for g in range(G) if np.allclose(O.grid_point(spec, g)[0], [0.1, 0.5, 0.7])]
+    g = cand[0]
+    q, _ = O.grid_point(spec, g)
+    m, _ = O.eval_grid(spec, [g], 2)
+    ds = O.make_design(spec, q)
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal(4_000_000)
+    resp = x > ndtri(tau)
+    I = spec["info"]
+    mu, r = [], []
+    for c in (None, ndtri(q[0]), ndtri(q[1]), ndtri(q[2])):
+        inside = np.ones_like(x, dtype=bool) if c is None else x > c
+        ri = inside.mean()
+        mu.append(math.sqrt(ri * I) * (0.05 + 0.45 * (resp & inside).mean() / ri))
+        r.append(ri)
+    R = _nested_R(r)
+    Z = rng.multivariate_normal(mu, R, size=4_000_000)
+    hit = (Z > ds["z4"]).any(axis=1)
+    p, se = hit.mean(), hit.std() / math.sqrt(hit.size)
+    assert abs(m[0] - p) < 5 * se + 2e-4, (m[0], p, se)

@@ -209,7 +209,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="3d", choices=["3d", "1d", "5d", "alpha", "alpha3", "alpha4", "levels", "grad",
-                                                         "refine", "batch", "smooth", "twolayer", "nested3", "tps"])
+                                                         "refine", "batch", "smooth", "twolayer", "nested3", "nested4", "tps"])
     ap.add_argument("--batch-scale", type=float, default=1.0,
                     help="batch workload only: scale of the per-axis grids and of the draw range (1 = full size)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -256,6 +256,8 @@ def main():
         return bench_two_layer(args)
     if args.workload == "nested3":
         return bench_nested3(args)
+    if args.workload == "nested4":
+        return bench_nested3(args, n=4)
     if args.workload == "tps":
         return bench_tps(args)
     spec = workload(args.workload)
@@ -496,16 +498,16 @@ def bench_nested(args, n):
     print(json.dumps(out), flush=True)
 
 
-def bench_nested3(args):
-    """Three nested populations cut from one biomarker by two cutoffs: the
-    64 x 64 grid of cutoff quantiles (q_1, q_2) over [0.1, 0.9], one z* on the
-    FWER boundary per design, step prior, M = 1e5.  A step is problem set-up
-    (critical values and launch order) + draws + sweep + smoothing over the
-    designs that exist + argmax.  FP32 and FP64."""
+def bench_nested3(args, n=3):
+    """n = 3 (4) nested populations cut from one biomarker by two (three)
+    cutoffs: the 64 x 64 (24^3) grid of cutoff quantiles over [0.1, 0.9], one
+    z* on the FWER boundary per design, step prior, M = 1e5.  A step is
+    problem set-up (critical values and launch order) + draws + sweep +
+    smoothing over the designs that exist + argmax.  FP32 and FP64."""
     import torch
     import paper_2005_10494_amd as bmd
     from paper_2005_10494_amd import workloads as W
-    spec = W.nested3_grid()
+    spec = W.nested3_grid() if n == 3 else W.nested4_grid()
     M, G = spec["n_draws"], int(np.prod(spec["m"]))
     res = {}
     for prec in ("fp32", "fp64"):
@@ -524,42 +526,60 @@ def bench_nested3(args):
             if it >= args.warmup:
                 ts.append(dt)
                 sw.append(ph["sweep"])
-            log(f"  nested3 {prec} step {it}: {1e3 * dt:.1f} ms, sweep {ph['sweep']:.1f} ms")
+            log(f"  nested{n} {prec} step {it}: {1e3 * dt:.1f} ms, sweep {ph['sweep']:.1f} ms")
         res[prec] = (float(np.mean(ts)), float(np.mean(sw)), mean, idx, val, cell)
     t32, s32, m32, i32, v32, c32 = res["fp32"]
     t64, s64, m64, i64, v64, _ = res["fp64"]
     exists = ~np.isnan(m32.cpu().numpy())
     feasible = int(exists.sum())
     evals = feasible * M
-    # Per summand: the three means and 1 - Phi_3 with the sums (22) and, per
-    # panel point, 22 as for the three-population sweep; the panel count is each
-    # design's own under the FP32 rule (the sweep runs a wavefront at its
-    # largest count, which the launch order keeps close to every lane's).
     m0 = spec["m"][0]
     q = spec["q_lo"] + (spec["q_hi"] - spec["q_lo"]) * np.arange(m0) / (m0 - 1)
-    q1, q2 = (a.ravel() for a in np.meshgrid(q, q, indexing="ij"))
-    r2, r3 = 1.0 - q1[exists], 1.0 - q2[exists]
-    scale = np.minimum(np.sqrt((1 - r2) / r2), np.sqrt((r2 - r3) / r3))
-    npan = np.clip(np.ceil(2.5 / scale), 3, 64)
-    flops = float(M * np.sum(22.0 + npan * 8 * 22.0))
+    qs = [a.ravel() for a in np.meshgrid(*([q] * (n - 1)), indexing="ij")]
+    rr = [1.0 - qq[exists] for qq in qs]
+    if n == 3:
+        # Per summand: the three means and 1 - Phi_3 with the sums (22) and, per
+        # panel point, 22 as for the three-population sweep; the panel count is
+        # each design's own under the FP32 rule (the sweep runs a wavefront at
+        # its largest count, which the launch order keeps close to every lane's).
+        r2, r3 = rr
+        scale = np.minimum(np.sqrt((1 - r2) / r2), np.sqrt((r2 - r3) / r3))
+        npan = np.clip(np.ceil(2.5 / scale), 3, 64)
+        flops = float(M * np.sum(22.0 + npan * 8 * 22.0))
+        kern = f"k_eval_nested3<float,false> (one design per thread, {npan.min():.0f}..{npan.max():.0f} panels " \
+               f"(mean {npan.mean():.2f}) x 8 points of two univariate CDFs given the middle statistic)"
+    else:
+        # Per summand: four means and the sums (28) and, per panel point,
+        # 35 + 6 nb as for the four-population sweep, with each design's own
+        # panel and bivariate node counts under the FP32 rules.
+        r2, r3, r4 = rr
+        scale = np.minimum(np.minimum(np.sqrt((1 - r2) / r2), np.sqrt((r2 - r3) / r3)), np.sqrt((r2 - r4) / r4))
+        npan = np.clip(np.ceil(2.5 / scale), 3, 64)
+        rho = np.sqrt(r4 * (r2 - r3) / (r3 * (r2 - r4)))
+        nb = bvn_nodes(rho, "fp32")
+        flops = float(M * np.sum(28.0 + npan * 8 * (35.0 + 6.0 * nb)))
+        kern = f"k_eval_nested4<float,12,false> (one design per thread, {npan.min():.0f}..{npan.max():.0f} panels " \
+               f"(mean {npan.mean():.2f}) x 8 points of a univariate and a {nb.min():.0f}..{nb.max():.0f}-node " \
+               f"bivariate CDF given the second statistic)"
     achieved = flops / (1e-3 * s32) / 1e12
-    best = [float(q[c]) for c in c32]
-    out = {"metric": "two-cutoff grid: integrand evals/s", "value": evals / t32,
+    cells = np.unravel_index(i32, spec["m"])
+    best = [float(q[c]) for c in cells]
+    names = "(q_1, q_2)" if n == 3 else "(q_1, q_2, q_3)"
+    out = {"metric": f"{'two' if n == 3 else 'three'}-cutoff grid: integrand evals/s", "value": evals / t32,
            "unit": "integrand evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1e3 * t32, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"three nested populations from two cutoffs on one biomarker, (q_1, q_2) grid "
-                                  f"{m0}x{m0} over [{spec['q_lo']}, {spec['q_hi']}], one z* on the FWER boundary, "
+           "config": {"workload": f"{'three' if n == 3 else 'four'} nested populations from {n - 1} cutoffs on "
+                                  f"one biomarker, {names} grid {'x'.join(str(x) for x in spec['m'])} over "
+                                  f"[{spec['q_lo']}, {spec['q_hi']}], one z* on the FWER boundary, "
                                   f"step prior b0 ~ N({spec['mu_b0']}, {spec['sd_b0']}^2), b1 ~ N({spec['mu_b1']}, "
                                   f"{spec['sd_b1']}^2), tau ~ U({spec['tau_lo']}, {spec['tau_hi']}), I = "
-                                  f"{spec['info']:g}, M={M}, smoothing sd {spec['bandwidth'][0]} on both axes, "
+                                  f"{spec['info']:g}, M={M}, smoothing sd {spec['bandwidth'][0]} on every axis, "
                                   f"steps = precompute+order+draws+sweep+smooth+argmax over designs that exist",
                       "designs": G, "feasible_designs": feasible, "n_draws": M},
            "roofline": {"bound": "alu", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
                         "frac": achieved / 157.3, "traffic": None,
-                        "kernel": f"k_eval_nested3<float,false> (one design per thread, {npan.min():.0f}.."
-                                  f"{npan.max():.0f} panels (mean {npan.mean():.2f}) x 8 points of two univariate "
-                                  f"CDFs given the middle statistic)", "flops_per_launch": flops},
+                        "kernel": kern, "flops_per_launch": flops},
            "sweep_ms": s32, "sweep_evals_per_s": evals / (1e-3 * s32),
            "result": {"best_q": best, "best_power_smoothed": v32, "raw_power_at_best": float(m32[i32].item())},
            "fp64": {"ms_per_step": 1e3 * t64, "sweep_ms": s64},

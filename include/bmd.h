@@ -136,7 +136,19 @@ typedef enum {
      * BMD_ALPHA_BONFERRONI (Phi^-1(1 - alpha0 / 3)); indicator_width 0; at
      * most 16,776,960 designs (ERANGE); grid sweeps, smoothing (over the
      * designs that exist) and argmax only. */
-    BMD_DESIGN_NESTED3 = 4
+    BMD_DESIGN_NESTED3 = 4,
+    /* n = 4 nested populations cut from one biomarker by three cutoffs: d = 3,
+     * axes q_1, q_2, q_3 over [q_lo, q_hi] with 0.1 <= q_lo and q_hi < 1; the
+     * tests are the full population and {x > Phi^-1(q_i)} (r_{i+1} = 1 - q_i).
+     * Designs outside q_1 < q_2 < q_3, with a partial correlation of the third
+     * statistic on the second (given the first) or of the fourth and third
+     * (given the second) above 0.975, or with r_3 > 0.95 r_2 do not exist (NaN).
+     * Step prior with one true cutoff, as BMD_DESIGN_NESTED3; alpha_rule
+     * BMD_ALPHA_FWER_EQUAL (one z* with 1 - Phi_4(z*, .., z*) = alpha0) or
+     * BMD_ALPHA_BONFERRONI (Phi^-1(1 - alpha0 / 4)); indicator_width 0; at most
+     * 16,776,960 designs; grid sweeps, smoothing (over the designs that exist)
+     * and argmax only. */
+    BMD_DESIGN_NESTED4 = 5
 } bmd_design_space;
 
 /* Problem descriptor (copied by bmd_create_problem). */
@@ -243,7 +255,7 @@ bmd_status bmd_eval_grid_noalloc(bmd_problem *p, uint64_t n_draws, int32_t prec,
  * thin-plate spline, Sec. 2.3, which bmd_smooth_tps fits).  d_in and d_out are
  * FP64 arrays of length G and must not alias.  prec: FP64 uses FP64 matrix
  * cores; FP32_COMP uses FP32 matrix cores with FP32 accumulation.
- * BMD_DESIGN_ALPHA3, BMD_DESIGN_ALPHA4 and BMD_DESIGN_NESTED3 grids sum over
+ * BMD_DESIGN_ALPHA3/4 and BMD_DESIGN_NESTED3/4 grids sum over
  * the designs whose value is not NaN only (the designs that exist), which stay
  * NaN; other problems propagate NaN like any value. */
 bmd_status bmd_smooth(bmd_problem *p, const double *d_in, double *d_out, int32_t prec,
@@ -428,7 +440,7 @@ bmd_status bmd_eval_batch(bmd_problem *const *ps, int32_t n, const uint64_t *n_d
  * K = prod_j exp(-((q_j - q_{h,j}) / b_j)^2 / 2) over the grid designs h whose
  * value d_surface[h] (FP64, length G, typically bmd_eval_grid's mean) is not
  * NaN.  At a grid design it equals bmd_smooth's FP64 output there when no
- * value is NaN (bmd_smooth propagates NaN except on BMD_DESIGN_ALPHA3/4 and NESTED3 grids,
+ * value is NaN (bmd_smooth propagates NaN except on BMD_DESIGN_ALPHA3/4 and NESTED3/4 grids,
  * where it skips NaN designs as this call does).
  *   h_q     [d]    the design (any finite point; the grid's box is its range)
  *   h_value        S(q)
@@ -548,7 +560,8 @@ bmd_status bmd_draws(bmd_problem *p, uint64_t k0, uint64_t n, double *d_u, doubl
  *            and c[1] = z3, NaN when the design has no third level of three
  *            populations; BMD_DESIGN_ALPHA4 also c[2] = r_4 and c[3] = z4, NaN
  *            when the design has no fourth level; BMD_DESIGN_NESTED3: c[0] = r_3,
- *            c[1] = z3 (= z1 = z2), NaN for designs that do not exist) */
+ *            c[1] = z3 (= z1 = z2), NaN for designs that do not exist;
+ *            BMD_DESIGN_NESTED4 also c[2] = r_4 and c[3] = z4 (= z3)) */
 bmd_status bmd_designs(bmd_problem *p, int64_t g0, int64_t n, double *d_fields, void *stream);
 
 #ifdef __cplusplus

@@ -20,7 +20,7 @@ FP64, FP32_COMP = 0, 1
 _PREC = {"fp64": FP64, "f64": FP64, "fp32": FP32_COMP, "fp32_comp": FP32_COMP, "f32": FP32_COMP}
 _ALPHA = {"fwer": 0, "fwer_equal": 0, "bonferroni": 1, "fixed": 2, "split": 3}
 _EFFECT = {"step": 0, "paper": 1, "paper_gauss": 1}
-_DESIGN = {"cutoffs": 0, "alpha": 1, "alpha3": 2, "alpha4": 3, "nested3": 4}
+_DESIGN = {"cutoffs": 0, "alpha": 1, "alpha3": 2, "alpha4": 3, "nested3": 4, "nested4": 5}
 DRAW_FIELDS = 17
 DESIGN_FIELDS = 16
 

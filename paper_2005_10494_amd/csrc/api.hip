@@ -271,6 +271,18 @@ bmd_status validate(const bmd_problem_desc* d, bool* grid) {
         if (static_cast<double>(d->m[0]) * d->m[1] > static_cast<double>(kNested3MaxTiles * kEvalBlock))
             return fail(BMD_ERANGE, "two-cutoff grids hold at most %lld designs",
                         static_cast<long long>(kNested3MaxTiles * kEvalBlock));
+    } else if (d->design_space == BMD_DESIGN_NESTED4) {
+        if (d->effect != BMD_EFFECT_STEP)
+            return fail(BMD_EINVAL, "three-cutoff designs need the step prior (one biomarker)");
+        if (d->alpha_rule != BMD_ALPHA_FWER_EQUAL && d->alpha_rule != BMD_ALPHA_BONFERRONI)
+            return fail(BMD_EINVAL, "three-cutoff designs need rule FWER_EQUAL or BONFERRONI");
+        if (!any || d->d != 3) return fail(BMD_ERANGE, "three-cutoff designs are a grid over (q_1, q_2, q_3)");
+        if (!(d->q_lo >= 0.1 && d->q_hi < 1.0))
+            return fail(BMD_ERANGE, "three-cutoff designs need 0.1 <= q_lo and q_hi < 1 (r_2 <= 0.9)");
+        if (d->indicator_width != 0.0) return fail(BMD_ERANGE, "three-cutoff designs use the exact indicator");
+        if (static_cast<double>(d->m[0]) * d->m[1] * d->m[2] > static_cast<double>(kNested3MaxTiles * kEvalBlock))
+            return fail(BMD_ERANGE, "three-cutoff grids hold at most %lld designs",
+                        static_cast<long long>(kNested3MaxTiles * kEvalBlock));
     } else if (d->design_space != BMD_DESIGN_CUTOFFS) {
         return fail(BMD_EINVAL, "unknown design_space %d", d->design_space);
     }
@@ -501,7 +513,7 @@ bmd_status bmd_create_problem(const bmd_problem_desc* desc, bmd_problem** out, v
     P.key0 = static_cast<uint32_t>(d.seed);
     P.key1 = static_cast<uint32_t>(d.seed >> 32);
     P.scenario = d.scenario_id;
-    P.n_uniform = d.design_space == BMD_DESIGN_NESTED3     ? 3
+    P.n_uniform = (d.design_space == BMD_DESIGN_NESTED3 || d.design_space == BMD_DESIGN_NESTED4) ? 3
                   : d.effect == BMD_EFFECT_STEP              ? 2 + d.d
                   : d.design_space == BMD_DESIGN_ALPHA3 ? 3
                   : d.design_space == BMD_DESIGN_ALPHA4 ? 4
@@ -569,9 +581,10 @@ bmd_status bmd_create_problem(const bmd_problem_desc* desc, bmd_problem** out, v
         if (st == BMD_OK) st = upload<double>(&p->d_z1, nullptr, P.G);
         if (st == BMD_OK) st = upload<double>(&p->d_z2, nullptr, P.G);
         if (st == BMD_OK && (d.design_space == BMD_DESIGN_ALPHA3 || d.design_space == BMD_DESIGN_ALPHA4 ||
-                             d.design_space == BMD_DESIGN_NESTED3))
+                             d.design_space == BMD_DESIGN_NESTED3 || d.design_space == BMD_DESIGN_NESTED4))
             st = upload<double>(&p->d_z3, nullptr, P.G);
-        if (st == BMD_OK && d.design_space == BMD_DESIGN_ALPHA4) st = upload<double>(&p->d_z4, nullptr, P.G);
+        if (st == BMD_OK && (d.design_space == BMD_DESIGN_ALPHA4 || d.design_space == BMD_DESIGN_NESTED4))
+            st = upload<double>(&p->d_z4, nullptr, P.G);
         if (st == BMD_OK) st = upload<int32_t>(&p->d_order, nullptr, P.G);
         // Smoothing matrices.
         std::vector<double> W;
@@ -930,7 +943,7 @@ bmd_status bmd_smooth(bmd_problem* p, const double* d_in, double* d_out, int32_t
     DeviceGuard guard(p->device);
     // designs without a third level are NaN: smooth over the others
     const bool masked = p->P.design_space == BMD_DESIGN_ALPHA3 || p->P.design_space == BMD_DESIGN_ALPHA4 ||
-                        p->P.design_space == BMD_DESIGN_NESTED3;
+                        p->P.design_space == BMD_DESIGN_NESTED3 || p->P.design_space == BMD_DESIGN_NESTED4;
     bmd_status st = ensure(&p->d_ws2, &p->ws2_cap, sizeof(double) * static_cast<size_t>(p->P.G) * (masked ? 4 : 1));
     if (st != BMD_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1680,7 +1693,7 @@ bmd_status bmd_eval_batch(bmd_problem* const* ps, int32_t n, const uint64_t* n_d
         if (!ps[i] || !d_means[i]) return fail(BMD_EINVAL, "problem or output %d is NULL", i);
         if (!ps[i]->grid) return fail(BMD_ESTATE, "problem %d has no grid", i);
         if (ps[i]->P.design_space == BMD_DESIGN_ALPHA3 || ps[i]->P.design_space == BMD_DESIGN_ALPHA4 ||
-            ps[i]->P.design_space == BMD_DESIGN_NESTED3)
+            ps[i]->P.design_space == BMD_DESIGN_NESTED3 || ps[i]->P.design_space == BMD_DESIGN_NESTED4)
             return fail(BMD_ENOTSUP, "problem %d: three- and four-population designs are not batched", i);
         if (ps[i]->device != ps[0]->device) return fail(BMD_EINVAL, "problems live on different devices");
         if (n_draws[i] == 0 || n_draws[i] > (1ull << 40)) return fail(BMD_ERANGE, "n_draws[%d] outside [1, 2^40]", i);

@@ -184,6 +184,12 @@ hipError_t tps_at_unit(const bmd_problem* p, const double* u, double* d_scratch,
 void tps_release(bmd_problem* p);
 int tps_dims(const bmd_problem* p);   // 0 without a fit
 int nested3_blocks_per_cu(int prec);
+// Three cutoffs on one biomarker (kernels_nested4.hip): the same for
+// (q_1, q_2, q_3) grids of four nested populations.
+hipError_t launch_nested4_precompute(const bmd_problem* p, hipStream_t s);
+int nested4_blocks_per_cu(int prec);
+hipError_t launch_eval_nested4(const bmd_problem* p, int prec, int64_t M, const void* ws, double* partials,
+                               int n_slices, int64_t slice_len, bool want_var, hipStream_t s);
 hipError_t launch_eval_nested3(const bmd_problem* p, int prec, int64_t M, const void* ws, double* partials,
                                int n_slices, int64_t slice_len, bool want_var, hipStream_t s);
 int three_blocks_per_cu(int prec);

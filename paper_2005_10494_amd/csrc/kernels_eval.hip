@@ -201,6 +201,7 @@ int64_t sweep_tiles(const bmd_problem* p, int prec) {
 int sweep_blocks_per_cu(const bmd_problem* p, int prec) {
     if (p->P.design_space == BMD_DESIGN_ALPHA3) return three_blocks_per_cu(prec);
     if (p->P.design_space == BMD_DESIGN_NESTED3) return nested3_blocks_per_cu(prec);
+    if (p->P.design_space == BMD_DESIGN_NESTED4) return nested4_blocks_per_cu(prec);
     if (p->P.design_space == BMD_DESIGN_ALPHA4) return four_blocks_per_cu(prec);
     return prec == BMD_FP64 ? resident_typed<double, 24>(p, prec) : resident_typed<float, 12>(p, prec);
 }
@@ -221,6 +222,8 @@ hipError_t launch_eval_grid(const bmd_problem* p, int prec, int64_t M, const voi
         return launch_eval_three(p, prec, M, ws, partials, n_slices, slice_len, want_var, s);
     if (p->P.design_space == BMD_DESIGN_NESTED3)
         return launch_eval_nested3(p, prec, M, ws, partials, n_slices, slice_len, want_var, s);
+    if (p->P.design_space == BMD_DESIGN_NESTED4)
+        return launch_eval_nested4(p, prec, M, ws, partials, n_slices, slice_len, want_var, s);
     if (p->P.design_space == BMD_DESIGN_ALPHA4)
         return launch_eval_four(p, prec, M, ws, partials, n_slices, slice_len, want_var, s);
     return launch_eval_mode(p, prec, M, ws, partials, n_slices, slice_len, want_var ? kSquares : kSums, s);

@@ -365,7 +365,7 @@ __device__ __forceinline__ void draw_one(const DevProblem& P, const double* __re
         const double b1 = P.mu_b1 + P.sd_b1 * norm_quantile(u[1]);
         double t[kMaxDim];
         // two cutoffs on one biomarker: one true cutoff per draw
-        const int nbio = P.design_space == BMD_DESIGN_NESTED3 ? 1 : P.d;
+        const int nbio = (P.design_space == BMD_DESIGN_NESTED3 || P.design_space == BMD_DESIGN_NESTED4) ? 1 : P.d;
         for (int j = 0; j < nbio; ++j) {
             const double tau = affine_uniform(P.tau_lo, P.tau_hi, u[2 + j]);
             t[j] = norm_quantile(tau);
@@ -448,7 +448,7 @@ __global__ __launch_bounds__(128) void k_inspect_draws(DevProblem P, const doubl
         f[0] = P.mu_b0 + P.sd_b0 * norm_quantile(u[0]);
         f[1] = P.mu_b1 + P.sd_b1 * norm_quantile(u[1]);
         double t[kMaxDim];
-        const int nbio = P.design_space == BMD_DESIGN_NESTED3 ? 1 : P.d;
+        const int nbio = (P.design_space == BMD_DESIGN_NESTED3 || P.design_space == BMD_DESIGN_NESTED4) ? 1 : P.d;
         for (int j = 0; j < nbio; ++j) {
             const double tau = affine_uniform(P.tau_lo, P.tau_hi, u[2 + j]);
             t[j] = norm_quantile(tau);
@@ -485,6 +485,11 @@ __global__ __launch_bounds__(128) void k_inspect_designs(DevProblem P, int64_t g
     } else if (P.design_space == BMD_DESIGN_NESTED3) {
         f[6] = 1.0 - f[1];   // r_3
         f[7] = z3[g];
+    } else if (P.design_space == BMD_DESIGN_NESTED4) {
+        f[6] = 1.0 - f[1];   // r_3
+        f[7] = z3[g];
+        f[8] = 1.0 - f[2];   // r_4
+        f[9] = z4[g];
     } else if (P.design_space == BMD_DESIGN_ALPHA4) {
         f[6] = P.r_hi;
         f[7] = z3[g];
@@ -572,6 +577,7 @@ __global__ __launch_bounds__(1024) void k_order_feasible(int64_t G, const double
 hipError_t launch_design_precompute(const bmd_problem* p, hipStream_t s) {
     if (p->P.G == 0) return hipSuccess;
     if (p->P.design_space == BMD_DESIGN_NESTED3) return launch_nested3_precompute(p, s);   // its own order
+    if (p->P.design_space == BMD_DESIGN_NESTED4) return launch_nested4_precompute(p, s);
     if (p->P.design_space == BMD_DESIGN_ALPHA3 || p->P.design_space == BMD_DESIGN_ALPHA4) {
         const bool four = p->P.design_space == BMD_DESIGN_ALPHA4;
         hipError_t e = four ? launch_four_precompute(p, s) : launch_three_precompute(p, s);

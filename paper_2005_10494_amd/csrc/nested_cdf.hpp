@@ -257,8 +257,9 @@ __device__ __forceinline__ int qvn_panels(double r2, double r3, double r4) {
 }
 
 // Per-problem constants of Phi_4 for four nested populations, in type T.
-template <typename T, int NMAX>
+template <typename T, int NMAX, bool UNI = true>
 struct QvnConst {
+    __device__ static T U(T x) { return UNI ? uniform(x) : x; }
     T r12, r23, r24;     // regressions on the second coordinate
     T is12, is23, is24;  // 1 / s12, 1 / s23, 1 / s24
     T tail;
@@ -301,24 +302,24 @@ struct QvnConst {
         }
         {
             const double kk = static_cast<double>(kPhiScale);
-            g1 = uniform(static_cast<T>(a / sa));
-            g3 = uniform(static_cast<T>(b / sb));
-            g4 = uniform(static_cast<T>(c / sc));
-            k1 = uniform(static_cast<T>(kk / sa));
-            k3 = uniform(static_cast<T>(kk / sb));
-            k4 = uniform(static_cast<T>(kk / sc));
+            g1 = U(static_cast<T>(a / sa));
+            g3 = U(static_cast<T>(b / sb));
+            g4 = U(static_cast<T>(c / sc));
+            k1 = U(static_cast<T>(kk / sa));
+            k3 = U(static_cast<T>(kk / sb));
+            k4 = U(static_cast<T>(kk / sc));
 #pragma unroll
             for (int i = 0; i < kNodes; ++i) {
                 lw[i] = uniform(static_cast<T>(log2(0.5 * w[i] * 0.39894228040143267794 / kk)));
                 px[i] = uniform(px[i]);
             }
             tail = uniform(tail);
-            c1 = uniform(c1);
-            c3 = uniform(c3);
-            c4 = uniform(c4);
-            ir12 = uniform(ir12);
-            ir23 = uniform(ir23);
-            ir24 = uniform(ir24);
+            c1 = U(c1);
+            c3 = U(c3);
+            c4 = U(c4);
+            ir12 = U(ir12);
+            ir23 = U(ir23);
+            ir24 = U(ir24);
         }
         np = panels;
         nb = bvn_n;
@@ -327,10 +328,10 @@ struct QvnConst {
 #pragma unroll
         for (int i = 0; i < NMAX; ++i) {
             bw[i] = uniform(static_cast<T>(i < bvn_n ? bwx[i] : 0.0));
-            bc.a[i] = uniform(bc.a[i]);
-            bc.b[i] = uniform(bc.b[i]);
+            bc.a[i] = U(bc.a[i]);
+            bc.b[i] = U(bc.b[i]);
         }
-        bc.scale = uniform(bc.scale);
+        bc.scale = U(bc.scale);
     }
 };
 
@@ -338,19 +339,19 @@ struct QvnConst {
 // prescaled, FP64 as they are.
 __device__ __forceinline__ float qvn_cdf1(float x) { return norm_cdf_scaled(x); }
 __device__ __forceinline__ double qvn_cdf1(double x) { return norm_cdf(x); }
-template <int NMAX>
-__device__ __forceinline__ float qvn_cdf2(float a, float b, const QvnConst<float, NMAX>& c) {
+template <int NMAX, bool UNI>
+__device__ __forceinline__ float qvn_cdf2(float a, float b, const QvnConst<float, NMAX, UNI>& c) {
     return bvn_cdf_scaled<NMAX>(a, b, c.bc, c.bw, c.nb);
 }
-template <int NMAX>
-__device__ __forceinline__ double qvn_cdf2(double a, double b, const QvnConst<double, NMAX>& c) {
+template <int NMAX, bool UNI>
+__device__ __forceinline__ double qvn_cdf2(double a, double b, const QvnConst<double, NMAX, UNI>& c) {
     return bvn_cdf<NMAX>(a, b, c.bc, c.bw, c.nb);
 }
 
 // FP32 Phi_4 in y' (see TvnConst): the three conditional arguments are one
 // FMA each and arrive prescaled at the univariate and bivariate CDFs.
-template <int NMAX>
-__device__ __forceinline__ float qvn(float h1, float h2, float h3, float h4, const QvnConst<float, NMAX>& c) {
+template <int NMAX, bool UNI>
+__device__ __forceinline__ float qvn(float h1, float h2, float h3, float h4, const QvnConst<float, NMAX, UNI>& c) {
     const float k = kPhiScale;
     const float lo = -c.tail * k;
     const float hi = k * fminf(fminf(fminf(h2, c.tail), (h1 + c.c1) * c.ir12),
@@ -375,8 +376,8 @@ __device__ __forceinline__ float qvn(float h1, float h2, float h3, float h4, con
 
 // Phi_4(h1, h2, h3, h4) over c.np panels (wave-uniform); an empty range gives
 // zero, NaN inputs NaN.
-template <typename T, int NMAX>
-__device__ __forceinline__ T qvn(T h1, T h2, T h3, T h4, const QvnConst<T, NMAX>& c) {
+template <typename T, int NMAX, bool UNI>
+__device__ __forceinline__ T qvn(T h1, T h2, T h3, T h4, const QvnConst<T, NMAX, UNI>& c) {
     const T lo = -c.tail;
     const T hi = fmin(fmin(fmin(h2, c.tail), (h1 + c.c1) * c.ir12),
                       fmin((h3 + c.c3) * c.ir23, (h4 + c.c4) * c.ir24));
@@ -390,7 +391,7 @@ __device__ __forceinline__ T qvn(T h1, T h2, T h3, T h4, const QvnConst<T, NMAX>
             const T u1 = (h1 - c.r12 * y) * c.is12;
             const T u3 = (h3 - c.r23 * y) * c.is23;
             const T u4 = (h4 - c.r24 * y) * c.is24;
-            acc = fma(c.pw[i] * half_gauss(y) * qvn_cdf1(u1), qvn_cdf2<NMAX>(u3, u4, c), acc);
+            acc = fma(c.pw[i] * half_gauss(y) * qvn_cdf1(u1), qvn_cdf2(u3, u4, c), acc);
         }
     }
     return acc * width;
@@ -410,7 +411,7 @@ __device__ __forceinline__ double qvn_wave(double h1, double h2, double h3, doub
         const double u1 = (h1 - c.r12 * y) * c.is12;
         const double u3 = (h3 - c.r23 * y) * c.is23;
         const double u4 = (h4 - c.r24 * y) * c.is24;
-        acc = fma(nd.pw * half_gauss(y) * qvn_cdf1(u1), qvn_cdf2<NMAX>(u3, u4, c), acc);
+        acc = fma(nd.pw * half_gauss(y) * qvn_cdf1(u1), qvn_cdf2(u3, u4, c), acc);
     }
     return wave_total(acc) * width;
 }

@@ -12,16 +12,10 @@
 #include "bmd_internal.hpp"
 #include "device_math.hpp"
 #include "nested_cdf.hpp"
+#include "nested_order.hpp"
 
 namespace bmd {
 namespace {
-
-// Largest value of v over the wavefront, in a scalar register.
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
-    return __builtin_amdgcn_readfirstlane(v);
-}
 
 // Cutoff quantiles of design g.
 __device__ __forceinline__ void nested3_q(const DevProblem& P, int64_t g, double* q1, double* q2) {
@@ -86,54 +80,10 @@ __device__ __forceinline__ int nested3_key(const DevProblem& P, const double* z,
     return kOrderBins - 2 - ((tvn_panels<float>(1.0 - q1, 1.0 - q2) - 3) + (tvn_panels<double>(1.0 - q1, 1.0 - q2) - 8));
 }
 
-// One workgroup of 16 wavefronts: a stable counting sort.  Bin counts by LDS
-// atomics and their exclusive scan into bin starts; then, tile by tile of
-// 1,024 designs, each wavefront's count per bin, each lane's rank among the
-// lanes of its wavefront with the same key (by 63 shuffles), and per bin the
-// wavefronts' starts in turn.
+// The stable counting sort of nested_order.hpp (one workgroup of 16 wavefronts).
 __global__ __launch_bounds__(1024) void k_order_nested3(DevProblem P, const double* __restrict__ z,
                                                         int32_t* __restrict__ order) {
-    __shared__ int start[kOrderBins];
-    __shared__ int wstart[16][kOrderBins];
-    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-    const int64_t G = P.G;
-    for (int b = t; b < kOrderBins; b += 1024) start[b] = 0;
-    __syncthreads();
-    for (int64_t g = t; g < G; g += 1024) atomicAdd(&start[nested3_key(P, z, g)], 1);
-    __syncthreads();
-    if (t == 0) {
-        int run = 0;
-        for (int b = 0; b < kOrderBins; ++b) {
-            const int c = start[b];
-            start[b] = run;
-            run += c;
-        }
-    }
-    for (int64_t g0 = 0; g0 < G; g0 += 1024) {
-        for (int b = t; b < 16 * kOrderBins; b += 1024) (&wstart[0][0])[b] = 0;
-        __syncthreads();   // also orders the scan above and the previous tile's reads before these writes
-        const int64_t g = g0 + t;
-        const int key = g < G ? nested3_key(P, z, g) : -1;
-        if (key >= 0) atomicAdd(&wstart[wave][key], 1);
-        int rank = 0;
-        for (int j = 0; j < 64; ++j) {
-            const int kj = __shfl(key, j);
-            rank += (j < lane && kj == key) ? 1 : 0;
-        }
-        __syncthreads();
-        for (int b = t; b < kOrderBins; b += 1024) {
-            int run = start[b];
-            for (int w = 0; w < 16; ++w) {
-                const int c = wstart[w][b];
-                wstart[w][b] = run;
-                run += c;
-            }
-            start[b] = run;
-        }
-        __syncthreads();
-        if (key >= 0) order[wstart[wave][key] + rank] = static_cast<int32_t>(g);
-        __syncthreads();
-    }
+    order_by_key<kOrderBins>(P.G, [&](int64_t g) { return nested3_key(P, z, g); }, order);
 }
 
 template <typename T>
@@ -184,7 +134,7 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_nested3(Nested3Args<T> a) {
     }
     const double r2 = 1.0 - q1, r3 = 1.0 - q2;
     TvnConst<T, false> c;
-    c.init(r2, r3, wave_max(tvn_panels<T>(r2, r3)), a.gl);
+    c.init(r2, r3, wave_max_i32(tvn_panels<T>(r2, r3)), a.gl);
     const T z = static_cast<T>(exists ? zd : 2.0);
     const T s1 = static_cast<T>(a.P.sqrtI), s2 = static_cast<T>(sqrt(r2 * a.P.info)),
             s3 = static_cast<T>(sqrt(r3 * a.P.info));

@@ -12,18 +12,13 @@
 #include "bmd_internal.hpp"
 #include "device_math.hpp"
 #include "nested_cdf.hpp"
+#include "nested_order.hpp"
 
 namespace bmd {
 namespace {
 
 constexpr int kN4Bvn64 = 24;   // largest FP64 bivariate rule of the packed table
 constexpr int kN4Bvn32 = 12;   // largest FP32 rule
-
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
-    return __builtin_amdgcn_readfirstlane(v);
-}
 
 // Cutoff quantiles of design g.
 __device__ __forceinline__ void nested4_q(const DevProblem& P, int64_t g, double* q) {
@@ -83,8 +78,7 @@ __global__ __launch_bounds__(64) void k_nested4_precompute(DevProblem P, const d
 
 // Launch order: existing designs by their FP32 work, largest first (panel
 // count, then bivariate node count), ties in index order; designs that do
-// not exist last.  A stable counting sort in one workgroup of 16 wavefronts,
-// as for two cutoffs.
+// not exist last, by the stable counting sort of nested_order.hpp.
 constexpr int kN4Nodes = 5;   // FP32 rules of 4, 6, 8, 10 and 12 nodes
 constexpr int kN4Bins = (64 - 3 + 1) * kN4Nodes + 1;
 
@@ -101,47 +95,7 @@ __device__ __forceinline__ int nested4_key(const DevProblem& P, const double* z,
 
 __global__ __launch_bounds__(1024) void k_order_nested4(DevProblem P, const double* __restrict__ z,
                                                         int32_t* __restrict__ order) {
-    __shared__ int start[kN4Bins];
-    __shared__ int wstart[16][kN4Bins];
-    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-    const int64_t G = P.G;
-    for (int b = t; b < kN4Bins; b += 1024) start[b] = 0;
-    __syncthreads();
-    for (int64_t g = t; g < G; g += 1024) atomicAdd(&start[nested4_key(P, z, g)], 1);
-    __syncthreads();
-    if (t == 0) {
-        int run = 0;
-        for (int b = 0; b < kN4Bins; ++b) {
-            const int c = start[b];
-            start[b] = run;
-            run += c;
-        }
-    }
-    for (int64_t g0 = 0; g0 < G; g0 += 1024) {
-        for (int b = t; b < 16 * kN4Bins; b += 1024) (&wstart[0][0])[b] = 0;
-        __syncthreads();
-        const int64_t g = g0 + t;
-        const int key = g < G ? nested4_key(P, z, g) : -1;
-        if (key >= 0) atomicAdd(&wstart[wave][key], 1);
-        int rank = 0;
-        for (int j = 0; j < 64; ++j) {
-            const int kj = __shfl(key, j);
-            rank += (j < lane && kj == key) ? 1 : 0;
-        }
-        __syncthreads();
-        for (int b = t; b < kN4Bins; b += 1024) {
-            int run = start[b];
-            for (int w = 0; w < 16; ++w) {
-                const int c = wstart[w][b];
-                wstart[w][b] = run;
-                run += c;
-            }
-            start[b] = run;
-        }
-        __syncthreads();
-        if (key >= 0) order[wstart[wave][key] + rank] = static_cast<int32_t>(g);
-        __syncthreads();
-    }
+    order_by_key<kN4Bins>(P.G, [&](int64_t g) { return nested4_key(P, z, g); }, order);
 }
 
 template <typename T>
@@ -189,8 +143,8 @@ __global__ __launch_bounds__(kEvalBlock) void k_eval_nested4(Nested4Args<T> a) {
     }
     const double r2 = 1.0 - q[0], r3 = 1.0 - q[1], r4 = 1.0 - q[2];
     const double rho = qvn_partial_rho(r2, r3, r4);
-    const int np = wave_max(qvn_panels<T>(r2, r3, r4));
-    const int nb = wave_max(sizeof(T) == 8 ? bvn_nodes_fp64(rho) : bvn_nodes_fp32(rho));
+    const int np = wave_max_i32(qvn_panels<T>(r2, r3, r4));
+    const int nb = wave_max_i32(sizeof(T) == 8 ? bvn_nodes_fp64(rho) : bvn_nodes_fp32(rho));
     QvnConst<T, NB, false> c;
     c.init(r2, r3, r4, np, nb, a.gl);
     const T z = static_cast<T>(exists ? zd : 2.0);

@@ -635,7 +635,8 @@ def bench_tps(args):
                                   f"refinement on the spline", "designs_fitted": n, "lambda": lam},
            "roofline": {"bound": "alu", "achieved": achieved, "peak": 78.6, "unit": "TFLOP/s", "frac": achieved / 78.6,
                         "traffic": None, "kernel": "the whole fit (k_chol_update does the O(n^3) work on the FP64 "
-                                                   "vector units, 64 x 64 output tiles)", "flops_per_call": flops},
+                                                   "matrix cores, 64 x 64 output tiles; priced against the "
+                                                   "FP64 vector peak)", "flops_per_call": flops},
            "result": {"best_alpha_grid": [float(x) for x in q0], "best_alpha_refined": [float(x) for x in q],
                       "spline_at_grid_best": v, "spline_at_refined": val, "refine_steps": iters}}
     print(json.dumps(out), flush=True)

@@ -50,6 +50,15 @@ __device__ __forceinline__ void unit_coords(const DevProblem& P, int64_t g, doub
     }
 }
 
+// Lane src's value of v on every lane (src wave-uniform): two reads into
+// scalar registers, no round trip through LDS as a shuffle takes.
+__device__ __forceinline__ double lane_value(double v, int src) {
+    const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v));
+    const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(u & 0xffffffffu), src));
+    const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(u >> 32), src));
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
 __device__ double block_sum(double v, double* red) {
     const int t = threadIdx.x, nt = blockDim.x;
 #pragma unroll
@@ -198,65 +207,111 @@ __global__ void k_tps_rank2(int64_t n, int np, int k, const double* __restrict__
     A[i * n + j] -= vi * wj + wi * vj;
 }
 
-// Cholesky of the kNB x kNB diagonal block at (o + kb, o + kb) (one
-// wavefront; lane r holds row r in registers): per column j every lane takes
-// the pivot's square root by a shuffle, lanes below it scale their element of
-// column j, and each updates its row to the diagonal with the other lanes'
-// column-j elements, also by shuffles.  A pivot <= 0 raises *bad.
-__global__ __launch_bounds__(64) void k_chol_diag(int64_t n, int64_t o, int64_t kb, int bs, double* __restrict__ A,
-                                                  int* __restrict__ bad) {
-    const int t = threadIdx.x;
-    double row[kNB];
+// Panel slices are kPanelRows rows: thread t of a slice owns its row t.
+constexpr int kPanelRows = 128;
+
+// The bs x bs block at blk (row stride n) into L by NT threads: thread t
+// takes column t % kNB of rows t / kNB + (NT / kNB) i, all loads in flight
+// before the first LDS write.
+template <int NT>
+__device__ __forceinline__ void stage_block(const double* __restrict__ blk, int64_t n, int bs, double (*L)[kNB + 1]) {
+    constexpr int kStep = NT / kNB, kIt = kNB / kStep;
+    const int t = threadIdx.x, c = t % kNB, r = t / kNB;
+    double v[kIt];
 #pragma unroll
-    for (int c = 0; c < kNB; ++c) row[c] = (t < bs && c <= t) ? A[(o + kb + t) * n + o + kb + c] : 0.0;
-    bool neg = false;
+    for (int i = 0; i < kIt; ++i) v[i] = (r + kStep * i < bs && c < bs) ? blk[(r + kStep * i) * n + c] : 0.0;
 #pragma unroll
-    for (int j = 0; j < kNB; ++j) {
-        if (j < bs) {   // wave-uniform
-            const double pv = __shfl(row[j], j);
-            neg |= !(pv > 0.0);
-            const double dj = pv > 0.0 ? sqrt(pv) : 1.0;
-            const double lrj = (t > j) ? row[j] / dj : (t == j ? dj : row[j]);
-            row[j] = lrj;
-#pragma unroll
-            for (int c = j + 1; c < kNB; ++c) {
-                const double lcj = __shfl(lrj, c);   // column j of row c
-                if (t >= c) row[c] -= lrj * lcj;
-            }
-        }
-    }
-    if (t == 0 && neg) *bad = 1;
-    if (t < bs) {
-#pragma unroll
-        for (int c = 0; c < kNB; ++c)
-            if (c <= t) A[(o + kb + t) * n + o + kb + c] = row[c];
-    }
+    for (int i = 0; i < kIt; ++i) L[r + kStep * i][c] = v[i];
 }
 
-// Panel below the diagonal block: L21 = A21 L11^-T, one thread per row.
-__global__ __launch_bounds__(256) void k_chol_panel(int64_t n, int64_t o, int64_t kb, int bs, int64_t n2,
-                                                    double* __restrict__ A) {
+// Rows [0, nr) x columns [0, bs) of the slice at base (row stride n) into X:
+// thread t takes column t % kNB of rows t / kNB + 4 i, every load issued
+// before the first LDS write so the loads' latencies overlap.
+__device__ __forceinline__ void stage_rows(const double* __restrict__ base, int64_t n, int nr, int bs,
+                                           double (*X)[kNB + 1]) {
+    static_assert(kPanelRows == 4 * kNB, "four rows per pass");
+    const int t = threadIdx.x, c = t % kNB, r = t / kNB;
+    double v[kNB];
+#pragma unroll
+    for (int i = 0; i < kNB; ++i) v[i] = (r + 4 * i < nr && c < bs) ? base[(r + 4 * i) * n + c] : 0.0;
+#pragma unroll
+    for (int i = 0; i < kNB; ++i) X[r + 4 * i][c] = v[i];
+}
+
+// One step of the blocked Cholesky M22 = L L^T at block column kb: the kNB x
+// kNB diagonal block, then the panel below it, L21 = A21 L11^-T.  Every
+// workgroup factors the diagonal block itself in its first wavefront (lane r
+// holds row r in registers; per column j every lane reads the pivot from lane
+// j, lanes below scale their element of column j and update their rows with
+// the other lanes' column-j elements, read from their lanes), so the step is
+// one launch; A's diagonal block is only read, and workgroup 0 stores the
+// factor in Ld (row stride kNB, zeros above the diagonal) for the triangular
+// solves.  The panel's row segments go through LDS with consecutive lanes on
+// consecutive columns (a thread walking its own row in memory would touch a
+// different cache line per lane on every load).  A pivot <= 0 raises *bad.
+__global__ __launch_bounds__(kPanelRows) void k_chol_step(int64_t n, int64_t o, int64_t kb, int bs, int64_t n2,
+                                                          double* __restrict__ A, double* __restrict__ Ld,
+                                                          int* __restrict__ bad) {
     __shared__ double L[kNB][kNB + 1];
+    __shared__ double X[kPanelRows][kNB + 1];
     const int t = threadIdx.x;
-    for (int e = t; e < bs * bs; e += blockDim.x) L[e / bs][e % bs] = A[(o + kb + e / bs) * n + o + kb + e % bs];
-    __syncthreads();
-    const int64_t r = kb + bs + static_cast<int64_t>(blockIdx.x) * blockDim.x + t;
-    if (r >= n2) return;
-    double* row = A + (o + r) * n + o + kb;
-    double x[kNB];
+    const int64_t r0 = kb + bs + static_cast<int64_t>(blockIdx.x) * kPanelRows;
+    const int nr = static_cast<int>(max<int64_t>(0, min<int64_t>(kPanelRows, n2 - r0)));
+    double* base = A + (o + r0) * n + o + kb;
+    if (nr > 0) stage_rows(base, n, nr, bs, X);
+    if (t < 64) {   // the first wavefront
+        double row[kNB];
 #pragma unroll
-    for (int c = 0; c < kNB; ++c) {
-        if (c < bs) {
-            double s = row[c];
+        for (int c = 0; c < kNB; ++c) row[c] = (t < bs && c <= t) ? A[(o + kb + t) * n + o + kb + c] : 0.0;
+        bool neg = false;
 #pragma unroll
-            for (int e = 0; e < kNB; ++e)
-                if (e < c) s -= x[e] * L[c][e];
-            x[c] = s / L[c][c];
+        for (int j = 0; j < kNB; ++j) {
+            if (j < bs) {   // wave-uniform
+                const double pv = lane_value(row[j], j);
+                neg |= !(pv > 0.0);
+                const double dj = pv > 0.0 ? sqrt(pv) : 1.0;
+                const double lrj = (t > j) ? row[j] / dj : (t == j ? dj : row[j]);
+                row[j] = lrj;
+#pragma unroll
+                for (int c = j + 1; c < kNB; ++c) {
+                    const double lcj = lane_value(lrj, c);   // column j of row c
+                    if (t >= c) row[c] -= lrj * lcj;
+                }
+            }
         }
-    }
+        if (t < kNB) {
 #pragma unroll
-    for (int c = 0; c < kNB; ++c)
-        if (c < bs) row[c] = x[c];
+            for (int c = 0; c < kNB; ++c) L[t][c] = c <= t ? row[c] : 0.0;
+        }
+        if (blockIdx.x == 0 && t == 0 && neg) *bad = 1;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0) {
+        double* ld = Ld + kb * kNB;
+        for (int e = t; e < kNB * kNB; e += kPanelRows) ld[e] = L[e / kNB][e % kNB];
+    }
+    if (nr == 0) return;   // workgroup-uniform
+    if (t < nr) {
+        double x[kNB];
+#pragma unroll
+        for (int c = 0; c < kNB; ++c) {
+            if (c < bs) {
+                double s = X[t][c];
+#pragma unroll
+                for (int e = 0; e < kNB; ++e)
+                    if (e < c) s -= x[e] * L[c][e];
+                x[c] = s / L[c][c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kNB; ++c)
+            if (c < bs) X[t][c] = x[c];
+    }
+    __syncthreads();
+    const int c = t % kNB, r = t / kNB;
+#pragma unroll
+    for (int i = 0; i < kNB; ++i)
+        if (r + 4 * i < nr && c < bs) base[(r + 4 * i) * n + c] = X[r + 4 * i][c];
 }
 
 // Trailing update A22 -= L21 L21^T on the lower triangle, kUT x kUT output
@@ -325,53 +380,66 @@ __global__ __launch_bounds__(1024) void k_tps_qty(int64_t n, int np, const doubl
     }
 }
 
-// M22 w = z2 with M22 = L L^T, by blocks of kNB rows: the block's own rows
-// by one wavefront (lane l holds row l; column by column, each solved value
-// broadcast and subtracted from the rows below it, or above it for L^T), then
-// the remaining rows updated by the whole GPU.  w overwrites z2 = z [o, n).
-__global__ __launch_bounds__(64) void k_trsv_diag(int64_t n, int64_t o, int64_t kb, int bs, bool upper,
-                                                  const double* __restrict__ A, double* __restrict__ b) {
+// One block of kNB rows of M22 w = z2 with M22 = L L^T, forward (L t = z2)
+// or backward (L^T w = t): every workgroup solves the block's own rows in its
+// first wavefront from the factor in Ld (lane l holds element l; per row r
+// the solved value is read from lane r and subtracted from the lanes below
+// it, or above it for L^T), workgroup 0 stores them in out, and each
+// workgroup updates its slice of the remaining rows of in: forward the rows
+// below, b[r] -= L[r][kb..] x (row segments through LDS as in the Cholesky
+// step), backward the rows above, b[r] -= L[kb..][r]^T x (consecutive
+// threads on consecutive elements).  The block's own elements of in are only
+// read, so no workgroup sees another's results within a launch.
+__global__ __launch_bounds__(kPanelRows) void k_trsv_step(int64_t n, int64_t o, int64_t kb, int bs, int64_t n2,
+                                                          bool upper, const double* __restrict__ A,
+                                                          const double* __restrict__ Ld, double* __restrict__ in,
+                                                          double* __restrict__ out) {
     __shared__ double Lb[kNB][kNB + 1];
-    const int l = threadIdx.x;
-    for (int e = l; e < bs * bs; e += 64) Lb[e / bs][e % bs] = A[(o + kb + e / bs) * n + o + kb + e % bs];
-    __syncthreads();
-    double x = l < bs ? b[kb + l] : 0.0;
+    __shared__ double X[kPanelRows][kNB + 1];
+    __shared__ double xb[kNB];
+    const int t = threadIdx.x;
+    stage_block<kPanelRows>(Ld + kb * kNB, kNB, bs, Lb);
+    int64_t r0 = 0;
+    int nr = 0;
     if (!upper) {
-        for (int r = 0; r < bs; ++r) {   // L x = b
-            const double xr = __shfl(x, r) / Lb[r][r];
-            if (l == r) x = xr;
-            if (l > r && l < bs) x -= Lb[l][r] * xr;
+        r0 = kb + bs + static_cast<int64_t>(blockIdx.x) * kPanelRows;
+        nr = static_cast<int>(max<int64_t>(0, min<int64_t>(kPanelRows, n2 - r0)));
+        if (nr > 0) stage_rows(A + (o + r0) * n + o + kb, n, nr, bs, X);
+    }
+    __syncthreads();
+    if (t < 64) {   // the first wavefront
+        double x = t < bs ? in[kb + t] : 0.0;
+        if (!upper) {
+            for (int r = 0; r < bs; ++r) {
+                const double xr = lane_value(x, r) / Lb[r][r];
+                if (t == r) x = xr;
+                if (t > r && t < bs) x -= Lb[t][r] * xr;
+            }
+        } else {
+            for (int r = bs - 1; r >= 0; --r) {
+                const double xr = lane_value(x, r) / Lb[r][r];
+                if (t == r) x = xr;
+                if (t < r) x -= Lb[r][t] * xr;
+            }
         }
-    } else {
-        for (int r = bs - 1; r >= 0; --r) {   // L^T x = b
-            const double xr = __shfl(x, r) / Lb[r][r];
-            if (l == r) x = xr;
-            if (l < r) x -= Lb[r][l] * xr;
+        if (t < bs) {
+            xb[t] = x;
+            if (blockIdx.x == 0) out[kb + t] = x;
         }
     }
-    if (l < bs) b[kb + l] = x;
-}
-
-// Rows outside the block: b[r] -= L[r][kb..] x (forward, rows below) or
-// b[r] -= L[kb..][r]^T x (backward, rows above), one thread per row.
-__global__ __launch_bounds__(256) void k_trsv_update(int64_t n, int64_t o, int64_t kb, int bs, int64_t n2, bool upper,
-                                                     const double* __restrict__ A, double* __restrict__ b) {
-    __shared__ double xb[kNB];
-    if (threadIdx.x < bs) xb[threadIdx.x] = b[kb + threadIdx.x];
     __syncthreads();
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     double s = 0.0;
     if (!upper) {
-        const int64_t r = kb + bs + t;
-        if (r >= n2) return;
-        const double* row = A + (o + r) * n + o + kb;
-        for (int c = 0; c < bs; ++c) s = fma(row[c], xb[c], s);
-        b[r] -= s;
+        if (t < nr) {
+            for (int c = 0; c < bs; ++c) s = fma(X[t][c], xb[c], s);
+            in[r0 + t] -= s;
+        }
     } else {
-        const int64_t r = t;
-        if (r >= kb) return;
-        for (int c = 0; c < bs; ++c) s = fma(A[(o + kb + c) * n + o + r], xb[c], s);
-        b[r] -= s;
+        const int64_t r = static_cast<int64_t>(blockIdx.x) * kPanelRows + t;
+        if (r < kb) {
+            for (int c = 0; c < bs; ++c) s = fma(A[(o + kb + c) * n + o + r], xb[c], s);
+            in[r] -= s;
+        }
     }
 }
 
@@ -529,6 +597,7 @@ TpsFitResult tps_fit_grid(bmd_problem* p, const double* d_in, double lam, double
     int* d_bad = nullptr;
     double *d_tau = nullptr, *d_R = nullptr, *d_kappa = nullptr;
     double *A = nullptr, *V = nullptr, *Pm = nullptr, *y = nullptr, *z = nullptr, *pv = nullptr;
+    double *Ld = nullptr, *T = nullptr;   // diagonal blocks of the factor; the forward solve's result
     double *U = nullptr, *c = nullptr, *a = nullptr;
     const size_t small_bytes = sizeof(int64_t) * (G + 2) + 64 + sizeof(double) * (2 * np + np * np + 8);
     if (hipMalloc(&small, small_bytes) != hipSuccess) {
@@ -554,7 +623,7 @@ TpsFitResult tps_fit_grid(bmd_problem* p, const double* d_in, double lam, double
     }
     {
         const size_t nn = static_cast<size_t>(n);
-        const size_t big_count = nn * nn + 2 * nn * np + 3 * nn;
+        const size_t big_count = nn * nn + 2 * nn * np + 4 * nn + kNB * (nn + kNB);
         if (hipMalloc(&big, sizeof(double) * big_count) != hipSuccess ||
             hipMalloc(&fitmem, sizeof(double) * (nn * d + nn + np)) != hipSuccess) {
             (void)hipGetLastError();
@@ -567,6 +636,8 @@ TpsFitResult tps_fit_grid(bmd_problem* p, const double* d_in, double lam, double
         y = Pm + nn * np;
         z = y + nn;
         pv = z + nn;
+        Ld = pv + nn;
+        T = Ld + kNB * (nn + kNB);
         U = fitmem;
         c = U + nn * d;
         a = c + nn;
@@ -594,31 +665,26 @@ TpsFitResult tps_fit_grid(bmd_problem* p, const double* d_in, double lam, double
     n2 = n - np;
     for (int64_t kb = 0; kb < n2; kb += kNB) {   // M22 = L L^T
         const int bs = static_cast<int>(std::min<int64_t>(kNB, n2 - kb));
-        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(64), 0, s, n, o, kb, bs, A, d_bad);
         const int64_t rest = n2 - kb - bs;
+        hipLaunchKernelGGL(k_chol_step, dim3(static_cast<unsigned>(std::max<int64_t>(1, (rest + kPanelRows - 1) / kPanelRows))),
+                           dim3(kPanelRows), 0, s, n, o, kb, bs, n2, A, Ld, d_bad);
         if (rest > 0) {
-            hipLaunchKernelGGL(k_chol_panel, dim3(static_cast<unsigned>((rest + 255) / 256)), dim3(256), 0, s, n, o, kb,
-                               bs, n2, A);
             const unsigned tiles = static_cast<unsigned>((rest + kUT - 1) / kUT);
             hipLaunchKernelGGL(k_chol_update, dim3(tiles, tiles), dim3(256), 0, s, n, o, kb, bs, n2, A);
         }
         TPS_TRY(hipGetLastError());
     }
     hipLaunchKernelGGL(k_tps_qty, dim3(1), dim3(1024), 0, s, n, np, V, d_tau, y, z);
-    for (int64_t kb = 0; kb < n2; kb += kNB) {   // L t = z2
+    for (int64_t kb = 0; kb < n2; kb += kNB) {   // L t = z2: z2 = z [o, n) in, t out
         const int bs = static_cast<int>(std::min<int64_t>(kNB, n2 - kb));
-        hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(64), 0, s, n, o, kb, bs, false, A, z + o);
         const int64_t rest = n2 - kb - bs;
-        if (rest > 0)
-            hipLaunchKernelGGL(k_trsv_update, dim3(static_cast<unsigned>((rest + 255) / 256)), dim3(256), 0, s, n, o,
-                               kb, bs, n2, false, A, z + o);
+        hipLaunchKernelGGL(k_trsv_step, dim3(static_cast<unsigned>(std::max<int64_t>(1, (rest + kPanelRows - 1) / kPanelRows))),
+                           dim3(kPanelRows), 0, s, n, o, kb, bs, n2, false, A, Ld, z + o, T);
     }
-    for (int64_t kb = ((n2 - 1) / kNB) * kNB; kb >= 0; kb -= kNB) {   // L^T w = t
+    for (int64_t kb = ((n2 - 1) / kNB) * kNB; kb >= 0; kb -= kNB) {   // L^T w = t: t in, w out to z [o, n)
         const int bs = static_cast<int>(std::min<int64_t>(kNB, n2 - kb));
-        hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(64), 0, s, n, o, kb, bs, true, A, z + o);
-        if (kb > 0)
-            hipLaunchKernelGGL(k_trsv_update, dim3(static_cast<unsigned>((kb + 255) / 256)), dim3(256), 0, s, n, o, kb,
-                               bs, n2, true, A, z + o);
+        hipLaunchKernelGGL(k_trsv_step, dim3(static_cast<unsigned>(std::max<int64_t>(1, (kb + kPanelRows - 1) / kPanelRows))),
+                           dim3(kPanelRows), 0, s, n, o, kb, bs, n2, true, A, Ld, T, z + o);
     }
     hipLaunchKernelGGL(k_tps_coeffs, dim3(1), dim3(1024), 0, s, n, np, A, V, d_tau, d_R, z, c, a);
     TPS_TRY(hipGetLastError());

@@ -317,7 +317,7 @@ __global__ __launch_bounds__(kPanelRows) void k_chol_step(int64_t n, int64_t o, 
 // Trailing update A22 -= L21 L21^T on the lower triangle, kUT x kUT output
 // tiles on the matrix cores (FP64 16x16x4): four wavefronts, each a 32 x 32
 // quarter as 2 x 2 blocks of 16 x 16; the tile's rows of L21 (both factors)
-// staged in LDS; tiles above the diagonal leave.  Operand layout of the
+// staged in LDS; one workgroup per tile on or below the diagonal.  Operand layout of the
 // instruction: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; its
 // result element v is row l / 16 + 4 v, column l % 16.
 typedef double tps_d4 __attribute__((ext_vector_type(4)));
@@ -325,15 +325,30 @@ typedef double tps_d4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_chol_update(int64_t n, int64_t o, int64_t kb, int bs, int64_t n2,
                                                      double* __restrict__ A) {
     const int64_t t0 = kb + bs;
-    const int64_t ti = blockIdx.y, tk = blockIdx.x;
-    if (tk > ti) return;
+    // workgroup b -> lower-triangle tile (ti, tk), tk <= ti, b = ti (ti + 1) / 2 + tk
+    const int64_t b = blockIdx.x;
+    int64_t ti = static_cast<int64_t>((sqrt(8.0 * static_cast<double>(b) + 1.0) - 1.0) * 0.5);
+    while (ti * (ti + 1) / 2 > b) --ti;
+    while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
+    const int64_t tk = b - ti * (ti + 1) / 2;
     __shared__ double Li[kUT][kNB + 1], Lk[kUT][kNB + 1];
     const int t = threadIdx.x;
     const int64_t i0 = t0 + ti * kUT, k0 = t0 + tk * kUT;
-    for (int e = t; e < kUT * kNB; e += 256) {
-        const int r = e / kNB, c = e % kNB;
-        Li[r][c] = (i0 + r < n2 && c < bs) ? A[(o + i0 + r) * n + o + kb + c] : 0.0;
-        Lk[r][c] = (k0 + r < n2 && c < bs) ? A[(o + k0 + r) * n + o + kb + c] : 0.0;
+    {   // thread t takes column t % kNB of rows t / kNB + 8 q; every load issued before the first LDS write
+        constexpr int kIt = kUT * kNB / 256;
+        const int c = t % kNB, r = t / kNB;
+        double vi[kIt], vk[kIt];
+#pragma unroll
+        for (int q = 0; q < kIt; ++q) {
+            const int rr = r + 8 * q;
+            vi[q] = (i0 + rr < n2 && c < bs) ? A[(o + i0 + rr) * n + o + kb + c] : 0.0;
+            vk[q] = (k0 + rr < n2 && c < bs) ? A[(o + k0 + rr) * n + o + kb + c] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kIt; ++q) {
+            Li[r + 8 * q][c] = vi[q];
+            Lk[r + 8 * q][c] = vk[q];
+        }
     }
     __syncthreads();
     const int wave = t >> 6, lane = t & 63;
@@ -669,8 +684,9 @@ TpsFitResult tps_fit_grid(bmd_problem* p, const double* d_in, double lam, double
         hipLaunchKernelGGL(k_chol_step, dim3(static_cast<unsigned>(std::max<int64_t>(1, (rest + kPanelRows - 1) / kPanelRows))),
                            dim3(kPanelRows), 0, s, n, o, kb, bs, n2, A, Ld, d_bad);
         if (rest > 0) {
-            const unsigned tiles = static_cast<unsigned>((rest + kUT - 1) / kUT);
-            hipLaunchKernelGGL(k_chol_update, dim3(tiles, tiles), dim3(256), 0, s, n, o, kb, bs, n2, A);
+            const int64_t tiles = (rest + kUT - 1) / kUT;
+            hipLaunchKernelGGL(k_chol_update, dim3(static_cast<unsigned>(tiles * (tiles + 1) / 2)), dim3(256), 0, s, n,
+                               o, kb, bs, n2, A);
         }
         TPS_TRY(hipGetLastError());
     }
